@@ -1,0 +1,368 @@
+/*
+ * CPU oracle for the online muon trigger's L1 seeds, causal N-fold count,
+ * trigger fires and event windows.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the HIP library is compared against.  It is used by the
+ * tests, by the smoke check and by the benchmark's CPU-baseline leg, and by
+ * nothing else; the product library neither links nor calls it, and this
+ * file includes no header of the product library.
+ *
+ * What is computed (the paper: Bouhadef, Morganti, Terreni, "Parallel
+ * Neutrino Triggers using GPUs for an Underwater Telescope", GPUHEP2014):
+ *
+ *   hits k = 0..n-1 with PMT p_k, time t_k (int64 ns), charge q_k (0.01 pe);
+ *   floor_id[P]; thr[P*P] (row-major, integer ns); parameters
+ *   Q (charge threshold), tau (floor-coincidence window), W (causal window
+ *   cap), N (fold threshold), H (half event window).
+ *
+ *   seed  (Sec. 4.2 trigger list: charge over threshold QTRIG and floor
+ *          coincidence FC; Sec. 3 charge trigger):
+ *     S_k = q_k >= Q  or  (tau >= 0 and there is a hit m with p_m != p_k,
+ *           floor_id[p_m] == floor_id[p_k] and |t_k - t_m| <= tau)
+ *   fold  (Sec. 3: space-time correlation of hits within less than 3 us):
+ *     for S_k:  fold_k = 1 + #{ m != k : S_m and |t_k - t_m| <= min(thr[p_k][p_m], W) }
+ *   fires (N-fold trigger): F = { k : S_k and fold_k >= N }, ordered by (t, p, k)
+ *   events (Sec. 2: a 6 us window centred on the trigger seed goes to the
+ *           Event Manager; Sec. 4.2: hits within +-3 us of a trigger seed are
+ *           tagged): each fire opens [t-H, t+H]; walking F in order, a fire
+ *           whose window starts at or before the current event's end extends
+ *           it, otherwise it opens a new event.
+ *
+ * Two forms:  "strict" evaluates every pair (O(n^2));  "blocked" evaluates
+ * the very same pair tests, restricted to hits in the same or adjacent time
+ * blocks of width B >= the largest window the test can accept (tau for
+ * seeds, W for folds), which is complete because any accepted pair has
+ * |dt| <= B and therefore lies in the same or an adjacent block.
+ *
+ * Readings of points the paper leaves open are listed with the test
+ * fixtures: all windows inclusive; the fold counts the seed itself; a floor
+ * partner must be a different PMT and need not be a seed; same-PMT seed
+ * pairs count when the table allows (thr[p][p]); the table row is the seed
+ * being counted; equal times order by (pmt, input index); slices are
+ * self-contained and windows are not clipped.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    uint32_t q_seed;
+    int32_t  t_floor_ns;
+    uint32_t w_ns;
+    uint32_t min_fold;
+    uint32_t half_event_ns;
+} orc_params;
+
+typedef struct {
+    int64_t  t_ns;
+    uint32_t hit_index;
+    uint32_t fold;
+    uint16_t pmt_id;
+    uint16_t pad[3];
+} orc_fire;
+
+typedef struct {
+    int64_t  t_trig, t_begin, t_end;
+    uint32_t n_fire, max_fold;
+} orc_event;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -2, ORC_ENOMEM = -3, ORC_EOVERFLOW = -5 };
+
+static int64_t absdiff(int64_t a, int64_t b) { return a > b ? a - b : b - a; }
+
+/* Input validation: every PMT index below P, fewer than 2^32 hits, time span
+ * below 2^31 ns, and event windows representable in int64. */
+int orc_validate(uint64_t n, const uint16_t *pmt, const int64_t *t, uint32_t n_pmt,
+                 const orc_params *prm)
+{
+    if (n >= (1ull << 32)) return ORC_ERANGE;
+    if (n == 0) return ORC_OK;
+    int64_t lo = t[0], hi = t[0];
+    for (uint64_t k = 0; k < n; ++k) {
+        if (pmt[k] >= n_pmt) return ORC_ERANGE;
+        if (t[k] < lo) lo = t[k];
+        if (t[k] > hi) hi = t[k];
+    }
+    if ((uint64_t)hi - (uint64_t)lo >= (1ull << 31)) return ORC_ERANGE;
+    if (lo < INT64_MIN + (int64_t)prm->half_event_ns) return ORC_ERANGE;
+    if (hi > INT64_MAX - (int64_t)prm->half_event_ns) return ORC_ERANGE;
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- strict */
+
+static int floor_partner_strict(uint64_t n, const uint16_t *pmt, const int64_t *t,
+                                const int32_t *floor_id, uint64_t k, int64_t tau)
+{
+    for (uint64_t m = 0; m < n; ++m) {
+        if (pmt[m] == pmt[k]) continue;
+        if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
+        if (absdiff(t[k], t[m]) <= tau) return 1;
+    }
+    return 0;
+}
+
+static void seeds_strict(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
+                         const int32_t *floor_id, const orc_params *prm, uint8_t *seed)
+{
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        int s = q[k] >= prm->q_seed;
+        if (!s && prm->t_floor_ns >= 0)
+            s = floor_partner_strict(n, pmt, t, floor_id, (uint64_t)k, prm->t_floor_ns);
+        seed[k] = (uint8_t)s;
+    }
+}
+
+static uint32_t pair_limit(const uint32_t *thr, uint32_t n_pmt, uint16_t pk, uint16_t pm, uint32_t w)
+{
+    uint32_t lim = thr[(uint64_t)pk * n_pmt + pm];
+    return lim < w ? lim : w;
+}
+
+static void folds_strict(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint8_t *seed,
+                         uint32_t n_pmt, const uint32_t *thr, const orc_params *prm, uint32_t *fold)
+{
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        if (!seed[k]) { fold[k] = 0; continue; }
+        uint32_t c = 1;
+        for (uint64_t m = 0; m < n; ++m) {
+            if ((int64_t)m == k || !seed[m]) continue;
+            if (absdiff(t[k], t[m]) <= (int64_t)pair_limit(thr, n_pmt, pmt[k], pmt[m], prm->w_ns)) ++c;
+        }
+        fold[k] = c;
+    }
+}
+
+/* --------------------------------------------------------------- blocked */
+
+/* Group the indices of the selected hits by time block b = (t - t_lo) / B.
+ * start[b]..start[b+1] lists block b's members in input order. */
+typedef struct { uint64_t nb; uint64_t *start; uint32_t *member; int64_t t_lo; uint64_t width; } blocks;
+
+static int make_blocks(uint64_t n, const int64_t *t, const uint8_t *sel, uint64_t width, blocks *B)
+{
+    int64_t lo = 0, hi = 0; int any = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        if (sel && !sel[k]) continue;
+        if (!any) { lo = hi = t[k]; any = 1; }
+        if (t[k] < lo) lo = t[k];
+        if (t[k] > hi) hi = t[k];
+    }
+    uint64_t span = any ? (uint64_t)(hi - lo) : 0;
+    uint64_t cnt = 0;
+    for (uint64_t k = 0; k < n; ++k) cnt += (!sel || sel[k]);
+    /* never more blocks than members: a wider block is still complete */
+    uint64_t minw = cnt ? (span + cnt) / cnt : 1;
+    if (width < minw) width = minw;
+    if (width < 1) width = 1;
+    B->t_lo = lo; B->width = width;
+    B->nb = span / width + 1;
+    B->start = (uint64_t *)calloc(B->nb + 1, sizeof(uint64_t));
+    B->member = (uint32_t *)malloc((cnt ? cnt : 1) * sizeof(uint32_t));
+    if (!B->start || !B->member) { free(B->start); free(B->member); return ORC_ENOMEM; }
+    for (uint64_t k = 0; k < n; ++k)
+        if (!sel || sel[k]) B->start[(uint64_t)(t[k] - lo) / width + 1]++;
+    for (uint64_t b = 0; b < B->nb; ++b) B->start[b + 1] += B->start[b];
+    uint64_t *fill = (uint64_t *)malloc((B->nb + 1) * sizeof(uint64_t));
+    if (!fill) { free(B->start); free(B->member); return ORC_ENOMEM; }
+    memcpy(fill, B->start, (B->nb + 1) * sizeof(uint64_t));
+    for (uint64_t k = 0; k < n; ++k)
+        if (!sel || sel[k]) B->member[fill[(uint64_t)(t[k] - lo) / width]++] = (uint32_t)k;
+    free(fill);
+    return ORC_OK;
+}
+
+static void free_blocks(blocks *B) { free(B->start); free(B->member); }
+
+static int seeds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
+                         const int32_t *floor_id, const orc_params *prm, uint8_t *seed)
+{
+    for (uint64_t k = 0; k < n; ++k) seed[k] = q[k] >= prm->q_seed;
+    if (prm->t_floor_ns < 0 || n == 0) return ORC_OK;
+    blocks B;
+    int rc = make_blocks(n, t, NULL, (uint64_t)prm->t_floor_ns, &B);
+    if (rc) return rc;
+    const int64_t tau = prm->t_floor_ns;
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        if (seed[k]) continue;
+        uint64_t b = (uint64_t)(t[k] - B.t_lo) / B.width;
+        uint64_t b0 = b ? b - 1 : 0, b1 = b + 1 < B.nb ? b + 1 : b;
+        int s = 0;
+        for (uint64_t bb = b0; bb <= b1 && !s; ++bb)
+            for (uint64_t i = B.start[bb]; i < B.start[bb + 1]; ++i) {
+                uint32_t m = B.member[i];
+                if (pmt[m] == pmt[k]) continue;
+                if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
+                if (absdiff(t[k], t[m]) <= tau) { s = 1; break; }
+            }
+        seed[k] = (uint8_t)s;
+    }
+    free_blocks(&B);
+    return ORC_OK;
+}
+
+static int folds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint8_t *seed,
+                         uint32_t n_pmt, const uint32_t *thr, const orc_params *prm, uint32_t *fold)
+{
+    for (uint64_t k = 0; k < n; ++k) fold[k] = 0;
+    if (n == 0) return ORC_OK;
+    blocks B;
+    int rc = make_blocks(n, t, seed, prm->w_ns, &B);
+    if (rc) return rc;
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t k = 0; k < (int64_t)n; ++k) {
+        if (!seed[k]) continue;
+        uint64_t b = (uint64_t)(t[k] - B.t_lo) / B.width;
+        uint64_t b0 = b ? b - 1 : 0, b1 = b + 1 < B.nb ? b + 1 : b;
+        uint32_t c = 1;
+        for (uint64_t bb = b0; bb <= b1; ++bb)
+            for (uint64_t i = B.start[bb]; i < B.start[bb + 1]; ++i) {
+                uint32_t m = B.member[i];
+                if ((int64_t)m == k) continue;
+                if (absdiff(t[k], t[m]) <= (int64_t)pair_limit(thr, n_pmt, pmt[k], pmt[m], prm->w_ns)) ++c;
+            }
+        fold[k] = c;
+    }
+    free_blocks(&B);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------- fires and events */
+
+static int fire_cmp(const void *a, const void *b)
+{
+    const orc_fire *x = (const orc_fire *)a, *y = (const orc_fire *)b;
+    if (x->t_ns != y->t_ns) return x->t_ns < y->t_ns ? -1 : 1;
+    if (x->pmt_id != y->pmt_id) return x->pmt_id < y->pmt_id ? -1 : 1;
+    if (x->hit_index != y->hit_index) return x->hit_index < y->hit_index ? -1 : 1;
+    return 0;
+}
+
+/* Fires: every seed whose fold reaches N, ordered by (t, pmt, input index). */
+static uint64_t collect_fires(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint8_t *seed,
+                              const uint32_t *fold, uint32_t min_fold, orc_fire *out)
+{
+    uint64_t c = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        if (!seed[k] || fold[k] < min_fold) continue;
+        orc_fire f;
+        memset(&f, 0, sizeof f);
+        f.t_ns = t[k]; f.hit_index = (uint32_t)k; f.fold = fold[k]; f.pmt_id = pmt[k];
+        out[c++] = f;
+    }
+    qsort(out, c, sizeof(orc_fire), fire_cmp);
+    return c;
+}
+
+/* Events: walk the ordered fires; a fire whose window [t-H, t+H] starts at
+ * or before the current event's end joins it, otherwise it opens a new one. */
+uint64_t orc_events(const orc_fire *f, uint64_t nf, uint32_t half_event_ns, orc_event *ev)
+{
+    const int64_t H = half_event_ns;
+    uint64_t ne = 0;
+    for (uint64_t i = 0; i < nf; ++i) {
+        if (ne > 0 && f[i].t_ns - H <= ev[ne - 1].t_end) {
+            orc_event *e = &ev[ne - 1];
+            e->t_end = f[i].t_ns + H;
+            e->n_fire += 1;
+            if (f[i].fold > e->max_fold) e->max_fold = f[i].fold;
+        } else {
+            orc_event e;
+            e.t_trig = f[i].t_ns; e.t_begin = f[i].t_ns - H; e.t_end = f[i].t_ns + H;
+            e.n_fire = 1; e.max_fold = f[i].fold;
+            ev[ne++] = e;
+        }
+    }
+    return ne;
+}
+
+/* Whole path.  form 0 = strict, 1 = blocked.  seed_out / fold_out are [n]
+ * (by input index).  fires / events need room for up to n records.  Returns
+ * ORC_OK or the validation error (outputs then hold zero counts). */
+int orc_run(int form, uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
+            uint32_t n_pmt, const int32_t *floor_id, const uint32_t *thr, const orc_params *prm,
+            uint8_t *seed_out, uint32_t *fold_out,
+            orc_fire *fires, uint64_t *n_fires, orc_event *events, uint64_t *n_events,
+            int n_threads)
+{
+    *n_fires = 0; *n_events = 0;
+    if (!prm || n_pmt == 0 || (n && (!pmt || !t || !q))) return ORC_EINVAL;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int rc = orc_validate(n, pmt, t, n_pmt, prm);
+    if (rc) return rc;
+    if (form == 0) {
+        seeds_strict(n, pmt, t, q, floor_id, prm, seed_out);
+        folds_strict(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
+    } else {
+        rc = seeds_blocked(n, pmt, t, q, floor_id, prm, seed_out);
+        if (rc) return rc;
+        rc = folds_blocked(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
+        if (rc) return rc;
+    }
+    *n_fires = collect_fires(n, pmt, t, seed_out, fold_out, prm->min_fold, fires);
+    *n_events = orc_events(fires, *n_fires, prm->half_event_ns, events);
+    return ORC_OK;
+}
+
+/* Sampled check at any size: seed flag and fold of the hits listed in ks,
+ * each from the definition evaluated on the hits within W + tau of it (one
+ * pass over the slice per sample; every partner a test can accept lies in
+ * that neighbourhood).  fold is 0 for a non-seed. */
+int orc_point(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
+              uint32_t n_pmt, const int32_t *floor_id, const uint32_t *thr, const orc_params *prm,
+              const uint64_t *ks, uint64_t nk, uint8_t *seed_k, uint32_t *fold_k, int n_threads)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    int rc = orc_validate(n, pmt, t, n_pmt, prm);
+    if (rc) return rc;
+    const int64_t tau = prm->t_floor_ns;
+    const int64_t reach = (int64_t)prm->w_ns + (tau > 0 ? tau : 0);
+    int fail = 0;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < (int64_t)nk; ++s) {
+        uint64_t k = ks[s];
+        if (k >= n) { fail = 1; continue; }
+        uint64_t cap = 1024, L = 0;
+        uint64_t *near = (uint64_t *)malloc(cap * sizeof(uint64_t));
+        for (uint64_t m = 0; m < n && near; ++m) {
+            if (absdiff(t[m], t[k]) > reach) continue;
+            if (L == cap) { cap *= 2; near = (uint64_t *)realloc(near, cap * sizeof(uint64_t)); if (!near) break; }
+            near[L++] = m;
+        }
+        if (!near) { fail = 1; continue; }
+        /* seed flag of a neighbour m (within W of k): its floor partners lie within tau of it */
+        uint8_t sk = 0; uint32_t fk = 0;
+        for (uint64_t a = 0; a < L; ++a) {
+            uint64_t m = near[a];
+            if (m != k && absdiff(t[m], t[k]) > (int64_t)prm->w_ns) continue;
+            int s_m = q[m] >= prm->q_seed;
+            if (!s_m && tau >= 0)
+                for (uint64_t b = 0; b < L && !s_m; ++b) {
+                    uint64_t r = near[b];
+                    if (pmt[r] != pmt[m] && floor_id[pmt[r]] == floor_id[pmt[m]] && absdiff(t[r], t[m]) <= tau)
+                        s_m = 1;
+                }
+            if (m == k) { sk = (uint8_t)s_m; continue; }
+            if (s_m && absdiff(t[k], t[m]) <= (int64_t)pair_limit(thr, n_pmt, pmt[k], pmt[m], prm->w_ns)) ++fk;
+        }
+        seed_k[s] = sk;
+        fold_k[s] = sk ? fk + 1 : 0;
+        free(near);
+    }
+    return fail ? ORC_EINVAL : ORC_OK;
+}

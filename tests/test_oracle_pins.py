@@ -1,0 +1,288 @@
+"""Pins of the oracle against facts outside itself.
+
+* hand-worked boundary slices (tests/golden/hand_cases.json);
+* the literal pure-Python rule, the strict all-pairs C form and the blocked C
+  form agree on random and adversarial slices;
+* closed forms: the floor-coincidence seed count of Poisson streams and the
+  N-fold fire count of thinned Poisson seeds (Palm / Slivnyak);
+* physics: injected Cherenkov tracks always fire and are covered by a window;
+* invariances: time shift, input permutation, PMT relabelling.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from conftest import events_as_tuples, fires_as_tuples, load_hand_cases
+from oracle import literal
+
+HAND = load_hand_cases()
+
+
+# ------------------------------------------------------------- hand cases
+
+@pytest.mark.parametrize("case", HAND, ids=[c["name"] for c in HAND])
+def test_hand_case_literal(case):
+    r = literal.run(case["pmt"], case["t"], case["q"], list(case["floor_id"]), case["thr"].tolist(), **case["params"])
+    assert r["status"] == case["status"], case["cite"]
+    if case["status"] != 0:
+        return
+    assert r["seed"] == case["seed"]
+    assert r["fold"] == case["fold"]
+    assert [list(f) for f in r["fires"]] == case["fires"]
+    assert [list(e) for e in r["events"]] == case["events"]
+
+
+@pytest.mark.parametrize("form", ["strict", "blocked"])
+@pytest.mark.parametrize("case", HAND, ids=[c["name"] for c in HAND])
+def test_hand_case_c(oracle_lib, case, form):
+    r = oracle_lib.run(case["pmt"], case["t"], case["q"], case["floor_id"], case["thr"], case["params"], form)
+    assert r["status"] == case["status"], case["cite"]
+    if case["status"] != 0:
+        return
+    assert r["seed"].tolist() == case["seed"]
+    assert r["fold"].tolist() == case["fold"]
+    assert [list(f) for f in fires_as_tuples(r["fires"])] == case["fires"]
+    assert [list(e) for e in events_as_tuples(r["events"])] == case["events"]
+
+
+# ------------------------------------------------- three forms agree
+
+def _random_case(rng, n, n_pmt, n_floor, span, dense_frac=0.0, tie_frac=0.0):
+    floor_id = rng.integers(0, n_floor, size=n_pmt).astype(np.int32)
+    thr = rng.integers(0, 4000, size=(n_pmt, n_pmt)).astype(np.uint32)    # asymmetric on purpose
+    pmt = rng.integers(0, n_pmt, size=n).astype(np.uint16)
+    t = rng.integers(-span // 2, span // 2, size=n).astype(np.int64) + int(rng.integers(-10**17, 10**17))
+    k = int(dense_frac * n)
+    if k:
+        t[:k] = t[0] + rng.integers(0, 200, size=k)                         # a dense burst
+    k = int(tie_frac * n)
+    if k:
+        t[-k:] = t[-1] + rng.integers(0, 3, size=k)                         # many equal times
+    q = rng.integers(0, 600, size=n).astype(np.uint16)
+    params = dict(q_seed=int(rng.integers(200, 700)), t_floor_ns=int(rng.integers(-1, 60)),
+                  w_ns=int(rng.integers(0, 5000)), min_fold=int(rng.integers(0, 7)),
+                  half_event_ns=int(rng.integers(0, 5000)))
+    return pmt, t, q, floor_id, thr, params
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_literal_strict_blocked_agree(oracle_lib, seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 500))
+    pmt, t, q, floor_id, thr, params = _random_case(rng, n, int(rng.integers(1, 12)), int(rng.integers(1, 4)),
+                                                     int(rng.integers(10, 200000)), dense_frac=0.2 * (seed % 3 == 1),
+                                                     tie_frac=0.3 * (seed % 3 == 2))
+    lit = literal.run(pmt, t, q, floor_id.tolist(), thr.tolist(), **params)
+    s = oracle_lib.run(pmt, t, q, floor_id, thr, params, "strict")
+    b = oracle_lib.run(pmt, t, q, floor_id, thr, params, "blocked")
+    assert lit["status"] == s["status"] == b["status"] == 0
+    assert lit["seed"] == s["seed"].tolist() == b["seed"].tolist()
+    assert lit["fold"] == s["fold"].tolist() == b["fold"].tolist()
+    assert [tuple(f) for f in lit["fires"]] == fires_as_tuples(s["fires"]) == fires_as_tuples(b["fires"])
+    assert [tuple(e) for e in lit["events"]] == events_as_tuples(s["events"]) == events_as_tuples(b["events"])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_strict_blocked_agree_mid_size(oracle_lib, seed):
+    rng = np.random.default_rng(2000 + seed)
+    pmt, t, q, floor_id, thr, params = _random_case(rng, 20000, 30, 6, 3_000_000, dense_frac=0.02, tie_frac=0.02)
+    s = oracle_lib.run(pmt, t, q, floor_id, thr, params, "strict")
+    b = oracle_lib.run(pmt, t, q, floor_id, thr, params, "blocked")
+    for k in ("seed", "fold", "fires", "events"):
+        assert np.array_equal(s[k], b[k]), k
+
+
+def test_strict_blocked_agree_nemo_slice(oracle_lib):
+    from gen import configs as C
+    w = C.nemo(seed=5, length_ns=40_000_000)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    a = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "strict")
+    b = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    for k in ("seed", "fold", "fires", "events"):
+        assert np.array_equal(a[k], b[k]), k
+    assert len(a["fires"]) > 0
+
+
+def test_point_oracle_matches_full(oracle_lib):
+    from gen import configs as C
+    w = C.km3(seed=3, length_ns=10_000_000)
+    g, thr = w.geoms["km3"]
+    s = w.slices[0][1]
+    full = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    rng = np.random.default_rng(9)
+    ks = np.concatenate([rng.choice(s.n, 150, replace=False), np.nonzero(full["seed"])[0][:100]])
+    seed, fold = oracle_lib.point(s.pmt, s.t, s.q, g.floor_id, thr, ks, w.params)
+    assert np.array_equal(seed, full["seed"][ks])
+    assert np.array_equal(fold, full["fold"][ks])
+
+
+# ------------------------------------------------------------ closed forms
+
+def _poisson_stream(rng, rate_per_ns, T):
+    k = rng.poisson(rate_per_ns * T)
+    return np.sort(rng.integers(0, T, size=k)).astype(np.int64)
+
+
+def test_floor_coincidence_seed_rate_closed_form(oracle_lib):
+    """Charge rule off, four PMTs on one floor at 1 MHz for 1 s.
+
+    For independent Poisson streams at integer-ns times, a hit on PMT p has
+    no partner within +-tau (inclusive) with probability
+    exp(-(2 tau + 1) * sum_{p' != p} R_p'), so
+    E[#seeds] = sum_p N_p (1 - exp(-(2 tau + 1) sum_{p' != p} N_p' / T)).
+    The (2 tau + 1) versus 2 tau difference (an exclusive window) is >10 sigma.
+    """
+    rng = np.random.default_rng(77)
+    T, R, tau = 1_000_000_000, 1e-3, 20
+    streams = [_poisson_stream(rng, R, T) for _ in range(4)]
+    pmt = np.concatenate([np.full(len(s), i, np.uint16) for i, s in enumerate(streams)])
+    t = np.concatenate(streams)
+    q = np.zeros(len(t), np.uint16)
+    floor_id = np.zeros(4, np.int32)
+    thr = np.full((4, 4), 20, np.uint32)
+    r = oracle_lib.run(pmt, t, q, floor_id, thr, dict(q_seed=65536, t_floor_ns=tau, w_ns=3000, min_fold=99),
+                       "blocked")
+    N = np.array([len(s) for s in streams], dtype=np.float64)
+
+    def expect(width):
+        return sum(N[p] * (1 - math.exp(-width * (N.sum() - N[p]) / T)) for p in range(4))
+
+    obs = int(r["seed"].sum())
+    e_ok, e_excl = expect(2 * tau + 1), expect(2 * tau)
+    sigma = math.sqrt(2.0 * e_ok)           # seeds come in correlated pairs: variance ~ 2 E
+    assert abs(obs - e_ok) < 4 * sigma, (obs, e_ok, sigma)
+    assert abs(obs - e_excl) > 6 * sigma     # the pin tells the two window conventions apart
+    # pairs: (2 tau + 1) R1 R2 T per PMT pair
+    pairs_expected = 6 * (2 * tau + 1) * R * R * T
+    assert obs > 0.9 * pairs_expected
+
+
+def test_nfold_fire_rate_closed_form(oracle_lib):
+    """Floor rule off; charge seeds an independent thinning of Poisson streams.
+
+    Given a seed on PMT p (Palm / Slivnyak), the other seeds within
+    +-L_pp' (L = min(thr[p][p'], W), inclusive) of it are Poisson with mean
+    mu_p = sum_p' R^s_p' (2 L_pp' + 1) (p' = p included), so
+    E[#fires on p] = N^s_p * P(Poisson(mu_p) >= N - 1).
+    The strongly asymmetric table makes a transposed lookup fail per PMT.
+    """
+    rng = np.random.default_rng(78)
+    P, T, Rs = 8, 1_000_000_000, 5e-5
+    W = 2500
+    thr = np.where(np.arange(P)[:, None] > np.arange(P)[None, :], 2800, 150).astype(np.uint32)
+    np.fill_diagonal(thr, 60)
+    streams = [_poisson_stream(rng, Rs * 2, T) for _ in range(P)]
+    pmt = np.concatenate([np.full(len(s), i, np.uint16) for i, s in enumerate(streams)])
+    t = np.concatenate(streams)
+    q = np.where(rng.random(len(t)) < 0.5, 400, 100).astype(np.uint16)
+    r = oracle_lib.run(pmt, t, q, np.arange(P, dtype=np.int32), thr,
+                       dict(q_seed=300, t_floor_ns=-1, w_ns=W, min_fold=4), "blocked")
+    seeds = r["seed"].astype(bool)
+    Ns = np.array([np.sum(seeds & (pmt == p)) for p in range(P)], dtype=np.float64)
+    L = np.minimum(thr, W).astype(np.float64)
+
+    def expected(table):
+        mu = ((2 * table + 1) * (Ns / T)[None, :]).sum(1)
+        return Ns * stats.poisson.sf(2, mu)           # P(X >= 3)
+
+    e = expected(L)
+    e_t = expected(L.T)
+    fires_p = np.bincount(r["fires"]["pmt_id"], minlength=P).astype(np.float64)
+    sig = np.sqrt(4.0 * e) + 5                         # fires cluster: generous variance
+    assert np.all(np.abs(fires_p - e) < 5 * sig), (fires_p, e)
+    assert np.any(np.abs(fires_p - e_t) > 10 * sig)     # transposed table is rejected
+    assert fires_p.sum() > 5000
+
+
+# ------------------------------------------------------------- physics
+
+def test_injected_tracks_fire_and_are_covered(oracle_lib):
+    """Every track with >= N charge-seeded hits that are pairwise causal fires, and
+    one event window covers all those hits (Sec. 3: Cherenkov hits of one muon
+    are correlated in time and space within 3 us)."""
+    from gen import configs as C
+    w = C.nemo(seed=0)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    r = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    fired = set(int(x) for x in r["fires"]["hit_index"])
+    ev = r["events"]
+    W, N = w.params["w_ns"], w.params["min_fold"]
+    checked = 0
+    pair_ok = pair_all = 0
+    for tr in s.tracks:
+        for a in range(len(tr.pmt)):
+            for b in range(a + 1, len(tr.pmt)):
+                pair_all += 1
+                pair_ok += abs(int(tr.t[a]) - int(tr.t[b])) <= int(thr[tr.pmt[a], tr.pmt[b]])
+        sel = [i for i in range(len(tr.pmt)) if tr.q[i] >= w.params["q_seed"]]
+        if len(sel) < N:
+            continue
+        causal = all(abs(int(tr.t[a]) - int(tr.t[b])) <= min(int(thr[tr.pmt[a], tr.pmt[b]]), W)
+                     for a in sel for b in sel if a != b)
+        if not causal:
+            continue
+        checked += 1
+        for i in sel:
+            assert int(tr.hit_index[i]) in fired
+        lo, hi = min(int(tr.t[i]) for i in sel), max(int(tr.t[i]) for i in sel)
+        assert any(e["t_begin"] <= lo and hi <= e["t_end"] for e in ev)
+    assert checked >= 3
+    # jitter-free track pairs satisfy |dt| <= n d / c <= thr - 20; 3 ns jitter rarely breaks it
+    assert pair_ok >= 0.99 * pair_all
+
+
+# ----------------------------------------------------------- invariances
+
+@pytest.fixture(scope="module")
+def mid_slice():
+    from gen import configs as C
+    w = C.km3(seed=11, length_ns=8_000_000, n_tracks=6)
+    g, thr = w.geoms["km3"]
+    return w, g, thr, w.slices[0][1]
+
+
+def test_time_shift_invariance(oracle_lib, mid_slice):
+    w, g, thr, s = mid_slice
+    a = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params)
+    d = -1_400_000_000_000_000_000 - 123_457
+    b = oracle_lib.run(s.pmt, s.t + d, s.q, g.floor_id, thr, w.params)
+    assert np.array_equal(a["seed"], b["seed"]) and np.array_equal(a["fold"], b["fold"])
+    assert np.array_equal(a["fires"]["t_ns"] + d, b["fires"]["t_ns"])
+    assert np.array_equal(a["fires"]["hit_index"], b["fires"]["hit_index"])
+    for k in ("t_trig", "t_begin", "t_end"):
+        assert np.array_equal(a["events"][k] + d, b["events"][k])
+
+
+def test_permutation_invariance(oracle_lib, mid_slice):
+    w, g, thr, s = mid_slice
+    a = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params)
+    perm = np.random.default_rng(5).permutation(s.n)
+    b = oracle_lib.run(s.pmt[perm], s.t[perm], s.q[perm], g.floor_id, thr, w.params)
+    assert np.array_equal(a["seed"][perm], b["seed"]) and np.array_equal(a["fold"][perm], b["fold"])
+    fb = b["fires"].copy()
+    fb["hit_index"] = perm[fb["hit_index"]]
+    # equal (t, pmt) keys may reorder with the input positions; compare as sorted records
+    key = lambda f: np.lexsort((f["hit_index"], f["pmt_id"], f["t_ns"]))
+    assert np.array_equal(a["fires"][key(a["fires"])], fb[key(fb)])
+    assert np.array_equal(a["events"], b["events"])
+
+
+def test_pmt_relabel_invariance(oracle_lib, mid_slice):
+    w, g, thr, s = mid_slice
+    a = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params)
+    P = g.n_pmt
+    pi = np.random.default_rng(6).permutation(P)           # old id -> new id
+    floor2 = np.empty(P, np.int32)
+    floor2[pi] = g.floor_id
+    thr2 = np.empty_like(thr)
+    thr2[np.ix_(pi, pi)] = thr
+    b = oracle_lib.run(pi[s.pmt].astype(np.uint16), s.t, s.q, floor2, thr2, w.params)
+    assert np.array_equal(a["seed"], b["seed"]) and np.array_equal(a["fold"], b["fold"])
+    sa = sorted(zip(a["fires"]["hit_index"].tolist(), a["fires"]["t_ns"].tolist(), a["fires"]["fold"].tolist()))
+    sb = sorted(zip(b["fires"]["hit_index"].tolist(), b["fires"]["t_ns"].tolist(), b["fires"]["fold"].tolist()))
+    assert sa == sb
+    assert np.array_equal(a["events"], b["events"])
