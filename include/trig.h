@@ -1,0 +1,221 @@
+/*
+ * trig.h -- C ABI of the MI355X muon-trigger library (libtrig.so).
+ *
+ * The library runs the data-parallel hot path of the online muon trigger of
+ * Bouhadef, Morganti and Terreni, "Parallel Neutrino Triggers using GPUs for
+ * an Underwater Telescope" (GPUHEP2014), on one AMD Instinct MI355X:
+ *
+ *   1. ingest a time slice of PMT hits (Sec. 2: the Hit Managers cut the merged
+ *      PMT streams into 200 ms time slices; Sec. 4: each hit reduced to a
+ *      fixed record of charge, time and detection-unit id);
+ *   2. merge the hits into time order (Sec. 4.2: hits are time-sorted on the
+ *      GPU before any trigger; each PMT's stream is already time-ordered);
+ *   3. mark L1 seeds: charge over threshold (Sec. 3, Sec. 4.2 QTRIG) or a
+ *      coincidence of two PMTs of one floor within a short window (Sec. 4.2 FC);
+ *   4. count, for each seed, the other seeds causally correlated with it,
+ *      |t_i - t_j| <= min(thr[pmt_i][pmt_j], W) (Sec. 3: Cherenkov hits of one
+ *      muon are correlated in space and time within less than 3 us);
+ *   5. fire an N-fold trigger on every seed whose count (itself included)
+ *      reaches N;
+ *   6. emit event windows of +-H around every fire, merging windows that
+ *      overlap or touch (Sec. 2: a 6 us window centred on the trigger seed is
+ *      sent to the Event Manager; Sec. 4.2: hits within +-3 us are tagged).
+ *
+ * All arithmetic is integer.  Results are unique (ties in time are ordered by
+ * PMT id, then by input position) and independent of launch configuration.
+ *
+ * Conventions
+ *  - Status codes: 0 = OK, >0 informational, <0 error.  No C++ exception
+ *    crosses this ABI.  After an error, trig_last_error() describes it.
+ *  - Threading: one context per host thread for trig_slice / trig_batch;
+ *    trig_stream_submit and trig_stream_poll are thread-safe with respect to
+ *    each other on one context.
+ *  - hip_stream arguments are hipStream_t values passed as void* (NULL = the
+ *    null stream).  Work is ordered on that stream.
+ */
+#ifndef TRIG_H
+#define TRIG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIG_OK         0
+#define TRIG_PENDING    1   /* poll: the ticket is not finished yet                     */
+#define TRIG_EINVAL    -1   /* null pointer, n_pmt == 0, bad geometry id, bad argument   */
+#define TRIG_ERANGE    -2   /* pmt_id >= n_pmt, n_hits >= 2^32, time span >= 2^31 ns,
+                               or an event window outside int64                         */
+#define TRIG_ENOMEM    -3   /* the request can never fit the HBM budget, or a device
+                               allocation failed                                        */
+#define TRIG_EAGAIN    -4   /* stream admission: budget or slots currently full; retry */
+#define TRIG_EOVERFLOW -5   /* caller capacity too small; n_fires / n_events hold the
+                               required counts and no list was written                 */
+#define TRIG_EHIP      -6   /* HIP runtime error (message in trig_last_error)           */
+#define TRIG_ECANCELED -7   /* poll: the ticket was cancelled                            */
+
+typedef struct trig_ctx trig_ctx;   /* opaque; owns every device buffer it allocates */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
+ * memory the context may hold (0 = 32 GiB).  *out is NULL on failure. */
+int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes);
+
+/* Destroy a context: waits for all submitted stream work to finish (tickets
+ * not yet polled are dropped), then frees every device and host buffer. */
+void trig_destroy(trig_ctx *ctx);
+
+/* Message of the last error on ctx (empty string if none).  Valid until the
+ * next call on ctx. */
+const char *trig_last_error(const trig_ctx *ctx);
+
+/* Library version string. */
+const char *trig_version(void);
+
+/* Tower geometry (Sec. 2: detection units on floors of a tower).
+ *   floor_id[n_pmt]           global floor index of each PMT
+ *   thr_ns[n_pmt * n_pmt]     row-major causality table in ns; thr_ns[i*n_pmt+j]
+ *                             bounds |t_i - t_j| when counting for a seed on PMT i
+ * Host pointers; the arrays are copied, the caller keeps ownership.
+ * 1 <= n_pmt <= 65536.  On success *geom_id names the copy. */
+typedef struct {
+    uint32_t        n_pmt;
+    const int32_t  *floor_id;
+    const uint32_t *thr_ns;
+} trig_geom_desc;
+
+int trig_geom_load(trig_ctx *ctx, const trig_geom_desc *geom, uint32_t *geom_id);
+
+/* Trigger parameters.
+ *   q_seed        charge seed threshold in 0.01 pe (seed if charge >= q_seed;
+ *                 > 65535 disables the charge rule)
+ *   t_floor_ns    floor-coincidence window (inclusive); < 0 disables the rule
+ *   w_ns          cap on the causal window (the table value is min(thr, w_ns))
+ *   min_fold      fire when 1 + correlated seeds >= min_fold
+ *   half_event_ns half width H of the event window [t - H, t + H] */
+typedef struct {
+    uint32_t q_seed;
+    int32_t  t_floor_ns;
+    uint32_t w_ns;
+    uint32_t min_fold;
+    uint32_t half_event_ns;
+} trig_params;
+
+enum { TRIG_MEM_HOST = 0, TRIG_MEM_DEVICE = 1 };
+
+/* One time slice, structure of arrays in any order (the fast path is taken
+ * when the order is a concatenation of time-ordered runs, as PMT streams
+ * are).  mem says whether the three arrays are host or device (HIP) memory.
+ * Device arrays are borrowed until the call returns (stream tickets: until
+ * the poll that returns the result).  tag is echoed in the result. */
+typedef struct {
+    uint32_t        geom_id;
+    uint32_t        mem;
+    uint64_t        n_hits;
+    const uint16_t *pmt_id;   /* [n_hits] */
+    const int64_t  *t_ns;     /* [n_hits] ns, int64 */
+    const uint16_t *charge;   /* [n_hits] 0.01 pe */
+    uint64_t        tag;
+} trig_slice_desc;
+
+/* A fired seed: its time, input position, fold and PMT. 24 bytes. */
+typedef struct {
+    int64_t  t_ns;
+    uint32_t hit_index;
+    uint32_t fold;
+    uint16_t pmt_id;
+    uint16_t pad[3];
+} trig_fire;
+
+/* A merged event window: first fire time, window bounds, number of fires and
+ * the largest fold among them. 32 bytes. */
+typedef struct {
+    int64_t  t_trig, t_begin, t_end;
+    uint32_t n_fire, max_fold;
+} trig_event;
+
+/* Result of one slice.  The caller sets fires/fire_cap, events/event_cap and
+ * seed_flags (host buffers; seed_flags may be NULL, else [n_hits] bytes by
+ * input position, 1 for a seed).  The library fills the counts, status and
+ * tag.  Fires are ordered by (t_ns, pmt_id, hit_index), events by t_begin.
+ * On TRIG_EOVERFLOW n_fires / n_events hold the required counts and no list
+ * is written.  path reports the ordering method used (0: run merge, 1:
+ * general radix sort). */
+typedef struct {
+    trig_fire  *fires;
+    uint64_t    fire_cap, n_fires;
+    trig_event *events;
+    uint64_t    event_cap, n_events;
+    uint8_t    *seed_flags;
+    uint64_t    n_hits, n_seeds, tag;
+    int32_t     status;
+    uint32_t    path;
+} trig_result;
+
+/* Trigger one slice.  Synchronous with respect to the caller's buffers: it
+ * returns after the results are in host memory.  Returns result->status. */
+int trig_slice(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
+               trig_result *result, void *hip_stream);
+
+/* Trigger n slices together: every stage runs once over all slices (device
+ * work queues spread the uneven slices over the GPU).  results[i] receives
+ * slice i; a bad slice gets its own error status and the others complete.
+ * Returns TRIG_OK if every slice succeeded, else the first failing status. */
+int trig_batch(trig_ctx *ctx, uint32_t n, const trig_slice_desc *slices, const trig_params *params,
+               trig_result *results, void *hip_stream);
+
+/* Serving: submit a slice for asynchronous triggering.  The inputs are copied
+ * (host memory) or borrowed (device memory) and admitted when the context's
+ * device budget allows.  Returns TRIG_OK with a ticket, TRIG_EAGAIN when the
+ * budget or the slots are full right now, TRIG_ENOMEM when the slice can
+ * never fit. */
+int trig_stream_submit(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
+                       uint64_t *ticket);
+
+/* Serving: wait up to timeout_us (0 = do not wait, <0 = wait forever) for a
+ * ticket.  Returns TRIG_PENDING if not done, else the slice's status with
+ * *result filled as for trig_slice (the caller's buffers in *result are
+ * used).  A ticket is released by the poll that returns its result. */
+int trig_stream_poll(trig_ctx *ctx, uint64_t ticket, trig_result *result, int32_t timeout_us);
+
+/* Serving statistics since trig_create. */
+typedef struct {
+    uint64_t submitted, completed, rejected_again, in_flight;
+    uint64_t device_bytes_in_use, device_bytes_peak;
+    uint64_t rounds;        /* device rounds launched by the serving loop */
+} trig_stream_stats;
+
+int trig_stream_stats_get(trig_ctx *ctx, trig_stream_stats *out);
+
+/* Tuning knobs of the device pipeline, per PMT-count class.  Chosen by the
+ * autotuner; defaults are used until set.
+ *   seg_target    expected hits per time segment of the ordering stage
+ *   seg_cap       LDS capacity of one segment (2048, 4096 or 8192)
+ *   grid_per_cu   persistent workgroups per compute unit */
+typedef struct {
+    uint32_t seg_target;
+    uint32_t seg_cap;
+    uint32_t grid_per_cu;
+    uint32_t reserved;
+} trig_tune;
+
+int trig_tune_get(trig_ctx *ctx, uint32_t n_pmt, trig_tune *out);
+int trig_tune_set(trig_ctx *ctx, uint32_t n_pmt_max, const trig_tune *tune);
+
+/* Per-kernel timing with HIP events recorded on the launching stream.
+ * enable != 0 starts recording (and clears totals); entries are returned in
+ * launch order of first appearance. */
+typedef struct {
+    char     name[32];
+    uint64_t launches;
+    double   total_ms;
+} trig_kernel_time;
+
+int trig_profile_enable(trig_ctx *ctx, int enable);
+int trig_profile_read(trig_ctx *ctx, trig_kernel_time *out, uint32_t cap, uint32_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIG_H */

@@ -1,0 +1,606 @@
+// Host side of libtrig: context, geometry upload, workspace layout, the
+// synchronous slice / batch entry points, per-kernel timing and tuning.
+// The serving loop (stream submit / poll) lives in serve.hip.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_internal.h"
+
+using namespace trigdev;
+
+// ------------------------------------------------------------------ errors
+
+void ctx_set_error(trig_ctx *c, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::lock_guard<std::mutex> g(c->err_mu);
+    c->err = buf;
+}
+
+int hip_fail(trig_ctx *c, hipError_t e, const char *where) {
+    ctx_set_error(c, "%s: %s", where, hipGetErrorString(e));
+    return TRIG_EHIP;
+}
+
+// ----------------------------------------------------------- device memory
+
+int ctx_reserve(trig_ctx *c, uint64_t bytes) {
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    if (c->bytes_in_use + bytes > c->budget) return TRIG_ENOMEM;
+    c->bytes_in_use += bytes;
+    c->bytes_peak = std::max(c->bytes_peak, c->bytes_in_use);
+    return TRIG_OK;
+}
+
+void ctx_release(trig_ctx *c, uint64_t bytes) {
+    std::lock_guard<std::mutex> g(c->mem_mu);
+    c->bytes_in_use -= std::min(c->bytes_in_use, bytes);
+}
+
+int DevBuf::ensure(trig_ctx *c, size_t want, hipStream_t s) {
+    if (want <= cap) return TRIG_OK;
+    size_t nc = std::max(want, cap + cap / 2);
+    nc = (nc + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    if (ctx_reserve(c, nc - cap) != TRIG_OK) {
+        nc = want;
+        if (ctx_reserve(c, nc - cap) != TRIG_OK) {
+            ctx_set_error(c, "device budget of %llu bytes exceeded (need %llu more)",
+                          (unsigned long long)c->budget, (unsigned long long)(nc - cap));
+            return TRIG_ENOMEM;
+        }
+    }
+    if (ptr) {
+        hipStreamSynchronize(s);
+        hipFree(ptr);
+        ptr = nullptr;
+    }
+    hipError_t e = hipMalloc(&ptr, nc);
+    if (e != hipSuccess) {
+        ctx_release(c, nc);
+        ctx_release(c, cap);
+        cap = 0;
+        ptr = nullptr;
+        ctx_set_error(c, "hipMalloc(%zu): %s", nc, hipGetErrorString(e));
+        return TRIG_ENOMEM;
+    }
+    cap = nc;
+    return TRIG_OK;
+}
+
+void DevBuf::release(trig_ctx *c) {
+    if (ptr) hipFree(ptr);
+    ctx_release(c, cap);
+    ptr = nullptr;
+    cap = 0;
+}
+
+int PinBuf::ensure(size_t want) {
+    if (want <= cap) return TRIG_OK;
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    size_t nc = std::max(want, (size_t)4096);
+    if (hipHostMalloc(&ptr, nc, hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        cap = 0;
+        return TRIG_ENOMEM;
+    }
+    cap = nc;
+    return TRIG_OK;
+}
+
+void PinBuf::release() {
+    if (ptr) hipHostFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+}
+
+// ------------------------------------------------------------------ tuning
+
+trig_tune ctx_tune_for(const trig_ctx *c, uint32_t n_pmt) {
+    for (const auto &t : c->tunes)
+        if (n_pmt <= t.first) return t.second;
+    return c->tunes.back().second;
+}
+
+static uint32_t pbits_of(uint32_t n_pmt) {
+    return n_pmt <= 1 ? 0u : 32u - (uint32_t)__builtin_clz(n_pmt - 1);
+}
+
+// ---------------------------------------------------------------- profiling
+
+static void prof_mark(void *vc, const char *name, int phase) {
+    trig_ctx *c = (trig_ctx *)vc;
+    if (!c->prof_on) return;
+    hipEvent_t ev;
+    if (c->ev_pool.empty()) {
+        if (hipEventCreate(&ev) != hipSuccess) return;
+    } else {
+        ev = c->ev_pool.back();
+        c->ev_pool.pop_back();
+    }
+    hipEventRecord(ev, c->prof_stream);
+    c->prof_pending.push_back({name, phase, ev});
+}
+
+// Called after the profiled stream was synchronised.
+static void prof_collect(trig_ctx *c) {
+    std::vector<ProfMark> &v = c->prof_pending;
+    for (size_t i = 0; i < v.size(); ++i) {
+        if (v[i].phase != 0) continue;
+        for (size_t j = i + 1; j < v.size(); ++j) {
+            if (v[j].phase == 1 && v[j].name == v[i].name) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, v[i].ev, v[j].ev) == hipSuccess) {
+                    auto it = std::find_if(c->prof.begin(), c->prof.end(),
+                                           [&](const trig_kernel_time &k) { return v[i].name == k.name; });
+                    if (it == c->prof.end()) {
+                        trig_kernel_time k = {};
+                        snprintf(k.name, sizeof k.name, "%s", v[i].name.c_str());
+                        c->prof.push_back(k);
+                        it = c->prof.end() - 1;
+                    }
+                    it->launches += 1;
+                    it->total_ms += ms;
+                }
+                break;
+            }
+        }
+    }
+    for (auto &m : v) c->ev_pool.push_back(m.ev);
+    v.clear();
+}
+
+// ------------------------------------------------------------ one job
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte layout of one slice's workspace; returns the size.
+static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLayout &L) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    const uint64_t n_chunks = (n + CHUNK - 1) / CHUNK;
+    const uint64_t n_tiles = (n + TILE - 1) / TILE;
+    L.pos_cap = 2 * n + 65536;
+    L.in_pmt = host_input ? take(n * 2) : SIZE_MAX;
+    L.in_t = host_input ? take(n * 8) : SIZE_MAX;
+    L.in_q = host_input ? take(n * 2) : SIZE_MAX;
+    L.part = take(std::max<uint64_t>(n_chunks, 1) * sizeof(ChunkPart));
+    L.pos = take(L.pos_cap * 4);
+    L.o_t = take(n * 4 + 4);
+    L.o_pq = take(n * 4 + 4);
+    L.o_idx = take(n * 4 + 4);
+    L.seed_mask = take(std::max<uint64_t>(n_tiles, 1) * (TILE / 64) * 8);
+    L.tile_seeds = take(std::max<uint64_t>(n_tiles, 1) * 4);
+    L.s_t = take(n * 4 + 4);
+    L.s_pq = take(n * 4 + 4);
+    L.s_idx = take(n * 4 + 4);
+    L.s_fold = take(n * 4 + 4);
+    L.ctile = take((n / CTILE + 2) * 4);
+    L.fires = take(n * sizeof(trig_fire) + 32);
+    L.events = take(n * sizeof(trig_event) + 32);
+    L.flags = want_flags ? take(n + 4) : SIZE_MAX;
+    return o;
+}
+
+int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, bool want_flags_any,
+                 const uint8_t *want_flags, hipStream_t s) {
+    stream = s;
+    params = *prm;
+    slices.assign(n, SliceInfo{});
+    size_t total = 0;
+    uint32_t chunk_base = 0, tile_base = 0;
+    uint32_t cap_max = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        SliceInfo &si = slices[i];
+        si.desc = d[i];
+        si.host_status = TRIG_OK;
+        if (d[i].geom_id >= c->geoms.size()) {
+            si.host_status = TRIG_EINVAL;
+            ctx_set_error(c, "slice %u: unknown geom_id %u", i, d[i].geom_id);
+        } else if (d[i].n_hits >= (1ull << 32)) {
+            si.host_status = TRIG_ERANGE;
+            ctx_set_error(c, "slice %u: n_hits >= 2^32", i);
+        } else if (d[i].n_hits && (!d[i].pmt_id || !d[i].t_ns || !d[i].charge)) {
+            si.host_status = TRIG_EINVAL;
+            ctx_set_error(c, "slice %u: null input array", i);
+        } else if (d[i].mem != TRIG_MEM_HOST && d[i].mem != TRIG_MEM_DEVICE) {
+            si.host_status = TRIG_EINVAL;
+            ctx_set_error(c, "slice %u: bad mem kind", i);
+        }
+        const uint64_t nh = si.host_status == TRIG_OK ? d[i].n_hits : 0;
+        si.n = nh;
+        si.want_flags = want_flags && want_flags[i];
+        si.ws_off = total;
+        total += slice_layout(nh, d[i].mem == TRIG_MEM_HOST, si.want_flags, si.L);
+        si.chunk_base = chunk_base;
+        si.n_chunks = (uint32_t)((nh + CHUNK - 1) / CHUNK);
+        si.tile_base = tile_base;
+        si.n_tiles = (uint32_t)((nh + TILE - 1) / TILE);
+        chunk_base += si.n_chunks;
+        tile_base += si.n_tiles;
+        const uint32_t np = (d[i].geom_id < c->geoms.size()) ? c->geoms[d[i].geom_id].n_pmt : 1u;
+        si.tune = ctx_tune_for(c, np);
+        cap_max = std::max(cap_max, si.tune.seg_cap);
+    }
+    (void)want_flags_any;
+    seg_cap = cap_max ? cap_max : 4096;
+    total_chunks = chunk_base;
+    total_tiles = tile_base;
+    int rc = ws.ensure(c, total, s);
+    if (rc) return rc;
+    const size_t desc_bytes = align256(n * sizeof(SliceDev)) + align256(n * sizeof(Plan)) + 256;
+    rc = dmeta.ensure(c, desc_bytes, s);
+    if (rc) return rc;
+    if (h_slices.ensure(n * sizeof(SliceDev) + 64) || h_plans.ensure(n * sizeof(Plan) + 64)) {
+        ctx_set_error(c, "pinned host allocation failed");
+        return TRIG_ENOMEM;
+    }
+    d_slices = (SliceDev *)dmeta.ptr;
+    d_plans = (Plan *)((char *)dmeta.ptr + align256(n * sizeof(SliceDev)));
+    d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
+    SliceDev *hs = (SliceDev *)h_slices.ptr;
+    char *base = (char *)ws.ptr;
+    for (uint32_t i = 0; i < n; ++i) {
+        SliceInfo &si = slices[i];
+        SliceDev S = {};
+        char *b = base + si.ws_off;
+        const SliceLayout &L = si.L;
+        const uint64_t nh = si.n;
+        if (si.host_status == TRIG_OK) {
+            const GeomDev &g = c->geoms[si.desc.geom_id];
+            S.floor_id = g.floor_id;
+            S.thr32 = g.thr32;
+            S.thr16 = g.thr16;
+            S.n_pmt = g.n_pmt;
+            S.pbits = pbits_of(g.n_pmt);
+        } else {
+            const GeomDev &g = c->geoms.empty() ? GeomDev{} : c->geoms[0];
+            S.floor_id = g.floor_id; S.thr32 = g.thr32; S.thr16 = g.thr16; S.n_pmt = std::max(1u, g.n_pmt);
+        }
+        if (si.desc.mem == TRIG_MEM_HOST && nh) {
+            S.pmt = (const uint16_t *)(b + L.in_pmt);
+            S.t = (const int64_t *)(b + L.in_t);
+            S.q = (const uint16_t *)(b + L.in_q);
+            hipError_t e = hipMemcpyAsync((void *)S.pmt, si.desc.pmt_id, nh * 2, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync((void *)S.t, si.desc.t_ns, nh * 8, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync((void *)S.q, si.desc.charge, nh * 2, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(c, e, "H2D of slice inputs");
+        } else {
+            S.pmt = si.desc.pmt_id;
+            S.t = si.desc.t_ns;
+            S.q = si.desc.charge;
+        }
+        S.n = nh;
+        S.chunk_base = si.chunk_base;
+        S.n_chunks = si.n_chunks;
+        S.tile_base = si.tile_base;
+        S.n_tiles = si.n_tiles;
+        S.seg_target = std::min(si.tune.seg_target, seg_cap / 2 ? seg_cap / 2 : 1);
+        S.pos_cap = L.pos_cap;
+        S.part = (ChunkPart *)(b + L.part);
+        S.pos = (uint32_t *)(b + L.pos);
+        S.o_t = (uint32_t *)(b + L.o_t);
+        S.o_pq = (uint32_t *)(b + L.o_pq);
+        S.o_idx = (uint32_t *)(b + L.o_idx);
+        S.seed_mask = (uint64_t *)(b + L.seed_mask);
+        S.tile_seeds = (uint32_t *)(b + L.tile_seeds);
+        S.s_t = (uint32_t *)(b + L.s_t);
+        S.s_pq = (uint32_t *)(b + L.s_pq);
+        S.s_idx = (uint32_t *)(b + L.s_idx);
+        S.s_fold = (uint32_t *)(b + L.s_fold);
+        S.ctile_fires = (uint32_t *)(b + L.ctile);
+        // event scratch reuses the ordered arrays (dead once the seed list exists)
+        S.fire_ev = S.o_t;
+        S.ev_first = S.o_pq;
+        S.ev_max = S.o_idx;
+        S.fires = (trig_fire *)(b + L.fires);
+        S.events = (trig_event *)(b + L.events);
+        S.seed_flags = si.want_flags ? (uint8_t *)(b + L.flags) : nullptr;
+        S.plan = d_plans + i;
+        hs[i] = S;
+        si.dev = S;
+    }
+    hipError_t e = hipMemcpyAsync(d_slices, hs, n * sizeof(SliceDev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "H2D of slice descriptors");
+    batch = {};
+    batch.slices = d_slices;
+    batch.plans = d_plans;
+    batch.n_slices = n;
+    batch.total_chunks = total_chunks;
+    batch.total_tiles = total_tiles;
+    batch.tail_state = ST_FAST;
+    batch.counters = d_counters;
+    batch.prm = params;
+    return TRIG_OK;
+}
+
+int Job::launch(trig_ctx *c, bool profile) {
+    void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
+    TrigLaunchCfg cfg = c->cfg;
+    cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices.empty() ? 2 : slices[0].tune.grid_per_cu);
+    hipError_t e = trig_launch_front(batch, seg_cap, cfg, stream, mark, c);
+    if (e != hipSuccess) return hip_fail(c, e, "front kernels");
+    e = trig_launch_tail(batch, cfg, stream, mark, c);
+    if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
+    e = hipMemcpyAsync(h_plans.ptr, d_plans, slices.size() * sizeof(Plan), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "D2H of plans");
+    return TRIG_OK;
+}
+
+// After the plans arrived on the host: run the general ordering for the slices
+// that need it, then their tail.
+int Job::generic_pass(trig_ctx *c, bool profile) {
+    Plan *hp = (Plan *)h_plans.ptr;
+    std::vector<uint32_t> todo;
+    for (uint32_t i = 0; i < slices.size(); ++i)
+        if (slices[i].host_status == TRIG_OK && hp[i].state == ST_NEED_GENERIC) todo.push_back(i);
+    if (todo.empty()) return TRIG_OK;
+    void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
+    for (uint32_t i : todo) {
+        SliceInfo &si = slices[i];
+        const size_t need = trig_generic_scratch_bytes(si.n);
+        int rc = gscratch.ensure(c, need, stream);
+        if (rc) return rc;
+        const uint64_t span = (uint64_t)hp[i].t_max - (uint64_t)hp[i].t_min;
+        const uint32_t span_bits = span ? 64u - (uint32_t)__builtin_clzll(span) : 0u;
+        const uint32_t key_bits = span_bits + si.dev.pbits;
+        hipError_t e = trig_launch_generic_slice(si.dev, hp[i], key_bits, gscratch.ptr, stream, mark, c);
+        if (e != hipSuccess) return hip_fail(c, e, "general ordering");
+    }
+    BatchDev b2 = batch;
+    b2.tail_state = ST_GENERIC_DONE;
+    TrigLaunchCfg cfg = c->cfg;
+    cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices[0].tune.grid_per_cu);
+    hipError_t e = trig_launch_tail(b2, cfg, stream, mark, c);
+    if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
+    e = hipMemcpyAsync(h_plans.ptr, d_plans, slices.size() * sizeof(Plan), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "D2H of plans");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise (general path)");
+    return TRIG_OK;
+}
+
+// Copy the results of slice i into the caller's result record.
+int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
+    const SliceInfo &si = slices[i];
+    const Plan &P = ((Plan *)h_plans.ptr)[i];
+    r->tag = si.desc.tag;
+    r->n_hits = si.desc.n_hits;
+    r->path = (P.state == ST_GENERIC_DONE) ? 1u : 0u;
+    r->n_seeds = r->n_fires = r->n_events = 0;
+    if (si.host_status != TRIG_OK) return r->status = si.host_status;
+    if (P.status != TRIG_OK) {
+        ctx_set_error(c, "slice %u: input out of range (PMT id, time span or event window)", i);
+        return r->status = P.status;
+    }
+    if (si.n == 0) return r->status = TRIG_OK;
+    r->n_seeds = P.n_seeds;
+    r->n_fires = P.n_fires;
+    r->n_events = P.n_events;
+    if ((P.n_fires && (!r->fires || r->fire_cap < P.n_fires)) ||
+        (P.n_events && (!r->events || r->event_cap < P.n_events))) {
+        ctx_set_error(c, "slice %u: result capacity too small (need %u fires, %u events)", i, P.n_fires,
+                      P.n_events);
+        return r->status = TRIG_EOVERFLOW;
+    }
+    hipError_t e = hipSuccess;
+    if (P.n_fires)
+        e = hipMemcpyAsync(r->fires, si.dev.fires, (size_t)P.n_fires * sizeof(trig_fire), hipMemcpyDeviceToHost,
+                           stream);
+    if (e == hipSuccess && P.n_events)
+        e = hipMemcpyAsync(r->events, si.dev.events, (size_t)P.n_events * sizeof(trig_event),
+                           hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess && r->seed_flags && si.dev.seed_flags)
+        e = hipMemcpyAsync(r->seed_flags, si.dev.seed_flags, si.n, hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return r->status = hip_fail(c, e, "D2H of results");
+    return r->status = TRIG_OK;
+}
+
+void Job::release(trig_ctx *c) {
+    ws.release(c);
+    dmeta.release(c);
+    gscratch.release(c);
+    h_slices.release();
+    h_plans.release();
+}
+
+static int check_params(trig_ctx *c, const trig_params *p) {
+    if (!p) {
+        ctx_set_error(c, "null params");
+        return TRIG_EINVAL;
+    }
+    if ((uint64_t)p->half_event_ns > (1ull << 62)) {
+        ctx_set_error(c, "half_event_ns too large");
+        return TRIG_EINVAL;
+    }
+    return TRIG_OK;
+}
+
+int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
+             hipStream_t s) {
+    int rc = check_params(c, prm);
+    if (rc) return rc;
+    if (n == 0) return TRIG_OK;
+    if (!d || !res) {
+        ctx_set_error(c, "null slices or results");
+        return TRIG_EINVAL;
+    }
+    std::vector<uint8_t> flags(n);
+    bool any = false;
+    for (uint32_t i = 0; i < n; ++i) {
+        flags[i] = res[i].seed_flags != nullptr;
+        any |= flags[i];
+    }
+    Job &J = c->sync_job;
+    const bool prof = c->prof_on;
+    if (prof) c->prof_stream = s;
+    rc = J.prepare(c, n, d, prm, any, flags.data(), s);
+    if (rc) return rc;
+    rc = J.launch(c, prof);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise");
+    rc = J.generic_pass(c, prof);
+    if (rc) return rc;
+    int first_bad = TRIG_OK;
+    for (uint32_t i = 0; i < n; ++i) {
+        const int st = J.deliver(c, i, &res[i]);
+        if (st != TRIG_OK && first_bad == TRIG_OK) first_bad = st;
+    }
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise results");
+    if (prof) prof_collect(c);
+    return first_bad;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char *trig_version(void) { return "libtrig 0.1 gfx950"; }
+
+int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
+    if (!out) return TRIG_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TRIG_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TRIG_EHIP;
+    trig_ctx *c = new trig_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (64ull << 30);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return TRIG_EHIP;
+    }
+    c->cfg.n_cu = prop.multiProcessorCount;
+    c->cfg.persist_per_cu = 2;
+    trig_tune def = {2048, 4096, 2, 0};
+    c->tunes.push_back({0xFFFFFFFFu, def});
+    *out = c;
+    return TRIG_OK;
+}
+
+void trig_destroy(trig_ctx *c) {
+    if (!c) return;
+    serve_shutdown(c);
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    c->sync_job.release(c);
+    for (auto &g : c->geoms) {
+        hipFree(g.floor_id);
+        hipFree(g.thr32);
+        hipFree(g.thr16);
+    }
+    for (auto ev : c->ev_pool) hipEventDestroy(ev);
+    for (auto &m : c->prof_pending) hipEventDestroy(m.ev);
+    delete c;
+}
+
+const char *trig_last_error(const trig_ctx *c) {
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
+    if (!c) return TRIG_EINVAL;
+    if (!g || !geom_id || !g->floor_id || !g->thr_ns || g->n_pmt == 0 || g->n_pmt > 65536) {
+        ctx_set_error(c, "bad geometry descriptor");
+        return TRIG_EINVAL;
+    }
+    hipSetDevice(c->device);
+    const uint64_t P = g->n_pmt;
+    const uint64_t bytes = P * 4 + P * P * 4 + P * P * 2;
+    if (ctx_reserve(c, bytes) != TRIG_OK) {
+        ctx_set_error(c, "device budget exceeded by geometry");
+        return TRIG_ENOMEM;
+    }
+    GeomDev d = {};
+    d.n_pmt = g->n_pmt;
+    std::vector<uint16_t> t16(P * P);
+    for (uint64_t i = 0; i < P * P; ++i) t16[i] = (uint16_t)std::min<uint32_t>(g->thr_ns[i], 65535u);
+    hipError_t e = hipMalloc(&d.floor_id, P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.thr32, P * P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.thr16, P * P * 2);
+    if (e == hipSuccess) e = hipMemcpy(d.floor_id, g->floor_id, P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.thr32, g->thr_ns, P * P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.thr16, t16.data(), P * P * 2, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(d.floor_id);
+        hipFree(d.thr32);
+        hipFree(d.thr16);
+        ctx_release(c, bytes);
+        return hip_fail(c, e, "geometry upload");
+    }
+    std::lock_guard<std::mutex> lk(c->geom_mu);
+    c->geoms.push_back(d);
+    *geom_id = (uint32_t)(c->geoms.size() - 1);
+    return TRIG_OK;
+}
+
+int trig_slice(trig_ctx *c, const trig_slice_desc *slice, const trig_params *params, trig_result *result,
+               void *hip_stream) {
+    if (!c) return TRIG_EINVAL;
+    if (!slice || !result) {
+        ctx_set_error(c, "null slice or result");
+        return TRIG_EINVAL;
+    }
+    hipSetDevice(c->device);
+    int rc = run_sync(c, 1, slice, params, result, (hipStream_t)hip_stream);
+    if (rc != TRIG_OK && result->status == TRIG_OK) result->status = rc;
+    return rc;
+}
+
+int trig_batch(trig_ctx *c, uint32_t n, const trig_slice_desc *slices, const trig_params *params,
+               trig_result *results, void *hip_stream) {
+    if (!c) return TRIG_EINVAL;
+    hipSetDevice(c->device);
+    return run_sync(c, n, slices, params, results, (hipStream_t)hip_stream);
+}
+
+int trig_tune_get(trig_ctx *c, uint32_t n_pmt, trig_tune *out) {
+    if (!c || !out) return TRIG_EINVAL;
+    *out = ctx_tune_for(c, n_pmt);
+    return TRIG_OK;
+}
+
+int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
+    if (!c || !t) return TRIG_EINVAL;
+    if (!(t->seg_cap == 2048 || t->seg_cap == 4096 || t->seg_cap == 8192) || t->seg_target == 0 ||
+        t->grid_per_cu == 0 || t->grid_per_cu > 16) {
+        ctx_set_error(c, "bad tuning values");
+        return TRIG_EINVAL;
+    }
+    auto it = std::find_if(c->tunes.begin(), c->tunes.end(),
+                           [&](const std::pair<uint32_t, trig_tune> &p) { return p.first == n_pmt_max; });
+    if (it != c->tunes.end()) it->second = *t;
+    else c->tunes.push_back({n_pmt_max, *t});
+    std::sort(c->tunes.begin(), c->tunes.end(),
+              [](const std::pair<uint32_t, trig_tune> &a, const std::pair<uint32_t, trig_tune> &b) {
+                  return a.first < b.first;
+              });
+    return TRIG_OK;
+}
+
+int trig_profile_enable(trig_ctx *c, int enable) {
+    if (!c) return TRIG_EINVAL;
+    c->prof_on = enable != 0;
+    c->prof.clear();
+    return TRIG_OK;
+}
+
+int trig_profile_read(trig_ctx *c, trig_kernel_time *out, uint32_t cap, uint32_t *n_out) {
+    if (!c || !n_out) return TRIG_EINVAL;
+    *n_out = (uint32_t)c->prof.size();
+    for (uint32_t i = 0; i < cap && i < c->prof.size(); ++i) out[i] = c->prof[i];
+    return TRIG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Host-side internals of libtrig shared by api.hip and serve.hip.
+#pragma once
+
+#include <condition_variable>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "trig_dev.h"
+
+struct trig_ctx;
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    int ensure(trig_ctx *c, size_t want, hipStream_t s);   // grows; contents not kept
+    void release(trig_ctx *c);
+};
+
+struct PinBuf {
+    void *ptr = nullptr;
+    size_t cap = 0;
+    int ensure(size_t want);
+    void release();
+};
+
+struct GeomDev {
+    uint32_t n_pmt = 0;
+    int32_t *floor_id = nullptr;
+    uint32_t *thr32 = nullptr;
+    uint16_t *thr16 = nullptr;
+};
+
+// Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
+struct SliceLayout {
+    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, seed_mask, tile_seeds;
+    size_t s_t, s_pq, s_idx, s_fold, ctile, fires, events, flags;
+    uint64_t pos_cap;
+};
+
+struct SliceInfo {
+    trig_slice_desc desc;
+    int host_status;
+    uint64_t n;
+    bool want_flags;
+    size_t ws_off;
+    SliceLayout L;
+    uint32_t chunk_base, n_chunks, tile_base, n_tiles;
+    trig_tune tune;
+    trigdev::SliceDev dev;
+};
+
+// One device round over a set of slices: workspace, descriptors, plans.
+struct Job {
+    std::vector<SliceInfo> slices;
+    trig_params params;
+    hipStream_t stream = nullptr;
+    uint32_t seg_cap = 4096;
+    uint32_t total_chunks = 0, total_tiles = 0;
+    DevBuf ws, dmeta, gscratch;
+    PinBuf h_slices, h_plans;
+    trigdev::SliceDev *d_slices = nullptr;
+    trigdev::Plan *d_plans = nullptr;
+    uint32_t *d_counters = nullptr;
+    trigdev::BatchDev batch;
+
+    int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, bool want_flags_any,
+                const uint8_t *want_flags, hipStream_t s);
+    int launch(trig_ctx *c, bool profile);
+    int generic_pass(trig_ctx *c, bool profile);
+    int deliver(trig_ctx *c, uint32_t i, trig_result *r);
+    void release(trig_ctx *c);
+};
+
+struct ProfMark {
+    std::string name;
+    int phase;
+    hipEvent_t ev;
+};
+
+struct ServeState;   // serve.hip
+
+struct trig_ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    std::string err;
+    std::mutex err_mu;
+    TrigLaunchCfg cfg = {256, 2};
+    std::mutex geom_mu;
+    std::vector<GeomDev> geoms;
+    std::mutex mem_mu;
+    uint64_t bytes_in_use = 0, bytes_peak = 0;
+    std::vector<std::pair<uint32_t, trig_tune>> tunes;
+    Job sync_job;
+    bool prof_on = false;
+    hipStream_t prof_stream = nullptr;
+    std::vector<ProfMark> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<trig_kernel_time> prof;
+    ServeState *serve = nullptr;
+};
+
+void ctx_set_error(trig_ctx *c, const char *fmt, ...);
+int hip_fail(trig_ctx *c, hipError_t e, const char *where);
+int ctx_reserve(trig_ctx *c, uint64_t bytes);
+void ctx_release(trig_ctx *c, uint64_t bytes);
+trig_tune ctx_tune_for(const trig_ctx *c, uint32_t n_pmt);
+int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
+             hipStream_t s);
+void serve_shutdown(trig_ctx *c);

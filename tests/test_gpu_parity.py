@@ -1,0 +1,234 @@
+"""GPU parity: the HIP library against the CPU oracle, byte for byte.
+
+Every output of the trigger is an integer, so the bar is exact equality of the
+fire list (t, input index, fold, PMT), the event list, the seed count and the
+per-hit seed flags.
+"""
+import numpy as np
+import pytest
+
+from conftest import load_hand_cases
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1411_3968_amd import trig
+    return trig
+
+
+@pytest.fixture(scope="module")
+def tr(T):
+    t = T.Trigger(0)
+    yield t
+    t.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import cpu
+    return cpu
+
+
+_GEOM = {}
+
+
+def gid_for(tr, floor_id, thr):
+    key = (floor_id.tobytes(), thr.tobytes())
+    if key not in _GEOM:
+        _GEOM[key] = tr.load_geometry(floor_id, thr)
+    return _GEOM[key]
+
+
+def check(got, ref, flags=True):
+    assert got["status"] == 0, got["status"]
+    assert got["n_seeds"] == int(ref["seed"].sum())
+    assert got["n_fires"] == len(ref["fires"])
+    assert np.array_equal(got["fires"], ref["fires"])
+    assert np.array_equal(got["events"], ref["events"])
+    if flags and "seed_flags" in got:
+        assert np.array_equal(got["seed_flags"], ref["seed"])
+
+
+def to_dev(s):
+    import torch
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(s.pmt).view(np.int16)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(s.t)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(s.q).view(np.int16)).to(dev))
+
+
+HAND = load_hand_cases()
+
+
+@pytest.mark.parametrize("case", HAND, ids=[c["name"] for c in HAND])
+def test_hand_cases(tr, case):
+    gid = gid_for(tr, case["floor_id"], case["thr"])
+    got = tr.slice(gid, case["pmt"], case["t"], case["q"], case["params"], seed_flags=True)
+    assert got["status"] == case["status"], case["cite"]
+    if case["status"] != 0:
+        return
+    assert got["seed_flags"].tolist() == case["seed"]
+    assert [[int(f["t_ns"]), int(f["hit_index"]), int(f["fold"]), int(f["pmt_id"])] for f in got["fires"]] == case["fires"]
+    assert [[int(e["t_trig"]), int(e["t_begin"]), int(e["t_end"]), int(e["n_fire"]), int(e["max_fold"])]
+            for e in got["events"]] == case["events"]
+
+
+def _random_case(rng, n, n_pmt, n_floor, span, dense_frac=0.0, tie_frac=0.0):
+    floor_id = rng.integers(0, n_floor, size=n_pmt).astype(np.int32)
+    thr = rng.integers(0, 4000, size=(n_pmt, n_pmt)).astype(np.uint32)
+    pmt = rng.integers(0, n_pmt, size=n).astype(np.uint16)
+    t = rng.integers(0, span, size=n).astype(np.int64) + int(rng.integers(-10**17, 10**17))
+    k = int(dense_frac * n)
+    if k:
+        t[:k] = t[0] + rng.integers(0, 200, size=k)
+    k = int(tie_frac * n)
+    if k:
+        t[-k:] = t[-1] + rng.integers(0, 3, size=k)
+    q = rng.integers(0, 600, size=n).astype(np.uint16)
+    params = dict(q_seed=int(rng.integers(200, 700)), t_floor_ns=int(rng.integers(-1, 60)),
+                  w_ns=int(rng.integers(0, 5000)), min_fold=int(rng.integers(0, 7)),
+                  half_event_ns=int(rng.integers(0, 5000)))
+    return pmt, t, q, floor_id, thr, params
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_slices(tr, orc, seed):
+    rng = np.random.default_rng(5000 + seed)
+    n = int(rng.integers(1, 30000)) if seed % 4 else int(rng.integers(1, 300))
+    pmt, t, q, floor_id, thr, params = _random_case(rng, n, int(rng.integers(1, 40)), int(rng.integers(1, 6)),
+                                                     int(rng.integers(10, 5_000_000)),
+                                                     dense_frac=0.05 * (seed % 3 == 1), tie_frac=0.1 * (seed % 3 == 2))
+    if seed % 2:                       # runs per PMT, like DAQ streams
+        o = np.lexsort((t, pmt))
+        pmt, t, q = pmt[o], t[o], q[o]
+    gid = gid_for(tr, floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, params, seed_flags=True)
+    ref = orc.run(pmt, t, q, floor_id, thr, params, "strict" if n < 5000 else "blocked")
+    check(got, ref)
+
+
+@pytest.mark.parametrize("order", ["runs", "sorted", "shuffled"])
+@pytest.mark.parametrize("key", ["nemo", "km3"])
+def test_tower_slices(tr, orc, key, order):
+    from gen import configs as C
+    w = (C.nemo if key == "nemo" else C.km3)(seed=21, length_ns=30_000_000, n_tracks=5, order=order)
+    g, thr = w.geoms[key]
+    s = w.slices[0][1]
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, s.pmt, s.t, s.q, w.params, seed_flags=True)
+    ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["path"] == (1 if order == "shuffled" else 0)
+
+
+@pytest.mark.parametrize("key", ["nemo", "km3"])
+def test_full_size_tower_device_inputs(tr, orc, key):
+    from gen import configs as C
+    w = C.nemo() if key == "nemo" else C.km3()
+    g, thr = w.geoms[key]
+    s = w.slices[0][1]
+    gid = gid_for(tr, g.floor_id, thr)
+    dp, dt, dq = to_dev(s)
+    got = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
+    ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["path"] == 0 and got["n_fires"] > 0
+
+
+def test_repeat_is_bit_identical(tr):
+    from gen import configs as C
+    w = C.km3(seed=8, length_ns=50_000_000)
+    g, thr = w.geoms["km3"]
+    s = w.slices[0][1]
+    gid = gid_for(tr, g.floor_id, thr)
+    dp, dt, dq = to_dev(s)
+    first = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
+    for _ in range(9):
+        again = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
+        assert np.array_equal(first["fires"], again["fires"])
+        assert np.array_equal(first["events"], again["events"])
+        assert np.array_equal(first["seed_flags"], again["seed_flags"])
+
+
+def test_dense_segment_takes_general_path(tr, orc):
+    """A burst far denser than a segment's LDS capacity: the run-merge ordering hands
+    the slice to the general radix path; results are unchanged."""
+    from gen import configs as C
+    w = C.km3(seed=9, length_ns=20_000_000, n_tracks=0)
+    g, thr = w.geoms["km3"]
+    s = w.slices[0][1]
+    rng = np.random.default_rng(3)
+    k = 20000
+    bt = s.t.min() + 5_000_000 + np.sort(rng.integers(0, 500, size=k))
+    bp = np.full(k, 17, np.uint16)
+    bq = rng.integers(0, 500, size=k).astype(np.uint16)
+    pmt = np.concatenate([s.pmt, bp])
+    t = np.concatenate([s.t, bt])
+    q = np.concatenate([s.q, bq])
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
+    ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["path"] == 1
+
+
+def test_errors(T, tr):
+    from gen import configs as C
+    w = C.nemo(seed=4, length_ns=5_000_000)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    gid = gid_for(tr, g.floor_id, thr)
+    bad = s.pmt.copy()
+    bad[17] = 32
+    r = tr.slice(gid, bad, s.t, s.q, w.params)
+    assert r["status"] == T.TRIG_ERANGE
+    t2 = s.t.copy()
+    t2[3] = t2.min() + (1 << 31)
+    r = tr.slice(gid, s.pmt, t2, s.q, w.params)
+    assert r["status"] == T.TRIG_ERANGE
+    ok = tr.slice(gid, s.pmt, s.t, s.q, dict(w.params, min_fold=1))
+    assert ok["n_fires"] > 2
+    small = tr.slice(gid, s.pmt, s.t, s.q, dict(w.params, min_fold=1), fire_cap=1, event_cap=1)
+    assert small["status"] == T.TRIG_EOVERFLOW
+    assert small["n_fires"] == ok["n_fires"] and small["n_events"] == ok["n_events"]
+    with pytest.raises(T.TrigError):
+        T.trig_slice(tr.ctx, 12345, s.pmt, s.t, s.q, w.params)
+
+
+def test_batch_matches_alone_and_oracle(tr, orc):
+    from gen import configs as C
+    w = C.batch(seed=2, n_slices=24, scale=0.08)
+    gids = {k: gid_for(tr, g.floor_id, thr) for k, (g, thr) in w.geoms.items()}
+    sl = [(gids[k], s.pmt, s.t, s.q) for k, s in w.slices]
+    bad = w.slices[5][1].pmt.copy()
+    bad[0] = 500
+    sl[5] = (sl[5][0], bad, sl[5][2], sl[5][3])
+    res = tr.batch(sl, w.params, seed_flags=True)
+    assert res[5]["status"] == -2
+    for i, (k, s) in enumerate(w.slices):
+        if i == 5:
+            continue
+        g, thr = w.geoms[k]
+        ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+        check(res[i], ref)
+        alone = tr.slice(gids[k], s.pmt, s.t, s.q, w.params, seed_flags=True)
+        assert np.array_equal(alone["fires"], res[i]["fires"])
+        assert np.array_equal(alone["events"], res[i]["events"])
+
+
+def test_block_slice_reduced(tr, orc):
+    """2688-PMT block (dense 2688^2 table, row groups on the 8 XCDs), 20 ms."""
+    from gen import configs as C
+    w = C.block_workload(seed=3, length_ns=20_000_000, n_tracks=20)
+    g, thr = w.geoms["block"]
+    s = w.slices[0][1]
+    gid = gid_for(tr, g.floor_id, thr)
+    dp, dt, dq = to_dev(s)
+    got = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
+    ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
