@@ -178,6 +178,11 @@ int trig_stream_submit(trig_ctx *ctx, const trig_slice_desc *slice, const trig_p
  * used).  A ticket is released by the poll that returns its result. */
 int trig_stream_poll(trig_ctx *ctx, uint64_t ticket, trig_result *result, int32_t timeout_us);
 
+/* Serving: hold (paused != 0) or resume (0) the start of new device rounds.
+ * Submissions are still admitted against the budget while held; rounds already
+ * running finish.  For operators (drain control) and deterministic tests. */
+int trig_stream_pause(trig_ctx *ctx, int paused);
+
 /* Serving statistics since trig_create. */
 typedef struct {
     uint64_t submitted, completed, rejected_again, in_flight;

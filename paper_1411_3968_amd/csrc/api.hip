@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -77,6 +78,27 @@ int DevBuf::ensure(trig_ctx *c, size_t want, hipStream_t s) {
 void DevBuf::release(trig_ctx *c) {
     if (ptr) hipFree(ptr);
     ctx_release(c, cap);
+    ptr = nullptr;
+    cap = 0;
+}
+
+int DevBuf::ensure_async(trig_ctx *c, size_t want, hipStream_t s) {
+    if (want <= cap) return TRIG_OK;
+    if (ptr) hipFreeAsync(ptr, s);
+    ptr = nullptr;
+    cap = 0;
+    hipError_t e = hipMallocAsync(&ptr, std::max<size_t>(want, 256), s);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        ctx_set_error(c, "hipMallocAsync(%zu): %s", want, hipGetErrorString(e));
+        return TRIG_ENOMEM;
+    }
+    cap = std::max<size_t>(want, 256);
+    return TRIG_OK;
+}
+
+void DevBuf::release_async(hipStream_t s) {
+    if (ptr) hipFreeAsync(ptr, s);
     ptr = nullptr;
     cap = 0;
 }
@@ -167,7 +189,7 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     auto take = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     const uint64_t n_chunks = (n + CHUNK - 1) / CHUNK;
     const uint64_t n_tiles = (n + TILE - 1) / TILE;
-    L.pos_cap = 2 * n + 65536;
+    L.pos_cap = 3 * n + 65536;
     L.in_pmt = host_input ? take(n * 2) : SIZE_MAX;
     L.in_t = host_input ? take(n * 8) : SIZE_MAX;
     L.in_q = host_input ? take(n * 2) : SIZE_MAX;
@@ -182,15 +204,20 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.s_pq = take(n * 4 + 4);
     L.s_idx = take(n * 4 + 4);
     L.s_fold = take(n * 4 + 4);
-    L.ctile = take((n / CTILE + 2) * 4);
+    L.ctile = take((n / CT1 + 2) * 4);
     L.fires = take(n * sizeof(trig_fire) + 32);
     L.events = take(n * sizeof(trig_event) + 32);
     L.flags = want_flags ? take(n + 4) : SIZE_MAX;
     return o;
 }
 
-int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, bool want_flags_any,
-                 const uint8_t *want_flags, hipStream_t s) {
+size_t slice_footprint(uint64_t n, bool host_input) {
+    SliceLayout L;
+    return slice_layout(n, host_input, false, L) + align256(sizeof(SliceDev)) + align256(sizeof(Plan));
+}
+
+int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
+                 const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s) {
     stream = s;
     params = *prm;
     slices.assign(n, SliceInfo{});
@@ -229,22 +256,46 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         si.tune = ctx_tune_for(c, np);
         cap_max = std::max(cap_max, si.tune.seg_cap);
     }
-    (void)want_flags_any;
     seg_cap = cap_max ? cap_max : 4096;
+    // pinned result staging: plans, then per slice min(n, cap) fires and events
+    size_t xs = align256(n * sizeof(Plan));
+    for (uint32_t i = 0; i < n; ++i) {
+        SliceInfo &si = slices[i];
+        const uint64_t dflt = si.n / 16 + 4096;
+        const uint64_t fc = std::min<uint64_t>(si.n, fire_caps ? fire_caps[i] : dflt);
+        const uint64_t ec = std::min<uint64_t>(si.n, event_caps ? event_caps[i] : dflt);
+        si.x_fcap = (uint32_t)fc;
+        si.x_ecap = (uint32_t)ec;
+        si.x_off_f = xs;
+        xs = align256(xs + fc * sizeof(trig_fire));
+        si.x_off_e = xs;
+        xs = align256(xs + ec * sizeof(trig_event));
+    }
     total_chunks = chunk_base;
     total_tiles = tile_base;
-    int rc = ws.ensure(c, total, s);
-    if (rc) return rc;
     const size_t desc_bytes = align256(n * sizeof(SliceDev)) + align256(n * sizeof(Plan)) + 256;
-    rc = dmeta.ensure(c, desc_bytes, s);
+    int rc = async_mem ? ws.ensure_async(c, total, s) : ws.ensure(c, total, s);
     if (rc) return rc;
-    if (h_slices.ensure(n * sizeof(SliceDev) + 64) || h_plans.ensure(n * sizeof(Plan) + 64)) {
+    rc = async_mem ? dmeta.ensure_async(c, desc_bytes, s) : dmeta.ensure(c, desc_bytes, s);
+    if (rc) return rc;
+    if (h_slices.ensure(n * sizeof(SliceDev) + 64) || h_plans.ensure(xs + 64)) {
         ctx_set_error(c, "pinned host allocation failed");
         return TRIG_ENOMEM;
+    }
+    {
+        void *dp = nullptr;
+        hipError_t e0 = hipHostGetDevicePointer(&dp, h_plans.ptr, 0);
+        if (e0 != hipSuccess) return hip_fail(c, e0, "mapping the result staging");
+        x_plans_dev = (Plan *)dp;
     }
     d_slices = (SliceDev *)dmeta.ptr;
     d_plans = (Plan *)((char *)dmeta.ptr + align256(n * sizeof(SliceDev)));
     d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
+    {
+        // work-queue and completion counters start at zero (the kernels leave them at zero)
+        hipError_t e0 = hipMemsetAsync(d_counters, 0, N_COUNTERS * sizeof(uint32_t), s);
+        if (e0 != hipSuccess) return hip_fail(c, e0, "clearing counters");
+    }
     SliceDev *hs = (SliceDev *)h_slices.ptr;
     char *base = (char *)ws.ptr;
     for (uint32_t i = 0; i < n; ++i) {
@@ -256,6 +307,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         if (si.host_status == TRIG_OK) {
             const GeomDev &g = c->geoms[si.desc.geom_id];
             S.floor_id = g.floor_id;
+            S.floor16 = g.floor16;
             S.thr32 = g.thr32;
             S.thr16 = g.thr16;
             S.n_pmt = g.n_pmt;
@@ -283,6 +335,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.tile_base = si.tile_base;
         S.n_tiles = si.n_tiles;
         S.seg_target = std::min(si.tune.seg_target, seg_cap / 2 ? seg_cap / 2 : 1);
+        S.seg_cap = seg_cap;
         S.pos_cap = L.pos_cap;
         S.part = (ChunkPart *)(b + L.part);
         S.pos = (uint32_t *)(b + L.pos);
@@ -304,6 +357,10 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.events = (trig_event *)(b + L.events);
         S.seed_flags = si.want_flags ? (uint8_t *)(b + L.flags) : nullptr;
         S.plan = d_plans + i;
+        S.x_fires = (trig_fire *)((char *)x_plans_dev + si.x_off_f);
+        S.x_events = (trig_event *)((char *)x_plans_dev + si.x_off_e);
+        S.x_fire_cap = si.x_fcap;
+        S.x_event_cap = si.x_ecap;
         hs[i] = S;
         si.dev = S;
     }
@@ -317,20 +374,78 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.total_tiles = total_tiles;
     batch.tail_state = ST_FAST;
     batch.counters = d_counters;
+    batch.x_plans = x_plans_dev;
     batch.prm = params;
     return TRIG_OK;
 }
 
+// Launch the whole device pipeline on the job's stream.  Every kernel argument
+// is in the launch key (the per-slice descriptors are read from device memory),
+// so a launch sequence seen twice is captured once into a HIP graph on a private
+// stream and replayed on the job's stream from then on.  Timed launches
+// (profile) stay eager so the per-kernel events sit between the kernels.
 int Job::launch(trig_ctx *c, bool profile) {
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     TrigLaunchCfg cfg = c->cfg;
     cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices.empty() ? 2 : slices[0].tune.grid_per_cu);
-    hipError_t e = trig_launch_front(batch, seg_cap, cfg, stream, mark, c);
-    if (e != hipSuccess) return hip_fail(c, e, "front kernels");
-    e = trig_launch_tail(batch, cfg, stream, mark, c);
-    if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
-    e = hipMemcpyAsync(h_plans.ptr, d_plans, slices.size() * sizeof(Plan), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "D2H of plans");
+    auto eager = [&](hipStream_t s) -> int {
+        hipError_t e = trig_launch_front(batch, seg_cap, cfg, s, mark, c);
+        if (e != hipSuccess) return hip_fail(c, e, "front kernels");
+        e = trig_launch_tail(batch, cfg, s, mark, c);
+        if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
+        return TRIG_OK;
+    };
+    if (profile || !graphs_ok || !c->use_graphs) return eager(stream);
+    std::vector<uint8_t> key(sizeof(BatchDev) + sizeof(TrigLaunchCfg) + sizeof(uint32_t));
+    std::memcpy(key.data(), &batch, sizeof(BatchDev));
+    std::memcpy(key.data() + sizeof(BatchDev), &cfg, sizeof(TrigLaunchCfg));
+    std::memcpy(key.data() + sizeof(BatchDev) + sizeof(TrigLaunchCfg), &seg_cap, sizeof(uint32_t));
+    if (graph_exec && key == graph_key) {
+        hipError_t e = hipGraphLaunch(graph_exec, stream);
+        if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+        return TRIG_OK;
+    }
+    if (key != seen_key) {
+        seen_key = key;
+        return eager(stream);
+    }
+    if (!capture_stream && hipStreamCreateWithFlags(&capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        graphs_ok = false;
+        return eager(stream);
+    }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const int rc = eager(capture_stream);
+        hipError_t e2 = hipStreamEndCapture(capture_stream, &g);
+        if (rc != TRIG_OK || e2 != hipSuccess) e = e2 != hipSuccess ? e2 : hipErrorUnknown;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        graphs_ok = false;   // this runtime cannot capture the sequence: stay eager
+        return eager(stream);
+    }
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    graph_exec = ex;
+    graph_key = key;
+    e = hipGraphLaunch(graph_exec, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    return TRIG_OK;
+}
+
+// Seed flags of the slices in `state` to the caller's host buffers (ordered
+// after the kernels that wrote them).
+int Job::enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only) {
+    const uint32_t cnt = only ? (uint32_t)only->size() : (uint32_t)slices.size();
+    for (uint32_t x = 0; x < cnt; ++x) {
+        SliceInfo &si = slices[only ? (*only)[x] : x];
+        if (!si.want_flags || !si.dev.seed_flags || !si.flags_dst || si.n == 0) continue;
+        hipError_t e = hipMemcpyAsync(si.flags_dst, si.dev.seed_flags, si.n, hipMemcpyDeviceToHost, stream);
+        if (e != hipSuccess) return hip_fail(c, e, "D2H of seed flags");
+    }
     return TRIG_OK;
 }
 
@@ -346,7 +461,19 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     for (uint32_t i : todo) {
         SliceInfo &si = slices[i];
         const size_t need = trig_generic_scratch_bytes(si.n);
-        int rc = gscratch.ensure(c, need, stream);
+        int rc;
+        if (async_mem) {
+            if (need > gscratch.cap) {
+                if (ctx_reserve(c, need - gscratch.cap) != TRIG_OK) {
+                    ctx_set_error(c, "device budget exceeded by general-path scratch");
+                    return TRIG_ENOMEM;
+                }
+                async_extra += need - gscratch.cap;
+            }
+            rc = gscratch.ensure_async(c, need, stream);
+        } else {
+            rc = gscratch.ensure(c, need, stream);
+        }
         if (rc) return rc;
         const uint64_t span = (uint64_t)hp[i].t_max - (uint64_t)hp[i].t_min;
         const uint32_t span_bits = span ? 64u - (uint32_t)__builtin_clzll(span) : 0u;
@@ -360,8 +487,8 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices[0].tune.grid_per_cu);
     hipError_t e = trig_launch_tail(b2, cfg, stream, mark, c);
     if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
-    e = hipMemcpyAsync(h_plans.ptr, d_plans, slices.size() * sizeof(Plan), hipMemcpyDeviceToHost, stream);
-    if (e != hipSuccess) return hip_fail(c, e, "D2H of plans");
+    int rc2 = enqueue_flags(c, &todo);
+    if (rc2) return rc2;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (general path)");
     return TRIG_OK;
@@ -390,20 +517,32 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
                       P.n_events);
         return r->status = TRIG_EOVERFLOW;
     }
+    // staged lists come from pinned memory; longer ones are copied from the device
+    const char *xb = (const char *)h_plans.ptr;
     hipError_t e = hipSuccess;
-    if (P.n_fires)
-        e = hipMemcpyAsync(r->fires, si.dev.fires, (size_t)P.n_fires * sizeof(trig_fire), hipMemcpyDeviceToHost,
-                           stream);
-    if (e == hipSuccess && P.n_events)
-        e = hipMemcpyAsync(r->events, si.dev.events, (size_t)P.n_events * sizeof(trig_event),
-                           hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess && r->seed_flags && si.dev.seed_flags)
-        e = hipMemcpyAsync(r->seed_flags, si.dev.seed_flags, si.n, hipMemcpyDeviceToHost, stream);
+    if (P.n_fires) {
+        if (P.n_fires <= si.x_fcap)
+            std::memcpy(r->fires, xb + si.x_off_f, (size_t)P.n_fires * sizeof(trig_fire));
+        else
+            e = hipMemcpyAsync(r->fires, si.dev.fires, (size_t)P.n_fires * sizeof(trig_fire),
+                               hipMemcpyDeviceToHost, stream);
+    }
+    if (e == hipSuccess && P.n_events) {
+        if (P.n_events <= si.x_ecap)
+            std::memcpy(r->events, xb + si.x_off_e, (size_t)P.n_events * sizeof(trig_event));
+        else
+            e = hipMemcpyAsync(r->events, si.dev.events, (size_t)P.n_events * sizeof(trig_event),
+                               hipMemcpyDeviceToHost, stream);
+    }
     if (e != hipSuccess) return r->status = hip_fail(c, e, "D2H of results");
     return r->status = TRIG_OK;
 }
 
 void Job::release(trig_ctx *c) {
+    if (graph_exec) hipGraphExecDestroy(graph_exec);
+    graph_exec = nullptr;
+    if (capture_stream) hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
     ws.release(c);
     dmeta.release(c);
     gscratch.release(c);
@@ -433,17 +572,21 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
         return TRIG_EINVAL;
     }
     std::vector<uint8_t> flags(n);
-    bool any = false;
+    std::vector<uint64_t> fcap(n), ecap(n);
     for (uint32_t i = 0; i < n; ++i) {
         flags[i] = res[i].seed_flags != nullptr;
-        any |= flags[i];
+        fcap[i] = res[i].fires ? res[i].fire_cap : 0;
+        ecap[i] = res[i].events ? res[i].event_cap : 0;
     }
     Job &J = c->sync_job;
     const bool prof = c->prof_on;
     if (prof) c->prof_stream = s;
-    rc = J.prepare(c, n, d, prm, any, flags.data(), s);
+    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s);
     if (rc) return rc;
+    for (uint32_t i = 0; i < n; ++i) J.slices[i].flags_dst = res[i].seed_flags;
     rc = J.launch(c, prof);
+    if (rc) return rc;
+    rc = J.enqueue_flags(c, nullptr);
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise");
@@ -454,6 +597,7 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
         const int st = J.deliver(c, i, &res[i]);
         if (st != TRIG_OK && first_bad == TRIG_OK) first_bad = st;
     }
+    // lists longer than their staging were queued as copies from the device
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise results");
     if (prof) prof_collect(c);
@@ -482,6 +626,8 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     }
     c->cfg.n_cu = prop.multiProcessorCount;
     c->cfg.persist_per_cu = 2;
+    const char *g = getenv("TRIG_GRAPHS");
+    c->use_graphs = !(g && g[0] == '0');
     trig_tune def = {2048, 4096, 2, 0};
     c->tunes.push_back({0xFFFFFFFFu, def});
     *out = c;
@@ -496,6 +642,7 @@ void trig_destroy(trig_ctx *c) {
     c->sync_job.release(c);
     for (auto &g : c->geoms) {
         hipFree(g.floor_id);
+        hipFree(g.floor16);
         hipFree(g.thr32);
         hipFree(g.thr16);
     }
@@ -517,7 +664,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     }
     hipSetDevice(c->device);
     const uint64_t P = g->n_pmt;
-    const uint64_t bytes = P * 4 + P * P * 4 + P * P * 2;
+    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2;
     if (ctx_reserve(c, bytes) != TRIG_OK) {
         ctx_set_error(c, "device budget exceeded by geometry");
         return TRIG_ENOMEM;
@@ -526,13 +673,28 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     d.n_pmt = g->n_pmt;
     std::vector<uint16_t> t16(P * P);
     for (uint64_t i = 0; i < P * P; ++i) t16[i] = (uint16_t)std::min<uint32_t>(g->thr_ns[i], 65535u);
+    // dense floor numbering: equal ids map to equal u16 indices (at most n_pmt floors)
+    std::vector<uint16_t> f16(P);
+    {
+        std::vector<std::pair<int32_t, uint32_t>> byid(P);
+        for (uint64_t i = 0; i < P; ++i) byid[i] = {g->floor_id[i], (uint32_t)i};
+        std::sort(byid.begin(), byid.end());
+        uint32_t k = 0;
+        for (uint64_t i = 0; i < P; ++i) {
+            if (i && byid[i].first != byid[i - 1].first) ++k;
+            f16[byid[i].second] = (uint16_t)k;
+        }
+    }
     hipError_t e = hipMalloc(&d.floor_id, P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.floor16, P * 2);
     if (e == hipSuccess) e = hipMalloc(&d.thr32, P * P * 4);
-    if (e == hipSuccess) e = hipMalloc(&d.thr16, P * P * 2);
+    if (e == hipSuccess) e = hipMalloc(&d.thr16, P * P * 2 + 16);   // read as 32-bit pairs
     if (e == hipSuccess) e = hipMemcpy(d.floor_id, g->floor_id, P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.floor16, f16.data(), P * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d.thr32, g->thr_ns, P * P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d.thr16, t16.data(), P * P * 2, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
+        hipFree(d.floor16);
         hipFree(d.floor_id);
         hipFree(d.thr32);
         hipFree(d.thr16);

@@ -15,8 +15,11 @@ struct trig_ctx;
 struct DevBuf {
     void *ptr = nullptr;
     size_t cap = 0;
-    int ensure(trig_ctx *c, size_t want, hipStream_t s);   // grows; contents not kept
+    int ensure(trig_ctx *c, size_t want, hipStream_t s);   // grows; contents not kept; budget-accounted
     void release(trig_ctx *c);
+    // Stream-ordered variants (serving rounds): the caller accounts the bytes.
+    int ensure_async(trig_ctx *c, size_t want, hipStream_t s);
+    void release_async(hipStream_t s);
 };
 
 struct PinBuf {
@@ -29,6 +32,7 @@ struct PinBuf {
 struct GeomDev {
     uint32_t n_pmt = 0;
     int32_t *floor_id = nullptr;
+    uint16_t *floor16 = nullptr;   // dense renumbering of floor_id (first appearance order)
     uint32_t *thr32 = nullptr;
     uint16_t *thr16 = nullptr;
 };
@@ -50,6 +54,9 @@ struct SliceInfo {
     uint32_t chunk_base, n_chunks, tile_base, n_tiles;
     trig_tune tune;
     trigdev::SliceDev dev;
+    size_t x_off_f, x_off_e;     // result staging offsets in the pinned buffer
+    uint32_t x_fcap, x_ecap;
+    uint8_t *flags_dst;          // caller's host buffer for seed flags (or null)
 };
 
 // One device round over a set of slices: workspace, descriptors, plans.
@@ -65,10 +72,22 @@ struct Job {
     trigdev::Plan *d_plans = nullptr;
     uint32_t *d_counters = nullptr;
     trigdev::BatchDev batch;
+    bool async_mem = false;          // serving: workspace from the stream-ordered pool
+    uint64_t async_extra = 0;        // serving: bytes accounted on demand (general-path scratch)
+    // h_plans is the pinned result staging: plans, then each slice's fires and events
+    trigdev::Plan *x_plans_dev = nullptr;
+    // launch-sequence graph: captured on the second call with the same launch key
+    hipStream_t capture_stream = nullptr;
+    std::vector<uint8_t> seen_key, graph_key;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graphs_ok = true;
 
-    int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, bool want_flags_any,
-                const uint8_t *want_flags, hipStream_t s);
+    // want_flags / fire_caps / event_caps: per slice, may be null (no flags /
+    // default staging capacity).
+    int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
+                const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s);
     int launch(trig_ctx *c, bool profile);
+    int enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only);   // null: every slice
     int generic_pass(trig_ctx *c, bool profile);
     int deliver(trig_ctx *c, uint32_t i, trig_result *r);
     void release(trig_ctx *c);
@@ -94,11 +113,13 @@ struct trig_ctx {
     uint64_t bytes_in_use = 0, bytes_peak = 0;
     std::vector<std::pair<uint32_t, trig_tune>> tunes;
     Job sync_job;
+    bool use_graphs = true;      // TRIG_GRAPHS=0 in the environment keeps every launch eager
     bool prof_on = false;
     hipStream_t prof_stream = nullptr;
     std::vector<ProfMark> prof_pending;
     std::vector<hipEvent_t> ev_pool;
     std::vector<trig_kernel_time> prof;
+    std::mutex serve_mu;     // guards creation of the serving loop
     ServeState *serve = nullptr;
 };
 
@@ -110,3 +131,5 @@ trig_tune ctx_tune_for(const trig_ctx *c, uint32_t n_pmt);
 int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
              hipStream_t s);
 void serve_shutdown(trig_ctx *c);
+// Device bytes one slice of n hits needs in a job workspace (host inputs staged in it or not).
+size_t slice_footprint(uint64_t n, bool host_input);

@@ -31,11 +31,7 @@ __device__ __forceinline__ uint32_t wave_sumu(uint32_t v) {
     return v;
 }
 
-__global__ void k_reset(uint32_t *counters) {
-    if (threadIdx.x < N_COUNTERS) counters[threadIdx.x] = 0;
-}
-
-// Per chunk of 4096 input hits: time range, largest PMT id, run starts
+// Per chunk of CHUNK input hits: time range, largest PMT id, run starts
 // (position 0 and every position whose time is below its predecessor's).
 __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint32_t item = blockIdx.x;
@@ -47,13 +43,30 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint64_t k1 = (k0 + CHUNK < S.n) ? k0 + CHUNK : S.n;
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     uint32_t pmax = 0, ns = 0;
-    for (uint64_t k = k0 + threadIdx.x; k < k1; k += NT_ING) {
-        const int64_t t = S.t[k];
-        lo = t < lo ? t : lo;
-        hi = t > hi ? t : hi;
-        const uint32_t p = S.pmt[k];
-        pmax = p > pmax ? p : pmax;
-        ns += (k == 0) || (t < S.t[k - 1]);
+    const int64_t *tin = S.t;
+    const uint16_t *pin = S.pmt;
+    constexpr int PER = CHUNK / NT_ING;
+    int64_t tv[PER], tp[PER];
+    uint32_t pv[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
+        if (k < k1) {
+            tv[e] = tin[k];
+            tp[e] = k ? tin[k - 1] : INT64_MIN;
+            pv[e] = pin[k];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
+        if (k < k1) {
+            const int64_t t = tv[e];
+            lo = t < lo ? t : lo;
+            hi = t > hi ? t : hi;
+            pmax = pv[e] > pmax ? pv[e] : pmax;
+            ns += (k == 0) || (t < tp[e]);
+        }
     }
     __shared__ int64_t slo[NT_ING / 64], shi[NT_ING / 64];
     __shared__ uint32_t sp[NT_ING / 64], sn[NT_ING / 64];
@@ -75,86 +88,111 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 }
 
 // Per slice: reduce the chunks, validate the input range, number the runs and
-// choose the segment width of the ordering stage.
-__global__ __launch_bounds__(256) void k_plan(BatchDev b) {
+// choose the segment width of the ordering stage.  The last slice to finish
+// builds the work list of the ordering stage (segments of run-merge slices).
+__global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
+    constexpr int NT = 1024, NW = NT / 64;
     const uint32_t si = blockIdx.x;
     const SliceDev &S = b.slices[si];
     Plan *P = S.plan;
-    __shared__ uint32_t sh[256 / 64 + 1];
-    __shared__ int64_t slo[4], shi[4];
-    __shared__ uint32_t spm[4];
-    if (S.n == 0) {
-        if (threadIdx.x == 0) {
-            Plan p = {};
-            p.status = TRIG_OK; p.state = ST_SKIP;
-            *P = p;
-        }
-        return;
-    }
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
-    uint32_t pmax = 0;
-    for (uint32_t c = threadIdx.x; c < S.n_chunks; c += 256) {
-        const ChunkPart cp = S.part[c];
-        lo = cp.t_min < lo ? cp.t_min : lo;
-        hi = cp.t_max > hi ? cp.t_max : hi;
-        pmax = cp.pmt_max > pmax ? cp.pmt_max : pmax;
-    }
-    lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; }
-    __syncthreads();
-    lo = slo[0]; hi = shi[0]; pmax = spm[0];
-    for (int i = 1; i < 4; ++i) {
-        lo = slo[i] < lo ? slo[i] : lo;
-        hi = shi[i] > hi ? shi[i] : hi;
-        pmax = spm[i] > pmax ? spm[i] : pmax;
-    }
-    // run numbering: exclusive scan of run starts over the chunks
-    uint32_t runs = 0;
-    for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += 256) {
-        const uint32_t c = c0 + threadIdx.x;
-        const uint32_t v = c < S.n_chunks ? S.part[c].n_start : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<256>(v, tot, sh);
-        if (c < S.n_chunks) S.part[c].run_base = runs + ex;
-        runs += tot;
-    }
-    if (threadIdx.x != 0) return;
+    __shared__ uint32_t sh[NW + 1];
+    __shared__ int64_t slo[NW], shi[NW];
+    __shared__ uint32_t spm[NW];
+    __shared__ bool last;
     Plan p = {};
-    p.t_min = lo; p.t_max = hi; p.n_runs = runs;
-    const uint64_t span = (uint64_t)hi - (uint64_t)lo;
-    const int64_t H = (int64_t)b.prm.half_event_ns;
-    if (pmax >= S.n_pmt || span >= (1ull << 31) || lo < INT64_MIN + H || hi > INT64_MAX - H) {
-        p.status = TRIG_ERANGE; p.state = ST_SKIP;
-        *P = p;
-        return;
-    }
-    // segment width: the largest power of two with expected occupancy <= seg_target
-    const uint64_t x = ((uint64_t)S.seg_target * (span + 1)) / S.n;
-    uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
-    if (sft > 31) sft = 31;
-    const uint64_t nseg = (span >> sft) + 1;
-    p.shift = sft; p.n_seg = (uint32_t)nseg;
     p.status = TRIG_OK;
-    const bool fits = (uint64_t)runs * (nseg + 1) <= S.pos_cap;
-    p.state = fits ? ST_FAST : ST_NEED_GENERIC;
-    *P = p;
-}
-
-// One block: work-list bases of the ordering stage (segments of fast slices).
-__global__ __launch_bounds__(256) void k_seg_prefix(BatchDev b) {
-    __shared__ uint32_t sh[256 / 64 + 1];
-    uint32_t acc = 0;
-    for (uint32_t i0 = 0; i0 < b.n_slices; i0 += 256) {
-        const uint32_t i = i0 + threadIdx.x;
-        uint32_t v = 0;
-        if (i < b.n_slices) v = (b.plans[i].state == ST_FAST) ? b.plans[i].n_seg : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<256>(v, tot, sh);
-        if (i < b.n_slices) b.plans[i].seg_item_base = acc + ex;
-        acc += tot;
+    p.state = ST_SKIP;
+    if (S.n > 0) {
+        int64_t lo = INT64_MAX, hi = INT64_MIN;
+        uint32_t pmax = 0;
+        constexpr int U = 4;
+        for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * U) {
+            ChunkPart cp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t c = c0 + u * NT + threadIdx.x;
+                if (c < S.n_chunks) cp[u] = S.part[c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t c = c0 + u * NT + threadIdx.x;
+                if (c < S.n_chunks) {
+                    lo = cp[u].t_min < lo ? cp[u].t_min : lo;
+                    hi = cp[u].t_max > hi ? cp[u].t_max : hi;
+                    pmax = cp[u].pmt_max > pmax ? cp[u].pmt_max : pmax;
+                }
+            }
+        }
+        lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
+        const int w = threadIdx.x >> 6;
+        if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; }
+        __syncthreads();
+        lo = slo[0]; hi = shi[0]; pmax = spm[0];
+        for (int i = 1; i < NW; ++i) {
+            lo = slo[i] < lo ? slo[i] : lo;
+            hi = shi[i] > hi ? shi[i] : hi;
+            pmax = spm[i] > pmax ? spm[i] : pmax;
+        }
+        // run numbering: exclusive scan of run starts over the chunks
+        // (8 consecutive chunks per thread per round)
+        uint32_t runs = 0;
+        constexpr int RP = 8;
+        for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * RP) {
+            const uint32_t cb = c0 + threadIdx.x * RP;
+            uint32_t v[RP], sum = 0;
+#pragma unroll
+            for (int u = 0; u < RP; ++u) {
+                v[u] = (cb + u < S.n_chunks) ? S.part[cb + u].n_start : 0u;
+                sum += v[u];
+            }
+            uint32_t tot;
+            uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
+#pragma unroll
+            for (int u = 0; u < RP; ++u) {
+                if (cb + u < S.n_chunks) S.part[cb + u].run_base = run;
+                run += v[u];
+            }
+            runs += tot;
+        }
+        p.t_min = lo; p.t_max = hi; p.n_runs = runs;
+        const uint64_t span = (uint64_t)hi - (uint64_t)lo;
+        const int64_t H = (int64_t)b.prm.half_event_ns;
+        if (pmax >= S.n_pmt || span >= (1ull << 31) || lo < INT64_MIN + H || hi > INT64_MAX - H) {
+            p.status = TRIG_ERANGE;
+        } else {
+            // segment width: the largest power of two with expected occupancy <= seg_target
+            const uint64_t x = ((uint64_t)S.seg_target * (span + 1)) / S.n;
+            uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
+            if (sft > 31) sft = 31;
+            // many runs: widen the segments (up to half the LDS capacity expected)
+            // until the boundary table fits its budget
+            while (sft < 31 && (uint64_t)runs * ((span >> sft) + 2) > S.pos_cap &&
+                   2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)S.seg_cap)
+                ++sft;
+            const uint64_t nseg = (span >> sft) + 1;
+            p.shift = sft;
+            p.n_seg = (uint32_t)nseg;
+            const bool fits = (uint64_t)runs * (nseg + 1) <= S.pos_cap;
+            p.state = fits ? ST_FAST : ST_NEED_GENERIC;
+        }
     }
-    if (threadIdx.x == 0) { b.counters[Q_SEG_TOTAL] = acc; b.counters[Q_SEG] = 0; }
+    if (threadIdx.x == 0) {
+        *P = p;
+        __threadfence();
+        last = atomicAdd(&b.counters[C_PLAN_DONE], 1u) == b.n_slices - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < b.n_slices; ++i) {
+        Plan *Pi = &b.plans[i];
+        Pi->seg_item_base = acc;
+        if (load_acquire(&Pi->state) == ST_FAST) acc += load_acquire(&Pi->n_seg);
+    }
+    b.counters[Q_SEG_TOTAL] = acc;
+    b.counters[Q_SEG] = 0;
+    b.counters[C_PLAN_DONE] = 0;
 }
 
 // Per chunk: for every run r and segment boundary j (time j << shift relative to
@@ -173,7 +211,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     __shared__ uint32_t sh[NT / 64 + 1];
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint32_t len = (uint32_t)((k0 + CHUNK < S.n) ? CHUNK : S.n - k0);
-    for (uint32_t i = threadIdx.x; i < len; i += NT) st[i + 1] = S.t[k0 + i];
+    stage_copy<NT, PER>(st + 1, S.t + k0, len);
     if (threadIdx.x == 0) {
         st[0] = k0 ? S.t[k0 - 1] : INT64_MIN;
         st[len + 1] = (k0 + len < S.n) ? S.t[k0 + len] : INT64_MIN;
@@ -212,48 +250,67 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     }
 }
 
-// Persistent ordering of time segments.  Segment j of a slice holds the hits with
+// Ordering of time segments.  Segment j of a slice holds the hits with
 // t - t_min in [j << shift, (j + 1) << shift); each run contributes the stretch
-// [pos[r][j], pos[r][j + 1]).  The segment is gathered into LDS, ranked by the key
-// ((t - segment start) << pbits | pmt) with a stable LSD radix over 8-bit digits,
-// ties of equal (t, pmt) are put in input-position order, and the ordered
-// structure-of-arrays is written at the segment's global offset.
+// [pos[r][j], pos[r][j + 1]).  Workgroup b owns a contiguous range of the
+// segment work list (consecutive segments share boundary rows in cache).  A
+// segment is gathered into LDS, scattered into 256 buckets by the top 8 bits of
+// its local time (LDS atomics give each hit a slot; the order within a bucket is
+// then fixed by an insertion sort on (t, pmt, input index)), and written as the
+// ordered structure-of-arrays at the segment's global offset.  A segment with a
+// crowded bucket (a dense burst) is ordered by a stable LSD radix over 8-bit
+// digits of (t << pbits | pmt) instead, then equal (t, pmt) keys are put in
+// input order.
 template <int NT, int CAP>
 struct SegShared {
     uint32_t dt[CAP], dpq[CAP], didx[CAP];
     uint16_t perm[2][CAP];
     uint32_t run_lo[NT], run_base[NT];
+    uint32_t bcount[256], bbase[256];
     RankScratch<NT> rs;
-    uint32_t misc[8];
 };
+
+constexpr uint32_t BUCKET_MAX = 48;   // larger buckets take the radix path
 
 template <int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     constexpr int E = CAP / NT;
+    constexpr int GU = 4;   // gathered hits in flight per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SegShared<NT, CAP> &sm = *reinterpret_cast<SegShared<NT, CAP> *>(smem_raw);
     const uint32_t total = b.counters[Q_SEG_TOTAL];
-    for (;;) {
-        if (threadIdx.x == 0) sm.misc[0] = atomicAdd(&b.counters[Q_SEG], 1u);
-        __syncthreads();
-        const uint32_t item = sm.misc[0];
-        __syncthreads();
-        if (item >= total) break;
-        const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
-        const SliceDev &S = b.slices[si];
-        const Plan P = b.plans[si];
-        const uint32_t j = item - P.seg_item_base;
+    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
+    const uint32_t first = blockIdx.x * per;
+    const uint32_t end = (first + per < total) ? first + per : total;
+    uint32_t si = 0, s_base = 1, s_end = 0;
+    const uint16_t *in_pmt = nullptr, *in_q = nullptr;
+    const int64_t *in_t = nullptr;
+    const uint32_t *pos = nullptr;
+    uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
+    uint32_t pbits = 0;
+    Plan P = {};
+    for (uint32_t item = first; item < end; ++item) {
+        if (item < s_base || item >= s_end) {
+            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
+            P = b.plans[si];
+            const SliceDev &S = b.slices[si];
+            in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
+            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx; pbits = S.pbits;
+            s_base = P.seg_item_base;
+            s_end = s_base + P.n_seg;
+        }
+        const uint32_t j = item - s_base;
         const uint32_t row_len = P.n_seg + 1;
-        const uint64_t seg_lo = (uint64_t)j << P.shift;
+        const uint32_t seg_lo = (uint32_t)((uint64_t)j << P.shift);
         // gather the segment's stretch of every run
         uint32_t m = 0;
-        uint32_t goff_part = 0;   // this thread's share of the global offset
+        uint32_t goff_part = 0;   // this thread's share of the segment's global offset
         bool over = false;
         for (uint32_t r0 = 0; r0 < P.n_runs; r0 += NT) {
             const uint32_t r = r0 + threadIdx.x;
             uint32_t lo = 0, hi = 0;
             if (r < P.n_runs) {
-                const uint32_t *row = S.pos + (uint64_t)r * row_len;
+                const uint32_t *row = pos + (uint64_t)r * row_len;
                 lo = row[j];
                 hi = row[j + 1];
                 goff_part += lo - row[0];
@@ -265,44 +322,109 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             sm.run_base[threadIdx.x] = ex;
             __syncthreads();
             const uint32_t nr = (P.n_runs - r0 < (uint32_t)NT) ? P.n_runs - r0 : (uint32_t)NT;
-            for (uint32_t k = threadIdx.x; k < cnt_tot; k += NT) {
-                // run of element k: last run whose base is <= k
-                uint32_t a = 0, z = nr;
-                while (a < z) {
-                    const uint32_t mid = (a + z) >> 1;
-                    if (sm.run_base[mid] <= k) a = mid + 1; else z = mid;
+            for (uint32_t k0 = 0; k0 < cnt_tot; k0 += NT * GU) {
+                uint32_t src[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    const uint32_t k = k0 + u * NT + threadIdx.x;
+                    src[u] = 0xFFFFFFFFu;
+                    if (k < cnt_tot) {
+                        uint32_t a = 0, z = nr;   // last run whose base is <= k
+                        while (a < z) {
+                            const uint32_t mid = (a + z) >> 1;
+                            if (sm.run_base[mid] <= k) a = mid + 1; else z = mid;
+                        }
+                        src[u] = sm.run_lo[a - 1] + (k - sm.run_base[a - 1]);
+                    }
                 }
-                const uint32_t rr = a - 1;
-                const uint32_t src = sm.run_lo[rr] + (k - sm.run_base[rr]);
-                sm.dt[m + k] = (uint32_t)(S.t[src] - P.t_min);
-                sm.dpq[m + k] = ((uint32_t)S.pmt[src] << 16) | (uint32_t)S.q[src];
-                sm.didx[m + k] = src;
+                int64_t tv[GU];
+                uint32_t pv[GU], qv[GU];
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    if (src[u] != 0xFFFFFFFFu) {
+                        tv[u] = in_t[src[u]];
+                        pv[u] = in_pmt[src[u]];
+                        qv[u] = in_q[src[u]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < GU; ++u) {
+                    if (src[u] != 0xFFFFFFFFu) {
+                        const uint32_t k = m + k0 + u * NT + threadIdx.x;
+                        sm.dt[k] = (uint32_t)(tv[u] - P.t_min);
+                        sm.dpq[k] = (pv[u] << 16) | qv[u];
+                        sm.didx[k] = src[u];
+                    }
+                }
             }
             m += cnt_tot;
             __syncthreads();
         }
         if (over) {
-            if (threadIdx.x == 0) { S.plan->overflow = 1u; S.plan->state = ST_NEED_GENERIC; }
+            if (threadIdx.x == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
             __syncthreads();
             continue;
         }
         const uint32_t goff = block_sum<NT>(goff_part, sm.rs.scan);
-        // stable LSD radix over the key bits
-        const uint32_t pbits = S.pbits;
+        auto less = [&](uint32_t a, uint32_t c) -> bool {
+            if (sm.dt[a] != sm.dt[c]) return sm.dt[a] < sm.dt[c];
+            const uint32_t pa = sm.dpq[a] >> 16, pc = sm.dpq[c] >> 16;
+            if (pa != pc) return pa < pc;
+            return sm.didx[a] < sm.didx[c];
+        };
+        // bucket scatter by the top 8 bits of the local time
+        const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
+        if (threadIdx.x < 256) sm.bcount[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < m; k += NT) {
+            const uint32_t d = (sm.dt[k] - seg_lo) >> tb;
+            sm.perm[1][k] = (uint16_t)atomicAdd(&sm.bcount[d], 1u);
+        }
+        __syncthreads();
+        uint32_t bc = threadIdx.x < 256 ? sm.bcount[threadIdx.x] : 0u;
+        uint32_t btot;
+        const uint32_t bex = block_excl_scan<NT>(bc, btot, sm.rs.scan);
+        if (threadIdx.x < 256) sm.bbase[threadIdx.x] = bex;
+        const int crowd = __syncthreads_or(bc > BUCKET_MAX);
+        if (!crowd) {
+            for (uint32_t k = threadIdx.x; k < m; k += NT) {
+                const uint32_t d = (sm.dt[k] - seg_lo) >> tb;
+                sm.perm[0][sm.bbase[d] + sm.perm[1][k]] = (uint16_t)k;
+            }
+            __syncthreads();
+            if (threadIdx.x < 256 && bc > 1) {
+                uint16_t *bk = sm.perm[0] + bex;
+                for (uint32_t x = 1; x < bc; ++x) {
+                    const uint16_t v = bk[x];
+                    uint32_t y = x;
+                    while (y > 0 && less(v, bk[y - 1])) { bk[y] = bk[y - 1]; --y; }
+                    bk[y] = v;
+                }
+            }
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < m; k += NT) {
+                const uint32_t v = sm.perm[0][k];
+                o_t[goff + k] = sm.dt[v];
+                o_pq[goff + k] = sm.dpq[v];
+                o_idx[goff + k] = sm.didx[v];
+            }
+            __syncthreads();
+            continue;
+        }
+        // crowded segment: stable LSD radix over the key bits
+        auto keyof = [&](uint32_t v) -> uint64_t {
+            return ((uint64_t)(sm.dt[v] - seg_lo) << pbits) | (uint64_t)(sm.dpq[v] >> 16);
+        };
         const uint32_t key_bits = P.shift + pbits;
         const int passes = (int)((key_bits + 7) / 8);
-        for (int k = threadIdx.x; k < (int)m; k += NT) sm.perm[0][k] = (uint16_t)k;
+        for (uint32_t k = threadIdx.x; k < m; k += NT) sm.perm[0][k] = (uint16_t)k;
         __syncthreads();
         int cur = 0;
         for (int ps = 0; ps < passes; ++ps) {
             const uint32_t sh8 = 8u * (uint32_t)ps;
             uint32_t rk[E], dg[E];
-            auto digit_of = [&](int k) -> uint32_t {
-                const uint32_t v = sm.perm[cur][k];
-                const uint64_t key = ((uint64_t)(sm.dt[v] - (uint32_t)seg_lo) << pbits) | (uint64_t)(sm.dpq[v] >> 16);
-                return (uint32_t)(key >> sh8) & 255u;
-            };
-            block_rank8<NT, E>((int)m, digit_of, sm.rs, rk, dg);
+            block_rank8<NT, E>((int)m, [&](int k) -> uint32_t { return (uint32_t)(keyof(sm.perm[cur][k]) >> sh8) & 255u; },
+                               sm.rs, rk, dg);
             const int w = threadIdx.x >> 6, lane = lane_id();
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -313,29 +435,26 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             cur ^= 1;
         }
         // equal (t, pmt): order by input position
-        auto keyof = [&](uint32_t v) -> uint64_t {
-            return ((uint64_t)(sm.dt[v] - (uint32_t)seg_lo) << pbits) | (uint64_t)(sm.dpq[v] >> 16);
-        };
-        for (int k = threadIdx.x; k < (int)m; k += NT) {
+        for (uint32_t k = threadIdx.x; k < m; k += NT) {
             const uint32_t v = sm.perm[cur][k];
             const uint64_t kv = keyof(v);
             const bool tie_prev = k > 0 && keyof(sm.perm[cur][k - 1]) == kv;
-            const bool tie_next = k + 1 < (int)m && keyof(sm.perm[cur][k + 1]) == kv;
+            const bool tie_next = k + 1 < m && keyof(sm.perm[cur][k + 1]) == kv;
             if (!tie_prev && !tie_next) { sm.perm[cur ^ 1][k] = (uint16_t)v; continue; }
-            int a = k, z = k + 1;
+            uint32_t a = k, z = k + 1;
             while (a > 0 && keyof(sm.perm[cur][a - 1]) == kv) --a;
-            while (z < (int)m && keyof(sm.perm[cur][z]) == kv) ++z;
-            int rank = 0;
-            for (int u = a; u < z; ++u) rank += sm.didx[sm.perm[cur][u]] < sm.didx[v];
+            while (z < m && keyof(sm.perm[cur][z]) == kv) ++z;
+            uint32_t rank = 0;
+            for (uint32_t u = a; u < z; ++u) rank += sm.didx[sm.perm[cur][u]] < sm.didx[v];
             sm.perm[cur ^ 1][a + rank] = (uint16_t)v;
         }
         __syncthreads();
         cur ^= 1;
-        for (int k = threadIdx.x; k < (int)m; k += NT) {
+        for (uint32_t k = threadIdx.x; k < m; k += NT) {
             const uint32_t v = sm.perm[cur][k];
-            S.o_t[goff + k] = sm.dt[v];
-            S.o_pq[goff + k] = sm.dpq[v];
-            S.o_idx[goff + k] = sm.didx[v];
+            o_t[goff + k] = sm.dt[v];
+            o_pq[goff + k] = sm.dpq[v];
+            o_idx[goff + k] = sm.didx[v];
         }
         __syncthreads();
     }
@@ -363,10 +482,6 @@ hipError_t launch_segsort(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream
 
 hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, const TrigLaunchCfg &cfg, hipStream_t s,
                              void (*mark)(void *, const char *, int), void *mark_ctx) {
-    TRIG_MARK("k_reset", 0);
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, b.counters);
-    TRIG_CHECK();
-    TRIG_MARK("k_reset", 1);
     if (b.total_chunks) {
         TRIG_MARK("k_ingest", 0);
         hipLaunchKernelGGL(k_ingest, dim3(b.total_chunks), dim3(NT_ING), 0, s, b);
@@ -374,13 +489,9 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, const TrigLaun
         TRIG_MARK("k_ingest", 1);
     }
     TRIG_MARK("k_plan", 0);
-    hipLaunchKernelGGL(k_plan, dim3(b.n_slices), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_plan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_plan", 1);
-    TRIG_MARK("k_seg_prefix", 0);
-    hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(256), 0, s, b);
-    TRIG_CHECK();
-    TRIG_MARK("k_seg_prefix", 1);
     if (b.total_chunks) {
         TRIG_MARK("k_bounds", 0);
         hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks), dim3(256), 0, s, b);

@@ -11,7 +11,7 @@ using namespace trigdev;
 namespace {
 
 constexpr int NT = 256;
-constexpr int E = TILE / NT;
+constexpr int E = GTILE / NT;
 
 __global__ __launch_bounds__(NT) void k_gkeys(SliceDev S, Plan P, uint64_t *key, uint32_t *val) {
     const uint64_t k = (uint64_t)blockIdx.x * NT + threadIdx.x;
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(NT) void k_ghist(uint64_t n, const uint64_t *key, u
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t b0 = (uint64_t)blockIdx.x * TILE;
+    const uint64_t b0 = (uint64_t)blockIdx.x * GTILE;
     for (int e = 0; e < E; ++e) {
         const uint64_t k = b0 + (uint64_t)e * NT + threadIdx.x;
         if (k < n) atomicAdd(&cnt[(uint32_t)(key[k] >> shift) & 255u], 1u);
@@ -55,8 +55,8 @@ __global__ __launch_bounds__(NT) void k_gscatter(uint64_t n, const uint64_t *key
                                                  uint64_t *key2, uint32_t *val2, uint32_t shift, uint32_t nblk,
                                                  const uint32_t *hist) {
     __shared__ RankScratch<NT> rs;
-    const uint64_t b0 = (uint64_t)blockIdx.x * TILE;
-    const int m = (int)((n - b0) < (uint64_t)TILE ? (n - b0) : (uint64_t)TILE);
+    const uint64_t b0 = (uint64_t)blockIdx.x * GTILE;
+    const int m = (int)((n - b0) < (uint64_t)GTILE ? (n - b0) : (uint64_t)GTILE);
     uint64_t kk[E];
     uint32_t vv[E];
     const int w = threadIdx.x >> 6, lane = lane_id();
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(NT) void k_gfinish(SliceDev S, const uint64_t *key,
 }  // namespace
 
 size_t trig_generic_scratch_bytes(uint64_t n) {
-    const uint64_t nblk = (n + TILE - 1) / TILE;
+    const uint64_t nblk = (n + GTILE - 1) / GTILE;
     return 2 * n * sizeof(uint64_t) + 2 * n * sizeof(uint32_t) + 256 * nblk * sizeof(uint32_t) + 1024;
 }
 
@@ -109,7 +109,7 @@ hipError_t trig_launch_generic_slice(const SliceDev &S, const Plan &P, uint32_t 
                                      hipStream_t s, void (*mark)(void *, const char *, int), void *mark_ctx) {
     const uint64_t n = S.n;
     if (n == 0) return hipSuccess;
-    const uint64_t nblk = (n + TILE - 1) / TILE;
+    const uint64_t nblk = (n + GTILE - 1) / GTILE;
     uint64_t *key0 = (uint64_t *)scratch;
     uint64_t *key1 = key0 + n;
     uint32_t *val0 = (uint32_t *)(key1 + n);

@@ -11,87 +11,116 @@ namespace {
 
 constexpr int NT = 256;
 
-__device__ __forceinline__ uint32_t wave_sumu(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-// Seed bits of one tile of 4096 ordered hits.  Element e*256 + tid of the tile is
-// handled by thread tid in iteration e, so every wave's ballot covers one aligned
-// 64-hit word of the seed mask.  A floor partner is searched among the ordered
-// neighbours within t_floor_ns on both sides.
+// Seed bits of one tile of 1024 ordered hits.  The tile and SHALO neighbours on
+// each side are staged in LDS with coalesced loads; a floor partner is searched
+// among the ordered neighbours within t_floor_ns on both sides (reading global
+// memory only when a search runs past the staged halo).  Element e*256 + tid of
+// the tile is handled by thread tid in round e, so every wave's ballot is one
+// aligned 64-hit word of the seed mask.
 __global__ __launch_bounds__(NT) void k_seed(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
     const SliceDev &S = b.slices[si];
     const uint32_t tile = item - S.tile_base;
     if (tile >= S.n_tiles) return;
-    const uint32_t state = S.plan->state;
-    if (!slice_in_tail(b, state)) return;
+    if (!slice_in_tail(b, S.plan->state)) return;
+    __shared__ uint32_t lt[TILE + 2 * SHALO], lpq[TILE + 2 * SHALO];
+    __shared__ uint16_t lfloor[SEED_LDS_FLOORS];
     __shared__ uint32_t sh[NT / 64 + 1];
-    const uint64_t base = (uint64_t)tile * TILE;
+    const uint32_t *o_t = S.o_t, *o_pq = S.o_pq;
     const uint64_t n = S.n;
+    const uint32_t np = S.n_pmt;
+    const uint16_t *floor16 = S.floor16;
+    const bool lds_floor = np <= (uint32_t)SEED_LDS_FLOORS;
+    const uint64_t base = (uint64_t)tile * TILE;
+    const uint64_t lo = base >= (uint64_t)SHALO ? base - SHALO : 0;
+    const uint64_t hi = (base + TILE + SHALO < n) ? base + TILE + SHALO : n;
+    stage_copy<NT, 5>(lt, o_t + lo, (uint32_t)(hi - lo));
+    stage_copy<NT, 5>(lpq, o_pq + lo, (uint32_t)(hi - lo));
+    if (lds_floor) stage_copy<NT, 8>(lfloor, floor16, np);
+    __syncthreads();
+    auto T_at = [&](uint64_t m) -> uint32_t { return (m >= lo && m < hi) ? lt[m - lo] : o_t[m]; };
+    auto P_at = [&](uint64_t m) -> uint32_t { return ((m >= lo && m < hi) ? lpq[m - lo] : o_pq[m]) >> 16; };
+    auto F_of = [&](uint32_t p) -> uint32_t { return lds_floor ? lfloor[p] : floor16[p]; };
     const uint32_t Q = b.prm.q_seed;
     const int32_t tau = b.prm.t_floor_ns;
+    uint8_t *flags = S.seed_flags;
     uint32_t cnt = 0;
+#pragma unroll
     for (int e = 0; e < TILE / NT; ++e) {
         const uint64_t k = base + (uint64_t)e * NT + threadIdx.x;
         bool seed = false;
         if (k < n) {
-            const uint32_t t = S.o_t[k];
-            const uint32_t pq = S.o_pq[k];
+            const uint32_t t = lt[k - lo];
+            const uint32_t pq = lpq[k - lo];
             const uint32_t p = pq >> 16;
             seed = (pq & 0xFFFFu) >= Q;
             if (!seed && tau >= 0) {
-                const int32_t f = S.floor_id[p];
+                const uint32_t f = F_of(p);
                 for (uint64_t m = k; m > 0;) {
                     --m;
-                    const uint32_t tm = S.o_t[m];
-                    if (t - tm > (uint32_t)tau) break;
-                    const uint32_t pm = S.o_pq[m] >> 16;
-                    if (pm != p && S.floor_id[pm] == f) { seed = true; break; }
+                    if (t - T_at(m) > (uint32_t)tau) break;
+                    const uint32_t pm = P_at(m);
+                    if (pm != p && F_of(pm) == f) { seed = true; break; }
                 }
                 for (uint64_t m = k + 1; !seed && m < n; ++m) {
-                    const uint32_t tm = S.o_t[m];
-                    if (tm - t > (uint32_t)tau) break;
-                    const uint32_t pm = S.o_pq[m] >> 16;
-                    if (pm != p && S.floor_id[pm] == f) seed = true;
+                    if (T_at(m) - t > (uint32_t)tau) break;
+                    const uint32_t pm = P_at(m);
+                    if (pm != p && F_of(pm) == f) seed = true;
                 }
             }
-            if (S.seed_flags) S.seed_flags[S.o_idx[k]] = seed ? 1 : 0;
+            if (flags) flags[S.o_idx[k]] = seed ? 1 : 0;
         }
         const uint64_t bal = __ballot(seed);
-        if (lane_id() == 0 && base + (uint64_t)e * NT + (threadIdx.x & ~63u) < n)
-            S.seed_mask[(base + (uint64_t)e * NT + (threadIdx.x & ~63u)) >> 6] = bal;
+        const uint64_t w0 = base + (uint64_t)e * NT + (threadIdx.x & ~63u);
+        if (lane_id() == 0 && w0 < n) S.seed_mask[w0 >> 6] = bal;
         cnt += seed;
     }
     const uint32_t tot = block_sum<NT>(cnt, sh);
     if (threadIdx.x == 0) S.tile_seeds[tile] = tot;
 }
 
-// Per slice: exclusive scan of the per-tile seed counts.
-__global__ __launch_bounds__(NT) void k_seed_scan(BatchDev b) {
+// Per slice: exclusive scan of the per-tile seed counts.  The last slice to
+// finish builds the work list of the counting stage (slices with a large table
+// use ROWGROUPS items per tile, item % 8 == row group, starting at a multiple of 8).
+__global__ __launch_bounds__(1024) void k_seed_scan(BatchDev b) {
     const SliceDev &S = b.slices[blockIdx.x];
     Plan *P = S.plan;
-    if (!slice_in_tail(b, P->state)) return;
-    __shared__ uint32_t sh[NT / 64 + 1];
-    uint32_t acc = 0;
-    for (uint32_t i0 = 0; i0 < S.n_tiles; i0 += NT) {
-        const uint32_t i = i0 + threadIdx.x;
-        const uint32_t v = i < S.n_tiles ? S.tile_seeds[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<NT>(v, tot, sh);
-        if (i < S.n_tiles) S.tile_seeds[i] = acc + ex;
-        acc += tot;
+    __shared__ uint32_t sh[1024 / 64 + 1];
+    __shared__ bool last;
+    if (slice_in_tail(b, P->state)) {
+        const uint32_t ns = block_scan_array<1024>(S.tile_seeds, S.n_tiles, sh);
+        const uint32_t groups = (S.n_pmt > (uint32_t)LDS_THR_MAX_PMT) ? ROWGROUPS : 1u;
+        const uint32_t nct = (ns + count_tile(groups) - 1) / count_tile(groups);
+        for (uint32_t i = threadIdx.x; i < nct; i += 1024) S.ctile_fires[i] = 0;
+        if (threadIdx.x == 0) {
+            P->n_seeds = ns;
+            P->n_ctiles = nct;
+            P->groups = groups;
+        }
     }
-    const uint32_t nct = (acc + CTILE - 1) / CTILE;
-    for (uint32_t i = threadIdx.x; i < nct; i += NT) S.ctile_fires[i] = 0;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        P->n_seeds = acc;
-        P->n_ctiles = nct;
-        P->groups = (S.n_pmt > (uint32_t)LDS_THR_MAX_PMT) ? ROWGROUPS : 1u;
+        __threadfence();
+        last = atomicAdd(&b.counters[C_SCAN_DONE], 1u) == b.n_slices - 1;
     }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < b.n_slices; ++i) {
+        Plan *Pi = &b.plans[i];
+        uint32_t items = 0;
+        if (slice_in_tail(b, load_acquire(&Pi->state))) {
+            const uint32_t g = load_acquire(&Pi->groups);
+            if (g > 1) acc = (acc + ROWGROUPS - 1) / ROWGROUPS * ROWGROUPS;
+            items = load_acquire(&Pi->n_ctiles) * g;
+        }
+        Pi->count_item_base = acc;
+        acc += items;
+    }
+    b.counters[Q_COUNT_TOTAL] = acc;
+    b.counters[C_SCAN_DONE] = 0;
 }
 
 // Compact seed list of one tile, in ordered-hit order.
@@ -102,8 +131,9 @@ __global__ __launch_bounds__(NT) void k_seed_emit(BatchDev b) {
     const uint32_t tile = item - S.tile_base;
     if (tile >= S.n_tiles) return;
     if (!slice_in_tail(b, S.plan->state)) return;
-    __shared__ uint32_t wpre[TILE / 64];
-    __shared__ uint64_t wmask[TILE / 64];
+    constexpr int NWORD = TILE / 64;
+    __shared__ uint32_t wpre[NWORD];
+    __shared__ uint64_t wmask[NWORD];
     const uint64_t base = (uint64_t)tile * TILE;
     const uint64_t n = S.n;
     const uint32_t nwords = (uint32_t)(((n - base < (uint64_t)TILE ? n - base : (uint64_t)TILE) + 63) / 64);
@@ -111,11 +141,14 @@ __global__ __launch_bounds__(NT) void k_seed_emit(BatchDev b) {
         const uint64_t wv = threadIdx.x < nwords ? S.seed_mask[(base >> 6) + threadIdx.x] : 0ull;
         const uint32_t c = (uint32_t)__popcll(wv);
         const uint32_t inc = wave_incl_scan(c);
-        wpre[threadIdx.x] = inc - c;
-        wmask[threadIdx.x] = wv;
+        if (threadIdx.x < NWORD) {
+            wpre[threadIdx.x] = inc - c;
+            wmask[threadIdx.x] = wv;
+        }
     }
     __syncthreads();
     const uint32_t off = S.tile_seeds[tile];
+#pragma unroll
     for (int e = 0; e < TILE / NT; ++e) {
         const uint32_t i = (uint32_t)e * NT + threadIdx.x;
         const uint64_t k = base + i;
@@ -132,31 +165,20 @@ __global__ __launch_bounds__(NT) void k_seed_emit(BatchDev b) {
     }
 }
 
-// One block: work-list bases of the counting stage.  Slices with a large table
-// use ROWGROUPS items per tile (item % 8 == row group) and start at a multiple of 8.
-__global__ __launch_bounds__(NT) void k_count_prefix(BatchDev b) {
-    if (threadIdx.x != 0) return;
-    uint32_t acc = 0;
-    for (uint32_t i = 0; i < b.n_slices; ++i) {
-        Plan *P = &b.plans[i];
-        uint32_t items = 0;
-        if (slice_in_tail(b, P->state)) {
-            if (P->groups > 1) acc = (acc + ROWGROUPS - 1) / ROWGROUPS * ROWGROUPS;
-            items = P->n_ctiles * P->groups;
-        }
-        P->count_item_base = acc;
-        acc += items;
-    }
-    b.counters[Q_COUNT_TOTAL] = acc;
-}
-
 // Causal fold of every seed: 1 + the other seeds j with
 // |t_i - t_j| <= min(thr[p_i][p_j], w_ns), scanned outwards over the time-ordered
-// seed list until the time difference exceeds w_ns.  Static grid-stride over items
-// (grid a multiple of 8): for large tables each workgroup keeps one row group, so the
-// rows it reads stay in one L2.
+// seed list until the time difference exceeds w_ns.  A counting tile and CHALO
+// seeds on each side are staged in LDS.  Tables of up to 128 PMTs are kept in LDS
+// as u16 min(thr, w_ns).  Larger tables are read from L2: such a slice has 8 items
+// per tile (row groups), the grid is a multiple of 8 and items are taken with a
+// grid stride, so workgroup b (dispatched to XCD b mod 8) only reads the rows of
+// group b mod 8 and that 1/8 of the table stays in one XCD's L2.
 __global__ __launch_bounds__(NT) void k_count(BatchDev b) {
-    __shared__ uint16_t lthr[LDS_THR_MAX_PMT * LDS_THR_MAX_PMT];
+    constexpr int LTHR_BYTES = LDS_THR_MAX_PMT * LDS_THR_MAX_PMT * 2;
+    constexpr int STAGE = CT8 + 2 * CHALO;
+    __shared__ __align__(16) unsigned char raw[LTHR_BYTES + (CT1 + 2 * CHALO) * 8 > STAGE * 8 + CT8 * 2
+                                                   ? LTHR_BYTES + (CT1 + 2 * CHALO) * 8
+                                                   : STAGE * 8 + CT8 * 2];
     __shared__ uint32_t sh[NT / 64 + 1];
     __shared__ const uint32_t *loaded_thr;
     if (threadIdx.x == 0) loaded_thr = nullptr;
@@ -174,59 +196,91 @@ __global__ __launch_bounds__(NT) void k_count(BatchDev b) {
         const uint32_t tile = local / G, g = local % G;
         if (tile >= P.n_ctiles) continue;
         const uint32_t np = S.n_pmt;
+        const uint32_t TS = count_tile(G);
         const bool use_lds = (G == 1) && (W <= 65535u);
+        uint16_t *lthr = (uint16_t *)raw;
+        uint32_t *st = (uint32_t *)(raw + (G == 1 ? LTHR_BYTES : 0));
+        const uint32_t stage_cap = G == 1 ? CT1 + 2 * CHALO : STAGE;
+        uint32_t *sp = st + stage_cap;
+        uint16_t *mine = (uint16_t *)(sp + stage_cap);
         if (use_lds && loaded_thr != S.thr32) {
             __syncthreads();
-            for (uint32_t x = threadIdx.x; x < np * np; x += NT) {
-                const uint32_t v = S.thr32[x];
-                lthr[x] = (uint16_t)(v < W ? v : W);
-            }
+            // the u16 copy min(thr, 65535) moves as 32-bit pairs; min(., W) at use
+            stage_copy<NT, 8>((uint32_t *)lthr, (const uint32_t *)S.thr16, (np * np + 1) / 2);
             __syncthreads();
             if (threadIdx.x == 0) loaded_thr = S.thr32;
             __syncthreads();
+        } else if (!use_lds && G > 1 && loaded_thr != nullptr) {
+            __syncthreads();
+            if (threadIdx.x == 0) loaded_thr = nullptr;   // the staging area overwrites the table
+            __syncthreads();
         }
         const uint32_t ns = P.n_seeds;
-        const uint32_t i0 = tile * CTILE;
-        const uint32_t i1 = (i0 + CTILE < ns) ? i0 + CTILE : ns;
+        const uint32_t i0 = tile * TS;
+        const uint32_t i1 = (i0 + TS < ns) ? i0 + TS : ns;
+        const uint32_t lo = i0 >= (uint32_t)CHALO ? i0 - CHALO : 0u;
+        const uint32_t hi = (i1 + CHALO < ns) ? i1 + CHALO : ns;
+        stage_copy<NT, 6>(st, S.s_t + lo, hi - lo);
+        stage_copy<NT, 6>(sp, S.s_pq + lo, hi - lo, [](uint32_t v) { return v >> 16; });
+        __syncthreads();
+        // the seeds of this item: the whole tile, or those whose PMT is in row group g
+        uint32_t m = i1 - i0;
+        if (G > 1) {
+            uint32_t tot_all = 0;
+            for (uint32_t c0 = 0; c0 < i1 - i0; c0 += NT) {
+                const uint32_t x = c0 + threadIdx.x;
+                const bool mineflag = x < i1 - i0 && (sp[i0 - lo + x] * G) / np == g;
+                uint32_t tot;
+                const uint32_t ex = block_excl_scan<NT>(mineflag ? 1u : 0u, tot, sh);
+                if (mineflag) mine[tot_all + ex] = (uint16_t)x;
+                tot_all += tot;
+            }
+            m = tot_all;
+            __syncthreads();
+        }
+        auto T_at = [&](uint32_t j) -> uint32_t { return (j >= lo && j < hi) ? st[j - lo] : S.s_t[j]; };
+        auto P_at = [&](uint32_t j) -> uint32_t { return (j >= lo && j < hi) ? sp[j - lo] : (S.s_pq[j] >> 16); };
         uint32_t fires = 0;
-        for (uint32_t i = i0 + threadIdx.x; i < i1; i += NT) {
-            const uint32_t p = S.s_pq[i] >> 16;
-            if (G > 1 && (p * G) / np != g) continue;
-            const uint32_t t = S.s_t[i];
+        for (uint32_t x = threadIdx.x; x < m; x += NT) {
+            const uint32_t i = i0 + (G > 1 ? (uint32_t)mine[x] : x);
+            const uint32_t p = sp[i - lo];
+            const uint32_t t = st[i - lo];
+            // the window: seeds [jl, jr) within w_ns of seed i
+            uint32_t jl = i, jr = i + 1;
+            while (jl > 0 && t - T_at(jl - 1) <= W) --jl;
+            while (jr < ns && T_at(jr) - t <= W) ++jr;
             uint32_t c = 1;
             if (use_lds) {
                 const uint16_t *row = lthr + p * np;
-                for (uint32_t j = i; j > 0;) {
-                    --j;
-                    const uint32_t d = t - S.s_t[j];
-                    if (d > W) break;
-                    c += d <= row[S.s_pq[j] >> 16];
-                }
-                for (uint32_t j = i + 1; j < ns; ++j) {
-                    const uint32_t d = S.s_t[j] - t;
-                    if (d > W) break;
-                    c += d <= row[S.s_pq[j] >> 16];
+                for (uint32_t j = jl; j < jr; ++j) {
+                    if (j == i) continue;
+                    const uint32_t tj = T_at(j);
+                    const uint32_t d = tj > t ? tj - t : t - tj;
+                    c += d <= row[P_at(j)];
                 }
             } else {
+                // table rows from L2: issue CB lookups before using any of them
+                constexpr int CB = 8;
                 const uint64_t rb = (uint64_t)p * np;
-                for (uint32_t j = i; j > 0;) {
-                    --j;
-                    const uint32_t d = t - S.s_t[j];
-                    if (d > W) break;
-                    uint32_t lim;
-                    if (W <= 65535u) lim = S.thr16[rb + (S.s_pq[j] >> 16)];
-                    else lim = S.thr32[rb + (S.s_pq[j] >> 16)];
-                    lim = lim < W ? lim : W;
-                    c += d <= lim;
-                }
-                for (uint32_t j = i + 1; j < ns; ++j) {
-                    const uint32_t d = S.s_t[j] - t;
-                    if (d > W) break;
-                    uint32_t lim;
-                    if (W <= 65535u) lim = S.thr16[rb + (S.s_pq[j] >> 16)];
-                    else lim = S.thr32[rb + (S.s_pq[j] >> 16)];
-                    lim = lim < W ? lim : W;
-                    c += d <= lim;
+                for (uint32_t j0 = jl; j0 < jr; j0 += CB) {
+                    uint32_t lim[CB], dd[CB];
+#pragma unroll
+                    for (int u = 0; u < CB; ++u) {
+                        const uint32_t j = j0 + u;
+                        dd[u] = 0xFFFFFFFFu;
+                        lim[u] = 0;
+                        if (j < jr && j != i) {
+                            const uint32_t tj = T_at(j);
+                            dd[u] = tj > t ? tj - t : t - tj;
+                            const uint32_t pj = P_at(j);
+                            lim[u] = (W <= 65535u) ? (uint32_t)S.thr16[rb + pj] : S.thr32[rb + pj];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < CB; ++u) {
+                        const uint32_t l = lim[u] < W ? lim[u] : W;
+                        c += dd[u] != 0xFFFFFFFFu && dd[u] <= l;
+                    }
                 }
             }
             S.s_fold[i] = c;
@@ -238,22 +292,13 @@ __global__ __launch_bounds__(NT) void k_count(BatchDev b) {
 }
 
 // Per slice: exclusive scan of fires per seed tile.
-__global__ __launch_bounds__(NT) void k_fire_scan(BatchDev b) {
+__global__ __launch_bounds__(1024) void k_fire_scan(BatchDev b) {
     const SliceDev &S = b.slices[blockIdx.x];
     Plan *P = S.plan;
     if (!slice_in_tail(b, P->state)) return;
-    __shared__ uint32_t sh[NT / 64 + 1];
-    const uint32_t nct = P->n_ctiles;
-    uint32_t acc = 0;
-    for (uint32_t i0 = 0; i0 < nct; i0 += NT) {
-        const uint32_t i = i0 + threadIdx.x;
-        const uint32_t v = i < nct ? S.ctile_fires[i] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<NT>(v, tot, sh);
-        if (i < nct) S.ctile_fires[i] = acc + ex;
-        acc += tot;
-    }
-    if (threadIdx.x == 0) P->n_fires = acc;
+    __shared__ uint32_t sh[1024 / 64 + 1];
+    const uint32_t nf = block_scan_array<1024>(S.ctile_fires, P->n_ctiles, sh);
+    if (threadIdx.x == 0) P->n_fires = nf;
 }
 
 // Ordered fire records of one seed tile (row group 0 items only).
@@ -269,12 +314,14 @@ __global__ __launch_bounds__(NT) void k_fire_emit(BatchDev b) {
         const uint32_t local = item - P.count_item_base;
         const uint32_t tile = local / P.groups;
         if (local % P.groups != 0 || tile >= P.n_ctiles) continue;
+        const uint32_t TS = count_tile(P.groups);
         const uint32_t ns = P.n_seeds;
-        const uint32_t i0 = tile * CTILE;
+        const uint32_t i0 = tile * TS;
+        const uint32_t i1 = (i0 + TS < ns) ? i0 + TS : ns;
         uint32_t off = S.ctile_fires[tile];
-        for (uint32_t c0 = i0; c0 < i0 + CTILE && c0 < ns; c0 += NT) {
+        for (uint32_t c0 = i0; c0 < i1; c0 += NT) {
             const uint32_t i = c0 + threadIdx.x;
-            const bool f = i < ns && i < i0 + CTILE && S.s_fold[i] >= N;
+            const bool f = i < i1 && S.s_fold[i] >= N;
             uint32_t tot;
             const uint32_t ex = block_excl_scan<NT>(f ? 1u : 0u, tot, sh);
             if (f) {
@@ -359,6 +406,24 @@ __global__ __launch_bounds__(1024) void k_events(BatchDev b) {
     if (threadIdx.x == 0) P->n_events = ne;
 }
 
+// Results to host-mapped staging: every plan, and the fires and events of each
+// slice of this tail that fit its staging capacity (the host copies larger lists
+// from device memory).  One sync then delivers the whole batch.
+__global__ __launch_bounds__(NT) void k_export(BatchDev b) {
+    const uint32_t gt = blockIdx.x * NT + threadIdx.x;
+    const uint32_t gs = gridDim.x * NT;
+    for (uint32_t i = gt; i < b.n_slices; i += gs) b.x_plans[i] = b.plans[i];
+    for (uint32_t si = 0; si < b.n_slices; ++si) {
+        const SliceDev &S = b.slices[si];
+        const Plan &P = b.plans[si];
+        if (!slice_in_tail(b, P.state)) continue;
+        if (S.x_fires && P.n_fires <= S.x_fire_cap)
+            for (uint32_t i = gt; i < P.n_fires; i += gs) S.x_fires[i] = S.fires[i];
+        if (S.x_events && P.n_events <= S.x_event_cap)
+            for (uint32_t i = gt; i < P.n_events; i += gs) S.x_events[i] = S.events[i];
+    }
+}
+
 }  // namespace
 
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
@@ -374,7 +439,7 @@ hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &cfg, hipStre
         TRIG_MARK("k_seed", 1);
     }
     TRIG_MARK("k_seed_scan", 0);
-    hipLaunchKernelGGL(k_seed_scan, dim3(b.n_slices), dim3(NT), 0, s, b);
+    hipLaunchKernelGGL(k_seed_scan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_seed_scan", 1);
     if (b.total_tiles) {
@@ -383,16 +448,12 @@ hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &cfg, hipStre
         TRIG_CHECK();
         TRIG_MARK("k_seed_emit", 1);
     }
-    TRIG_MARK("k_count_prefix", 0);
-    hipLaunchKernelGGL(k_count_prefix, dim3(1), dim3(64), 0, s, b);
-    TRIG_CHECK();
-    TRIG_MARK("k_count_prefix", 1);
     TRIG_MARK("k_count", 0);
     hipLaunchKernelGGL(k_count, dim3(grid), dim3(NT), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_count", 1);
     TRIG_MARK("k_fire_scan", 0);
-    hipLaunchKernelGGL(k_fire_scan, dim3(b.n_slices), dim3(NT), 0, s, b);
+    hipLaunchKernelGGL(k_fire_scan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_fire_scan", 1);
     TRIG_MARK("k_fire_emit", 0);
@@ -403,5 +464,11 @@ hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &cfg, hipStre
     hipLaunchKernelGGL(k_events, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_events", 1);
+    if (b.x_plans) {
+        TRIG_MARK("k_export", 0);
+        hipLaunchKernelGGL(k_export, dim3(64), dim3(NT), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_export", 1);
+    }
     return hipSuccess;
 }

@@ -29,10 +29,15 @@
 
 namespace trigdev {
 
-constexpr int CHUNK = 4096;       // hits per ingest / bounds item
-constexpr int TILE = 4096;        // ordered hits per seed tile
-constexpr int CTILE = 1024;       // seeds per counting tile
+constexpr int CHUNK = 1024;       // hits per ingest / bounds item
+constexpr int TILE = 1024;        // ordered hits per seed tile
+constexpr int SHALO = 64;         // ordered neighbours staged on each side of a seed tile
+constexpr int CT1 = 256;          // seeds per counting tile (table in LDS)
+constexpr int CT8 = 2048;         // seeds per counting tile (row-grouped table in L2)
+constexpr int CHALO = 256;        // seeds staged on each side of a counting tile
+constexpr int GTILE = 4096;       // elements per block of the general radix sort
 constexpr int LDS_THR_MAX_PMT = 128;  // thr table kept in LDS up to this many PMTs
+constexpr int SEED_LDS_FLOORS = 8192; // dense floor ids kept in LDS up to this many PMTs
 constexpr int ROWGROUPS = 8;      // counting rows split over the 8 XCDs for large tables
 
 enum State : uint32_t {
@@ -47,8 +52,12 @@ enum Counter : int {
     Q_SEG = 0,           // dequeue counter of k_segsort
     Q_SEG_TOTAL = 1,     // number of segment items
     Q_COUNT_TOTAL = 2,   // number of counting items
+    C_PLAN_DONE = 3,     // slices planned so far (the last block builds the segment work list)
+    C_SCAN_DONE = 4,     // slices whose seed list is scanned (the last block builds the count work list)
     N_COUNTERS = 16,
 };
+
+__host__ __device__ constexpr uint32_t count_tile(uint32_t groups) { return groups > 1 ? CT8 : CT1; }
 
 struct ChunkPart {
     int64_t t_min, t_max;
@@ -82,12 +91,13 @@ struct SliceDev {
     const uint16_t *q;
     uint64_t n;
     const int32_t *floor_id;
+    const uint16_t *floor16; // dense floor index per PMT (equal iff floor_id equal)
     const uint32_t *thr32;
     const uint16_t *thr16;   // min(thr, 65535)
     uint32_t n_pmt, pbits;
     uint32_t chunk_base, n_chunks;
     uint32_t tile_base, n_tiles;
-    uint32_t seg_target, pad0;
+    uint32_t seg_target, seg_cap;
     uint64_t pos_cap;
     ChunkPart *part;
     uint32_t *pos;           // run-major: pos[r * (n_seg + 1) + j]
@@ -101,6 +111,9 @@ struct SliceDev {
     trig_event *events;
     uint8_t *seed_flags;     // optional, by input index
     Plan *plan;
+    trig_fire *x_fires;      // host-mapped staging of the results (null: none)
+    trig_event *x_events;
+    uint32_t x_fire_cap, x_event_cap;
 };
 
 struct BatchDev {
@@ -111,6 +124,7 @@ struct BatchDev {
     uint32_t total_tiles;
     uint32_t tail_state;     // the tail kernels process slices in this state
     uint32_t *counters;
+    Plan *x_plans;           // host-mapped copy of the plans written at the end of the tail
     trig_params prm;
 };
 
@@ -149,6 +163,62 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &total,
     total = sh[NT / 64];
     __syncthreads();
     return r;
+}
+
+// In-place exclusive scan of a[0..len) by one block (4 consecutive items per
+// thread per round); returns the total.
+template <int NT>
+__device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t len, uint32_t *sh) {
+    constexpr uint32_t PT = 4;
+    uint32_t acc = 0;
+    for (uint32_t i0 = 0; i0 < len; i0 += NT * PT) {
+        const uint32_t b = i0 + threadIdx.x * PT;
+        uint32_t v[PT], sum = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < PT; ++p) {
+            v[p] = (b + p < len) ? a[b + p] : 0u;
+            sum += v[p];
+        }
+        uint32_t tot;
+        uint32_t run = acc + block_excl_scan<NT>(sum, tot, sh);
+#pragma unroll
+        for (uint32_t p = 0; p < PT; ++p) {
+            if (b + p < len) a[b + p] = run;
+            run += v[p];
+        }
+        acc += tot;
+    }
+    return acc;
+}
+
+// Cooperative copy src[0..n) -> dst[0..n) by one block with U loads in flight
+// per thread before any store (a plain strided loop waits for every load).
+template <int NT, int U, class T, class Tr>
+__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n, Tr tr) {
+    for (uint32_t b0 = 0; b0 < n; b0 += NT * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = b0 + u * NT + threadIdx.x;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = b0 + u * NT + threadIdx.x;
+            if (i < n) dst[i] = tr(v[u]);
+        }
+    }
+}
+
+template <int NT, int U, class T>
+__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n) {
+    stage_copy<NT, U>(dst, src, n, [](T x) { return x; });
+}
+
+// Device-scope load that bypasses a possibly stale L1 line (data written by
+// other workgroups of the same kernel before a release fence).
+__device__ __forceinline__ uint32_t load_acquire(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int NT>

@@ -74,7 +74,8 @@ class StreamStats(C.Structure):
 assert C.sizeof(Result) == 88 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 20
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
-           "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_stats_get", "trig_tune_get",
+           "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_pause", "trig_stream_stats_get",
+           "trig_tune_get",
            "trig_tune_set", "trig_profile_enable", "trig_profile_read"]
 
 
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.trig_stream_submit.argtypes = [P, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(C.c_uint64)]
     lib.trig_stream_poll.argtypes = [P, C.c_uint64, C.POINTER(Result), C.c_int32]
     lib.trig_stream_stats_get.argtypes = [P, C.POINTER(StreamStats)]
+    lib.trig_stream_pause.argtypes = [P, C.c_int]
     lib.trig_tune_get.argtypes = [P, C.c_uint32, C.POINTER(Tune)]
     lib.trig_tune_set.argtypes = [P, C.c_uint32, C.POINTER(Tune)]
     lib.trig_profile_enable.argtypes = [P, C.c_int]
@@ -104,6 +106,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice", "trig_batch",
                                                "trig_stream_submit", "trig_stream_poll", "trig_stream_stats_get",
+                                               "trig_stream_pause",
                                                "trig_tune_get", "trig_tune_set", "trig_profile_enable",
                                                "trig_profile_read"):
             fn.restype = C.c_int
@@ -318,6 +321,12 @@ def trig_stream_poll(ctx, ticket: int, timeout_us: int = -1, fire_cap: int = 1 <
     return rc, rb.as_dict()
 
 
+def trig_stream_pause(ctx, paused: bool = True) -> None:
+    rc = _LIB.trig_stream_pause(ctx, 1 if paused else 0)
+    if rc != TRIG_OK:
+        raise TrigError(rc, _err(ctx))
+
+
 def trig_stream_stats_get(ctx) -> dict:
     s = StreamStats()
     rc = _LIB.trig_stream_stats_get(ctx, C.byref(s))
@@ -352,6 +361,40 @@ def trig_profile_read(ctx) -> list:
     _LIB.trig_profile_read(ctx, arr, n.value, C.byref(n))
     return [dict(name=arr[i].name.decode(), launches=int(arr[i].launches), total_ms=float(arr[i].total_ms))
             for i in range(n.value)]
+
+
+class SliceRunner:
+    """Repeated ``trig_slice`` on one slice with marshalling done once.
+
+    Descriptor, parameters and result buffers are built at construction; each
+    call only invokes the C ABI.  Returned arrays are views into buffers that
+    the next call overwrites.
+    """
+
+    def __init__(self, ctx, geom_id, pmt, t, q, params=None, *, stream=None, fire_cap=None, event_cap=None,
+                 seed_flags=False):
+        self.ctx = ctx
+        self.desc, self._keep = slice_desc(geom_id, pmt, t, q)
+        n = int(self.desc.n_hits)
+        fc, ec = _default_caps(n)
+        self.buf = ResultBuffers(fire_cap or fc, event_cap or ec, n, seed_flags)
+        self.prm = params_struct(params)
+        if stream is None and _is_torch(t):
+            import torch
+            stream = torch.cuda.current_stream()
+        self.sp = _stream_ptr(stream)
+        self._pd, self._pp, self._pr = C.byref(self.desc), C.byref(self.prm), C.byref(self.buf.rec)
+
+    def __call__(self) -> dict:
+        rc = _LIB.trig_slice(self.ctx, self._pd, self._pp, self._pr, self.sp)
+        r = self.buf.rec
+        if rc != TRIG_OK:
+            raise TrigError(rc, _err(self.ctx))
+        out = dict(status=rc, n_seeds=int(r.n_seeds), n_fires=int(r.n_fires), n_events=int(r.n_events),
+                   path=int(r.path), fires=self.buf.fires[:r.n_fires], events=self.buf.events[:r.n_events])
+        if self.buf.flags is not None:
+            out["seed_flags"] = self.buf.flags[:r.n_hits]
+        return out
 
 
 class Trigger:

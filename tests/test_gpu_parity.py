@@ -155,6 +155,35 @@ def test_repeat_is_bit_identical(tr):
         assert np.array_equal(first["seed_flags"], again["seed_flags"])
 
 
+def test_graph_replays_match_eager_with_work_between(tr, orc):
+    """The launch sequence is captured into a HIP graph on its second use; every
+    replay, with other slices (eager or captured) run in between, equals the
+    first (eager) result and the oracle."""
+    from gen import configs as C
+    wa = C.km3(seed=31, length_ns=15_000_000)
+    wb = C.nemo(seed=32, length_ns=25_000_000)
+    ga, thra = wa.geoms["km3"]
+    gb, thrb = wb.geoms["nemo"]
+    sa, sb = wa.slices[0][1], wb.slices[0][1]
+    ida, idb = gid_for(tr, ga.floor_id, thra), gid_for(tr, gb.floor_id, thrb)
+    da, db = to_dev(sa), to_dev(sb)
+    ra0 = tr.slice(ida, *da, wa.params, seed_flags=True)
+    rb0 = tr.slice(idb, *db, wb.params, seed_flags=True)
+    check(ra0, orc.run(sa.pmt, sa.t, sa.q, ga.floor_id, thra, wa.params))
+    check(rb0, orc.run(sb.pmt, sb.t, sb.q, gb.floor_id, thrb, wb.params))
+    seq = "aaabababbbaaab"
+    for x in seq:
+        if x == "a":
+            r = tr.slice(ida, *da, wa.params, seed_flags=True)
+            ref = ra0
+        else:
+            r = tr.slice(idb, *db, wb.params, seed_flags=True)
+            ref = rb0
+        assert np.array_equal(r["fires"], ref["fires"])
+        assert np.array_equal(r["events"], ref["events"])
+        assert np.array_equal(r["seed_flags"], ref["seed_flags"])
+
+
 def test_dense_segment_takes_general_path(tr, orc):
     """A burst far denser than a segment's LDS capacity: the run-merge ordering hands
     the slice to the general radix path; results are unchanged."""

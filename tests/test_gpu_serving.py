@@ -1,0 +1,138 @@
+"""Serving loop on the GPU: each ticket's result equals the slice triggered alone,
+while other slices overlap on the device; admission by HBM budget; cancellation."""
+import threading
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    from paper_1411_3968_amd import trig
+    return trig
+
+
+@pytest.fixture(scope="module")
+def pool():
+    from gen import configs as C
+    return C.serving_pool(seed=4, n_pool=12, length_ns=20_000_000)
+
+
+def _alone(T, pool):
+    out = []
+    with T.Trigger(0) as tr:
+        g, thr = pool.geoms["km3"]
+        gid = tr.load_geometry(g.floor_id, thr)
+        for _, s in pool.slices:
+            out.append(tr.slice(gid, s.pmt, s.t, s.q, pool.params))
+    return out
+
+
+def test_stream_results_equal_alone_under_overlap(T, pool):
+    alone = _alone(T, pool)
+    ctx = T.trig_create(0)
+    try:
+        g, thr = pool.geoms["km3"]
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        tickets = {}
+        lock = threading.Lock()
+
+        def producer(k):
+            for i in range(k, len(pool.slices), 3):
+                s = pool.slices[i][1]
+                for rep in range(2):
+                    st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params, tag=i)
+                    assert st == 0
+                    with lock:
+                        tickets[(i, rep)] = tk
+
+        ths = [threading.Thread(target=producer, args=(k,)) for k in range(3)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        for (i, rep), tk in tickets.items():
+            st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 14, event_cap=1 << 14)
+            assert st == 0 and r["tag"] == i
+            assert np.array_equal(r["fires"], alone[i]["fires"])
+            assert np.array_equal(r["events"], alone[i]["events"])
+            assert r["n_seeds"] == alone[i]["n_seeds"]
+        stats = T.trig_stream_stats_get(ctx)
+        assert stats["completed"] == len(tickets) and stats["in_flight"] == 0
+        assert stats["rounds"] >= 1
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_admission_by_budget(T, pool):
+    from gen import configs as C
+    s = pool.slices[0][1]
+    g, thr = pool.geoms["km3"]
+    # a budget that holds a handful of slices of this size; rounds held back so
+    # nothing completes while the budget fills
+    ctx = T.trig_create(0, 64 << 20)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        T.trig_stream_pause(ctx, True)
+        got_again = False
+        tks = []
+        for _ in range(100):
+            st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+            if st == T.TRIG_EAGAIN:
+                got_again = True
+                break
+            assert st == 0
+            tks.append(tk)
+        assert got_again and len(tks) >= 2
+        T.trig_stream_pause(ctx, False)
+        for tk in tks:
+            st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 14, event_cap=1 << 14)
+            assert st == 0
+        st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+        assert st == 0
+        assert T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 14, event_cap=1 << 14)[0] == 0
+        big = C.km3(seed=2).slices[0][1]
+        st, _ = T.trig_stream_submit(ctx, gid, big.pmt, big.t, big.q, pool.params)
+        assert st == T.TRIG_ENOMEM
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_poll_overflow_then_deliver_and_errors(T, pool):
+    s = pool.slices[1][1]
+    g, thr = pool.geoms["km3"]
+    ctx = T.trig_create(0)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        prm = dict(pool.params, min_fold=1)
+        st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, prm)
+        assert st == 0
+        st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=1, event_cap=1)
+        assert st == T.TRIG_EOVERFLOW and r["n_fires"] > 1
+        st, r2 = T.trig_stream_poll(ctx, tk, -1, fire_cap=r["n_fires"], event_cap=r["n_events"])
+        assert st == 0 and r2["n_fires"] == r["n_fires"]
+        assert T.trig_stream_poll(ctx, tk, 0)[0] == T.TRIG_EINVAL      # released
+        bad = s.pmt.copy()
+        bad[3] = 999
+        st, tk = T.trig_stream_submit(ctx, gid, bad, s.t, s.q, prm)
+        assert st == 0
+        assert T.trig_stream_poll(ctx, tk, -1)[0] == T.TRIG_ERANGE
+        st, _ = T.trig_stream_submit(ctx, 77, s.pmt, s.t, s.q, prm)
+        assert st == T.TRIG_EINVAL
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_destroy_with_tickets_in_flight(T, pool):
+    g, thr = pool.geoms["km3"]
+    ctx = T.trig_create(0)
+    gid = T.trig_geom_load(ctx, g.floor_id, thr)
+    for _, s in pool.slices[:8]:
+        st, _ = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+        assert st == 0
+    T.trig_destroy(ctx)      # drains running rounds, cancels the rest, frees everything
