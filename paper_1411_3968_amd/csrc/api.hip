@@ -224,6 +224,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     size_t total = 0;
     uint32_t chunk_base = 0, tile_base = 0;
     uint32_t cap_max = 0;
+    sort_kernels = 0;
+    wave_wgs = 0;
+    block_wgs = 0;
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
         si.desc = d[i];
@@ -254,7 +257,17 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         tile_base += si.n_tiles;
         const uint32_t np = (d[i].geom_id < c->geoms.size()) ? c->geoms[d[i].geom_id].n_pmt : 1u;
         si.tune = ctx_tune_for(c, np);
-        cap_max = std::max(cap_max, si.tune.seg_cap);
+        if (si.host_status == TRIG_OK && nh) {
+            if (si.tune.seg_cap == (uint32_t)WAVE_CAP) {
+                sort_kernels |= 1u;
+                wave_wgs = std::max(wave_wgs, si.tune.grid_per_cu);
+                if (np > (uint32_t)WAVE_RUNS) sort_kernels |= 2u;   // a slice may hand over to the block kernel
+            } else {
+                sort_kernels |= 2u;
+                cap_max = std::max(cap_max, si.tune.seg_cap);
+                block_wgs = std::max(block_wgs, si.tune.grid_per_cu);
+            }
+        }
     }
     seg_cap = cap_max ? cap_max : 4096;
     // pinned result staging: plans, then per slice min(n, cap) fires and events
@@ -334,8 +347,14 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.n_chunks = si.n_chunks;
         S.tile_base = si.tile_base;
         S.n_tiles = si.n_tiles;
-        S.seg_target = std::min(si.tune.seg_target, seg_cap / 2 ? seg_cap / 2 : 1);
-        S.seg_cap = seg_cap;
+        if (si.tune.seg_cap == (uint32_t)WAVE_CAP) {
+            S.seg_cap = WAVE_CAP;
+            S.seg_target = std::min<uint32_t>(si.tune.seg_target, WAVE_CAP * 3 / 4);
+        } else {
+            S.seg_cap = seg_cap;
+            S.seg_target = std::min(si.tune.seg_target, seg_cap / 2);
+        }
+        S.seg_target = std::max<uint32_t>(S.seg_target, 1);
         S.pos_cap = L.pos_cap;
         S.part = (ChunkPart *)(b + L.part);
         S.pos = (uint32_t *)(b + L.pos);
@@ -373,6 +392,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.total_chunks = total_chunks;
     batch.total_tiles = total_tiles;
     batch.tail_state = ST_FAST;
+    batch.sort_kernels = sort_kernels;
+    batch.block_cap = seg_cap;
+    batch.block_target = seg_cap / 2;
     batch.counters = d_counters;
     batch.x_plans = x_plans_dev;
     batch.prm = params;
@@ -387,9 +409,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
 int Job::launch(trig_ctx *c, bool profile) {
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     TrigLaunchCfg cfg = c->cfg;
-    cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices.empty() ? 2 : slices[0].tune.grid_per_cu);
+    cfg.persist_per_cu = (int)std::max<uint32_t>(1, block_wgs);
     auto eager = [&](hipStream_t s) -> int {
-        hipError_t e = trig_launch_front(batch, seg_cap, cfg, s, mark, c);
+        hipError_t e = trig_launch_front(batch, seg_cap, (int)std::max<uint32_t>(1, wave_wgs), cfg, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "front kernels");
         e = trig_launch_tail(batch, cfg, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
@@ -484,7 +506,7 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     BatchDev b2 = batch;
     b2.tail_state = ST_GENERIC_DONE;
     TrigLaunchCfg cfg = c->cfg;
-    cfg.persist_per_cu = (int)std::max<uint32_t>(1, slices[0].tune.grid_per_cu);
+    cfg.persist_per_cu = (int)std::max<uint32_t>(2, block_wgs);
     hipError_t e = trig_launch_tail(b2, cfg, stream, mark, c);
     if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
     int rc2 = enqueue_flags(c, &todo);
@@ -628,7 +650,7 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     c->cfg.persist_per_cu = 2;
     const char *g = getenv("TRIG_GRAPHS");
     c->use_graphs = !(g && g[0] == '0');
-    trig_tune def = {2048, 4096, 2, 0};
+    trig_tune def = {384, (uint32_t)WAVE_CAP, 3, 0};   // wave per segment; 3 workgroups of 4 waves per CU
     c->tunes.push_back({0xFFFFFFFFu, def});
     *out = c;
     return TRIG_OK;
@@ -735,7 +757,8 @@ int trig_tune_get(trig_ctx *c, uint32_t n_pmt, trig_tune *out) {
 
 int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
     if (!c || !t) return TRIG_EINVAL;
-    if (!(t->seg_cap == 2048 || t->seg_cap == 4096 || t->seg_cap == 8192) || t->seg_target == 0 ||
+    if (!(t->seg_cap == (uint32_t)WAVE_CAP || t->seg_cap == 2048 || t->seg_cap == 4096 || t->seg_cap == 8192) ||
+        t->seg_target == 0 ||
         t->grid_per_cu == 0 || t->grid_per_cu > 16) {
         ctx_set_error(c, "bad tuning values");
         return TRIG_EINVAL;

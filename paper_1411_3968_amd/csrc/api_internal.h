@@ -64,7 +64,9 @@ struct Job {
     std::vector<SliceInfo> slices;
     trig_params params;
     hipStream_t stream = nullptr;
-    uint32_t seg_cap = 4096;
+    uint32_t seg_cap = 4096;          // capacity of the block-per-segment ordering kernel
+    uint32_t sort_kernels = 0;        // ordering kernels to launch (bit 0 wave, bit 1 block)
+    uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
     uint32_t total_chunks = 0, total_tiles = 0;
     DevBuf ws, dmeta, gscratch;
     PinBuf h_slices, h_plans;

@@ -160,19 +160,28 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         if (pmax >= S.n_pmt || span >= (1ull << 31) || lo < INT64_MIN + H || hi > INT64_MAX - H) {
             p.status = TRIG_ERANGE;
         } else {
-            // segment width: the largest power of two with expected occupancy <= seg_target
-            const uint64_t x = ((uint64_t)S.seg_target * (span + 1)) / S.n;
+            // ordering kernel: wave per segment for few runs, else block per segment
+            uint32_t cap = S.seg_cap, target = S.seg_target;
+            bool ok = true;
+            if (cap == (uint32_t)WAVE_CAP && runs > (uint32_t)WAVE_RUNS) {
+                cap = b.block_cap;
+                target = b.block_target;
+                ok = (b.sort_kernels & 2u) != 0;
+            }
+            p.seg_kind = cap == (uint32_t)WAVE_CAP ? 0u : 1u;
+            // segment width: the largest power of two with expected occupancy <= target
+            const uint64_t x = ((uint64_t)target * (span + 1)) / S.n;
             uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
             if (sft > 31) sft = 31;
             // many runs: widen the segments (up to half the LDS capacity expected)
             // until the boundary table fits its budget
             while (sft < 31 && (uint64_t)runs * ((span >> sft) + 2) > S.pos_cap &&
-                   2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)S.seg_cap)
+                   2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)cap)
                 ++sft;
             const uint64_t nseg = (span >> sft) + 1;
             p.shift = sft;
             p.n_seg = (uint32_t)nseg;
-            const bool fits = (uint64_t)runs * (nseg + 1) <= S.pos_cap;
+            const bool fits = ok && (uint64_t)runs * (nseg + 1) <= S.pos_cap;
             p.state = fits ? ST_FAST : ST_NEED_GENERIC;
         }
     }
@@ -184,14 +193,18 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     __syncthreads();
     if (!last || threadIdx.x != 0) return;
     __threadfence();
-    uint32_t acc = 0;
+    uint32_t acc = 0, acc_b = 0;
     for (uint32_t i = 0; i < b.n_slices; ++i) {
         Plan *Pi = &b.plans[i];
         Pi->seg_item_base = acc;
-        if (load_acquire(&Pi->state) == ST_FAST) acc += load_acquire(&Pi->n_seg);
+        Pi->seg_item_base_b = acc_b;
+        if (load_acquire(&Pi->state) == ST_FAST) {
+            const uint32_t ns = load_acquire(&Pi->n_seg);
+            if (load_acquire(&Pi->seg_kind) == 0) acc += ns; else acc_b += ns;
+        }
     }
     b.counters[Q_SEG_TOTAL] = acc;
-    b.counters[Q_SEG] = 0;
+    b.counters[Q_SEG_TOTAL_B] = acc_b;
     b.counters[C_PLAN_DONE] = 0;
 }
 
@@ -278,7 +291,7 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     constexpr int GU = 4;   // gathered hits in flight per thread
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SegShared<NT, CAP> &sm = *reinterpret_cast<SegShared<NT, CAP> *>(smem_raw);
-    const uint32_t total = b.counters[Q_SEG_TOTAL];
+    const uint32_t total = b.counters[Q_SEG_TOTAL_B];
     const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
     const uint32_t first = blockIdx.x * per;
     const uint32_t end = (first + per < total) ? first + per : total;
@@ -291,12 +304,12 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     Plan P = {};
     for (uint32_t item = first; item < end; ++item) {
         if (item < s_base || item >= s_end) {
-            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
+            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base_b; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
             in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
             o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx; pbits = S.pbits;
-            s_base = P.seg_item_base;
+            s_base = P.seg_item_base_b;
             s_end = s_base + P.n_seg;
         }
         const uint32_t j = item - s_base;
@@ -460,6 +473,302 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     }
 }
 
+// ------------------------------------------------------ wave per segment
+// Same ordering with one wave per time segment (slices with at most WAVE_RUNS
+// runs, segments of at most WAVE_CAP hits).  A wave owns a contiguous range of
+// the segment work list and needs no workgroup barrier, so the waves of a CU
+// overlap each other's memory latency.
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct WaveSeg {
+    uint32_t dt[WAVE_CAP], dpq[WAVE_CAP], didx[WAVE_CAP];
+    uint16_t perm[2][WAVE_CAP];
+    uint32_t run_lo[WAVE_RUNS], run_base[WAVE_RUNS];
+    uint32_t bcount[256], bbase[256];
+};
+
+// Stable rank of the wave's m elements (element k = e * 64 + lane, so the walk
+// order is k order) by an 8-bit digit: dest[e] = position of element k.
+template <int E, class DigitOf>
+__device__ __forceinline__ void wave_rank8(int m, DigitOf digit_of, uint32_t *hist, uint32_t (&dest)[E]) {
+    const int lane = lane_id();
+    for (int i = lane; i < 256; i += 64) hist[i] = 0;
+    wave_sync();
+    uint32_t rk[E], dg[E];
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * 64 + lane;
+        const bool act = k < m;
+        const uint32_t d = act ? digit_of(k) : 0u;
+        uint64_t peers = __ballot(act);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool x = (d >> bit) & 1u;
+            const uint64_t bb = __ballot(x);
+            peers &= x ? bb : ~bb;
+        }
+        uint32_t r = 0;
+        if (act) {
+            const uint32_t below = (uint32_t)__popcll(peers & lt);
+            const uint32_t base = hist[d];
+            r = base + below;
+            __builtin_amdgcn_wave_barrier();
+            if (below == 0) hist[d] = base + (uint32_t)__popcll(peers);
+        } else {
+            __builtin_amdgcn_wave_barrier();
+        }
+        __builtin_amdgcn_wave_barrier();
+        rk[e] = r;
+        dg[e] = d;
+    }
+    wave_sync();
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { v[i] = hist[lane * 4 + i]; sum += v[i]; }
+    const uint32_t incl = wave_incl_scan(sum);
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { hist[lane * 4 + i] = run; run += v[i]; }
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (e * 64 + lane < m) dest[e] = hist[dg[e]] + rk[e];
+    wave_sync();
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
+    constexpr int EG = WAVE_CAP / 64;
+    constexpr int RI = WAVE_RUNS / 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    WaveSeg &sm = reinterpret_cast<WaveSeg *>(smem_raw)[w];
+    const uint32_t total = b.counters[Q_SEG_TOTAL];
+    const uint32_t nwv = gridDim.x * 4;
+    const uint32_t gw = blockIdx.x * 4 + (uint32_t)w;
+    const uint32_t per = (total + nwv - 1) / nwv;
+    const uint32_t first = gw * per;
+    const uint32_t end = (first + per < total) ? first + per : total;
+    uint32_t si = 0, s_base = 1, s_end = 0;
+    const uint16_t *in_pmt = nullptr, *in_q = nullptr;
+    const int64_t *in_t = nullptr;
+    const uint32_t *pos = nullptr;
+    uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
+    uint32_t pbits = 0;
+    Plan P = {};
+    for (uint32_t item = first; item < end; ++item) {
+        if (item < s_base || item >= s_end) {
+            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
+            P = b.plans[si];
+            const SliceDev &S = b.slices[si];
+            in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
+            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx; pbits = S.pbits;
+            s_base = P.seg_item_base;
+            s_end = s_base + P.n_seg;
+        }
+        const uint32_t j = item - s_base;
+        const uint32_t row_len = P.n_seg + 1;
+        const uint32_t seg_lo = (uint32_t)((uint64_t)j << P.shift);
+        const uint32_t R = P.n_runs;
+        // the segment's stretch of every run (run r = i * 64 + lane)
+        uint32_t lo[RI], hi[RI], st[RI];
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const uint32_t r = (uint32_t)(i * 64 + lane);
+            lo[i] = hi[i] = st[i] = 0;
+            if (r < R) {
+                const uint32_t *row = pos + (uint64_t)r * row_len;
+                lo[i] = row[j];
+                hi[i] = row[j + 1];
+                st[i] = row[0];
+            }
+        }
+        uint32_t m = 0, gpart = 0;
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const uint32_t c = hi[i] - lo[i];
+            const uint32_t incl = wave_incl_scan(c);
+            const uint32_t r = (uint32_t)(i * 64 + lane);
+            if (r < R) {
+                sm.run_lo[r] = lo[i];
+                sm.run_base[r] = m + incl - c;
+            }
+            m += __shfl(incl, 63, 64);
+            gpart += lo[i] - st[i];
+        }
+        const uint32_t goff = wave_sum_u32(gpart);
+        if (m > (uint32_t)WAVE_CAP) {
+            if (lane == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
+            continue;
+        }
+        wave_sync();
+        // gather: EG hits per lane in flight
+        uint32_t src[EG];
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)(e * 64 + lane);
+            src[e] = 0xFFFFFFFFu;
+            if (k < m) {
+                uint32_t a = 0, z = R;   // last run whose base is <= k
+                while (a < z) {
+                    const uint32_t mid = (a + z) >> 1;
+                    if (sm.run_base[mid] <= k) a = mid + 1; else z = mid;
+                }
+                src[e] = sm.run_lo[a - 1] + (k - sm.run_base[a - 1]);
+            }
+        }
+        int64_t tv[EG];
+        uint32_t pv[EG], qv[EG];
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            if (src[e] != 0xFFFFFFFFu) {
+                tv[e] = in_t[src[e]];
+                pv[e] = in_pmt[src[e]];
+                qv[e] = in_q[src[e]];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)(e * 64 + lane);
+            if (src[e] != 0xFFFFFFFFu) {
+                sm.dt[k] = (uint32_t)(tv[e] - P.t_min);
+                sm.dpq[k] = (pv[e] << 16) | qv[e];
+                sm.didx[k] = src[e];
+            }
+        }
+        // bucket scatter by the top 8 bits of the local time
+        const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
+        for (int i = lane; i < 256; i += 64) sm.bcount[i] = 0;
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)(e * 64 + lane);
+            if (k < m) sm.perm[1][k] = (uint16_t)atomicAdd(&sm.bcount[(sm.dt[k] - seg_lo) >> tb], 1u);
+        }
+        wave_sync();
+        uint32_t v[4], sum = 0, vmax = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[i] = sm.bcount[lane * 4 + i];
+            sum += v[i];
+            vmax = v[i] > vmax ? v[i] : vmax;
+        }
+        {
+            const uint32_t incl = wave_incl_scan(sum);
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = run; run += v[i]; }
+        }
+        const bool crowd = __ballot(vmax > BUCKET_MAX) != 0ull;
+        wave_sync();
+        auto less = [&](uint32_t a, uint32_t c) -> bool {
+            if (sm.dt[a] != sm.dt[c]) return sm.dt[a] < sm.dt[c];
+            const uint32_t pa = sm.dpq[a] >> 16, pc = sm.dpq[c] >> 16;
+            if (pa != pc) return pa < pc;
+            return sm.didx[a] < sm.didx[c];
+        };
+        int cur = 0;
+        if (!crowd) {
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t k = (uint32_t)(e * 64 + lane);
+                if (k < m) sm.perm[0][sm.bbase[(sm.dt[k] - seg_lo) >> tb] + sm.perm[1][k]] = (uint16_t)k;
+            }
+            wave_sync();
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t bc = v[i];
+                if (bc > 1) {
+                    uint16_t *bk = sm.perm[0] + sm.bbase[lane * 4 + i];
+                    for (uint32_t x = 1; x < bc; ++x) {
+                        const uint16_t vv = bk[x];
+                        uint32_t y = x;
+                        while (y > 0 && less(vv, bk[y - 1])) { bk[y] = bk[y - 1]; --y; }
+                        bk[y] = vv;
+                    }
+                }
+            }
+            wave_sync();
+        } else {
+            // crowded bucket: stable LSD radix over (t << pbits | pmt), then input order for ties
+            auto keyof = [&](uint32_t x) -> uint64_t {
+                return ((uint64_t)(sm.dt[x] - seg_lo) << pbits) | (uint64_t)(sm.dpq[x] >> 16);
+            };
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t k = (uint32_t)(e * 64 + lane);
+                if (k < m) sm.perm[0][k] = (uint16_t)k;
+            }
+            wave_sync();
+            const int passes = (int)((P.shift + pbits + 7) / 8);
+            for (int ps = 0; ps < passes; ++ps) {
+                const uint32_t sh8 = 8u * (uint32_t)ps;
+                uint32_t dest[EG];
+                wave_rank8<EG>((int)m, [&](int k) -> uint32_t { return (uint32_t)(keyof(sm.perm[cur][k]) >> sh8) & 255u; },
+                               sm.bcount, dest);
+#pragma unroll
+                for (int e = 0; e < EG; ++e) {
+                    const uint32_t k = (uint32_t)(e * 64 + lane);
+                    if (k < m) sm.perm[cur ^ 1][dest[e]] = sm.perm[cur][k];
+                }
+                wave_sync();
+                cur ^= 1;
+            }
+            for (uint32_t k = lane; k < m; k += 64) {
+                const uint32_t x = sm.perm[cur][k];
+                const uint64_t kv = keyof(x);
+                const bool tie_prev = k > 0 && keyof(sm.perm[cur][k - 1]) == kv;
+                const bool tie_next = k + 1 < m && keyof(sm.perm[cur][k + 1]) == kv;
+                if (!tie_prev && !tie_next) { sm.perm[cur ^ 1][k] = (uint16_t)x; continue; }
+                uint32_t a = k, z = k + 1;
+                while (a > 0 && keyof(sm.perm[cur][a - 1]) == kv) --a;
+                while (z < m && keyof(sm.perm[cur][z]) == kv) ++z;
+                uint32_t rank = 0;
+                for (uint32_t u = a; u < z; ++u) rank += sm.didx[sm.perm[cur][u]] < sm.didx[x];
+                sm.perm[cur ^ 1][a + rank] = (uint16_t)x;
+            }
+            wave_sync();
+            cur ^= 1;
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)(e * 64 + lane);
+            if (k < m) {
+                const uint32_t x = sm.perm[cur][k];
+                o_t[goff + k] = sm.dt[x];
+                o_pq[goff + k] = sm.dpq[x];
+                o_idx[goff + k] = sm.didx[x];
+            }
+        }
+        wave_sync();
+    }
+}
+
+hipError_t launch_segsort_w(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s) {
+    const size_t shm = 4 * sizeof(WaveSeg);
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_segsort_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    const int grid = cfg.n_cu * cfg.persist_per_cu;
+    hipLaunchKernelGGL(k_segsort_w, dim3(grid), dim3(256), shm, s, b);
+    return hipGetLastError();
+}
+
 template <int NT, int CAP>
 hipError_t launch_segsort(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s) {
     const size_t shm = sizeof(SegShared<NT, CAP>);
@@ -480,8 +789,8 @@ hipError_t launch_segsort(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
 #define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, const TrigLaunchCfg &cfg, hipStream_t s,
-                             void (*mark)(void *, const char *, int), void *mark_ctx) {
+hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, int wave_wgs_per_cu, const TrigLaunchCfg &cfg,
+                             hipStream_t s, void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (b.total_chunks) {
         TRIG_MARK("k_ingest", 0);
         hipLaunchKernelGGL(k_ingest, dim3(b.total_chunks), dim3(NT_ING), 0, s, b);
@@ -498,12 +807,22 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, const TrigLaun
         TRIG_CHECK();
         TRIG_MARK("k_bounds", 1);
     }
-    TRIG_MARK("k_segsort", 0);
     hipError_t e;
-    if (seg_cap <= 2048) e = launch_segsort<256, 2048>(b, cfg, s);
-    else if (seg_cap <= 4096) e = launch_segsort<256, 4096>(b, cfg, s);
-    else e = launch_segsort<512, 8192>(b, cfg, s);
-    if (e != hipSuccess) return e;
-    TRIG_MARK("k_segsort", 1);
+    if (b.sort_kernels & 1u) {
+        TRIG_MARK("k_segsort_w", 0);
+        TrigLaunchCfg wc = cfg;
+        wc.persist_per_cu = wave_wgs_per_cu;
+        e = launch_segsort_w(b, wc, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_segsort_w", 1);
+    }
+    if (b.sort_kernels & 2u) {
+        TRIG_MARK("k_segsort", 0);
+        if (seg_cap <= 2048) e = launch_segsort<256, 2048>(b, cfg, s);
+        else if (seg_cap <= 4096) e = launch_segsort<256, 4096>(b, cfg, s);
+        else e = launch_segsort<512, 8192>(b, cfg, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_segsort", 1);
+    }
     return hipSuccess;
 }

@@ -39,6 +39,8 @@ constexpr int GTILE = 4096;       // elements per block of the general radix sor
 constexpr int LDS_THR_MAX_PMT = 128;  // thr table kept in LDS up to this many PMTs
 constexpr int SEED_LDS_FLOORS = 8192; // dense floor ids kept in LDS up to this many PMTs
 constexpr int ROWGROUPS = 8;      // counting rows split over the 8 XCDs for large tables
+constexpr int WAVE_CAP = 512;     // hits per segment of the wave-per-segment ordering
+constexpr int WAVE_RUNS = 256;    // most runs a wave-per-segment slice may have
 
 enum State : uint32_t {
     ST_SKIP = 0,          // error or empty: nothing to do
@@ -54,6 +56,7 @@ enum Counter : int {
     Q_COUNT_TOTAL = 2,   // number of counting items
     C_PLAN_DONE = 3,     // slices planned so far (the last block builds the segment work list)
     C_SCAN_DONE = 4,     // slices whose seed list is scanned (the last block builds the count work list)
+    Q_SEG_TOTAL_B = 5,   // number of segment items of the block-per-segment kernel
     N_COUNTERS = 16,
 };
 
@@ -82,7 +85,9 @@ struct Plan {
     uint32_t count_item_base;
     uint32_t groups;         // counting row groups (1 or ROWGROUPS)
     uint32_t overflow;       // a segment exceeded the LDS capacity
-    uint32_t pad[3];
+    uint32_t seg_item_base_b;  // base in the block-kernel segment work list
+    uint32_t seg_kind;       // 0: wave-per-segment ordering, 1: block-per-segment ordering
+    uint32_t pad;
 };
 
 struct SliceDev {
@@ -123,6 +128,8 @@ struct BatchDev {
     uint32_t total_chunks;
     uint32_t total_tiles;
     uint32_t tail_state;     // the tail kernels process slices in this state
+    uint32_t sort_kernels;   // ordering kernels launched: bit 0 wave-per-segment, bit 1 block-per-segment
+    uint32_t block_cap, block_target;   // block kernel capacity / target for slices it takes over
     uint32_t *counters;
     Plan *x_plans;           // host-mapped copy of the plans written at the end of the tail
     trig_params prm;
@@ -253,8 +260,9 @@ struct TrigLaunchCfg {
     int persist_per_cu;
 };
 
-hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, const TrigLaunchCfg &cfg,
-                             hipStream_t s, void (*mark)(void *, const char *, int), void *mark_ctx);
+hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, int wave_wgs_per_cu,
+                             const TrigLaunchCfg &cfg, hipStream_t s, void (*mark)(void *, const char *, int),
+                             void *mark_ctx);
 hipError_t trig_launch_tail(const trigdev::BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s,
                             void (*mark)(void *, const char *, int), void *mark_ctx);
 // General path for one slice: device-wide stable LSD radix sort over key_bits
