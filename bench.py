@@ -29,7 +29,8 @@ ALGO_BYTES_PER_HIT = {
     "k_ingest": 10.0,      # read t (8) + pmt (2)
     "k_bounds": 8.0,       # read t (8); the boundary table is counted separately
     "k_segsort": 24.0,     # read t, pmt, q (12) + write ordered t, pmt|q, index (12)
-    "k_seed": 8.125,       # read ordered t + pmt|q (8) + write one seed bit
+    "k_segsort_w": 24.0,   # the same, one wave per segment
+    "k_trig": 8.0,         # read ordered t + pmt|q (8); fires and events are per fire
 }
 
 
@@ -42,7 +43,182 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
+    ap.add_argument("--batch-slices", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-form leg")
+    ap.add_argument("--serve-pool", type=int, default=48, help="distinct pre-generated slices replayed")
+    ap.add_argument("--serve-slices", type=int, default=10000, help="slices of the saturating run")
+    ap.add_argument("--serve-inflight", type=int, default=32)
+    ap.add_argument("--serve-paced-slices", type=int, default=800, help="slices of the real-time run")
     return ap.parse_args()
+
+
+def _dev_slice(torch, dev, s):
+    return (torch.from_numpy(s.pmt.view(np.int16)).to(dev), torch.from_numpy(s.t).to(dev),
+            torch.from_numpy(s.q.view(np.int16)).to(dev))
+
+
+def _pct(x, p):
+    return round(float(np.percentile(np.asarray(x), p)), 4) if len(x) else None
+
+
+def bench_batch(T, torch, dev, a):
+    """Batched form: many uneven slices of two tower types in one launch sequence,
+    against the same slices triggered one call each."""
+    from gen import configs as C
+    g0 = time.perf_counter()
+    w = C.batch(seed=2, n_slices=a.batch_slices)
+    gen_s = time.perf_counter() - g0
+    tr = T.Trigger(0)
+    gids = {k: tr.load_geometry(g.floor_id, thr) for k, (g, thr) in w.geoms.items()}
+    dsl = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in w.slices]
+    n = int(sum(s.n for _, s in w.slices))
+    torch.cuda.synchronize()
+    first = tr.batch(dsl, w.params)
+    assert all(r["status"] == 0 for r in first)
+    caps = [(max(1, r["n_fires"]), max(1, r["n_events"])) for r in first]
+    run = T.BatchRunner(tr.ctx, dsl, w.params, caps=caps)
+    for _ in range(2):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.batch_steps):
+        res = run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / a.batch_steps
+    # the same slices, one plain per-slice call each
+    runners = [T.SliceRunner(tr.ctx, *d, w.params, fire_cap=c[0], event_cap=c[1]) for d, c in zip(dsl, caps)]
+    for r in runners:
+        r()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for r, b in zip(runners, res):
+        x = r()
+        same &= x["n_fires"] == b["n_fires"] and np.array_equal(x["fires"], b["fires"]) \
+            and np.array_equal(x["events"], b["events"])
+    torch.cuda.synchronize()
+    el_loop = time.perf_counter() - t0
+    assert same, "batched and per-slice results differ"
+    T.trig_profile_enable(tr.ctx, True)
+    run()
+    torch.cuda.synchronize()
+    prof = T.trig_profile_read(tr.ctx)
+    T.trig_profile_enable(tr.ctx, False)
+    kernels = {}
+    for p in prof:
+        us = p["total_ms"] / max(1, p["launches"]) * 1e3
+        e = dict(avg_us=round(us, 2))
+        if p["name"] in ALGO_BYTES_PER_HIT:
+            e["gbs"] = round(ALGO_BYTES_PER_HIT[p["name"]] * n / (us * 1e-6) / 1e9, 1)
+        kernels[p["name"]] = e
+    tr.close()
+    return dict(workload="batch-256-mixed-32/84pmt-50-200ms", slices=len(dsl), hits=n,
+                value=round(n / el, 1), unit="hits/s", ms_per_batch=round(el * 1e3, 3),
+                per_slice_loop=dict(value=round(n / el_loop, 1), ms=round(el_loop * 1e3, 3)),
+                speedup_vs_per_slice=round(el_loop / el, 3), results_equal_per_slice=bool(same),
+                fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1))
+
+
+def bench_serving(T, torch, dev, a):
+    """Serving form: slices submitted to the stream loop as they arrive (device
+    resident), results polled; every result is checked against the same slice
+    triggered alone."""
+    from gen import configs as C
+    w = C.serving_pool(seed=4, n_pool=a.serve_pool)
+    g, thr = w.geoms["km3"]
+    tr = T.Trigger(0, hbm_budget_bytes=32 << 30)
+    gid = tr.load_geometry(g.floor_id, thr)
+    pool = [_dev_slice(torch, dev, s) for _, s in w.slices]
+    ns = [int(s.n) for _, s in w.slices]
+    alone = [tr.slice(gid, *d, w.params) for d in pool]
+    torch.cuda.synchronize()
+    cap = max(max(r["n_fires"] for r in alone), max(r["n_events"] for r in alone), 1)
+    bufs = [T.ResultBuffers(cap, cap, 0, False) for _ in range(max(a.serve_inflight, 64))]
+
+    def run(order, arrivals, inflight_max):
+        """Submit pool[order[i]] at arrivals[i] (None: as soon as fewer than
+        inflight_max are outstanding); returns (latencies s, wall s, mismatches)."""
+        lat, bad = [], 0
+        outstanding = []      # [ticket, arrival, pool index, buffer]
+        free = list(range(len(bufs)))
+        i, n_tot = 0, len(order)
+        t_start = time.perf_counter()
+
+        def finish(j, rc, r):
+            nonlocal bad
+            tk, arr, k, bi = outstanding.pop(j)
+            lat.append(time.perf_counter() - t_start - arr)
+            free.append(bi)
+            if rc != T.TRIG_OK or r["n_fires"] != alone[k]["n_fires"] or \
+                    not np.array_equal(r["fires"], alone[k]["fires"]) or \
+                    not np.array_equal(r["events"], alone[k]["events"]):
+                bad += 1
+
+        while i < n_tot or outstanding:
+            now = time.perf_counter() - t_start
+            while i < n_tot and len(outstanding) < inflight_max and \
+                    (arrivals is None or arrivals[i] <= now):
+                k = order[i]
+                rc, tk = T.trig_stream_submit(tr.ctx, gid, *pool[k], w.params, tag=i)
+                if rc == T.TRIG_EAGAIN:
+                    break
+                if rc != T.TRIG_OK:
+                    raise T.TrigError(rc, T.trig_last_error(tr.ctx))
+                outstanding.append((tk, now if arrivals is None else float(arrivals[i]), k, free.pop()))
+                i += 1
+            done_any = False
+            j = 0
+            while j < len(outstanding):
+                rc, r = T.trig_stream_poll(tr.ctx, outstanding[j][0], timeout_us=0, buffers=bufs[outstanding[j][3]])
+                if rc == T.TRIG_PENDING:
+                    j += 1
+                    continue
+                finish(j, rc, r)
+                done_any = True
+            if done_any:
+                continue
+            wait = 0.0002
+            if arrivals is not None and i < n_tot:
+                wait = min(wait, max(0.0, arrivals[i] - (time.perf_counter() - t_start)))
+            if outstanding:
+                rc, r = T.trig_stream_poll(tr.ctx, outstanding[0][0], timeout_us=int(wait * 1e6),
+                                           buffers=bufs[outstanding[0][3]])
+                if rc != T.TRIG_PENDING:
+                    finish(0, rc, r)
+            else:
+                time.sleep(wait)
+        return lat, time.perf_counter() - t_start, bad
+
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 99])))
+    # saturating: arrivals as fast as admission and the in-flight cap allow
+    order = rng.integers(0, len(pool), a.serve_slices)
+    run(order[:min(64, len(order))], None, a.serve_inflight)          # warm-up
+    lat, wall, bad = run(order, None, a.serve_inflight)
+    hits = int(sum(ns[k] for k in order))
+    sat = dict(slices=int(len(order)), hits=hits, value=round(hits / wall, 1), unit="hits/s",
+               latency_ms=dict(p50=_pct(np.array(lat) * 1e3, 50), p99=_pct(np.array(lat) * 1e3, 99)),
+               inflight=a.serve_inflight, mismatches=bad)
+    # paced: 16 towers, slice k of a tower arrives at k * 200 ms + Exp(10 ms)
+    m = a.serve_paced_slices
+    k_of = np.arange(m) // 16
+    arr = k_of * 0.2 + rng.exponential(0.010, m)
+    ordp = np.argsort(arr, kind="stable")
+    arr = arr[ordp]
+    porder = rng.integers(0, len(pool), m)
+    lat_p, wall_p, bad_p = run(porder, arr, 1 << 30)
+    hits_p = int(sum(ns[k] for k in porder))
+    paced = dict(slices=m, hits=hits_p, offered=round(hits_p / float(arr[-1] + 1e-9), 1),
+                 sustained=round(hits_p / wall_p, 1), unit="hits/s",
+                 latency_ms=dict(p50=_pct(np.array(lat_p) * 1e3, 50), p99=_pct(np.array(lat_p) * 1e3, 99),
+                                 max=_pct(np.array(lat_p) * 1e3, 100)),
+                 mismatches=bad_p)
+    stats = T.trig_stream_stats_get(tr.ctx)
+    tr.close()
+    assert bad == 0 and bad_p == 0, "serving results differ from the slices triggered alone"
+    return dict(workload="serving-16x84pmt-200ms-50-150kHz", pool=len(pool), saturating=sat, paced=paced,
+                rounds=stats.get("rounds"), device_bytes_peak=stats.get("device_bytes_peak"))
 
 
 def main():
@@ -130,6 +306,10 @@ def main():
         cpu = dict(value=round(n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
                    sample=f"blocked form, whole {n}-hit slice x {reps} runs ({tc:.1f} s)")
 
+    tr.close()
+    batch = None if a.no_batch else bench_batch(T, torch, dev, a)
+    serving = None if a.no_serve else bench_serving(T, torch, dev, a)
+
     lat_ms = np.array(lat) * 1e3
     out = dict(
         metric="hits/s triggered on 1 MI355X",
@@ -152,8 +332,9 @@ def main():
         kernels=per_kernel,
         cpu_baseline=cpu,
         results=dict(n_seeds=r["n_seeds"], n_fires=r["n_fires"], n_events=r["n_events"], path=r["path"]),
+        batched=batch,
+        serving=serving,
     )
-    tr.close()
     print(json.dumps(out))
 
 

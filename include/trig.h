@@ -139,8 +139,10 @@ typedef struct {
  * input position, 1 for a seed).  The library fills the counts, status and
  * tag.  Fires are ordered by (t_ns, pmt_id, hit_index), events by t_begin.
  * On TRIG_EOVERFLOW n_fires / n_events hold the required counts and no list
- * is written.  path reports the ordering method used (0: run merge, 1:
- * general radix sort). */
+ * is written.  path reports how the slice was processed: bit 0 set when the
+ * general radix sort ordered it (else the run merge), bit 1 set when its
+ * trigger stage was rerun with a precomputed seed mask (a burst far denser than
+ * the slice's mean density). */
 typedef struct {
     trig_fire  *fires;
     uint64_t    fire_cap, n_fires;

@@ -82,27 +82,6 @@ void DevBuf::release(trig_ctx *c) {
     cap = 0;
 }
 
-int DevBuf::ensure_async(trig_ctx *c, size_t want, hipStream_t s) {
-    if (want <= cap) return TRIG_OK;
-    if (ptr) hipFreeAsync(ptr, s);
-    ptr = nullptr;
-    cap = 0;
-    hipError_t e = hipMallocAsync(&ptr, std::max<size_t>(want, 256), s);
-    if (e != hipSuccess) {
-        ptr = nullptr;
-        ctx_set_error(c, "hipMallocAsync(%zu): %s", want, hipGetErrorString(e));
-        return TRIG_ENOMEM;
-    }
-    cap = std::max<size_t>(want, 256);
-    return TRIG_OK;
-}
-
-void DevBuf::release_async(hipStream_t s) {
-    if (ptr) hipFreeAsync(ptr, s);
-    ptr = nullptr;
-    cap = 0;
-}
-
 int PinBuf::ensure(size_t want) {
     if (want <= cap) return TRIG_OK;
     if (ptr) hipHostFree(ptr);
@@ -198,17 +177,17 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.o_t = take(n * 4 + 4);
     L.o_pq = take(n * 4 + 4);
     L.o_idx = take(n * 4 + 4);
-    L.seed_mask = take(std::max<uint64_t>(n_tiles, 1) * (TILE / 64) * 8);
-    L.tile_seeds = take(std::max<uint64_t>(n_tiles, 1) * 4);
-    L.s_t = take(n * 4 + 4);
-    L.s_pq = take(n * 4 + 4);
-    L.s_idx = take(n * 4 + 4);
-    L.s_fold = take(n * 4 + 4);
-    L.ctile = take((n / CT1 + 2) * 4);
+    L.tstat = take(std::max<uint64_t>(n_tiles, 1) * sizeof(TileStat));
+    L.dmask = take((n / 64 + 1) * 8);
+    L.fsc = take(std::max<uint64_t>(n_tiles, 1) * TILE * sizeof(FireRec));
     L.fires = take(n * sizeof(trig_fire) + 32);
     L.events = take(n * sizeof(trig_event) + 32);
     L.flags = want_flags ? take(n + 4) : SIZE_MAX;
     return o;
+}
+
+size_t job_meta_bytes(uint32_t n) {
+    return align256(n * sizeof(SliceDev)) + align256(n * sizeof(Plan)) + 256;
 }
 
 size_t slice_footprint(uint64_t n, bool host_input) {
@@ -225,6 +204,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     uint32_t chunk_base = 0, tile_base = 0;
     uint32_t cap_max = 0;
     sort_kernels = 0;
+    max_pmt = 0;
     wave_wgs = 0;
     block_wgs = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -252,10 +232,11 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         si.chunk_base = chunk_base;
         si.n_chunks = (uint32_t)((nh + CHUNK - 1) / CHUNK);
         si.tile_base = tile_base;
-        si.n_tiles = (uint32_t)((nh + TILE - 1) / TILE);
+        si.n_tiles = std::max<uint32_t>(1, (uint32_t)((nh + TILE - 1) / TILE));
         chunk_base += si.n_chunks;
         tile_base += si.n_tiles;
         const uint32_t np = (d[i].geom_id < c->geoms.size()) ? c->geoms[d[i].geom_id].n_pmt : 1u;
+        max_pmt = std::max(max_pmt, np);
         si.tune = ctx_tune_for(c, np);
         if (si.host_status == TRIG_OK && nh) {
             if (si.tune.seg_cap == (uint32_t)WAVE_CAP) {
@@ -286,10 +267,19 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     total_chunks = chunk_base;
     total_tiles = tile_base;
-    const size_t desc_bytes = align256(n * sizeof(SliceDev)) + align256(n * sizeof(Plan)) + 256;
-    int rc = async_mem ? ws.ensure_async(c, total, s) : ws.ensure(c, total, s);
+    const size_t desc_bytes = job_meta_bytes(n);
+    const bool own_ws = ext_ws.empty();
+    if (!own_ws) {
+        bool bad = ext_ws.size() != n;
+        for (uint32_t i = 0; !bad && i < n; ++i) bad = d[i].mem == TRIG_MEM_HOST && d[i].n_hits;
+        if (bad) {   // caller-supplied workspaces hold no input staging
+            ctx_set_error(c, "internal: workspace bases need %u device-resident slices", n);
+            return TRIG_EINVAL;
+        }
+    }
+    int rc = own_ws ? ws.ensure(c, total, s) : TRIG_OK;
     if (rc) return rc;
-    rc = async_mem ? dmeta.ensure_async(c, desc_bytes, s) : dmeta.ensure(c, desc_bytes, s);
+    rc = dmeta.ensure(c, desc_bytes, s);
     if (rc) return rc;
     if (h_slices.ensure(n * sizeof(SliceDev) + 64) || h_plans.ensure(xs + 64)) {
         ctx_set_error(c, "pinned host allocation failed");
@@ -314,7 +304,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
         SliceDev S = {};
-        char *b = base + si.ws_off;
+        char *b = own_ws ? base + si.ws_off : ext_ws[i];
         const SliceLayout &L = si.L;
         const uint64_t nh = si.n;
         if (si.host_status == TRIG_OK) {
@@ -361,17 +351,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.o_t = (uint32_t *)(b + L.o_t);
         S.o_pq = (uint32_t *)(b + L.o_pq);
         S.o_idx = (uint32_t *)(b + L.o_idx);
-        S.seed_mask = (uint64_t *)(b + L.seed_mask);
-        S.tile_seeds = (uint32_t *)(b + L.tile_seeds);
-        S.s_t = (uint32_t *)(b + L.s_t);
-        S.s_pq = (uint32_t *)(b + L.s_pq);
-        S.s_idx = (uint32_t *)(b + L.s_idx);
-        S.s_fold = (uint32_t *)(b + L.s_fold);
-        S.ctile_fires = (uint32_t *)(b + L.ctile);
-        // event scratch reuses the ordered arrays (dead once the seed list exists)
-        S.fire_ev = S.o_t;
-        S.ev_first = S.o_pq;
-        S.ev_max = S.o_idx;
+        S.tstat = (TileStat *)(b + L.tstat);
+        S.dmask = (uint64_t *)(b + L.dmask);
+        S.fsc = (FireRec *)(b + L.fsc);
         S.fires = (trig_fire *)(b + L.fires);
         S.events = (trig_event *)(b + L.events);
         S.seed_flags = si.want_flags ? (uint8_t *)(b + L.flags) : nullptr;
@@ -413,7 +395,7 @@ int Job::launch(trig_ctx *c, bool profile) {
     auto eager = [&](hipStream_t s) -> int {
         hipError_t e = trig_launch_front(batch, seg_cap, (int)std::max<uint32_t>(1, wave_wgs), cfg, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "front kernels");
-        e = trig_launch_tail(batch, cfg, s, mark, c);
+        e = trig_launch_tail(batch, cfg, max_pmt, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
         return TRIG_OK;
     };
@@ -482,37 +464,54 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     for (uint32_t i : todo) {
         SliceInfo &si = slices[i];
+        // the slice's fire and event areas are unused until its trigger stage runs,
+        // so the radix scratch lives there when it fits (always but for tiny slices)
         const size_t need = trig_generic_scratch_bytes(si.n);
-        int rc;
-        if (async_mem) {
-            if (need > gscratch.cap) {
-                if (ctx_reserve(c, need - gscratch.cap) != TRIG_OK) {
-                    ctx_set_error(c, "device budget exceeded by general-path scratch");
-                    return TRIG_ENOMEM;
-                }
-                async_extra += need - gscratch.cap;
-            }
-            rc = gscratch.ensure_async(c, need, stream);
-        } else {
-            rc = gscratch.ensure(c, need, stream);
+        const size_t avail = si.L.events + align256(si.n * sizeof(trig_event) + 32) - si.L.fires;
+        void *scratch = si.dev.fires;
+        if (need > avail) {
+            const int rc = gscratch.ensure(c, need, stream);
+            if (rc) return rc;
+            scratch = gscratch.ptr;
         }
-        if (rc) return rc;
         const uint64_t span = (uint64_t)hp[i].t_max - (uint64_t)hp[i].t_min;
         const uint32_t span_bits = span ? 64u - (uint32_t)__builtin_clzll(span) : 0u;
         const uint32_t key_bits = span_bits + si.dev.pbits;
-        hipError_t e = trig_launch_generic_slice(si.dev, hp[i], key_bits, gscratch.ptr, stream, mark, c);
+        hipError_t e = trig_launch_generic_slice(si.dev, hp[i], key_bits, scratch, stream, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "general ordering");
     }
     BatchDev b2 = batch;
     b2.tail_state = ST_GENERIC_DONE;
     TrigLaunchCfg cfg = c->cfg;
     cfg.persist_per_cu = (int)std::max<uint32_t>(2, block_wgs);
-    hipError_t e = trig_launch_tail(b2, cfg, stream, mark, c);
+    hipError_t e = trig_launch_tail(b2, cfg, max_pmt, stream, mark, c);
     if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
     int rc2 = enqueue_flags(c, &todo);
     if (rc2) return rc2;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (general path)");
+    return TRIG_OK;
+}
+
+// After the plans arrived on the host: rerun the trigger stage of the slices
+// whose windows outran the staged halo, with a precomputed seed mask.
+int Job::dense_pass(trig_ctx *c, bool profile) {
+    Plan *hp = (Plan *)h_plans.ptr;
+    std::vector<uint32_t> todo;
+    for (uint32_t i = 0; i < slices.size(); ++i)
+        if (slices[i].host_status == TRIG_OK && hp[i].status == TRIG_OK && hp[i].dense &&
+            (hp[i].state == ST_FAST || hp[i].state == ST_GENERIC_DONE))
+            todo.push_back(i);
+    if (todo.empty()) return TRIG_OK;
+    void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
+    BatchDev b3 = batch;
+    b3.tail_state = ST_DENSE;
+    hipError_t e = trig_launch_dense(b3, c->cfg, max_pmt, stream, mark, c);
+    if (e != hipSuccess) return hip_fail(c, e, "trigger stage (dense rerun)");
+    int rc = enqueue_flags(c, &todo);
+    if (rc) return rc;
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise (dense rerun)");
     return TRIG_OK;
 }
 
@@ -522,7 +521,7 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     const Plan &P = ((Plan *)h_plans.ptr)[i];
     r->tag = si.desc.tag;
     r->n_hits = si.desc.n_hits;
-    r->path = (P.state == ST_GENERIC_DONE) ? 1u : 0u;
+    r->path = (P.generic ? 1u : 0u) | (P.dense ? 2u : 0u);
     r->n_seeds = r->n_fires = r->n_events = 0;
     if (si.host_status != TRIG_OK) return r->status = si.host_status;
     if (P.status != TRIG_OK) {
@@ -613,6 +612,8 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise");
     rc = J.generic_pass(c, prof);
+    if (rc) return rc;
+    rc = J.dense_pass(c, prof);
     if (rc) return rc;
     int first_bad = TRIG_OK;
     for (uint32_t i = 0; i < n; ++i) {

@@ -17,9 +17,6 @@ struct DevBuf {
     size_t cap = 0;
     int ensure(trig_ctx *c, size_t want, hipStream_t s);   // grows; contents not kept; budget-accounted
     void release(trig_ctx *c);
-    // Stream-ordered variants (serving rounds): the caller accounts the bytes.
-    int ensure_async(trig_ctx *c, size_t want, hipStream_t s);
-    void release_async(hipStream_t s);
 };
 
 struct PinBuf {
@@ -39,8 +36,7 @@ struct GeomDev {
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
 struct SliceLayout {
-    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, seed_mask, tile_seeds;
-    size_t s_t, s_pq, s_idx, s_fold, ctile, fires, events, flags;
+    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags;
     uint64_t pos_cap;
 };
 
@@ -68,14 +64,16 @@ struct Job {
     uint32_t sort_kernels = 0;        // ordering kernels to launch (bit 0 wave, bit 1 block)
     uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
     uint32_t total_chunks = 0, total_tiles = 0;
+    uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;
     PinBuf h_slices, h_plans;
     trigdev::SliceDev *d_slices = nullptr;
     trigdev::Plan *d_plans = nullptr;
     uint32_t *d_counters = nullptr;
     trigdev::BatchDev batch;
-    bool async_mem = false;          // serving: workspace from the stream-ordered pool
-    uint64_t async_extra = 0;        // serving: bytes accounted on demand (general-path scratch)
+    // per-slice workspace bases supplied by the caller (serving: each ticket's
+    // region of the resident arena); empty: one workspace owned by the job
+    std::vector<char *> ext_ws;
     // h_plans is the pinned result staging: plans, then each slice's fires and events
     trigdev::Plan *x_plans_dev = nullptr;
     // launch-sequence graph: captured on the second call with the same launch key
@@ -91,6 +89,7 @@ struct Job {
     int launch(trig_ctx *c, bool profile);
     int enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only);   // null: every slice
     int generic_pass(trig_ctx *c, bool profile);
+    int dense_pass(trig_ctx *c, bool profile);
     int deliver(trig_ctx *c, uint32_t i, trig_result *r);
     void release(trig_ctx *c);
 };
@@ -135,3 +134,5 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
 void serve_shutdown(trig_ctx *c);
 // Device bytes one slice of n hits needs in a job workspace (host inputs staged in it or not).
 size_t slice_footprint(uint64_t n, bool host_input);
+// Device bytes of a job's descriptors, plans and counters for n slices.
+size_t job_meta_bytes(uint32_t n);

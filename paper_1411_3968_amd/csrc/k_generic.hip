@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NT) void k_gscatter(uint64_t n, const uint64_t *key
 
 __global__ __launch_bounds__(NT) void k_gfinish(SliceDev S, const uint64_t *key, const uint32_t *val) {
     const uint64_t k = (uint64_t)blockIdx.x * NT + threadIdx.x;
-    if (k == 0) S.plan->state = ST_GENERIC_DONE;
+    if (k == 0) { S.plan->state = ST_GENERIC_DONE; S.plan->generic = 1; }
     if (k >= S.n) return;
     const uint64_t kv = key[k];
     const uint32_t v = val[k];

@@ -1,0 +1,673 @@
+// Trigger stage on the time-ordered hits of each slice:
+//   L1 seeds (paper Sec. 3 and Sec. 4.2: charge over threshold, floor coincidence),
+//   causal N-fold count (Sec. 3: the Cherenkov hits of one muon are correlated in
+//   space and time, within less than 3 us across a tower), fires, and the merged
+//   event windows (Sec. 2: a 6 us window centred on the trigger seed; Sec. 4.2:
+//   +-3 us tagging around each seed).
+//
+// k_tile: one workgroup per ordered tile of TILE hits.  The tile and a halo of
+// ordered neighbours on both sides are staged in LDS; the halo is sized from the
+// slice's mean hit density so that it spans w_ns + t_floor_ns of time.  Seeds are
+// marked for the whole stage, the stage's seeds are compacted in LDS, and the
+// fold of each seed of the tile is counted over the compacted seeds within w_ns.
+// The tile's fires go to its scratch slot, and a summary of them (TileAgg: count,
+// first and last time, event starts among them, largest folds around the starts)
+// to its status.  A tile whose halo does not span the window (a local burst far
+// above the mean density) flags its slice for a rerun with a precomputed seed
+// mask and a wider halo, where such tiles are counted from global memory.
+// k_tscan: per slice, the scan of the tile summaries gives every tile the
+// summary of the tiles before it.  k_place: every tile with fires writes them at
+// their place in the slice's list, and writes event records in two halves: the
+// tile of an event's first fire writes its start, the tile of the next event's
+// first fire (or k_tscan, for the slice's last event) its end, fire count and
+// largest fold.  No workgroup waits on another.
+#include <algorithm>
+
+#include "trig_dev.h"
+
+using namespace trigdev;
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+
+__device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = umax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ TileAgg agg_empty() {
+    TileAgg a;
+    a.F = a.S = a.E_int = a.first_t = a.last_t = a.m_head = a.m_tail = a.ls_t = 0;
+    a.ls_idx = NO_START;
+    return a;
+}
+
+// Summary of run A followed by run B (twoH: the merge distance 2H).  Associative.
+__device__ __forceinline__ TileAgg agg_combine(const TileAgg &A, const TileAgg &B, uint64_t twoH) {
+    if (A.F == 0) {
+        TileAgg r = B;
+        r.S = A.S + B.S;
+        return r;
+    }
+    if (B.F == 0) {
+        TileAgg r = A;
+        r.S = A.S + B.S;
+        return r;
+    }
+    const bool bs = (uint64_t)(B.first_t - A.last_t) > twoH;
+    TileAgg r;
+    r.F = A.F + B.F;
+    r.S = A.S + B.S;
+    r.first_t = A.first_t;
+    r.last_t = B.last_t;
+    r.E_int = A.E_int + B.E_int + (bs ? 1u : 0u);
+    r.m_head = (A.E_int > 0 || bs) ? A.m_head : umax(A.m_head, B.m_head);
+    r.m_tail = (B.E_int > 0 || bs) ? B.m_tail : umax(A.m_tail, B.m_tail);
+    if (B.E_int > 0) {
+        r.ls_idx = A.F + B.ls_idx;
+        r.ls_t = B.ls_t;
+    } else if (bs) {
+        r.ls_idx = A.F;
+        r.ls_t = B.first_t;
+    } else {
+        r.ls_idx = A.ls_idx;
+        r.ls_t = A.ls_t;
+    }
+    return r;
+}
+
+// Index (within the slice's fire list) of the first fire of the last event of
+// a prefix summary.
+__device__ __forceinline__ uint32_t open_start(const TileAgg &P) { return P.ls_idx == NO_START ? 0u : P.ls_idx; }
+
+__device__ __forceinline__ TileAgg agg_shfl_up(const TileAgg &a, int d) {
+    TileAgg r;
+    r.F = __shfl_up(a.F, d, 64);
+    r.S = __shfl_up(a.S, d, 64);
+    r.E_int = __shfl_up(a.E_int, d, 64);
+    r.first_t = __shfl_up(a.first_t, d, 64);
+    r.last_t = __shfl_up(a.last_t, d, 64);
+    r.m_head = __shfl_up(a.m_head, d, 64);
+    r.m_tail = __shfl_up(a.m_tail, d, 64);
+    r.ls_idx = __shfl_up(a.ls_idx, d, 64);
+    r.ls_t = __shfl_up(a.ls_t, d, 64);
+    return r;
+}
+
+__device__ __forceinline__ bool mask_bit(const SliceDev &S, uint64_t j) { return (S.dmask[j >> 6] >> (j & 63)) & 1ull; }
+
+__device__ __forceinline__ uint32_t lim_global(const SliceDev &S, uint32_t W, uint32_t p, uint32_t q) {
+    const uint64_t x = (uint64_t)p * S.n_pmt + q;
+    const uint32_t v = (W <= 65535u) ? (uint32_t)S.thr16[x] : S.thr32[x];
+    return v < W ? v : W;
+}
+
+// Fold of seed j (time t, PMT p) counted from global memory with the seed mask.
+__device__ uint32_t fold_global(const SliceDev &S, uint32_t W, uint64_t j, uint32_t t, uint32_t p) {
+    uint32_t c = 1;
+    for (uint64_t m = j; m > 0;) {
+        --m;
+        const uint32_t d = t - S.o_t[m];
+        if (d > W) break;
+        const uint32_t q = S.o_pq[m] >> 16;
+        if (d <= lim_global(S, W, p, q) && mask_bit(S, m)) ++c;
+    }
+    for (uint64_t m = j + 1; m < S.n; ++m) {
+        const uint32_t d = S.o_t[m] - t;
+        if (d > W) break;
+        const uint32_t q = S.o_pq[m] >> 16;
+        if (d <= lim_global(S, W, p, q) && mask_bit(S, m)) ++c;
+    }
+    return c;
+}
+
+// Plans of slices whose trigger stage does not run in this pass (errors, empty
+// slices, general ordering pending) go to the host as they are.
+__device__ __forceinline__ bool export_as_is(uint32_t state) {
+    return state != ST_FAST && state != ST_GENERIC_DONE && state != ST_DENSE;
+}
+
+template <int HMAX, bool MASK>
+__global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
+    constexpr int STG = TILE + 2 * HMAX;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *st = (uint32_t *)smem;                 // staged t - t_min
+    uint32_t *sp = st + STG;                         // staged pmt << 16 | q
+    uint32_t *ct = sp + STG;                         // compacted seeds: time
+    uint32_t *fold = ct + STG;                       // fold of each seed of the tile
+    uint64_t *sbits = (uint64_t *)(fold + TILE);     // seed bits of the stage
+    uint32_t *wpre = (uint32_t *)(sbits + STG / 64); // seeds before each 64-hit word
+    uint16_t *cp = (uint16_t *)(wpre + STG / 64 + 1);   // compacted seeds: PMT
+    uint16_t *cidx = cp + STG;                       // compacted seeds: stage position
+    uint16_t *fci = cidx + STG;                      // fires: compacted index
+    __shared__ uint32_t sh[NW + 1];
+    __shared__ uint32_t s_ncs, s_ca, s_cb;
+
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const SliceDev &S = b.slices[si];
+    const uint32_t k = item - S.tile_base;
+    if (k >= S.n_tiles) return;
+    Plan *Pp = S.plan;
+    if (!slice_in_tail(b, Pp->state)) return;
+    const uint64_t n = S.n;
+    const int64_t t_min = Pp->t_min;
+    const uint64_t span = (uint64_t)(Pp->t_max - t_min);
+    const uint32_t W = b.prm.w_ns;
+    const uint32_t N = b.prm.min_fold;
+    const int32_t tau = b.prm.t_floor_ns;
+    const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+
+    const uint64_t a = (uint64_t)k * TILE;
+    const uint64_t e = (a + TILE < n) ? a + TILE : n;
+    // halo: twice the mean number of hits in w_ns + t_floor_ns, plus a margin
+    const uint64_t reach = (uint64_t)W + tau_u;
+    uint64_t halo = (2ull * n * reach) / (span + 1) + 64;
+    if (halo > (uint64_t)HMAX) halo = HMAX;
+    const uint64_t sl = a > halo ? a - halo : 0;
+    const uint64_t sh_end = (e + halo < n) ? e + halo : n;
+    const uint32_t len = (uint32_t)(sh_end - sl);
+    {
+        // stage both arrays with all loads of a thread in flight
+        constexpr int U = (STG + NT - 1) / NT;
+        uint32_t vt[U], vp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
+            if (x < len) {
+                vt[u] = S.o_t[sl + x];
+                vp[u] = S.o_pq[sl + x];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
+            if (x < len) {
+                st[x] = vt[u];
+                sp[x] = vp[u];
+            }
+        }
+    }
+    __syncthreads();
+    // the thr table and the floor numbering are read through the caches (a tile
+    // makes few lookups: its seeds times the seeds within w_ns of each)
+    const uint16_t *fl = S.floor16;
+    auto lim = [&](uint32_t p, uint32_t q) -> uint32_t { return lim_global(S, W, p, q); };
+    const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
+    // the stage spans the window of every seed of the tile when the halo reaches
+    // past w_ns + t_floor_ns on both sides (or the slice ends there)
+    const bool cover_l = sl == 0 || (uint64_t)st[0] + reach < (uint64_t)ta;
+    const bool cover_r = sh_end == n || (uint64_t)st[len - 1] > (uint64_t)te + reach;
+    uint32_t ca = 0, cb = 0;
+    uint64_t cbase = a;
+    if (cover_l && cover_r) {
+        cbase = sl;
+        // seed bits of the whole stage
+        for (uint32_t x0 = 0; x0 < len; x0 += NT) {
+            const uint32_t x = x0 + threadIdx.x;
+            bool seed = false;
+            if (x < len && MASK) {
+                seed = mask_bit(S, sl + x);
+            } else if (x < len) {
+                const uint32_t pq = sp[x];
+                seed = (pq & 0xFFFFu) >= b.prm.q_seed;
+                if (!seed && tau >= 0) {
+                    const uint32_t t = st[x], p = pq >> 16, f = fl[p];
+                    for (uint32_t m = x; m > 0;) {
+                        --m;
+                        if (t - st[m] > (uint32_t)tau) break;
+                        const uint32_t pm = sp[m] >> 16;
+                        if (pm != p && fl[pm] == f) { seed = true; break; }
+                    }
+                    for (uint32_t m = x + 1; !seed && m < len; ++m) {
+                        if (st[m] - t > (uint32_t)tau) break;
+                        const uint32_t pm = sp[m] >> 16;
+                        if (pm != p && fl[pm] == f) seed = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(seed);
+            if (lane == 0) sbits[x0 / 64 + w] = bal;
+        }
+        __syncthreads();
+        const uint32_t nwords = (len + 63) / 64;
+        if (w == 0) {
+            // word prefixes (one lane per word)
+            uint32_t tot = 0;
+            for (uint32_t w0 = 0; w0 < nwords; w0 += 64) {
+                const uint32_t wd = w0 + lane;
+                const uint32_t c = wd < nwords ? (uint32_t)__popcll(sbits[wd]) : 0u;
+                const uint32_t inc = wave_incl_scan(c);
+                if (wd < nwords) wpre[wd] = tot + inc - c;
+                tot += __shfl(inc, 63, 64);
+            }
+            if (lane == 0) {
+                wpre[nwords] = tot;
+                s_ncs = tot;
+            }
+        }
+        __syncthreads();
+        // seeds before the tile and before its end
+        if (threadIdx.x < 2) {
+            const uint32_t x = (uint32_t)((threadIdx.x == 0 ? a : e) - sl);
+            const uint32_t wd = x / 64, bit = x % 64;
+            const uint64_t word = wd < nwords ? sbits[wd] : 0ull;
+            const uint32_t v = wpre[wd] + (uint32_t)__popcll(bit ? word & (~0ull >> (64 - bit)) : 0ull);
+            if (threadIdx.x == 0) s_ca = v; else s_cb = v;
+        }
+        // compacted seeds of the stage (time order kept)
+        for (uint32_t x = threadIdx.x; x < len; x += NT) {
+            const uint64_t word = sbits[x / 64];
+            const uint32_t bit = x % 64;
+            if ((word >> bit) & 1ull) {
+                const uint32_t r = wpre[x / 64] + (uint32_t)__popcll(bit ? word & (~0ull >> (64 - bit)) : 0ull);
+                ct[r] = st[x];
+                cp[r] = (uint16_t)(sp[x] >> 16);
+                cidx[r] = (uint16_t)x;
+            }
+        }
+        __syncthreads();
+        ca = s_ca;
+        cb = s_cb;
+        const uint32_t ncs = s_ncs;
+        // causal fold of each seed of the tile over the compacted seeds within w_ns
+        for (uint32_t ci = ca + threadIdx.x; ci < cb; ci += NT) {
+            const uint32_t t = ct[ci], p = cp[ci];
+            uint32_t c = 1;
+            for (uint32_t j = ci; j > 0;) {
+                --j;
+                const uint32_t d = t - ct[j];
+                if (d > W) break;
+                c += d <= lim(p, cp[j]);
+            }
+            for (uint32_t j = ci + 1; j < ncs; ++j) {
+                const uint32_t d = ct[j] - t;
+                if (d > W) break;
+                c += d <= lim(p, cp[j]);
+            }
+            fold[ci - ca] = c;
+        }
+        if (S.seed_flags) {
+            for (uint64_t j = a + threadIdx.x; j < e; j += NT) {
+                const uint32_t x = (uint32_t)(j - sl);
+                S.seed_flags[S.o_idx[j]] = (uint8_t)((sbits[x / 64] >> (x % 64)) & 1ull);
+            }
+        }
+    } else if (!MASK) {
+        // a window beyond the staged halo: this pass leaves the tile empty and the
+        // slice is rerun with a seed mask
+        if (threadIdx.x == 0) atomicOr(&Pp->dense, 1u);
+    } else {
+        // seeds from the mask, folds of the tile from global memory
+        uint32_t acc = 0;
+        for (uint64_t j0 = a; j0 < e; j0 += NT) {
+            const uint64_t j = j0 + threadIdx.x;
+            const bool seed = j < e && mask_bit(S, j);
+            uint32_t tot;
+            const uint32_t ex = block_excl_scan<NT>(seed ? 1u : 0u, tot, sh);
+            if (seed) {
+                ct[acc + ex] = S.o_t[j];
+                cp[acc + ex] = (uint16_t)(S.o_pq[j] >> 16);
+                cidx[acc + ex] = (uint16_t)(j - a);
+            }
+            if (j < e && S.seed_flags) S.seed_flags[S.o_idx[j]] = seed ? 1 : 0;
+            acc += tot;
+        }
+        __syncthreads();
+        cb = acc;
+        for (uint32_t ci = threadIdx.x; ci < cb; ci += NT)
+            fold[ci] = fold_global(S, W, a + cidx[ci], ct[ci], cp[ci]);
+    }
+    __syncthreads();
+    // fires of the tile in order, to the tile's scratch slot
+    uint32_t nf = 0;
+    FireRec *slot = S.fsc + (uint64_t)k * TILE;
+    for (uint32_t c0 = ca; c0 < cb; c0 += NT) {
+        const uint32_t ci = c0 + threadIdx.x;
+        const bool f = ci < cb && fold[ci - ca] >= N;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NT>(f ? 1u : 0u, tot, sh);
+        if (f) {
+            fci[nf + ex] = (uint16_t)ci;
+            FireRec fr;
+            fr.t = ct[ci];
+            fr.hit = S.o_idx[cbase + cidx[ci]];
+            fr.fold = fold[ci - ca];
+            fr.pmt = cp[ci];
+            slot[nf + ex] = fr;
+        }
+        nf += tot;
+    }
+    __syncthreads();
+    if (w != 0) return;
+    // summary of this tile's fires (wave 0)
+    TileAgg A = agg_empty();
+    A.S = cb - ca;
+    A.F = nf;
+    uint32_t prev_t = 0, first_int = NO_START, last_int = NO_START, m_head = 0, m_tail = 0;
+    for (uint32_t r0 = 0; r0 < nf; r0 += 64) {
+        const uint32_t r = r0 + lane;
+        const bool v = r < nf;
+        uint32_t t = 0, fd = 0;
+        if (v) {
+            const uint32_t ci = fci[r];
+            t = ct[ci];
+            fd = fold[ci - ca];
+        }
+        const uint32_t tpl = __shfl_up(t, 1, 64);
+        const uint32_t tp = lane == 0 ? prev_t : tpl;
+        const bool is_int = v && r > 0 && (uint64_t)(t - tp) > twoH;
+        const uint64_t ib = __ballot(is_int);
+        if (r0 == 0) A.first_t = __shfl(t, 0, 64);
+        prev_t = __shfl(t, 63, 64);
+        if (ib) {
+            const int lo = __ffsll((unsigned long long)ib) - 1;
+            const int hi = 63 - __clzll((long long)ib);
+            if (first_int == NO_START) {
+                first_int = r0 + lo;
+                m_head = umax(m_head, wave_max_u32(v && lane < lo ? fd : 0u));
+            }
+            last_int = r0 + hi;
+            m_tail = wave_max_u32(v && lane >= hi ? fd : 0u);
+            A.ls_t = __shfl(t, hi, 64);
+        } else {
+            const uint32_t mx = wave_max_u32(v ? fd : 0u);
+            if (first_int == NO_START) m_head = umax(m_head, mx);
+            m_tail = umax(m_tail, mx);
+        }
+        A.E_int += (uint32_t)__popcll(ib);
+    }
+    if (nf) A.last_t = ct[fci[nf - 1]];
+    A.m_tail = m_tail;
+    A.m_head = first_int == NO_START ? m_tail : m_head;
+    A.ls_idx = last_int;
+    if (last_int == NO_START) A.ls_t = 0;
+    if (lane == 0) S.tstat[k].agg = A;
+}
+
+// Per slice (1024 threads): exclusive scan of the tile summaries, counts, the
+// end of the slice's last event, and the plan to host-mapped staging.
+__global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
+    constexpr int NTS = 1024, NWS = NTS / 64;
+    const uint32_t si = blockIdx.x;
+    const SliceDev &S = b.slices[si];
+    Plan *Pp = S.plan;
+    const uint32_t state = Pp->state;
+    if (!slice_in_tail(b, state)) {
+        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) b.x_plans[si] = *Pp;
+        return;
+    }
+    __shared__ TileAgg wsum[NWS];
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t nt = S.n_tiles;
+    const uint32_t per = (nt + NTS - 1) / NTS;
+    const uint32_t t0 = threadIdx.x * per;
+    const uint32_t t1 = (t0 + per < nt) ? t0 + per : nt;
+    TileAgg mine = agg_empty();
+    for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, S.tstat[t].agg, twoH);
+    // inclusive scan within the wave
+    TileAgg inc = mine;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const TileAgg o = agg_shfl_up(inc, d);
+        if (lane >= d) inc = agg_combine(o, inc, twoH);
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    TileAgg before = agg_empty();   // waves before this one
+    for (int i = 0; i < w; ++i) before = agg_combine(before, wsum[i], twoH);
+    const TileAgg ex_lane = agg_shfl_up(inc, 1);
+    TileAgg P = agg_combine(before, lane ? ex_lane : agg_empty(), twoH);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const TileAgg A = S.tstat[t].agg;
+        S.tstat[t].pre = P;
+        P = agg_combine(P, A, twoH);
+    }
+    if (threadIdx.x != NTS - 1) return;
+    const TileAgg I = P;   // the last thread ends with the whole slice
+    const uint32_t n_ev = I.F ? 1 + I.E_int : 0u;
+    const int64_t H = (int64_t)b.prm.half_event_ns;
+    const int64_t t_min = Pp->t_min;
+    if (I.F && !(Pp->dense && b.tail_state != ST_DENSE)) {
+        // the slice's last event ends at its last fire
+        const uint32_t le = n_ev - 1, s0 = open_start(I);
+        const int64_t tend = t_min + (int64_t)I.last_t + H;
+        S.events[le].t_end = tend;
+        S.events[le].n_fire = I.F - s0;
+        S.events[le].max_fold = I.m_tail;
+        if (S.x_events && le < S.x_event_cap) {
+            S.x_events[le].t_end = tend;
+            S.x_events[le].n_fire = I.F - s0;
+            S.x_events[le].max_fold = I.m_tail;
+        }
+    }
+    Pp->n_seeds = I.S;
+    Pp->n_fires = I.F;
+    Pp->n_events = n_ev;
+    if (b.x_plans) b.x_plans[si] = *Pp;
+}
+
+// One wave per tile with fires: fire records and event halves at their places.
+__global__ __launch_bounds__(64) void k_place(BatchDev b) {
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const SliceDev &S = b.slices[si];
+    const uint32_t k = item - S.tile_base;
+    if (k >= S.n_tiles) return;
+    const Plan *Pp = S.plan;
+    if (!slice_in_tail(b, Pp->state)) return;
+    if (Pp->dense && b.tail_state != ST_DENSE) return;   // this slice is rerun
+    const uint32_t nf = S.tstat[k].agg.F;
+    if (nf == 0) return;
+    const TileAgg P = S.tstat[k].pre;
+    const FireRec *slot = S.fsc + (uint64_t)k * TILE;
+    const int lane = lane_id();
+    const int64_t t_min = Pp->t_min;
+    const int64_t H = (int64_t)b.prm.half_event_ns;
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const uint32_t EP = P.F ? 1 + P.E_int : 0u;       // events begun before this tile
+    const uint32_t p_open = open_start(P);
+    uint32_t carry_starts = 0;                       // starts among earlier fires of the tile
+    int32_t carry_latest = -1;                       // local index of the latest start, -1: none
+    uint32_t carry_max = P.F ? P.m_tail : 0u;        // largest fold of the open event so far
+    uint32_t prev_t = P.F ? P.last_t : 0u;
+    for (uint32_t r0 = 0; r0 < nf; r0 += 64) {
+        const uint32_t r = r0 + lane;
+        const bool v = r < nf;
+        FireRec fr = {0, 0, 0, 0};
+        if (v) fr = slot[r];
+        const uint32_t t = fr.t, fd = fr.fold;
+        const uint32_t tpl = __shfl_up(t, 1, 64);
+        const uint32_t tp = lane == 0 ? prev_t : tpl;
+        const bool first_of_slice = r == 0 && P.F == 0;
+        const bool st = v && (first_of_slice || (uint64_t)(t - tp) > twoH);
+        const uint64_t sb = __ballot(st);
+        const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const uint32_t starts_incl = carry_starts + (uint32_t)__popcll(sb & upto);
+        const uint64_t sbu = sb & upto;
+        const int32_t latest = sbu ? (int32_t)(r0 + 63 - __clzll((long long)sbu)) : carry_latest;
+        // segmented inclusive max of the folds (segments begin at starts)
+        uint32_t mv = fd;
+        bool mf = st;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t ov = __shfl_up(mv, d, 64);
+            const bool of = __shfl_up(mf ? 1 : 0, d, 64) != 0;
+            if (lane >= d && !mf) {
+                mv = umax(mv, ov);
+                mf = of;
+            }
+        }
+        if (!mf) mv = umax(mv, carry_max);
+        const uint32_t ev = EP + starts_incl - 1;   // event of fire r
+        if (v) {
+            trig_fire out;
+            out.t_ns = t_min + (int64_t)t;
+            out.hit_index = fr.hit;
+            out.fold = fd;
+            out.pmt_id = (uint16_t)fr.pmt;
+            out.pad[0] = out.pad[1] = out.pad[2] = 0;
+            const uint32_t g = P.F + r;
+            S.fires[g] = out;
+            if (S.x_fires && g < S.x_fire_cap) S.x_fires[g] = out;
+            if (st) {
+                S.events[ev].t_trig = out.t_ns;
+                S.events[ev].t_begin = out.t_ns - H;
+                if (S.x_events && ev < S.x_event_cap) {
+                    S.x_events[ev].t_trig = out.t_ns;
+                    S.x_events[ev].t_begin = out.t_ns - H;
+                }
+                if (r == 0 && P.F) {
+                    // this fire ends the event left open by the preceding tiles
+                    const uint32_t pe = EP - 1;
+                    const int64_t tend = t_min + (int64_t)P.last_t + H;
+                    S.events[pe].t_end = tend;
+                    S.events[pe].n_fire = P.F - p_open;
+                    S.events[pe].max_fold = P.m_tail;
+                    if (S.x_events && pe < S.x_event_cap) {
+                        S.x_events[pe].t_end = tend;
+                        S.x_events[pe].n_fire = P.F - p_open;
+                        S.x_events[pe].max_fold = P.m_tail;
+                    }
+                }
+            }
+            // the next fire of the tile starts a new event: this one ends its event
+            if (r + 1 < nf && (uint64_t)(slot[r + 1].t - t) > twoH) {
+                const uint32_t sg = latest >= 0 ? P.F + (uint32_t)latest : p_open;
+                const int64_t tend = out.t_ns + H;
+                S.events[ev].t_end = tend;
+                S.events[ev].n_fire = P.F + r - sg + 1;
+                S.events[ev].max_fold = mv;
+                if (S.x_events && ev < S.x_event_cap) {
+                    S.x_events[ev].t_end = tend;
+                    S.x_events[ev].n_fire = P.F + r - sg + 1;
+                    S.x_events[ev].max_fold = mv;
+                }
+            }
+        }
+        carry_starts = __shfl(starts_incl, 63, 64);
+        carry_latest = __shfl(latest, 63, 64);
+        carry_max = __shfl(mv, 63, 64);
+        prev_t = __shfl(t, 63, 64);
+    }
+}
+
+// Seed mask of the slices being rerun (plan.dense), one tile per workgroup: the
+// tile and DSH ordered neighbours on each side are staged in LDS; a floor partner
+// search that runs past them reads global memory.  Also moves the slice to
+// ST_DENSE for the rerun.
+constexpr int DSH = 64;
+
+__global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const SliceDev &S = b.slices[si];
+    const uint32_t k = item - S.tile_base;
+    if (k >= S.n_tiles) return;
+    Plan *Pp = S.plan;
+    if (!Pp->dense || Pp->status != TRIG_OK) return;
+    if (k == 0 && threadIdx.x == 0) Pp->state = ST_DENSE;
+    __shared__ uint32_t lt[TILE + 2 * DSH], lpq[TILE + 2 * DSH];
+    const uint64_t n = S.n;
+    const uint64_t a = (uint64_t)k * TILE;
+    if (a >= n) return;
+    const uint64_t lo = a >= (uint64_t)DSH ? a - DSH : 0;
+    const uint64_t hi = (a + TILE + DSH < n) ? a + TILE + DSH : n;
+    stage_copy<NT, 5>(lt, S.o_t + lo, (uint32_t)(hi - lo));
+    stage_copy<NT, 5>(lpq, S.o_pq + lo, (uint32_t)(hi - lo));
+    __syncthreads();
+    auto T_at = [&](uint64_t m) -> uint32_t { return (m >= lo && m < hi) ? lt[m - lo] : S.o_t[m]; };
+    auto P_at = [&](uint64_t m) -> uint32_t { return ((m >= lo && m < hi) ? lpq[m - lo] : S.o_pq[m]) >> 16; };
+    const uint32_t Q = b.prm.q_seed;
+    const int32_t tau = b.prm.t_floor_ns;
+#pragma unroll
+    for (int e = 0; e < TILE / NT; ++e) {
+        const uint64_t j = a + (uint64_t)e * NT + threadIdx.x;
+        bool seed = false;
+        if (j < n) {
+            const uint32_t t = lt[j - lo], pq = lpq[j - lo], p = pq >> 16;
+            seed = (pq & 0xFFFFu) >= Q;
+            if (!seed && tau >= 0) {
+                const uint32_t f = S.floor16[p];
+                for (uint64_t m = j; m > 0;) {
+                    --m;
+                    if (t - T_at(m) > (uint32_t)tau) break;
+                    const uint32_t pm = P_at(m);
+                    if (pm != p && S.floor16[pm] == f) { seed = true; break; }
+                }
+                for (uint64_t m = j + 1; !seed && m < n; ++m) {
+                    if (T_at(m) - t > (uint32_t)tau) break;
+                    const uint32_t pm = P_at(m);
+                    if (pm != p && S.floor16[pm] == f) seed = true;
+                }
+            }
+        }
+        const uint64_t bal = __ballot(seed);
+        const uint64_t w0 = a + (uint64_t)e * NT + (threadIdx.x & ~63u);
+        if (lane_id() == 0 && w0 < n) S.dmask[w0 >> 6] = bal;
+    }
+}
+
+template <int HMAX>
+constexpr size_t tile_lds_bytes() {
+    constexpr size_t STG = TILE + 2 * HMAX;
+    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 2 + TILE * 2;
+}
+
+template <int HMAX, bool MASK>
+hipError_t launch_tile(const BatchDev &b, hipStream_t s) {
+    constexpr size_t shm = tile_lds_bytes<HMAX>();
+    if (shm > 64 * 1024) {
+        static const hipError_t attr = hipFuncSetAttribute(
+            (const void *)k_tile<HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (attr != hipSuccess) return attr;
+    }
+    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(b.total_tiles), dim3(NT), shm, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
+#define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+static hipError_t launch_trigger(const BatchDev &b, bool dense, hipStream_t s,
+                                 void (*mark)(void *, const char *, int), void *mark_ctx) {
+    TRIG_MARK("k_tile", 0);
+    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, s) : launch_tile<HALO_SMALL, false>(b, s);
+    if (e != hipSuccess) return e;
+    TRIG_MARK("k_tile", 1);
+    TRIG_MARK("k_tscan", 0);
+    hipLaunchKernelGGL(k_tscan, dim3(b.n_slices), dim3(1024), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_tscan", 1);
+    TRIG_MARK("k_place", 0);
+    hipLaunchKernelGGL(k_place, dim3(b.total_tiles), dim3(64), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_place", 1);
+    return hipSuccess;
+}
+
+hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &, uint32_t, hipStream_t s,
+                            void (*mark)(void *, const char *, int), void *mark_ctx) {
+    if (!b.total_tiles) return hipSuccess;
+    return launch_trigger(b, false, s, mark, mark_ctx);
+}
+
+hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &, uint32_t, hipStream_t s,
+                             void (*mark)(void *, const char *, int), void *mark_ctx) {
+    if (!b.total_tiles) return hipSuccess;
+    TRIG_MARK("k_dseed", 0);
+    hipLaunchKernelGGL(k_dseed, dim3(b.total_tiles), dim3(NT), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_dseed", 1);
+    return launch_trigger(b, true, s, mark, mark_ctx);
+}

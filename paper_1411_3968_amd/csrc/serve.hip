@@ -12,11 +12,15 @@
 // parameters) as one device round through the batch-native pipeline.  Slices
 // that arrive while rounds are running join the next round of whichever slot
 // frees first, so their work overlaps on the device with the rounds in flight.
-// Device memory of a round comes from the stream-ordered pool and returns to it
-// when the round's results are on the host, which admits waiting slices.
+// Device memory: the loop keeps chunks of device memory for as long as it runs
+// (taken from HIP when needed, within the context's budget) and carves each
+// admitted slice a region of them (its input copy and its pipeline workspace);
+// the region returns to the free list when the slice's results are on the host,
+// which admits waiting slices.  No HIP allocation or free happens per slice.
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <thread>
 #include <unordered_map>
 
@@ -31,8 +35,9 @@ struct Ticket {
     uint64_t id = 0;
     trig_slice_desc desc = {};   // device pointers once admitted
     trig_params params = {};
-    void *dev_input = nullptr;   // owned device copy of host inputs
-    uint64_t footprint = 0;
+    char *region = nullptr;      // arena region: input copy (host inputs), then workspace
+    uint64_t footprint = 0;      // bytes of the region
+    uint64_t in_bytes = 0;       // input copy at the start of the region
     bool done = false;
     int status = TRIG_PENDING;
     uint64_t n_hits = 0, n_seeds = 0, tag = 0;
@@ -42,6 +47,89 @@ struct Ticket {
 };
 
 bool same_params(const trig_params &a, const trig_params &b) { return std::memcmp(&a, &b, sizeof a) == 0; }
+
+// First-fit allocator over device chunks that live until shutdown.  Chunk bytes
+// are accounted in the context budget when a chunk is taken.
+struct Arena {
+    static constexpr size_t ALIGN = 256;
+    static constexpr size_t GROW_MIN = 1ull << 30;
+    struct Chunk {
+        char *base;
+        size_t size;
+        std::map<size_t, size_t> free;   // offset -> length
+    };
+    std::vector<Chunk> chunks;
+    size_t total = 0;
+
+    static size_t round_up(size_t x) { return (x + ALIGN - 1) & ~(ALIGN - 1); }
+
+    char *take(size_t bytes) {
+        for (Chunk &ch : chunks)
+            for (auto it = ch.free.begin(); it != ch.free.end(); ++it)
+                if (it->second >= bytes) {
+                    const size_t off = it->first, len = it->second;
+                    ch.free.erase(it);
+                    if (len > bytes) ch.free.emplace(off + bytes, len - bytes);
+                    return ch.base + off;
+                }
+        return nullptr;
+    }
+
+    // A region of `bytes`, growing by a new chunk if no free range fits;
+    // null when the budget does not allow it now.
+    char *alloc(trig_ctx *c, size_t bytes) {
+        bytes = round_up(std::max<size_t>(bytes, 1));
+        if (char *p = take(bytes)) return p;
+        uint64_t room;
+        {
+            std::lock_guard<std::mutex> g(c->mem_mu);
+            room = c->budget > c->bytes_in_use ? c->budget - c->bytes_in_use : 0;
+        }
+        size_t want = std::max(bytes, GROW_MIN);
+        if (want > room) want = room & ~(ALIGN - 1);
+        if (want < bytes || ctx_reserve(c, want) != TRIG_OK) return nullptr;
+        char *p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx_release(c, want);
+            return nullptr;
+        }
+        chunks.push_back(Chunk{p, want, {}});
+        if (want > bytes) chunks.back().free.emplace(bytes, want - bytes);
+        total += want;
+        return p;
+    }
+
+    void release(char *p, size_t bytes) {
+        bytes = round_up(std::max<size_t>(bytes, 1));
+        for (Chunk &ch : chunks) {
+            if (p < ch.base || p >= ch.base + ch.size) continue;
+            auto it = ch.free.emplace((size_t)(p - ch.base), bytes).first;
+            auto nx = std::next(it);
+            if (nx != ch.free.end() && it->first + it->second == nx->first) {
+                it->second += nx->second;
+                ch.free.erase(nx);
+            }
+            if (it != ch.free.begin()) {
+                auto pv = std::prev(it);
+                if (pv->first + pv->second == it->first) {
+                    pv->second += it->second;
+                    ch.free.erase(it);
+                }
+            }
+            return;
+        }
+    }
+
+    void release_all(trig_ctx *c) {
+        for (Chunk &ch : chunks) {
+            hipFree(ch.base);
+            ctx_release(c, ch.size);
+        }
+        chunks.clear();
+        total = 0;
+    }
+};
 
 }  // namespace
 
@@ -58,7 +146,8 @@ struct ServeState {
     bool stop = false;
     bool paused = false;
     uint64_t next_id = 1;
-    uint64_t reserved = 0;       // bytes of admitted, unfinished tickets
+    Arena arena;                 // guarded by mu
+    std::vector<std::unique_ptr<Job>> jobs;   // one per slot, descriptors sized for a full round
     trig_stream_stats st = {};
 };
 
@@ -66,7 +155,11 @@ static void run_round(ServeState *S, Job &job, hipStream_t stream, std::vector<T
     trig_ctx *c = S->c;
     const uint32_t n = (uint32_t)round.size();
     std::vector<trig_slice_desc> descs(n);
-    for (uint32_t i = 0; i < n; ++i) descs[i] = round[i]->desc;
+    job.ext_ws.resize(n);
+    for (uint32_t i = 0; i < n; ++i) {
+        descs[i] = round[i]->desc;
+        job.ext_ws[i] = round[i]->region + round[i]->in_bytes;
+    }
     int rc = job.prepare(c, n, descs.data(), &round[0]->params, nullptr, nullptr, nullptr, stream);
     if (rc == TRIG_OK) rc = job.launch(c, false);
     if (rc == TRIG_OK) {
@@ -74,8 +167,10 @@ static void run_round(ServeState *S, Job &job, hipStream_t stream, std::vector<T
         if (e != hipSuccess) rc = hip_fail(c, e, "serving round");
     }
     if (rc == TRIG_OK) rc = job.generic_pass(c, false);
+    if (rc == TRIG_OK) rc = job.dense_pass(c, false);
     if (rc == TRIG_OK) {
         const trigdev::Plan *hp = (const trigdev::Plan *)job.h_plans.ptr;
+        bool copies = false;
         for (uint32_t i = 0; i < n; ++i) {
             Ticket *t = round[i];
             trig_result r = {};
@@ -92,26 +187,22 @@ static void run_round(ServeState *S, Job &job, hipStream_t stream, std::vector<T
             t->n_seeds = r.n_seeds;
             t->tag = r.tag;
             t->path = r.path;
+            copies |= P.n_fires > job.slices[i].x_fcap || P.n_events > job.slices[i].x_ecap;
         }
-        hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) rc = hip_fail(c, e, "serving results");
+        if (copies) {   // lists beyond the staging capacity came by D2H copies
+            hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) rc = hip_fail(c, e, "serving results");
+        }
     }
     if (rc != TRIG_OK)
         for (Ticket *t : round) { t->status = rc; t->fires.clear(); t->events.clear(); }
-    job.ws.release_async(stream);
-    job.dmeta.release_async(stream);
-    job.gscratch.release_async(stream);
-    for (Ticket *t : round)
-        if (t->dev_input) { hipFreeAsync(t->dev_input, stream); t->dev_input = nullptr; }
-    hipStreamSynchronize(stream);
-    if (job.async_extra) { ctx_release(c, job.async_extra); job.async_extra = 0; }
+    job.ext_ws.clear();
 }
 
 static void slot_main(ServeState *S, int slot) {
     hipSetDevice(S->c->device);
     hipStream_t stream = S->streams[slot];
-    Job job;
-    job.async_mem = true;
+    Job &job = *S->jobs[slot];
     for (;;) {
         std::vector<Ticket *> round;
         {
@@ -130,15 +221,14 @@ static void slot_main(ServeState *S, int slot) {
             std::lock_guard<std::mutex> lk(S->mu);
             for (Ticket *t : round) {
                 t->done = true;
-                S->reserved -= t->footprint;
-                ctx_release(S->c, t->footprint);
+                S->arena.release(t->region, t->footprint);
+                t->region = nullptr;
                 S->st.completed += 1;
             }
         }
         S->cv_done.notify_all();
     }
-    job.h_slices.release();
-    job.h_plans.release();
+    job.release(S->c);
 }
 
 static ServeState *serve_get(trig_ctx *c) {
@@ -147,14 +237,15 @@ static ServeState *serve_get(trig_ctx *c) {
     ServeState *S = new ServeState();
     S->c = c;
     hipSetDevice(c->device);
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, c->device) == hipSuccess) {
-        uint64_t keep = UINT64_MAX;
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
     hipStreamCreateWithFlags(&S->copy_stream, hipStreamNonBlocking);
     S->streams.resize(SLOTS);
     for (int i = 0; i < SLOTS; ++i) hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking);
+    // descriptor buffers of every slot are taken before any slice is admitted, so
+    // a budget filled by admitted slices never starves a round of them
+    for (int i = 0; i < SLOTS; ++i) {
+        S->jobs.emplace_back(new Job());
+        (void)S->jobs.back()->dmeta.ensure(c, job_meta_bytes(MAX_PER_ROUND), S->streams[i]);
+    }
     for (int i = 0; i < SLOTS; ++i) S->threads.emplace_back(slot_main, S, i);
     c->serve = S;
     return S;
@@ -170,8 +261,8 @@ void serve_shutdown(trig_ctx *c) {
         for (Ticket *t : S->queue) {
             t->done = true;
             t->status = TRIG_ECANCELED;
-            S->reserved -= t->footprint;
-            ctx_release(c, t->footprint);
+            S->arena.release(t->region, t->footprint);
+            t->region = nullptr;
         }
         S->queue.clear();
     }
@@ -179,10 +270,8 @@ void serve_shutdown(trig_ctx *c) {
     for (auto &th : S->threads) th.join();
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (auto &kv : S->tickets) {
-        if (kv.second->dev_input) hipFree(kv.second->dev_input);
-        delete kv.second;
-    }
+    for (auto &kv : S->tickets) delete kv.second;
+    S->arena.release_all(c);
     for (auto s : S->streams) hipStreamDestroy(s);
     hipStreamDestroy(S->copy_stream);
     delete S;
@@ -218,43 +307,47 @@ int trig_stream_submit(trig_ctx *c, const trig_slice_desc *d, const trig_params 
     const bool host = d->mem == TRIG_MEM_HOST && n > 0;
     const uint64_t in_bytes = host ? ((n * 2 + 255) & ~255ull) * 2 + ((n * 8 + 255) & ~255ull) : 0;
     const uint64_t foot = slice_footprint(n, false) + in_bytes;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        if (S->stop) return TRIG_ECANCELED;
-        uint64_t other;
-        {
-            std::lock_guard<std::mutex> g(c->mem_mu);
-            other = c->bytes_in_use - S->reserved;
-        }
-        if (foot + other > c->budget) {
-            ctx_set_error(c, "slice of %llu hits can never fit the device budget", (unsigned long long)n);
-            return TRIG_ENOMEM;
-        }
-        if (ctx_reserve(c, foot) != TRIG_OK) {
-            S->st.rejected_again += 1;
-            return TRIG_EAGAIN;
-        }
-        S->reserved += foot;
-    }
     Ticket *t = new Ticket();
     t->params = *prm;
     t->desc = *d;
     t->footprint = foot;
+    t->in_bytes = in_bytes;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            delete t;
+            return TRIG_ECANCELED;
+        }
+        uint64_t other;   // device bytes held outside the arena (geometry, synchronous jobs)
+        {
+            std::lock_guard<std::mutex> g(c->mem_mu);
+            other = c->bytes_in_use - S->arena.total;
+        }
+        if (foot + other > c->budget) {
+            ctx_set_error(c, "slice of %llu hits can never fit the device budget", (unsigned long long)n);
+            delete t;
+            return TRIG_ENOMEM;
+        }
+        hipSetDevice(c->device);
+        t->region = S->arena.alloc(c, foot);
+        if (!t->region) {
+            S->st.rejected_again += 1;
+            delete t;
+            return TRIG_EAGAIN;
+        }
+    }
     if (host) {
         std::lock_guard<std::mutex> g(S->copy_mu);
         hipSetDevice(c->device);
-        hipError_t e = hipMallocAsync(&t->dev_input, in_bytes, S->copy_stream);
-        char *b = (char *)t->dev_input;
+        char *b = t->region;
         const uint64_t o_t = (n * 2 + 255) & ~255ull, o_q = o_t + ((n * 8 + 255) & ~255ull);
-        if (e == hipSuccess) e = hipMemcpyAsync(b, d->pmt_id, n * 2, hipMemcpyHostToDevice, S->copy_stream);
+        hipError_t e = hipMemcpyAsync(b, d->pmt_id, n * 2, hipMemcpyHostToDevice, S->copy_stream);
         if (e == hipSuccess) e = hipMemcpyAsync(b + o_t, d->t_ns, n * 8, hipMemcpyHostToDevice, S->copy_stream);
         if (e == hipSuccess) e = hipMemcpyAsync(b + o_q, d->charge, n * 2, hipMemcpyHostToDevice, S->copy_stream);
         if (e == hipSuccess) e = hipStreamSynchronize(S->copy_stream);
         if (e != hipSuccess) {
-            if (t->dev_input) hipFree(t->dev_input);
             std::lock_guard<std::mutex> lk(S->mu);
-            S->reserved -= foot;
-            ctx_release(c, foot);
+            S->arena.release(t->region, t->footprint);
             delete t;
             return hip_fail(c, e, "copying slice inputs to the device");
         }

@@ -1,25 +1,30 @@
 // Device-side data structures and helpers of the trigger pipeline (gfx950).
 //
-// Pipeline of one batch of slices (every kernel covers all slices of the batch):
-//   k_reset      clear work-queue counters
-//   k_ingest     per 4096-hit chunk: min/max time, max PMT, run starts
-//   k_plan       per slice: validation, t_min, run count, segment width, path
-//   k_seg_prefix one block: work-list bases of the ordering stage
+// Pipeline of one batch of slices (every kernel covers all slices of the batch;
+// work counters are cleared by the host before the first kernel):
+//   k_ingest     per 1024-hit chunk: min/max time, max PMT, run starts
+//   k_plan       per slice: validation, t_min, run count, segment width, path and
+//                ordering-kernel kind; the last block to finish builds the
+//                segment work lists of both ordering kernels
 //   k_bounds     per chunk: run start and segment-boundary positions of every run
-//   k_segsort    persistent: gather one time segment from all runs into LDS,
-//                radix-sort it by (t, pmt) with input-position tie-break, write the
-//                ordered structure-of-arrays
-//   k_seed       per 4096-hit ordered tile: L1 seed bits (charge or floor coincidence)
-//   k_seed_scan  per slice: tile offsets of the seed list
-//   k_seed_emit  per tile: compact seed list (t, pmt|q, input index)
-//   k_count_prefix one block: work-list bases of the counting stage
-//   k_count      persistent: causal fold of every seed, fire counts per seed tile
-//   k_fire_scan  per slice: fire offsets
-//   k_fire_emit  per seed tile: ordered fire records
-//   k_events     per slice: merged event windows
+//   k_segsort_w  persistent, one wave per time segment of at most WAVE_CAP hits:
+//                gather the segment's stretch of every run into LDS, order it by
+//                (t, pmt, input index), write the ordered structure-of-arrays
+//   k_segsort    the same with one block per segment, for wider segments
+//   k_tile       per ordered tile of TILE hits: L1 seeds, causal folds and fires of
+//                the tile (fire records to a per-tile scratch slot), and a summary
+//                of its fires and their event structure
+//   k_tscan      per slice: scan of the tile summaries (each tile's place in the
+//                fire and event lists), counts, the last event's end, the plan
+//                to host-mapped staging
+//   k_place      per tile with fires: fire records and event halves at their
+//                places, also to host-mapped staging
+// A slice with a tile whose time window reaches past its staged halo (a burst far
+// denser than the slice's mean) reruns the trigger stage after k_dseed has
+// written the seed bit of every ordered hit.
 // A slice whose input is not a concatenation of a modest number of time-ordered
 // runs (or whose time density overflows a segment) is re-ordered by a general
-// LSD radix sort (k_g*) and then runs the same tail (k_seed ... k_events).
+// LSD radix sort (k_g*) and then runs k_trig.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,15 +35,11 @@
 namespace trigdev {
 
 constexpr int CHUNK = 1024;       // hits per ingest / bounds item
-constexpr int TILE = 1024;        // ordered hits per seed tile
-constexpr int SHALO = 64;         // ordered neighbours staged on each side of a seed tile
-constexpr int CT1 = 256;          // seeds per counting tile (table in LDS)
-constexpr int CT8 = 2048;         // seeds per counting tile (row-grouped table in L2)
-constexpr int CHALO = 256;        // seeds staged on each side of a counting tile
+constexpr int TILE = 1024;        // ordered hits per trigger tile
+constexpr int HALO_SMALL = 256;   // ordered hits staged on each side of a tile (first pass)
+constexpr int HALO_BIG = 1024;    // the same in the dense-window rerun
 constexpr int GTILE = 4096;       // elements per block of the general radix sort
 constexpr int LDS_THR_MAX_PMT = 128;  // thr table kept in LDS up to this many PMTs
-constexpr int SEED_LDS_FLOORS = 8192; // dense floor ids kept in LDS up to this many PMTs
-constexpr int ROWGROUPS = 8;      // counting rows split over the 8 XCDs for large tables
 constexpr int WAVE_CAP = 512;     // hits per segment of the wave-per-segment ordering
 constexpr int WAVE_RUNS = 256;    // most runs a wave-per-segment slice may have
 
@@ -47,20 +48,48 @@ enum State : uint32_t {
     ST_FAST = 1,          // run-merge ordering
     ST_NEED_GENERIC = 2,  // needs the general radix ordering
     ST_GENERIC_DONE = 3,  // ordered by the general path
+    ST_DENSE = 4,         // trigger stage rerun with a precomputed seed mask
 };
 
 // Work-queue / counter slots in BatchDev::counters.
 enum Counter : int {
     Q_SEG = 0,           // dequeue counter of k_segsort
     Q_SEG_TOTAL = 1,     // number of segment items
-    Q_COUNT_TOTAL = 2,   // number of counting items
     C_PLAN_DONE = 3,     // slices planned so far (the last block builds the segment work list)
-    C_SCAN_DONE = 4,     // slices whose seed list is scanned (the last block builds the count work list)
     Q_SEG_TOTAL_B = 5,   // number of segment items of the block-per-segment kernel
     N_COUNTERS = 16,
 };
 
-__host__ __device__ constexpr uint32_t count_tile(uint32_t groups) { return groups > 1 ? CT8 : CT1; }
+constexpr uint32_t NO_START = 0xFFFFFFFFu;
+
+// Summary of a run of consecutive tiles of one slice: its fires (in
+// ordered-hit order) and the event structure among them.  A fire "starts" an
+// event when it comes more than 2H after the previous fire; the first fire of
+// the run is not counted as a start here (that depends on what precedes it).
+struct TileAgg {
+    uint32_t F;          // fires
+    uint32_t S;          // seeds
+    uint32_t E_int;      // starts among the fires after the first
+    uint32_t first_t, last_t;   // t - t_min of the first and the last fire
+    uint32_t m_head;     // largest fold before the first start (all fires if none)
+    uint32_t m_tail;     // largest fold from the last start on (all fires if none)
+    uint32_t ls_idx;     // index within the run of the last start, NO_START if none
+    uint32_t ls_t;       // its t - t_min
+};
+
+// Per tile: its own summary, and the summary of all tiles of the slice before it.
+struct TileStat {
+    TileAgg agg;
+    TileAgg pre;
+};
+
+// One fire in a tile's scratch slot, before it is placed.
+struct FireRec {
+    uint32_t t;          // t - t_min
+    uint32_t hit;        // input index
+    uint32_t fold;
+    uint32_t pmt;
+};
 
 struct ChunkPart {
     int64_t t_min, t_max;
@@ -81,12 +110,11 @@ struct Plan {
     uint32_t n_fires;
     uint32_t n_events;
     uint32_t seg_item_base;
-    uint32_t n_ctiles;
-    uint32_t count_item_base;
-    uint32_t groups;         // counting row groups (1 or ROWGROUPS)
     uint32_t overflow;       // a segment exceeded the LDS capacity
     uint32_t seg_item_base_b;  // base in the block-kernel segment work list
     uint32_t seg_kind;       // 0: wave-per-segment ordering, 1: block-per-segment ordering
+    uint32_t dense;          // a trigger tile's window outran its staged halo: rerun with a seed mask
+    uint32_t generic;        // ordered by the general path
     uint32_t pad;
 };
 
@@ -101,17 +129,15 @@ struct SliceDev {
     const uint16_t *thr16;   // min(thr, 65535)
     uint32_t n_pmt, pbits;
     uint32_t chunk_base, n_chunks;
-    uint32_t tile_base, n_tiles;
+    uint32_t tile_base, n_tiles;   // k_trig tiles: max(1, chunks) (an empty slice has one)
     uint32_t seg_target, seg_cap;
     uint64_t pos_cap;
     ChunkPart *part;
     uint32_t *pos;           // run-major: pos[r * (n_seg + 1) + j]
     uint32_t *o_t, *o_pq, *o_idx;   // ordered: t - t_min, pmt << 16 | q, input index
-    uint64_t *seed_mask;     // one bit per ordered hit
-    uint32_t *tile_seeds;    // per tile: count, then offset
-    uint32_t *s_t, *s_pq, *s_idx, *s_fold;   // seed list
-    uint32_t *ctile_fires;   // per seed tile: count, then offset
-    uint32_t *fire_ev, *ev_first, *ev_max;
+    TileStat *tstat;         // per trigger tile
+    FireRec *fsc;            // per trigger tile, TILE fire slots
+    uint64_t *dmask;         // seed bits by ordered position (dense-window rerun only)
     trig_fire *fires;
     trig_event *events;
     uint8_t *seed_flags;     // optional, by input index
@@ -263,8 +289,13 @@ struct TrigLaunchCfg {
 hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, int wave_wgs_per_cu,
                              const TrigLaunchCfg &cfg, hipStream_t s, void (*mark)(void *, const char *, int),
                              void *mark_ctx);
-hipError_t trig_launch_tail(const trigdev::BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s,
+// max_pmt: the largest PMT count of the batch's geometries (sizes the LDS table).
+hipError_t trig_launch_tail(const trigdev::BatchDev &b, const TrigLaunchCfg &cfg, uint32_t max_pmt, hipStream_t s,
                             void (*mark)(void *, const char *, int), void *mark_ctx);
+// Dense-window rerun of the slices whose plan has `dense` set: seed mask, then
+// the trigger stage reading it (b.tail_state must be ST_DENSE).
+hipError_t trig_launch_dense(const trigdev::BatchDev &b, const TrigLaunchCfg &cfg, uint32_t max_pmt, hipStream_t s,
+                             void (*mark)(void *, const char *, int), void *mark_ctx);
 // General path for one slice: device-wide stable LSD radix sort over key_bits
 // bits; scratch holds trig_generic_scratch_bytes(n) bytes.
 hipError_t trig_launch_generic_slice(const trigdev::SliceDev &S, const trigdev::Plan &P, uint32_t key_bits,

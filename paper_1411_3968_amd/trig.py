@@ -312,9 +312,14 @@ def trig_stream_submit(ctx, geom_id: int, pmt, t, q, params: dict | None = None,
 
 
 def trig_stream_poll(ctx, ticket: int, timeout_us: int = -1, fire_cap: int = 1 << 16, event_cap: int = 1 << 16,
-                     n_hits: int = 0, seed_flags: bool = False):
-    """Returns ``(status, result dict or None)``."""
-    rb = ResultBuffers(fire_cap, event_cap, n_hits, seed_flags)
+                     n_hits: int = 0, seed_flags: bool = False, buffers: ResultBuffers | None = None):
+    """Returns ``(status, result dict or None)``.  ``buffers``: reuse these host
+    buffers (their capacities apply) instead of allocating new ones."""
+    if buffers is not None:
+        rb = buffers
+        rb.reset()
+    else:
+        rb = ResultBuffers(fire_cap, event_cap, n_hits, seed_flags)
     rc = _LIB.trig_stream_poll(ctx, int(ticket), C.byref(rb.rec), int(timeout_us))
     if rc == TRIG_PENDING:
         return rc, None
@@ -394,6 +399,53 @@ class SliceRunner:
                    path=int(r.path), fires=self.buf.fires[:r.n_fires], events=self.buf.events[:r.n_events])
         if self.buf.flags is not None:
             out["seed_flags"] = self.buf.flags[:r.n_hits]
+        return out
+
+
+class BatchRunner:
+    """Repeated ``trig_batch`` over one list of slices with marshalling done once.
+
+    ``slices``: list of ``(geom_id, pmt, t, q)``.  ``caps``: per slice
+    ``(fire_cap, event_cap)`` (default: an eighth of the hits, at least 4096).
+    Each call returns one dict per slice whose arrays are views into buffers
+    that the next call overwrites; a slice whose lists exceed its capacity
+    reports TRIG_EOVERFLOW in its ``status``.
+    """
+
+    def __init__(self, ctx, slices, params=None, *, stream=None, caps=None):
+        self.ctx = ctx
+        n = len(slices)
+        self.n = n
+        self.descs = (SliceDesc * max(n, 1))()
+        self._keep = []
+        ns = []
+        for i, (gid, pmt, t, q) in enumerate(slices):
+            d, k = slice_desc(gid, pmt, t, q, tag=i)
+            self.descs[i] = d
+            self._keep.append(k)
+            ns.append(int(d.n_hits))
+        caps = caps or [_default_caps(x) for x in ns]
+        self.bufs = [ResultBuffers(caps[i][0], caps[i][1], ns[i], False) for i in range(n)]
+        self.recs = (Result * max(n, 1))()
+        self.prm = params_struct(params)
+        if stream is None and n and _is_torch(slices[0][2]):
+            import torch
+            stream = torch.cuda.current_stream()
+        self.sp = _stream_ptr(stream)
+
+    def __call__(self) -> list:
+        for i in range(self.n):
+            self.recs[i] = self.bufs[i].rec
+        rc = _LIB.trig_batch(self.ctx, self.n, self.descs, C.byref(self.prm), self.recs, self.sp)
+        if rc not in (TRIG_OK, TRIG_ERANGE, TRIG_EINVAL, TRIG_EOVERFLOW):
+            raise TrigError(rc, _err(self.ctx))
+        out = []
+        for i in range(self.n):
+            r, b = self.recs[i], self.bufs[i]
+            out.append(dict(status=int(r.status), n_hits=int(r.n_hits), n_seeds=int(r.n_seeds), path=int(r.path),
+                            n_fires=int(r.n_fires), n_events=int(r.n_events),
+                            fires=b.fires[:r.n_fires] if r.status == TRIG_OK else b.fires[:0],
+                            events=b.events[:r.n_events] if r.status == TRIG_OK else b.events[:0]))
         return out
 
 

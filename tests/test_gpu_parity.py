@@ -203,7 +203,36 @@ def test_dense_segment_takes_general_path(tr, orc):
     got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
     ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
     check(got, ref)
-    assert got["path"] == 1
+    # general ordering, and the burst outruns the trigger stage's staged halo too
+    assert got["path"] == 3
+
+
+def test_dense_window_rerun_on_run_merge(tr, orc):
+    """A short burst on one floor, dense enough that trigger windows reach past the
+    halo sized from the slice's mean density but small enough for the run-merge
+    ordering: the trigger stage is rerun with a seed mask; results unchanged."""
+    from gen import configs as C
+    w = C.nemo(seed=11, length_ns=20_000_000, n_tracks=2)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    rng = np.random.default_rng(5)
+    k = 240
+    floor0 = np.flatnonzero(g.floor_id == g.floor_id[0])[:4].astype(np.uint16)
+    # the burst straddles the boundary of trigger tiles 9 and 10 (ordered position 10240)
+    t0 = np.sort(s.t)[10240 - k // 2] + 1
+    bt = t0 + np.sort(rng.integers(0, 400, size=k))
+    bp = rng.choice(floor0, size=k).astype(np.uint16)
+    bq = rng.integers(50, 400, size=k).astype(np.uint16)
+    # appended as one more time-ordered run per PMT
+    order = np.lexsort((bt, bp))
+    pmt = np.concatenate([s.pmt, bp[order]])
+    t = np.concatenate([s.t, bt[order]])
+    q = np.concatenate([s.q, bq[order]])
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
+    ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["path"] == 2 and got["n_fires"] > 0
 
 
 def test_errors(T, tr):
