@@ -137,25 +137,30 @@ def bench_serving(T, torch, dev, a):
     cap = max(max(r["n_fires"] for r in alone), max(r["n_events"] for r in alone), 1)
     bufs = [T.ResultBuffers(cap, cap, 0, False) for _ in range(max(a.serve_inflight, 64))]
 
+    def same_as_alone(r, ref):
+        """Counts always; the lists whole up to 2^16 records, else every 61st
+        record plus both ends (a burst slice's 2M fires would otherwise cost the
+        single submitting thread more than the GPU spends on a dozen slices)."""
+        if (r["n_fires"], r["n_events"], r["n_seeds"]) != (ref["n_fires"], ref["n_events"], ref["n_seeds"]):
+            return False
+        for key in ("fires", "events"):
+            a, b2 = r[key], ref[key]
+            if len(a) <= 1 << 16:
+                if not np.array_equal(a, b2):
+                    return False
+            elif not (np.array_equal(a[::61], b2[::61]) and np.array_equal(a[:256], b2[:256])
+                      and np.array_equal(a[-256:], b2[-256:])):
+                return False
+        return True
+
     def run(order, arrivals, inflight_max):
         """Submit pool[order[i]] at arrivals[i] (None: as soon as fewer than
         inflight_max are outstanding); returns (latencies s, wall s, mismatches)."""
         lat, bad = [], 0
-        outstanding = []      # [ticket, arrival, pool index, buffer]
+        outstanding = {}      # ticket -> (arrival, pool index, buffer)
         free = list(range(len(bufs)))
         i, n_tot = 0, len(order)
         t_start = time.perf_counter()
-
-        def finish(j, rc, r):
-            nonlocal bad
-            tk, arr, k, bi = outstanding.pop(j)
-            lat.append(time.perf_counter() - t_start - arr)
-            free.append(bi)
-            if rc != T.TRIG_OK or r["n_fires"] != alone[k]["n_fires"] or \
-                    not np.array_equal(r["fires"], alone[k]["fires"]) or \
-                    not np.array_equal(r["events"], alone[k]["events"]):
-                bad += 1
-
         while i < n_tot or outstanding:
             now = time.perf_counter() - t_start
             while i < n_tot and len(outstanding) < inflight_max and \
@@ -166,29 +171,23 @@ def bench_serving(T, torch, dev, a):
                     break
                 if rc != T.TRIG_OK:
                     raise T.TrigError(rc, T.trig_last_error(tr.ctx))
-                outstanding.append((tk, now if arrivals is None else float(arrivals[i]), k, free.pop()))
+                outstanding[tk] = (now if arrivals is None else float(arrivals[i]), k, free.pop())
                 i += 1
-            done_any = False
-            j = 0
-            while j < len(outstanding):
-                rc, r = T.trig_stream_poll(tr.ctx, outstanding[j][0], timeout_us=0, buffers=bufs[outstanding[j][3]])
-                if rc == T.TRIG_PENDING:
-                    j += 1
-                    continue
-                finish(j, rc, r)
-                done_any = True
-            if done_any:
+            # wait for whichever ticket finishes first (until the next arrival is due)
+            wait_us = -1 if (arrivals is None or i >= n_tot) else \
+                max(0, int((arrivals[i] - (time.perf_counter() - t_start)) * 1e6))
+            if not outstanding:
+                time.sleep(max(0.0, wait_us * 1e-6) if wait_us >= 0 else 0.0005)
                 continue
-            wait = 0.0002
-            if arrivals is not None and i < n_tot:
-                wait = min(wait, max(0.0, arrivals[i] - (time.perf_counter() - t_start)))
-            if outstanding:
-                rc, r = T.trig_stream_poll(tr.ctx, outstanding[0][0], timeout_us=int(wait * 1e6),
-                                           buffers=bufs[outstanding[0][3]])
-                if rc != T.TRIG_PENDING:
-                    finish(0, rc, r)
-            else:
-                time.sleep(wait)
+            rc, tk = T.trig_stream_next_done(tr.ctx, wait_us)
+            if rc != T.TRIG_OK:
+                continue
+            arr, k, bi = outstanding.pop(tk)
+            rc, r = T.trig_stream_poll(tr.ctx, tk, timeout_us=0, buffers=bufs[bi], copy=False)
+            lat.append(time.perf_counter() - t_start - arr)
+            if rc != T.TRIG_OK or not same_as_alone(r, alone[k]):
+                bad += 1
+            free.append(bi)
         return lat, time.perf_counter() - t_start, bad
 
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 99])))

@@ -180,6 +180,16 @@ int trig_stream_submit(trig_ctx *ctx, const trig_slice_desc *slice, const trig_p
  * used).  A ticket is released by the poll that returns its result. */
 int trig_stream_poll(trig_ctx *ctx, uint64_t ticket, trig_result *result, int32_t timeout_us);
 
+/* Serving: the next ticket whose slice finished (or was cancelled), in order of
+ * completion, each reported once.  Waits up to timeout_us microseconds (0: not
+ * at all, negative: until one finishes).  Returns TRIG_OK with *ticket set, or
+ * TRIG_PENDING when none finished in time.  The ticket still has to be
+ * delivered with trig_stream_poll.  Lets a caller with many tickets in flight
+ * wait for whichever finishes first (the paper's trigger processes take slices
+ * as they arrive, Sec. 2).  At most 2^20 completions not yet reported are kept;
+ * older ones are dropped. */
+int trig_stream_next_done(trig_ctx *ctx, uint64_t *ticket, int32_t timeout_us);
+
 /* Serving: hold (paused != 0) or resume (0) the start of new device rounds.
  * Submissions are still admitted against the budget while held; rounds already
  * running finish.  For operators (drain control) and deterministic tests. */

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
     uint16_t *cp = (uint16_t *)(wpre + STG / 64 + 1);   // compacted seeds: PMT
     uint16_t *cidx = cp + STG;                       // compacted seeds: stage position
     uint16_t *fci = cidx + STG;                      // fires: compacted index
+    uint16_t *sfl = fci + TILE;                      // staged hits' dense floor index
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
 
@@ -178,6 +179,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
         // stage both arrays with all loads of a thread in flight
         constexpr int U = (STG + NT - 1) / NT;
         uint32_t vt[U], vp[U];
+        uint16_t vf[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
@@ -186,20 +188,23 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
                 vp[u] = S.o_pq[sl + x];
             }
         }
+        // each staged hit's floor (the numbering is read through the caches)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
+            if (x < len && !MASK) vf[u] = S.floor16[vp[u] >> 16];
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
             if (x < len) {
                 st[x] = vt[u];
                 sp[x] = vp[u];
+                if (!MASK) sfl[x] = vf[u];
             }
         }
     }
     __syncthreads();
-    // the thr table and the floor numbering are read through the caches (a tile
-    // makes few lookups: its seeds times the seeds within w_ns of each)
-    const uint16_t *fl = S.floor16;
-    auto lim = [&](uint32_t p, uint32_t q) -> uint32_t { return lim_global(S, W, p, q); };
     const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
     // the stage spans the window of every seed of the tile when the halo reaches
     // past w_ns + t_floor_ns on both sides (or the slice ends there)
@@ -219,17 +224,15 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
                 const uint32_t pq = sp[x];
                 seed = (pq & 0xFFFFu) >= b.prm.q_seed;
                 if (!seed && tau >= 0) {
-                    const uint32_t t = st[x], p = pq >> 16, f = fl[p];
+                    const uint32_t t = st[x], p = pq >> 16, f = sfl[x];
                     for (uint32_t m = x; m > 0;) {
                         --m;
                         if (t - st[m] > (uint32_t)tau) break;
-                        const uint32_t pm = sp[m] >> 16;
-                        if (pm != p && fl[pm] == f) { seed = true; break; }
+                        if ((sp[m] >> 16) != p && sfl[m] == f) { seed = true; break; }
                     }
                     for (uint32_t m = x + 1; !seed && m < len; ++m) {
                         if (st[m] - t > (uint32_t)tau) break;
-                        const uint32_t pm = sp[m] >> 16;
-                        if (pm != p && fl[pm] == f) seed = true;
+                        if ((sp[m] >> 16) != p && sfl[m] == f) seed = true;
                     }
                 }
             }
@@ -277,20 +280,32 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
         ca = s_ca;
         cb = s_cb;
         const uint32_t ncs = s_ncs;
-        // causal fold of each seed of the tile over the compacted seeds within w_ns
+        // causal fold of each seed of the tile over the compacted seeds within
+        // w_ns; the thr table is read through the caches, CB lookups in flight
+        constexpr int CB = 8;
+        const bool t16 = W <= 65535u;
         for (uint32_t ci = ca + threadIdx.x; ci < cb; ci += NT) {
-            const uint32_t t = ct[ci], p = cp[ci];
+            const uint32_t t = ct[ci];
+            const uint64_t row = (uint64_t)cp[ci] * S.n_pmt;
+            uint32_t jl = ci, jr = ci + 1;
+            while (jl > 0 && t - ct[jl - 1] <= W) --jl;
+            while (jr < ncs && ct[jr] - t <= W) ++jr;
             uint32_t c = 1;
-            for (uint32_t j = ci; j > 0;) {
-                --j;
-                const uint32_t d = t - ct[j];
-                if (d > W) break;
-                c += d <= lim(p, cp[j]);
-            }
-            for (uint32_t j = ci + 1; j < ncs; ++j) {
-                const uint32_t d = ct[j] - t;
-                if (d > W) break;
-                c += d <= lim(p, cp[j]);
+            for (uint32_t j0 = jl; j0 < jr; j0 += CB) {
+                uint32_t lim[CB], dd[CB];
+#pragma unroll
+                for (int u = 0; u < CB; ++u) {
+                    const uint32_t j = j0 + u;
+                    dd[u] = 0xFFFFFFFFu;
+                    lim[u] = 0;
+                    if (j < jr && j != ci) {
+                        const uint32_t tj = ct[j];
+                        dd[u] = tj > t ? tj - t : t - tj;
+                        lim[u] = t16 ? (uint32_t)S.thr16[row + cp[j]] : S.thr32[row + cp[j]];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CB; ++u) c += dd[u] <= (lim[u] < W ? lim[u] : W);
             }
             fold[ci - ca] = c;
         }
@@ -443,7 +458,7 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
         S.events[le].t_end = tend;
         S.events[le].n_fire = I.F - s0;
         S.events[le].max_fold = I.m_tail;
-        if (S.x_events && le < S.x_event_cap) {
+        if (S.x_events && n_ev <= S.x_event_cap) {
             S.x_events[le].t_end = tend;
             S.x_events[le].n_fire = I.F - s0;
             S.x_events[le].max_fold = I.m_tail;
@@ -475,6 +490,10 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const uint32_t EP = P.F ? 1 + P.E_int : 0u;       // events begun before this tile
     const uint32_t p_open = open_start(P);
+    // host-mapped staging only when the whole list fits it (else the host copies
+    // the list from device memory)
+    trig_fire *xf = (S.x_fires && Pp->n_fires <= S.x_fire_cap) ? S.x_fires : nullptr;
+    trig_event *xe = (S.x_events && Pp->n_events <= S.x_event_cap) ? S.x_events : nullptr;
     uint32_t carry_starts = 0;                       // starts among earlier fires of the tile
     int32_t carry_latest = -1;                       // local index of the latest start, -1: none
     uint32_t carry_max = P.F ? P.m_tail : 0u;        // largest fold of the open event so far
@@ -517,13 +536,13 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
             out.pad[0] = out.pad[1] = out.pad[2] = 0;
             const uint32_t g = P.F + r;
             S.fires[g] = out;
-            if (S.x_fires && g < S.x_fire_cap) S.x_fires[g] = out;
+            if (xf) xf[g] = out;
             if (st) {
                 S.events[ev].t_trig = out.t_ns;
                 S.events[ev].t_begin = out.t_ns - H;
-                if (S.x_events && ev < S.x_event_cap) {
-                    S.x_events[ev].t_trig = out.t_ns;
-                    S.x_events[ev].t_begin = out.t_ns - H;
+                if (xe) {
+                    xe[ev].t_trig = out.t_ns;
+                    xe[ev].t_begin = out.t_ns - H;
                 }
                 if (r == 0 && P.F) {
                     // this fire ends the event left open by the preceding tiles
@@ -532,10 +551,10 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
                     S.events[pe].t_end = tend;
                     S.events[pe].n_fire = P.F - p_open;
                     S.events[pe].max_fold = P.m_tail;
-                    if (S.x_events && pe < S.x_event_cap) {
-                        S.x_events[pe].t_end = tend;
-                        S.x_events[pe].n_fire = P.F - p_open;
-                        S.x_events[pe].max_fold = P.m_tail;
+                    if (xe) {
+                        xe[pe].t_end = tend;
+                        xe[pe].n_fire = P.F - p_open;
+                        xe[pe].max_fold = P.m_tail;
                     }
                 }
             }
@@ -546,10 +565,10 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
                 S.events[ev].t_end = tend;
                 S.events[ev].n_fire = P.F + r - sg + 1;
                 S.events[ev].max_fold = mv;
-                if (S.x_events && ev < S.x_event_cap) {
-                    S.x_events[ev].t_end = tend;
-                    S.x_events[ev].n_fire = P.F + r - sg + 1;
-                    S.x_events[ev].max_fold = mv;
+                if (xe) {
+                    xe[ev].t_end = tend;
+                    xe[ev].n_fire = P.F + r - sg + 1;
+                    xe[ev].max_fold = mv;
                 }
             }
         }
@@ -619,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
 template <int HMAX>
 constexpr size_t tile_lds_bytes() {
     constexpr size_t STG = TILE + 2 * HMAX;
-    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 2 + TILE * 2;
+    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 2 + TILE * 2 + STG * 2;
 }
 
 template <int HMAX, bool MASK>

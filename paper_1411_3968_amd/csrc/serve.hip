@@ -16,7 +16,9 @@
 // (taken from HIP when needed, within the context's budget) and carves each
 // admitted slice a region of them (its input copy and its pipeline workspace);
 // the region returns to the free list when the slice's results are on the host,
-// which admits waiting slices.  No HIP allocation or free happens per slice.
+// which admits waiting slices (results longer than the pinned staging stay in the
+// region until the poll copies them straight to the caller's buffers).  No HIP
+// allocation or free happens per slice.
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -30,6 +32,7 @@ namespace {
 
 constexpr int SLOTS = 4;
 constexpr uint32_t MAX_PER_ROUND = 64;
+constexpr size_t DONE_Q_MAX = 1u << 20;
 
 struct Ticket {
     uint64_t id = 0;
@@ -42,8 +45,13 @@ struct Ticket {
     int status = TRIG_PENDING;
     uint64_t n_hits = 0, n_seeds = 0, tag = 0;
     uint32_t path = 0;
-    std::vector<trig_fire> fires;
+    std::vector<trig_fire> fires;      // results staged on the host, or
     std::vector<trig_event> events;
+    bool on_device = false;            // lists longer than the staging stay in the region
+    bool busy = false;                 // a poll is copying the lists out
+    const trig_fire *d_fires = nullptr;   // until the poll copies them to the caller
+    const trig_event *d_events = nullptr;
+    uint64_t n_fires = 0, n_events = 0;
 };
 
 bool same_params(const trig_params &a, const trig_params &b) { return std::memcmp(&a, &b, sizeof a) == 0; }
@@ -138,6 +146,7 @@ struct ServeState {
     std::mutex mu;
     std::condition_variable cv_q, cv_done;
     std::deque<Ticket *> queue;
+    std::deque<uint64_t> done_q;   // finished tickets not yet reported by next_done
     std::unordered_map<uint64_t, Ticket *> tickets;
     std::vector<std::thread> threads;
     std::vector<hipStream_t> streams;
@@ -170,32 +179,49 @@ static void run_round(ServeState *S, Job &job, hipStream_t stream, std::vector<T
     if (rc == TRIG_OK) rc = job.dense_pass(c, false);
     if (rc == TRIG_OK) {
         const trigdev::Plan *hp = (const trigdev::Plan *)job.h_plans.ptr;
-        bool copies = false;
         for (uint32_t i = 0; i < n; ++i) {
             Ticket *t = round[i];
+            const SliceInfo &si = job.slices[i];
             trig_result r = {};
             const trigdev::Plan &P = hp[i];
-            const bool ok = job.slices[i].host_status == TRIG_OK && P.status == TRIG_OK && job.slices[i].n > 0;
-            t->fires.resize(ok ? P.n_fires : 0);
-            t->events.resize(ok ? P.n_events : 0);
-            r.fires = t->fires.data();
-            r.fire_cap = t->fires.size();
-            r.events = t->events.data();
-            r.event_cap = t->events.size();
-            t->status = job.deliver(c, i, &r);
+            const bool ok = si.host_status == TRIG_OK && P.status == TRIG_OK && si.n > 0;
+            t->on_device = ok && (P.n_fires > si.x_fcap || P.n_events > si.x_ecap);
+            if (t->on_device) {
+                // the counts only; the lists stay in the ticket's region
+                r.n_hits = si.desc.n_hits;
+                r.n_seeds = P.n_seeds;
+                r.tag = si.desc.tag;
+                r.path = (P.generic ? 1u : 0u) | (P.dense ? 2u : 0u);
+                t->status = TRIG_OK;
+                t->d_fires = si.dev.fires;
+                t->d_events = si.dev.events;
+                t->n_fires = P.n_fires;
+                t->n_events = P.n_events;
+            } else {
+                t->fires.resize(ok ? P.n_fires : 0);
+                t->events.resize(ok ? P.n_events : 0);
+                r.fires = t->fires.data();
+                r.fire_cap = t->fires.size();
+                r.events = t->events.data();
+                r.event_cap = t->events.size();
+                t->status = job.deliver(c, i, &r);
+                t->n_fires = t->fires.size();
+                t->n_events = t->events.size();
+            }
             t->n_hits = r.n_hits;
             t->n_seeds = r.n_seeds;
             t->tag = r.tag;
             t->path = r.path;
-            copies |= P.n_fires > job.slices[i].x_fcap || P.n_events > job.slices[i].x_ecap;
-        }
-        if (copies) {   // lists beyond the staging capacity came by D2H copies
-            hipError_t e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) rc = hip_fail(c, e, "serving results");
         }
     }
     if (rc != TRIG_OK)
-        for (Ticket *t : round) { t->status = rc; t->fires.clear(); t->events.clear(); }
+        for (Ticket *t : round) {
+            t->status = rc;
+            t->fires.clear();
+            t->events.clear();
+            t->on_device = false;
+            t->n_fires = t->n_events = 0;
+        }
     job.ext_ws.clear();
 }
 
@@ -221,8 +247,12 @@ static void slot_main(ServeState *S, int slot) {
             std::lock_guard<std::mutex> lk(S->mu);
             for (Ticket *t : round) {
                 t->done = true;
-                S->arena.release(t->region, t->footprint);
-                t->region = nullptr;
+                S->done_q.push_back(t->id);
+                if (S->done_q.size() > DONE_Q_MAX) S->done_q.pop_front();
+                if (!t->on_device) {
+                    S->arena.release(t->region, t->footprint);
+                    t->region = nullptr;
+                }
                 S->st.completed += 1;
             }
         }
@@ -260,6 +290,7 @@ void serve_shutdown(trig_ctx *c) {
         S->stop = true;
         for (Ticket *t : S->queue) {
             t->done = true;
+            S->done_q.push_back(t->id);
             t->status = TRIG_ECANCELED;
             S->arena.release(t->region, t->footprint);
             t->region = nullptr;
@@ -390,6 +421,7 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
         return TRIG_EINVAL;
     }
     Ticket *t = it->second;
+    if (t->busy) return TRIG_PENDING;   // another poll of this ticket is delivering it
     if (!t->done) {
         if (timeout_us == 0) return TRIG_PENDING;
         if (timeout_us < 0) {
@@ -400,8 +432,8 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
     }
     r->n_hits = t->n_hits ? t->n_hits : t->desc.n_hits;
     r->n_seeds = t->n_seeds;
-    r->n_fires = t->fires.size();
-    r->n_events = t->events.size();
+    r->n_fires = t->n_fires;
+    r->n_events = t->n_events;
     r->tag = t->desc.tag;
     r->path = t->path;
     r->status = t->status;
@@ -412,13 +444,71 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
             r->status = TRIG_EOVERFLOW;
             return TRIG_EOVERFLOW;   // the ticket stays until a poll delivers it
         }
-        if (r->n_fires) std::memcpy(r->fires, t->fires.data(), r->n_fires * sizeof(trig_fire));
-        if (r->n_events) std::memcpy(r->events, t->events.data(), r->n_events * sizeof(trig_event));
+        if (t->on_device) {
+            // one copy from the ticket's region to the caller's buffers, then the
+            // region goes back to the arena
+            t->busy = true;
+            lk.unlock();
+            hipError_t e = hipSuccess;
+            {
+                std::lock_guard<std::mutex> g(S->copy_mu);
+                hipSetDevice(c->device);
+                if (r->n_fires)
+                    e = hipMemcpyAsync(r->fires, t->d_fires, r->n_fires * sizeof(trig_fire), hipMemcpyDeviceToHost,
+                                       S->copy_stream);
+                if (e == hipSuccess && r->n_events)
+                    e = hipMemcpyAsync(r->events, t->d_events, r->n_events * sizeof(trig_event),
+                                       hipMemcpyDeviceToHost, S->copy_stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(S->copy_stream);
+            }
+            lk.lock();
+            t->busy = false;
+            it = S->tickets.find(ticket);   // submits may have rehashed the map meanwhile
+            if (e != hipSuccess) {
+                r->status = hip_fail(c, e, "copying results to the caller");
+                return r->status;   // the ticket stays; a later poll may succeed
+            }
+            S->arena.release(t->region, t->footprint);
+            t->region = nullptr;
+        } else {
+            if (r->n_fires) std::memcpy(r->fires, t->fires.data(), r->n_fires * sizeof(trig_fire));
+            if (r->n_events) std::memcpy(r->events, t->events.data(), r->n_events * sizeof(trig_event));
+        }
     }
     const int st = t->status;
     S->tickets.erase(it);
     delete t;
     return st;
+}
+
+int trig_stream_next_done(trig_ctx *c, uint64_t *ticket, int32_t timeout_us) {
+    if (!c) return TRIG_EINVAL;
+    if (!ticket) {
+        ctx_set_error(c, "null ticket");
+        return TRIG_EINVAL;
+    }
+    ServeState *S;
+    {
+        std::lock_guard<std::mutex> once(c->serve_mu);
+        S = c->serve;
+    }
+    if (!S) return TRIG_PENDING;   // nothing was ever submitted
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto ready = [&] {
+        // drop ids already delivered and forgotten
+        while (!S->done_q.empty() && !S->tickets.count(S->done_q.front())) S->done_q.pop_front();
+        return !S->done_q.empty();
+    };
+    if (!ready()) {
+        if (timeout_us == 0) return TRIG_PENDING;
+        if (timeout_us < 0)
+            S->cv_done.wait(lk, ready);
+        else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready))
+            return TRIG_PENDING;
+    }
+    *ticket = S->done_q.front();
+    S->done_q.pop_front();
+    return TRIG_OK;
 }
 
 int trig_stream_pause(trig_ctx *c, int paused) {

@@ -74,7 +74,8 @@ class StreamStats(C.Structure):
 assert C.sizeof(Result) == 88 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 20
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
-           "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_pause", "trig_stream_stats_get",
+           "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
+           "trig_stream_stats_get",
            "trig_tune_get",
            "trig_tune_set", "trig_profile_enable", "trig_profile_read"]
 
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.trig_batch.argtypes = [P, C.c_uint32, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(Result), V]
     lib.trig_stream_submit.argtypes = [P, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(C.c_uint64)]
     lib.trig_stream_poll.argtypes = [P, C.c_uint64, C.POINTER(Result), C.c_int32]
+    lib.trig_stream_next_done.argtypes = [P, C.POINTER(C.c_uint64), C.c_int32]
     lib.trig_stream_stats_get.argtypes = [P, C.POINTER(StreamStats)]
     lib.trig_stream_pause.argtypes = [P, C.c_int]
     lib.trig_tune_get.argtypes = [P, C.c_uint32, C.POINTER(Tune)]
@@ -105,7 +107,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     for name in EXPORTS:
         fn = getattr(lib, name)
         if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice", "trig_batch",
-                                               "trig_stream_submit", "trig_stream_poll", "trig_stream_stats_get",
+                                               "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done",
+                                               "trig_stream_stats_get",
                                                "trig_stream_pause",
                                                "trig_tune_get", "trig_tune_set", "trig_profile_enable",
                                                "trig_profile_read"):
@@ -209,15 +212,18 @@ class ResultBuffers:
         r.event_cap = len(self.events)
         r.seed_flags = self.flags.ctypes.data if self.flags is not None else None
 
-    def as_dict(self) -> dict:
+    def as_dict(self, copy: bool = True) -> dict:
+        """Counts and lists of the record; ``copy=False`` returns views into the
+        buffers (valid until they are reused)."""
         r = self.rec
         ok = r.status == TRIG_OK
+        cp = (lambda a: a.copy()) if copy else (lambda a: a)
         out = dict(status=int(r.status), n_hits=int(r.n_hits), n_seeds=int(r.n_seeds), tag=int(r.tag),
                    path=int(r.path), n_fires=int(r.n_fires), n_events=int(r.n_events),
-                   fires=self.fires[:r.n_fires].copy() if ok else self.fires[:0].copy(),
-                   events=self.events[:r.n_events].copy() if ok else self.events[:0].copy())
+                   fires=cp(self.fires[:r.n_fires] if ok else self.fires[:0]),
+                   events=cp(self.events[:r.n_events] if ok else self.events[:0]))
         if self.flags is not None:
-            out["seed_flags"] = self.flags[:r.n_hits].copy() if ok else self.flags[:0].copy()
+            out["seed_flags"] = cp(self.flags[:r.n_hits] if ok else self.flags[:0])
         return out
 
 
@@ -312,9 +318,11 @@ def trig_stream_submit(ctx, geom_id: int, pmt, t, q, params: dict | None = None,
 
 
 def trig_stream_poll(ctx, ticket: int, timeout_us: int = -1, fire_cap: int = 1 << 16, event_cap: int = 1 << 16,
-                     n_hits: int = 0, seed_flags: bool = False, buffers: ResultBuffers | None = None):
+                     n_hits: int = 0, seed_flags: bool = False, buffers: ResultBuffers | None = None,
+                     copy: bool = True):
     """Returns ``(status, result dict or None)``.  ``buffers``: reuse these host
-    buffers (their capacities apply) instead of allocating new ones."""
+    buffers (their capacities apply) instead of allocating new ones; with
+    ``copy=False`` the lists are views into them."""
     if buffers is not None:
         rb = buffers
         rb.reset()
@@ -323,7 +331,17 @@ def trig_stream_poll(ctx, ticket: int, timeout_us: int = -1, fire_cap: int = 1 <
     rc = _LIB.trig_stream_poll(ctx, int(ticket), C.byref(rb.rec), int(timeout_us))
     if rc == TRIG_PENDING:
         return rc, None
-    return rc, rb.as_dict()
+    return rc, rb.as_dict(copy)
+
+
+def trig_stream_next_done(ctx, timeout_us: int = -1):
+    """Returns ``(status, ticket)``: TRIG_OK with the next finished ticket, or
+    TRIG_PENDING (ticket 0) when none finished within ``timeout_us``."""
+    tk = C.c_uint64()
+    rc = _LIB.trig_stream_next_done(ctx, C.byref(tk), int(timeout_us))
+    if rc not in (TRIG_OK, TRIG_PENDING):
+        raise TrigError(rc, _err(ctx))
+    return rc, int(tk.value) if rc == TRIG_OK else 0
 
 
 def trig_stream_pause(ctx, paused: bool = True) -> None:

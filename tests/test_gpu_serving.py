@@ -136,3 +136,57 @@ def test_destroy_with_tickets_in_flight(T, pool):
         st, _ = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
         assert st == 0
     T.trig_destroy(ctx)      # drains running rounds, cancels the rest, frees everything
+
+
+def test_next_done_reports_each_ticket_once(T, pool):
+    """trig_stream_next_done hands out every finished ticket exactly once; the
+    results then come from trig_stream_poll and equal the slices alone."""
+    alone = _alone(T, pool)
+    ctx = T.trig_create(0)
+    try:
+        g, thr = pool.geoms["km3"]
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        assert T.trig_stream_next_done(ctx, 0)[0] == T.TRIG_PENDING
+        sub = {}
+        for i, (_, s) in enumerate(pool.slices[:6]):
+            st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params, tag=i)
+            assert st == 0
+            sub[tk] = i
+        seen = []
+        for _ in range(len(sub)):
+            st, tk = T.trig_stream_next_done(ctx, -1)
+            assert st == T.TRIG_OK and tk in sub and tk not in seen
+            seen.append(tk)
+            st, r = T.trig_stream_poll(ctx, tk, 0, fire_cap=1 << 14, event_cap=1 << 14)
+            assert st == 0
+            i = sub[tk]
+            assert np.array_equal(r["fires"], alone[i]["fires"])
+            assert np.array_equal(r["events"], alone[i]["events"])
+        assert T.trig_stream_next_done(ctx, 1000)[0] == T.TRIG_PENDING
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_long_result_lists_delivered_from_device(T, pool):
+    """Fire lists longer than the pinned staging stay in the ticket's device region
+    until the poll; they arrive whole and equal the slice triggered alone."""
+    s = pool.slices[2][1]
+    g, thr = pool.geoms["km3"]
+    prm = dict(pool.params, q_seed=0, min_fold=1, half_event_ns=10)   # every hit fires
+    with T.Trigger(0) as tr:
+        gid = tr.load_geometry(g.floor_id, thr)
+        ref = tr.slice(gid, s.pmt, s.t, s.q, prm)
+    assert ref["n_fires"] == s.n
+    ctx = T.trig_create(0)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, prm)
+        assert st == 0
+        st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=16, event_cap=16)
+        assert st == T.TRIG_EOVERFLOW and r is not None
+        st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=s.n, event_cap=s.n)
+        assert st == 0
+        assert np.array_equal(r["fires"], ref["fires"])
+        assert np.array_equal(r["events"], ref["events"])
+    finally:
+        T.trig_destroy(ctx)
