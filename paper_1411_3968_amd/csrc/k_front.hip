@@ -209,8 +209,10 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
 }
 
 // Per chunk: for every run r and segment boundary j (time j << shift relative to
-// t_min), pos[r][j] = first position of run r whose time is at or after the boundary;
-// pos[r][n_seg] = end of run r.  Runs are maximal time-non-decreasing stretches.
+// t_min), pos[j][r] = first position of run r whose time is at or after the
+// boundary; pos[n_seg][r] = end of run r.  Runs are maximal time-non-decreasing
+// stretches.  The table is segment-major (pos[j * n_runs + r]) so that one
+// segment's bounds over all runs are contiguous for the ordering kernels.
 __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     constexpr int NT = 256, PER = CHUNK / NT;
     const uint32_t item = blockIdx.x;
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<NT>(starts, tot, sh);
-    const uint32_t row_len = P.n_seg + 1;
+    const uint64_t R = P.n_runs;
     const uint32_t sft = P.shift;
     const int64_t tmin = P.t_min;
     int64_t r = (int64_t)S.part[c].run_base + ex - 1;   // run of the element before a
@@ -250,16 +252,16 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         const bool is_start = (k == 0) || (t < st[i]);
         const bool is_end = (k + 1 == S.n) || (st[i + 2] < t);
         if (is_start) ++r;
-        uint32_t *row = S.pos + (uint64_t)r * row_len;
+        uint32_t *col = S.pos + r;
         const uint32_t g = (uint32_t)((uint64_t)(t - tmin) >> sft);
         if (is_start) {
-            for (uint32_t j = 0; j <= g; ++j) row[j] = (uint32_t)k;
+            for (uint32_t j = 0; j <= g; ++j) col[(uint64_t)j * R] = (uint32_t)k;
         } else {
             const uint32_t gp = (uint32_t)((uint64_t)(st[i] - tmin) >> sft);
-            for (uint32_t j = gp + 1; j <= g; ++j) row[j] = (uint32_t)k;
+            for (uint32_t j = gp + 1; j <= g; ++j) col[(uint64_t)j * R] = (uint32_t)k;
         }
         if (is_end)
-            for (uint32_t j = g + 1; j <= P.n_seg; ++j) row[j] = (uint32_t)(k + 1);
+            for (uint32_t j = g + 1; j <= P.n_seg; ++j) col[(uint64_t)j * R] = (uint32_t)(k + 1);
     }
 }
 
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             s_end = s_base + P.n_seg;
         }
         const uint32_t j = item - s_base;
-        const uint32_t row_len = P.n_seg + 1;
+        const uint64_t R = P.n_runs;
         const uint32_t seg_lo = (uint32_t)((uint64_t)j << P.shift);
         // gather the segment's stretch of every run
         uint32_t m = 0;
@@ -323,10 +325,9 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             const uint32_t r = r0 + threadIdx.x;
             uint32_t lo = 0, hi = 0;
             if (r < P.n_runs) {
-                const uint32_t *row = pos + (uint64_t)r * row_len;
-                lo = row[j];
-                hi = row[j + 1];
-                goff_part += lo - row[0];
+                lo = pos[(uint64_t)j * R + r];
+                hi = pos[(uint64_t)(j + 1) * R + r];
+                goff_part += lo - pos[r];
             }
             uint32_t cnt_tot;
             const uint32_t ex = block_excl_scan<NT>(hi - lo, cnt_tot, sm.rs.scan);
@@ -478,6 +479,12 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
 // runs, segments of at most WAVE_CAP hits).  A wave owns a contiguous range of
 // the segment work list and needs no workgroup barrier, so the waves of a CU
 // overlap each other's memory latency.
+//
+// Gathered element k of a segment comes from run r (runs in input order, each
+// run's stretch in input order), so k increases with the input index among
+// hits of equal (t, pmt).  The segment is split into 256 buckets by its local
+// time; the rank of element k in the segment is its bucket's base plus the
+// number of bucket members that precede it in (t, pmt, k) order.
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -486,65 +493,28 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 struct WaveSeg {
-    uint32_t dt[WAVE_CAP], dpq[WAVE_CAP], didx[WAVE_CAP];
-    uint16_t perm[2][WAVE_CAP];
+    uint32_t dt[WAVE_CAP], dpq[WAVE_CAP], dsrc[WAVE_CAP];   // t - t_min, pmt << 16 | q, input index
+    uint16_t aux[WAVE_CAP];      // run marks while gathering, then slots within buckets
+    uint16_t perm[WAVE_CAP];     // elements grouped by bucket
+    uint16_t inv[WAVE_CAP];      // element at each ordered position
     uint32_t run_lo[WAVE_RUNS], run_base[WAVE_RUNS];
-    uint32_t bcount[256], bbase[256];
+    uint32_t bcount[256];
+    uint16_t bbase[256];
 };
-
-// Stable rank of the wave's m elements (element k = e * 64 + lane, so the walk
-// order is k order) by an 8-bit digit: dest[e] = position of element k.
-template <int E, class DigitOf>
-__device__ __forceinline__ void wave_rank8(int m, DigitOf digit_of, uint32_t *hist, uint32_t (&dest)[E]) {
-    const int lane = lane_id();
-    for (int i = lane; i < 256; i += 64) hist[i] = 0;
-    wave_sync();
-    uint32_t rk[E], dg[E];
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = e * 64 + lane;
-        const bool act = k < m;
-        const uint32_t d = act ? digit_of(k) : 0u;
-        uint64_t peers = __ballot(act);
-#pragma unroll
-        for (int bit = 0; bit < 8; ++bit) {
-            const bool x = (d >> bit) & 1u;
-            const uint64_t bb = __ballot(x);
-            peers &= x ? bb : ~bb;
-        }
-        uint32_t r = 0;
-        if (act) {
-            const uint32_t below = (uint32_t)__popcll(peers & lt);
-            const uint32_t base = hist[d];
-            r = base + below;
-            __builtin_amdgcn_wave_barrier();
-            if (below == 0) hist[d] = base + (uint32_t)__popcll(peers);
-        } else {
-            __builtin_amdgcn_wave_barrier();
-        }
-        __builtin_amdgcn_wave_barrier();
-        rk[e] = r;
-        dg[e] = d;
-    }
-    wave_sync();
-    uint32_t v[4], sum = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { v[i] = hist[lane * 4 + i]; sum += v[i]; }
-    const uint32_t incl = wave_incl_scan(sum);
-    uint32_t run = incl - sum;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { hist[lane * 4 + i] = run; run += v[i]; }
-    wave_sync();
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-        if (e * 64 + lane < m) dest[e] = hist[dg[e]] + rk[e];
-    wave_sync();
-}
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v = u > v ? u : v;
+    }
     return v;
 }
 
@@ -565,7 +535,6 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     const int64_t *in_t = nullptr;
     const uint32_t *pos = nullptr;
     uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
-    uint32_t pbits = 0;
     Plan P = {};
     for (uint32_t item = first; item < end; ++item) {
         if (item < s_base || item >= s_end) {
@@ -573,25 +542,24 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
             in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
-            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx; pbits = S.pbits;
+            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx;
             s_base = P.seg_item_base;
             s_end = s_base + P.n_seg;
         }
         const uint32_t j = item - s_base;
-        const uint32_t row_len = P.n_seg + 1;
+        const uint64_t R = P.n_runs;
         const uint32_t seg_lo = (uint32_t)((uint64_t)j << P.shift);
-        const uint32_t R = P.n_runs;
-        // the segment's stretch of every run (run r = i * 64 + lane)
+        // the segment's stretch of every run (run r = i * 64 + lane), from the
+        // contiguous bound rows j and j + 1 and the run starts (row 0)
         uint32_t lo[RI], hi[RI], st[RI];
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
             const uint32_t r = (uint32_t)(i * 64 + lane);
             lo[i] = hi[i] = st[i] = 0;
             if (r < R) {
-                const uint32_t *row = pos + (uint64_t)r * row_len;
-                lo[i] = row[j];
-                hi[i] = row[j + 1];
-                st[i] = row[0];
+                lo[i] = pos[(uint64_t)j * R + r];
+                hi[i] = pos[(uint64_t)(j + 1) * R + r];
+                st[i] = pos[r];
             }
         }
         uint32_t m = 0, gpart = 0;
@@ -612,21 +580,26 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             if (lane == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
             continue;
         }
+        // run marks: each non-empty run's index at its first gathered position
+#pragma unroll
+        for (int e = 0; e < EG; ++e) sm.aux[e * 64 + lane] = 0;
         wave_sync();
-        // gather: EG hits per lane in flight
+#pragma unroll
+        for (int i = 0; i < RI; ++i) {
+            const uint32_t r = (uint32_t)(i * 64 + lane);
+            if (r < R && hi[i] > lo[i]) sm.aux[sm.run_base[r]] = (uint16_t)r;
+        }
+        wave_sync();
+        // gather: run of element k = the largest mark at or before k
         uint32_t src[EG];
+        uint32_t carry = 0;
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
-            src[e] = 0xFFFFFFFFu;
-            if (k < m) {
-                uint32_t a = 0, z = R;   // last run whose base is <= k
-                while (a < z) {
-                    const uint32_t mid = (a + z) >> 1;
-                    if (sm.run_base[mid] <= k) a = mid + 1; else z = mid;
-                }
-                src[e] = sm.run_lo[a - 1] + (k - sm.run_base[a - 1]);
-            }
+            uint32_t r = wave_incl_max(k < m ? (uint32_t)sm.aux[k] : 0u);
+            r = r > carry ? r : carry;
+            carry = __shfl(r, 63, 64);
+            src[e] = k < m ? sm.run_lo[r] + (k - sm.run_base[r]) : 0xFFFFFFFFu;
         }
         int64_t tv[EG];
         uint32_t pv[EG], qv[EG];
@@ -638,117 +611,70 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 qv[e] = in_q[src[e]];
             }
         }
+        // bucket of each element by the top 8 bits of its local time
+        const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sm.bcount[lane * 4 + i] = 0;
+        wave_sync();
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
             if (src[e] != 0xFFFFFFFFu) {
-                sm.dt[k] = (uint32_t)(tv[e] - P.t_min);
+                const uint32_t dt = (uint32_t)(tv[e] - P.t_min);
+                sm.dt[k] = dt;
                 sm.dpq[k] = (pv[e] << 16) | qv[e];
-                sm.didx[k] = src[e];
+                sm.dsrc[k] = src[e];
+                sm.aux[k] = (uint16_t)atomicAdd(&sm.bcount[(dt - seg_lo) >> tb], 1u);
             }
         }
-        // bucket scatter by the top 8 bits of the local time
-        const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
-        for (int i = lane; i < 256; i += 64) sm.bcount[i] = 0;
+        wave_sync();
+        {
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { v[i] = sm.bcount[lane * 4 + i]; sum += v[i]; }
+            const uint32_t incl = wave_incl_scan(sum);
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = (uint16_t)run; run += v[i]; }
+        }
         wave_sync();
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
-            if (k < m) sm.perm[1][k] = (uint16_t)atomicAdd(&sm.bcount[(sm.dt[k] - seg_lo) >> tb], 1u);
+            if (k < m) sm.perm[sm.bbase[(sm.dt[k] - seg_lo) >> tb] + sm.aux[k]] = (uint16_t)k;
         }
         wave_sync();
-        uint32_t v[4], sum = 0, vmax = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            v[i] = sm.bcount[lane * 4 + i];
-            sum += v[i];
-            vmax = v[i] > vmax ? v[i] : vmax;
-        }
-        {
-            const uint32_t incl = wave_incl_scan(sum);
-            uint32_t run = incl - sum;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = run; run += v[i]; }
-        }
-        const bool crowd = __ballot(vmax > BUCKET_MAX) != 0ull;
-        wave_sync();
-        auto less = [&](uint32_t a, uint32_t c) -> bool {
-            if (sm.dt[a] != sm.dt[c]) return sm.dt[a] < sm.dt[c];
-            const uint32_t pa = sm.dpq[a] >> 16, pc = sm.dpq[c] >> 16;
-            if (pa != pc) return pa < pc;
-            return sm.didx[a] < sm.didx[c];
-        };
-        int cur = 0;
-        if (!crowd) {
-#pragma unroll
-            for (int e = 0; e < EG; ++e) {
-                const uint32_t k = (uint32_t)(e * 64 + lane);
-                if (k < m) sm.perm[0][sm.bbase[(sm.dt[k] - seg_lo) >> tb] + sm.perm[1][k]] = (uint16_t)k;
-            }
-            wave_sync();
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint32_t bc = v[i];
-                if (bc > 1) {
-                    uint16_t *bk = sm.perm[0] + sm.bbase[lane * 4 + i];
-                    for (uint32_t x = 1; x < bc; ++x) {
-                        const uint16_t vv = bk[x];
-                        uint32_t y = x;
-                        while (y > 0 && less(vv, bk[y - 1])) { bk[y] = bk[y - 1]; --y; }
-                        bk[y] = vv;
-                    }
-                }
-            }
-            wave_sync();
-        } else {
-            // crowded bucket: stable LSD radix over (t << pbits | pmt), then input order for ties
-            auto keyof = [&](uint32_t x) -> uint64_t {
-                return ((uint64_t)(sm.dt[x] - seg_lo) << pbits) | (uint64_t)(sm.dpq[x] >> 16);
-            };
-#pragma unroll
-            for (int e = 0; e < EG; ++e) {
-                const uint32_t k = (uint32_t)(e * 64 + lane);
-                if (k < m) sm.perm[0][k] = (uint16_t)k;
-            }
-            wave_sync();
-            const int passes = (int)((P.shift + pbits + 7) / 8);
-            for (int ps = 0; ps < passes; ++ps) {
-                const uint32_t sh8 = 8u * (uint32_t)ps;
-                uint32_t dest[EG];
-                wave_rank8<EG>((int)m, [&](int k) -> uint32_t { return (uint32_t)(keyof(sm.perm[cur][k]) >> sh8) & 255u; },
-                               sm.bcount, dest);
-#pragma unroll
-                for (int e = 0; e < EG; ++e) {
-                    const uint32_t k = (uint32_t)(e * 64 + lane);
-                    if (k < m) sm.perm[cur ^ 1][dest[e]] = sm.perm[cur][k];
-                }
-                wave_sync();
-                cur ^= 1;
-            }
-            for (uint32_t k = lane; k < m; k += 64) {
-                const uint32_t x = sm.perm[cur][k];
-                const uint64_t kv = keyof(x);
-                const bool tie_prev = k > 0 && keyof(sm.perm[cur][k - 1]) == kv;
-                const bool tie_next = k + 1 < m && keyof(sm.perm[cur][k + 1]) == kv;
-                if (!tie_prev && !tie_next) { sm.perm[cur ^ 1][k] = (uint16_t)x; continue; }
-                uint32_t a = k, z = k + 1;
-                while (a > 0 && keyof(sm.perm[cur][a - 1]) == kv) --a;
-                while (z < m && keyof(sm.perm[cur][z]) == kv) ++z;
-                uint32_t rank = 0;
-                for (uint32_t u = a; u < z; ++u) rank += sm.didx[sm.perm[cur][u]] < sm.didx[x];
-                sm.perm[cur ^ 1][a + rank] = (uint16_t)x;
-            }
-            wave_sync();
-            cur ^= 1;
-        }
+        // rank within the bucket by (t, pmt, k)
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
             if (k < m) {
-                const uint32_t x = sm.perm[cur][k];
-                o_t[goff + k] = sm.dt[x];
-                o_pq[goff + k] = sm.dpq[x];
-                o_idx[goff + k] = sm.didx[x];
+                const uint32_t t = sm.dt[k], p = sm.dpq[k] >> 16;
+                const uint32_t bk = (t - seg_lo) >> tb;
+                const uint32_t base = sm.bbase[bk], cnt = sm.bcount[bk];
+                uint32_t rank = 0;
+                for (uint32_t x = 0; x < cnt; ++x) {
+                    const uint32_t u = sm.perm[base + x];
+                    const uint32_t tu = sm.dt[u];
+                    bool before = tu < t;
+                    if (tu == t) {
+                        const uint32_t pu = sm.dpq[u] >> 16;
+                        before = pu < p || (pu == p && u < k);
+                    }
+                    rank += before;
+                }
+                sm.inv[base + rank] = (uint16_t)k;
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t i = (uint32_t)(e * 64 + lane);
+            if (i < m) {
+                const uint32_t k = sm.inv[i];
+                o_t[goff + i] = sm.dt[k];
+                o_pq[goff + i] = sm.dpq[k];
+                o_idx[goff + i] = sm.dsrc[k];
             }
         }
         wave_sync();
