@@ -30,7 +30,7 @@ ALGO_BYTES_PER_HIT = {
     "k_bounds": 8.0,       # read t (8); the boundary table is counted separately
     "k_segsort": 24.0,     # read t, pmt, q (12) + write ordered t, pmt|q, index (12)
     "k_segsort_w": 24.0,   # the same, one wave per segment
-    "k_trig": 8.0,         # read ordered t + pmt|q (8); fires and events are per fire
+    "k_tile": 8.0,         # read ordered t + pmt|q (8): seeds and causal folds; fires are per fire
 }
 
 

@@ -525,11 +525,16 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     const int w = threadIdx.x >> 6, lane = lane_id();
     WaveSeg &sm = reinterpret_cast<WaveSeg *>(smem_raw)[w];
     const uint32_t total = b.counters[Q_SEG_TOTAL];
-    const uint32_t nwv = gridDim.x * 4;
-    const uint32_t gw = blockIdx.x * 4 + (uint32_t)w;
-    const uint32_t per = (total + nwv - 1) / nwv;
-    const uint32_t first = gw * per;
-    const uint32_t end = (first + per < total) ? first + per : total;
+    // XCD-aware split: workgroup b runs on XCD b % 8 (round-robin dispatch), and
+    // each XCD takes one contiguous eighth of the segment list, so the cache lines
+    // that neighbouring segments share in every run are fetched into one L2
+    const uint32_t xcd = blockIdx.x % 8, wg_in_xcd = blockIdx.x / 8, wg_per_xcd = gridDim.x / 8;
+    const uint32_t x0 = (uint32_t)(((uint64_t)total * xcd) / 8), x1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / 8);
+    const uint32_t nwv = wg_per_xcd * 4;
+    const uint32_t gw = wg_in_xcd * 4 + (uint32_t)w;
+    const uint32_t per = (x1 - x0 + nwv - 1) / nwv;
+    const uint32_t first = x0 + gw * per;
+    const uint32_t end = (first + per < x1) ? first + per : x1;
     uint32_t si = 0, s_base = 1, s_end = 0;
     const uint16_t *in_pmt = nullptr, *in_q = nullptr;
     const int64_t *in_t = nullptr;
@@ -690,7 +695,7 @@ hipError_t launch_segsort_w(const BatchDev &b, const TrigLaunchCfg &cfg, hipStre
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    const int grid = cfg.n_cu * cfg.persist_per_cu;
+    const int grid = ((cfg.n_cu * cfg.persist_per_cu + 7) / 8) * 8;   // a multiple of the 8 XCDs
     hipLaunchKernelGGL(k_segsort_w, dim3(grid), dim3(256), shm, s, b);
     return hipGetLastError();
 }

@@ -149,7 +149,12 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
 
-    const uint32_t item = blockIdx.x;
+    // XCD-aware order: workgroup b runs on XCD b % 8 and takes tiles from that
+    // XCD's contiguous eighth of the list, so neighbouring tiles share their halos
+    // in one L2
+    const uint32_t per_xcd = (b.total_tiles + 7) / 8;
+    const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (item >= b.total_tiles) return;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
@@ -649,7 +654,7 @@ hipError_t launch_tile(const BatchDev &b, hipStream_t s) {
             (const void *)k_tile<HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (attr != hipSuccess) return attr;
     }
-    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(b.total_tiles), dim3(NT), shm, s, b);
+    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b);
     return hipGetLastError();
 }
 
