@@ -94,6 +94,10 @@ def bench_batch(T, torch, dev, a):
     dsl = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in w.slices]
     n = int(sum(s.n for _, s in w.slices))
     torch.cuda.synchronize()
+    # ordering-stage launch parameters from the autotuner, tuned on this batch
+    # (one class for both tower types)
+    from paper_1411_3968_amd import autotune
+    tuned = autotune.tune_class(tr.ctx, 84, dsl, w.params, reps=5, time_budget_s=30.0)
     first = tr.batch(dsl, w.params)
     assert all(r["status"] == 0 for r in first)
     caps = [(max(1, r["n_fires"]), max(1, r["n_events"])) for r in first]
@@ -137,7 +141,9 @@ def bench_batch(T, torch, dev, a):
                 value=round(n / el, 1), unit="hits/s", ms_per_batch=round(el * 1e3, 3),
                 per_slice_loop=dict(value=round(n / el_loop, 1), ms=round(el_loop * 1e3, 3)),
                 speedup_vs_per_slice=round(el_loop / el, 3), results_equal_per_slice=bool(same),
-                fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1))
+                fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1),
+                autotune=dict({k: tuned["best"][k] for k in ("seg_cap", "seg_target", "grid_per_cu")},
+                              candidates=len(tuned["trials"]), seconds=round(tuned["seconds"], 1)))
 
 
 def bench_serving(T, torch, dev, a):

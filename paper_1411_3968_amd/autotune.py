@@ -1,12 +1,13 @@
 """Autotuner of the ordering stage's launch parameters.
 
-The knobs (``trig_tune``): the LDS capacity of one time segment (2048, 4096 or
-8192 hits, a compiled kernel variant), the expected hits per segment (which
-sets the segment width 2^s ns of a slice from its density), and the number of
-persistent workgroups per compute unit.  Each PMT-count class is tuned on
-representative slices by timing the whole pipeline (``trig_batch``), and the
-choice is kept in a JSON cache keyed by the class.  Correctness never depends
-on the choice: every setting gives byte-identical results.
+The knobs (``trig_tune``): the ordering kernel and its LDS capacity per time
+segment (512 hits: one wave per segment; 2048, 4096 or 8192 hits: one workgroup
+per segment, compiled variants), the expected hits per segment (which sets the
+segment width 2^s ns of a slice from its density), and the number of persistent
+workgroups per compute unit.  Each PMT-count class is tuned on representative
+slices by timing the whole pipeline (``trig_batch`` with marshalling done once),
+and the choice is kept in a JSON cache keyed by the class.  Correctness never
+depends on the choice: every setting gives byte-identical results.
 """
 from __future__ import annotations
 
@@ -18,31 +19,38 @@ import numpy as np
 
 from . import trig as T
 
-DEFAULT_CANDIDATES = [
-    (cap, tgt, g)
-    for cap in (2048, 4096, 8192)
-    for tgt in (cap // 8, cap // 4, cap // 2)
-    for g in (1, 2, 4)
-    if not (cap == 8192 and g > 1)          # one 8192-hit segment fills most of a CU's LDS
-]
+WAVE_CAP = 512
+
+DEFAULT_CANDIDATES = (
+    [(WAVE_CAP, tgt, g) for tgt in (192, 256, 320, 384) for g in (2, 3)] +
+    [(cap, tgt, g) for cap in (2048, 4096) for tgt in (cap // 4, cap // 2) for g in (1, 2, 4)]
+)
 
 
 def _time_batch(ctx, slices, params, reps: int, stream=None) -> float:
-    T.trig_batch(ctx, slices, params, stream=stream)      # warm-up (workspace, graph capture)
-    T.trig_batch(ctx, slices, params, stream=stream)
+    first = T.trig_batch(ctx, slices, params, stream=stream)     # sizes the result lists
+    caps = [(max(1, r["n_fires"]), max(1, r["n_events"])) for r in first]
+    run = T.BatchRunner(ctx, slices, params, stream=stream, caps=caps)
+    run()                                                        # graph capture
     ts = []
     for _ in range(reps):
         t0 = time.perf_counter()
-        T.trig_batch(ctx, slices, params, stream=stream)
+        run()
         ts.append(time.perf_counter() - t0)
     return float(np.median(ts))
 
 
-def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int = 5, stream=None, log=None) -> dict:
-    """Try every candidate on ``slices`` (list of (geom_id, pmt, t, q)); keep the fastest."""
+def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int = 5, stream=None, log=None,
+               time_budget_s: float | None = None) -> dict:
+    """Try the candidates on ``slices`` (list of (geom_id, pmt, t, q)); keep the
+    fastest.  With ``time_budget_s`` the search stops once that much time is spent
+    (the candidates tried so far decide)."""
     best = None
     trials = []
+    t_start = time.perf_counter()
     for (cap, tgt, g) in candidates or DEFAULT_CANDIDATES:
+        if time_budget_s is not None and trials and time.perf_counter() - t_start > time_budget_s:
+            break
         T.trig_tune_set(ctx, n_pmt_max, tgt, cap, g)
         dt = _time_batch(ctx, slices, params, reps, stream)
         trials.append(dict(seg_cap=cap, seg_target=tgt, grid_per_cu=g, s=dt))
@@ -51,7 +59,7 @@ def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int =
         if best is None or dt < best["s"]:
             best = trials[-1]
     T.trig_tune_set(ctx, n_pmt_max, best["seg_target"], best["seg_cap"], best["grid_per_cu"])
-    return dict(n_pmt_max=n_pmt_max, best=best, trials=trials)
+    return dict(n_pmt_max=n_pmt_max, best=best, trials=trials, seconds=time.perf_counter() - t_start)
 
 
 def save(path: str, results: list, device: str = "") -> None:
