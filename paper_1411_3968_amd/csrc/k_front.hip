@@ -88,8 +88,7 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 }
 
 // Per slice: reduce the chunks, validate the input range, number the runs and
-// choose the segment width of the ordering stage.  The last slice to finish
-// builds the work list of the ordering stage (segments of run-merge slices).
+// choose the segment width and the ordering kernel of the slice.
 __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     constexpr int NT = 1024, NW = NT / 64;
     const uint32_t si = blockIdx.x;
@@ -98,7 +97,6 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     __shared__ uint32_t sh[NW + 1];
     __shared__ int64_t slo[NW], shi[NW];
     __shared__ uint32_t spm[NW];
-    __shared__ bool last;
     Plan p = {};
     p.status = TRIG_OK;
     p.state = ST_SKIP;
@@ -185,27 +183,40 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             p.state = fits ? ST_FAST : ST_NEED_GENERIC;
         }
     }
-    if (threadIdx.x == 0) {
-        *P = p;
-        __threadfence();
-        last = atomicAdd(&b.counters[C_PLAN_DONE], 1u) == b.n_slices - 1;
-    }
-    __syncthreads();
-    if (!last || threadIdx.x != 0) return;
-    __threadfence();
+    if (threadIdx.x == 0) *P = p;
+}
+
+// Work lists of the two ordering kernels (run-merge slices' segments), by one
+// extra block of k_bounds: every plan is final once k_plan has finished.  (A last-block
+// pattern inside k_plan would need a device-scope fence per block, which costs
+// microseconds each on this chip.)
+__device__ void build_segment_lists(const BatchDev &b) {
+    constexpr int NT = 256;
+    __shared__ uint32_t sh[NT / 64 + 1];
     uint32_t acc = 0, acc_b = 0;
-    for (uint32_t i = 0; i < b.n_slices; ++i) {
-        Plan *Pi = &b.plans[i];
-        Pi->seg_item_base = acc;
-        Pi->seg_item_base_b = acc_b;
-        if (load_acquire(&Pi->state) == ST_FAST) {
-            const uint32_t ns = load_acquire(&Pi->n_seg);
-            if (load_acquire(&Pi->seg_kind) == 0) acc += ns; else acc_b += ns;
+    for (uint32_t i0 = 0; i0 < b.n_slices; i0 += NT) {
+        const uint32_t i = i0 + threadIdx.x;
+        uint32_t nw = 0, nb = 0;
+        if (i < b.n_slices) {
+            const Plan &P = b.plans[i];
+            if (P.state == ST_FAST) {
+                if (P.seg_kind == 0) nw = P.n_seg; else nb = P.n_seg;
+            }
         }
+        uint32_t tw, tbk;
+        const uint32_t ew = block_excl_scan<NT>(nw, tw, sh);
+        const uint32_t eb = block_excl_scan<NT>(nb, tbk, sh);
+        if (i < b.n_slices) {
+            b.plans[i].seg_item_base = acc + ew;
+            b.plans[i].seg_item_base_b = acc_b + eb;
+        }
+        acc += tw;
+        acc_b += tbk;
     }
-    b.counters[Q_SEG_TOTAL] = acc;
-    b.counters[Q_SEG_TOTAL_B] = acc_b;
-    b.counters[C_PLAN_DONE] = 0;
+    if (threadIdx.x == 0) {
+        b.counters[Q_SEG_TOTAL] = acc;
+        b.counters[Q_SEG_TOTAL_B] = acc_b;
+    }
 }
 
 // Per chunk: for every run r and segment boundary j (time j << shift relative to
@@ -216,6 +227,10 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
 __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     constexpr int NT = 256, PER = CHUNK / NT;
     const uint32_t item = blockIdx.x;
+    if (item == b.total_chunks) {   // one extra block
+        build_segment_lists(b);
+        return;
+    }
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].chunk_base; });
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - S.chunk_base;
@@ -734,7 +749,7 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, int wave_wgs_p
     TRIG_MARK("k_plan", 1);
     if (b.total_chunks) {
         TRIG_MARK("k_bounds", 0);
-        hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks), dim3(256), 0, s, b);
+        hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
         TRIG_CHECK();
         TRIG_MARK("k_bounds", 1);
     }

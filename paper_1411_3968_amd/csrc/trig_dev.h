@@ -4,9 +4,10 @@
 // work counters are cleared by the host before the first kernel):
 //   k_ingest     per 1024-hit chunk: min/max time, max PMT, run starts
 //   k_plan       per slice: validation, t_min, run count, segment width, path and
-//                ordering-kernel kind; the last block to finish builds the
-//                segment work lists of both ordering kernels
+//                ordering-kernel kind
 //   k_bounds     per chunk: run start and segment-boundary positions of every run
+//                (one extra block builds the segment work lists of both
+//                ordering kernels from the plans)
 //   k_segsort_w  persistent, one wave per time segment of at most WAVE_CAP hits:
 //                gather the segment's stretch of every run into LDS, order it by
 //                (t, pmt, input index), write the ordered structure-of-arrays
@@ -55,7 +56,6 @@ enum State : uint32_t {
 enum Counter : int {
     Q_SEG = 0,           // dequeue counter of k_segsort
     Q_SEG_TOTAL = 1,     // number of segment items
-    C_PLAN_DONE = 3,     // slices planned so far (the last block builds the segment work list)
     Q_SEG_TOTAL_B = 5,   // number of segment items of the block-per-segment kernel
     N_COUNTERS = 16,
 };
