@@ -31,6 +31,7 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int NW = NT / 64;
+constexpr int FLOOR_LDS_MAX = 4096;   // floor numbering kept in LDS up to this many PMTs
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
@@ -133,7 +134,7 @@ __device__ __forceinline__ bool export_as_is(uint32_t state) {
 }
 
 template <int HMAX, bool MASK>
-__global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
+__global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     constexpr int STG = TILE + 2 * HMAX;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *st = (uint32_t *)smem;                 // staged t - t_min
@@ -146,6 +147,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
     uint16_t *cidx = cp + STG;                       // compacted seeds: stage position
     uint16_t *fci = cidx + STG;                      // fires: compacted index
     uint16_t *sfl = fci + TILE;                      // staged hits' dense floor index
+    uint16_t *lfl = sfl + STG;                       // dense floor index of every PMT (floor_lds of them)
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
 
@@ -184,7 +186,6 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
         // stage both arrays with all loads of a thread in flight
         constexpr int U = (STG + NT - 1) / NT;
         uint32_t vt[U], vp[U];
-        uint16_t vf[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
@@ -193,23 +194,25 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
                 vp[u] = S.o_pq[sl + x];
             }
         }
-        // each staged hit's floor (the numbering is read through the caches)
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t x = u * NT + threadIdx.x;
-            if (x < len && !MASK) vf[u] = S.floor16[vp[u] >> 16];
-        }
+        // the floor numbering (independent of the staged hits, so in flight with them)
+        if (!MASK && S.n_pmt <= floor_lds)
+            for (uint32_t x = threadIdx.x; x < S.n_pmt; x += NT) lfl[x] = S.floor16[x];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
             if (x < len) {
                 st[x] = vt[u];
                 sp[x] = vp[u];
-                if (!MASK) sfl[x] = vf[u];
             }
         }
     }
     __syncthreads();
+    if (!MASK) {
+        // each staged hit's floor, so the partner search reads one LDS word per side
+        const uint16_t *fl = S.n_pmt <= floor_lds ? lfl : S.floor16;
+        for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = fl[sp[x] >> 16];
+        __syncthreads();
+    }
     const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
     // the stage spans the window of every seed of the tile when the halo reaches
     // past w_ns + t_floor_ns on both sides (or the slice ends there)
@@ -229,15 +232,15 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
                 const uint32_t pq = sp[x];
                 seed = (pq & 0xFFFFu) >= b.prm.q_seed;
                 if (!seed && tau >= 0) {
+                    // neighbours at distance d on both sides together, so each step
+                    // waits on one round of independent LDS reads
                     const uint32_t t = st[x], p = pq >> 16, f = sfl[x];
-                    for (uint32_t m = x; m > 0;) {
-                        --m;
-                        if (t - st[m] > (uint32_t)tau) break;
-                        if ((sp[m] >> 16) != p && sfl[m] == f) { seed = true; break; }
-                    }
-                    for (uint32_t m = x + 1; !seed && m < len; ++m) {
-                        if (st[m] - t > (uint32_t)tau) break;
-                        if ((sp[m] >> 16) != p && sfl[m] == f) seed = true;
+                    for (uint32_t d = 1;; ++d) {
+                        const bool l_in = x >= d && t - st[x - d] <= (uint32_t)tau;
+                        const bool r_in = x + d < len && st[x + d] - t <= (uint32_t)tau;
+                        if (!l_in && !r_in) break;
+                        if (l_in && (sp[x - d] >> 16) != p && sfl[x - d] == f) { seed = true; break; }
+                        if (r_in && (sp[x + d] >> 16) != p && sfl[x + d] == f) { seed = true; break; }
                     }
                 }
             }
@@ -286,21 +289,34 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
         cb = s_cb;
         const uint32_t ncs = s_ncs;
         // causal fold of each seed of the tile over the compacted seeds within
-        // w_ns; the thr table is read through the caches, CB lookups in flight
-        constexpr int CB = 8;
+        // w_ns: G lanes per seed split its window (bounds by binary search in the
+        // time-ordered seeds), each with CB table lookups in flight (the thr table
+        // is read through the caches)
+        constexpr int G = 4, CB = 8;
         const bool t16 = W <= 65535u;
-        for (uint32_t ci = ca + threadIdx.x; ci < cb; ci += NT) {
+        const uint32_t sub = threadIdx.x % G;
+        for (uint32_t ci = ca + threadIdx.x / G; ci < cb; ci += NT / G) {
             const uint32_t t = ct[ci];
             const uint64_t row = (uint64_t)cp[ci] * S.n_pmt;
-            uint32_t jl = ci, jr = ci + 1;
-            while (jl > 0 && t - ct[jl - 1] <= W) --jl;
-            while (jr < ncs && ct[jr] - t <= W) ++jr;
-            uint32_t c = 1;
-            for (uint32_t j0 = jl; j0 < jr; j0 += CB) {
+            const uint32_t t_lo = t > W ? t - W : 0u;
+            const uint64_t t_hi = (uint64_t)t + W;
+            uint32_t jl = 0, z = ci;          // first seed with time >= t - W
+            while (jl < z) {
+                const uint32_t mid = (jl + z) >> 1;
+                if (ct[mid] < t_lo) jl = mid + 1; else z = mid;
+            }
+            uint32_t jr = ci + 1;
+            z = ncs;                          // first seed with time > t + W
+            while (jr < z) {
+                const uint32_t mid = (jr + z) >> 1;
+                if ((uint64_t)ct[mid] <= t_hi) jr = mid + 1; else z = mid;
+            }
+            uint32_t c = 0;
+            for (uint32_t j0 = jl + sub; j0 < jr; j0 += G * CB) {
                 uint32_t lim[CB], dd[CB];
 #pragma unroll
                 for (int u = 0; u < CB; ++u) {
-                    const uint32_t j = j0 + u;
+                    const uint32_t j = j0 + u * G;
                     dd[u] = 0xFFFFFFFFu;
                     lim[u] = 0;
                     if (j < jr && j != ci) {
@@ -312,7 +328,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b) {
 #pragma unroll
                 for (int u = 0; u < CB; ++u) c += dd[u] <= (lim[u] < W ? lim[u] : W);
             }
-            fold[ci - ca] = c;
+#pragma unroll
+            for (int d = 1; d < G; d <<= 1) c += __shfl_xor(c, d, 64);
+            if (sub == 0) fold[ci - ca] = c + 1;
         }
         if (S.seed_flags) {
             for (uint64_t j = a + threadIdx.x; j < e; j += NT) {
@@ -643,18 +661,20 @@ __global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
 template <int HMAX>
 constexpr size_t tile_lds_bytes() {
     constexpr size_t STG = TILE + 2 * HMAX;
-    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 2 + TILE * 2 + STG * 2;
+    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 3 + TILE * 2;
 }
 
 template <int HMAX, bool MASK>
-hipError_t launch_tile(const BatchDev &b, hipStream_t s) {
-    constexpr size_t shm = tile_lds_bytes<HMAX>();
-    if (shm > 64 * 1024) {
-        static const hipError_t attr = hipFuncSetAttribute(
-            (const void *)k_tile<HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (attr != hipSuccess) return attr;
-    }
-    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b);
+hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
+    // the floor numbering of the batch's largest geometry in LDS when it is small
+    const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
+    const size_t shm = tile_lds_bytes<HMAX>() + ((floor_lds * 2 + 15) & ~15u);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tile<HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(tile_lds_bytes<HMAX>() + FLOOR_LDS_MAX * 2));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
+                       floor_lds);
     return hipGetLastError();
 }
 
@@ -663,10 +683,10 @@ hipError_t launch_tile(const BatchDev &b, hipStream_t s) {
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
 #define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-static hipError_t launch_trigger(const BatchDev &b, bool dense, hipStream_t s,
+static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, bool dense, hipStream_t s,
                                  void (*mark)(void *, const char *, int), void *mark_ctx) {
     TRIG_MARK("k_tile", 0);
-    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, s) : launch_tile<HALO_SMALL, false>(b, s);
+    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, max_pmt, s) : launch_tile<HALO_SMALL, false>(b, max_pmt, s);
     if (e != hipSuccess) return e;
     TRIG_MARK("k_tile", 1);
     TRIG_MARK("k_tscan", 0);
@@ -680,18 +700,18 @@ static hipError_t launch_trigger(const BatchDev &b, bool dense, hipStream_t s,
     return hipSuccess;
 }
 
-hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &, uint32_t, hipStream_t s,
+hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &, uint32_t max_pmt, hipStream_t s,
                             void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (!b.total_tiles) return hipSuccess;
-    return launch_trigger(b, false, s, mark, mark_ctx);
+    return launch_trigger(b, max_pmt, false, s, mark, mark_ctx);
 }
 
-hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &, uint32_t, hipStream_t s,
+hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &, uint32_t max_pmt, hipStream_t s,
                              void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (!b.total_tiles) return hipSuccess;
     TRIG_MARK("k_dseed", 0);
     hipLaunchKernelGGL(k_dseed, dim3(b.total_tiles), dim3(NT), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_dseed", 1);
-    return launch_trigger(b, true, s, mark, mark_ctx);
+    return launch_trigger(b, max_pmt, true, s, mark, mark_ctx);
 }

@@ -265,6 +265,7 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
 // slice whose base is <= item.
 template <class BaseOf>
 __device__ __forceinline__ uint32_t find_slice(uint32_t n_slices, uint32_t item, BaseOf base_of) {
+    if (n_slices <= 1) return 0;      // no load on the single-slice path
     uint32_t lo = 0, hi = n_slices;   // first index with base > item, in [lo, hi]
     while (lo < hi) {
         uint32_t mid = (lo + hi) >> 1;
