@@ -664,26 +664,46 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             if (k < m) sm.perm[sm.bbase[(sm.dt[k] - seg_lo) >> tb] + sm.aux[k]] = (uint16_t)k;
         }
         wave_sync();
-        // rank within the bucket by (t, pmt, k)
+        // rank within the bucket by (t, pmt, k); the EG elements of a lane walk
+        // their buckets together, so each step waits on one round of LDS reads
+        {
+            uint32_t et[EG], ep[EG], ebase[EG], ecnt[EG], rank[EG];
+            uint32_t most = 0;
 #pragma unroll
-        for (int e = 0; e < EG; ++e) {
-            const uint32_t k = (uint32_t)(e * 64 + lane);
-            if (k < m) {
-                const uint32_t t = sm.dt[k], p = sm.dpq[k] >> 16;
-                const uint32_t bk = (t - seg_lo) >> tb;
-                const uint32_t base = sm.bbase[bk], cnt = sm.bcount[bk];
-                uint32_t rank = 0;
-                for (uint32_t x = 0; x < cnt; ++x) {
-                    const uint32_t u = sm.perm[base + x];
-                    const uint32_t tu = sm.dt[u];
-                    bool before = tu < t;
-                    if (tu == t) {
-                        const uint32_t pu = sm.dpq[u] >> 16;
-                        before = pu < p || (pu == p && u < k);
-                    }
-                    rank += before;
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t k = (uint32_t)(e * 64 + lane);
+                ecnt[e] = 0;
+                rank[e] = 0;
+                et[e] = ep[e] = ebase[e] = 0;
+                if (k < m) {
+                    et[e] = sm.dt[k];
+                    ep[e] = sm.dpq[k] >> 16;
+                    const uint32_t bk = (et[e] - seg_lo) >> tb;
+                    ebase[e] = sm.bbase[bk];
+                    ecnt[e] = sm.bcount[bk];
                 }
-                sm.inv[base + rank] = (uint16_t)k;
+                most = ecnt[e] > most ? ecnt[e] : most;
+            }
+            for (uint32_t x = 0; x < most; ++x) {
+#pragma unroll
+                for (int e = 0; e < EG; ++e) {
+                    if (x < ecnt[e]) {
+                        const uint32_t k = (uint32_t)(e * 64 + lane);
+                        const uint32_t u = sm.perm[ebase[e] + x];
+                        const uint32_t tu = sm.dt[u];
+                        bool before = tu < et[e];
+                        if (tu == et[e]) {
+                            const uint32_t pu = sm.dpq[u] >> 16;
+                            before = pu < ep[e] || (pu == ep[e] && u < k);
+                        }
+                        rank[e] += before;
+                    }
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t k = (uint32_t)(e * 64 + lane);
+                if (k < m) sm.inv[ebase[e] + rank[e]] = (uint16_t)k;
             }
         }
         wave_sync();
