@@ -29,7 +29,7 @@ using namespace trigdev;
 
 namespace {
 
-constexpr int NT = 256;
+constexpr int NT = 512;           // k_tile workgroup (the LDS of a tile, not its threads, bounds occupancy)
 constexpr int NW = NT / 64;
 constexpr int FLOOR_LDS_MAX = 4096;   // floor numbering kept in LDS up to this many PMTs
 
@@ -607,8 +607,9 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
 // search that runs past them reads global memory.  Also moves the slice to
 // ST_DENSE for the rerun.
 constexpr int DSH = 64;
+constexpr int NTD = 256;
 
-__global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
+__global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
     const SliceDev &S = b.slices[si];
@@ -623,16 +624,16 @@ __global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
     if (a >= n) return;
     const uint64_t lo = a >= (uint64_t)DSH ? a - DSH : 0;
     const uint64_t hi = (a + TILE + DSH < n) ? a + TILE + DSH : n;
-    stage_copy<NT, 5>(lt, S.o_t + lo, (uint32_t)(hi - lo));
-    stage_copy<NT, 5>(lpq, S.o_pq + lo, (uint32_t)(hi - lo));
+    stage_copy<NTD, 5>(lt, S.o_t + lo, (uint32_t)(hi - lo));
+    stage_copy<NTD, 5>(lpq, S.o_pq + lo, (uint32_t)(hi - lo));
     __syncthreads();
     auto T_at = [&](uint64_t m) -> uint32_t { return (m >= lo && m < hi) ? lt[m - lo] : S.o_t[m]; };
     auto P_at = [&](uint64_t m) -> uint32_t { return ((m >= lo && m < hi) ? lpq[m - lo] : S.o_pq[m]) >> 16; };
     const uint32_t Q = b.prm.q_seed;
     const int32_t tau = b.prm.t_floor_ns;
 #pragma unroll
-    for (int e = 0; e < TILE / NT; ++e) {
-        const uint64_t j = a + (uint64_t)e * NT + threadIdx.x;
+    for (int e = 0; e < TILE / NTD; ++e) {
+        const uint64_t j = a + (uint64_t)e * NTD + threadIdx.x;
         bool seed = false;
         if (j < n) {
             const uint32_t t = lt[j - lo], pq = lpq[j - lo], p = pq >> 16;
@@ -653,7 +654,7 @@ __global__ __launch_bounds__(NT) void k_dseed(BatchDev b) {
             }
         }
         const uint64_t bal = __ballot(seed);
-        const uint64_t w0 = a + (uint64_t)e * NT + (threadIdx.x & ~63u);
+        const uint64_t w0 = a + (uint64_t)e * NTD + (threadIdx.x & ~63u);
         if (lane_id() == 0 && w0 < n) S.dmask[w0 >> 6] = bal;
     }
 }
@@ -710,7 +711,7 @@ hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &, uint32_t 
                              void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (!b.total_tiles) return hipSuccess;
     TRIG_MARK("k_dseed", 0);
-    hipLaunchKernelGGL(k_dseed, dim3(b.total_tiles), dim3(NT), 0, s, b);
+    hipLaunchKernelGGL(k_dseed, dim3(b.total_tiles), dim3(NTD), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_dseed", 1);
     return launch_trigger(b, max_pmt, true, s, mark, mark_ctx);
