@@ -29,9 +29,15 @@ using namespace trigdev;
 
 namespace {
 
-constexpr int NT = 512;           // k_tile workgroup (the LDS of a tile, not its threads, bounds occupancy)
-constexpr int NW = NT / 64;
+// k_tile workgroups: 512 threads when the tiles fit the GPU in one wave of
+// workgroups (lower latency per tile), else 256 (more tiles per CU in flight)
+constexpr int NT_ONE_WAVE = 512, NT_MANY = 256;
 constexpr int FLOOR_LDS_MAX = 4096;   // floor numbering kept in LDS up to this many PMTs
+
+// Seeds of one stage that the compacted lists hold: a fraction of the stage in
+// the first pass (seeds are a few per cent of the hits; a stage with more is
+// rerun with the mask), every hit in the rerun.
+__host__ __device__ constexpr int compact_cap(int hmax, bool mask) { return mask ? TILE + 2 * hmax : 512; }
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
@@ -133,20 +139,22 @@ __device__ __forceinline__ bool export_as_is(uint32_t state) {
     return state != ST_FAST && state != ST_GENERIC_DONE && state != ST_DENSE;
 }
 
-template <int HMAX, bool MASK>
+template <int NT, int HMAX, bool MASK>
 __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
+    constexpr int NW = NT / 64;
     constexpr int STG = TILE + 2 * HMAX;
+    constexpr int CS = compact_cap(HMAX, MASK);      // seeds of a stage the compacted lists hold
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *st = (uint32_t *)smem;                 // staged t - t_min
     uint32_t *sp = st + STG;                         // staged pmt << 16 | q
     uint32_t *ct = sp + STG;                         // compacted seeds: time
-    uint32_t *fold = ct + STG;                       // fold of each seed of the tile
-    uint64_t *sbits = (uint64_t *)(fold + TILE);     // seed bits of the stage
+    uint32_t *fold = ct + CS;                        // fold of each seed of the tile
+    uint64_t *sbits = (uint64_t *)(fold + CS);       // seed bits of the stage
     uint32_t *wpre = (uint32_t *)(sbits + STG / 64); // seeds before each 64-hit word
     uint16_t *cp = (uint16_t *)(wpre + STG / 64 + 1);   // compacted seeds: PMT
-    uint16_t *cidx = cp + STG;                       // compacted seeds: stage position
-    uint16_t *fci = cidx + STG;                      // fires: compacted index
-    uint16_t *sfl = fci + TILE;                      // staged hits' dense floor index
+    uint16_t *cidx = cp + CS;                        // compacted seeds: stage position
+    uint16_t *fci = cidx + CS;                       // fires: compacted index
+    uint16_t *sfl = fci + CS;                        // staged hits' dense floor index
     uint16_t *lfl = sfl + STG;                       // dense floor index of every PMT (floor_lds of them)
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
@@ -220,7 +228,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const bool cover_r = sh_end == n || (uint64_t)st[len - 1] > (uint64_t)te + reach;
     uint32_t ca = 0, cb = 0;
     uint64_t cbase = a;
-    if (cover_l && cover_r) {
+    const bool covered = cover_l && cover_r;
+    bool fits = true;
+    if (covered) {
         cbase = sl;
         // seed bits of the whole stage
         for (uint32_t x0 = 0; x0 < len; x0 += NT) {
@@ -265,6 +275,13 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             }
         }
         __syncthreads();
+        fits = s_ncs <= (uint32_t)CS;
+    }
+    if (covered && !fits) {
+        // more seeds in the stage than the compacted lists hold: rerun with a mask
+        if (threadIdx.x == 0) atomicOr(&Pp->dense, 1u);
+    } else if (covered) {
+        const uint32_t nwords = (len + 63) / 64;
         // seeds before the tile and before its end
         if (threadIdx.x < 2) {
             const uint32_t x = (uint32_t)((threadIdx.x == 0 ? a : e) - sl);
@@ -342,7 +359,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
         // a window beyond the staged halo: this pass leaves the tile empty and the
         // slice is rerun with a seed mask
         if (threadIdx.x == 0) atomicOr(&Pp->dense, 1u);
-    } else {
+    } else if (!covered) {
         // seeds from the mask, folds of the tile from global memory
         uint32_t acc = 0;
         for (uint64_t j0 = a; j0 < e; j0 += NT) {
@@ -659,24 +676,30 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     }
 }
 
-template <int HMAX>
+template <int HMAX, bool MASK>
 constexpr size_t tile_lds_bytes() {
-    constexpr size_t STG = TILE + 2 * HMAX;
-    return STG * 4 * 3 + TILE * 4 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + STG * 2 * 3 + TILE * 2;
+    constexpr size_t STG = TILE + 2 * HMAX, CS = compact_cap(HMAX, MASK);
+    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + CS * 2 * 3 + STG * 2;
+}
+
+template <int NT, int HMAX, bool MASK>
+hipError_t launch_tile_nt(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
+    const size_t shm = tile_lds_bytes<HMAX, MASK>() + ((floor_lds * 2 + 15) & ~15u);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_tile<NT, HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(tile_lds_bytes<HMAX, MASK>() + FLOOR_LDS_MAX * 2));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_tile<NT, HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
+                       floor_lds);
+    return hipGetLastError();
 }
 
 template <int HMAX, bool MASK>
-hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
+hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipStream_t s) {
     // the floor numbering of the batch's largest geometry in LDS when it is small
     const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
-    const size_t shm = tile_lds_bytes<HMAX>() + ((floor_lds * 2 + 15) & ~15u);
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_tile<HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(tile_lds_bytes<HMAX>() + FLOOR_LDS_MAX * 2));
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_tile<HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
-                       floor_lds);
-    return hipGetLastError();
+    if (b.total_tiles <= 4 * n_cu) return launch_tile_nt<NT_ONE_WAVE, HMAX, MASK>(b, floor_lds, s);
+    return launch_tile_nt<NT_MANY, HMAX, MASK>(b, floor_lds, s);
 }
 
 }  // namespace
@@ -684,10 +707,11 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
 #define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, bool dense, hipStream_t s,
+static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, bool dense, hipStream_t s,
                                  void (*mark)(void *, const char *, int), void *mark_ctx) {
     TRIG_MARK("k_tile", 0);
-    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, max_pmt, s) : launch_tile<HALO_SMALL, false>(b, max_pmt, s);
+    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, max_pmt, n_cu, s)
+                         : launch_tile<HALO_SMALL, false>(b, max_pmt, n_cu, s);
     if (e != hipSuccess) return e;
     TRIG_MARK("k_tile", 1);
     TRIG_MARK("k_tscan", 0);
@@ -701,18 +725,18 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, bool dense
     return hipSuccess;
 }
 
-hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &, uint32_t max_pmt, hipStream_t s,
+hipError_t trig_launch_tail(const BatchDev &b, const TrigLaunchCfg &cfg, uint32_t max_pmt, hipStream_t s,
                             void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (!b.total_tiles) return hipSuccess;
-    return launch_trigger(b, max_pmt, false, s, mark, mark_ctx);
+    return launch_trigger(b, max_pmt, (uint32_t)cfg.n_cu, false, s, mark, mark_ctx);
 }
 
-hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &, uint32_t max_pmt, hipStream_t s,
+hipError_t trig_launch_dense(const BatchDev &b, const TrigLaunchCfg &cfg, uint32_t max_pmt, hipStream_t s,
                              void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (!b.total_tiles) return hipSuccess;
     TRIG_MARK("k_dseed", 0);
     hipLaunchKernelGGL(k_dseed, dim3(b.total_tiles), dim3(NTD), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_dseed", 1);
-    return launch_trigger(b, max_pmt, true, s, mark, mark_ctx);
+    return launch_trigger(b, max_pmt, (uint32_t)cfg.n_cu, true, s, mark, mark_ctx);
 }
