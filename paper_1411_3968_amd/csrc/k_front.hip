@@ -610,16 +610,29 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             if (r < R && hi[i] > lo[i]) sm.aux[sm.run_base[r]] = (uint16_t)r;
         }
         wave_sync();
-        // gather: run of element k = the largest mark at or before k
-        uint32_t src[EG];
-        uint32_t carry = 0;
+        // gather: run of element k = the largest mark at or before k (the EG
+        // scans are independent; their carries are a max over earlier groups)
+        uint32_t src[EG], rr[EG];
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
-            uint32_t r = wave_incl_max(k < m ? (uint32_t)sm.aux[k] : 0u);
-            r = r > carry ? r : carry;
-            carry = __shfl(r, 63, 64);
-            src[e] = k < m ? sm.run_lo[r] + (k - sm.run_base[r]) : 0xFFFFFFFFu;
+            rr[e] = k < m ? (uint32_t)sm.aux[k] : 0u;
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) rr[e] = wave_incl_max(rr[e]);
+        {
+            uint32_t carry = 0;
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t last = __shfl(rr[e], 63, 64);
+                rr[e] = rr[e] > carry ? rr[e] : carry;
+                carry = last > carry ? last : carry;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)(e * 64 + lane);
+            src[e] = k < m ? sm.run_lo[rr[e]] + (k - sm.run_base[rr[e]]) : 0xFFFFFFFFu;
         }
         int64_t tv[EG];
         uint32_t pv[EG], qv[EG];
