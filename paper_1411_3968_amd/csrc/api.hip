@@ -293,17 +293,14 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     d_slices = (SliceDev *)dmeta.ptr;
     d_plans = (Plan *)((char *)dmeta.ptr + align256(n * sizeof(SliceDev)));
+    // (the counters are written by k_bounds before any kernel reads them)
     d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
-    {
-        // work-queue and completion counters start at zero (the kernels leave them at zero)
-        hipError_t e0 = hipMemsetAsync(d_counters, 0, N_COUNTERS * sizeof(uint32_t), s);
-        if (e0 != hipSuccess) return hip_fail(c, e0, "clearing counters");
-    }
     SliceDev *hs = (SliceDev *)h_slices.ptr;
     char *base = (char *)ws.ptr;
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
-        SliceDev S = {};
+        SliceDev S;
+        std::memset(&S, 0, sizeof S);   // padding too: descriptors are compared bytewise
         char *b = own_ws ? base + si.ws_off : ext_ws[i];
         const SliceLayout &L = si.L;
         const uint64_t nh = si.n;
@@ -365,8 +362,17 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         hs[i] = S;
         si.dev = S;
     }
-    hipError_t e = hipMemcpyAsync(d_slices, hs, n * sizeof(SliceDev), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(c, e, "H2D of slice descriptors");
+    // the previous round on this job has completed (every entry point synchronises
+    // before it returns), so the device copy of an unchanged set is intact
+    if (up_ptr != dmeta.ptr || up_cap != dmeta.cap || up_slices.size() != n ||
+        std::memcmp(up_slices.data(), hs, n * sizeof(SliceDev)) != 0) {
+        up_ptr = nullptr;
+        hipError_t e = hipMemcpyAsync(d_slices, hs, n * sizeof(SliceDev), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return hip_fail(c, e, "H2D of slice descriptors");
+        up_slices.assign(hs, hs + n);
+        up_ptr = dmeta.ptr;
+        up_cap = dmeta.cap;
+    }
     batch = {};
     batch.slices = d_slices;
     batch.plans = d_plans;
@@ -544,16 +550,20 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     if (P.n_fires) {
         if (P.n_fires <= si.x_fcap)
             std::memcpy(r->fires, xb + si.x_off_f, (size_t)P.n_fires * sizeof(trig_fire));
-        else
+        else {
             e = hipMemcpyAsync(r->fires, si.dev.fires, (size_t)P.n_fires * sizeof(trig_fire),
                                hipMemcpyDeviceToHost, stream);
+            copies_queued = true;
+        }
     }
     if (e == hipSuccess && P.n_events) {
         if (P.n_events <= si.x_ecap)
             std::memcpy(r->events, xb + si.x_off_e, (size_t)P.n_events * sizeof(trig_event));
-        else
+        else {
             e = hipMemcpyAsync(r->events, si.dev.events, (size_t)P.n_events * sizeof(trig_event),
                                hipMemcpyDeviceToHost, stream);
+            copies_queued = true;
+        }
     }
     if (e != hipSuccess) return r->status = hip_fail(c, e, "D2H of results");
     return r->status = TRIG_OK;
@@ -566,6 +576,8 @@ void Job::release(trig_ctx *c) {
     capture_stream = nullptr;
     ws.release(c);
     dmeta.release(c);
+    up_ptr = nullptr;
+    up_slices.clear();
     gscratch.release(c);
     h_slices.release();
     h_plans.release();
@@ -616,13 +628,16 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
     rc = J.dense_pass(c, prof);
     if (rc) return rc;
     int first_bad = TRIG_OK;
+    J.copies_queued = false;
     for (uint32_t i = 0; i < n; ++i) {
         const int st = J.deliver(c, i, &res[i]);
         if (st != TRIG_OK && first_bad == TRIG_OK) first_bad = st;
     }
-    // lists longer than their staging were queued as copies from the device
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(c, e, "synchronise results");
+    if (J.copies_queued) {
+        // lists longer than their staging were queued as copies from the device
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(c, e, "synchronise results");
+    }
     if (prof) prof_collect(c);
     return first_bad;
 }

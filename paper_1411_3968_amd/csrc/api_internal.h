@@ -70,6 +70,11 @@ struct Job {
     trigdev::SliceDev *d_slices = nullptr;
     trigdev::Plan *d_plans = nullptr;
     uint32_t *d_counters = nullptr;
+    // the descriptors last uploaded and the device buffer that holds them: an
+    // unchanged set is not uploaded again
+    std::vector<trigdev::SliceDev> up_slices;
+    const void *up_ptr = nullptr;
+    size_t up_cap = 0;
     trigdev::BatchDev batch;
     // per-slice workspace bases supplied by the caller (serving: each ticket's
     // region of the resident arena); empty: one workspace owned by the job
@@ -81,6 +86,7 @@ struct Job {
     std::vector<uint8_t> seen_key, graph_key;
     hipGraphExec_t graph_exec = nullptr;
     bool graphs_ok = true;
+    bool copies_queued = false;       // deliver queued a device-to-host copy
 
     // want_flags / fire_caps / event_caps: per slice, may be null (no flags /
     // default staging capacity).

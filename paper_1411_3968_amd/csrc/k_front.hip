@@ -780,12 +780,11 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, int wave_wgs_p
     hipLaunchKernelGGL(k_plan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_plan", 1);
-    if (b.total_chunks) {
-        TRIG_MARK("k_bounds", 0);
-        hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
-        TRIG_CHECK();
-        TRIG_MARK("k_bounds", 1);
-    }
+    // always launched: its extra block writes the segment counts the ordering kernels read
+    TRIG_MARK("k_bounds", 0);
+    hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_bounds", 1);
     hipError_t e;
     if (b.sort_kernels & 1u) {
         TRIG_MARK("k_segsort_w", 0);

@@ -1,7 +1,6 @@
 // Device-side data structures and helpers of the trigger pipeline (gfx950).
 //
-// Pipeline of one batch of slices (every kernel covers all slices of the batch;
-// work counters are cleared by the host before the first kernel):
+// Pipeline of one batch of slices (every kernel covers all slices of the batch):
 //   k_ingest     per 1024-hit chunk: min/max time, max PMT, run starts
 //   k_plan       per slice: validation, t_min, run count, segment width, path and
 //                ordering-kernel kind
@@ -52,11 +51,10 @@ enum State : uint32_t {
     ST_DENSE = 4,         // trigger stage rerun with a precomputed seed mask
 };
 
-// Work-queue / counter slots in BatchDev::counters.
+// Slots in BatchDev::counters (written by k_bounds, read by the ordering kernels).
 enum Counter : int {
-    Q_SEG = 0,           // dequeue counter of k_segsort
-    Q_SEG_TOTAL = 1,     // number of segment items
-    Q_SEG_TOTAL_B = 5,   // number of segment items of the block-per-segment kernel
+    Q_SEG_TOTAL = 0,     // number of segment items of the wave-per-segment kernel
+    Q_SEG_TOTAL_B = 1,   // number of segment items of the block-per-segment kernel
     N_COUNTERS = 16,
 };
 
