@@ -43,8 +43,8 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint64_t k1 = (k0 + CHUNK < S.n) ? k0 + CHUNK : S.n;
     int64_t lo = INT64_MAX, hi = INT64_MIN;
     uint32_t pmax = 0, ns = 0;
-    const int64_t *tin = S.t;
-    const uint16_t *pin = S.pmt;
+    const TRIG_GAS int64_t *tin = gmem(S.t);
+    const TRIG_GAS uint16_t *pin = gmem(S.pmt);
     constexpr int PER = CHUNK / NT_ING;
     int64_t tv[PER], tp[PER];
     uint32_t pv[PER];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
         }
         ChunkPart cp;
         cp.t_min = lo; cp.t_max = hi; cp.pmt_max = pmax; cp.n_start = ns; cp.run_base = 0; cp.pad = 0;
-        S.part[c] = cp;
+        gstore(gmem(S.part) + c, cp);
     }
 }
 
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const uint32_t c = c0 + u * NT + threadIdx.x;
-                if (c < S.n_chunks) cp[u] = S.part[c];
+                if (c < S.n_chunks) cp[u] = gload(gmem(S.part) + c);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -140,14 +140,14 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             uint32_t v[RP], sum = 0;
 #pragma unroll
             for (int u = 0; u < RP; ++u) {
-                v[u] = (cb + u < S.n_chunks) ? S.part[cb + u].n_start : 0u;
+                v[u] = (cb + u < S.n_chunks) ? gmem(S.part)[cb + u].n_start : 0u;
                 sum += v[u];
             }
             uint32_t tot;
             uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
 #pragma unroll
             for (int u = 0; u < RP; ++u) {
-                if (cb + u < S.n_chunks) S.part[cb + u].run_base = run;
+                if (cb + u < S.n_chunks) gmem(S.part)[cb + u].run_base = run;
                 run += v[u];
             }
             runs += tot;
@@ -235,16 +235,17 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - S.chunk_base;
     if (c >= S.n_chunks) return;
-    const Plan P = *S.plan;
+    const Plan P = gload(gmem(S.plan));
     if (P.state != ST_FAST) return;
+    const TRIG_GAS int64_t *tin = gmem(S.t);
     __shared__ int64_t st[CHUNK + 2];
     __shared__ uint32_t sh[NT / 64 + 1];
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint32_t len = (uint32_t)((k0 + CHUNK < S.n) ? CHUNK : S.n - k0);
-    stage_copy<NT, PER>(st + 1, S.t + k0, len);
+    stage_copy<NT, PER>(st + 1, tin + k0, len);
     if (threadIdx.x == 0) {
-        st[0] = k0 ? S.t[k0 - 1] : INT64_MIN;
-        st[len + 1] = (k0 + len < S.n) ? S.t[k0 + len] : INT64_MIN;
+        st[0] = k0 ? tin[k0 - 1] : INT64_MIN;
+        st[len + 1] = (k0 + len < S.n) ? tin[k0 + len] : INT64_MIN;
     }
     __syncthreads();
     const uint32_t a = threadIdx.x * PER;
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const uint64_t R = P.n_runs;
     const uint32_t sft = P.shift;
     const int64_t tmin = P.t_min;
-    int64_t r = (int64_t)S.part[c].run_base + ex - 1;   // run of the element before a
+    int64_t r = (int64_t)gmem(S.part)[c].run_base + ex - 1;   // run of the element before a
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = a + e;
         if (i >= len) break;
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         const bool is_start = (k == 0) || (t < st[i]);
         const bool is_end = (k + 1 == S.n) || (st[i + 2] < t);
         if (is_start) ++r;
-        uint32_t *col = S.pos + r;
+        TRIG_GAS uint32_t *col = gmem(S.pos) + r;
         const uint32_t g = (uint32_t)((uint64_t)(t - tmin) >> sft);
         if (is_start) {
             for (uint32_t j = 0; j <= g; ++j) col[(uint64_t)j * R] = (uint32_t)k;
@@ -313,10 +314,10 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     const uint32_t first = blockIdx.x * per;
     const uint32_t end = (first + per < total) ? first + per : total;
     uint32_t si = 0, s_base = 1, s_end = 0;
-    const uint16_t *in_pmt = nullptr, *in_q = nullptr;
-    const int64_t *in_t = nullptr;
-    const uint32_t *pos = nullptr;
-    uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
+    const TRIG_GAS uint16_t *in_pmt = nullptr, *in_q = nullptr;
+    const TRIG_GAS int64_t *in_t = nullptr;
+    const TRIG_GAS uint32_t *pos = nullptr;
+    TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     uint32_t pbits = 0;
     Plan P = {};
     for (uint32_t item = first; item < end; ++item) {
@@ -324,8 +325,8 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base_b; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
-            in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
-            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx; pbits = S.pbits;
+            in_pmt = gmem(S.pmt); in_q = gmem(S.q); in_t = gmem(S.t); pos = gmem(S.pos);
+            o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx); pbits = S.pbits;
             s_base = P.seg_item_base_b;
             s_end = s_base + P.n_seg;
         }
@@ -551,18 +552,18 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     const uint32_t first = x0 + gw * per;
     const uint32_t end = (first + per < x1) ? first + per : x1;
     uint32_t si = 0, s_base = 1, s_end = 0;
-    const uint16_t *in_pmt = nullptr, *in_q = nullptr;
-    const int64_t *in_t = nullptr;
-    const uint32_t *pos = nullptr;
-    uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
+    const TRIG_GAS uint16_t *in_pmt = nullptr, *in_q = nullptr;
+    const TRIG_GAS int64_t *in_t = nullptr;
+    const TRIG_GAS uint32_t *pos = nullptr;
+    TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     Plan P = {};
     for (uint32_t item = first; item < end; ++item) {
         if (item < s_base || item >= s_end) {
             si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
-            in_pmt = S.pmt; in_q = S.q; in_t = S.t; pos = S.pos;
-            o_t = S.o_t; o_pq = S.o_pq; o_idx = S.o_idx;
+            in_pmt = gmem(S.pmt); in_q = gmem(S.q); in_t = gmem(S.t); pos = gmem(S.pos);
+            o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx);
             s_base = P.seg_item_base;
             s_end = s_base + P.n_seg;
         }

@@ -169,11 +169,21 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
     if (k >= S.n_tiles) return;
-    Plan *Pp = S.plan;
-    if (!slice_in_tail(b, Pp->state)) return;
+    Plan *Pp = S.plan;   // generic: the flag updates below are atomics
+    const TRIG_GAS Plan *Pg = gmem(Pp);
+    if (!slice_in_tail(b, Pg->state)) return;
+    // descriptor fields read once, as global-memory pointers
+    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
+    const TRIG_GAS uint32_t *o_pq = gmem(S.o_pq);
+    const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
+    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
+    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
+    const TRIG_GAS uint16_t *floor16 = gmem(S.floor16);
+    TRIG_GAS uint8_t *seed_flags = gmem(S.seed_flags);
+    const uint32_t n_pmt = S.n_pmt;
     const uint64_t n = S.n;
-    const int64_t t_min = Pp->t_min;
-    const uint64_t span = (uint64_t)(Pp->t_max - t_min);
+    const int64_t t_min = Pg->t_min;
+    const uint64_t span = (uint64_t)(Pg->t_max - t_min);
     const uint32_t W = b.prm.w_ns;
     const uint32_t N = b.prm.min_fold;
     const int32_t tau = b.prm.t_floor_ns;
@@ -198,13 +208,13 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
             if (x < len) {
-                vt[u] = S.o_t[sl + x];
-                vp[u] = S.o_pq[sl + x];
+                vt[u] = o_t[sl + x];
+                vp[u] = o_pq[sl + x];
             }
         }
         // the floor numbering (independent of the staged hits, so in flight with them)
-        if (!MASK && S.n_pmt <= floor_lds)
-            for (uint32_t x = threadIdx.x; x < S.n_pmt; x += NT) lfl[x] = S.floor16[x];
+        if (!MASK && n_pmt <= floor_lds)
+            for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
@@ -217,8 +227,10 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     __syncthreads();
     if (!MASK) {
         // each staged hit's floor, so the partner search reads one LDS word per side
-        const uint16_t *fl = S.n_pmt <= floor_lds ? lfl : S.floor16;
-        for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = fl[sp[x] >> 16];
+        if (n_pmt <= floor_lds)
+            for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = lfl[sp[x] >> 16];
+        else
+            for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = floor16[sp[x] >> 16];
         __syncthreads();
     }
     const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
         const uint32_t sub = threadIdx.x % G;
         for (uint32_t ci = ca + threadIdx.x / G; ci < cb; ci += NT / G) {
             const uint32_t t = ct[ci];
-            const uint64_t row = (uint64_t)cp[ci] * S.n_pmt;
+            const uint64_t row = (uint64_t)cp[ci] * n_pmt;
             const uint32_t t_lo = t > W ? t - W : 0u;
             const uint64_t t_hi = (uint64_t)t + W;
             uint32_t jl = 0, z = ci;          // first seed with time >= t - W
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                     if (j < jr && j != ci) {
                         const uint32_t tj = ct[j];
                         dd[u] = tj > t ? tj - t : t - tj;
-                        lim[u] = t16 ? (uint32_t)S.thr16[row + cp[j]] : S.thr32[row + cp[j]];
+                        lim[u] = t16 ? (uint32_t)thr16[row + cp[j]] : thr32[row + cp[j]];
                     }
                 }
 #pragma unroll
@@ -349,10 +361,10 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             for (int d = 1; d < G; d <<= 1) c += __shfl_xor(c, d, 64);
             if (sub == 0) fold[ci - ca] = c + 1;
         }
-        if (S.seed_flags) {
+        if (seed_flags) {
             for (uint64_t j = a + threadIdx.x; j < e; j += NT) {
                 const uint32_t x = (uint32_t)(j - sl);
-                S.seed_flags[S.o_idx[j]] = (uint8_t)((sbits[x / 64] >> (x % 64)) & 1ull);
+                seed_flags[o_idx[j]] = (uint8_t)((sbits[x / 64] >> (x % 64)) & 1ull);
             }
         }
     } else if (!MASK) {
@@ -368,11 +380,11 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             uint32_t tot;
             const uint32_t ex = block_excl_scan<NT>(seed ? 1u : 0u, tot, sh);
             if (seed) {
-                ct[acc + ex] = S.o_t[j];
-                cp[acc + ex] = (uint16_t)(S.o_pq[j] >> 16);
+                ct[acc + ex] = o_t[j];
+                cp[acc + ex] = (uint16_t)(o_pq[j] >> 16);
                 cidx[acc + ex] = (uint16_t)(j - a);
             }
-            if (j < e && S.seed_flags) S.seed_flags[S.o_idx[j]] = seed ? 1 : 0;
+            if (j < e && seed_flags) seed_flags[o_idx[j]] = seed ? 1 : 0;
             acc += tot;
         }
         __syncthreads();
@@ -383,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     __syncthreads();
     // fires of the tile in order, to the tile's scratch slot
     uint32_t nf = 0;
-    FireRec *slot = S.fsc + (uint64_t)k * TILE;
+    TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)k * TILE;
     for (uint32_t c0 = ca; c0 < cb; c0 += NT) {
         const uint32_t ci = c0 + threadIdx.x;
         const bool f = ci < cb && fold[ci - ca] >= N;
@@ -393,10 +405,10 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             fci[nf + ex] = (uint16_t)ci;
             FireRec fr;
             fr.t = ct[ci];
-            fr.hit = S.o_idx[cbase + cidx[ci]];
+            fr.hit = o_idx[cbase + cidx[ci]];
             fr.fold = fold[ci - ca];
             fr.pmt = cp[ci];
-            slot[nf + ex] = fr;
+            gstore(slot + nf + ex, fr);
         }
         nf += tot;
     }
@@ -444,7 +456,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     A.m_head = first_int == NO_START ? m_tail : m_head;
     A.ls_idx = last_int;
     if (last_int == NO_START) A.ls_t = 0;
-    if (lane == 0) S.tstat[k].agg = A;
+    if (lane == 0) gstore(&gmem(S.tstat)[k].agg, A);
 }
 
 // Per slice (1024 threads): exclusive scan of the tile summaries, counts, the
@@ -453,12 +465,13 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     constexpr int NTS = 1024, NWS = NTS / 64;
     const uint32_t si = blockIdx.x;
     const SliceDev &S = b.slices[si];
-    Plan *Pp = S.plan;
+    TRIG_GAS Plan *Pp = gmem(S.plan);
     const uint32_t state = Pp->state;
     if (!slice_in_tail(b, state)) {
-        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) b.x_plans[si] = *Pp;
+        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
         return;
     }
+    TRIG_GAS TileStat *tstat = gmem(S.tstat);
     __shared__ TileAgg wsum[NWS];
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const int lane = lane_id(), w = threadIdx.x >> 6;
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const uint32_t t0 = threadIdx.x * per;
     const uint32_t t1 = (t0 + per < nt) ? t0 + per : nt;
     TileAgg mine = agg_empty();
-    for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, S.tstat[t].agg, twoH);
+    for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, gload(&tstat[t].agg), twoH);
     // inclusive scan within the wave
     TileAgg inc = mine;
 #pragma unroll
@@ -482,8 +495,8 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const TileAgg ex_lane = agg_shfl_up(inc, 1);
     TileAgg P = agg_combine(before, lane ? ex_lane : agg_empty(), twoH);
     for (uint32_t t = t0; t < t1; ++t) {
-        const TileAgg A = S.tstat[t].agg;
-        S.tstat[t].pre = P;
+        const TileAgg A = gload(&tstat[t].agg);
+        gstore(&tstat[t].pre, P);
         P = agg_combine(P, A, twoH);
     }
     if (threadIdx.x != NTS - 1) return;
@@ -495,19 +508,21 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
         // the slice's last event ends at its last fire
         const uint32_t le = n_ev - 1, s0 = open_start(I);
         const int64_t tend = t_min + (int64_t)I.last_t + H;
-        S.events[le].t_end = tend;
-        S.events[le].n_fire = I.F - s0;
-        S.events[le].max_fold = I.m_tail;
+        TRIG_GAS trig_event *events = gmem(S.events);
+        events[le].t_end = tend;
+        events[le].n_fire = I.F - s0;
+        events[le].max_fold = I.m_tail;
         if (S.x_events && n_ev <= S.x_event_cap) {
-            S.x_events[le].t_end = tend;
-            S.x_events[le].n_fire = I.F - s0;
-            S.x_events[le].max_fold = I.m_tail;
+            TRIG_GAS trig_event *xe = gmem(S.x_events);
+            xe[le].t_end = tend;
+            xe[le].n_fire = I.F - s0;
+            xe[le].max_fold = I.m_tail;
         }
     }
     Pp->n_seeds = I.S;
     Pp->n_fires = I.F;
     Pp->n_events = n_ev;
-    if (b.x_plans) b.x_plans[si] = *Pp;
+    if (b.x_plans) gstore(gmem(b.x_plans) + si, gload(Pp));
 }
 
 // One wave per tile with fires: fire records and event halves at their places.
@@ -517,13 +532,16 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
     if (k >= S.n_tiles) return;
-    const Plan *Pp = S.plan;
+    const TRIG_GAS Plan *Pp = gmem(S.plan);
     if (!slice_in_tail(b, Pp->state)) return;
     if (Pp->dense && b.tail_state != ST_DENSE) return;   // this slice is rerun
-    const uint32_t nf = S.tstat[k].agg.F;
+    const TRIG_GAS TileStat *tstat = gmem(S.tstat);
+    const uint32_t nf = tstat[k].agg.F;
     if (nf == 0) return;
-    const TileAgg P = S.tstat[k].pre;
-    const FireRec *slot = S.fsc + (uint64_t)k * TILE;
+    const TileAgg P = gload(&tstat[k].pre);
+    const TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)k * TILE;
+    TRIG_GAS trig_fire *fires = gmem(S.fires);
+    TRIG_GAS trig_event *events = gmem(S.events);
     const int lane = lane_id();
     const int64_t t_min = Pp->t_min;
     const int64_t H = (int64_t)b.prm.half_event_ns;
@@ -532,8 +550,8 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const uint32_t p_open = open_start(P);
     // host-mapped staging only when the whole list fits it (else the host copies
     // the list from device memory)
-    trig_fire *xf = (S.x_fires && Pp->n_fires <= S.x_fire_cap) ? S.x_fires : nullptr;
-    trig_event *xe = (S.x_events && Pp->n_events <= S.x_event_cap) ? S.x_events : nullptr;
+    TRIG_GAS trig_fire *xf = (S.x_fires && Pp->n_fires <= S.x_fire_cap) ? gmem(S.x_fires) : nullptr;
+    TRIG_GAS trig_event *xe = (S.x_events && Pp->n_events <= S.x_event_cap) ? gmem(S.x_events) : nullptr;
     uint32_t carry_starts = 0;                       // starts among earlier fires of the tile
     int32_t carry_latest = -1;                       // local index of the latest start, -1: none
     uint32_t carry_max = P.F ? P.m_tail : 0u;        // largest fold of the open event so far
@@ -542,7 +560,7 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
         const uint32_t r = r0 + lane;
         const bool v = r < nf;
         FireRec fr = {0, 0, 0, 0};
-        if (v) fr = slot[r];
+        if (v) fr = gload(slot + r);
         const uint32_t t = fr.t, fd = fr.fold;
         const uint32_t tpl = __shfl_up(t, 1, 64);
         const uint32_t tp = lane == 0 ? prev_t : tpl;
@@ -575,11 +593,11 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
             out.pmt_id = (uint16_t)fr.pmt;
             out.pad[0] = out.pad[1] = out.pad[2] = 0;
             const uint32_t g = P.F + r;
-            S.fires[g] = out;
-            if (xf) xf[g] = out;
+            gstore(fires + g, out);
+            if (xf) gstore(xf + g, out);
             if (st) {
-                S.events[ev].t_trig = out.t_ns;
-                S.events[ev].t_begin = out.t_ns - H;
+                events[ev].t_trig = out.t_ns;
+                events[ev].t_begin = out.t_ns - H;
                 if (xe) {
                     xe[ev].t_trig = out.t_ns;
                     xe[ev].t_begin = out.t_ns - H;
@@ -588,9 +606,9 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
                     // this fire ends the event left open by the preceding tiles
                     const uint32_t pe = EP - 1;
                     const int64_t tend = t_min + (int64_t)P.last_t + H;
-                    S.events[pe].t_end = tend;
-                    S.events[pe].n_fire = P.F - p_open;
-                    S.events[pe].max_fold = P.m_tail;
+                    events[pe].t_end = tend;
+                    events[pe].n_fire = P.F - p_open;
+                    events[pe].max_fold = P.m_tail;
                     if (xe) {
                         xe[pe].t_end = tend;
                         xe[pe].n_fire = P.F - p_open;
@@ -602,9 +620,9 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
             if (r + 1 < nf && (uint64_t)(slot[r + 1].t - t) > twoH) {
                 const uint32_t sg = latest >= 0 ? P.F + (uint32_t)latest : p_open;
                 const int64_t tend = out.t_ns + H;
-                S.events[ev].t_end = tend;
-                S.events[ev].n_fire = P.F + r - sg + 1;
-                S.events[ev].max_fold = mv;
+                events[ev].t_end = tend;
+                events[ev].n_fire = P.F + r - sg + 1;
+                events[ev].max_fold = mv;
                 if (xe) {
                     xe[ev].t_end = tend;
                     xe[ev].n_fire = P.F + r - sg + 1;
@@ -641,8 +659,8 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     if (a >= n) return;
     const uint64_t lo = a >= (uint64_t)DSH ? a - DSH : 0;
     const uint64_t hi = (a + TILE + DSH < n) ? a + TILE + DSH : n;
-    stage_copy<NTD, 5>(lt, S.o_t + lo, (uint32_t)(hi - lo));
-    stage_copy<NTD, 5>(lpq, S.o_pq + lo, (uint32_t)(hi - lo));
+    stage_copy<NTD, 5>(lt, gmem(S.o_t) + lo, (uint32_t)(hi - lo));
+    stage_copy<NTD, 5>(lpq, gmem(S.o_pq) + lo, (uint32_t)(hi - lo));
     __syncthreads();
     auto T_at = [&](uint64_t m) -> uint32_t { return (m >= lo && m < hi) ? lt[m - lo] : S.o_t[m]; };
     auto P_at = [&](uint64_t m) -> uint32_t { return ((m >= lo && m < hi) ? lpq[m - lo] : S.o_pq[m]) >> 16; };

@@ -161,6 +161,31 @@ struct BatchDev {
 
 // ------------------------------------------------------------------ helpers
 
+// Global-memory views of pointers read from descriptors.  Pointers loaded from
+// memory are generic, and generic (flat) accesses count against the LDS wait
+// counter too; through these views loads and stores compile to global
+// instructions, so waiting on LDS does not wait on HBM.
+#define TRIG_GAS __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ TRIG_GAS T *gmem(T *p) { return (TRIG_GAS T *)p; }
+template <class T> __device__ __forceinline__ const TRIG_GAS T *gmem(const T *p) { return (const TRIG_GAS T *)p; }
+// Whole-struct copies through such pointers, a word at a time.
+template <class T> __device__ __forceinline__ T gload(const TRIG_GAS T *p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+    T v;
+    uint32_t *d = (uint32_t *)&v;
+    const TRIG_GAS uint32_t *s = (const TRIG_GAS uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+    return v;
+}
+template <class T> __device__ __forceinline__ void gstore(TRIG_GAS T *p, const T &v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+    const uint32_t *s = (const uint32_t *)&v;
+    TRIG_GAS uint32_t *d = (TRIG_GAS uint32_t *)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = s[i];
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -225,7 +250,7 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t *a, uint32_t len, 
 // Cooperative copy src[0..n) -> dst[0..n) by one block with U loads in flight
 // per thread before any store (a plain strided loop waits for every load).
 template <int NT, int U, class T, class Tr>
-__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n, Tr tr) {
+__device__ __forceinline__ void stage_copy(T *dst, const TRIG_GAS T *src, uint32_t n, Tr tr) {
     for (uint32_t b0 = 0; b0 < n; b0 += NT * U) {
         T v[U];
 #pragma unroll
@@ -242,7 +267,7 @@ __device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n, Tr 
 }
 
 template <int NT, int U, class T>
-__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n) {
+__device__ __forceinline__ void stage_copy(T *dst, const TRIG_GAS T *src, uint32_t n) {
     stage_copy<NT, U>(dst, src, n, [](T x) { return x; });
 }
 
