@@ -186,8 +186,12 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     return o;
 }
 
+// Descriptors, then the per-slice chunk and tile bases (two dense arrays that the
+// kernels binary-search), then plans and counters.
+static size_t desc_upload_bytes(uint32_t n) { return n * sizeof(SliceDev) + 2 * (size_t)n * sizeof(uint32_t); }
+
 size_t job_meta_bytes(uint32_t n) {
-    return align256(n * sizeof(SliceDev)) + align256(n * sizeof(Plan)) + 256;
+    return align256(desc_upload_bytes(n)) + align256(n * sizeof(Plan)) + 256;
 }
 
 size_t slice_footprint(uint64_t n, bool host_input) {
@@ -281,7 +285,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     if (rc) return rc;
     rc = dmeta.ensure(c, desc_bytes, s);
     if (rc) return rc;
-    if (h_slices.ensure(n * sizeof(SliceDev) + 64) || h_plans.ensure(xs + 64)) {
+    if (h_slices.ensure(desc_upload_bytes(n) + 64) || h_plans.ensure(xs + 64)) {
         ctx_set_error(c, "pinned host allocation failed");
         return TRIG_ENOMEM;
     }
@@ -292,7 +296,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         x_plans_dev = (Plan *)dp;
     }
     d_slices = (SliceDev *)dmeta.ptr;
-    d_plans = (Plan *)((char *)dmeta.ptr + align256(n * sizeof(SliceDev)));
+    d_plans = (Plan *)((char *)dmeta.ptr + align256(desc_upload_bytes(n)));
     // (the counters are written by k_bounds before any kernel reads them)
     d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
     SliceDev *hs = (SliceDev *)h_slices.ptr;
@@ -364,17 +368,25 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     // the previous round on this job has completed (every entry point synchronises
     // before it returns), so the device copy of an unchanged set is intact
-    if (up_ptr != dmeta.ptr || up_cap != dmeta.cap || up_slices.size() != n ||
-        std::memcmp(up_slices.data(), hs, n * sizeof(SliceDev)) != 0) {
+    uint32_t *hbases = (uint32_t *)(hs + n);
+    for (uint32_t i = 0; i < n; ++i) {
+        hbases[i] = slices[i].chunk_base;
+        hbases[n + i] = slices[i].tile_base;
+    }
+    const size_t up_bytes = desc_upload_bytes(n);
+    if (up_ptr != dmeta.ptr || up_cap != dmeta.cap || up_slices.size() != up_bytes ||
+        std::memcmp(up_slices.data(), hs, up_bytes) != 0) {
         up_ptr = nullptr;
-        hipError_t e = hipMemcpyAsync(d_slices, hs, n * sizeof(SliceDev), hipMemcpyHostToDevice, s);
+        hipError_t e = hipMemcpyAsync(d_slices, hs, up_bytes, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return hip_fail(c, e, "H2D of slice descriptors");
-        up_slices.assign(hs, hs + n);
+        up_slices.assign((const unsigned char *)hs, (const unsigned char *)hs + up_bytes);
         up_ptr = dmeta.ptr;
         up_cap = dmeta.cap;
     }
     batch = {};
     batch.slices = d_slices;
+    batch.chunk_bases = (const uint32_t *)(d_slices + n);
+    batch.tile_bases = batch.chunk_bases + n;
     batch.plans = d_plans;
     batch.n_slices = n;
     batch.total_chunks = total_chunks;

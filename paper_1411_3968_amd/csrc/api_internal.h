@@ -72,7 +72,7 @@ struct Job {
     uint32_t *d_counters = nullptr;
     // the descriptors last uploaded and the device buffer that holds them: an
     // unchanged set is not uploaded again
-    std::vector<trigdev::SliceDev> up_slices;
+    std::vector<unsigned char> up_slices;
     const void *up_ptr = nullptr;
     size_t up_cap = 0;
     trigdev::BatchDev batch;

@@ -35,7 +35,7 @@ __device__ __forceinline__ uint32_t wave_sumu(uint32_t v) {
 // (position 0 and every position whose time is below its predecessor's).
 __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].chunk_base; });
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - S.chunk_base;
     if (c >= S.n_chunks) return;
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         build_segment_lists(b);
         return;
     }
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].chunk_base; });
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - S.chunk_base;
     if (c >= S.n_chunks) return;

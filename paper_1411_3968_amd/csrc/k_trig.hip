@@ -106,6 +106,11 @@ __device__ __forceinline__ TileAgg agg_shfl_up(const TileAgg &a, int d) {
     return r;
 }
 
+// Staged words pmt << 16 | floor: another PMT on the same floor.
+__device__ __forceinline__ bool floor_partner(uint32_t a, uint32_t b) {
+    return (a >> 16) != (b >> 16) && (a & 0xFFFFu) == (b & 0xFFFFu);
+}
+
 __device__ __forceinline__ bool mask_bit(const SliceDev &S, uint64_t j) { return (S.dmask[j >> 6] >> (j & 63)) & 1ull; }
 
 __device__ __forceinline__ uint32_t lim_global(const SliceDev &S, uint32_t W, uint32_t p, uint32_t q) {
@@ -146,16 +151,15 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     constexpr int CS = compact_cap(HMAX, MASK);      // seeds of a stage the compacted lists hold
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *st = (uint32_t *)smem;                 // staged t - t_min
-    uint32_t *sp = st + STG;                         // staged pmt << 16 | q
-    uint32_t *ct = sp + STG;                         // compacted seeds: time
+    uint32_t *spf = st + STG;                        // staged pmt << 16 | dense floor index
+    uint32_t *ct = spf + STG;                        // compacted seeds: time
     uint32_t *fold = ct + CS;                        // fold of each seed of the tile
     uint64_t *sbits = (uint64_t *)(fold + CS);       // seed bits of the stage
     uint32_t *wpre = (uint32_t *)(sbits + STG / 64); // seeds before each 64-hit word
     uint16_t *cp = (uint16_t *)(wpre + STG / 64 + 1);   // compacted seeds: PMT
     uint16_t *cidx = cp + CS;                        // compacted seeds: stage position
     uint16_t *fci = cidx + CS;                       // fires: compacted index
-    uint16_t *sfl = fci + CS;                        // staged hits' dense floor index
-    uint16_t *lfl = sfl + STG;                       // dense floor index of every PMT (floor_lds of them)
+    uint16_t *lfl = fci + CS;                        // dense floor index of every PMT (floor_lds of them)
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
 
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const uint32_t per_xcd = (b.total_tiles + 7) / 8;
     const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (item >= b.total_tiles) return;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
     if (k >= S.n_tiles) return;
@@ -200,8 +204,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const uint64_t sl = a > halo ? a - halo : 0;
     const uint64_t sh_end = (e + halo < n) ? e + halo : n;
     const uint32_t len = (uint32_t)(sh_end - sl);
+    const uint32_t q_seed = b.prm.q_seed;
     {
-        // stage both arrays with all loads of a thread in flight
+        // stage the times and PMTs with all loads of a thread in flight
         constexpr int U = (STG + NT - 1) / NT;
         uint32_t vt[U], vp[U];
 #pragma unroll
@@ -218,21 +223,27 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
+            if (x < len) st[x] = vt[u];
+            if (!MASK) {
+                // charge seeds of the stage, a word per wave (the floor coincidences
+                // are added below); x / 64 is this wave's word
+                const uint64_t qb = __ballot(x < len && (vp[u] & 0xFFFFu) >= q_seed);
+                if (lane == 0 && u * NT + w * 64 < len) sbits[(u * NT) / 64 + w] = qb;
+            }
+        }
+        if (!MASK) __syncthreads();   // floor numbering complete
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
             if (x < len) {
-                st[x] = vt[u];
-                sp[x] = vp[u];
+                const uint32_t p = vp[u] >> 16;
+                uint32_t f = 0;
+                if (!MASK) f = n_pmt <= floor_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
+                spf[x] = (p << 16) | f;
             }
         }
     }
     __syncthreads();
-    if (!MASK) {
-        // each staged hit's floor, so the partner search reads one LDS word per side
-        if (n_pmt <= floor_lds)
-            for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = lfl[sp[x] >> 16];
-        else
-            for (uint32_t x = threadIdx.x; x < len; x += NT) sfl[x] = floor16[sp[x] >> 16];
-        __syncthreads();
-    }
     const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
     // the stage spans the window of every seed of the tile when the halo reaches
     // past w_ns + t_floor_ns on both sides (or the slice ends there)
@@ -248,26 +259,36 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
         for (uint32_t x0 = 0; x0 < len; x0 += NT) {
             const uint32_t x = x0 + threadIdx.x;
             bool seed = false;
-            if (x < len && MASK) {
-                seed = mask_bit(S, sl + x);
-            } else if (x < len) {
-                const uint32_t pq = sp[x];
-                seed = (pq & 0xFFFFu) >= b.prm.q_seed;
-                if (!seed && tau >= 0) {
-                    // neighbours at distance d on both sides together, so each step
-                    // waits on one round of independent LDS reads
-                    const uint32_t t = st[x], p = pq >> 16, f = sfl[x];
-                    for (uint32_t d = 1;; ++d) {
-                        const bool l_in = x >= d && t - st[x - d] <= (uint32_t)tau;
-                        const bool r_in = x + d < len && st[x + d] - t <= (uint32_t)tau;
-                        if (!l_in && !r_in) break;
-                        if (l_in && (sp[x - d] >> 16) != p && sfl[x - d] == f) { seed = true; break; }
-                        if (r_in && (sp[x + d] >> 16) != p && sfl[x + d] == f) { seed = true; break; }
+            if (MASK) {
+                seed = x < len && mask_bit(S, sl + x);
+            } else if (tau >= 0 && x < len) {
+                // floor coincidence: a hit of another PMT on the same floor within
+                // t_floor_ns.  The nearest neighbours on both sides are read together;
+                // a hit with a closer non-partner looks further.
+                const uint32_t xl = x ? x - 1 : 0, xr = x + 1 < len ? x + 1 : x;
+                const uint32_t t = st[x], f = spf[x];
+                const uint32_t tl = st[xl], fl = spf[xl], tr = st[xr], fr = spf[xr];
+                // (bitwise operators: no branch between the reads and their use)
+                const bool l_in = (x >= 1) & (t - tl <= tau_u);
+                const bool r_in = (x + 1 < len) & (tr - t <= tau_u);
+                seed = (l_in & floor_partner(fl, f)) | (r_in & floor_partner(fr, f));
+                if (!seed && (l_in || r_in)) {
+                    for (uint32_t d = 2;; ++d) {
+                        const bool ll = x >= d && t - st[x - d] <= tau_u;
+                        const bool rr = x + d < len && st[x + d] - t <= tau_u;
+                        if (!ll && !rr) break;
+                        if ((ll && floor_partner(spf[x - d], f)) || (rr && floor_partner(spf[x + d], f))) {
+                            seed = true;
+                            break;
+                        }
                     }
                 }
             }
             const uint64_t bal = __ballot(seed);
-            if (lane == 0) sbits[x0 / 64 + w] = bal;
+            if (lane == 0 && x0 + w * 64 < len) {
+                if (MASK) sbits[x0 / 64 + w] = bal;
+                else sbits[x0 / 64 + w] |= bal;
+            }
         }
         __syncthreads();
         const uint32_t nwords = (len + 63) / 64;
@@ -309,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             if ((word >> bit) & 1ull) {
                 const uint32_t r = wpre[x / 64] + (uint32_t)__popcll(bit ? word & (~0ull >> (64 - bit)) : 0ull);
                 ct[r] = st[x];
-                cp[r] = (uint16_t)(sp[x] >> 16);
+                cp[r] = (uint16_t)(spf[x] >> 16);
                 cidx[r] = (uint16_t)x;
             }
         }
@@ -528,7 +549,7 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
 // One wave per tile with fires: fire records and event halves at their places.
 __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
     if (k >= S.n_tiles) return;
@@ -646,7 +667,7 @@ constexpr int NTD = 256;
 
 __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.slices[i].tile_base; });
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - S.tile_base;
     if (k >= S.n_tiles) return;
@@ -697,7 +718,7 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
 template <int HMAX, bool MASK>
 constexpr size_t tile_lds_bytes() {
     constexpr size_t STG = TILE + 2 * HMAX, CS = compact_cap(HMAX, MASK);
-    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + CS * 2 * 3 + STG * 2;
+    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + CS * 2 * 3;
 }
 
 template <int NT, int HMAX, bool MASK>

@@ -147,6 +147,7 @@ struct SliceDev {
 
 struct BatchDev {
     SliceDev *slices;
+    const uint32_t *chunk_bases, *tile_bases;   // per slice: first chunk / first tile (dense copies)
     Plan *plans;
     uint32_t n_slices;
     uint32_t total_chunks;
