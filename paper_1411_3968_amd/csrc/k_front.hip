@@ -10,26 +10,18 @@ namespace {
 
 constexpr int NT_ING = 256;
 
+__device__ __forceinline__ int64_t lane_read_i64(int64_t v, int src) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)lane_read((uint32_t)(u >> 32), src) << 32) | lane_read((uint32_t)u, src));
+}
 __device__ __forceinline__ int64_t wave_min64(int64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) { int64_t u = __shfl_xor(v, d, 64); v = u < v ? u : v; }
-    return v;
+    return lane_read_i64(wave_scan(v, (int64_t)INT64_MAX, [](int64_t a, int64_t b) { return a < b ? a : b; }), 63);
 }
 __device__ __forceinline__ int64_t wave_max64(int64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) { int64_t u = __shfl_xor(v, d, 64); v = u > v ? u : v; }
-    return v;
+    return lane_read_i64(wave_scan(v, (int64_t)INT64_MIN, [](int64_t a, int64_t b) { return a > b ? a : b; }), 63);
 }
-__device__ __forceinline__ uint32_t wave_maxu(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) { uint32_t u = __shfl_xor(v, d, 64); v = u > v ? u : v; }
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_sumu(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
+__device__ __forceinline__ uint32_t wave_maxu(uint32_t v) { return wave_max_all(v); }
+__device__ __forceinline__ uint32_t wave_sumu(uint32_t v) { return wave_total(v); }
 
 // Per chunk of CHUNK input hits: time range, largest PMT id, run starts
 // (position 0 and every position whose time is below its predecessor's).
@@ -518,21 +510,7 @@ struct WaveSeg {
     uint16_t bbase[256];
 };
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v = u > v ? u : v;
-    }
-    return v;
-}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total(v); }
 
 __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     constexpr int EG = WAVE_CAP / 64;
@@ -593,7 +571,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 sm.run_lo[r] = lo[i];
                 sm.run_base[r] = m + incl - c;
             }
-            m += __shfl(incl, 63, 64);
+            m += lane_read(incl, 63);
             gpart += lo[i] - st[i];
         }
         const uint32_t goff = wave_sum_u32(gpart);
@@ -620,12 +598,12 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             rr[e] = k < m ? (uint32_t)sm.aux[k] : 0u;
         }
 #pragma unroll
-        for (int e = 0; e < EG; ++e) rr[e] = wave_incl_max(rr[e]);
+        for (int e = 0; e < EG; ++e) rr[e] = wave_incl_max_u32(rr[e]);
         {
             uint32_t carry = 0;
 #pragma unroll
             for (int e = 0; e < EG; ++e) {
-                const uint32_t last = __shfl(rr[e], 63, 64);
+                const uint32_t last = lane_read(rr[e], 63);
                 rr[e] = rr[e] > carry ? rr[e] : carry;
                 carry = last > carry ? last : carry;
             }

@@ -41,11 +41,7 @@ __host__ __device__ constexpr int compact_cap(int hmax, bool mask) { return mask
 
 __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b ? a : b; }
 
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = umax(v, __shfl_xor(v, d, 64));
-    return v;
-}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) { return wave_max_all(v); }
 
 __device__ __forceinline__ TileAgg agg_empty() {
     TileAgg a;
@@ -92,19 +88,6 @@ __device__ __forceinline__ TileAgg agg_combine(const TileAgg &A, const TileAgg &
 // a prefix summary.
 __device__ __forceinline__ uint32_t open_start(const TileAgg &P) { return P.ls_idx == NO_START ? 0u : P.ls_idx; }
 
-__device__ __forceinline__ TileAgg agg_shfl_up(const TileAgg &a, int d) {
-    TileAgg r;
-    r.F = __shfl_up(a.F, d, 64);
-    r.S = __shfl_up(a.S, d, 64);
-    r.E_int = __shfl_up(a.E_int, d, 64);
-    r.first_t = __shfl_up(a.first_t, d, 64);
-    r.last_t = __shfl_up(a.last_t, d, 64);
-    r.m_head = __shfl_up(a.m_head, d, 64);
-    r.m_tail = __shfl_up(a.m_tail, d, 64);
-    r.ls_idx = __shfl_up(a.ls_idx, d, 64);
-    r.ls_t = __shfl_up(a.ls_t, d, 64);
-    return r;
-}
 
 // Staged words pmt << 16 | floor: another PMT on the same floor.
 __device__ __forceinline__ bool floor_partner(uint32_t a, uint32_t b) {
@@ -300,7 +283,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                 const uint32_t c = wd < nwords ? (uint32_t)__popcll(sbits[wd]) : 0u;
                 const uint32_t inc = wave_incl_scan(c);
                 if (wd < nwords) wpre[wd] = tot + inc - c;
-                tot += __shfl(inc, 63, 64);
+                tot += lane_read(inc, 63);
             }
             if (lane == 0) {
                 wpre[nwords] = tot;
@@ -378,8 +361,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
 #pragma unroll
                 for (int u = 0; u < CB; ++u) c += dd[u] <= (lim[u] < W ? lim[u] : W);
             }
-#pragma unroll
-            for (int d = 1; d < G; d <<= 1) c += __shfl_xor(c, d, 64);
+            // sum over the G = 4 lanes of the seed (quad permutations: lane ^ 1, lane ^ 2)
+            c += dpp_u32<0xB1, 0xF>(0u, c);
+            c += dpp_u32<0x4E, 0xF>(0u, c);
             if (sub == 0) fold[ci - ca] = c + 1;
         }
         if (seed_flags) {
@@ -449,12 +433,14 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             t = ct[ci];
             fd = fold[ci - ca];
         }
-        const uint32_t tpl = __shfl_up(t, 1, 64);
-        const uint32_t tp = lane == 0 ? prev_t : tpl;
+        // the lane move runs in every lane (under a select it would run with lane 0
+        // masked off, and lane 1 would read the fill value)
+        const uint32_t t_below = wave_shr1(t, 0u);
+        const uint32_t tp = lane == 0 ? prev_t : t_below;
         const bool is_int = v && r > 0 && (uint64_t)(t - tp) > twoH;
         const uint64_t ib = __ballot(is_int);
-        if (r0 == 0) A.first_t = __shfl(t, 0, 64);
-        prev_t = __shfl(t, 63, 64);
+        if (r0 == 0) A.first_t = lane_read(t, 0);
+        prev_t = lane_read(t, 63);
         if (ib) {
             const int lo = __ffsll((unsigned long long)ib) - 1;
             const int hi = 63 - __clzll((long long)ib);
@@ -464,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             }
             last_int = r0 + hi;
             m_tail = wave_max_u32(v && lane >= hi ? fd : 0u);
-            A.ls_t = __shfl(t, hi, 64);
+            A.ls_t = lane_read(t, hi);
         } else {
             const uint32_t mx = wave_max_u32(v ? fd : 0u);
             if (first_int == NO_START) m_head = umax(m_head, mx);
@@ -503,18 +489,12 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     TileAgg mine = agg_empty();
     for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, gload(&tstat[t].agg), twoH);
     // inclusive scan within the wave
-    TileAgg inc = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const TileAgg o = agg_shfl_up(inc, d);
-        if (lane >= d) inc = agg_combine(o, inc, twoH);
-    }
+    const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     TileAgg before = agg_empty();   // waves before this one
     for (int i = 0; i < w; ++i) before = agg_combine(before, wsum[i], twoH);
-    const TileAgg ex_lane = agg_shfl_up(inc, 1);
-    TileAgg P = agg_combine(before, lane ? ex_lane : agg_empty(), twoH);
+    TileAgg P = agg_combine(before, wave_shr1(inc, agg_empty()), twoH);
     for (uint32_t t = t0; t < t1; ++t) {
         const TileAgg A = gload(&tstat[t].agg);
         gstore(&tstat[t].pre, P);
@@ -545,6 +525,11 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     Pp->n_events = n_ev;
     if (b.x_plans) gstore(gmem(b.x_plans) + si, gload(Pp));
 }
+
+// Segmented max: (a segment starts here, running max since the last start).
+struct SegMax {
+    uint32_t f, v;
+};
 
 // One wave per tile with fires: fire records and event halves at their places.
 __global__ __launch_bounds__(64) void k_place(BatchDev b) {
@@ -583,8 +568,10 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
         FireRec fr = {0, 0, 0, 0};
         if (v) fr = gload(slot + r);
         const uint32_t t = fr.t, fd = fr.fold;
-        const uint32_t tpl = __shfl_up(t, 1, 64);
-        const uint32_t tp = lane == 0 ? prev_t : tpl;
+        // the lane move runs in every lane (under a select it would run with lane 0
+        // masked off, and lane 1 would read the fill value)
+        const uint32_t t_below = wave_shr1(t, 0u);
+        const uint32_t tp = lane == 0 ? prev_t : t_below;
         const bool first_of_slice = r == 0 && P.F == 0;
         const bool st = v && (first_of_slice || (uint64_t)(t - tp) > twoH);
         const uint64_t sb = __ballot(st);
@@ -593,18 +580,19 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
         const uint64_t sbu = sb & upto;
         const int32_t latest = sbu ? (int32_t)(r0 + 63 - __clzll((long long)sbu)) : carry_latest;
         // segmented inclusive max of the folds (segments begin at starts)
-        uint32_t mv = fd;
-        bool mf = st;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t ov = __shfl_up(mv, d, 64);
-            const bool of = __shfl_up(mf ? 1 : 0, d, 64) != 0;
-            if (lane >= d && !mf) {
-                mv = umax(mv, ov);
-                mf = of;
-            }
-        }
-        if (!mf) mv = umax(mv, carry_max);
+        SegMax sm0;
+        sm0.f = st ? 1u : 0u;
+        sm0.v = fd;
+        SegMax id0;
+        id0.f = id0.v = 0;
+        const SegMax sx = wave_scan(sm0, id0, [](const SegMax &x, const SegMax &y) {
+            SegMax z;
+            z.f = x.f | y.f;
+            z.v = y.f ? y.v : umax(x.v, y.v);
+            return z;
+        });
+        uint32_t mv = sx.v;
+        if (!sx.f) mv = umax(mv, carry_max);
         const uint32_t ev = EP + starts_incl - 1;   // event of fire r
         if (v) {
             trig_fire out;
@@ -651,10 +639,10 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
                 }
             }
         }
-        carry_starts = __shfl(starts_incl, 63, 64);
-        carry_latest = __shfl(latest, 63, 64);
-        carry_max = __shfl(mv, 63, 64);
-        prev_t = __shfl(t, 63, 64);
+        carry_starts = lane_read(starts_incl, 63);
+        carry_latest = (int32_t)lane_read((uint32_t)latest, 63);
+        carry_max = lane_read(mv, 63);
+        prev_t = lane_read(t, 63);
     }
 }
 

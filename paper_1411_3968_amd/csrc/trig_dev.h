@@ -189,15 +189,60 @@ template <class T> __device__ __forceinline__ void gstore(TRIG_GAS T *p, const T
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = lane_id();
+// ---- wave-wide scans on DPP lane moves (VALU, no LDS round trip).  A move
+// reads a 32-bit word from another lane of the wave; lanes whose source is out
+// of range, or whose 16-lane row is masked off, receive `id`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t id, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)id, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+
+template <int CTRL, int ROW_MASK, class T>
+__device__ __forceinline__ T dpp_words(const T &id, const T &v) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized values only");
+    T r;
+    const uint32_t *pi = (const uint32_t *)&id;
+    const uint32_t *pv = (const uint32_t *)&v;
+    uint32_t *pr = (uint32_t *)&r;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) pr[i] = dpp_u32<CTRL, ROW_MASK>(pi[i], pv[i]);
+    return r;
+}
+
+// Inclusive scan over the 64 lanes under an associative `op(earlier, later)`
+// with left identity `id`: shifts by 1, 2, 4 and 8 lanes within each row, then
+// the last lane of row 0 (2) into row 1 (3), then lane 31 into rows 2 and 3.
+template <class T, class Op>
+__device__ __forceinline__ T wave_scan(T v, const T &id, Op op) {
+    v = op(dpp_words<0x111, 0xF>(id, v), v);   // row_shr:1
+    v = op(dpp_words<0x112, 0xF>(id, v), v);   // row_shr:2
+    v = op(dpp_words<0x114, 0xF>(id, v), v);   // row_shr:4
+    v = op(dpp_words<0x118, 0xF>(id, v), v);   // row_shr:8
+    v = op(dpp_words<0x142, 0xA>(id, v), v);   // row_bcast:15 into rows 1, 3
+    v = op(dpp_words<0x143, 0xC>(id, v), v);   // row_bcast:31 into rows 2, 3
     return v;
 }
+
+// Value of the lane below (lane 0 receives id).  Like every lane move here it
+// must run with all lanes active: a lane masked off reads as id.
+template <class T>
+__device__ __forceinline__ T wave_shr1(const T &v, const T &id) { return dpp_words<0x138, 0xF>(id, v); }
+
+// Value of lane `src` (uniform) in every lane.
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    return wave_scan(v, 0u, [](uint32_t a, uint32_t b) { return a + b; });
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
+    return wave_scan(v, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+}
+
+__device__ __forceinline__ uint32_t wave_total(uint32_t v) { return lane_read(wave_incl_scan(v), 63); }
+__device__ __forceinline__ uint32_t wave_max_all(uint32_t v) { return lane_read(wave_incl_max_u32(v), 63); }
 
 // Exclusive scan over the block; sh needs NT/64 + 1 words.  Ends with a barrier.
 template <int NT>
