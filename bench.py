@@ -143,7 +143,9 @@ def bench_batch(T, torch, dev, a):
                 speedup_vs_per_slice=round(el_loop / el, 3), results_equal_per_slice=bool(same),
                 fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1),
                 autotune=dict({k: tuned["best"][k] for k in ("seg_cap", "seg_target", "grid_per_cu")},
-                              candidates=len(tuned["trials"]), seconds=round(tuned["seconds"], 1)))
+                              candidates=len(tuned["trials"]), seconds=round(tuned["seconds"], 1),
+                              trials_ms=[[t["seg_cap"], t["seg_target"], t["grid_per_cu"], round(t["s"] * 1e3, 3)]
+                                         for t in tuned["trials"]]))
 
 
 def bench_serving(T, torch, dev, a):

@@ -207,8 +207,12 @@ int trig_stream_stats_get(trig_ctx *ctx, trig_stream_stats *out);
 /* Tuning knobs of the device pipeline, per PMT-count class.  Chosen by the
  * autotuner; defaults are used until set.
  *   seg_target    expected hits per time segment of the ordering stage
- *   seg_cap       LDS capacity of one segment (2048, 4096 or 8192)
- *   grid_per_cu   persistent workgroups per compute unit */
+ *   seg_cap       hits one segment may hold: 256 or 512 order each segment
+ *                 with one wave (256: fewer registers and LDS per wave, more
+ *                 waves in flight), 2048, 4096 or 8192 with one workgroup
+ *   grid_per_cu   persistent workgroups per compute unit
+ * trig_tune_set returns TRIG_EINVAL for other capacities, a zero target or a
+ * grid_per_cu outside 1..16. */
 typedef struct {
     uint32_t seg_target;
     uint32_t seg_cap;

@@ -1,8 +1,8 @@
 """Autotuner of the ordering stage's launch parameters.
 
 The knobs (``trig_tune``): the ordering kernel and its LDS capacity per time
-segment (512 hits: one wave per segment; 2048, 4096 or 8192 hits: one workgroup
-per segment, compiled variants), the expected hits per segment (which sets the
+segment (256 or 512 hits: one wave per segment; 2048, 4096 or 8192 hits: one
+workgroup per segment, compiled variants), the expected hits per segment (which sets the
 segment width 2^s ns of a slice from its density), and the number of persistent
 workgroups per compute unit.  Each PMT-count class is tuned on representative
 slices by timing the whole pipeline (``trig_batch`` with marshalling done once),
@@ -20,9 +20,11 @@ import numpy as np
 from . import trig as T
 
 WAVE_CAP = 512
+WAVE_CAP_SMALL = 256
 
 DEFAULT_CANDIDATES = (
     [(WAVE_CAP, tgt, g) for tgt in (192, 256, 320, 384) for g in (2, 3)] +
+    [(WAVE_CAP_SMALL, tgt, g) for tgt in (128, 160, 192) for g in (4, 5)] +
     [(cap, tgt, g) for cap in (2048, 4096) for tgt in (cap // 4, cap // 2) for g in (1, 2, 4)]
 )
 

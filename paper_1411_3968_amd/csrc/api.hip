@@ -210,6 +210,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     sort_kernels = 0;
     max_pmt = 0;
     wave_wgs = 0;
+    wave_cap = 0;
     block_wgs = 0;
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
@@ -243,9 +244,10 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         max_pmt = std::max(max_pmt, np);
         si.tune = ctx_tune_for(c, np);
         if (si.host_status == TRIG_OK && nh) {
-            if (si.tune.seg_cap == (uint32_t)WAVE_CAP) {
+            if (si.tune.seg_cap <= (uint32_t)WAVE_CAP) {
                 sort_kernels |= 1u;
                 wave_wgs = std::max(wave_wgs, si.tune.grid_per_cu);
+                wave_cap = std::max(wave_cap, si.tune.seg_cap);
                 if (np > (uint32_t)WAVE_RUNS) sort_kernels |= 2u;   // a slice may hand over to the block kernel
             } else {
                 sort_kernels |= 2u;
@@ -338,9 +340,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.n_chunks = si.n_chunks;
         S.tile_base = si.tile_base;
         S.n_tiles = si.n_tiles;
-        if (si.tune.seg_cap == (uint32_t)WAVE_CAP) {
-            S.seg_cap = WAVE_CAP;
-            S.seg_target = std::min<uint32_t>(si.tune.seg_target, WAVE_CAP * 3 / 4);
+        if (si.tune.seg_cap <= (uint32_t)WAVE_CAP) {
+            S.seg_cap = si.tune.seg_cap;
+            S.seg_target = std::min<uint32_t>(si.tune.seg_target, si.tune.seg_cap * 3 / 4);
         } else {
             S.seg_cap = seg_cap;
             S.seg_target = std::min(si.tune.seg_target, seg_cap / 2);
@@ -411,17 +413,20 @@ int Job::launch(trig_ctx *c, bool profile) {
     TrigLaunchCfg cfg = c->cfg;
     cfg.persist_per_cu = (int)std::max<uint32_t>(1, block_wgs);
     auto eager = [&](hipStream_t s) -> int {
-        hipError_t e = trig_launch_front(batch, seg_cap, (int)std::max<uint32_t>(1, wave_wgs), cfg, s, mark, c);
+        hipError_t e = trig_launch_front(batch, seg_cap, wave_cap, (int)std::max<uint32_t>(1, wave_wgs), cfg, s,
+                                         mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "front kernels");
         e = trig_launch_tail(batch, cfg, max_pmt, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
         return TRIG_OK;
     };
     if (profile || !graphs_ok || !c->use_graphs) return eager(stream);
-    std::vector<uint8_t> key(sizeof(BatchDev) + sizeof(TrigLaunchCfg) + sizeof(uint32_t));
+    // every host-side launch choice: kernel arguments, grids, variants, LDS sizes
+    const uint32_t extra[4] = {seg_cap, wave_cap, wave_wgs, max_pmt};
+    std::vector<uint8_t> key(sizeof(BatchDev) + sizeof(TrigLaunchCfg) + sizeof(extra));
     std::memcpy(key.data(), &batch, sizeof(BatchDev));
     std::memcpy(key.data() + sizeof(BatchDev), &cfg, sizeof(TrigLaunchCfg));
-    std::memcpy(key.data() + sizeof(BatchDev) + sizeof(TrigLaunchCfg), &seg_cap, sizeof(uint32_t));
+    std::memcpy(key.data() + sizeof(BatchDev) + sizeof(TrigLaunchCfg), extra, sizeof(extra));
     if (graph_exec && key == graph_key) {
         hipError_t e = hipGraphLaunch(graph_exec, stream);
         if (e != hipSuccess) return hip_fail(c, e, "graph launch");
@@ -785,7 +790,8 @@ int trig_tune_get(trig_ctx *c, uint32_t n_pmt, trig_tune *out) {
 
 int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
     if (!c || !t) return TRIG_EINVAL;
-    if (!(t->seg_cap == (uint32_t)WAVE_CAP || t->seg_cap == 2048 || t->seg_cap == 4096 || t->seg_cap == 8192) ||
+    if (!(t->seg_cap == (uint32_t)WAVE_CAP || t->seg_cap == (uint32_t)WAVE_CAP_SMALL || t->seg_cap == 2048 ||
+          t->seg_cap == 4096 || t->seg_cap == 8192) ||
         t->seg_target == 0 ||
         t->grid_per_cu == 0 || t->grid_per_cu > 16) {
         ctx_set_error(c, "bad tuning values");

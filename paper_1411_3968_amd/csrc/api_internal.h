@@ -63,6 +63,7 @@ struct Job {
     uint32_t seg_cap = 4096;          // capacity of the block-per-segment ordering kernel
     uint32_t sort_kernels = 0;        // ordering kernels to launch (bit 0 wave, bit 1 block)
     uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
+    uint32_t wave_cap = 0;            // variant of the wave-per-segment kernel (largest tuned capacity)
     uint32_t total_chunks = 0, total_tiles = 0;
     uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;

@@ -153,12 +153,12 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             // ordering kernel: wave per segment for few runs, else block per segment
             uint32_t cap = S.seg_cap, target = S.seg_target;
             bool ok = true;
-            if (cap == (uint32_t)WAVE_CAP && runs > (uint32_t)WAVE_RUNS) {
+            if (cap <= (uint32_t)WAVE_CAP && runs > (uint32_t)WAVE_RUNS) {
                 cap = b.block_cap;
                 target = b.block_target;
                 ok = (b.sort_kernels & 2u) != 0;
             }
-            p.seg_kind = cap == (uint32_t)WAVE_CAP ? 0u : 1u;
+            p.seg_kind = cap <= (uint32_t)WAVE_CAP ? 0u : 1u;
             // segment width: the largest power of two with expected occupancy <= target
             const uint64_t x = ((uint64_t)target * (span + 1)) / S.n;
             uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
@@ -500,11 +500,17 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Sort key of a gathered element: local time, PMT, gather position.
+constexpr int KEY_P_SHIFT = 9, KEY_T_SHIFT = 25;   // gather positions < 512, PMT ids < 2^16
+constexpr uint32_t KEY_K_MASK = (1u << KEY_P_SHIFT) - 1;
+static_assert(WAVE_CAP <= (1 << KEY_P_SHIFT), "gather positions must fit the key");
+
+template <int CAP>
 struct WaveSeg {
-    uint32_t dt[WAVE_CAP], dpq[WAVE_CAP], dsrc[WAVE_CAP];   // t - t_min, pmt << 16 | q, input index
-    uint16_t aux[WAVE_CAP];      // run marks while gathering, then slots within buckets
-    uint16_t perm[WAVE_CAP];     // elements grouped by bucket
-    uint16_t inv[WAVE_CAP];      // element at each ordered position
+    uint64_t key[CAP];           // keys grouped by bucket, then in output order
+    uint32_t dsrc[CAP];          // input index of each gathered element
+    uint16_t dq[CAP];            // charge of each gathered element
+    uint16_t aux[CAP];           // run marks while gathering
     uint32_t run_lo[WAVE_RUNS], run_base[WAVE_RUNS];
     uint32_t bcount[256];
     uint16_t bbase[256];
@@ -512,12 +518,13 @@ struct WaveSeg {
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total(v); }
 
+template <int CAP>
 __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
-    constexpr int EG = WAVE_CAP / 64;
+    constexpr int EG = CAP / 64;
     constexpr int RI = WAVE_RUNS / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = lane_id();
-    WaveSeg &sm = reinterpret_cast<WaveSeg *>(smem_raw)[w];
+    WaveSeg<CAP> &sm = reinterpret_cast<WaveSeg<CAP> *>(smem_raw)[w];
     const uint32_t total = b.counters[Q_SEG_TOTAL];
     // XCD-aware split: workgroup b runs on XCD b % 8 (round-robin dispatch), and
     // each XCD takes one contiguous eighth of the segment list, so the cache lines
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             gpart += lo[i] - st[i];
         }
         const uint32_t goff = wave_sum_u32(gpart);
-        if (m > (uint32_t)WAVE_CAP) {
+        if (m > (uint32_t)CAP) {
             if (lane == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
             continue;
         }
@@ -623,20 +630,25 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 qv[e] = in_q[src[e]];
             }
         }
-        // bucket of each element by the top 8 bits of its local time
+        // key of each element: (local time, PMT, gather position), unique and in
+        // the output order; bucket by the top 8 bits of the local time
         const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
 #pragma unroll
         for (int i = 0; i < 4; ++i) sm.bcount[lane * 4 + i] = 0;
         wave_sync();
+        uint64_t key[EG];
+        uint32_t slot[EG];
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
+            key[e] = 0;
+            slot[e] = 0;
             if (src[e] != 0xFFFFFFFFu) {
-                const uint32_t dt = (uint32_t)(tv[e] - P.t_min);
-                sm.dt[k] = dt;
-                sm.dpq[k] = (pv[e] << 16) | qv[e];
+                const uint32_t tl = (uint32_t)(tv[e] - P.t_min) - seg_lo;
+                key[e] = ((uint64_t)tl << KEY_T_SHIFT) | ((uint64_t)pv[e] << KEY_P_SHIFT) | k;
+                sm.dq[k] = (uint16_t)qv[e];
                 sm.dsrc[k] = src[e];
-                sm.aux[k] = (uint16_t)atomicAdd(&sm.bcount[(dt - seg_lo) >> tb], 1u);
+                slot[e] = atomicAdd(&sm.bcount[tl >> tb], 1u);
             }
         }
         wave_sync();
@@ -650,62 +662,43 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = (uint16_t)run; run += v[i]; }
         }
         wave_sync();
+        // keys grouped by bucket
+        uint32_t ebase[EG], ecnt[EG], rank[EG];
+        uint32_t most = 0;
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
-            const uint32_t k = (uint32_t)(e * 64 + lane);
-            if (k < m) sm.perm[sm.bbase[(sm.dt[k] - seg_lo) >> tb] + sm.aux[k]] = (uint16_t)k;
+            ebase[e] = ecnt[e] = rank[e] = 0;
+            if (src[e] != 0xFFFFFFFFu) {
+                const uint32_t bk = (uint32_t)(key[e] >> KEY_T_SHIFT) >> tb;
+                ebase[e] = sm.bbase[bk];
+                ecnt[e] = sm.bcount[bk];
+                sm.key[ebase[e] + slot[e]] = key[e];
+            }
+            most = ecnt[e] > most ? ecnt[e] : most;
         }
         wave_sync();
-        // rank within the bucket by (t, pmt, k); the EG elements of a lane walk
-        // their buckets together, so each step waits on one round of LDS reads
-        {
-            uint32_t et[EG], ep[EG], ebase[EG], ecnt[EG], rank[EG];
-            uint32_t most = 0;
+        // rank within the bucket: the members with a smaller key (independent
+        // reads; the EG elements of a lane walk their buckets together)
+        for (uint32_t x = 0; x < most; ++x) {
 #pragma unroll
-            for (int e = 0; e < EG; ++e) {
-                const uint32_t k = (uint32_t)(e * 64 + lane);
-                ecnt[e] = 0;
-                rank[e] = 0;
-                et[e] = ep[e] = ebase[e] = 0;
-                if (k < m) {
-                    et[e] = sm.dt[k];
-                    ep[e] = sm.dpq[k] >> 16;
-                    const uint32_t bk = (et[e] - seg_lo) >> tb;
-                    ebase[e] = sm.bbase[bk];
-                    ecnt[e] = sm.bcount[bk];
-                }
-                most = ecnt[e] > most ? ecnt[e] : most;
-            }
-            for (uint32_t x = 0; x < most; ++x) {
-#pragma unroll
-                for (int e = 0; e < EG; ++e) {
-                    if (x < ecnt[e]) {
-                        const uint32_t k = (uint32_t)(e * 64 + lane);
-                        const uint32_t u = sm.perm[ebase[e] + x];
-                        const uint32_t tu = sm.dt[u];
-                        bool before = tu < et[e];
-                        if (tu == et[e]) {
-                            const uint32_t pu = sm.dpq[u] >> 16;
-                            before = pu < ep[e] || (pu == ep[e] && u < k);
-                        }
-                        rank[e] += before;
-                    }
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < EG; ++e) {
-                const uint32_t k = (uint32_t)(e * 64 + lane);
-                if (k < m) sm.inv[ebase[e] + rank[e]] = (uint16_t)k;
-            }
+            for (int e = 0; e < EG; ++e)
+                if (x < ecnt[e]) rank[e] += sm.key[ebase[e] + x] < key[e] ? 1u : 0u;
         }
+        wave_sync();
+        // keys in output order (each bucket's range rewritten by its own members)
+#pragma unroll
+        for (int e = 0; e < EG; ++e)
+            if (src[e] != 0xFFFFFFFFu) sm.key[ebase[e] + rank[e]] = key[e];
         wave_sync();
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t i = (uint32_t)(e * 64 + lane);
             if (i < m) {
-                const uint32_t k = sm.inv[i];
-                o_t[goff + i] = sm.dt[k];
-                o_pq[goff + i] = sm.dpq[k];
+                const uint64_t kk = sm.key[i];
+                const uint32_t k = (uint32_t)kk & KEY_K_MASK;
+                const uint32_t p = (uint32_t)(kk >> KEY_P_SHIFT) & 0xFFFFu;
+                o_t[goff + i] = seg_lo + (uint32_t)(kk >> KEY_T_SHIFT);
+                o_pq[goff + i] = (p << 16) | sm.dq[k];
                 o_idx[goff + i] = sm.dsrc[k];
             }
         }
@@ -713,17 +706,18 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     }
 }
 
+template <int CAP>
 hipError_t launch_segsort_w(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s) {
-    const size_t shm = 4 * sizeof(WaveSeg);
+    const size_t shm = 4 * sizeof(WaveSeg<CAP>);
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_segsort_w, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)shm);
+        hipError_t e = hipFuncSetAttribute((const void *)k_segsort_w<CAP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
     const int grid = ((cfg.n_cu * cfg.persist_per_cu + 7) / 8) * 8;   // a multiple of the 8 XCDs
-    hipLaunchKernelGGL(k_segsort_w, dim3(grid), dim3(256), shm, s, b);
+    hipLaunchKernelGGL(k_segsort_w<CAP>, dim3(grid), dim3(256), shm, s, b);
     return hipGetLastError();
 }
 
@@ -747,7 +741,8 @@ hipError_t launch_segsort(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
 #define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
 
-hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, int wave_wgs_per_cu, const TrigLaunchCfg &cfg,
+hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_cap, int wave_wgs_per_cu,
+                             const TrigLaunchCfg &cfg,
                              hipStream_t s, void (*mark)(void *, const char *, int), void *mark_ctx) {
     if (b.total_chunks) {
         TRIG_MARK("k_ingest", 0);
@@ -769,7 +764,9 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, int wave_wgs_p
         TRIG_MARK("k_segsort_w", 0);
         TrigLaunchCfg wc = cfg;
         wc.persist_per_cu = wave_wgs_per_cu;
-        e = launch_segsort_w(b, wc, s);
+        // segments of slices tuned for the small variant also fit the large one
+        e = wave_cap <= (uint32_t)WAVE_CAP_SMALL ? launch_segsort_w<WAVE_CAP_SMALL>(b, wc, s)
+                                                 : launch_segsort_w<WAVE_CAP>(b, wc, s);
         if (e != hipSuccess) return e;
         TRIG_MARK("k_segsort_w", 1);
     }

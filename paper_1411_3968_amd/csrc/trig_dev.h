@@ -40,7 +40,8 @@ constexpr int HALO_SMALL = 256;   // ordered hits staged on each side of a tile 
 constexpr int HALO_BIG = 1024;    // the same in the dense-window rerun
 constexpr int GTILE = 4096;       // elements per block of the general radix sort
 constexpr int LDS_THR_MAX_PMT = 128;  // thr table kept in LDS up to this many PMTs
-constexpr int WAVE_CAP = 512;     // hits per segment of the wave-per-segment ordering
+constexpr int WAVE_CAP = 512;     // hits per segment of the wave-per-segment ordering (largest variant)
+constexpr int WAVE_CAP_SMALL = 256;   // its smaller variant (half the registers and LDS per wave)
 constexpr int WAVE_RUNS = 256;    // most runs a wave-per-segment slice may have
 
 enum State : uint32_t {
@@ -356,7 +357,7 @@ struct TrigLaunchCfg {
     int persist_per_cu;
 };
 
-hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, int wave_wgs_per_cu,
+hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, uint32_t wave_cap, int wave_wgs_per_cu,
                              const TrigLaunchCfg &cfg, hipStream_t s, void (*mark)(void *, const char *, int),
                              void *mark_ctx);
 // max_pmt: the largest PMT count of the batch's geometries (sizes the LDS table).

@@ -11,11 +11,12 @@ def test_candidates_are_valid_tunings():
     assert "WAVE_CAP" in src
     seen = set()
     for cap, tgt, g in autotune.DEFAULT_CANDIDATES:
-        assert cap in (autotune.WAVE_CAP, 2048, 4096, 8192)
+        assert cap in (autotune.WAVE_CAP, autotune.WAVE_CAP_SMALL, 2048, 4096, 8192)
         assert 0 < tgt <= cap and 1 <= g <= 16
         assert (cap, tgt, g) not in seen
         seen.add((cap, tgt, g))
-    assert any(c[0] == autotune.WAVE_CAP for c in seen) and any(c[0] != autotune.WAVE_CAP for c in seen)
+    assert any(c[0] == autotune.WAVE_CAP for c in seen) and any(c[0] == autotune.WAVE_CAP_SMALL for c in seen)
+    assert any(c[0] > autotune.WAVE_CAP for c in seen)
 
 
 def test_cache_roundtrip_format(tmp_path):
