@@ -503,15 +503,15 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
         hipError_t e = trig_launch_generic_slice(si.dev, hp[i], key_bits, scratch, stream, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "general ordering");
     }
-    BatchDev b2 = batch;
-    b2.tail_state = ST_GENERIC_DONE;
-    TrigLaunchCfg cfg = c->cfg;
-    cfg.persist_per_cu = (int)std::max<uint32_t>(2, block_wgs);
-    hipError_t e = trig_launch_tail(b2, cfg, max_pmt, stream, mark, c);
-    if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
+    // the trigger stage of just those slices, each as a launch of its own
+    for (uint32_t i : todo) {
+        const BatchDev b1 = one_slice(i, ST_GENERIC_DONE);
+        hipError_t e = trig_launch_tail(b1, c->cfg, slices[i].dev.n_pmt, stream, mark, c);
+        if (e != hipSuccess) return hip_fail(c, e, "tail kernels (general path)");
+    }
     int rc2 = enqueue_flags(c, &todo);
     if (rc2) return rc2;
-    e = hipStreamSynchronize(stream);
+    const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (general path)");
     return TRIG_OK;
 }
@@ -527,15 +527,31 @@ int Job::dense_pass(trig_ctx *c, bool profile) {
             todo.push_back(i);
     if (todo.empty()) return TRIG_OK;
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
-    BatchDev b3 = batch;
-    b3.tail_state = ST_DENSE;
-    hipError_t e = trig_launch_dense(b3, c->cfg, max_pmt, stream, mark, c);
-    if (e != hipSuccess) return hip_fail(c, e, "trigger stage (dense rerun)");
+    hipError_t e = hipSuccess;
+    for (uint32_t i : todo) {
+        const BatchDev b1 = one_slice(i, ST_DENSE);
+        e = trig_launch_dense(b1, c->cfg, slices[i].dev.n_pmt, stream, mark, c);
+        if (e != hipSuccess) return hip_fail(c, e, "trigger stage (dense rerun)");
+    }
     int rc = enqueue_flags(c, &todo);
     if (rc) return rc;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (dense rerun)");
     return TRIG_OK;
+}
+
+// The batch descriptor narrowed to slice i, for reruns of one slice's trigger
+// stage (tiles numbered from 0, its plan exported to its own staging slot).
+BatchDev Job::one_slice(uint32_t i, uint32_t state) const {
+    BatchDev b1 = batch;
+    b1.slices = d_slices + i;
+    b1.plans = d_plans + i;
+    b1.n_slices = 1;
+    b1.total_chunks = slices[i].n_chunks;
+    b1.total_tiles = slices[i].n_tiles;
+    b1.x_plans = x_plans_dev ? x_plans_dev + i : nullptr;
+    b1.tail_state = state;
+    return b1;
 }
 
 // Copy the results of slice i into the caller's result record.

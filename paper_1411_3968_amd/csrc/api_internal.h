@@ -98,6 +98,7 @@ struct Job {
     int generic_pass(trig_ctx *c, bool profile);
     int dense_pass(trig_ctx *c, bool profile);
     int deliver(trig_ctx *c, uint32_t i, trig_result *r);
+    trigdev::BatchDev one_slice(uint32_t i, uint32_t state) const;
     void release(trig_ctx *c);
 };
 

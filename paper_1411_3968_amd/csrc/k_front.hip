@@ -29,7 +29,7 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t c = item - S.chunk_base;
+    const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint64_t k1 = (k0 + CHUNK < S.n) ? k0 + CHUNK : S.n;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     }
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t c = item - S.chunk_base;
+    const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
     const Plan P = gload(gmem(S.plan));
     if (P.state != ST_FAST) return;

@@ -154,7 +154,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     if (item >= b.total_tiles) return;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t k = item - S.tile_base;
+    const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
     Plan *Pp = S.plan;   // generic: the flag updates below are atomics
     const TRIG_GAS Plan *Pg = gmem(Pp);
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t k = item - S.tile_base;
+    const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
     const TRIG_GAS Plan *Pp = gmem(S.plan);
     if (!slice_in_tail(b, Pp->state)) return;
@@ -657,7 +657,7 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t k = item - S.tile_base;
+    const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
     Plan *Pp = S.plan;
     if (!Pp->dense || Pp->status != TRIG_OK) return;

@@ -344,6 +344,15 @@ __device__ __forceinline__ uint32_t find_slice(uint32_t n_slices, uint32_t item,
     return lo ? lo - 1 : 0;
 }
 
+// First tile / chunk of slice si in the launch's numbering: a one-slice launch
+// (one slice of a larger batch rerun on its own) numbers from 0.
+__device__ __forceinline__ uint32_t tile_base_of(const BatchDev &b, uint32_t si) {
+    return b.n_slices <= 1 ? 0u : b.tile_bases[si];
+}
+__device__ __forceinline__ uint32_t chunk_base_of(const BatchDev &b, uint32_t si) {
+    return b.n_slices <= 1 ? 0u : b.chunk_bases[si];
+}
+
 __device__ __forceinline__ bool slice_in_tail(const BatchDev &b, uint32_t state) {
     return state == b.tail_state;
 }
