@@ -6,7 +6,8 @@ the benchmark's CPU-baseline leg.  The product library never imports it.
 ``build()`` compiles ``oracle.c`` with gcc (OpenMP) into ``liboracle.so``
 next to this file.  ``run()`` evaluates the whole rule on one slice and
 returns numpy arrays; ``point()`` evaluates the seed flag and fold of a few
-sampled hits at any slice size.
+sampled hits at any slice size; ``tag()`` lists the hits within the event
+windows of a fire list.
 """
 from __future__ import annotations
 
@@ -57,6 +58,8 @@ def _load():
         lib.orc_point.argtypes = [C.c_uint64, P, P, P, C.c_uint32, P, P, C.POINTER(Params),
                                   P, C.c_uint64, P, P, C.c_int]
         lib.orc_point.restype = C.c_int
+        lib.orc_tag.argtypes = [C.c_uint64, P, P, P, C.c_uint64, C.c_uint32, P]
+        lib.orc_tag.restype = C.c_uint64
         _lib = lib
     return _lib
 
@@ -96,6 +99,22 @@ def run(pmt, t, q, floor_id, thr, params: dict | None = None, form: str = "block
                          events.ctypes.data_as(C.c_void_p), C.byref(ne), int(threads))
     return dict(status=int(rc), seed=seed[:n] if rc == 0 else seed[:0], fold=fold[:n] if rc == 0 else fold[:0],
                 fires=fires[:nf.value].copy(), events=events[:ne.value].copy())
+
+
+def tag(pmt, t, fires, half_event_ns: int = 3000):
+    """Input indices of the hits within +-half_event_ns of some fire, ordered by
+    (t, pmt, input index).  ``fires`` as returned by :func:`run` (time order)."""
+    pmt = np.ascontiguousarray(pmt, dtype=np.uint16)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    fires = np.ascontiguousarray(fires, dtype=FIRE_DTYPE)
+    n = t.shape[0]
+    out = np.zeros(max(n, 1), np.uint32)
+    lib = _load()
+    c = lib.orc_tag(n, _ptr(pmt), _ptr(t), _ptr(fires), len(fires), int(half_event_ns),
+                    out.ctypes.data_as(C.c_void_p))
+    if c == (1 << 64) - 1:
+        raise MemoryError("orc_tag")
+    return out[:c].copy()
 
 
 def point(pmt, t, q, floor_id, thr, ks, params: dict | None = None, threads: int = 0):

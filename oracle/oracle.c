@@ -28,6 +28,9 @@
  *           tagged): each fire opens [t-H, t+H]; walking F in order, a fire
  *           whose window starts at or before the current event's end extends
  *           it, otherwise it opens a new event.
+ *   tagged hits (Sec. 4.2: the hits within +-3 us of a trigger seed are
+ *           tagged to be saved): T = { k : |t_k - t_f| <= H for some f in F },
+ *           ordered by (t, p, k)
  *
  * Two forms:  "strict" evaluates every pair (O(n^2));  "blocked" evaluates
  * the very same pair tests, restricted to hits in the same or adjacent time
@@ -281,6 +284,40 @@ uint64_t orc_events(const orc_fire *f, uint64_t nf, uint32_t half_event_ns, orc_
         }
     }
     return ne;
+}
+
+/* Tagged hits (Sec. 4.2: once the trigger fires, every hit within +-3 us of a
+ * trigger seed is tagged to be saved; Sec. 2: the 6 us window of tower data
+ * centred on the trigger seed is what goes to storage).  Hit k is tagged when
+ * some fire f has |t_k - t_f| <= H.  fires must be ordered by time (as
+ * collect_fires leaves them).  out[] (room for n) receives the tagged hits'
+ * input indices ordered by (t, pmt, input index); returns their number, or
+ * UINT64_MAX when out of memory. */
+uint64_t orc_tag(uint64_t n, const uint16_t *pmt, const int64_t *t, const orc_fire *f, uint64_t nf,
+                 uint32_t half_event_ns, uint32_t *out)
+{
+    const int64_t H = half_event_ns;
+    orc_fire *rec = (orc_fire *)malloc((n ? n : 1) * sizeof(orc_fire));
+    if (!rec) return UINT64_MAX;
+    uint64_t c = 0;
+    for (uint64_t k = 0; k < n; ++k) {
+        /* the first fire at or after t_k - H; hit k is tagged when it is also at
+         * or before t_k + H */
+        uint64_t lo = 0, hi = nf;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2;
+            if (f[mid].t_ns < t[k] - H) lo = mid + 1; else hi = mid;
+        }
+        if (lo < nf && f[lo].t_ns <= t[k] + H) {
+            memset(&rec[c], 0, sizeof rec[c]);
+            rec[c].t_ns = t[k]; rec[c].pmt_id = pmt[k]; rec[c].hit_index = (uint32_t)k;
+            ++c;
+        }
+    }
+    qsort(rec, c, sizeof(orc_fire), fire_cmp);   /* the fires' order: (t, pmt, index) */
+    for (uint64_t i = 0; i < c; ++i) out[i] = rec[i].hit_index;
+    free(rec);
+    return c;
 }
 
 /* Whole path.  form 0 = strict, 1 = blocked.  seed_out / fold_out are [n]

@@ -286,3 +286,57 @@ def test_pmt_relabel_invariance(oracle_lib, mid_slice):
     sb = sorted(zip(b["fires"]["hit_index"].tolist(), b["fires"]["t_ns"].tolist(), b["fires"]["fold"].tolist()))
     assert sa == sb
     assert np.array_equal(a["events"], b["events"])
+
+
+# ------------------------------------------------------------- tagged hits
+
+def _fires(rows):
+    from oracle.cpu import FIRE_DTYPE
+    f = np.zeros(len(rows), FIRE_DTYPE)
+    for i, (t, k, fold, p) in enumerate(rows):
+        f[i]["t_ns"], f[i]["hit_index"], f[i]["fold"], f[i]["pmt_id"] = t, k, fold, p
+    return f
+
+
+def test_tag_hand_example(oracle_lib):
+    """Worked by hand: fires at 10 000, 10 500 and 30 000 ns with H = 3000 ns
+    tag [7000, 13500] and [27000, 33000] (both ends inclusive); equal times
+    order by PMT, then input position."""
+    hits = [(5, 6999), (4, 7000), (1, 10000), (3, 10500), (0, 13500), (0, 13501), (2, 20000), (2, 30000),
+            (7, 33000), (7, 33001), (2, 7000), (4, 7000), (6, 27000), (6, 26999)]
+    pmt = np.array([h[0] for h in hits], np.uint16)
+    t = np.array([h[1] for h in hits], np.int64)
+    fires = _fires([(10000, 2, 4, 1), (10500, 3, 4, 3), (30000, 7, 5, 2)])
+    got = oracle_lib.tag(pmt, t, fires, 3000)
+    assert got.tolist() == [10, 1, 11, 2, 3, 4, 12, 7, 8]
+
+
+def test_tag_equals_hits_inside_the_event_windows(oracle_lib, mid_slice):
+    """The tagged hits are exactly those inside a merged event window (the
+    events come from the separate merge walk over the fires)."""
+    w, g, thr, s = mid_slice
+    r = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params)
+    assert len(r["events"]) > 0
+    got = oracle_lib.tag(s.pmt, s.t, r["fires"], w.params["half_event_ns"])
+    ev = r["events"]
+    i = np.searchsorted(ev["t_begin"], s.t, side="right") - 1
+    inside = (i >= 0) & (s.t <= ev["t_end"][np.maximum(i, 0)])
+    idx = np.flatnonzero(inside)
+    want = idx[np.lexsort((idx, s.pmt[idx], s.t[idx]))]
+    assert np.array_equal(got, want.astype(np.uint32))
+    assert len(got) > r["fires"].shape[0]
+
+
+def test_tag_special_cases(oracle_lib, mid_slice):
+    w, g, thr, s = mid_slice
+    r = oracle_lib.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params)
+    f = r["fires"]
+    # no fires: nothing tagged
+    assert len(oracle_lib.tag(s.pmt, s.t, f[:0], 3000)) == 0
+    # a window wider than the slice around one fire: every hit, in (t, pmt, index) order
+    allh = oracle_lib.tag(s.pmt, s.t, f[:1], 2**31 - 1)
+    assert np.array_equal(allh, np.lexsort((np.arange(s.n), s.pmt, s.t)).astype(np.uint32))
+    # H = 0: the hits at a fire's exact time (the fires among them)
+    z = oracle_lib.tag(s.pmt, s.t, f, 0)
+    assert set(z.tolist()) == set(np.flatnonzero(np.isin(s.t, f["t_ns"])).tolist())
+    assert set(f["hit_index"].tolist()) <= set(z.tolist())
