@@ -134,15 +134,22 @@ typedef struct {
     uint32_t n_fire, max_fold;
 } trig_event;
 
-/* Result of one slice.  The caller sets fires/fire_cap, events/event_cap and
- * seed_flags (host buffers; seed_flags may be NULL, else [n_hits] bytes by
- * input position, 1 for a seed).  The library fills the counts, status and
- * tag.  Fires are ordered by (t_ns, pmt_id, hit_index), events by t_begin.
- * On TRIG_EOVERFLOW n_fires / n_events hold the required counts and no list
- * is written.  path reports how the slice was processed: bit 0 set when the
- * general radix sort ordered it (else the run merge), bit 1 set when its
- * trigger stage was rerun with a precomputed seed mask (a burst far denser than
- * the slice's mean density). */
+/* Result of one slice.  The caller sets fires/fire_cap, events/event_cap,
+ * seed_flags and tagged/tagged_cap (host buffers; seed_flags may be NULL, else
+ * [n_hits] bytes by input position, 1 for a seed; tagged may be NULL, else
+ * room for tagged_cap input indices).  The library fills the counts, status
+ * and tag.  Fires are ordered by (t_ns, pmt_id, hit_index), events by t_begin.
+ * tagged receives the hits inside the event windows (paper Sec. 4.2: the hits
+ * within +-3 us of a trigger seed are tagged to be saved; Sec. 2: the 6 us
+ * window of tower data around the trigger is stored): the input index of every
+ * hit with t_begin <= t <= t_end for some event, ordered by (t, pmt, input
+ * index); it is computed only when tagged is not NULL (trig_slice and
+ * trig_batch; the stream entry points leave it NULL and n_tagged 0).
+ * On TRIG_EOVERFLOW n_fires / n_events / n_tagged hold the required counts
+ * and no list is written.  path reports how the slice was processed: bit 0 set
+ * when the general radix sort ordered it (else the run merge), bit 1 set when
+ * its trigger stage was rerun with a precomputed seed mask (a burst far denser
+ * than the slice's mean density). */
 typedef struct {
     trig_fire  *fires;
     uint64_t    fire_cap, n_fires;
@@ -152,6 +159,8 @@ typedef struct {
     uint64_t    n_hits, n_seeds, tag;
     int32_t     status;
     uint32_t    path;
+    uint32_t   *tagged;
+    uint64_t    tagged_cap, n_tagged;
 } trig_result;
 
 /* Trigger one slice.  Synchronous with respect to the caller's buffers: it

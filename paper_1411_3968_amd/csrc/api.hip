@@ -183,6 +183,7 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.fires = take(n * sizeof(trig_fire) + 32);
     L.events = take(n * sizeof(trig_event) + 32);
     L.flags = want_flags ? take(n + 4) : SIZE_MAX;
+    L.tagc = take(std::max<uint64_t>(n_tiles, 1) * 4);
     return o;
 }
 
@@ -200,7 +201,8 @@ size_t slice_footprint(uint64_t n, bool host_input) {
 }
 
 int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
-                 const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s) {
+                 const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
+                 const uint8_t *want_tags) {
     stream = s;
     params = *prm;
     slices.assign(n, SliceInfo{});
@@ -232,6 +234,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         const uint64_t nh = si.host_status == TRIG_OK ? d[i].n_hits : 0;
         si.n = nh;
         si.want_flags = want_flags && want_flags[i];
+        si.want_tag = want_tags && want_tags[i];
         si.ws_off = total;
         total += slice_layout(nh, d[i].mem == TRIG_MEM_HOST, si.want_flags, si.L);
         si.chunk_base = chunk_base;
@@ -365,6 +368,9 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.x_events = (trig_event *)((char *)x_plans_dev + si.x_off_e);
         S.x_fire_cap = si.x_fcap;
         S.x_event_cap = si.x_ecap;
+        S.tagc = (uint32_t *)(b + L.tagc);
+        S.tagged = (uint32_t *)(b + L.fsc);   // free once the fires are placed
+        S.tag_on = si.want_tag && si.host_status == TRIG_OK ? 1u : 0u;
         hs[i] = S;
         si.dev = S;
     }
@@ -540,6 +546,20 @@ int Job::dense_pass(trig_ctx *c, bool profile) {
     return TRIG_OK;
 }
 
+// After every pass that can change the events: the tagged-hit lists of the
+// slices that asked for them.
+int Job::tag_pass(trig_ctx *c, bool profile) {
+    bool any = false;
+    for (const SliceInfo &si : slices) any |= si.want_tag && si.host_status == TRIG_OK && si.n > 0;
+    if (!any) return TRIG_OK;
+    void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
+    hipError_t e = trig_launch_tag(batch, stream, mark, c);
+    if (e != hipSuccess) return hip_fail(c, e, "tagged hits");
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(c, e, "synchronise (tagged hits)");
+    return TRIG_OK;
+}
+
 // The batch descriptor narrowed to slice i, for reruns of one slice's trigger
 // stage (tiles numbered from 0, its plan exported to its own staging slot).
 BatchDev Job::one_slice(uint32_t i, uint32_t state) const {
@@ -561,7 +581,7 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     r->tag = si.desc.tag;
     r->n_hits = si.desc.n_hits;
     r->path = (P.generic ? 1u : 0u) | (P.dense ? 2u : 0u);
-    r->n_seeds = r->n_fires = r->n_events = 0;
+    r->n_seeds = r->n_fires = r->n_events = r->n_tagged = 0;
     if (si.host_status != TRIG_OK) return r->status = si.host_status;
     if (P.status != TRIG_OK) {
         ctx_set_error(c, "slice %u: input out of range (PMT id, time span or event window)", i);
@@ -571,10 +591,12 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     r->n_seeds = P.n_seeds;
     r->n_fires = P.n_fires;
     r->n_events = P.n_events;
+    r->n_tagged = si.want_tag ? P.n_tagged : 0;
     if ((P.n_fires && (!r->fires || r->fire_cap < P.n_fires)) ||
-        (P.n_events && (!r->events || r->event_cap < P.n_events))) {
-        ctx_set_error(c, "slice %u: result capacity too small (need %u fires, %u events)", i, P.n_fires,
-                      P.n_events);
+        (P.n_events && (!r->events || r->event_cap < P.n_events)) ||
+        (si.want_tag && r->tagged_cap < P.n_tagged)) {
+        ctx_set_error(c, "slice %u: result capacity too small (need %u fires, %u events, %u tagged hits)", i,
+                      P.n_fires, P.n_events, si.want_tag ? P.n_tagged : 0u);
         return r->status = TRIG_EOVERFLOW;
     }
     // staged lists come from pinned memory; longer ones are copied from the device
@@ -597,6 +619,11 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
                                hipMemcpyDeviceToHost, stream);
             copies_queued = true;
         }
+    }
+    if (e == hipSuccess && si.want_tag && P.n_tagged) {
+        e = hipMemcpyAsync(r->tagged, si.dev.tagged, (size_t)P.n_tagged * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                           stream);
+        copies_queued = true;
     }
     if (e != hipSuccess) return r->status = hip_fail(c, e, "D2H of results");
     return r->status = TRIG_OK;
@@ -637,17 +664,18 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
         ctx_set_error(c, "null slices or results");
         return TRIG_EINVAL;
     }
-    std::vector<uint8_t> flags(n);
+    std::vector<uint8_t> flags(n), tags(n);
     std::vector<uint64_t> fcap(n), ecap(n);
     for (uint32_t i = 0; i < n; ++i) {
         flags[i] = res[i].seed_flags != nullptr;
+        tags[i] = res[i].tagged != nullptr;
         fcap[i] = res[i].fires ? res[i].fire_cap : 0;
         ecap[i] = res[i].events ? res[i].event_cap : 0;
     }
     Job &J = c->sync_job;
     const bool prof = c->prof_on;
     if (prof) c->prof_stream = s;
-    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s);
+    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data());
     if (rc) return rc;
     for (uint32_t i = 0; i < n; ++i) J.slices[i].flags_dst = res[i].seed_flags;
     rc = J.launch(c, prof);
@@ -659,6 +687,8 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
     rc = J.generic_pass(c, prof);
     if (rc) return rc;
     rc = J.dense_pass(c, prof);
+    if (rc) return rc;
+    rc = J.tag_pass(c, prof);
     if (rc) return rc;
     int first_bad = TRIG_OK;
     J.copies_queued = false;

@@ -36,7 +36,7 @@ struct GeomDev {
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
 struct SliceLayout {
-    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags;
+    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags, tagc;
     uint64_t pos_cap;
 };
 
@@ -53,6 +53,7 @@ struct SliceInfo {
     size_t x_off_f, x_off_e;     // result staging offsets in the pinned buffer
     uint32_t x_fcap, x_ecap;
     uint8_t *flags_dst;          // caller's host buffer for seed flags (or null)
+    bool want_tag;               // the tagged-hit list is asked for
 };
 
 // One device round over a set of slices: workspace, descriptors, plans.
@@ -92,11 +93,13 @@ struct Job {
     // want_flags / fire_caps / event_caps: per slice, may be null (no flags /
     // default staging capacity).
     int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
-                const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s);
+                const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
+                const uint8_t *want_tags = nullptr);
     int launch(trig_ctx *c, bool profile);
     int enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only);   // null: every slice
     int generic_pass(trig_ctx *c, bool profile);
     int dense_pass(trig_ctx *c, bool profile);
+    int tag_pass(trig_ctx *c, bool profile);
     int deliver(trig_ctx *c, uint32_t i, trig_result *r);
     trigdev::BatchDev one_slice(uint32_t i, uint32_t state) const;
     void release(trig_ctx *c);

@@ -437,6 +437,7 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
     r->tag = t->desc.tag;
     r->path = t->path;
     r->status = t->status;
+    r->n_tagged = 0;   // the stream path computes no tagged-hit list
     if (t->status == TRIG_OK) {
         if ((r->n_fires && (!r->fires || r->fire_cap < r->n_fires)) ||
             (r->n_events && (!r->events || r->event_cap < r->n_events))) {

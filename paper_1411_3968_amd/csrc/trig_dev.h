@@ -114,7 +114,7 @@ struct Plan {
     uint32_t seg_kind;       // 0: wave-per-segment ordering, 1: block-per-segment ordering
     uint32_t dense;          // a trigger tile's window outran its staged halo: rerun with a seed mask
     uint32_t generic;        // ordered by the general path
-    uint32_t pad;
+    uint32_t n_tagged;       // hits inside the event windows (slices that ask for the tagged list)
 };
 
 struct SliceDev {
@@ -144,6 +144,9 @@ struct SliceDev {
     trig_fire *x_fires;      // host-mapped staging of the results (null: none)
     trig_event *x_events;
     uint32_t x_fire_cap, x_event_cap;
+    uint32_t *tagc;          // per tile: tagged-hit count, then its exclusive prefix
+    uint32_t *tagged;        // tagged hits' input indices (the fire-scratch area)
+    uint32_t tag_on, pad2;   // the caller asked for the tagged list
 };
 
 struct BatchDev {
@@ -366,6 +369,8 @@ struct TrigLaunchCfg {
     int persist_per_cu;
 };
 
+hipError_t trig_launch_tag(const trigdev::BatchDev &b, hipStream_t s, void (*mark)(void *, const char *, int),
+                           void *mark_ctx);
 hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, uint32_t wave_cap, int wave_wgs_per_cu,
                              const TrigLaunchCfg &cfg, hipStream_t s, void (*mark)(void *, const char *, int),
                              void *mark_ctx);

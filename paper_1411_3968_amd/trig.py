@@ -53,7 +53,8 @@ class Result(C.Structure):
     _fields_ = [("fires", C.c_void_p), ("fire_cap", C.c_uint64), ("n_fires", C.c_uint64),
                 ("events", C.c_void_p), ("event_cap", C.c_uint64), ("n_events", C.c_uint64),
                 ("seed_flags", C.c_void_p), ("n_hits", C.c_uint64), ("n_seeds", C.c_uint64),
-                ("tag", C.c_uint64), ("status", C.c_int32), ("path", C.c_uint32)]
+                ("tag", C.c_uint64), ("status", C.c_int32), ("path", C.c_uint32),
+                ("tagged", C.c_void_p), ("tagged_cap", C.c_uint64), ("n_tagged", C.c_uint64)]
 
 
 class Tune(C.Structure):
@@ -71,7 +72,7 @@ class StreamStats(C.Structure):
                 ("device_bytes_peak", C.c_uint64), ("rounds", C.c_uint64)]
 
 
-assert C.sizeof(Result) == 88 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 20
+assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 20
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
            "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
@@ -197,10 +198,11 @@ def slice_desc(geom_id: int, pmt, t, q, tag: int = 0):
 class ResultBuffers:
     """Host buffers of one result record."""
 
-    def __init__(self, fire_cap: int, event_cap: int, n_hits: int, seed_flags: bool):
+    def __init__(self, fire_cap: int, event_cap: int, n_hits: int, seed_flags: bool, tagged_cap: int | None = None):
         self.fires = np.zeros(max(fire_cap, 1), FIRE_DTYPE)
         self.events = np.zeros(max(event_cap, 1), EVENT_DTYPE)
         self.flags = np.zeros(max(n_hits, 1), np.uint8) if seed_flags else None
+        self.tagged = np.zeros(max(tagged_cap, 1), np.uint32) if tagged_cap is not None else None
         self.rec = Result()
         self.reset()
 
@@ -211,6 +213,8 @@ class ResultBuffers:
         r.events = self.events.ctypes.data
         r.event_cap = len(self.events)
         r.seed_flags = self.flags.ctypes.data if self.flags is not None else None
+        r.tagged = self.tagged.ctypes.data if self.tagged is not None else None
+        r.tagged_cap = len(self.tagged) if self.tagged is not None else 0
 
     def as_dict(self, copy: bool = True) -> dict:
         """Counts and lists of the record; ``copy=False`` returns views into the
@@ -224,6 +228,9 @@ class ResultBuffers:
                    events=cp(self.events[:r.n_events] if ok else self.events[:0]))
         if self.flags is not None:
             out["seed_flags"] = cp(self.flags[:r.n_hits] if ok else self.flags[:0])
+        if self.tagged is not None:
+            out["n_tagged"] = int(r.n_tagged)
+            out["tagged"] = cp(self.tagged[:r.n_tagged] if ok else self.tagged[:0])
         return out
 
 
@@ -241,8 +248,10 @@ def _stream_ptr(stream):
 
 def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed_flags: bool = False,
                fire_cap: int | None = None, event_cap: int | None = None, stream=None, tag: int = 0,
-               raise_on_error: bool = True) -> dict:
-    """Trigger one slice; retries once with exact capacities on TRIG_EOVERFLOW."""
+               raise_on_error: bool = True, tagged: bool = False, tagged_cap: int | None = None) -> dict:
+    """Trigger one slice; retries once with exact capacities on TRIG_EOVERFLOW.
+    ``tagged=True`` also returns the input indices of the hits inside the event
+    windows (``tagged``, ordered by time, PMT, input index)."""
     d, keep = slice_desc(geom_id, pmt, t, q, tag)
     n = int(d.n_hits)
     fc, ec = _default_caps(n)
@@ -253,11 +262,14 @@ def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed
         import torch
         stream = torch.cuda.current_stream()
     sp = _stream_ptr(stream)
+    tc = (tagged_cap if tagged_cap is not None else max(4096, n // 8)) if tagged else None
     for attempt in range(2):
-        rb = ResultBuffers(fc, ec, n, seed_flags)
+        rb = ResultBuffers(fc, ec, n, seed_flags, tc)
         rc = _LIB.trig_slice(ctx, C.byref(d), C.byref(prm), C.byref(rb.rec), sp)
-        if rc == TRIG_EOVERFLOW and attempt == 0 and fire_cap is None and event_cap is None:
+        if rc == TRIG_EOVERFLOW and attempt == 0 and fire_cap is None and event_cap is None \
+                and (not tagged or tagged_cap is None):
             fc, ec = int(rb.rec.n_fires), int(rb.rec.n_events)
+            tc = int(rb.rec.n_tagged) if tagged else None
             continue
         break
     del keep
@@ -267,8 +279,9 @@ def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed
 
 
 def trig_batch(ctx, slices, params: dict | None = None, *, seed_flags: bool = False, stream=None,
-               caps=None) -> list:
-    """``slices``: list of ``(geom_id, pmt, t, q)``.  Returns one dict per slice."""
+               caps=None, tagged: bool = False) -> list:
+    """``slices``: list of ``(geom_id, pmt, t, q)``.  Returns one dict per slice
+    (with ``tagged``, the hits inside the event windows, when asked for)."""
     n = len(slices)
     descs = (SliceDesc * max(n, 1))()
     keep = []
@@ -284,8 +297,10 @@ def trig_batch(ctx, slices, params: dict | None = None, *, seed_flags: bool = Fa
     sp = _stream_ptr(stream)
     prm = params_struct(params)
     caps = caps or [_default_caps(x) for x in ns]
+    tcaps = [max(4096, x // 8) for x in ns] if tagged else None
     for attempt in range(2):
-        bufs = [ResultBuffers(caps[i][0], caps[i][1], ns[i], seed_flags) for i in range(n)]
+        bufs = [ResultBuffers(caps[i][0], caps[i][1], ns[i], seed_flags, tcaps[i] if tagged else None)
+                for i in range(n)]
         recs = (Result * max(n, 1))()
         for i in range(n):
             recs[i] = bufs[i].rec
@@ -294,6 +309,8 @@ def trig_batch(ctx, slices, params: dict | None = None, *, seed_flags: bool = Fa
         if over and attempt == 0:
             caps = [(max(int(recs[i].n_fires), caps[i][0]), max(int(recs[i].n_events), caps[i][1]))
                     for i in range(n)]
+            if tagged:
+                tcaps = [max(int(recs[i].n_tagged), tcaps[i]) for i in range(n)]
             continue
         break
     out = []

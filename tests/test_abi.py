@@ -42,7 +42,7 @@ def test_binding_mirrors_the_abi_names():
 def test_struct_sizes_match_header():
     from paper_1411_3968_amd import trig as T
     assert T.FIRE_DTYPE.itemsize == 24 and T.EVENT_DTYPE.itemsize == 32
-    assert ctypes.sizeof(T.Result) == 88
+    assert ctypes.sizeof(T.Result) == 112
     assert ctypes.sizeof(T.SliceDesc) == 48
 
 
