@@ -31,6 +31,7 @@ ALGO_BYTES_PER_HIT = {
     "k_segsort": 24.0,     # read t, pmt, q (12) + write ordered t, pmt|q, index (12)
     "k_segsort_w": 24.0,   # the same, one wave per segment
     "k_tile": 8.0,         # read ordered t + pmt|q (8): seeds and causal folds; fires are per fire
+    "k_tag_bits": 4.125,   # read ordered t (4) + write one tag bit; the few event windows are per event
 }
 
 
@@ -80,6 +81,38 @@ def _dev_slice(torch, dev, s):
 
 def _pct(x, p):
     return round(float(np.percentile(np.asarray(x), p)), 4) if len(x) else None
+
+
+def bench_tagging(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream):
+    """The same slice with the tagged-hit list asked for (hits inside the event
+    windows, extracted to the host): step time and the tagging kernels."""
+    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, params, stream=stream, tagged=True)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    tagged = r["tagged"].copy()
+    T.trig_profile_enable(tr.ctx, True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    prof = T.trig_profile_read(tr.ctx)
+    T.trig_profile_enable(tr.ctx, False)
+    kernels = {}
+    for p in prof:
+        if not p["name"].startswith("k_tag"):
+            continue
+        avg_us = p["total_ms"] / max(1, p["launches"]) * 1e3
+        e = dict(avg_us=round(avg_us, 3), launches=int(p["launches"]))
+        if p["name"] in ALGO_BYTES_PER_HIT:
+            e["gbs"] = round(ALGO_BYTES_PER_HIT[p["name"]] * n / (avg_us * 1e-6) / 1e9, 1)
+        kernels[p["name"]] = e
+    return dict(value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4), n_tagged=int(r["n_tagged"]),
+                kernels=kernels), tagged
 
 
 def bench_batch(T, torch, dev, a):
@@ -321,6 +354,8 @@ def main():
                     frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom),
                     bytes_per_hit=ALGO_BYTES_PER_HIT[dom], hits_per_launch=n)
 
+    tagging, tagged = bench_tagging(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
+
     cpu = None
     if not a.no_cpu:
         from oracle import cpu as orc
@@ -333,6 +368,8 @@ def main():
             tc += time.perf_counter() - c0
             reps += 1
         assert np.array_equal(ref["fires"], r["fires"]) and np.array_equal(ref["events"], r["events"])
+        tagging["equals_oracle"] = bool(np.array_equal(orc.tag(s.pmt, s.t, ref["fires"], w.params["half_event_ns"]),
+                                                       tagged))
         cpu = dict(value=round(n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
                    sample=f"blocked form, whole {n}-hit slice x {reps} runs ({tc:.1f} s)")
 
@@ -362,6 +399,7 @@ def main():
         kernels=per_kernel,
         cpu_baseline=cpu,
         results=dict(n_seeds=r["n_seeds"], n_fires=r["n_fires"], n_events=r["n_events"], path=r["path"]),
+        tagging=tagging,
         batched=batch,
         serving=serving,
     )

@@ -412,12 +412,13 @@ class SliceRunner:
     """
 
     def __init__(self, ctx, geom_id, pmt, t, q, params=None, *, stream=None, fire_cap=None, event_cap=None,
-                 seed_flags=False):
+                 seed_flags=False, tagged=False, tagged_cap=None):
         self.ctx = ctx
         self.desc, self._keep = slice_desc(geom_id, pmt, t, q)
         n = int(self.desc.n_hits)
         fc, ec = _default_caps(n)
-        self.buf = ResultBuffers(fire_cap or fc, event_cap or ec, n, seed_flags)
+        tc = (tagged_cap or max(4096, n // 8)) if tagged else None
+        self.buf = ResultBuffers(fire_cap or fc, event_cap or ec, n, seed_flags, tc)
         self.prm = params_struct(params)
         if stream is None and _is_torch(t):
             import torch
@@ -434,6 +435,9 @@ class SliceRunner:
                    path=int(r.path), fires=self.buf.fires[:r.n_fires], events=self.buf.events[:r.n_events])
         if self.buf.flags is not None:
             out["seed_flags"] = self.buf.flags[:r.n_hits]
+        if self.buf.tagged is not None:
+            out["n_tagged"] = int(r.n_tagged)
+            out["tagged"] = self.buf.tagged[:r.n_tagged]
         return out
 
 
