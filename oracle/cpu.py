@@ -30,7 +30,8 @@ assert FIRE_DTYPE.itemsize == 24 and EVENT_DTYPE.itemsize == 32
 
 class Params(C.Structure):
     _fields_ = [("q_seed", C.c_uint32), ("t_floor_ns", C.c_int32), ("w_ns", C.c_uint32),
-                ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32)]
+                ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32),
+                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32)]
 
 
 def build(force: bool = True) -> str:
@@ -66,7 +67,8 @@ def _load():
 
 def _params(p: dict) -> Params:
     return Params(int(p.get("q_seed", 300)), int(p.get("t_floor_ns", 20)), int(p.get("w_ns", 3000)),
-                  int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)))
+                  int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)),
+                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))))
 
 
 def _ptr(a):

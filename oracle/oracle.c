@@ -28,6 +28,13 @@
  *           tagged): each fire opens [t-H, t+H]; walking F in order, a fire
  *           whose window starts at or before the current event's end extends
  *           it, otherwise it opens a new event.
+ *   level 0 (optional; Sec. 3: a level-0 trigger of N hits in a fixed time
+ *           window TW, N7TW1000, N7TW500 for the 84-PMT tower; Sec. 4.1:
+ *           DN7TW1000 counts hits of different PMTs): with N = l0_n > 0,
+ *     L_k = there is a hit i with t_i <= t_k < t_i + TW whose window
+ *           [t_i, t_i + TW) holds >= N hits (>= N distinct PMTs for DN);
+ *           the seed rule then runs on the hits that pass: S_k requires L_k,
+ *           and a floor partner m requires L_m
  *   tagged hits (Sec. 4.2: the hits within +-3 us of a trigger seed are
  *           tagged to be saved): T = { k : |t_k - t_f| <= H for some f in F },
  *           ordered by (t, p, k)
@@ -58,6 +65,9 @@ typedef struct {
     uint32_t w_ns;
     uint32_t min_fold;
     uint32_t half_event_ns;
+    uint32_t l0_n;           /* level-0 prefilter: hits (0 = off) ... */
+    uint32_t l0_tw_ns;       /* ... within this window ... */
+    uint32_t l0_distinct;    /* ... counting distinct PMTs when set */
 } orc_params;
 
 typedef struct {
@@ -99,9 +109,10 @@ int orc_validate(uint64_t n, const uint16_t *pmt, const int64_t *t, uint32_t n_p
 /* ---------------------------------------------------------------- strict */
 
 static int floor_partner_strict(uint64_t n, const uint16_t *pmt, const int64_t *t,
-                                const int32_t *floor_id, uint64_t k, int64_t tau)
+                                const int32_t *floor_id, const uint8_t *l0, uint64_t k, int64_t tau)
 {
     for (uint64_t m = 0; m < n; ++m) {
+        if (l0 && !l0[m]) continue;
         if (pmt[m] == pmt[k]) continue;
         if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
         if (absdiff(t[k], t[m]) <= tau) return 1;
@@ -110,13 +121,14 @@ static int floor_partner_strict(uint64_t n, const uint16_t *pmt, const int64_t *
 }
 
 static void seeds_strict(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
-                         const int32_t *floor_id, const orc_params *prm, uint8_t *seed)
+                         const int32_t *floor_id, const uint8_t *l0, const orc_params *prm, uint8_t *seed)
 {
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t k = 0; k < (int64_t)n; ++k) {
+        if (l0 && !l0[k]) { seed[k] = 0; continue; }
         int s = q[k] >= prm->q_seed;
         if (!s && prm->t_floor_ns >= 0)
-            s = floor_partner_strict(n, pmt, t, floor_id, (uint64_t)k, prm->t_floor_ns);
+            s = floor_partner_strict(n, pmt, t, floor_id, l0, (uint64_t)k, prm->t_floor_ns);
         seed[k] = (uint8_t)s;
     }
 }
@@ -184,9 +196,9 @@ static int make_blocks(uint64_t n, const int64_t *t, const uint8_t *sel, uint64_
 static void free_blocks(blocks *B) { free(B->start); free(B->member); }
 
 static int seeds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
-                         const int32_t *floor_id, const orc_params *prm, uint8_t *seed)
+                         const int32_t *floor_id, const uint8_t *l0, const orc_params *prm, uint8_t *seed)
 {
-    for (uint64_t k = 0; k < n; ++k) seed[k] = q[k] >= prm->q_seed;
+    for (uint64_t k = 0; k < n; ++k) seed[k] = q[k] >= prm->q_seed && (!l0 || l0[k]);
     if (prm->t_floor_ns < 0 || n == 0) return ORC_OK;
     blocks B;
     int rc = make_blocks(n, t, NULL, (uint64_t)prm->t_floor_ns, &B);
@@ -194,13 +206,14 @@ static int seeds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, cons
     const int64_t tau = prm->t_floor_ns;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t k = 0; k < (int64_t)n; ++k) {
-        if (seed[k]) continue;
+        if (seed[k] || (l0 && !l0[k])) continue;
         uint64_t b = (uint64_t)(t[k] - B.t_lo) / B.width;
         uint64_t b0 = b ? b - 1 : 0, b1 = b + 1 < B.nb ? b + 1 : b;
         int s = 0;
         for (uint64_t bb = b0; bb <= b1 && !s; ++bb)
             for (uint64_t i = B.start[bb]; i < B.start[bb + 1]; ++i) {
                 uint32_t m = B.member[i];
+                if (l0 && !l0[m]) continue;
                 if (pmt[m] == pmt[k]) continue;
                 if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
                 if (absdiff(t[k], t[m]) <= tau) { s = 1; break; }
@@ -235,6 +248,89 @@ static int folds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, cons
     }
     free_blocks(&B);
     return ORC_OK;
+}
+
+/* --------------------------------------------------------------- level 0 */
+
+/* Size of the window [t0, t0 + tw) over the candidates idx[0..nc): its hits,
+ * or its distinct PMTs when distinct is set (seen[] has room for nc). */
+static uint64_t window_count(const uint16_t *pmt, const int64_t *t, int64_t t0, int64_t tw,
+                             const uint32_t *idx, uint64_t nc, int distinct, uint16_t *seen)
+{
+    uint64_t c = 0;
+    for (uint64_t u = 0; u < nc; ++u) {
+        const uint32_t m = idx[u];
+        if (t[m] < t0 || t[m] - t0 >= tw) continue;
+        if (distinct) {
+            int dup = 0;
+            for (uint64_t v = 0; v < c; ++v)
+                if (seen[v] == pmt[m]) { dup = 1; break; }
+            if (dup) continue;
+            seen[c] = pmt[m];
+        }
+        ++c;
+    }
+    return c;
+}
+
+/* L_k for every hit.  strict: every hit is a candidate window start and a
+ * candidate member; blocked: the same tests restricted to time blocks of
+ * width >= TW (a window [t_i, t_i + TW) lies in t_i's block and the next; a
+ * window holding t_k starts in t_k's block or the one before). */
+static int level0(int strict, uint64_t n, const uint16_t *pmt, const int64_t *t, const orc_params *prm,
+                  uint8_t *pass)
+{
+    const int64_t tw = prm->l0_tw_ns;
+    const uint64_t need = prm->l0_n;
+    const int distinct = prm->l0_distinct != 0;
+    uint8_t *ok = (uint8_t *)calloc(n ? n : 1, 1);
+    uint32_t *all = NULL;
+    uint16_t *seen = NULL;
+    blocks B;
+    B.start = NULL; B.member = NULL;
+    int rc = ORC_OK;
+    if (!ok) return ORC_ENOMEM;
+    if (strict) {
+        all = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+        seen = (uint16_t *)malloc((n ? n : 1) * sizeof(uint16_t));
+        if (!all || !seen) { rc = ORC_ENOMEM; goto out; }
+        for (uint64_t k = 0; k < n; ++k) all[k] = (uint32_t)k;
+        /* window starting at hit i */
+        for (uint64_t i = 0; i < n; ++i) ok[i] = window_count(pmt, t, t[i], tw, all, n, distinct, seen) >= need;
+        for (uint64_t k = 0; k < n; ++k) {
+            pass[k] = 0;
+            for (uint64_t i = 0; i < n && !pass[k]; ++i)
+                if (ok[i] && t[i] <= t[k] && t[k] - t[i] < tw) pass[k] = 1;
+        }
+    } else {
+        rc = make_blocks(n, t, NULL, (uint64_t)(tw > 0 ? tw : 1), &B);
+        if (rc) goto out;
+        uint64_t most = 1;
+        for (uint64_t b = 0; b < B.nb; ++b) {
+            const uint64_t e = b + 2 <= B.nb ? B.start[b + 2] : B.start[B.nb];
+            if (e - B.start[b] > most) most = e - B.start[b];
+        }
+        seen = (uint16_t *)malloc(most * sizeof(uint16_t));
+        if (!seen) { rc = ORC_ENOMEM; goto out; }
+        for (uint64_t i = 0; i < n; ++i) {
+            const uint64_t b = (uint64_t)(t[i] - B.t_lo) / B.width;
+            const uint64_t e = b + 2 <= B.nb ? B.start[b + 2] : B.start[B.nb];
+            ok[i] = window_count(pmt, t, t[i], tw, B.member + B.start[b], e - B.start[b], distinct, seen) >= need;
+        }
+        for (uint64_t k = 0; k < n; ++k) {
+            const uint64_t b = (uint64_t)(t[k] - B.t_lo) / B.width;
+            const uint64_t b0 = b ? b - 1 : 0;
+            pass[k] = 0;
+            for (uint64_t u = B.start[b0]; u < B.start[b + 1] && !pass[k]; ++u) {
+                const uint32_t i = B.member[u];
+                if (ok[i] && t[i] <= t[k] && t[k] - t[i] < tw) pass[k] = 1;
+            }
+        }
+    }
+out:
+    free(ok); free(all); free(seen);
+    if (B.start || B.member) free_blocks(&B);
+    return rc;
 }
 
 /* ------------------------------------------------------- fires and events */
@@ -338,15 +434,22 @@ int orc_run(int form, uint64_t n, const uint16_t *pmt, const int64_t *t, const u
 #endif
     int rc = orc_validate(n, pmt, t, n_pmt, prm);
     if (rc) return rc;
+    uint8_t *l0 = NULL;
+    if (prm->l0_n > 0 && n) {
+        l0 = (uint8_t *)malloc(n);
+        if (!l0) return ORC_ENOMEM;
+        rc = level0(form == 0, n, pmt, t, prm, l0);
+        if (rc) { free(l0); return rc; }
+    }
     if (form == 0) {
-        seeds_strict(n, pmt, t, q, floor_id, prm, seed_out);
+        seeds_strict(n, pmt, t, q, floor_id, l0, prm, seed_out);
         folds_strict(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
     } else {
-        rc = seeds_blocked(n, pmt, t, q, floor_id, prm, seed_out);
-        if (rc) return rc;
-        rc = folds_blocked(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
-        if (rc) return rc;
+        rc = seeds_blocked(n, pmt, t, q, floor_id, l0, prm, seed_out);
+        if (!rc) rc = folds_blocked(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
+        if (rc) { free(l0); return rc; }
     }
+    free(l0);
     *n_fires = collect_fires(n, pmt, t, seed_out, fold_out, prm->min_fold, fires);
     *n_events = orc_events(fires, *n_fires, prm->half_event_ns, events);
     return ORC_OK;
@@ -367,6 +470,7 @@ int orc_point(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t 
 #endif
     int rc = orc_validate(n, pmt, t, n_pmt, prm);
     if (rc) return rc;
+    if (prm->l0_n) return ORC_EINVAL;   /* sampled checks cover the rule without level 0 */
     const int64_t tau = prm->t_floor_ns;
     const int64_t reach = (int64_t)prm->w_ns + (tau > 0 ? tau : 0);
     int fail = 0;

@@ -340,3 +340,107 @@ def test_tag_special_cases(oracle_lib, mid_slice):
     z = oracle_lib.tag(s.pmt, s.t, f, 0)
     assert set(z.tolist()) == set(np.flatnonzero(np.isin(s.t, f["t_ns"])).tolist())
     assert set(f["hit_index"].tolist()) <= set(z.tolist())
+
+
+# ------------------------------------------------------------- level 0 (N hits in TW)
+
+def _l0_flags(oracle_lib, pmt, t, n_pmt, form="strict", **l0):
+    """Level-0 pass flags read through the seed rule: every charge is over a zero
+    threshold and the floor rule is off, so a hit is a seed exactly when it passes."""
+    pmt = np.asarray(pmt, np.uint16)
+    t = np.asarray(t, np.int64)
+    prm = dict(q_seed=0, t_floor_ns=-1, w_ns=0, min_fold=1, half_event_ns=0, **l0)
+    r = oracle_lib.run(pmt, t, np.zeros(len(t), np.uint16), np.zeros(n_pmt, np.int32),
+                       np.zeros((n_pmt, n_pmt), np.uint32), prm, form)
+    assert r["status"] == 0
+    return r["seed"].astype(bool)
+
+
+@pytest.mark.parametrize("form", ["strict", "blocked"])
+def test_l0_hand_example(oracle_lib, form):
+    """Worked by hand, N = 3, TW = 100 ns: the windows [0, 100) and [260, 360)
+    hold three hits each, and so do the three equal times at 1000; the hit at
+    150 sees at most two (the window is half-open)."""
+    t = [0, 40, 99, 150, 260, 300, 330, 1000, 1000, 1000]
+    got = _l0_flags(oracle_lib, [0, 1, 2, 3, 0, 1, 2, 0, 1, 1], t, 4, form, l0_n=3, l0_tw_ns=100)
+    assert got.tolist() == [True, True, True, False, True, True, True, True, True, True]
+    # strict window: two hits 100 ns apart are not within TW = 100, 99 ns apart are
+    assert _l0_flags(oracle_lib, [0, 1], [0, 100], 2, form, l0_n=2, l0_tw_ns=100).tolist() == [False, False]
+    assert _l0_flags(oracle_lib, [0, 1], [0, 99], 2, form, l0_n=2, l0_tw_ns=100).tolist() == [True, True]
+
+
+@pytest.mark.parametrize("form", ["strict", "blocked"])
+def test_l0_distinct_pmts_hand_example(oracle_lib, form):
+    """DN with N = 3, TW = 100 ns: four hits of two PMTs do not pass; a hit of a
+    third PMT inside the window lets all five pass.  Counting hits (not PMTs),
+    the four already pass."""
+    pmt, t = [1, 1, 2, 2], [0, 10, 20, 50]
+    assert not _l0_flags(oracle_lib, pmt, t, 4, form, l0_n=3, l0_tw_ns=100, l0_distinct=1).any()
+    assert _l0_flags(oracle_lib, pmt, t, 4, form, l0_n=3, l0_tw_ns=100).all()
+    assert _l0_flags(oracle_lib, pmt + [3], t + [90], 4, form, l0_n=3, l0_tw_ns=100, l0_distinct=1).all()
+
+
+def test_l0_restricts_floor_partners(oracle_lib):
+    """Floor coincidences count only between hits that pass level 0: E and F
+    (t = 400, 410; the same floor) are partners but fail N = 3 in TW = 50 ns."""
+    hits = [(0, 0), (10, 1), (20, 2), (400, 0), (410, 1), (1000, 0), (1005, 2), (1010, 3)]
+    t = np.array([h[0] for h in hits], np.int64)
+    pmt = np.array([h[1] for h in hits], np.uint16)
+    floor_id = np.array([0, 0, 1, 1], np.int32)
+    thr = np.zeros((4, 4), np.uint32)
+    base = dict(q_seed=300, t_floor_ns=20, w_ns=0, min_fold=1, half_event_ns=0)
+    q = np.zeros(len(t), np.uint16)
+    for form in ("strict", "blocked"):
+        on = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, l0_n=3, l0_tw_ns=50), form)
+        off = oracle_lib.run(pmt, t, q, floor_id, thr, base, form)
+        assert on["seed"].tolist() == [1, 1, 0, 0, 0, 0, 1, 1]
+        assert off["seed"].tolist() == [1, 1, 0, 1, 1, 0, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_l0_equals_consecutive_hits_form(oracle_lib, seed):
+    """Counting hits, a hit passes exactly when it lies in some run of N hits
+    that are consecutive in time order and span less than TW (the sliding form
+    t[i + N - 1] - t[i] < TW), computed here with numpy on the sorted times."""
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(200, 3000))
+    N, TW = int(rng.integers(2, 9)), int(rng.integers(50, 2000))
+    t = rng.integers(0, n * 300, size=n).astype(np.int64)
+    t[: n // 10] = t[0] + rng.integers(0, 3, size=n // 10)      # ties
+    pmt = rng.integers(0, 8, size=n).astype(np.uint16)
+    got = _l0_flags(oracle_lib, pmt, t, 8, "blocked", l0_n=N, l0_tw_ns=TW)
+    order = np.lexsort((np.arange(n), pmt, t))
+    ts = t[order]
+    ok = np.zeros(n, bool)
+    if n >= N:
+        ok[: n - N + 1] = ts[N - 1:] - ts[: n - N + 1] < TW
+    run_pass = np.convolve(ok.astype(int), np.ones(N, int))[:n] > 0   # some window start in [j-N+1, j]
+    want = np.zeros(n, bool)
+    want[order] = run_pass
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_l0_strict_blocked_and_variants_agree(oracle_lib, seed):
+    """Strict (all windows, all members) and blocked forms agree; the distinct
+    variant passes a subset; N = 1 is the same as no level 0."""
+    rng = np.random.default_rng(950 + seed)
+    n = int(rng.integers(100, 1500))
+    P = 12
+    t = rng.integers(0, n * 200, size=n).astype(np.int64) + 10**12
+    pmt = rng.integers(0, P, size=n).astype(np.uint16)
+    q = rng.integers(0, 600, size=n).astype(np.uint16)
+    floor_id = rng.integers(0, 3, size=P).astype(np.int32)
+    thr = rng.integers(0, 3000, size=(P, P)).astype(np.uint32)
+    base = dict(q_seed=400, t_floor_ns=30, w_ns=3000, min_fold=2, half_event_ns=500)
+    for l0 in (dict(l0_n=4, l0_tw_ns=800), dict(l0_n=4, l0_tw_ns=800, l0_distinct=1), dict(l0_n=7, l0_tw_ns=1000)):
+        a = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, **l0), "strict")
+        b = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, **l0), "blocked")
+        assert np.array_equal(a["seed"], b["seed"]) and np.array_equal(a["fold"], b["fold"])
+        assert np.array_equal(a["fires"], b["fires"]) and np.array_equal(a["events"], b["events"])
+    dn = _l0_flags(oracle_lib, pmt, t, P, "blocked", l0_n=4, l0_tw_ns=800, l0_distinct=1)
+    nn = _l0_flags(oracle_lib, pmt, t, P, "blocked", l0_n=4, l0_tw_ns=800)
+    assert not (dn & ~nn).any() and dn.sum() < nn.sum()
+    one = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, l0_n=1, l0_tw_ns=1), "blocked")
+    off = oracle_lib.run(pmt, t, q, floor_id, thr, base, "blocked")
+    assert np.array_equal(one["seed"], off["seed"]) and np.array_equal(one["fires"], off["fires"])
