@@ -92,13 +92,26 @@ int trig_geom_load(trig_ctx *ctx, const trig_geom_desc *geom, uint32_t *geom_id)
  *   t_floor_ns    floor-coincidence window (inclusive); < 0 disables the rule
  *   w_ns          cap on the causal window (the table value is min(thr, w_ns))
  *   min_fold      fire when 1 + correlated seeds >= min_fold
- *   half_event_ns half width H of the event window [t - H, t + H] */
+ *   half_event_ns half width H of the event window [t - H, t + H]
+ *   l0_n, l0_tw_ns, l0_distinct
+ *                 level-0 prefilter (paper Sec. 3: N hits in a fixed time window
+ *                 TW, N7TW1000; N7TW500 for the 84-PMT tower; Sec. 4.1:
+ *                 DN7TW1000 counts hits of distinct PMTs).  l0_n = 0 turns it
+ *                 off.  Otherwise a hit passes when a window [t_i, t_i + l0_tw_ns)
+ *                 that starts at a hit i and holds it also holds >= l0_n hits
+ *                 (>= l0_n distinct PMTs when l0_distinct != 0), and the seed
+ *                 rule runs on the hits that pass: a seed and its floor partner
+ *                 both pass.  TRIG_EINVAL unless 1 <= l0_n <= 64 and
+ *                 1 <= l0_tw_ns <= 1000000 when it is on. */
 typedef struct {
     uint32_t q_seed;
     int32_t  t_floor_ns;
     uint32_t w_ns;
     uint32_t min_fold;
     uint32_t half_event_ns;
+    uint32_t l0_n;
+    uint32_t l0_tw_ns;
+    uint32_t l0_distinct;
 } trig_params;
 
 enum { TRIG_MEM_HOST = 0, TRIG_MEM_DEVICE = 1 };

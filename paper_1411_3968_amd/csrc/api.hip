@@ -184,6 +184,7 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.events = take(n * sizeof(trig_event) + 32);
     L.flags = want_flags ? take(n + 4) : SIZE_MAX;
     L.tagc = take(std::max<uint64_t>(n_tiles, 1) * 4);
+    L.l0m = take((n / 64 + 1) * 8);
     return o;
 }
 
@@ -371,6 +372,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.tagc = (uint32_t *)(b + L.tagc);
         S.tagged = (uint32_t *)(b + L.fsc);   // free once the fires are placed
         S.tag_on = si.want_tag && si.host_status == TRIG_OK ? 1u : 0u;
+        S.l0m = (uint64_t *)(b + L.l0m);
         hs[i] = S;
         si.dev = S;
     }
@@ -643,13 +645,17 @@ void Job::release(trig_ctx *c) {
     h_plans.release();
 }
 
-static int check_params(trig_ctx *c, const trig_params *p) {
+int check_params(trig_ctx *c, const trig_params *p) {
     if (!p) {
         ctx_set_error(c, "null params");
         return TRIG_EINVAL;
     }
     if ((uint64_t)p->half_event_ns > (1ull << 62)) {
         ctx_set_error(c, "half_event_ns too large");
+        return TRIG_EINVAL;
+    }
+    if (p->l0_n > 0 && (p->l0_n > 64 || p->l0_tw_ns == 0 || p->l0_tw_ns > 1000000)) {
+        ctx_set_error(c, "level 0 needs 1 <= l0_n <= 64 and 1 <= l0_tw_ns <= 1000000");
         return TRIG_EINVAL;
     }
     return TRIG_OK;

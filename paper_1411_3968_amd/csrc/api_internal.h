@@ -36,7 +36,7 @@ struct GeomDev {
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
 struct SliceLayout {
-    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags, tagc;
+    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags, tagc, l0m;
     uint64_t pos_cap;
 };
 
@@ -147,3 +147,4 @@ void serve_shutdown(trig_ctx *c);
 size_t slice_footprint(uint64_t n, bool host_input);
 // Device bytes of a job's descriptors, plans and counters for n slices.
 size_t job_meta_bytes(uint32_t n);
+int check_params(trig_ctx *c, const trig_params *p);   // TRIG_OK or TRIG_EINVAL (message set)

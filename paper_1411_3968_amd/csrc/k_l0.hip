@@ -1,0 +1,120 @@
+// Level-0 prefilter (paper Sec. 3: a level-0 trigger of N hits in a fixed time
+// window TW, N7TW1000, and N7TW500 for the 84-PMT tower; Sec. 4.1: DN7TW1000
+// asks for hits of N different PMTs).  On the time-ordered hits of a slice, a
+// hit passes when some window [t_i, t_i + TW) that starts at a hit i and holds
+// the hit also holds >= N hits (>= N distinct PMTs for the DN form).  The seed
+// rule then runs on the hits that pass.
+//   k_l0_ok    per ordered position i: the window starting at i holds enough
+//              (counting hits: t[i + N - 1] - t[i] < TW)
+//   k_l0_pass  per ordered position x: some start i <= x within TW of it is ok
+//              (counting hits, the starts x - N + 1 .. x suffice)
+// Both write one ballot word per 64 positions; the ok words live in the seed
+// mask area, which the dense rerun overwrites later, the pass words in their own.
+#include "trig_dev.h"
+
+using namespace trigdev;
+
+namespace {
+
+constexpr int NTL = 256;
+static_assert(TILE % NTL == 0, "tile layout");
+
+__device__ __forceinline__ bool l0_slice(const BatchDev &b, const SliceDev &S, uint32_t &k, uint32_t si,
+                                         uint32_t item) {
+    k = item - tile_base_of(b, si);
+    if (k >= S.n_tiles) return false;
+    return slice_in_tail(b, gmem(S.plan)->state);
+}
+
+__global__ __launch_bounds__(NTL) void k_l0_ok(BatchDev b) {
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const SliceDev &S = b.slices[si];
+    uint32_t k;
+    if (!l0_slice(b, S, k, si, item)) return;
+    const uint64_t n = S.n;
+    const uint64_t a = (uint64_t)k * TILE;
+    if (a >= n) return;
+    const uint64_t e = (a + TILE < n) ? a + TILE : n;
+    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
+    const TRIG_GAS uint32_t *o_pq = gmem(S.o_pq);
+    TRIG_GAS uint64_t *okw = gmem(S.dmask);
+    const uint32_t N = b.prm.l0_n, TW = b.prm.l0_tw_ns;
+    const bool distinct = b.prm.l0_distinct != 0;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    for (uint32_t x0 = 0; x0 < (uint32_t)TILE; x0 += NTL) {
+        const uint64_t i = a + x0 + threadIdx.x;
+        bool ok = false;
+        if (i < e) {
+            const uint32_t ti = o_t[i];
+            if (!distinct) {
+                ok = i + N - 1 < n && o_t[i + N - 1] - ti < TW;
+            } else {
+                // distinct PMTs among the hits from i on within TW (stop at N)
+                uint32_t c = 0;
+                for (uint64_t m = i; m < n && o_t[m] - ti < TW && c < N; ++m) {
+                    const uint32_t pm = o_pq[m] >> 16;
+                    bool dup = false;
+                    for (uint64_t u = i; u < m && !dup; ++u) dup = (o_pq[u] >> 16) == pm;
+                    c += dup ? 0u : 1u;
+                }
+                ok = c >= N;
+            }
+        }
+        const uint64_t bal = __ballot(ok);
+        if (lane == 0 && a + x0 + (uint32_t)w * 64 < e) okw[(a + x0) / 64 + w] = bal;
+    }
+}
+
+__device__ __forceinline__ bool bit_at(const TRIG_GAS uint64_t *wv, uint64_t j) { return (wv[j >> 6] >> (j & 63)) & 1ull; }
+
+__global__ __launch_bounds__(NTL) void k_l0_pass(BatchDev b) {
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const SliceDev &S = b.slices[si];
+    uint32_t k;
+    if (!l0_slice(b, S, k, si, item)) return;
+    const uint64_t n = S.n;
+    const uint64_t a = (uint64_t)k * TILE;
+    if (a >= n) return;
+    const uint64_t e = (a + TILE < n) ? a + TILE : n;
+    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
+    const TRIG_GAS uint64_t *okw = gmem(S.dmask);
+    TRIG_GAS uint64_t *pw = gmem(S.l0m);
+    const uint32_t N = b.prm.l0_n, TW = b.prm.l0_tw_ns;
+    const bool distinct = b.prm.l0_distinct != 0;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    for (uint32_t x0 = 0; x0 < (uint32_t)TILE; x0 += NTL) {
+        const uint64_t x = a + x0 + threadIdx.x;
+        bool pass = false;
+        if (x < e) {
+            const uint32_t tx = o_t[x];
+            // window starts at or before x (in time order) that still hold x
+            const uint64_t lo = distinct ? 0 : (x + 1 >= N ? x + 1 - N : 0);
+            for (uint64_t i = x + 1; i-- > lo && !pass;) {
+                if (tx - o_t[i] >= TW) break;
+                pass = bit_at(okw, i);
+            }
+        }
+        const uint64_t bal = __ballot(pass);
+        if (lane == 0 && a + x0 + (uint32_t)w * 64 < e) pw[(a + x0) / 64 + w] = bal;
+    }
+}
+
+}  // namespace
+
+#define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
+#define TRIG_CHECK() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+
+hipError_t trig_launch_l0(const BatchDev &b, hipStream_t s, void (*mark)(void *, const char *, int), void *mark_ctx) {
+    if (!b.total_tiles || b.prm.l0_n == 0) return hipSuccess;
+    TRIG_MARK("k_l0_ok", 0);
+    hipLaunchKernelGGL(k_l0_ok, dim3(b.total_tiles), dim3(NTL), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_l0_ok", 1);
+    TRIG_MARK("k_l0_pass", 0);
+    hipLaunchKernelGGL(k_l0_pass, dim3(b.total_tiles), dim3(NTL), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_l0_pass", 1);
+    return hipSuccess;
+}

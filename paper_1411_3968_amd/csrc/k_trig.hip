@@ -138,7 +138,8 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     uint32_t *ct = spf + STG;                        // compacted seeds: time
     uint32_t *fold = ct + CS;                        // fold of each seed of the tile
     uint64_t *sbits = (uint64_t *)(fold + CS);       // seed bits of the stage
-    uint32_t *wpre = (uint32_t *)(sbits + STG / 64); // seeds before each 64-hit word
+    uint64_t *l0w = sbits + STG / 64;                // level-0 pass bits of the stage (level 0 on)
+    uint32_t *wpre = (uint32_t *)(l0w + STG / 64);   // seeds before each 64-hit word
     uint16_t *cp = (uint16_t *)(wpre + STG / 64 + 1);   // compacted seeds: PMT
     uint16_t *cidx = cp + CS;                        // compacted seeds: stage position
     uint16_t *fci = cidx + CS;                       // fires: compacted index
@@ -188,6 +189,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const uint64_t sh_end = (e + halo < n) ? e + halo : n;
     const uint32_t len = (uint32_t)(sh_end - sl);
     const uint32_t q_seed = b.prm.q_seed;
+    // level 0 on: only hits that pass it may be seeds or floor partners
+    const bool L0 = !MASK && b.prm.l0_n > 0;
+    const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
     {
         // stage the times and PMTs with all loads of a thread in flight
         constexpr int U = (STG + NT - 1) / NT;
@@ -210,8 +214,17 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             if (!MASK) {
                 // charge seeds of the stage, a word per wave (the floor coincidences
                 // are added below); x / 64 is this wave's word
-                const uint64_t qb = __ballot(x < len && (vp[u] & 0xFFFFu) >= q_seed);
-                if (lane == 0 && u * NT + w * 64 < len) sbits[(u * NT) / 64 + w] = qb;
+                bool l0x = x < len;
+                if (L0 && x < len) {
+                    const uint64_t j = sl + x;
+                    l0x = (l0m[j >> 6] >> (j & 63)) & 1ull;
+                }
+                const uint64_t lb = __ballot(l0x);
+                const uint64_t qb = __ballot(x < len && (vp[u] & 0xFFFFu) >= q_seed) & lb;
+                if (lane == 0 && u * NT + w * 64 < len) {
+                    sbits[(u * NT) / 64 + w] = qb;
+                    l0w[(u * NT) / 64 + w] = lb;
+                }
             }
         }
         if (!MASK) __syncthreads();   // floor numbering complete
@@ -254,18 +267,22 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                 // (bitwise operators: no branch between the reads and their use)
                 const bool l_in = (x >= 1) & (t - tl <= tau_u);
                 const bool r_in = (x + 1 < len) & (tr - t <= tau_u);
-                seed = (l_in & floor_partner(fl, f)) | (r_in & floor_partner(fr, f));
+                // (level 0 on: the partner must pass it, and so must the hit)
+                auto l0b = [&](uint32_t y) -> bool { return !L0 || ((l0w[y >> 6] >> (y & 63)) & 1ull); };
+                seed = (l_in & floor_partner(fl, f) & l0b(xl)) | (r_in & floor_partner(fr, f) & l0b(xr));
                 if (!seed && (l_in || r_in)) {
                     for (uint32_t d = 2;; ++d) {
                         const bool ll = x >= d && t - st[x - d] <= tau_u;
                         const bool rr = x + d < len && st[x + d] - t <= tau_u;
                         if (!ll && !rr) break;
-                        if ((ll && floor_partner(spf[x - d], f)) || (rr && floor_partner(spf[x + d], f))) {
+                        if ((ll && floor_partner(spf[x - d], f) && l0b(x - d)) ||
+                            (rr && floor_partner(spf[x + d], f) && l0b(x + d))) {
                             seed = true;
                             break;
                         }
                     }
                 }
+                seed = seed && l0b(x);
             }
             const uint64_t bal = __ballot(seed);
             if (lane == 0 && x0 + w * 64 < len) {
@@ -675,11 +692,15 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     auto P_at = [&](uint64_t m) -> uint32_t { return ((m >= lo && m < hi) ? lpq[m - lo] : S.o_pq[m]) >> 16; };
     const uint32_t Q = b.prm.q_seed;
     const int32_t tau = b.prm.t_floor_ns;
+    // level 0 on: a seed and its floor partner must both pass it
+    const bool L0 = b.prm.l0_n > 0;
+    const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
+    auto l0_at = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
 #pragma unroll
     for (int e = 0; e < TILE / NTD; ++e) {
         const uint64_t j = a + (uint64_t)e * NTD + threadIdx.x;
         bool seed = false;
-        if (j < n) {
+        if (j < n && l0_at(j)) {
             const uint32_t t = lt[j - lo], pq = lpq[j - lo], p = pq >> 16;
             seed = (pq & 0xFFFFu) >= Q;
             if (!seed && tau >= 0) {
@@ -688,12 +709,12 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
                     --m;
                     if (t - T_at(m) > (uint32_t)tau) break;
                     const uint32_t pm = P_at(m);
-                    if (pm != p && S.floor16[pm] == f) { seed = true; break; }
+                    if (pm != p && S.floor16[pm] == f && l0_at(m)) { seed = true; break; }
                 }
                 for (uint64_t m = j + 1; !seed && m < n; ++m) {
                     if (T_at(m) - t > (uint32_t)tau) break;
                     const uint32_t pm = P_at(m);
-                    if (pm != p && S.floor16[pm] == f) seed = true;
+                    if (pm != p && S.floor16[pm] == f && l0_at(m)) seed = true;
                 }
             }
         }
@@ -706,7 +727,7 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
 template <int HMAX, bool MASK>
 constexpr size_t tile_lds_bytes() {
     constexpr size_t STG = TILE + 2 * HMAX, CS = compact_cap(HMAX, MASK);
-    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 + (STG / 64 + 1) * 4 + CS * 2 * 3;
+    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 * 2 + (STG / 64 + 1) * 4 + CS * 2 * 3;
 }
 
 template <int NT, int HMAX, bool MASK>
@@ -736,6 +757,11 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
 
 static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, bool dense, hipStream_t s,
                                  void (*mark)(void *, const char *, int), void *mark_ctx) {
+    if (!dense) {
+        // level-0 pass bits of the ordered hits (the dense rerun keeps the first pass's)
+        hipError_t e0 = trig_launch_l0(b, s, mark, mark_ctx);
+        if (e0 != hipSuccess) return e0;
+    }
     TRIG_MARK("k_tile", 0);
     hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, max_pmt, n_cu, s)
                          : launch_tile<HALO_SMALL, false>(b, max_pmt, n_cu, s);

@@ -333,6 +333,8 @@ int trig_stream_submit(trig_ctx *c, const trig_slice_desc *d, const trig_params 
         ctx_set_error(c, "bad mem kind");
         return TRIG_EINVAL;
     }
+    const int prc = check_params(c, prm);
+    if (prc != TRIG_OK) return prc;
     ServeState *S = serve_get(c);
     const uint64_t n = d->n_hits;
     const bool host = d->mem == TRIG_MEM_HOST && n > 0;

@@ -147,6 +147,7 @@ struct SliceDev {
     uint32_t *tagc;          // per tile: tagged-hit count, then its exclusive prefix
     uint32_t *tagged;        // tagged hits' input indices (the fire-scratch area)
     uint32_t tag_on, pad2;   // the caller asked for the tagged list
+    uint64_t *l0m;           // level-0 pass bits by ordered position (level 0 on)
 };
 
 struct BatchDev {
@@ -371,6 +372,8 @@ struct TrigLaunchCfg {
 
 hipError_t trig_launch_tag(const trigdev::BatchDev &b, hipStream_t s, void (*mark)(void *, const char *, int),
                            void *mark_ctx);
+hipError_t trig_launch_l0(const trigdev::BatchDev &b, hipStream_t s, void (*mark)(void *, const char *, int),
+                          void *mark_ctx);
 hipError_t trig_launch_front(const trigdev::BatchDev &b, uint32_t seg_cap, uint32_t wave_cap, int wave_wgs_per_cu,
                              const TrigLaunchCfg &cfg, hipStream_t s, void (*mark)(void *, const char *, int),
                              void *mark_ctx);

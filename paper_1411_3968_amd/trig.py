@@ -41,7 +41,8 @@ class GeomDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("q_seed", C.c_uint32), ("t_floor_ns", C.c_int32), ("w_ns", C.c_uint32),
-                ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32)]
+                ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32),
+                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32)]
 
 
 class SliceDesc(C.Structure):
@@ -72,7 +73,7 @@ class StreamStats(C.Structure):
                 ("device_bytes_peak", C.c_uint64), ("rounds", C.c_uint64)]
 
 
-assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 20
+assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 32
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
            "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
@@ -127,7 +128,8 @@ def lib() -> C.CDLL:
 def params_struct(p: dict | None) -> Params:
     p = p or {}
     return Params(int(p.get("q_seed", 300)), int(p.get("t_floor_ns", 20)), int(p.get("w_ns", 3000)),
-                  int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)))
+                  int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)),
+                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))))
 
 
 def _err(ctx) -> str:
