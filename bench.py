@@ -115,6 +115,35 @@ def bench_tagging(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream
                 kernels=kernels), tagged
 
 
+def bench_level0(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream):
+    """The same slice with the paper's level-0 prefilter for this tower (N7TW500:
+    7 hits within 500 ns) ahead of the seed rule: step time, the level-0 kernels."""
+    prm = dict(params, l0_n=7, l0_tw_ns=500)
+    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, prm, stream=stream)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    out = dict(fires=r["fires"].copy(), events=r["events"].copy())
+    T.trig_profile_enable(tr.ctx, True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    prof = T.trig_profile_read(tr.ctx)
+    T.trig_profile_enable(tr.ctx, False)
+    kernels = {}
+    for p in prof:
+        if p["name"].startswith("k_l0"):
+            kernels[p["name"]] = dict(avg_us=round(p["total_ms"] / max(1, p["launches"]) * 1e3, 3),
+                                      launches=int(p["launches"]))
+    return dict(setting="N7TW500", value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
+                n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), kernels=kernels), prm, out
+
+
 def bench_batch(T, torch, dev, a):
     """Batched form: many uneven slices of two tower types in one launch sequence,
     against the same slices triggered one call each."""
@@ -355,6 +384,7 @@ def main():
                     bytes_per_hit=ALGO_BYTES_PER_HIT[dom], hits_per_launch=n)
 
     tagging, tagged = bench_tagging(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
+    level0, l0_prm, l0_out = bench_level0(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
 
     cpu = None
     if not a.no_cpu:
@@ -370,6 +400,9 @@ def main():
         assert np.array_equal(ref["fires"], r["fires"]) and np.array_equal(ref["events"], r["events"])
         tagging["equals_oracle"] = bool(np.array_equal(orc.tag(s.pmt, s.t, ref["fires"], w.params["half_event_ns"]),
                                                        tagged))
+        ref0 = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, l0_prm, "blocked", threads=threads)
+        level0["equals_oracle"] = bool(np.array_equal(ref0["fires"], l0_out["fires"]) and
+                                       np.array_equal(ref0["events"], l0_out["events"]))
         cpu = dict(value=round(n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
                    sample=f"blocked form, whole {n}-hit slice x {reps} runs ({tc:.1f} s)")
 
@@ -400,6 +433,7 @@ def main():
         cpu_baseline=cpu,
         results=dict(n_seeds=r["n_seeds"], n_fires=r["n_fires"], n_events=r["n_events"], path=r["path"]),
         tagging=tagging,
+        level0=level0,
         batched=batch,
         serving=serving,
     )
