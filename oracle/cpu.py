@@ -31,7 +31,8 @@ assert FIRE_DTYPE.itemsize == 24 and EVENT_DTYPE.itemsize == 32
 class Params(C.Structure):
     _fields_ = [("q_seed", C.c_uint32), ("t_floor_ns", C.c_int32), ("w_ns", C.c_uint32),
                 ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32),
-                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32)]
+                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32),
+                ("t_adj_ns", C.c_int32), ("t_afloor_ns", C.c_int32), ("seed_mode", C.c_uint32)]
 
 
 def build(force: bool = True) -> str:
@@ -53,7 +54,7 @@ def _load():
             build(force=False)
         lib = C.CDLL(LIB)
         P = C.c_void_p
-        lib.orc_run.argtypes = [C.c_int, C.c_uint64, P, P, P, C.c_uint32, P, P, C.POINTER(Params),
+        lib.orc_run.argtypes = [C.c_int, C.c_uint64, P, P, P, C.c_uint32, P, P, P, C.POINTER(Params),
                                 P, P, P, C.POINTER(C.c_uint64), P, C.POINTER(C.c_uint64), C.c_int]
         lib.orc_run.restype = C.c_int
         lib.orc_point.argtypes = [C.c_uint64, P, P, P, C.c_uint32, P, P, C.POINTER(Params),
@@ -68,7 +69,8 @@ def _load():
 def _params(p: dict) -> Params:
     return Params(int(p.get("q_seed", 300)), int(p.get("t_floor_ns", 20)), int(p.get("w_ns", 3000)),
                   int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)),
-                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))))
+                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))),
+                  int(p.get("t_adj_ns", -1)), int(p.get("t_afloor_ns", -1)), int(p.get("seed_mode", 0)))
 
 
 def _ptr(a):
@@ -85,9 +87,11 @@ def _inputs(pmt, t, q, floor_id, thr):
 
 
 def run(pmt, t, q, floor_id, thr, params: dict | None = None, form: str = "blocked",
-        threads: int = 0) -> dict:
-    """Whole rule on one slice.  ``form`` is ``strict`` (all pairs) or ``blocked``."""
+        threads: int = 0, adj_id=None) -> dict:
+    """Whole rule on one slice.  ``form`` is ``strict`` (all pairs) or ``blocked``;
+    ``adj_id`` (per PMT) groups the adjacent PMTs of a floor for the SC rule."""
     pmt, t, q, floor_id, thr = _inputs(pmt, t, q, floor_id, thr)
+    adj = None if adj_id is None else np.ascontiguousarray(adj_id, dtype=np.int32)
     n = t.shape[0]
     seed = np.zeros(max(n, 1), np.uint8)
     fold = np.zeros(max(n, 1), np.uint32)
@@ -96,7 +100,7 @@ def run(pmt, t, q, floor_id, thr, params: dict | None = None, form: str = "block
     nf, ne = C.c_uint64(0), C.c_uint64(0)
     prm = _params(params or {})
     rc = _load().orc_run(0 if form == "strict" else 1, n, _ptr(pmt), _ptr(t), _ptr(q), len(floor_id),
-                         _ptr(floor_id), _ptr(thr), C.byref(prm), seed.ctypes.data_as(C.c_void_p),
+                         _ptr(floor_id), _ptr(adj), _ptr(thr), C.byref(prm), seed.ctypes.data_as(C.c_void_p),
                          fold.ctypes.data_as(C.c_void_p), fires.ctypes.data_as(C.c_void_p), C.byref(nf),
                          events.ctypes.data_as(C.c_void_p), C.byref(ne), int(threads))
     return dict(status=int(rc), seed=seed[:n] if rc == 0 else seed[:0], fold=fold[:n] if rc == 0 else fold[:0],

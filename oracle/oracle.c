@@ -35,6 +35,17 @@
  *           [t_i, t_i + TW) holds >= N hits (>= N distinct PMTs for DN);
  *           the seed rule then runs on the hits that pass: S_k requires L_k,
  *           and a floor partner m requires L_m
+ *   seed menu (optional; Sec. 4.1 trigger list: SC, two adjacent PMTs within
+ *           20 ns; FC, two PMTs of one floor within 100 ns; AFC, two PMTs on
+ *           consecutive floors within 250 ns; Sec. 5: the candidate selection
+ *           [SC and AFC] or [FC and AFC]): with partner m != k on another PMT
+ *           (passing level 0 when it is on),
+ *     FC_k  floor_id equal, |t_k - t_m| <= tau_f (t_floor_ns, the rule above)
+ *     SC_k  floor_id equal and adj_id equal, |t_k - t_m| <= tau_sc (t_adj_ns)
+ *     AFC_k |floor_id difference| = 1, |t_k - t_m| <= tau_afc (t_afloor_ns)
+ *           (a negative window turns its rule off; adj_id NULL: no two PMTs
+ *           adjacent); seed_mode 0: S_k = Q_k or FC_k or SC_k or AFC_k;
+ *           seed_mode 1: S_k = Q_k or ((SC_k or FC_k) and AFC_k)
  *   tagged hits (Sec. 4.2: the hits within +-3 us of a trigger seed are
  *           tagged to be saved): T = { k : |t_k - t_f| <= H for some f in F },
  *           ordered by (t, p, k)
@@ -68,6 +79,9 @@ typedef struct {
     uint32_t l0_n;           /* level-0 prefilter: hits (0 = off) ... */
     uint32_t l0_tw_ns;       /* ... within this window ... */
     uint32_t l0_distinct;    /* ... counting distinct PMTs when set */
+    int32_t  t_adj_ns;       /* SC window (adjacent PMTs); < 0 off */
+    int32_t  t_afloor_ns;    /* AFC window (consecutive floors); < 0 off */
+    uint32_t seed_mode;      /* 0: any enabled rule; 1: Q or ((SC or FC) and AFC) */
 } orc_params;
 
 typedef struct {
@@ -108,28 +122,49 @@ int orc_validate(uint64_t n, const uint16_t *pmt, const int64_t *t, uint32_t n_p
 
 /* ---------------------------------------------------------------- strict */
 
-static int floor_partner_strict(uint64_t n, const uint16_t *pmt, const int64_t *t,
-                                const int32_t *floor_id, const uint8_t *l0, uint64_t k, int64_t tau)
+/* Partner rules of hit k met by hit m: bit 0 FC, bit 1 SC, bit 2 AFC. */
+static unsigned partner_bits(const uint16_t *pmt, const int64_t *t, const int32_t *floor_id,
+                             const int32_t *adj_id, const orc_params *prm, uint64_t k, uint64_t m)
 {
-    for (uint64_t m = 0; m < n; ++m) {
-        if (l0 && !l0[m]) continue;
-        if (pmt[m] == pmt[k]) continue;
-        if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
-        if (absdiff(t[k], t[m]) <= tau) return 1;
-    }
-    return 0;
+    if (m == k || pmt[m] == pmt[k]) return 0;
+    const int64_t dt = absdiff(t[k], t[m]);
+    const int64_t fk = floor_id[pmt[k]], fm = floor_id[pmt[m]];
+    unsigned b = 0;
+    if (prm->t_floor_ns >= 0 && fm == fk && dt <= prm->t_floor_ns) b |= 1u;
+    if (prm->t_adj_ns >= 0 && adj_id && fm == fk && adj_id[pmt[m]] == adj_id[pmt[k]] && dt <= prm->t_adj_ns)
+        b |= 2u;
+    if (prm->t_afloor_ns >= 0 && (fm - fk == 1 || fk - fm == 1) && dt <= prm->t_afloor_ns) b |= 4u;
+    return b;
+}
+
+static int seed_of(int charge, unsigned bits, const orc_params *prm)
+{
+    const int fc = bits & 1u, sc = (bits >> 1) & 1u, afc = (bits >> 2) & 1u;
+    if (prm->seed_mode == 1) return charge || ((sc || fc) && afc);
+    return charge || fc || sc || afc;
+}
+
+/* Widest partner window (< 0 when no partner rule is on). */
+static int64_t partner_reach(const orc_params *prm)
+{
+    int64_t r = prm->t_floor_ns;
+    if (prm->t_adj_ns > r) r = prm->t_adj_ns;
+    if (prm->t_afloor_ns > r) r = prm->t_afloor_ns;
+    return r;
 }
 
 static void seeds_strict(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
-                         const int32_t *floor_id, const uint8_t *l0, const orc_params *prm, uint8_t *seed)
+                         const int32_t *floor_id, const int32_t *adj_id, const uint8_t *l0, const orc_params *prm,
+                         uint8_t *seed)
 {
+    const int any_rule = partner_reach(prm) >= 0;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t k = 0; k < (int64_t)n; ++k) {
         if (l0 && !l0[k]) { seed[k] = 0; continue; }
-        int s = q[k] >= prm->q_seed;
-        if (!s && prm->t_floor_ns >= 0)
-            s = floor_partner_strict(n, pmt, t, floor_id, l0, (uint64_t)k, prm->t_floor_ns);
-        seed[k] = (uint8_t)s;
+        unsigned bits = 0;
+        for (uint64_t m = 0; any_rule && m < n; ++m)
+            if (!l0 || l0[m]) bits |= partner_bits(pmt, t, floor_id, adj_id, prm, (uint64_t)k, m);
+        seed[k] = (uint8_t)seed_of(q[k] >= prm->q_seed, bits, prm);
     }
 }
 
@@ -196,29 +231,28 @@ static int make_blocks(uint64_t n, const int64_t *t, const uint8_t *sel, uint64_
 static void free_blocks(blocks *B) { free(B->start); free(B->member); }
 
 static int seeds_blocked(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
-                         const int32_t *floor_id, const uint8_t *l0, const orc_params *prm, uint8_t *seed)
+                         const int32_t *floor_id, const int32_t *adj_id, const uint8_t *l0, const orc_params *prm,
+                         uint8_t *seed)
 {
-    for (uint64_t k = 0; k < n; ++k) seed[k] = q[k] >= prm->q_seed && (!l0 || l0[k]);
-    if (prm->t_floor_ns < 0 || n == 0) return ORC_OK;
+    for (uint64_t k = 0; k < n; ++k) seed[k] = seed_of(q[k] >= prm->q_seed, 0u, prm) && (!l0 || l0[k]);
+    const int64_t reach = partner_reach(prm);
+    if (reach < 0 || n == 0) return ORC_OK;
     blocks B;
-    int rc = make_blocks(n, t, NULL, (uint64_t)prm->t_floor_ns, &B);
+    int rc = make_blocks(n, t, NULL, (uint64_t)reach, &B);
     if (rc) return rc;
-    const int64_t tau = prm->t_floor_ns;
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t k = 0; k < (int64_t)n; ++k) {
         if (seed[k] || (l0 && !l0[k])) continue;
         uint64_t b = (uint64_t)(t[k] - B.t_lo) / B.width;
         uint64_t b0 = b ? b - 1 : 0, b1 = b + 1 < B.nb ? b + 1 : b;
-        int s = 0;
-        for (uint64_t bb = b0; bb <= b1 && !s; ++bb)
+        unsigned bits = 0;
+        for (uint64_t bb = b0; bb <= b1; ++bb)
             for (uint64_t i = B.start[bb]; i < B.start[bb + 1]; ++i) {
                 uint32_t m = B.member[i];
                 if (l0 && !l0[m]) continue;
-                if (pmt[m] == pmt[k]) continue;
-                if (floor_id[pmt[m]] != floor_id[pmt[k]]) continue;
-                if (absdiff(t[k], t[m]) <= tau) { s = 1; break; }
+                bits |= partner_bits(pmt, t, floor_id, adj_id, prm, (uint64_t)k, m);
             }
-        seed[k] = (uint8_t)s;
+        seed[k] = (uint8_t)seed_of(0, bits, prm);
     }
     free_blocks(&B);
     return ORC_OK;
@@ -420,7 +454,8 @@ uint64_t orc_tag(uint64_t n, const uint16_t *pmt, const int64_t *t, const orc_fi
  * (by input index).  fires / events need room for up to n records.  Returns
  * ORC_OK or the validation error (outputs then hold zero counts). */
 int orc_run(int form, uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t *q,
-            uint32_t n_pmt, const int32_t *floor_id, const uint32_t *thr, const orc_params *prm,
+            uint32_t n_pmt, const int32_t *floor_id, const int32_t *adj_id, const uint32_t *thr,
+            const orc_params *prm,
             uint8_t *seed_out, uint32_t *fold_out,
             orc_fire *fires, uint64_t *n_fires, orc_event *events, uint64_t *n_events,
             int n_threads)
@@ -442,10 +477,10 @@ int orc_run(int form, uint64_t n, const uint16_t *pmt, const int64_t *t, const u
         if (rc) { free(l0); return rc; }
     }
     if (form == 0) {
-        seeds_strict(n, pmt, t, q, floor_id, l0, prm, seed_out);
+        seeds_strict(n, pmt, t, q, floor_id, adj_id, l0, prm, seed_out);
         folds_strict(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
     } else {
-        rc = seeds_blocked(n, pmt, t, q, floor_id, l0, prm, seed_out);
+        rc = seeds_blocked(n, pmt, t, q, floor_id, adj_id, l0, prm, seed_out);
         if (!rc) rc = folds_blocked(n, pmt, t, seed_out, n_pmt, thr, prm, fold_out);
         if (rc) { free(l0); return rc; }
     }
@@ -470,7 +505,8 @@ int orc_point(uint64_t n, const uint16_t *pmt, const int64_t *t, const uint16_t 
 #endif
     int rc = orc_validate(n, pmt, t, n_pmt, prm);
     if (rc) return rc;
-    if (prm->l0_n) return ORC_EINVAL;   /* sampled checks cover the rule without level 0 */
+    /* sampled checks cover the rule without level 0 and the seed menu */
+    if (prm->l0_n || prm->t_adj_ns >= 0 || prm->t_afloor_ns >= 0 || prm->seed_mode) return ORC_EINVAL;
     const int64_t tau = prm->t_floor_ns;
     const int64_t reach = (int64_t)prm->w_ns + (tau > 0 ? tau : 0);
     int fail = 0;

@@ -444,3 +444,88 @@ def test_l0_strict_blocked_and_variants_agree(oracle_lib, seed):
     one = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, l0_n=1, l0_tw_ns=1), "blocked")
     off = oracle_lib.run(pmt, t, q, floor_id, thr, base, "blocked")
     assert np.array_equal(one["seed"], off["seed"]) and np.array_equal(one["fires"], off["fires"])
+
+
+# ------------------------------------------------------------- seed menu (SC, FC, AFC)
+
+# three floors x two bar ends x two PMTs; PMT = 4 floor + 2 end + j; adjacency group = bar end
+MENU_FLOOR = np.repeat(np.arange(3), 4).astype(np.int32)
+MENU_ADJ = np.repeat(np.arange(6), 2).astype(np.int32)
+MENU_WIN = dict(q_seed=300, t_floor_ns=100, t_adj_ns=20, t_afloor_ns=250, w_ns=0, min_fold=1, half_event_ns=0)
+
+
+@pytest.mark.parametrize("form", ["strict", "blocked"])
+def test_seed_menu_hand_example(oracle_lib, form):
+    """Worked by hand (SC 20 ns adjacent PMTs, FC 100 ns same floor, AFC 250 ns
+    consecutive floors, all inclusive):
+      h0 p0 t1000, h1 p1 t1015: SC (15), FC, AFC with h3      -> any / combination
+      h2 p2 t1080: FC with h0 (80), AFC with h3 (120)          -> any / combination
+      h3 p4 t1200: AFC only (floor 1 has no partner)           -> any
+      h4 p8 t5000, h5 p9 t5010: SC and FC; h6 p5 t5300 too far  -> any (h4, h5)
+      h7 p10 t9000, h8 p11 t9021: not SC (21 > 20) but FC       -> any / combination
+      h9 p6 t9250: AFC with h7 at exactly 250                  -> any"""
+    hits = [(0, 1000), (1, 1015), (2, 1080), (4, 1200), (8, 5000), (9, 5010), (5, 5300),
+            (10, 9000), (11, 9021), (6, 9250)]
+    pmt = np.array([h[0] for h in hits], np.uint16)
+    t = np.array([h[1] for h in hits], np.int64)
+    q = np.zeros(len(t), np.uint16)
+    thr = np.zeros((12, 12), np.uint32)
+    anyr = oracle_lib.run(pmt, t, q, MENU_FLOOR, thr, MENU_WIN, form, adj_id=MENU_ADJ)
+    comb = oracle_lib.run(pmt, t, q, MENU_FLOOR, thr, dict(MENU_WIN, seed_mode=1), form, adj_id=MENU_ADJ)
+    assert anyr["seed"].tolist() == [1, 1, 1, 1, 1, 1, 0, 1, 1, 1]
+    assert comb["seed"].tolist() == [1, 1, 1, 0, 0, 0, 0, 1, 1, 0]
+    # FC off: h4 and h5 are seeds through SC alone, and lose it without the
+    # adjacency groups; AFC still holds for the others
+    nofc = dict(MENU_WIN, t_floor_ns=-1)
+    sc = oracle_lib.run(pmt, t, q, MENU_FLOOR, thr, nofc, form, adj_id=MENU_ADJ)
+    noadj = oracle_lib.run(pmt, t, q, MENU_FLOOR, thr, nofc, form)
+    assert sc["seed"].tolist() == [1, 1, 1, 1, 1, 1, 0, 1, 1, 1]
+    assert noadj["seed"].tolist() == [1, 1, 1, 1, 0, 0, 0, 1, 1, 1]
+
+
+def test_adjacent_floor_seed_rate_closed_form(oracle_lib):
+    """Only the AFC rule, two PMTs on each of floors 0 and 1 at 1 MHz for 0.5 s:
+    a hit on floor f has no partner on the other floor within +-tau with
+    probability exp(-(2 tau + 1) R_other), so
+    E[#seeds] = sum_p N_p (1 - exp(-(2 tau + 1) N_other(p) / T)).
+    A same-floor partner must not count (the floors' own pairs are 3x as many)."""
+    rng = np.random.default_rng(78)
+    T, R, tau = 500_000_000, 1e-3, 30
+    streams = [_poisson_stream(rng, R, T) for _ in range(4)]
+    pmt = np.concatenate([np.full(len(s), i, np.uint16) for i, s in enumerate(streams)])
+    t = np.concatenate(streams)
+    q = np.zeros(len(t), np.uint16)
+    floor_id = np.array([0, 0, 1, 1], np.int32)
+    thr = np.full((4, 4), 20, np.uint32)
+    prm = dict(q_seed=65536, t_floor_ns=-1, t_afloor_ns=tau, w_ns=0, min_fold=99)
+    r = oracle_lib.run(pmt, t, q, floor_id, thr, prm, "blocked")
+    N = np.array([len(s) for s in streams], dtype=np.float64)
+    other = {0: N[2] + N[3], 1: N[2] + N[3], 2: N[0] + N[1], 3: N[0] + N[1]}
+    e = sum(N[p] * (1 - math.exp(-(2 * tau + 1) * other[p] / T)) for p in range(4))
+    obs = int(r["seed"].sum())
+    sigma = math.sqrt(2.0 * e)
+    assert abs(obs - e) < 4 * sigma, (obs, e, sigma)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_seed_menu_strict_blocked_and_modes(oracle_lib, seed):
+    rng = np.random.default_rng(970 + seed)
+    n = int(rng.integers(200, 2000))
+    P = 24
+    floor_id = (np.arange(P) // 4).astype(np.int32)
+    adj = (np.arange(P) // 2).astype(np.int32)
+    thr = rng.integers(0, 3000, size=(P, P)).astype(np.uint32)
+    t = rng.integers(0, n * 400, size=n).astype(np.int64) + 7 * 10**15
+    pmt = rng.integers(0, P, size=n).astype(np.uint16)
+    q = rng.integers(0, 600, size=n).astype(np.uint16)
+    base = dict(q_seed=500, t_floor_ns=int(rng.integers(-1, 120)), t_adj_ns=int(rng.integers(-1, 40)),
+                t_afloor_ns=int(rng.integers(-1, 300)), w_ns=3000, min_fold=2, half_event_ns=400)
+    for extra in (dict(), dict(seed_mode=1), dict(seed_mode=1, l0_n=3, l0_tw_ns=600)):
+        prm = dict(base, **extra)
+        a = oracle_lib.run(pmt, t, q, floor_id, thr, prm, "strict", adj_id=adj)
+        b = oracle_lib.run(pmt, t, q, floor_id, thr, prm, "blocked", adj_id=adj)
+        assert np.array_equal(a["seed"], b["seed"]) and np.array_equal(a["fold"], b["fold"])
+        assert np.array_equal(a["fires"], b["fires"]) and np.array_equal(a["events"], b["events"])
+    any_ = oracle_lib.run(pmt, t, q, floor_id, thr, base, "blocked", adj_id=adj)["seed"]
+    comb = oracle_lib.run(pmt, t, q, floor_id, thr, dict(base, seed_mode=1), "blocked", adj_id=adj)["seed"]
+    assert not (comb.astype(bool) & ~any_.astype(bool)).any()
