@@ -105,6 +105,17 @@ def block(nx: int = 4, ny: int = 8, pitch: float = 90.0, n_floors: int = 14,
                     height=(n_floors - 1) * dz)
 
 
+def bar_end_groups(geom: Geometry) -> np.ndarray:
+    """Group index per PMT: the PMTs at one end of one floor's bar (same floor,
+    same horizontal position) share a group; numbered in order of appearance."""
+    key = {}
+    out = np.empty(geom.n_pmt, np.int32)
+    for i in range(geom.n_pmt):
+        k = (int(geom.floor_id[i]), round(float(geom.pos[i, 0]), 3), round(float(geom.pos[i, 1]), 3))
+        out[i] = key.setdefault(k, len(key))
+    return out
+
+
 def thr_table(geom: Geometry, n: float = N_WATER, c: float = C_M_PER_NS, tol_ns: int = 20) -> np.ndarray:
     """Dense row-major ``uint32 [P, P]`` table ``ceil(n*d/c) + tol_ns`` (float64)."""
     d = np.sqrt(((geom.pos[:, None, :] - geom.pos[None, :, :]) ** 2).sum(-1))

@@ -73,15 +73,21 @@ const char *trig_last_error(const trig_ctx *ctx);
 const char *trig_version(void);
 
 /* Tower geometry (Sec. 2: detection units on floors of a tower).
- *   floor_id[n_pmt]           global floor index of each PMT
+ *   floor_id[n_pmt]           global floor index of each PMT (floors whose ids
+ *                             differ by 1 are consecutive, for the AFC rule)
  *   thr_ns[n_pmt * n_pmt]     row-major causality table in ns; thr_ns[i*n_pmt+j]
  *                             bounds |t_i - t_j| when counting for a seed on PMT i
+ *   adj_id[n_pmt]             may be NULL: adjacency group of each PMT for the SC
+ *                             rule (Sec. 4.1: two adjacent PMTs); two PMTs of one
+ *                             floor with equal adj_id are adjacent (e.g. the PMTs
+ *                             at one end of a floor's bar).  NULL: none adjacent.
  * Host pointers; the arrays are copied, the caller keeps ownership.
  * 1 <= n_pmt <= 65536.  On success *geom_id names the copy. */
 typedef struct {
     uint32_t        n_pmt;
     const int32_t  *floor_id;
     const uint32_t *thr_ns;
+    const int32_t  *adj_id;
 } trig_geom_desc;
 
 int trig_geom_load(trig_ctx *ctx, const trig_geom_desc *geom, uint32_t *geom_id);
@@ -102,7 +108,18 @@ int trig_geom_load(trig_ctx *ctx, const trig_geom_desc *geom, uint32_t *geom_id)
  *                 (>= l0_n distinct PMTs when l0_distinct != 0), and the seed
  *                 rule runs on the hits that pass: a seed and its floor partner
  *                 both pass.  TRIG_EINVAL unless 1 <= l0_n <= 64 and
- *                 1 <= l0_tw_ns <= 1000000 when it is on. */
+ *                 1 <= l0_tw_ns <= 1000000 when it is on.
+ *   t_adj_ns, t_afloor_ns, seed_mode
+ *                 seed menu (Sec. 4.1 trigger list; Sec. 5 candidate selection):
+ *                 SC, a hit of an adjacent PMT (same floor, same adj_id) within
+ *                 t_adj_ns; FC, a hit of another PMT of the same floor within
+ *                 t_floor_ns (the rule above); AFC, a hit on a consecutive floor
+ *                 within t_afloor_ns (all inclusive; a negative window turns its
+ *                 rule off; partners pass level 0 when it is on).  seed_mode 0:
+ *                 a seed meets the charge rule or any enabled partner rule;
+ *                 seed_mode 1: the charge rule, or (SC or FC) and AFC, the
+ *                 paper's [SC and AFC] or [FC and AFC].  TRIG_EINVAL for another
+ *                 seed_mode.  Defaults (-1, -1, 0) give the rule without them. */
 typedef struct {
     uint32_t q_seed;
     int32_t  t_floor_ns;
@@ -112,6 +129,9 @@ typedef struct {
     uint32_t l0_n;
     uint32_t l0_tw_ns;
     uint32_t l0_distinct;
+    int32_t  t_adj_ns;
+    int32_t  t_afloor_ns;
+    uint32_t seed_mode;
 } trig_params;
 
 enum { TRIG_MEM_HOST = 0, TRIG_MEM_DEVICE = 1 };

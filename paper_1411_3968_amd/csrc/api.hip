@@ -320,6 +320,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
             S.floor16 = g.floor16;
             S.thr32 = g.thr32;
             S.thr16 = g.thr16;
+            S.adj32 = g.adj32;
+            S.afl32 = g.afl32;
             S.n_pmt = g.n_pmt;
             S.pbits = pbits_of(g.n_pmt);
         } else {
@@ -658,6 +660,10 @@ int check_params(trig_ctx *c, const trig_params *p) {
         ctx_set_error(c, "level 0 needs 1 <= l0_n <= 64 and 1 <= l0_tw_ns <= 1000000");
         return TRIG_EINVAL;
     }
+    if (p->seed_mode > 1) {
+        ctx_set_error(c, "seed_mode must be 0 or 1");
+        return TRIG_EINVAL;
+    }
     return TRIG_OK;
 }
 
@@ -752,6 +758,8 @@ void trig_destroy(trig_ctx *c) {
         hipFree(g.floor16);
         hipFree(g.thr32);
         hipFree(g.thr16);
+        hipFree(g.adj32);
+        hipFree(g.afl32);
     }
     for (auto ev : c->ev_pool) hipEventDestroy(ev);
     for (auto &m : c->prof_pending) hipEventDestroy(m.ev);
@@ -771,7 +779,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     }
     hipSetDevice(c->device);
     const uint64_t P = g->n_pmt;
-    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2;
+    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2 + P * 8;
     if (ctx_reserve(c, bytes) != TRIG_OK) {
         ctx_set_error(c, "device budget exceeded by geometry");
         return TRIG_ENOMEM;
@@ -792,7 +800,32 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
             f16[byid[i].second] = (uint16_t)k;
         }
     }
+    // adjacency groups, densely numbered (each PMT its own group when none given)
+    std::vector<uint32_t> adj(P), afl(P);
+    {
+        std::vector<std::pair<int64_t, uint32_t>> byid(P);
+        for (uint64_t i = 0; i < P; ++i) byid[i] = {g->adj_id ? (int64_t)g->adj_id[i] : (int64_t)i, (uint32_t)i};
+        std::sort(byid.begin(), byid.end());
+        uint32_t k = 0;
+        for (uint64_t i = 0; i < P; ++i) {
+            if (i && byid[i].first != byid[i - 1].first) ++k;
+            adj[byid[i].second] = k;
+        }
+        // floor ranks: distinct floor ids in order, one apart when the ids differ by 1
+        std::vector<std::pair<int64_t, uint32_t>> fl(P);
+        for (uint64_t i = 0; i < P; ++i) fl[i] = {(int64_t)g->floor_id[i], (uint32_t)i};
+        std::sort(fl.begin(), fl.end());
+        uint32_t r = 0;
+        for (uint64_t i = 0; i < P; ++i) {
+            if (i && fl[i].first != fl[i - 1].first) r += fl[i].first - fl[i - 1].first == 1 ? 1u : 2u;
+            afl[fl[i].second] = r;
+        }
+    }
     hipError_t e = hipMalloc(&d.floor_id, P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.adj32, P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.afl32, P * 4);
+    if (e == hipSuccess) e = hipMemcpy(d.adj32, adj.data(), P * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.afl32, afl.data(), P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d.floor16, P * 2);
     if (e == hipSuccess) e = hipMalloc(&d.thr32, P * P * 4);
     if (e == hipSuccess) e = hipMalloc(&d.thr16, P * P * 2 + 16);   // read as 32-bit pairs
@@ -803,6 +836,8 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     if (e != hipSuccess) {
         hipFree(d.floor16);
         hipFree(d.floor_id);
+        hipFree(d.adj32);
+        hipFree(d.afl32);
         hipFree(d.thr32);
         hipFree(d.thr16);
         ctx_release(c, bytes);

@@ -32,6 +32,8 @@ struct GeomDev {
     uint16_t *floor16 = nullptr;   // dense renumbering of floor_id (first appearance order)
     uint32_t *thr32 = nullptr;
     uint16_t *thr16 = nullptr;
+    uint32_t *adj32 = nullptr;     // dense adjacency group (a PMT of its own when none is given)
+    uint32_t *afl32 = nullptr;     // floor rank, consecutive floor ids one apart, others two
 };
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).

@@ -168,6 +168,8 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
     const TRIG_GAS uint16_t *floor16 = gmem(S.floor16);
     TRIG_GAS uint8_t *seed_flags = gmem(S.seed_flags);
+    const TRIG_GAS uint32_t *adj32 = gmem(S.adj32);
+    const TRIG_GAS uint32_t *afl32 = gmem(S.afl32);
     const uint32_t n_pmt = S.n_pmt;
     const uint64_t n = S.n;
     const int64_t t_min = Pg->t_min;
@@ -175,7 +177,13 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const uint32_t W = b.prm.w_ns;
     const uint32_t N = b.prm.min_fold;
     const int32_t tau = b.prm.t_floor_ns;
-    const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
+    // the seed menu (adjacent PMTs, consecutive floors, the combination): its
+    // widest window sets the reach of the partner search
+    const int32_t t_sc = b.prm.t_adj_ns, t_afc = b.prm.t_afloor_ns;
+    const bool menu = !MASK && (t_sc >= 0 || t_afc >= 0 || b.prm.seed_mode != 0);
+    const bool mode1 = b.prm.seed_mode == 1;
+    const int32_t tmax = menu ? max(tau, max(t_sc, t_afc)) : tau;
+    const uint32_t tau_u = tmax > 0 ? (uint32_t)tmax : 0u;
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const int lane = lane_id(), w = threadIdx.x >> 6;
 
@@ -252,11 +260,41 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     if (covered) {
         cbase = sl;
         // seed bits of the whole stage
+        // (level 0 on: a partner must pass it, and so must the hit)
+        auto l0b = [&](uint32_t y) -> bool { return !L0 || ((l0w[y >> 6] >> (y & 63)) & 1ull); };
         for (uint32_t x0 = 0; x0 < len; x0 += NT) {
             const uint32_t x = x0 + threadIdx.x;
             bool seed = false;
             if (MASK) {
                 seed = x < len && mask_bit(S, sl + x);
+            } else if (menu) {
+                if (x < len && tmax >= 0) {
+                    // FC, SC and AFC partners within the widest window, both sides
+                    const uint32_t t = st[x], f = spf[x], p = f >> 16, fl = f & 0xFFFFu;
+                    const uint32_t ak = adj32[p], rk = afl32[p];
+                    bool fc = false, sc = false, afc = false;
+                    for (uint32_t d = 1;; ++d) {
+                        const bool ll = x >= d && t - st[x - d] <= tau_u;
+                        const bool rr = x + d < len && st[x + d] - t <= tau_u;
+                        if (!ll && !rr) break;
+                        for (int side = 0; side < 2; ++side) {
+                            if (!(side ? rr : ll)) continue;
+                            const uint32_t m = side ? x + d : x - d;
+                            const uint32_t g = spf[m], pm = g >> 16;
+                            if (pm == p || !l0b(m)) continue;
+                            const uint32_t dt = side ? st[m] - t : t - st[m];
+                            if ((g & 0xFFFFu) == fl) {
+                                fc = fc || (tau >= 0 && dt <= (uint32_t)tau);
+                                sc = sc || (t_sc >= 0 && dt <= (uint32_t)t_sc && adj32[pm] == ak);
+                            } else if (t_afc >= 0 && dt <= (uint32_t)t_afc) {
+                                const uint32_t rm = afl32[pm];
+                                afc = afc || rm == rk + 1 || rm + 1 == rk;
+                            }
+                        }
+                        if (mode1 ? ((fc || sc) && afc) : (fc || sc || afc)) break;
+                    }
+                    seed = (mode1 ? ((fc || sc) && afc) : (fc || sc || afc)) && l0b(x);
+                }
             } else if (tau >= 0 && x < len) {
                 // floor coincidence: a hit of another PMT on the same floor within
                 // t_floor_ns.  The nearest neighbours on both sides are read together;
@@ -267,8 +305,6 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                 // (bitwise operators: no branch between the reads and their use)
                 const bool l_in = (x >= 1) & (t - tl <= tau_u);
                 const bool r_in = (x + 1 < len) & (tr - t <= tau_u);
-                // (level 0 on: the partner must pass it, and so must the hit)
-                auto l0b = [&](uint32_t y) -> bool { return !L0 || ((l0w[y >> 6] >> (y & 63)) & 1ull); };
                 seed = (l_in & floor_partner(fl, f) & l0b(xl)) | (r_in & floor_partner(fr, f) & l0b(xr));
                 if (!seed && (l_in || r_in)) {
                     for (uint32_t d = 2;; ++d) {
@@ -696,6 +732,14 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     const bool L0 = b.prm.l0_n > 0;
     const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
     auto l0_at = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
+    // partner rules: FC (same floor, tau), SC (same floor and adjacency group),
+    // AFC (consecutive floors); without the seed menu only FC is on
+    const int32_t t_sc = b.prm.t_adj_ns, t_afc = b.prm.t_afloor_ns;
+    const bool mode1 = b.prm.seed_mode == 1;
+    const int32_t tmax = max(tau, max(t_sc, t_afc));
+    const TRIG_GAS uint16_t *floor16 = gmem(S.floor16);
+    const TRIG_GAS uint32_t *adj32 = gmem(S.adj32);
+    const TRIG_GAS uint32_t *afl32 = gmem(S.afl32);
 #pragma unroll
     for (int e = 0; e < TILE / NTD; ++e) {
         const uint64_t j = a + (uint64_t)e * NTD + threadIdx.x;
@@ -703,19 +747,33 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
         if (j < n && l0_at(j)) {
             const uint32_t t = lt[j - lo], pq = lpq[j - lo], p = pq >> 16;
             seed = (pq & 0xFFFFu) >= Q;
-            if (!seed && tau >= 0) {
-                const uint32_t f = S.floor16[p];
-                for (uint64_t m = j; m > 0;) {
+            if (!seed && tmax >= 0) {
+                const uint32_t f = floor16[p], ak = adj32[p], rk = afl32[p];
+                bool fc = false, sc = false, afc = false;
+                auto met = [&]() { return mode1 ? ((fc || sc) && afc) : (fc || sc || afc); };
+                auto visit = [&](uint64_t m, uint32_t dt) {
+                    const uint32_t pm = P_at(m);
+                    if (pm == p || !l0_at(m)) return;
+                    if (floor16[pm] == f) {
+                        fc = fc || (tau >= 0 && dt <= (uint32_t)tau);
+                        sc = sc || (t_sc >= 0 && dt <= (uint32_t)t_sc && adj32[pm] == ak);
+                    } else if (t_afc >= 0 && dt <= (uint32_t)t_afc) {
+                        const uint32_t rm = afl32[pm];
+                        afc = afc || rm == rk + 1 || rm + 1 == rk;
+                    }
+                };
+                for (uint64_t m = j; m > 0 && !met();) {
                     --m;
-                    if (t - T_at(m) > (uint32_t)tau) break;
-                    const uint32_t pm = P_at(m);
-                    if (pm != p && S.floor16[pm] == f && l0_at(m)) { seed = true; break; }
+                    const uint32_t dt = t - T_at(m);
+                    if (dt > (uint32_t)tmax) break;
+                    visit(m, dt);
                 }
-                for (uint64_t m = j + 1; !seed && m < n; ++m) {
-                    if (T_at(m) - t > (uint32_t)tau) break;
-                    const uint32_t pm = P_at(m);
-                    if (pm != p && S.floor16[pm] == f && l0_at(m)) seed = true;
+                for (uint64_t m = j + 1; m < n && !met(); ++m) {
+                    const uint32_t dt = T_at(m) - t;
+                    if (dt > (uint32_t)tmax) break;
+                    visit(m, dt);
                 }
+                seed = met();
             }
         }
         const uint64_t bal = __ballot(seed);

@@ -148,6 +148,8 @@ struct SliceDev {
     uint32_t *tagged;        // tagged hits' input indices (the fire-scratch area)
     uint32_t tag_on, pad2;   // the caller asked for the tagged list
     uint64_t *l0m;           // level-0 pass bits by ordered position (level 0 on)
+    const uint32_t *adj32;   // per PMT: adjacency group (SC)
+    const uint32_t *afl32;   // per PMT: floor rank, 1 apart exactly for consecutive floors (AFC)
 };
 
 struct BatchDev {

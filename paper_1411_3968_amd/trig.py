@@ -36,13 +36,14 @@ class TrigError(RuntimeError):
 
 
 class GeomDesc(C.Structure):
-    _fields_ = [("n_pmt", C.c_uint32), ("floor_id", C.c_void_p), ("thr_ns", C.c_void_p)]
+    _fields_ = [("n_pmt", C.c_uint32), ("floor_id", C.c_void_p), ("thr_ns", C.c_void_p), ("adj_id", C.c_void_p)]
 
 
 class Params(C.Structure):
     _fields_ = [("q_seed", C.c_uint32), ("t_floor_ns", C.c_int32), ("w_ns", C.c_uint32),
                 ("min_fold", C.c_uint32), ("half_event_ns", C.c_uint32),
-                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32)]
+                ("l0_n", C.c_uint32), ("l0_tw_ns", C.c_uint32), ("l0_distinct", C.c_uint32),
+                ("t_adj_ns", C.c_int32), ("t_afloor_ns", C.c_int32), ("seed_mode", C.c_uint32)]
 
 
 class SliceDesc(C.Structure):
@@ -73,7 +74,7 @@ class StreamStats(C.Structure):
                 ("device_bytes_peak", C.c_uint64), ("rounds", C.c_uint64)]
 
 
-assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 32
+assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 44
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
            "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
@@ -129,7 +130,8 @@ def params_struct(p: dict | None) -> Params:
     p = p or {}
     return Params(int(p.get("q_seed", 300)), int(p.get("t_floor_ns", 20)), int(p.get("w_ns", 3000)),
                   int(p.get("min_fold", 4)), int(p.get("half_event_ns", 3000)),
-                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))))
+                  int(p.get("l0_n", 0)), int(p.get("l0_tw_ns", 1000)), int(bool(p.get("l0_distinct", 0))),
+                  int(p.get("t_adj_ns", -1)), int(p.get("t_afloor_ns", -1)), int(p.get("seed_mode", 0)))
 
 
 def _err(ctx) -> str:
@@ -159,13 +161,16 @@ def trig_last_error(ctx) -> str:
     return _err(ctx)
 
 
-def trig_geom_load(ctx, floor_id, thr) -> int:
+def trig_geom_load(ctx, floor_id, thr, adj_id=None) -> int:
     floor_id = np.ascontiguousarray(floor_id, dtype=np.int32)
     thr = np.ascontiguousarray(thr, dtype=np.uint32).reshape(-1)
     P = floor_id.shape[0]
     if thr.shape[0] != P * P:
         raise ValueError("thr must be n_pmt x n_pmt")
-    g = GeomDesc(P, floor_id.ctypes.data, thr.ctypes.data)
+    adj = None if adj_id is None else np.ascontiguousarray(adj_id, dtype=np.int32)
+    if adj is not None and adj.shape[0] != P:
+        raise ValueError("adj_id must have n_pmt entries")
+    g = GeomDesc(P, floor_id.ctypes.data, thr.ctypes.data, adj.ctypes.data if adj is not None else None)
     gid = C.c_uint32()
     rc = _LIB.trig_geom_load(ctx, C.byref(g), C.byref(gid))
     if rc != TRIG_OK:
@@ -507,8 +512,8 @@ class Trigger:
     def __exit__(self, *a):
         self.close()
 
-    def load_geometry(self, floor_id, thr) -> int:
-        return trig_geom_load(self.ctx, floor_id, thr)
+    def load_geometry(self, floor_id, thr, adj_id=None) -> int:
+        return trig_geom_load(self.ctx, floor_id, thr, adj_id)
 
     def slice(self, geom_id, pmt, t, q, params=None, **kw) -> dict:
         return trig_slice(self.ctx, geom_id, pmt, t, q, params, **kw)

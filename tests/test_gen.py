@@ -74,3 +74,17 @@ def test_full_size_counts():
     tot = sum((32 if sp["key"] == "nemo" else 84) * sp["rate_hz"] * sp["length_ns"] * 1e-9 for sp in specs)
     assert 1.2e8 < tot < 2.5e8
     assert 10 <= sum(1 for sp in specs if sp["bursts"]) <= 45
+
+
+def test_bar_end_groups():
+    """Groups are the PMTs at one end of one floor's bar: half a floor each, one
+    floor and one horizontal position per group."""
+    from gen import geometry as G
+    for geom, per_floor in ((G.nemo_tower(), 4), (G.km3net_it_tower(), 6)):
+        grp = G.bar_end_groups(geom)
+        assert len(np.unique(grp)) == 2 * len(np.unique(geom.floor_id))
+        for k in np.unique(grp):
+            m = grp == k
+            assert m.sum() == per_floor // 2
+            assert len(np.unique(geom.floor_id[m])) == 1
+            assert np.allclose(geom.pos[m, :2], geom.pos[m, :2][0])
