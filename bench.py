@@ -115,10 +115,15 @@ def bench_tagging(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream
                 kernels=kernels), tagged
 
 
-def bench_level0(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream):
-    """The same slice with the paper's level-0 prefilter for this tower (N7TW500:
-    7 hits within 500 ns) ahead of the seed rule: step time, the level-0 kernels."""
-    prm = dict(params, l0_n=7, l0_tw_ns=500)
+# the paper's settings for the 84-PMT tower: level 0 N7TW500, then the candidate
+# selection [SC and AFC] or [FC and AFC] (SC 20 ns, FC 100 ns, AFC 250 ns)
+LEVEL0 = dict(l0_n=7, l0_tw_ns=500)
+SEED_MENU = dict(LEVEL0, t_adj_ns=20, t_floor_ns=100, t_afloor_ns=250, seed_mode=1)
+
+
+def bench_variant(T, torch, tr, gid, pmt, t, q, prm, n, steps, warmup, stream, prefix, setting):
+    """The same slice with one of the paper's rule variants on: step time and the
+    kernels whose names start with prefix."""
     run = T.SliceRunner(tr.ctx, gid, pmt, t, q, prm, stream=stream)
     for _ in range(warmup):
         run()
@@ -137,11 +142,11 @@ def bench_level0(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream)
     T.trig_profile_enable(tr.ctx, False)
     kernels = {}
     for p in prof:
-        if p["name"].startswith("k_l0"):
+        if p["name"].startswith(prefix):
             kernels[p["name"]] = dict(avg_us=round(p["total_ms"] / max(1, p["launches"]) * 1e3, 3),
                                       launches=int(p["launches"]))
-    return dict(setting="N7TW500", value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
-                n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), kernels=kernels), prm, out
+    return dict(setting=setting, value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
+                n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), kernels=kernels), out
 
 
 def bench_batch(T, torch, dev, a):
@@ -384,7 +389,15 @@ def main():
                     bytes_per_hit=ALGO_BYTES_PER_HIT[dom], hits_per_launch=n)
 
     tagging, tagged = bench_tagging(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
-    level0, l0_prm, l0_out = bench_level0(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
+    l0_prm = dict(w.params, **LEVEL0)
+    level0, l0_out = bench_variant(T, torch, tr, gid, pmt, t, q, l0_prm, n, a.steps, a.warmup, stream, "k_l0",
+                                   "N7TW500")
+    from gen.geometry import bar_end_groups
+    adj = bar_end_groups(g)
+    gid_adj = tr.load_geometry(g.floor_id, thr, adj)
+    menu_prm = dict(w.params, **SEED_MENU)
+    seed_menu, menu_out = bench_variant(T, torch, tr, gid_adj, pmt, t, q, menu_prm, n, a.steps, a.warmup, stream,
+                                        "k_tile", "N7TW500 then [SC and AFC] or [FC and AFC]")
 
     cpu = None
     if not a.no_cpu:
@@ -403,6 +416,9 @@ def main():
         ref0 = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, l0_prm, "blocked", threads=threads)
         level0["equals_oracle"] = bool(np.array_equal(ref0["fires"], l0_out["fires"]) and
                                        np.array_equal(ref0["events"], l0_out["events"]))
+        refm = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, menu_prm, "blocked", threads=threads, adj_id=adj)
+        seed_menu["equals_oracle"] = bool(np.array_equal(refm["fires"], menu_out["fires"]) and
+                                          np.array_equal(refm["events"], menu_out["events"]))
         cpu = dict(value=round(n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
                    sample=f"blocked form, whole {n}-hit slice x {reps} runs ({tc:.1f} s)")
 
@@ -434,6 +450,7 @@ def main():
         results=dict(n_seeds=r["n_seeds"], n_fires=r["n_fires"], n_events=r["n_events"], path=r["path"]),
         tagging=tagging,
         level0=level0,
+        seed_menu=seed_menu,
         batched=batch,
         serving=serving,
     )

@@ -127,7 +127,7 @@ __device__ __forceinline__ bool export_as_is(uint32_t state) {
     return state != ST_FAST && state != ST_GENERIC_DONE && state != ST_DENSE;
 }
 
-template <int NT, int HMAX, bool MASK>
+template <int NT, int HMAX, bool MASK, bool MENU>
 __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     constexpr int NW = NT / 64;
     constexpr int STG = TILE + 2 * HMAX;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     // the seed menu (adjacent PMTs, consecutive floors, the combination): its
     // widest window sets the reach of the partner search
     const int32_t t_sc = b.prm.t_adj_ns, t_afc = b.prm.t_afloor_ns;
-    const bool menu = !MASK && (t_sc >= 0 || t_afc >= 0 || b.prm.seed_mode != 0);
+    constexpr bool menu = MENU && !MASK;   // a variant of its own: the plain rule keeps its registers
     const bool mode1 = b.prm.seed_mode == 1;
     const int32_t tmax = menu ? max(tau, max(t_sc, t_afc)) : tau;
     const uint32_t tau_u = tmax > 0 ? (uint32_t)tmax : 0u;
@@ -788,24 +788,24 @@ constexpr size_t tile_lds_bytes() {
     return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 * 2 + (STG / 64 + 1) * 4 + CS * 2 * 3;
 }
 
-template <int NT, int HMAX, bool MASK>
+template <int NT, int HMAX, bool MASK, bool MENU>
 hipError_t launch_tile_nt(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
     const size_t shm = tile_lds_bytes<HMAX, MASK>() + ((floor_lds * 2 + 15) & ~15u);
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_tile<NT, HMAX, MASK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (const void *)k_tile<NT, HMAX, MASK, MENU>, hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)(tile_lds_bytes<HMAX, MASK>() + FLOOR_LDS_MAX * 2));
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_tile<NT, HMAX, MASK>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
+    hipLaunchKernelGGL((k_tile<NT, HMAX, MASK, MENU>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
                        floor_lds);
     return hipGetLastError();
 }
 
-template <int HMAX, bool MASK>
+template <int HMAX, bool MASK, bool MENU>
 hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipStream_t s) {
     // the floor numbering of the batch's largest geometry in LDS when it is small
     const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
-    if (b.total_tiles <= 4 * n_cu) return launch_tile_nt<NT_ONE_WAVE, HMAX, MASK>(b, floor_lds, s);
-    return launch_tile_nt<NT_MANY, HMAX, MASK>(b, floor_lds, s);
+    if (b.total_tiles <= 4 * n_cu) return launch_tile_nt<NT_ONE_WAVE, HMAX, MASK, MENU>(b, floor_lds, s);
+    return launch_tile_nt<NT_MANY, HMAX, MASK, MENU>(b, floor_lds, s);
 }
 
 }  // namespace
@@ -821,8 +821,11 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
         if (e0 != hipSuccess) return e0;
     }
     TRIG_MARK("k_tile", 0);
-    hipError_t e = dense ? launch_tile<HALO_BIG, true>(b, max_pmt, n_cu, s)
-                         : launch_tile<HALO_SMALL, false>(b, max_pmt, n_cu, s);
+    // the seed menu (SC, AFC, their combination) runs in a variant of its own
+    const bool menu = b.prm.t_adj_ns >= 0 || b.prm.t_afloor_ns >= 0 || b.prm.seed_mode != 0;
+    hipError_t e = dense ? launch_tile<HALO_BIG, true, false>(b, max_pmt, n_cu, s)
+                 : menu  ? launch_tile<HALO_SMALL, false, true>(b, max_pmt, n_cu, s)
+                         : launch_tile<HALO_SMALL, false, false>(b, max_pmt, n_cu, s);
     if (e != hipSuccess) return e;
     TRIG_MARK("k_tile", 1);
     TRIG_MARK("k_tscan", 0);
