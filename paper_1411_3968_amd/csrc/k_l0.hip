@@ -87,11 +87,21 @@ __global__ __launch_bounds__(NTL) void k_l0_pass(BatchDev b) {
     for (uint32_t x0 = 0; x0 < (uint32_t)TILE; x0 += NTL) {
         const uint64_t x = a + x0 + threadIdx.x;
         bool pass = false;
-        if (x < e) {
+        if (x < e && !distinct) {
+            // counting hits: an ok start i in x - N + 1 .. x holds x (t_x <= t_{i+N-1}
+            // < t_i + TW), and a start before that is matched by a later one, so x
+            // passes exactly when one of those N bits is set (N <= 64: two words)
+            const uint64_t lo = x + 1 >= N ? x + 1 - N : 0;
+            const uint64_t wx = okw[x >> 6], hi_mask = (x & 63) == 63 ? ~0ull : ((2ull << (x & 63)) - 1ull);
+            if ((lo >> 6) == (x >> 6)) {
+                pass = (wx & hi_mask & (~0ull << (lo & 63))) != 0;
+            } else {
+                pass = (wx & hi_mask) != 0 || (okw[lo >> 6] & (~0ull << (lo & 63))) != 0;
+            }
+        } else if (x < e) {
+            // counting PMTs: every start at or before x (in time order) that still holds x
             const uint32_t tx = o_t[x];
-            // window starts at or before x (in time order) that still hold x
-            const uint64_t lo = distinct ? 0 : (x + 1 >= N ? x + 1 - N : 0);
-            for (uint64_t i = x + 1; i-- > lo && !pass;) {
+            for (uint64_t i = x + 1; i-- > 0 && !pass;) {
                 if (tx - o_t[i] >= TW) break;
                 pass = bit_at(okw, i);
             }

@@ -268,7 +268,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
             if (MASK) {
                 seed = x < len && mask_bit(S, sl + x);
             } else if (menu) {
-                if (x < len && tmax >= 0) {
+                if (x < len && tmax >= 0 && l0b(x)) {   // (a hit failing level 0 is no seed)
                     // FC, SC and AFC partners within the widest window, both sides
                     const uint32_t t = st[x], f = spf[x], p = f >> 16, fl = f & 0xFFFFu;
                     const uint32_t ak = adj32[p], rk = afl32[p];
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                         }
                         if (mode1 ? ((fc || sc) && afc) : (fc || sc || afc)) break;
                     }
-                    seed = (mode1 ? ((fc || sc) && afc) : (fc || sc || afc)) && l0b(x);
+                    seed = mode1 ? ((fc || sc) && afc) : (fc || sc || afc);
                 }
             } else if (tau >= 0 && x < len) {
                 // floor coincidence: a hit of another PMT on the same floor within
