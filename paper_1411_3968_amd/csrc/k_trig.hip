@@ -52,35 +52,26 @@ __device__ __forceinline__ TileAgg agg_empty() {
 
 // Summary of run A followed by run B (twoH: the merge distance 2H).  Associative.
 __device__ __forceinline__ TileAgg agg_combine(const TileAgg &A, const TileAgg &B, uint64_t twoH) {
-    if (A.F == 0) {
-        TileAgg r = B;
-        r.S = A.S + B.S;
-        return r;
-    }
-    if (B.F == 0) {
-        TileAgg r = A;
-        r.S = A.S + B.S;
-        return r;
-    }
-    const bool bs = (uint64_t)(B.first_t - A.last_t) > twoH;
+    // field by field, with selects: a branch between whole summaries makes the
+    // compiler pick one of the two addresses, which sends the summaries to
+    // private memory when one lives in LDS
+    const bool a0 = A.F == 0, b0 = B.F == 0;   // A empty: B; B empty: A (seed counts add)
+    const bool bs = !a0 && !b0 && (uint64_t)(B.first_t - A.last_t) > twoH;
     TileAgg r;
     r.F = A.F + B.F;
     r.S = A.S + B.S;
-    r.first_t = A.first_t;
-    r.last_t = B.last_t;
-    r.E_int = A.E_int + B.E_int + (bs ? 1u : 0u);
-    r.m_head = (A.E_int > 0 || bs) ? A.m_head : umax(A.m_head, B.m_head);
-    r.m_tail = (B.E_int > 0 || bs) ? B.m_tail : umax(A.m_tail, B.m_tail);
-    if (B.E_int > 0) {
-        r.ls_idx = A.F + B.ls_idx;
-        r.ls_t = B.ls_t;
-    } else if (bs) {
-        r.ls_idx = A.F;
-        r.ls_t = B.first_t;
-    } else {
-        r.ls_idx = A.ls_idx;
-        r.ls_t = A.ls_t;
-    }
+    r.first_t = a0 ? B.first_t : A.first_t;
+    r.last_t = (b0 && !a0) ? A.last_t : B.last_t;
+    const uint32_t e_int = A.E_int + B.E_int + (bs ? 1u : 0u);
+    const uint32_t m_head = (A.E_int > 0 || bs) ? A.m_head : umax(A.m_head, B.m_head);
+    const uint32_t m_tail = (B.E_int > 0 || bs) ? B.m_tail : umax(A.m_tail, B.m_tail);
+    const uint32_t ls_idx = B.E_int > 0 ? A.F + B.ls_idx : bs ? A.F : A.ls_idx;
+    const uint32_t ls_t = B.E_int > 0 ? B.ls_t : bs ? B.first_t : A.ls_t;
+    r.E_int = a0 ? B.E_int : b0 ? A.E_int : e_int;
+    r.m_head = a0 ? B.m_head : b0 ? A.m_head : m_head;
+    r.m_tail = a0 ? B.m_tail : b0 ? A.m_tail : m_tail;
+    r.ls_idx = a0 ? B.ls_idx : b0 ? A.ls_idx : ls_idx;
+    r.ls_t = a0 ? B.ls_t : b0 ? A.ls_t : ls_t;
     return r;
 }
 
@@ -127,6 +118,13 @@ __device__ __forceinline__ bool export_as_is(uint32_t state) {
     return state != ST_FAST && state != ST_GENERIC_DONE && state != ST_DENSE;
 }
 
+// LDS bytes of a tile's stage and lists (the per-PMT tables come after them).
+template <int HMAX, bool MASK>
+constexpr size_t tile_lds_bytes() {
+    constexpr size_t STG = TILE + 2 * HMAX, CS = compact_cap(HMAX, MASK);
+    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 * 2 + (STG / 64 + 1) * 4 + CS * 2 * 3;
+}
+
 template <int NT, int HMAX, bool MASK, bool MENU>
 __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     constexpr int NW = NT / 64;
@@ -144,6 +142,12 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     uint16_t *cidx = cp + CS;                        // compacted seeds: stage position
     uint16_t *fci = cidx + CS;                       // fires: compacted index
     uint16_t *lfl = fci + CS;                        // dense floor index of every PMT (floor_lds of them)
+    // seed menu: adjacency group and floor rank of every PMT (floor_lds of each)
+    uint32_t *ladj = (uint32_t *)(smem + tile_lds_bytes<HMAX, MASK>() + ((floor_lds * 2 + 15) & ~15u));
+    uint32_t *lafl = ladj + floor_lds;
+    // seed menu: the same two per staged hit, so the partner search reads no table
+    uint32_t *hadj = lafl + floor_lds;
+    uint32_t *hafl = hadj + STG;
     __shared__ uint32_t sh[NW + 1];
     __shared__ uint32_t s_ncs, s_ca, s_cb;
 
@@ -214,7 +218,13 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
         }
         // the floor numbering (independent of the staged hits, so in flight with them)
         if (!MASK && n_pmt <= floor_lds)
-            for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
+            for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) {
+                lfl[x] = floor16[x];
+                if (MENU) {
+                    ladj[x] = adj32[x];
+                    lafl[x] = afl32[x];
+                }
+            }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
@@ -244,6 +254,15 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                 uint32_t f = 0;
                 if (!MASK) f = n_pmt <= floor_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
                 spf[x] = (p << 16) | f;
+                if (menu) {
+                    if (n_pmt <= floor_lds) {
+                        hadj[x] = ladj[p];
+                        hafl[x] = lafl[p];
+                    } else {
+                        hadj[x] = adj32[p];
+                        hafl[x] = afl32[p];
+                    }
+                }
             }
         }
     }
@@ -271,29 +290,34 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
                 if (x < len && tmax >= 0 && l0b(x)) {   // (a hit failing level 0 is no seed)
                     // FC, SC and AFC partners within the widest window, both sides
                     const uint32_t t = st[x], f = spf[x], p = f >> 16, fl = f & 0xFFFFu;
-                    const uint32_t ak = adj32[p], rk = afl32[p];
-                    bool fc = false, sc = false, afc = false;
+                    const uint32_t ak = hadj[x], rk = hafl[x];
+                    // found rules as bits (1 FC, 2 SC, 4 AFC), kept in a register: a
+                    // window below zero is off (its limit 0 admits nothing)
+                    const uint32_t lim_fc = tau >= 0 ? (uint32_t)tau + 1u : 0u;
+                    const uint32_t lim_sc = t_sc >= 0 ? (uint32_t)t_sc + 1u : 0u;
+                    const uint32_t lim_afc = t_afc >= 0 ? (uint32_t)t_afc + 1u : 0u;
+                    auto look = [&](bool in, uint32_t dt, uint32_t g, uint32_t y, uint32_t am, uint32_t rm) -> uint32_t {
+                        const bool ok = in & ((g >> 16) != p) & l0b(y);
+                        const bool same = (g & 0xFFFFu) == fl;
+                        const bool nb = (rm == rk + 1u) | (rm + 1u == rk);
+                        return (uint32_t)(ok & same & (dt < lim_fc)) | ((uint32_t)(ok & same & (dt < lim_sc) & (am == ak)) << 1) |
+                               ((uint32_t)(ok & !same & (dt < lim_afc) & nb) << 2);
+                    };
+                    auto done = [&](uint32_t m) -> bool { return mode1 ? ((m & 3u) != 0u && (m & 4u) != 0u) : m != 0u; };
+                    uint32_t m = 0;
+                    // one step looks at the neighbours d positions away on both sides;
+                    // every read of a step is issued together (clamped positions)
                     for (uint32_t d = 1;; ++d) {
-                        const bool ll = x >= d && t - st[x - d] <= tau_u;
-                        const bool rr = x + d < len && st[x + d] - t <= tau_u;
+                        const uint32_t yl = x >= d ? x - d : x, yr = x + d < len ? x + d : x;
+                        const uint32_t tl = st[yl], tr = st[yr], gl = spf[yl], gr = spf[yr];
+                        const uint32_t al = hadj[yl], ar = hadj[yr], rl = hafl[yl], rr_ = hafl[yr];
+                        const bool ll = (x >= d) & (t - tl <= tau_u);
+                        const bool rr = (x + d < len) & (tr - t <= tau_u);
                         if (!ll && !rr) break;
-                        for (int side = 0; side < 2; ++side) {
-                            if (!(side ? rr : ll)) continue;
-                            const uint32_t m = side ? x + d : x - d;
-                            const uint32_t g = spf[m], pm = g >> 16;
-                            if (pm == p || !l0b(m)) continue;
-                            const uint32_t dt = side ? st[m] - t : t - st[m];
-                            if ((g & 0xFFFFu) == fl) {
-                                fc = fc || (tau >= 0 && dt <= (uint32_t)tau);
-                                sc = sc || (t_sc >= 0 && dt <= (uint32_t)t_sc && adj32[pm] == ak);
-                            } else if (t_afc >= 0 && dt <= (uint32_t)t_afc) {
-                                const uint32_t rm = afl32[pm];
-                                afc = afc || rm == rk + 1 || rm + 1 == rk;
-                            }
-                        }
-                        if (mode1 ? ((fc || sc) && afc) : (fc || sc || afc)) break;
+                        m |= look(ll, t - tl, gl, yl, al, rl) | look(rr, tr - t, gr, yr, ar, rr_);
+                        if (done(m)) break;
                     }
-                    seed = mode1 ? ((fc || sc) && afc) : (fc || sc || afc);
+                    seed = done(m);
                 }
             } else if (tau >= 0 && x < len) {
                 // floor coincidence: a hit of another PMT on the same floor within
@@ -532,7 +556,7 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
         return;
     }
     TRIG_GAS TileStat *tstat = gmem(S.tstat);
-    __shared__ TileAgg wsum[NWS];
+    __shared__ TileAgg wsum[NWS], wpre[NWS];
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const int lane = lane_id(), w = threadIdx.x >> 6;
     const uint32_t nt = S.n_tiles;
@@ -545,8 +569,15 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    TileAgg before = agg_empty();   // waves before this one
-    for (int i = 0; i < w; ++i) before = agg_combine(before, wsum[i], twoH);
+    // the wave totals scanned by the first wave (exclusive: the waves before each)
+    if (w == 0) {
+        const TileAgg v = lane < NWS ? wsum[lane] : agg_empty();
+        const TileAgg vi = wave_scan(v, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
+        const TileAgg vx = wave_shr1(vi, agg_empty());
+        if (lane < NWS) wpre[lane] = vx;
+    }
+    __syncthreads();
+    const TileAgg before = wpre[w];   // waves before this one
     TileAgg P = agg_combine(before, wave_shr1(inc, agg_empty()), twoH);
     for (uint32_t t = t0; t < t1; ++t) {
         const TileAgg A = gload(&tstat[t].agg);
@@ -749,18 +780,20 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
             seed = (pq & 0xFFFFu) >= Q;
             if (!seed && tmax >= 0) {
                 const uint32_t f = floor16[p], ak = adj32[p], rk = afl32[p];
-                bool fc = false, sc = false, afc = false;
-                auto met = [&]() { return mode1 ? ((fc || sc) && afc) : (fc || sc || afc); };
+                // found rules as bits (1 FC, 2 SC, 4 AFC), kept in a register
+                const uint32_t lim_fc = tau >= 0 ? (uint32_t)tau + 1u : 0u;
+                const uint32_t lim_sc = t_sc >= 0 ? (uint32_t)t_sc + 1u : 0u;
+                const uint32_t lim_afc = t_afc >= 0 ? (uint32_t)t_afc + 1u : 0u;
+                uint32_t found = 0;
+                auto met = [&]() { return mode1 ? ((found & 3u) != 0u && (found & 4u) != 0u) : found != 0u; };
                 auto visit = [&](uint64_t m, uint32_t dt) {
                     const uint32_t pm = P_at(m);
-                    if (pm == p || !l0_at(m)) return;
-                    if (floor16[pm] == f) {
-                        fc = fc || (tau >= 0 && dt <= (uint32_t)tau);
-                        sc = sc || (t_sc >= 0 && dt <= (uint32_t)t_sc && adj32[pm] == ak);
-                    } else if (t_afc >= 0 && dt <= (uint32_t)t_afc) {
-                        const uint32_t rm = afl32[pm];
-                        afc = afc || rm == rk + 1 || rm + 1 == rk;
-                    }
+                    const bool ok = pm != p && l0_at(m);
+                    const bool same = floor16[pm] == f;
+                    const uint32_t rm = afl32[pm];
+                    const bool nb = (rm == rk + 1u) | (rm + 1u == rk);
+                    found |= (uint32_t)(ok & same & (dt < lim_fc)) | ((uint32_t)(ok & same & (dt < lim_sc) & (adj32[pm] == ak)) << 1) |
+                             ((uint32_t)(ok & !same & (dt < lim_afc) & nb) << 2);
                 };
                 for (uint64_t m = j; m > 0 && !met();) {
                     --m;
@@ -782,18 +815,14 @@ __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     }
 }
 
-template <int HMAX, bool MASK>
-constexpr size_t tile_lds_bytes() {
-    constexpr size_t STG = TILE + 2 * HMAX, CS = compact_cap(HMAX, MASK);
-    return STG * 4 * 2 + CS * 4 * 2 + (STG / 64) * 8 * 2 + (STG / 64 + 1) * 4 + CS * 2 * 3;
-}
 
 template <int NT, int HMAX, bool MASK, bool MENU>
 hipError_t launch_tile_nt(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
-    const size_t shm = tile_lds_bytes<HMAX, MASK>() + ((floor_lds * 2 + 15) & ~15u);
+    constexpr size_t STG = TILE + 2 * HMAX;
+    const size_t shm = tile_lds_bytes<HMAX, MASK>() + ((floor_lds * 2 + 15) & ~15u) + (MENU ? floor_lds * 8 + STG * 8 : 0);
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_tile<NT, HMAX, MASK, MENU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(tile_lds_bytes<HMAX, MASK>() + FLOOR_LDS_MAX * 2));
+        (int)(tile_lds_bytes<HMAX, MASK>() + FLOOR_LDS_MAX * 2 + (MENU ? FLOOR_LDS_MAX * 8 + STG * 8 : 0)));
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_tile<NT, HMAX, MASK, MENU>), dim3(((b.total_tiles + 7) / 8) * 8), dim3(NT), shm, s, b,
                        floor_lds);
