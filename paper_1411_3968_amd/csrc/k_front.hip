@@ -24,7 +24,8 @@ __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) { return wave_max_all(
 __device__ __forceinline__ uint32_t wave_sumu(uint32_t v) { return wave_total(v); }
 
 // Per chunk of CHUNK input hits: time range, largest PMT id, run starts
-// (position 0 and every position whose time is below its predecessor's).
+// (position 0 and every position whose time is below its predecessor's), and
+// the packed copy of the chunk's hits that the wave ordering kernel gathers.
 __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
@@ -37,9 +38,11 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     uint32_t pmax = 0, ns = 0;
     const TRIG_GAS int64_t *tin = gmem(S.t);
     const TRIG_GAS uint16_t *pin = gmem(S.pmt);
+    const TRIG_GAS uint16_t *qin = gmem(S.q);
+    TRIG_GAS uint64_t *pk = packed_hits(S);
     constexpr int PER = CHUNK / NT_ING;
     int64_t tv[PER], tp[PER];
-    uint32_t pv[PER];
+    uint32_t pv[PER], qv[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
         const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
@@ -47,7 +50,13 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
             tv[e] = tin[k];
             tp[e] = k ? tin[k - 1] : INT64_MIN;
             pv[e] = pin[k];
+            qv[e] = qin[k];
         }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
+        if (k < k1) pk[k] = ((uint64_t)((pv[e] << 16) | qv[e]) << 32) | (uint32_t)(uint64_t)tv[e];
     }
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
@@ -537,8 +546,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     const uint32_t first = x0 + gw * per;
     const uint32_t end = (first + per < x1) ? first + per : x1;
     uint32_t si = 0, s_base = 1, s_end = 0;
-    const TRIG_GAS uint16_t *in_pmt = nullptr, *in_q = nullptr;
-    const TRIG_GAS int64_t *in_t = nullptr;
+    const TRIG_GAS uint64_t *in_pk = nullptr;
     const TRIG_GAS uint32_t *pos = nullptr;
     TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     Plan P = {};
@@ -547,7 +555,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
-            in_pmt = gmem(S.pmt); in_q = gmem(S.q); in_t = gmem(S.t); pos = gmem(S.pos);
+            in_pk = packed_hits(S); pos = gmem(S.pos);
             o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx);
             s_base = P.seg_item_base;
             s_end = s_base + P.n_seg;
@@ -620,15 +628,11 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
             src[e] = k < m ? sm.run_lo[rr[e]] + (k - sm.run_base[rr[e]]) : 0xFFFFFFFFu;
         }
-        int64_t tv[EG];
-        uint32_t pv[EG], qv[EG];
+        // one packed word per hit: a single stream of lines per run stretch
+        uint64_t hv[EG];
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
-            if (src[e] != 0xFFFFFFFFu) {
-                tv[e] = in_t[src[e]];
-                pv[e] = in_pmt[src[e]];
-                qv[e] = in_q[src[e]];
-            }
+            if (src[e] != 0xFFFFFFFFu) hv[e] = in_pk[src[e]];
         }
         // key of each element: (local time, PMT, gather position), unique and in
         // the output order; bucket by the top 8 bits of the local time
@@ -644,9 +648,9 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             key[e] = 0;
             slot[e] = 0;
             if (src[e] != 0xFFFFFFFFu) {
-                const uint32_t tl = (uint32_t)(tv[e] - P.t_min) - seg_lo;
-                key[e] = ((uint64_t)tl << KEY_T_SHIFT) | ((uint64_t)pv[e] << KEY_P_SHIFT) | k;
-                sm.dq[k] = (uint16_t)qv[e];
+                const uint32_t tl = ((uint32_t)hv[e] - (uint32_t)(uint64_t)P.t_min) - seg_lo;
+                key[e] = ((uint64_t)tl << KEY_T_SHIFT) | ((hv[e] >> 48) << KEY_P_SHIFT) | k;
+                sm.dq[k] = (uint16_t)(hv[e] >> 32);
                 sm.dsrc[k] = src[e];
                 slot[e] = atomicAdd(&sm.bcount[tl >> tb], 1u);
             }

@@ -359,6 +359,15 @@ __device__ __forceinline__ uint32_t chunk_base_of(const BatchDev &b, uint32_t si
     return b.n_slices <= 1 ? 0u : b.chunk_bases[si];
 }
 
+// Packed copy of the input hits for the ordering stage, one word per input hit:
+// low 32 bits the low 32 bits of t (t - t_min is then their difference modulo
+// 2^32, exact since the span is below 2^31), high 32 bits pmt << 16 | charge.  It
+// lives in the fire-record area, which is unused until the trigger stage (16
+// bytes per hit there, 8 needed).
+__device__ __forceinline__ TRIG_GAS uint64_t *packed_hits(const SliceDev &S) {
+    return (TRIG_GAS uint64_t *)gmem(S.fsc);
+}
+
 __device__ __forceinline__ bool slice_in_tail(const BatchDev &b, uint32_t state) {
     return state == b.tail_state;
 }
