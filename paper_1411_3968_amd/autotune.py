@@ -23,7 +23,7 @@ WAVE_CAP = 512
 WAVE_CAP_SMALL = 256
 
 DEFAULT_CANDIDATES = (
-    [(WAVE_CAP, tgt, g) for tgt in (192, 256, 320, 384) for g in (2, 3)] +
+    [(WAVE_CAP, tgt, g) for tgt in (192, 256, 320, 384) for g in (2, 3, 4)] +
     [(WAVE_CAP_SMALL, tgt, g) for tgt in (128, 160, 192) for g in (4, 5)] +
     [(cap, tgt, g) for cap in (2048, 4096) for tgt in (cap // 4, cap // 2) for g in (1, 2, 4)]
 )

@@ -517,9 +517,8 @@ static_assert(WAVE_CAP <= (1 << KEY_P_SHIFT), "gather positions must fit the key
 template <int CAP>
 struct WaveSeg {
     uint64_t key[CAP];           // keys grouped by bucket, then in output order
-    uint32_t dsrc[CAP];          // input index of each gathered element
     uint16_t dq[CAP];            // charge of each gathered element
-    uint16_t aux[CAP];           // run marks while gathering
+    uint16_t aux[CAP];           // run marks while gathering, then the run of each element
     uint32_t run_lo[WAVE_RUNS], run_base[WAVE_RUNS];
     uint32_t bcount[256];
     uint16_t bbase[256];
@@ -623,10 +622,13 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 carry = last > carry ? last : carry;
             }
         }
+        // (each lane rewrites only its own marks: the run of element k, from which
+        // the output recomputes the input index)
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
             src[e] = k < m ? sm.run_lo[rr[e]] + (k - sm.run_base[rr[e]]) : 0xFFFFFFFFu;
+            if (k < m) sm.aux[k] = (uint16_t)rr[e];
         }
         // one packed word per hit: a single stream of lines per run stretch
         uint64_t hv[EG];
@@ -651,7 +653,6 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 const uint32_t tl = ((uint32_t)hv[e] - (uint32_t)(uint64_t)P.t_min) - seg_lo;
                 key[e] = ((uint64_t)tl << KEY_T_SHIFT) | ((hv[e] >> 48) << KEY_P_SHIFT) | k;
                 sm.dq[k] = (uint16_t)(hv[e] >> 32);
-                sm.dsrc[k] = src[e];
                 slot[e] = atomicAdd(&sm.bcount[tl >> tb], 1u);
             }
         }
@@ -703,7 +704,8 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 const uint32_t p = (uint32_t)(kk >> KEY_P_SHIFT) & 0xFFFFu;
                 o_t[goff + i] = seg_lo + (uint32_t)(kk >> KEY_T_SHIFT);
                 o_pq[goff + i] = (p << 16) | sm.dq[k];
-                o_idx[goff + i] = sm.dsrc[k];
+                const uint32_t r = sm.aux[k];
+                o_idx[goff + i] = sm.run_lo[r] + (k - sm.run_base[r]);
             }
         }
         wave_sync();

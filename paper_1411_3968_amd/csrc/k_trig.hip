@@ -615,19 +615,10 @@ struct SegMax {
     uint32_t f, v;
 };
 
-// One wave per tile with fires: fire records and event halves at their places.
-__global__ __launch_bounds__(64) void k_place(BatchDev b) {
-    const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
-    const SliceDev &S = b.slices[si];
-    const uint32_t k = item - tile_base_of(b, si);
-    if (k >= S.n_tiles) return;
-    const TRIG_GAS Plan *Pp = gmem(S.plan);
-    if (!slice_in_tail(b, Pp->state)) return;
-    if (Pp->dense && b.tail_state != ST_DENSE) return;   // this slice is rerun
+// One tile with fires (nf of them), by one wave with every lane active: fire
+// records and event halves at their places.
+__device__ void place_tile(const BatchDev &b, const SliceDev &S, const TRIG_GAS Plan *Pp, uint32_t k, uint32_t nf) {
     const TRIG_GAS TileStat *tstat = gmem(S.tstat);
-    const uint32_t nf = tstat[k].agg.F;
-    if (nf == 0) return;
     const TileAgg P = gload(&tstat[k].pre);
     const TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)k * TILE;
     TRIG_GAS trig_fire *fires = gmem(S.fires);
@@ -727,6 +718,44 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
         carry_latest = (int32_t)lane_read((uint32_t)latest, 63);
         carry_max = lane_read(mv, 63);
         prev_t = lane_read(t, 63);
+    }
+}
+
+// Persistent: each wave owns a contiguous stretch of the tile list (XCD-aware as
+// in the ordering kernel), looks its slice up once per slice, reads the fire
+// counts of 64 tiles at a time and places only the tiles that have fires.
+__global__ __launch_bounds__(64) void k_place(BatchDev b) {
+    const uint32_t total = b.total_tiles;
+    const uint32_t xcd = blockIdx.x % 8, g = blockIdx.x / 8, per_xcd = gridDim.x / 8;
+    const uint32_t x0 = (uint32_t)(((uint64_t)total * xcd) / 8), x1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / 8);
+    const uint32_t per = (x1 - x0 + per_xcd - 1) / per_xcd;
+    uint32_t item = x0 + g * per;
+    const uint32_t end = (item + per < x1) ? item + per : x1;
+    const int lane = lane_id();
+    while (item < end) {
+        const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+        const SliceDev &S = b.slices[si];
+        const uint32_t base = tile_base_of(b, si);
+        uint32_t s_end = base + S.n_tiles;          // first item past this slice
+        if (s_end > end) s_end = end;
+        if (s_end <= item) { ++item; continue; }    // (an empty slice shares its base)
+        const TRIG_GAS Plan *Pp = gmem(S.plan);
+        // slices outside this pass, and slices that are rerun, place nothing
+        const bool live = slice_in_tail(b, Pp->state) && !(Pp->dense && b.tail_state != ST_DENSE);
+        if (live) {
+            const TRIG_GAS TileStat *tstat = gmem(S.tstat);
+            for (uint32_t i0 = item; i0 < s_end; i0 += 64) {
+                const uint32_t it = i0 + (uint32_t)lane;
+                const uint32_t nf = it < s_end ? tstat[it - base].agg.F : 0u;
+                uint64_t m = __ballot(nf != 0);
+                while (m) {
+                    const int l = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    place_tile(b, S, Pp, i0 + (uint32_t)l - base, lane_read(nf, l));
+                }
+            }
+        }
+        item = s_end;
     }
 }
 
@@ -862,7 +891,12 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
     TRIG_CHECK();
     TRIG_MARK("k_tscan", 1);
     TRIG_MARK("k_place", 0);
-    hipLaunchKernelGGL(k_place, dim3(b.total_tiles), dim3(64), 0, s, b);
+    {
+        // one wave per tile up to 8 per CU, then persistent waves; a multiple of the 8 XCDs
+        const uint32_t cap = 8u * (n_cu ? n_cu : 1u);
+        const uint32_t waves = b.total_tiles < cap ? b.total_tiles : cap;
+        hipLaunchKernelGGL(k_place, dim3(((waves + 7) / 8) * 8), dim3(64), 0, s, b);
+    }
     TRIG_CHECK();
     TRIG_MARK("k_place", 1);
     return hipSuccess;
