@@ -316,3 +316,29 @@ def test_block_slice_reduced(tr, orc):
     got = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
     ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
     check(got, ref)
+
+
+def test_batch_many_slices_with_empty_ones(tr, orc):
+    """150 slices (the slice lookup of a work item takes two levels of its 64-way
+    search), among them empty and one-hit slices whose item ranges are empty and
+    share a base with the next slice; every slice equals the oracle."""
+    rng = np.random.default_rng(77)
+    P = 12
+    floor_id = (np.arange(P) // 3).astype(np.int32)
+    thr = rng.integers(0, 2500, size=(P, P)).astype(np.uint32)
+    gid = gid_for(tr, floor_id, thr)
+    params = dict(q_seed=400, t_floor_ns=30, w_ns=2500, min_fold=2, half_event_ns=1500)
+    items, raw = [], []
+    for i in range(150):
+        kind = i % 7
+        n = 0 if kind in (0, 3) else 1 if kind == 5 else int(rng.integers(2, 6000))
+        pmt = rng.integers(0, P, size=n).astype(np.uint16)
+        t = np.sort(rng.integers(0, 3_000_000, size=n)).astype(np.int64) + int(rng.integers(0, 10**12))
+        q = rng.integers(0, 600, size=n).astype(np.uint16)
+        items.append((gid, pmt, t, q))
+        raw.append((pmt, t, q))
+    res = tr.batch(items, params, seed_flags=True)
+    assert len(res) == 150
+    for (pmt, t, q), r in zip(raw, res):
+        ref = orc.run(pmt, t, q, floor_id, thr, params, "blocked")
+        check(r, ref)
