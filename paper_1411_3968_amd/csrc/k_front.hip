@@ -90,6 +90,48 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 
 // Per slice: reduce the chunks, validate the input range, number the runs and
 // choose the segment width and the ordering kernel of the slice.
+// One read of every chunk summary, RP consecutive chunks per thread per round:
+// the time range, largest PMT id, and the run numbering (each chunk's run_base
+// from a block scan of the run starts).
+template <int NT, int RP>
+__device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax, uint32_t &runs,
+                                            uint32_t *sh) {
+    TRIG_GAS ChunkPart *part = gmem(S.part);
+    for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * RP) {
+        const uint32_t cb = c0 + threadIdx.x * RP;
+        int64_t tl[RP], th[RP];
+        uint32_t pm[RP], ns[RP];
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            ns[u] = 0;
+            if (cb + u < S.n_chunks) {
+                tl[u] = part[cb + u].t_min;
+                th[u] = part[cb + u].t_max;
+                pm[u] = part[cb + u].pmt_max;
+                ns[u] = part[cb + u].n_start;
+            }
+        }
+        uint32_t sum = 0;
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            if (cb + u < S.n_chunks) {
+                lo = tl[u] < lo ? tl[u] : lo;
+                hi = th[u] > hi ? th[u] : hi;
+                pmax = pm[u] > pmax ? pm[u] : pmax;
+                sum += ns[u];
+            }
+        }
+        uint32_t tot;
+        uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            if (cb + u < S.n_chunks) part[cb + u].run_base = run;
+            run += ns[u];
+        }
+        runs += tot;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     constexpr int NT = 1024, NW = NT / 64;
     const uint32_t si = blockIdx.x;
@@ -103,25 +145,10 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     p.state = ST_SKIP;
     if (S.n > 0) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
-        uint32_t pmax = 0;
-        constexpr int U = 4;
-        for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * U) {
-            ChunkPart cp[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t c = c0 + u * NT + threadIdx.x;
-                if (c < S.n_chunks) cp[u] = gload(gmem(S.part) + c);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t c = c0 + u * NT + threadIdx.x;
-                if (c < S.n_chunks) {
-                    lo = cp[u].t_min < lo ? cp[u].t_min : lo;
-                    hi = cp[u].t_max > hi ? cp[u].t_max : hi;
-                    pmax = cp[u].pmt_max > pmax ? cp[u].pmt_max : pmax;
-                }
-            }
-        }
+        uint32_t pmax = 0, runs = 0;
+        // a chunk per thread up to NT chunks (16M hits), else eight per thread per round
+        if (S.n_chunks <= (uint32_t)NT) plan_chunks<NT, 1>(S, lo, hi, pmax, runs, sh);
+        else plan_chunks<NT, 8>(S, lo, hi, pmax, runs, sh);
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
         const int w = threadIdx.x >> 6;
         if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; }
@@ -131,27 +158,6 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             lo = slo[i] < lo ? slo[i] : lo;
             hi = shi[i] > hi ? shi[i] : hi;
             pmax = spm[i] > pmax ? spm[i] : pmax;
-        }
-        // run numbering: exclusive scan of run starts over the chunks
-        // (8 consecutive chunks per thread per round)
-        uint32_t runs = 0;
-        constexpr int RP = 8;
-        for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * RP) {
-            const uint32_t cb = c0 + threadIdx.x * RP;
-            uint32_t v[RP], sum = 0;
-#pragma unroll
-            for (int u = 0; u < RP; ++u) {
-                v[u] = (cb + u < S.n_chunks) ? gmem(S.part)[cb + u].n_start : 0u;
-                sum += v[u];
-            }
-            uint32_t tot;
-            uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
-#pragma unroll
-            for (int u = 0; u < RP; ++u) {
-                if (cb + u < S.n_chunks) gmem(S.part)[cb + u].run_base = run;
-                run += v[u];
-            }
-            runs += tot;
         }
         p.t_min = lo; p.t_max = hi; p.n_runs = runs;
         const uint64_t span = (uint64_t)hi - (uint64_t)lo;

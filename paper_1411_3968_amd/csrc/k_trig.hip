@@ -550,11 +550,6 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const uint32_t si = blockIdx.x;
     const SliceDev &S = b.slices[si];
     TRIG_GAS Plan *Pp = gmem(S.plan);
-    const uint32_t state = Pp->state;
-    if (!slice_in_tail(b, state)) {
-        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
-        return;
-    }
     TRIG_GAS TileStat *tstat = gmem(S.tstat);
     __shared__ TileAgg wsum[NWS], wpre[NWS];
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
@@ -563,8 +558,15 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const uint32_t per = (nt + NTS - 1) / NTS;
     const uint32_t t0 = threadIdx.x * per;
     const uint32_t t1 = (t0 + per < nt) ? t0 + per : nt;
+    // the tile summaries are read in flight with the plan state (they are only
+    // used when the slice is in this pass)
     TileAgg mine = agg_empty();
     for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, gload(&tstat[t].agg), twoH);
+    const uint32_t state = Pp->state;
+    if (!slice_in_tail(b, state)) {
+        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
+        return;
+    }
     // inclusive scan within the wave
     const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
     if (lane == 63) wsum[w] = inc;
