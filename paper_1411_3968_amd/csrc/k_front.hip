@@ -91,11 +91,12 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 // Per slice: reduce the chunks, validate the input range, number the runs and
 // choose the segment width and the ordering kernel of the slice.
 // One read of every chunk summary, RP consecutive chunks per thread per round:
-// the time range, largest PMT id, and the run numbering (each chunk's run_base
-// from a block scan of the run starts).
+// the time range, largest PMT id, the run numbering (each chunk's run_base from a
+// block scan of the run starts) and the largest chunk density in hits per ns (a
+// chunk is mostly one run: a burst on one PMT shows as a short chunk).
 template <int NT, int RP>
 __device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax, uint32_t &runs,
-                                            uint32_t *sh) {
+                                            float &dmax, uint32_t *sh) {
     TRIG_GAS ChunkPart *part = gmem(S.part);
     for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * RP) {
         const uint32_t cb = c0 + threadIdx.x * RP;
@@ -119,6 +120,9 @@ __device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int6
                 hi = th[u] > hi ? th[u] : hi;
                 pmax = pm[u] > pmax ? pm[u] : pmax;
                 sum += ns[u];
+                const uint64_t cnt = (cb + u + 1 < S.n_chunks) ? (uint64_t)CHUNK : S.n - (uint64_t)(cb + u) * CHUNK;
+                const float d = (float)cnt / ((float)(uint64_t)(th[u] - tl[u]) + 1.0f);
+                dmax = d > dmax ? d : dmax;
             }
         }
         uint32_t tot;
@@ -140,24 +144,29 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     __shared__ uint32_t sh[NW + 1];
     __shared__ int64_t slo[NW], shi[NW];
     __shared__ uint32_t spm[NW];
+    __shared__ float sdm[NW];
     Plan p = {};
     p.status = TRIG_OK;
     p.state = ST_SKIP;
     if (S.n > 0) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
         uint32_t pmax = 0, runs = 0;
+        float dmax = 0.f;
         // a chunk per thread up to NT chunks (16M hits), else eight per thread per round
-        if (S.n_chunks <= (uint32_t)NT) plan_chunks<NT, 1>(S, lo, hi, pmax, runs, sh);
-        else plan_chunks<NT, 8>(S, lo, hi, pmax, runs, sh);
+        if (S.n_chunks <= (uint32_t)NT) plan_chunks<NT, 1>(S, lo, hi, pmax, runs, dmax, sh);
+        else plan_chunks<NT, 8>(S, lo, hi, pmax, runs, dmax, sh);
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
+        // (densities are non-negative: their bit patterns order as unsigned integers)
+        dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
         const int w = threadIdx.x >> 6;
-        if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; }
+        if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; sdm[w] = dmax; }
         __syncthreads();
-        lo = slo[0]; hi = shi[0]; pmax = spm[0];
+        lo = slo[0]; hi = shi[0]; pmax = spm[0]; dmax = sdm[0];
         for (int i = 1; i < NW; ++i) {
             lo = slo[i] < lo ? slo[i] : lo;
             hi = shi[i] > hi ? shi[i] : hi;
             pmax = spm[i] > pmax ? spm[i] : pmax;
+            dmax = sdm[i] > dmax ? sdm[i] : dmax;
         }
         p.t_min = lo; p.t_max = hi; p.n_runs = runs;
         const uint64_t span = (uint64_t)hi - (uint64_t)lo;
@@ -175,7 +184,11 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             }
             p.seg_kind = cap <= (uint32_t)WAVE_CAP ? 0u : 1u;
             // segment width: the largest power of two with expected occupancy <= target
-            const uint64_t x = ((uint64_t)target * (span + 1)) / S.n;
+            // at the slice's mean density plus its densest chunk's (a burst on one
+            // PMT would otherwise overflow the segments it crosses)
+            const float dens = (float)S.n / ((float)span + 1.0f) + dmax;
+            const float xf = (float)target / dens;
+            const uint64_t x = xf >= 1.0f ? (uint64_t)fminf(xf, 4.0e18f) : 0ull;
             uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
             if (sft > 31) sft = 31;
             // many runs: widen the segments (up to half the LDS capacity expected)
