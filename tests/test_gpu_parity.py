@@ -342,3 +342,25 @@ def test_batch_many_slices_with_empty_ones(tr, orc):
     for (pmt, t, q), r in zip(raw, res):
         ref = orc.run(pmt, t, q, floor_id, thr, params, "blocked")
         check(r, ref)
+
+
+def test_one_pmt_burst_keeps_the_fast_ordering(tr, orc):
+    """A 32-PMT slice at 40 kHz per PMT with one PMT at 3 MHz for 20 of its 60 ms.
+    Sized for the mean density alone (2.3 MHz: 131 us segments) a segment in the
+    burst would hold about 560 hits, past the 512 of a wave; sized for the mean
+    plus the densest chunk the segments are half as wide, so the slice stays on
+    the run-merge ordering (path 0) and equals the oracle."""
+    from gen import configs as C
+    from gen.slices import make_slice
+    g, thr = C.geometry("nemo")
+    s = make_slice(g, 60_000_000, 40e3, 91, n_tracks=3, bursts=[(5, 3.0e6, 20_000_000, 20_000_000)])
+    span = int(s.t.max() - s.t.min()) + 1
+    x_mean = 384 * span / s.n                    # the width rule at the mean density
+    width = 1 << (int(x_mean).bit_length() - 1)
+    burst_rate = (32 * 40e3 + 3.0e6) * 1e-9      # hits per ns inside the burst
+    assert burst_rate * width > 512              # (so the case does test the rule)
+    params = dict(C.DEFAULT_PARAMS)
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, s.pmt, s.t, s.q, params, seed_flags=True)
+    check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, params, "blocked"))
+    assert got["path"] == 0
