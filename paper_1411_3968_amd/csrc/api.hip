@@ -207,6 +207,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     stream = s;
     params = *prm;
     slices.assign(n, SliceInfo{});
+    any_tag = reran = false;
     size_t total = 0;
     uint32_t chunk_base = 0, tile_base = 0;
     uint32_t cap_max = 0;
@@ -236,6 +237,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         si.n = nh;
         si.want_flags = want_flags && want_flags[i];
         si.want_tag = want_tags && want_tags[i];
+        any_tag |= si.want_tag;
         si.ws_off = total;
         total += slice_layout(nh, d[i].mem == TRIG_MEM_HOST, si.want_flags, si.L);
         si.chunk_base = chunk_base;
@@ -428,11 +430,17 @@ int Job::launch(trig_ctx *c, bool profile) {
         if (e != hipSuccess) return hip_fail(c, e, "front kernels");
         e = trig_launch_tail(batch, cfg, max_pmt, s, mark, c);
         if (e != hipSuccess) return hip_fail(c, e, "tail kernels");
+        if (any_tag) {
+            // the slices whose events are final here (no rerun pending) are tagged in
+            // the same sequence; a rerun tags again afterwards
+            e = trig_launch_tag(batch, s, mark, c);
+            if (e != hipSuccess) return hip_fail(c, e, "tagged hits");
+        }
         return TRIG_OK;
     };
     if (profile || !graphs_ok || !c->use_graphs) return eager(stream);
     // every host-side launch choice: kernel arguments, grids, variants, LDS sizes
-    const uint32_t extra[4] = {seg_cap, wave_cap, wave_wgs, max_pmt};
+    const uint32_t extra[5] = {seg_cap, wave_cap, wave_wgs, max_pmt, any_tag ? 1u : 0u};
     std::vector<uint8_t> key(sizeof(BatchDev) + sizeof(TrigLaunchCfg) + sizeof(extra));
     std::memcpy(key.data(), &batch, sizeof(BatchDev));
     std::memcpy(key.data() + sizeof(BatchDev), &cfg, sizeof(TrigLaunchCfg));
@@ -494,6 +502,7 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     for (uint32_t i = 0; i < slices.size(); ++i)
         if (slices[i].host_status == TRIG_OK && hp[i].state == ST_NEED_GENERIC) todo.push_back(i);
     if (todo.empty()) return TRIG_OK;
+    reran = true;
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     for (uint32_t i : todo) {
         SliceInfo &si = slices[i];
@@ -536,6 +545,7 @@ int Job::dense_pass(trig_ctx *c, bool profile) {
             (hp[i].state == ST_FAST || hp[i].state == ST_GENERIC_DONE))
             todo.push_back(i);
     if (todo.empty()) return TRIG_OK;
+    reran = true;
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     hipError_t e = hipSuccess;
     for (uint32_t i : todo) {
@@ -553,6 +563,8 @@ int Job::dense_pass(trig_ctx *c, bool profile) {
 // After every pass that can change the events: the tagged-hit lists of the
 // slices that asked for them.
 int Job::tag_pass(trig_ctx *c, bool profile) {
+    // the launch tagged every slice whose events it finished; only a rerun needs more
+    if (!any_tag || !reran) return TRIG_OK;
     bool any = false;
     for (const SliceInfo &si : slices) any |= si.want_tag && si.host_status == TRIG_OK && si.n > 0;
     if (!any) return TRIG_OK;

@@ -91,6 +91,8 @@ struct Job {
     hipGraphExec_t graph_exec = nullptr;
     bool graphs_ok = true;
     bool copies_queued = false;       // deliver queued a device-to-host copy
+    bool any_tag = false;             // some slice asked for its tagged hits (tagged in the launch)
+    bool reran = false;               // a general-ordering or dense-window rerun changed events
 
     // want_flags / fire_caps / event_caps: per slice, may be null (no flags /
     // default staging capacity).

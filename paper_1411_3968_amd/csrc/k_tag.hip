@@ -21,9 +21,12 @@ constexpr int NTT = 256;       // threads per tile workgroup
 constexpr int EV_LDS = NTT;    // events over one tile's time range kept in LDS
 static_assert(TILE % NTT == 0 && NTT % 64 == 0, "tile layout");
 
+// A slice that asked for tags and whose events are final: ordered, triggered, and
+// no dense-window rerun pending (that rerun replaces its events, then tags again).
 __device__ __forceinline__ bool tag_slice(const SliceDev &S, const TRIG_GAS Plan *Pg) {
     const uint32_t st = Pg->state;
-    return S.tag_on && Pg->status == TRIG_OK && (st == ST_FAST || st == ST_GENERIC_DONE || st == ST_DENSE);
+    const bool pending = Pg->dense && st != ST_DENSE;
+    return S.tag_on && Pg->status == TRIG_OK && !pending && (st == ST_FAST || st == ST_GENERIC_DONE || st == ST_DENSE);
 }
 
 __global__ __launch_bounds__(NTT) void k_tag_bits(BatchDev b) {
