@@ -203,7 +203,7 @@ size_t slice_footprint(uint64_t n, bool host_input) {
 
 int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
                  const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
-                 const uint8_t *want_tags) {
+                 const uint8_t *want_tags, const uint64_t *tag_caps) {
     stream = s;
     params = *prm;
     slices.assign(n, SliceInfo{});
@@ -263,7 +263,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         }
     }
     seg_cap = cap_max ? cap_max : 4096;
-    // pinned result staging: plans, then per slice min(n, cap) fires and events
+    // pinned result staging: plans, then per slice min(n, cap) fires and events,
+    // and the tagged list when asked for
     size_t xs = align256(n * sizeof(Plan));
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
@@ -276,6 +277,10 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         xs = align256(xs + fc * sizeof(trig_fire));
         si.x_off_e = xs;
         xs = align256(xs + ec * sizeof(trig_event));
+        const uint64_t tc = si.want_tag ? std::min<uint64_t>(si.n, tag_caps ? tag_caps[i] : dflt) : 0;
+        si.x_tcap = (uint32_t)tc;
+        si.x_off_t = xs;
+        xs = align256(xs + tc * sizeof(uint32_t));
     }
     total_chunks = chunk_base;
     total_tiles = tile_base;
@@ -376,6 +381,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.tagc = (uint32_t *)(b + L.tagc);
         S.tagged = (uint32_t *)(b + L.fsc);   // free once the fires are placed
         S.tag_on = si.want_tag && si.host_status == TRIG_OK ? 1u : 0u;
+        S.x_tagged = si.x_tcap ? (uint32_t *)((char *)x_plans_dev + si.x_off_t) : nullptr;
+        S.x_tag_cap = si.x_tcap;
         S.l0m = (uint64_t *)(b + L.l0m);
         hs[i] = S;
         si.dev = S;
@@ -637,9 +644,13 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
         }
     }
     if (e == hipSuccess && si.want_tag && P.n_tagged) {
-        e = hipMemcpyAsync(r->tagged, si.dev.tagged, (size_t)P.n_tagged * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                           stream);
-        copies_queued = true;
+        if (P.n_tagged <= si.x_tcap)
+            std::memcpy(r->tagged, xb + si.x_off_t, (size_t)P.n_tagged * sizeof(uint32_t));
+        else {
+            e = hipMemcpyAsync(r->tagged, si.dev.tagged, (size_t)P.n_tagged * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, stream);
+            copies_queued = true;
+        }
     }
     if (e != hipSuccess) return r->status = hip_fail(c, e, "D2H of results");
     return r->status = TRIG_OK;
@@ -689,17 +700,18 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
         return TRIG_EINVAL;
     }
     std::vector<uint8_t> flags(n), tags(n);
-    std::vector<uint64_t> fcap(n), ecap(n);
+    std::vector<uint64_t> fcap(n), ecap(n), tcap(n);
     for (uint32_t i = 0; i < n; ++i) {
         flags[i] = res[i].seed_flags != nullptr;
         tags[i] = res[i].tagged != nullptr;
+        tcap[i] = res[i].tagged ? res[i].tagged_cap : 0;
         fcap[i] = res[i].fires ? res[i].fire_cap : 0;
         ecap[i] = res[i].events ? res[i].event_cap : 0;
     }
     Job &J = c->sync_job;
     const bool prof = c->prof_on;
     if (prof) c->prof_stream = s;
-    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data());
+    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data(), tcap.data());
     if (rc) return rc;
     for (uint32_t i = 0; i < n; ++i) J.slices[i].flags_dst = res[i].seed_flags;
     rc = J.launch(c, prof);

@@ -52,8 +52,8 @@ struct SliceInfo {
     uint32_t chunk_base, n_chunks, tile_base, n_tiles;
     trig_tune tune;
     trigdev::SliceDev dev;
-    size_t x_off_f, x_off_e;     // result staging offsets in the pinned buffer
-    uint32_t x_fcap, x_ecap;
+    size_t x_off_f, x_off_e, x_off_t;   // result staging offsets in the pinned buffer
+    uint32_t x_fcap, x_ecap, x_tcap;
     uint8_t *flags_dst;          // caller's host buffer for seed flags (or null)
     bool want_tag;               // the tagged-hit list is asked for
 };
@@ -98,7 +98,7 @@ struct Job {
     // default staging capacity).
     int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
                 const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
-                const uint8_t *want_tags = nullptr);
+                const uint8_t *want_tags = nullptr, const uint64_t *tag_caps = nullptr);
     int launch(trig_ctx *c, bool profile);
     int enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only);   // null: every slice
     int generic_pass(trig_ctx *c, bool profile);

@@ -154,6 +154,9 @@ __global__ __launch_bounds__(NTT) void k_tag_write(BatchDev b) {
     const uint32_t base = gmem(S.tagc)[k];
     const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
     TRIG_GAS uint32_t *out = gmem(S.tagged);
+    // host-mapped staging too when the whole list fits it (else the host copies
+    // the list from device memory)
+    TRIG_GAS uint32_t *xout = (S.x_tagged && Pg->n_tagged <= S.x_tag_cap) ? gmem(S.x_tagged) : nullptr;
     const int lane = lane_id();
     for (uint32_t x = threadIdx.x; x < (uint32_t)TILE; x += NTT) {
         const uint64_t j = a + x;
@@ -161,7 +164,9 @@ __global__ __launch_bounds__(NTT) void k_tag_write(BatchDev b) {
         const uint64_t word = sw[x / 64];
         if ((word >> lane) & 1ull) {
             const uint32_t r = spre[x / 64] + (uint32_t)__popcll(lane ? word & (~0ull >> (64 - lane)) : 0ull);
-            out[base + r] = o_idx[j];
+            const uint32_t v = o_idx[j];
+            out[base + r] = v;
+            if (xout) xout[base + r] = v;
         }
     }
 }

@@ -146,7 +146,9 @@ struct SliceDev {
     uint32_t x_fire_cap, x_event_cap;
     uint32_t *tagc;          // per tile: tagged-hit count, then its exclusive prefix
     uint32_t *tagged;        // tagged hits' input indices (the fire-scratch area)
-    uint32_t tag_on, pad2;   // the caller asked for the tagged list
+    uint32_t tag_on;         // the caller asked for the tagged list
+    uint32_t x_tag_cap;      // capacity of its host-mapped staging
+    uint32_t *x_tagged;      // host-mapped staging of the tagged list (null: none)
     uint64_t *l0m;           // level-0 pass bits by ordered position (level 0 on)
     const uint32_t *adj32;   // per PMT: adjacency group (SC)
     const uint32_t *afl32;   // per PMT: floor rank, 1 apart exactly for consecutive floors (AFC)
