@@ -234,19 +234,34 @@ def bench_serving(T, torch, dev, a):
     cap = max(max(r["n_fires"] for r in alone), max(r["n_events"] for r in alone), 1)
     bufs = [T.ResultBuffers(cap, cap, 0, False) for _ in range(max(a.serve_inflight, 64))]
 
-    def same_as_alone(r, ref):
-        """Counts always; the lists whole up to 2^16 records, else every 61st
-        record plus both ends (a burst slice's 2M fires would otherwise cost the
-        single submitting thread more than the GPU spends on a dozen slices)."""
+    def ref_bytes(ref):
+        """The reference lists as bytes (every field and the zeroed padding of a
+        record), whole up to 2^16 records, else every 61st record plus both ends."""
+        out = []
+        for key in ("fires", "events"):
+            b2 = ref[key]
+            if len(b2) <= 1 << 16:
+                out.append((True, b2.tobytes()))
+            else:
+                out.append((False, (b2[::61].tobytes(), b2[:256].tobytes(), b2[-256:].tobytes())))
+        return out
+
+    alone_b = [ref_bytes(r) for r in alone]
+
+    def same_as_alone(r, k):
+        """Counts always; the lists byte for byte against the slice triggered alone,
+        whole up to 2^16 records, else every 61st record plus both ends (a burst
+        slice's 2M fires would otherwise cost the single submitting thread more
+        than the GPU spends on a dozen slices)."""
+        ref = alone[k]
         if (r["n_fires"], r["n_events"], r["n_seeds"]) != (ref["n_fires"], ref["n_events"], ref["n_seeds"]):
             return False
-        for key in ("fires", "events"):
-            a, b2 = r[key], ref[key]
-            if len(a) <= 1 << 16:
-                if not np.array_equal(a, b2):
+        for key, (whole, rb) in zip(("fires", "events"), alone_b[k]):
+            a = r[key]
+            if whole:
+                if a.tobytes() != rb:
                     return False
-            elif not (np.array_equal(a[::61], b2[::61]) and np.array_equal(a[:256], b2[:256])
-                      and np.array_equal(a[-256:], b2[-256:])):
+            elif (a[::61].tobytes(), a[:256].tobytes(), a[-256:].tobytes()) != rb:
                 return False
         return True
 
@@ -282,7 +297,7 @@ def bench_serving(T, torch, dev, a):
             arr, k, bi = outstanding.pop(tk)
             rc, r = T.trig_stream_poll(tr.ctx, tk, timeout_us=0, buffers=bufs[bi], copy=False)
             lat.append(time.perf_counter() - t_start - arr)
-            if rc != T.TRIG_OK or not same_as_alone(r, alone[k]):
+            if rc != T.TRIG_OK or not same_as_alone(r, k):
                 bad += 1
             free.append(bi)
         return lat, time.perf_counter() - t_start, bad
