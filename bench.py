@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 ALGO_BYTES_PER_HIT = {
     "k_ingest": 20.0,      # read t (8) + pmt (2) + q (2), write the packed word (8)
     "k_bounds": 8.0,       # read t (8); the boundary table is counted separately
-    "k_segsort": 24.0,     # read t, pmt, q (12) + write ordered t, pmt|q, index (12)
-    "k_segsort_w": 20.0,   # read the packed word (8) + write ordered t, pmt|q, index (12)
+    "k_segsort": 20.0,     # read the packed word (8) + write ordered t, pmt|q, index (12)
+    "k_segsort_w": 20.0,   # the same, one wave per segment
     "k_tile": 8.0,         # read ordered t + pmt|q (8): seeds and causal folds; fires are per fire
     "k_tag_bits": 4.125,   # read ordered t (4) + write one tag bit; the few event windows are per event
 }

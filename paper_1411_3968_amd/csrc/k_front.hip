@@ -334,8 +334,7 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     const uint32_t first = blockIdx.x * per;
     const uint32_t end = (first + per < total) ? first + per : total;
     uint32_t si = 0, s_base = 1, s_end = 0;
-    const TRIG_GAS uint16_t *in_pmt = nullptr, *in_q = nullptr;
-    const TRIG_GAS int64_t *in_t = nullptr;
+    const TRIG_GAS uint64_t *in_pk = nullptr;
     const TRIG_GAS uint32_t *pos = nullptr;
     TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     uint32_t pbits = 0;
@@ -345,7 +344,7 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
             si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base_b; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
-            in_pmt = gmem(S.pmt); in_q = gmem(S.q); in_t = gmem(S.t); pos = gmem(S.pos);
+            in_pk = packed_hits(S); pos = gmem(S.pos);
             o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx); pbits = S.pbits;
             s_base = P.seg_item_base_b;
             s_end = s_base + P.n_seg;
@@ -387,22 +386,18 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
                         src[u] = sm.run_lo[a - 1] + (k - sm.run_base[a - 1]);
                     }
                 }
-                int64_t tv[GU];
-                uint32_t pv[GU], qv[GU];
+                // one packed word per hit (one stream of lines per run stretch)
+                uint64_t hv[GU];
 #pragma unroll
                 for (int u = 0; u < GU; ++u) {
-                    if (src[u] != 0xFFFFFFFFu) {
-                        tv[u] = in_t[src[u]];
-                        pv[u] = in_pmt[src[u]];
-                        qv[u] = in_q[src[u]];
-                    }
+                    if (src[u] != 0xFFFFFFFFu) hv[u] = in_pk[src[u]];
                 }
 #pragma unroll
                 for (int u = 0; u < GU; ++u) {
                     if (src[u] != 0xFFFFFFFFu) {
                         const uint32_t k = m + k0 + u * NT + threadIdx.x;
-                        sm.dt[k] = (uint32_t)(tv[u] - P.t_min);
-                        sm.dpq[k] = (pv[u] << 16) | qv[u];
+                        sm.dt[k] = (uint32_t)hv[u] - (uint32_t)(uint64_t)P.t_min;
+                        sm.dpq[k] = (uint32_t)(hv[u] >> 32);
                         sm.didx[k] = src[u];
                     }
                 }
