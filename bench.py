@@ -6,7 +6,7 @@ synthetic 200 ms slice of a KM3Net-It-like tower (84 PMTs on 14 floors x 6,
 55 kHz per PMT, about 924k hits, 20 injected muon tracks), inputs resident in
 HBM before the timed region.  Prints one JSON line.
 
-``--gpus N`` with N > 1 exits: this build drives one GPU.
+``--gpus N`` with N > 1 exits: the benchmark drives one GPU.
 """
 from __future__ import annotations
 
@@ -335,7 +335,7 @@ def bench_serving(T, torch, dev, a):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py drives a single MI355X: multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py drives a single MI355X: multi-GPU runs are not supported", file=sys.stderr)
         sys.exit(2)
     import torch
 
