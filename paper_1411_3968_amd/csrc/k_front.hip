@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
-    const Plan P = gload(gmem(S.plan));
+    const Plan P = gload(gmem(b.plans + si));
     if (P.state != ST_FAST) return;
     const TRIG_GAS int64_t *tin = gmem(S.t);
     __shared__ int64_t st[CHUNK + 2];

@@ -23,7 +23,7 @@ __device__ __forceinline__ bool l0_slice(const BatchDev &b, const SliceDev &S, u
                                          uint32_t item) {
     k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return false;
-    return slice_in_tail(b, gmem(S.plan)->state);
+    return slice_in_tail(b, gmem(b.plans + si)->state);
 }
 
 __global__ __launch_bounds__(NTL) void k_l0_ok(BatchDev b) {

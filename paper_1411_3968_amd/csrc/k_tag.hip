@@ -35,7 +35,7 @@ __global__ __launch_bounds__(NTT) void k_tag_bits(BatchDev b) {
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
-    const TRIG_GAS Plan *Pg = gmem(S.plan);
+    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
     if (!tag_slice(S, Pg)) return;
     const uint64_t n = S.n;
     const uint64_t a = (uint64_t)k * TILE;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(1024) void k_tag_scan(BatchDev b) {
     constexpr int NTS = 1024;
     const uint32_t si = blockIdx.x;
     const SliceDev &S = b.slices[si];
-    TRIG_GAS Plan *Pp = gmem(S.plan);
+    TRIG_GAS Plan *Pp = gmem(b.plans + si);
     if (!tag_slice(S, Pp) || S.n == 0) return;
     __shared__ uint32_t sh[NTS / 64 + 1];
     const uint32_t total = block_scan_array<NTS>(S.tagc, S.n_tiles, sh);
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NTT) void k_tag_write(BatchDev b) {
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
-    const TRIG_GAS Plan *Pg = gmem(S.plan);
+    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
     if (!tag_slice(S, Pg)) return;
     const uint64_t n = S.n;
     const uint64_t a = (uint64_t)k * TILE;

@@ -161,7 +161,9 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
-    Plan *Pp = S.plan;   // generic: the flag updates below are atomics
+    // (the plan by its index, in flight with the descriptor; generic: the flag
+    // updates below are atomics)
+    Plan *Pp = b.plans + si;
     const TRIG_GAS Plan *Pg = gmem(Pp);
     if (!slice_in_tail(b, Pg->state)) return;
     // descriptor fields read once, as global-memory pointers
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     constexpr int NTS = 1024, NWS = NTS / 64;
     const uint32_t si = blockIdx.x;
     const SliceDev &S = b.slices[si];
-    TRIG_GAS Plan *Pp = gmem(S.plan);
+    TRIG_GAS Plan *Pp = gmem(b.plans + si);
     TRIG_GAS TileStat *tstat = gmem(S.tstat);
     __shared__ TileAgg wsum[NWS], wpre[NWS];
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
@@ -741,7 +743,7 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
         uint32_t s_end = base + S.n_tiles;          // first item past this slice
         if (s_end > end) s_end = end;
         if (s_end <= item) { ++item; continue; }    // (an empty slice shares its base)
-        const TRIG_GAS Plan *Pp = gmem(S.plan);
+        const TRIG_GAS Plan *Pp = gmem(b.plans + si);
         // slices outside this pass, and slices that are rerun, place nothing
         const bool live = slice_in_tail(b, Pp->state) && !(Pp->dense && b.tail_state != ST_DENSE);
         if (live) {
