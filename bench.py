@@ -265,6 +265,8 @@ def bench_serving(T, torch, dev, a):
                 return False
         return True
 
+    submit = T.StreamSubmitter(tr.ctx, [(gid,) + d for d in pool], w.params)
+
     def run(order, arrivals, inflight_max):
         """Submit pool[order[i]] at arrivals[i] (None: as soon as fewer than
         inflight_max are outstanding); returns (latencies s, wall s, mismatches)."""
@@ -278,7 +280,7 @@ def bench_serving(T, torch, dev, a):
             while i < n_tot and len(outstanding) < inflight_max and \
                     (arrivals is None or arrivals[i] <= now):
                 k = order[i]
-                rc, tk = T.trig_stream_submit(tr.ctx, gid, *pool[k], w.params, tag=i)
+                rc, tk = submit(k, i)
                 if rc == T.TRIG_EAGAIN:
                     break
                 if rc != T.TRIG_OK:

@@ -341,6 +341,32 @@ def trig_stream_submit(ctx, geom_id: int, pmt, t, q, params: dict | None = None,
     return rc, int(tk.value)
 
 
+class StreamSubmitter:
+    """``trig_stream_submit`` over a fixed set of slices with marshalling done
+    once: the descriptors (``slices``: list of ``(geom_id, pmt, t, q)``) and the
+    parameters are built at construction; a call sets the tag of slice ``i`` and
+    invokes the C ABI (which copies the descriptor into its ticket).  Returns
+    ``(status, ticket)`` like ``trig_stream_submit``."""
+
+    def __init__(self, ctx, slices, params: dict | None = None):
+        self.ctx = ctx
+        self._d, self._keep = [], []
+        for geom_id, pmt, t, q in slices:
+            d, keep = slice_desc(geom_id, pmt, t, q)
+            self._d.append(d)
+            self._keep.append(keep)
+        self.prm = params_struct(params)
+        self._pp = C.byref(self.prm)
+        self._tk = C.c_uint64()
+        self._ptk = C.byref(self._tk)
+
+    def __call__(self, i: int, tag: int = 0):
+        d = self._d[i]
+        d.tag = tag
+        rc = _LIB.trig_stream_submit(self.ctx, C.byref(d), self._pp, self._ptk)
+        return rc, int(self._tk.value)
+
+
 def trig_stream_poll(ctx, ticket: int, timeout_us: int = -1, fire_cap: int = 1 << 16, event_cap: int = 1 << 16,
                      n_hits: int = 0, seed_flags: bool = False, buffers: ResultBuffers | None = None,
                      copy: bool = True):

@@ -190,3 +190,28 @@ def test_long_result_lists_delivered_from_device(T, pool):
         assert np.array_equal(r["events"], ref["events"])
     finally:
         T.trig_destroy(ctx)
+
+
+def test_stream_submitter_equals_alone(T, pool):
+    """Submissions through StreamSubmitter (descriptors built once, tag set per
+    call) give each slice's own result, tags echoed."""
+    alone = _alone(T, pool)
+    ctx = T.trig_create(0)
+    try:
+        g, thr = pool.geoms["km3"]
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        sub = T.StreamSubmitter(ctx, [(gid, s.pmt, s.t, s.q) for _, s in pool.slices], pool.params)
+        order = [3, 0, 7, 3, 11, 5]
+        tickets = []
+        for j, k in enumerate(order):
+            rc, tk = sub(k, tag=100 + j)
+            assert rc == T.TRIG_OK
+            tickets.append((tk, k, 100 + j))
+        for tk, k, tag in tickets:
+            rc, r = T.trig_stream_poll(ctx, tk, timeout_us=-1, fire_cap=1 << 20, event_cap=1 << 20)
+            assert rc == T.TRIG_OK and r["tag"] == tag
+            assert r["n_fires"] == alone[k]["n_fires"] and r["n_events"] == alone[k]["n_events"]
+            assert np.array_equal(r["fires"], alone[k]["fires"])
+            assert np.array_equal(r["events"], alone[k]["events"])
+    finally:
+        T.trig_destroy(ctx)
