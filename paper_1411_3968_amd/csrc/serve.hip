@@ -474,8 +474,16 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
             S->arena.release(t->region, t->footprint);
             t->region = nullptr;
         } else {
+            // the copy out of the ticket's host lists runs without the loop's lock
+            // (the ticket is done and marked busy, so no worker or other poll
+            // touches it), so the workers finishing rounds are not held up
+            t->busy = true;
+            lk.unlock();
             if (r->n_fires) std::memcpy(r->fires, t->fires.data(), r->n_fires * sizeof(trig_fire));
             if (r->n_events) std::memcpy(r->events, t->events.data(), r->n_events * sizeof(trig_event));
+            lk.lock();
+            t->busy = false;
+            it = S->tickets.find(ticket);   // submits may have rehashed the map meanwhile
         }
     }
     const int st = t->status;
