@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--serve-pool", type=int, default=48, help="distinct pre-generated slices replayed")
     ap.add_argument("--serve-slices", type=int, default=10000, help="slices of the saturating run")
     ap.add_argument("--serve-inflight", type=int, default=32)
+    ap.add_argument("--serve-pollers", type=int, default=4, help="threads delivering finished tickets")
     ap.add_argument("--serve-paced-slices", type=int, default=800, help="slices of the real-time run")
     return ap.parse_args()
 
@@ -267,17 +268,44 @@ def bench_serving(T, torch, dev, a):
 
     submit = T.StreamSubmitter(tr.ctx, [(gid,) + d for d in pool], w.params)
 
+    # finished tickets are delivered (polled into their buffers and checked) by a
+    # few threads: the copy of a result's lists runs with Python's lock released,
+    # so one thread's copies no longer cap the rate
+    from concurrent.futures import ThreadPoolExecutor
+    pollers = ThreadPoolExecutor(max_workers=max(1, a.serve_pollers))
+
+    def deliver(tk, arr, k, bi, t_start):
+        rc, r = T.trig_stream_poll(tr.ctx, tk, timeout_us=0, buffers=bufs[bi], copy=False)
+        lat = time.perf_counter() - t_start - arr
+        return lat, rc == T.TRIG_OK and same_as_alone(r, k), bi
+
     def run(order, arrivals, inflight_max):
         """Submit pool[order[i]] at arrivals[i] (None: as soon as fewer than
         inflight_max are outstanding); returns (latencies s, wall s, mismatches)."""
         lat, bad = [], 0
-        outstanding = {}      # ticket -> (arrival, pool index, buffer)
+        pending = {}          # ticket -> (arrival, pool index, buffer): submitted, not finished
+        delivering = []       # deliveries in progress (still counted as outstanding)
         free = list(range(len(bufs)))
         i, n_tot = 0, len(order)
         t_start = time.perf_counter()
-        while i < n_tot or outstanding:
+
+        def collect(wait):
+            nonlocal bad
+            still = []
+            for f in delivering:
+                if wait or f.done():
+                    l, ok, bi = f.result()
+                    lat.append(l)
+                    bad += 0 if ok else 1
+                    free.append(bi)
+                else:
+                    still.append(f)
+            delivering[:] = still
+
+        while i < n_tot or pending or delivering:
+            collect(False)
             now = time.perf_counter() - t_start
-            while i < n_tot and len(outstanding) < inflight_max and \
+            while i < n_tot and len(pending) + len(delivering) < inflight_max and \
                     (arrivals is None or arrivals[i] <= now):
                 k = order[i]
                 rc, tk = submit(k, i)
@@ -285,23 +313,23 @@ def bench_serving(T, torch, dev, a):
                     break
                 if rc != T.TRIG_OK:
                     raise T.TrigError(rc, T.trig_last_error(tr.ctx))
-                outstanding[tk] = (now if arrivals is None else float(arrivals[i]), k, free.pop())
+                pending[tk] = (now if arrivals is None else float(arrivals[i]), k, free.pop())
                 i += 1
             # wait for whichever ticket finishes first (until the next arrival is due)
             wait_us = -1 if (arrivals is None or i >= n_tot) else \
                 max(0, int((arrivals[i] - (time.perf_counter() - t_start)) * 1e6))
-            if not outstanding:
-                time.sleep(max(0.0, wait_us * 1e-6) if wait_us >= 0 else 0.0005)
+            if not pending:
+                if delivering and (wait_us < 0 or len(delivering) >= inflight_max):
+                    collect(True)
+                else:
+                    time.sleep(max(0.0, wait_us * 1e-6) if wait_us >= 0 else 0.0005)
                 continue
             rc, tk = T.trig_stream_next_done(tr.ctx, wait_us)
             if rc != T.TRIG_OK:
                 continue
-            arr, k, bi = outstanding.pop(tk)
-            rc, r = T.trig_stream_poll(tr.ctx, tk, timeout_us=0, buffers=bufs[bi], copy=False)
-            lat.append(time.perf_counter() - t_start - arr)
-            if rc != T.TRIG_OK or not same_as_alone(r, k):
-                bad += 1
-            free.append(bi)
+            arr, k, bi = pending.pop(tk)
+            delivering.append(pollers.submit(deliver, tk, arr, k, bi, t_start))
+        collect(True)
         return lat, time.perf_counter() - t_start, bad
 
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([4, 99])))
@@ -312,7 +340,7 @@ def bench_serving(T, torch, dev, a):
     hits = int(sum(ns[k] for k in order))
     sat = dict(slices=int(len(order)), hits=hits, value=round(hits / wall, 1), unit="hits/s",
                latency_ms=dict(p50=_pct(np.array(lat) * 1e3, 50), p99=_pct(np.array(lat) * 1e3, 99)),
-               inflight=a.serve_inflight, mismatches=bad)
+               inflight=a.serve_inflight, pollers=a.serve_pollers, mismatches=bad)
     # paced: 16 towers, slice k of a tower arrives at k * 200 ms + Exp(10 ms)
     m = a.serve_paced_slices
     k_of = np.arange(m) // 16
@@ -327,6 +355,7 @@ def bench_serving(T, torch, dev, a):
                  latency_ms=dict(p50=_pct(np.array(lat_p) * 1e3, 50), p99=_pct(np.array(lat_p) * 1e3, 99),
                                  max=_pct(np.array(lat_p) * 1e3, 100)),
                  mismatches=bad_p)
+    pollers.shutdown(wait=True)
     stats = T.trig_stream_stats_get(tr.ctx)
     tr.close()
     assert bad == 0 and bad_p == 0, "serving results differ from the slices triggered alone"
