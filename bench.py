@@ -1,16 +1,21 @@
 """Benchmark of the trigger hot path on one MI355X.
 
 One step = one pass of the whole path (ingest, time-order merge, L1 seeds,
-causal N-fold count, fire compaction, event windows, results to host) over one
-synthetic 200 ms slice of a KM3Net-It-like tower (84 PMTs on 14 floors x 6,
-55 kHz per PMT, about 924k hits, 20 injected muon tracks), inputs resident in
-HBM before the timed region.  Prints one JSON line.
+causal N-fold count, fire compaction, event windows, results to host) over the
+largest single-GPU workload: one synthetic 200 ms slice of a detector block of
+32 KM3Net-It-like towers (2688 PMTs, 55 kHz per PMT, 1 % of the PMTs bursting
+at 1 MHz for 20 ms, 200 injected muon tracks, about 30.1M hits, dense 2688^2
+threshold table), inputs resident in HBM before the timed region.  Prints one
+JSON line; further legs of the same line: the single-tower slices (84 and 32
+PMTs) with the paper's rule variants, the host-input (PCIe-inclusive) rate, the
+batched form (256 uneven slices) and the serving form.
 
 ``--gpus N`` with N > 1 exits: the benchmark drives one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -22,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MALL_FLUSH_BYTES = 1 << 30     # touched before every profiled step (the MALL holds 256 MB)
 
 # Algorithmic bytes per input hit of each kernel (what its function must move,
 # each byte counted once).
@@ -33,14 +39,14 @@ ALGO_BYTES_PER_HIT = {
     "k_tile": 8.0,         # read ordered t + pmt|q (8): seeds and causal folds; fires are per fire
     "k_tag_bits": 4.125,   # read ordered t (4) + write one tag bit; the few event windows are per event
 }
+COUNTING_KERNEL = "k_tile"
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` on this workload from the committed counter
-    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy), or
-    None when there is none or the kernel's sources changed since it was taken."""
-    import hashlib
-    fn = os.path.join(ROOT, "profiles", "hbm_traffic_km3.json")
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary (rocprofv3 read/write request counters), or None when there is none
+    or the kernel's sources changed since the counters were taken."""
+    fn = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
     if not os.path.exists(fn):
         return None
     with open(fn) as f:
@@ -57,21 +63,24 @@ def measured_traffic(kernel):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--only-headline", action="store_true", help="the block slice only (profiling runs)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, copy this many MiB once (counter calibration)")
+    ap.add_argument("--no-tower", action="store_true", help="skip the single-tower legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-form leg")
     ap.add_argument("--batch-slices", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-form leg")
-    ap.add_argument("--serve-pool", type=int, default=48, help="distinct pre-generated slices replayed")
+    ap.add_argument("--serve-pool", type=int, default=256, help="distinct pre-generated slices replayed")
     ap.add_argument("--serve-slices", type=int, default=10000, help="slices of the saturating run")
     ap.add_argument("--serve-inflight", type=int, default=32)
     ap.add_argument("--serve-pollers", type=int, default=4, help="threads delivering finished tickets")
-    ap.add_argument("--serve-paced-slices", type=int, default=800, help="slices of the real-time run")
+    ap.add_argument("--serve-paced-slices", type=int, default=10000,
+                    help="slices of the real-time run (16 towers, one slice each per 200 ms)")
     return ap.parse_args()
 
 
@@ -84,154 +93,221 @@ def _pct(x, p):
     return round(float(np.percentile(np.asarray(x), p)), 4) if len(x) else None
 
 
-def bench_tagging(T, torch, tr, gid, pmt, t, q, params, n, steps, warmup, stream):
-    """The same slice with the tagged-hit list asked for (hits inside the event
-    windows, extracted to the host): step time and the tagging kernels."""
-    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, params, stream=stream, tagged=True)
+def _kernel_table(prof, n, per_launch=True):
+    out = {}
+    for p in prof:
+        tot_us = p["total_ms"] * 1e3
+        avg_us = tot_us / max(1, p["launches"])
+        e = dict(avg_us=round(avg_us, 3), launches=int(p["launches"]))
+        if not per_launch:
+            e["total_us"] = round(tot_us, 2)
+        if p["name"] in ALGO_BYTES_PER_HIT:
+            us = avg_us if per_launch else tot_us
+            e["gbs"] = round(ALGO_BYTES_PER_HIT[p["name"]] * n / (us * 1e-6) / 1e9, 1)
+        out[p["name"]] = e
+    return out
+
+
+def time_steps(torch, run, steps, warmup):
+    """Warm-up, then `steps` timed calls bracketed by device synchronisation;
+    returns (seconds per step, per-call latencies, last result)."""
     for _ in range(warmup):
         run()
+    lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    r = None
     for _ in range(steps):
+        ts = time.perf_counter()
         r = run()
+        lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
-    tagged = r["tagged"].copy()
-    T.trig_profile_enable(tr.ctx, True)
+    return (time.perf_counter() - t0) / steps, lat, r
+
+
+def profile_steps(T, torch, ctx, run, steps, flush=None):
+    """Per-kernel durations: the same launch sequence launched kernel by kernel with
+    HIP events around each kernel on its launching stream (event nodes inside a
+    replayed graph do not order with its kernels); `flush` runs before each step,
+    outside the events."""
+    T.trig_profile_enable(ctx, True)
     for _ in range(steps):
+        if flush is not None:
+            flush()
         run()
     torch.cuda.synchronize()
-    prof = T.trig_profile_read(tr.ctx)
-    T.trig_profile_enable(tr.ctx, False)
-    kernels = {}
-    for p in prof:
-        if not p["name"].startswith("k_tag"):
-            continue
-        avg_us = p["total_ms"] / max(1, p["launches"]) * 1e3
-        e = dict(avg_us=round(avg_us, 3), launches=int(p["launches"]))
-        if p["name"] in ALGO_BYTES_PER_HIT:
-            e["gbs"] = round(ALGO_BYTES_PER_HIT[p["name"]] * n / (avg_us * 1e-6) / 1e9, 1)
-        kernels[p["name"]] = e
-    return dict(value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4), n_tagged=int(r["n_tagged"]),
-                kernels=kernels), tagged
+    prof = T.trig_profile_read(ctx)
+    T.trig_profile_enable(ctx, False)
+    return prof
+
+
+def roofline_of(kernels, name, n, workload):
+    k = kernels[name]
+    return dict(bound="hbm", kernel=name, achieved=k["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(k["gbs"] / HBM_PEAK_GBS, 4), traffic=measured_traffic(name, workload),
+                bytes_per_hit=ALGO_BYTES_PER_HIT[name], hits_per_launch=n, avg_us=k["avg_us"])
+
+
+def bench_variant(T, torch, tr, gid, dsl, prm, n, steps, warmup, prefix, setting, **kw):
+    """The same slice with one of the paper's rule variants on: step time and the
+    kernels whose names start with prefix."""
+    run = T.SliceRunner(tr.ctx, gid, *dsl, prm, **kw)
+    el, _, r = time_steps(torch, run, steps, warmup)
+    out = dict(fires=r["fires"].copy(), events=r["events"].copy())
+    if "tagged" in r:
+        out["tagged"] = r["tagged"].copy()
+    prof = profile_steps(T, torch, tr.ctx, run, steps)
+    kernels = {k: v for k, v in _kernel_table(prof, n).items() if k.startswith(prefix)}
+    res = dict(setting=setting, value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
+               n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), kernels=kernels)
+    if "tagged" in r:
+        res["n_tagged"] = int(r["n_tagged"])
+    return res, out
 
 
 # the paper's settings for the 84-PMT tower: level 0 N7TW500, then the candidate
-# selection [SC and AFC] or [FC and AFC] (SC 20 ns, FC 100 ns, AFC 250 ns)
+# selection [SC and AFC] or [FC and AFC] (SC 20 ns, FC 100 ns, AFC 250 ns); the
+# distinct-PMT level 0 of the 32-PMT tower, DN7TW1000
 LEVEL0 = dict(l0_n=7, l0_tw_ns=500)
+LEVEL0_DN = dict(l0_n=7, l0_tw_ns=1000, l0_distinct=1)
 SEED_MENU = dict(LEVEL0, t_adj_ns=20, t_floor_ns=100, t_afloor_ns=250, seed_mode=1)
 
 
-def bench_variant(T, torch, tr, gid, pmt, t, q, prm, n, steps, warmup, stream, prefix, setting):
-    """The same slice with one of the paper's rule variants on: step time and the
-    kernels whose names start with prefix."""
-    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, prm, stream=stream)
-    for _ in range(warmup):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        r = run()
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / steps
-    out = dict(fires=r["fires"].copy(), events=r["events"].copy())
-    T.trig_profile_enable(tr.ctx, True)
-    for _ in range(steps):
-        run()
-    torch.cuda.synchronize()
-    prof = T.trig_profile_read(tr.ctx)
-    T.trig_profile_enable(tr.ctx, False)
-    kernels = {}
-    for p in prof:
-        if p["name"].startswith(prefix):
-            kernels[p["name"]] = dict(avg_us=round(p["total_ms"] / max(1, p["launches"]) * 1e3, 3),
-                                      launches=int(p["launches"]))
-    return dict(setting=setting, value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
-                n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), kernels=kernels), out
+def bench_tower(T, torch, dev, a, orc):
+    """Single-tower slices: the KM3Net-It-like 84-PMT slice (plain rule, tagged
+    hits, N7TW500, DN7TW1000, the seed menu) and the NEMO-like 32-PMT slice, each
+    checked against the oracle."""
+    from gen import configs as C
+    from gen.geometry import bar_end_groups
+    out = {}
+    tr = T.Trigger(0)
+    for key, w in (("km3", C.km3(seed=1)), ("nemo", C.nemo(seed=0))):
+        g, thr = w.geoms[key]
+        s = w.slices[0][1]
+        n = s.n
+        d = _dev_slice(torch, dev, s)
+        torch.cuda.synchronize()
+        gid = tr.load_geometry(g.floor_id, thr)
+        run = T.SliceRunner(tr.ctx, gid, *d, w.params)
+        el, lat, r = time_steps(torch, run, a.steps, a.warmup)
+        res = dict(workload=w.name, hits=n, value=round(n / el, 1), unit="hits/s", ms_per_step=round(el * 1e3, 4),
+                   latency_ms=dict(p50=_pct(np.array(lat) * 1e3, 50), p99=_pct(np.array(lat) * 1e3, 99)),
+                   n_seeds=int(r["n_seeds"]), n_fires=int(r["n_fires"]), n_events=int(r["n_events"]))
+        fires, events = r["fires"].copy(), r["events"].copy()
+        res["kernels"] = _kernel_table(profile_steps(T, torch, tr.ctx, run, a.steps), n)
+        legs = {}
+        if key == "km3":
+            legs["tagging"] = bench_variant(T, torch, tr, gid, d, w.params, n, a.steps, a.warmup, "k_tag",
+                                            "tagged hits (+-H of every fire)", tagged=True)
+            legs["level0"] = bench_variant(T, torch, tr, gid, d, dict(w.params, **LEVEL0), n, a.steps, a.warmup,
+                                           "k_l0", "N7TW500")
+            legs["level0_dn"] = bench_variant(T, torch, tr, gid, d, dict(w.params, **LEVEL0_DN), n, a.steps,
+                                              a.warmup, "k_l0", "DN7TW1000")
+            adj = bar_end_groups(g)
+            gid_adj = tr.load_geometry(g.floor_id, thr, adj)
+            legs["seed_menu"] = bench_variant(T, torch, tr, gid_adj, d, dict(w.params, **SEED_MENU), n, a.steps,
+                                              a.warmup, "k_tile", "N7TW500 then [SC and AFC] or [FC and AFC]")
+        if orc is not None:
+            ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+            res["equals_oracle"] = bool(np.array_equal(ref["fires"], fires) and np.array_equal(ref["events"], events))
+            for name, (leg, o) in legs.items():
+                prm = dict(w.params, **{"level0": LEVEL0, "level0_dn": LEVEL0_DN, "seed_menu": SEED_MENU,
+                                        "tagging": {}}[name])
+                kw = dict(adj_id=bar_end_groups(g)) if name == "seed_menu" else {}
+                rr = ref if name == "tagging" else orc.run(s.pmt, s.t, s.q, g.floor_id, thr, prm, "blocked", **kw)
+                ok = np.array_equal(rr["fires"], o["fires"]) and np.array_equal(rr["events"], o["events"])
+                if name == "tagging":
+                    ok = ok and np.array_equal(orc.tag(s.pmt, s.t, rr["fires"], w.params["half_event_ns"]),
+                                               o["tagged"])
+                leg["equals_oracle"] = bool(ok)
+        for name, (leg, _) in legs.items():
+            res[name] = leg
+        out[key] = res
+        del d
+    tr.close()
+    return out
 
 
 def bench_batch(T, torch, dev, a):
     """Batched form: many uneven slices of two tower types in one launch sequence,
-    against the same slices triggered one call each."""
+    against the same slices triggered one call each.  The ordering stage's launch
+    parameters come from the autotuner, tuned per PMT-count class on a held-out
+    sample of slices drawn with another seed."""
     from gen import configs as C
+    from paper_1411_3968_amd import autotune
     g0 = time.perf_counter()
     w = C.batch(seed=2, n_slices=a.batch_slices)
+    held = C.batch(seed=12, n_slices=64)
     gen_s = time.perf_counter() - g0
     tr = T.Trigger(0)
     gids = {k: tr.load_geometry(g.floor_id, thr) for k, (g, thr) in w.geoms.items()}
+    tuned = {}
+    for key, pmax in (("nemo", 32), ("km3", 84)):
+        sample = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in held.slices if k == key]
+        tuned[key] = autotune.tune_class(tr.ctx, pmax, sample, w.params, reps=5, time_budget_s=20.0)
+        del sample
     dsl = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in w.slices]
     n = int(sum(s.n for _, s in w.slices))
     torch.cuda.synchronize()
-    # ordering-stage launch parameters from the autotuner, tuned on this batch
-    # (one class for both tower types)
-    from paper_1411_3968_amd import autotune
-    tuned = autotune.tune_class(tr.ctx, 84, dsl, w.params, reps=5, time_budget_s=30.0)
     first = tr.batch(dsl, w.params)
     assert all(r["status"] == 0 for r in first)
     caps = [(max(1, r["n_fires"]), max(1, r["n_events"])) for r in first]
     run = T.BatchRunner(tr.ctx, dsl, w.params, caps=caps)
-    for _ in range(2):
-        run()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.batch_steps):
-        res = run()
-    torch.cuda.synchronize()
-    el = (time.perf_counter() - t0) / a.batch_steps
-    # the same slices, one plain per-slice call each
+    el, _, res = time_steps(torch, run, a.batch_steps, 2)
+    res = [dict(r, fires=r["fires"].copy(), events=r["events"].copy()) for r in res]
+    # the same slices, one plain per-slice call each (graph-replayed per slice);
+    # the results are compared after the timed loop
     runners = [T.SliceRunner(tr.ctx, *d, w.params, fire_cap=c[0], event_cap=c[1]) for d, c in zip(dsl, caps)]
     for r in runners:
         r()
+    for r in runners:
+        r()
     torch.cuda.synchronize()
+    outs = []
     t0 = time.perf_counter()
-    same = True
-    for r, b in zip(runners, res):
-        x = r()
-        same &= x["n_fires"] == b["n_fires"] and np.array_equal(x["fires"], b["fires"]) \
-            and np.array_equal(x["events"], b["events"])
+    for r in runners:
+        outs.append(r())
     torch.cuda.synchronize()
     el_loop = time.perf_counter() - t0
+    same = all(x["n_fires"] == b["n_fires"] and np.array_equal(x["fires"], b["fires"]) and
+               np.array_equal(x["events"], b["events"]) for x, b in zip(outs, res))
     assert same, "batched and per-slice results differ"
-    T.trig_profile_enable(tr.ctx, True)
-    run()
-    torch.cuda.synchronize()
-    prof = T.trig_profile_read(tr.ctx)
-    T.trig_profile_enable(tr.ctx, False)
-    # per kernel over the whole pass: a kernel that also reruns single slices
-    # (general ordering, dense windows) has more launches than one per pass, so
-    # its algorithmic rate is taken over its total time
-    kernels = {}
-    for p in prof:
-        tot_us = p["total_ms"] * 1e3
-        e = dict(total_us=round(tot_us, 2), launches=int(p["launches"]))
-        if p["name"] in ALGO_BYTES_PER_HIT:
-            e["gbs"] = round(ALGO_BYTES_PER_HIT[p["name"]] * n / (tot_us * 1e-6) / 1e9, 1)
-        kernels[p["name"]] = e
+    kernels = _kernel_table(profile_steps(T, torch, tr.ctx, run, 1), n, per_launch=False)
     tr.close()
     return dict(workload="batch-256-mixed-32/84pmt-50-200ms", slices=len(dsl), hits=n,
                 value=round(n / el, 1), unit="hits/s", ms_per_batch=round(el * 1e3, 3),
                 per_slice_loop=dict(value=round(n / el_loop, 1), ms=round(el_loop * 1e3, 3)),
                 speedup_vs_per_slice=round(el_loop / el, 3), results_equal_per_slice=bool(same),
                 fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1),
-                autotune=dict({k: tuned["best"][k] for k in ("seg_cap", "seg_target", "grid_per_cu")},
-                              candidates=len(tuned["trials"]), seconds=round(tuned["seconds"], 1),
-                              trials_ms=[[t["seg_cap"], t["seg_target"], t["grid_per_cu"], round(t["s"] * 1e3, 3)]
-                                         for t in tuned["trials"]]))
+                autotune={key: dict({k: t["best"][k] for k in ("seg_cap", "seg_target", "grid_per_cu")},
+                                    sample="held-out: seed 12, %d slices" % sum(1 for k, _ in held.slices if k == key),
+                                    candidates=len(t["trials"]), seconds=round(t["seconds"], 1))
+                          for key, t in tuned.items()})
 
 
-def bench_serving(T, torch, dev, a):
+def bench_serving(T, torch, dev, a, orc):
     """Serving form: slices submitted to the stream loop as they arrive (device
     resident), results polled; every result is checked against the same slice
-    triggered alone."""
+    triggered alone, and each pool slice alone against the oracle."""
     from gen import configs as C
+    g0 = time.perf_counter()
     w = C.serving_pool(seed=4, n_pool=a.serve_pool)
+    gen_s = time.perf_counter() - g0
     g, thr = w.geoms["km3"]
-    tr = T.Trigger(0, hbm_budget_bytes=32 << 30)
+    tr = T.Trigger(0, hbm_budget_bytes=64 << 30)
     gid = tr.load_geometry(g.floor_id, thr)
     pool = [_dev_slice(torch, dev, s) for _, s in w.slices]
     ns = [int(s.n) for _, s in w.slices]
     alone = [tr.slice(gid, *d, w.params) for d in pool]
     torch.cuda.synchronize()
+    oracle_equal = None
+    if orc is not None:
+        oracle_equal = 0
+        for (_, s), r in zip(w.slices, alone):
+            ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
+            oracle_equal += int(np.array_equal(ref["fires"], r["fires"]) and
+                                np.array_equal(ref["events"], r["events"]) and
+                                int(ref["seed"].sum()) == r["n_seeds"])
     cap = max(max(r["n_fires"] for r in alone), max(r["n_events"] for r in alone), 1)
     bufs = [T.ResultBuffers(cap, cap, 0, False) for _ in range(max(a.serve_inflight, 64))]
 
@@ -252,17 +328,17 @@ def bench_serving(T, torch, dev, a):
     def same_as_alone(r, k):
         """Counts always; the lists byte for byte against the slice triggered alone,
         whole up to 2^16 records, else every 61st record plus both ends (a burst
-        slice's 2M fires would otherwise cost the single submitting thread more
-        than the GPU spends on a dozen slices)."""
+        slice's 2M fires would otherwise cost the delivering threads more than
+        the GPU spends on a dozen slices)."""
         ref = alone[k]
         if (r["n_fires"], r["n_events"], r["n_seeds"]) != (ref["n_fires"], ref["n_events"], ref["n_seeds"]):
             return False
         for key, (whole, rb) in zip(("fires", "events"), alone_b[k]):
-            a = r[key]
+            x = r[key]
             if whole:
-                if a.tobytes() != rb:
+                if x.tobytes() != rb:
                     return False
-            elif (a[::61].tobytes(), a[:256].tobytes(), a[-256:].tobytes()) != rb:
+            elif (x[::61].tobytes(), x[:256].tobytes(), x[-256:].tobytes()) != rb:
                 return False
         return True
 
@@ -270,7 +346,7 @@ def bench_serving(T, torch, dev, a):
 
     # finished tickets are delivered (polled into their buffers and checked) by a
     # few threads: the copy of a result's lists runs with Python's lock released,
-    # so one thread's copies no longer cap the rate
+    # so one thread's copies do not cap the rate
     from concurrent.futures import ThreadPoolExecutor
     pollers = ThreadPoolExecutor(max_workers=max(1, a.serve_pollers))
 
@@ -279,7 +355,7 @@ def bench_serving(T, torch, dev, a):
         lat = time.perf_counter() - t_start - arr
         return lat, rc == T.TRIG_OK and same_as_alone(r, k), bi
 
-    def run(order, arrivals, inflight_max):
+    def run(order, arrivals, inflight_max, progress=None):
         """Submit pool[order[i]] at arrivals[i] (None: as soon as fewer than
         inflight_max are outstanding); returns (latencies s, wall s, mismatches)."""
         lat, bad = [], 0
@@ -288,14 +364,15 @@ def bench_serving(T, torch, dev, a):
         free = list(range(len(bufs)))
         i, n_tot = 0, len(order)
         t_start = time.perf_counter()
+        next_note = 30.0
 
         def collect(wait):
             nonlocal bad
             still = []
             for f in delivering:
                 if wait or f.done():
-                    l, ok, bi = f.result()
-                    lat.append(l)
+                    lt, ok, bi = f.result()
+                    lat.append(lt)
                     bad += 0 if ok else 1
                     free.append(bi)
                 else:
@@ -305,6 +382,10 @@ def bench_serving(T, torch, dev, a):
         while i < n_tot or pending or delivering:
             collect(False)
             now = time.perf_counter() - t_start
+            if progress and now > next_note:
+                print(f"[bench] {progress}: {i}/{n_tot} slices submitted after {now:.0f} s", file=sys.stderr,
+                      flush=True)
+                next_note += 30.0
             while i < n_tot and len(pending) + len(delivering) < inflight_max and \
                     (arrivals is None or arrivals[i] <= now):
                 k = order[i]
@@ -345,12 +426,11 @@ def bench_serving(T, torch, dev, a):
     m = a.serve_paced_slices
     k_of = np.arange(m) // 16
     arr = k_of * 0.2 + rng.exponential(0.010, m)
-    ordp = np.argsort(arr, kind="stable")
-    arr = arr[ordp]
+    arr = np.sort(arr, kind="stable")
     porder = rng.integers(0, len(pool), m)
-    lat_p, wall_p, bad_p = run(porder, arr, 1 << 30)
+    lat_p, wall_p, bad_p = run(porder, arr, 1 << 30, progress="serving, paced")
     hits_p = int(sum(ns[k] for k in porder))
-    paced = dict(slices=m, hits=hits_p, offered=round(hits_p / float(arr[-1] + 1e-9), 1),
+    paced = dict(slices=m, towers=16, hits=hits_p, offered=round(hits_p / float(arr[-1] + 1e-9), 1),
                  sustained=round(hits_p / wall_p, 1), unit="hits/s",
                  latency_ms=dict(p50=_pct(np.array(lat_p) * 1e3, 50), p99=_pct(np.array(lat_p) * 1e3, 99),
                                  max=_pct(np.array(lat_p) * 1e3, 100)),
@@ -359,8 +439,49 @@ def bench_serving(T, torch, dev, a):
     stats = T.trig_stream_stats_get(tr.ctx)
     tr.close()
     assert bad == 0 and bad_p == 0, "serving results differ from the slices triggered alone"
-    return dict(workload="serving-16x84pmt-200ms-50-150kHz", pool=len(pool), saturating=sat, paced=paced,
+    return dict(workload="serving-16x84pmt-200ms-50-150kHz", pool=len(pool), pool_hits=int(sum(ns)),
+                pool_equal_oracle=oracle_equal, gen_seconds=round(gen_s, 1), saturating=sat, paced=paced,
                 rounds=stats.get("rounds"), device_bytes_peak=stats.get("device_bytes_peak"))
+
+
+def oracle_baseline(orc, w, cpu_seconds):
+    """The oracle on the host cores: the blocked form on the whole block slice with
+    every host thread (repeated for about cpu_seconds), single-threaded on a 20 ms
+    time sample of the same slice, and the strict (all-pairs) form on the first
+    50 ms of the 32-PMT slice and the first 20 ms of the 84-PMT slice."""
+    from gen import configs as C
+    g, thr = w.geoms["block"]
+    s = w.slices[0][1]
+    threads = os.cpu_count() or 1
+    reps, tc, ref = 0, 0.0, None
+    while tc < cpu_seconds or reps == 0:
+        c0 = time.perf_counter()
+        ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked", threads=threads)
+        tc += time.perf_counter() - c0
+        reps += 1
+    sel = s.t < s.t.min() + 20_000_000
+    c0 = time.perf_counter()
+    orc.run(s.pmt[sel], s.t[sel], s.q[sel], g.floor_id, thr, w.params, "blocked", threads=1)
+    t1 = time.perf_counter() - c0
+    strict = {}
+    for key, wk, ms in (("nemo", C.nemo(seed=0), 50), ("km3", C.km3(seed=1), 20)):
+        gk, thk = wk.geoms[key]
+        sk = wk.slices[0][1]
+        m = sk.t < sk.t.min() + ms * 1_000_000
+        c0 = time.perf_counter()
+        rs = orc.run(sk.pmt[m], sk.t[m], sk.q[m], gk.floor_id, thk, wk.params, "strict", threads=threads)
+        ts = time.perf_counter() - c0
+        rb = orc.run(sk.pmt[m], sk.t[m], sk.q[m], gk.floor_id, thk, wk.params, "blocked", threads=threads)
+        strict[key] = dict(value=round(int(m.sum()) / ts, 1), unit="hits/s", hits=int(m.sum()),
+                           sample=f"first {ms} ms of the slice",
+                           equals_blocked=bool(np.array_equal(rs["fires"], rb["fires"]) and
+                                               np.array_equal(rs["events"], rb["events"])))
+    cpu = dict(value=round(s.n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
+               sample=f"blocked form, whole {s.n}-hit block slice x {reps} runs ({tc:.1f} s)",
+               single_thread=dict(value=round(int(sel.sum()) / t1, 1), unit="hits/s", cores=1,
+                                  sample=f"blocked form, first 20 ms of the block slice ({int(sel.sum())} hits)"),
+               strict=dict(strict, cores=threads))
+    return cpu, ref
 
 
 def main():
@@ -377,126 +498,107 @@ def main():
         print("no GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    w = C.km3(seed=1)
-    g, thr = w.geoms["km3"]
+    g0 = time.perf_counter()
+    w = C.block_workload(seed=3)
+    gen_s = time.perf_counter() - g0
+    g, thr = w.geoms["block"]
     s = w.slices[0][1]
     n = s.n
-    pmt = torch.from_numpy(s.pmt.view(np.int16)).to(dev)
-    t = torch.from_numpy(s.t).to(dev)
-    q = torch.from_numpy(s.q.view(np.int16)).to(dev)
+    pmt, t, q = _dev_slice(torch, dev, s)
     torch.cuda.synchronize()
     tr = T.Trigger(0)
     gid = tr.load_geometry(g.floor_id, thr)
     stream = torch.cuda.current_stream()
     first = tr.slice(gid, pmt, t, q, w.params, stream=stream)
     assert first["status"] == 0
-    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, w.params, stream=stream)
-    for _ in range(a.warmup):
-        run()
+    run = T.SliceRunner(tr.ctx, gid, pmt, t, q, w.params, stream=stream,
+                        fire_cap=first["n_fires"], event_cap=first["n_events"])
     # timed region: the production path (launch sequence replayed as a HIP graph)
-    lat = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        ts = time.perf_counter()
-        r = run()
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el, lat, r = time_steps(torch, run, a.steps, a.warmup)
     assert r["n_fires"] == first["n_fires"] and np.array_equal(r["fires"], first["fires"])
-    # per-kernel durations: the same launch sequence, launched kernel by kernel with
-    # HIP events between the kernels on the launching stream (event nodes inside a
-    # replayed graph do not order with its kernels), right after the timed region
-    T.trig_profile_enable(tr.ctx, True)
-    for _ in range(a.steps):
-        run()
-    torch.cuda.synchronize()
-    prof = T.trig_profile_read(tr.ctx)
-    T.trig_profile_enable(tr.ctx, False)
+    print(f"[bench] block slice: {n} hits, {el * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    # per-kernel durations with the MALL flushed before every step
+    flush_buf = torch.empty(MALL_FLUSH_BYTES // 4, dtype=torch.int32, device=dev)
+
+    def flush():
+        flush_buf.add_(1)
+
+    prof = profile_steps(T, torch, tr.ctx, run, min(a.steps, 10), flush)
     if a.calib_copy_mib:
         x = torch.empty(a.calib_copy_mib << 18, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-
-    kern = {p["name"]: p for p in prof}
-    per_kernel = {}
-    for name, p in kern.items():
-        avg_ms = p["total_ms"] / max(1, p["launches"])
-        entry = dict(avg_us=round(avg_ms * 1e3, 3), launches=p["launches"])
-        if name in ALGO_BYTES_PER_HIT:
-            entry["gbs"] = round(ALGO_BYTES_PER_HIT[name] * n / (avg_ms * 1e-3) / 1e9, 1)
-        per_kernel[name] = entry
+        del x, y
+    del flush_buf
+    per_kernel = _kernel_table(prof, n)
     timed = {k: v for k, v in per_kernel.items() if k in ALGO_BYTES_PER_HIT}
     dom = max(timed, key=lambda k: timed[k]["avg_us"])
-    dom_gbs = timed[dom]["gbs"]
-    roofline = dict(bound="hbm", kernel=dom, achieved=dom_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(dom_gbs / HBM_PEAK_GBS, 4), traffic=measured_traffic(dom),
-                    bytes_per_hit=ALGO_BYTES_PER_HIT[dom], hits_per_launch=n)
+    roofline = roofline_of(per_kernel, dom, n, "block")
+    counting = roofline_of(per_kernel, COUNTING_KERNEL, n, "block") if COUNTING_KERNEL in per_kernel else None
 
-    tagging, tagged = bench_tagging(T, torch, tr, gid, pmt, t, q, w.params, n, a.steps, a.warmup, stream)
-    l0_prm = dict(w.params, **LEVEL0)
-    level0, l0_out = bench_variant(T, torch, tr, gid, pmt, t, q, l0_prm, n, a.steps, a.warmup, stream, "k_l0",
-                                   "N7TW500")
-    from gen.geometry import bar_end_groups
-    adj = bar_end_groups(g)
-    gid_adj = tr.load_geometry(g.floor_id, thr, adj)
-    menu_prm = dict(w.params, **SEED_MENU)
-    seed_menu, menu_out = bench_variant(T, torch, tr, gid_adj, pmt, t, q, menu_prm, n, a.steps, a.warmup, stream,
-                                        "k_tile", "N7TW500 then [SC and AFC] or [FC and AFC]")
+    # end to end with host inputs: pinned host copies of the slice, the H2D copy
+    # inside every step (PCIe-inclusive rate; not the benchmark value)
+    hp = [torch.from_numpy(x).pin_memory() for x in (s.pmt.view(np.int16), s.t, s.q.view(np.int16))]
+    run_h = T.SliceRunner(tr.ctx, gid, hp[0].numpy().view(np.uint16), hp[1].numpy(), hp[2].numpy().view(np.uint16),
+                          w.params, stream=stream, fire_cap=first["n_fires"], event_cap=first["n_events"])
+    el_h, _, r_h = time_steps(torch, run_h, max(3, a.steps // 4), 2)
+    assert np.array_equal(r_h["fires"], first["fires"]) and np.array_equal(r_h["events"], first["events"])
+    host_leg = dict(value=round(n / el_h, 1), unit="hits/s", ms_per_step=round(el_h * 1e3, 4),
+                    inputs="pinned host memory, copied to the device inside every step (PCIe-inclusive)")
+    del run_h, hp
+    first_fires, first_events = first["fires"], first["events"]
+    tr.close()
+    del pmt, t, q
+    torch.cuda.empty_cache()
 
-    cpu = None
+    cpu, orc = None, None
+    equals_oracle = None
     if not a.no_cpu:
         from oracle import cpu as orc
-        threads = os.cpu_count() or 1
-        reps, tc = 0, 0.0
-        ref = None
-        while tc < a.cpu_seconds or reps == 0:
-            c0 = time.perf_counter()
-            ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked", threads=threads)
-            tc += time.perf_counter() - c0
-            reps += 1
-        assert np.array_equal(ref["fires"], r["fires"]) and np.array_equal(ref["events"], r["events"])
-        tagging["equals_oracle"] = bool(np.array_equal(orc.tag(s.pmt, s.t, ref["fires"], w.params["half_event_ns"]),
-                                                       tagged))
-        ref0 = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, l0_prm, "blocked", threads=threads)
-        level0["equals_oracle"] = bool(np.array_equal(ref0["fires"], l0_out["fires"]) and
-                                       np.array_equal(ref0["events"], l0_out["events"]))
-        refm = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, menu_prm, "blocked", threads=threads, adj_id=adj)
-        seed_menu["equals_oracle"] = bool(np.array_equal(refm["fires"], menu_out["fires"]) and
-                                          np.array_equal(refm["events"], menu_out["events"]))
-        cpu = dict(value=round(n * reps / tc, 1), unit="hits/s", cores=threads, kind="oracle",
-                   sample=f"blocked form, whole {n}-hit slice x {reps} runs ({tc:.1f} s)")
+        cpu, ref = oracle_baseline(orc, w, a.cpu_seconds)
+        equals_oracle = bool(np.array_equal(ref["fires"], first_fires) and np.array_equal(ref["events"], first_events)
+                             and int(ref["seed"].sum()) == first["n_seeds"])
+        del ref
+    print("[bench] headline and CPU baseline done", file=sys.stderr, flush=True)
 
-    tr.close()
-    batch = None if a.no_batch else bench_batch(T, torch, dev, a)
-    serving = None if a.no_serve else bench_serving(T, torch, dev, a)
+    tower = batch = serving = None
+    if not a.only_headline:
+        tower = None if a.no_tower else bench_tower(T, torch, dev, a, orc)
+        print("[bench] tower legs done", file=sys.stderr, flush=True)
+        batch = None if a.no_batch else bench_batch(T, torch, dev, a)
+        print("[bench] batched leg done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        serving = None if a.no_serve else bench_serving(T, torch, dev, a, orc)
 
     lat_ms = np.array(lat) * 1e3
     out = dict(
         metric="hits/s triggered on 1 MI355X",
-        value=round(n * a.steps / el, 1),
+        value=round(n / el, 1),
         unit="hits/s",
         n_gpus=1,
         steps=a.steps,
         warmup=a.warmup,
-        ms_per_step=round(el / a.steps * 1e3, 4),
+        ms_per_step=round(el * 1e3, 4),
         higher_is_better=True,
         scaling="weak",
         vs_baseline=None,
         dtype="u32",
         data="synthetic",
-        config=dict(workload="km3net-it-84pmt-200ms", n_pmt=84, hits=n, slice_ms=200, rate_khz=55,
-                    tracks=20, inputs="device-resident", params=w.params),
+        config=dict(workload="block-32x84pmt-200ms", n_pmt=int(g.n_pmt), towers=32, hits=n, slice_ms=200,
+                    rate_khz=55, burst_pmts="1% at 1 MHz for 20 ms", tracks=200, inputs="device-resident",
+                    params=w.params, gen_seconds=round(gen_s, 1)),
         latency_ms=dict(p50=round(float(np.percentile(lat_ms, 50)), 4),
                         p99=round(float(np.percentile(lat_ms, 99)), 4)),
         roofline=roofline,
+        counting_kernel=counting,
         kernels=per_kernel,
+        kernels_note="HIP-event durations per launch, MALL flushed (1 GiB touched) before every profiled step",
         cpu_baseline=cpu,
-        results=dict(n_seeds=r["n_seeds"], n_fires=r["n_fires"], n_events=r["n_events"], path=r["path"]),
-        tagging=tagging,
-        level0=level0,
-        seed_menu=seed_menu,
+        results=dict(n_seeds=first["n_seeds"], n_fires=first["n_fires"], n_events=first["n_events"],
+                     path=first["path"], equals_oracle=equals_oracle),
+        host_inputs=host_leg,
+        tower=tower,
         batched=batch,
         serving=serving,
     )

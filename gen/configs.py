@@ -23,6 +23,8 @@ muon light arrives within 3 us), 4-fold trigger, +-3 us event window
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -45,6 +47,14 @@ class Workload:
 
 
 _GEOM_CACHE: dict = {}
+
+
+def _draw_all(jobs, workers=None):
+    """Run ``make_slice`` jobs (tuples of args and kwargs) on a thread pool; every
+    slice has its own random streams, so the result does not depend on the pool."""
+    workers = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(lambda j: make_slice(*j[0], **j[1]), jobs))
 
 
 def geometry(key: str):
@@ -93,14 +103,15 @@ def batch_specs(seed: int = 2, n_slices: int = 256, len_ms=(50.0, 200.0), rate_k
 def batch(seed: int = 2, n_slices: int = 256, scale: float = 1.0, order: str = "runs") -> Workload:
     """Batched workload; ``scale`` < 1 shortens every slice (tests)."""
     geoms = {k: geometry(k) for k in ("nemo", "km3")}
-    out = []
+    jobs, keys = [], []
     for sp in batch_specs(seed, n_slices):
         L = max(1000, int(sp["length_ns"] * scale))
         bursts = [(bp, br, int(bs * scale), max(1, int(bd * scale))) for (bp, br, bs, bd) in sp["bursts"]]
         g, _ = geoms[sp["key"]]
-        s = make_slice(g, L, sp["rate_hz"], sp["seed"], t0=sp["t0"], n_tracks=sp["n_tracks"] if scale >= 0.05 else 0,
-                       bursts=bursts, order=order)
-        out.append((sp["key"], s))
+        jobs.append(((g, L, sp["rate_hz"], sp["seed"]),
+                     dict(t0=sp["t0"], n_tracks=sp["n_tracks"] if scale >= 0.05 else 0, bursts=bursts, order=order)))
+        keys.append(sp["key"])
+    out = list(zip(keys, _draw_all(jobs)))
     return Workload("batch-256-mixed", geoms, out, dict(DEFAULT_PARAMS))
 
 
@@ -121,12 +132,12 @@ def serving_pool(seed: int = 4, n_pool: int = 256, length_ns: int = SLICE_NS, bu
     """Pool of 84-PMT slices for the serving loop: rate U[50,150] kHz, 2 % at 5x."""
     g, thr = geometry("km3")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 13])))
-    out = []
+    jobs = []
     for i in range(n_pool):
         R = float(rng.uniform(50e3, 150e3))
         if rng.random() < burst_frac:
             R *= 5.0
-        s = make_slice(g, length_ns, R, [seed, i], t0=T0_EPOCH_NS + i * length_ns,
-                       n_tracks=max(0, int(round(20 * length_ns / SLICE_NS))))
-        out.append(("km3", s))
+        jobs.append(((g, length_ns, R, [seed, i]),
+                     dict(t0=T0_EPOCH_NS + i * length_ns, n_tracks=max(0, int(round(20 * length_ns / SLICE_NS))))))
+    out = [("km3", s) for s in _draw_all(jobs)]
     return Workload("serving-16x84pmt", {"km3": (g, thr)}, out, dict(DEFAULT_PARAMS))

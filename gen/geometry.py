@@ -85,7 +85,9 @@ def km3net_it_tower() -> Geometry:
 
 def block(nx: int = 4, ny: int = 8, pitch: float = 90.0, n_floors: int = 14,
           per_floor: int = 6, dz: float = 20.0, arm: float = 8.0) -> Geometry:
-    """``nx * ny`` KM3Net-It-like towers on a square grid; floors numbered globally."""
+    """``nx * ny`` KM3Net-It-like towers on a square grid; floors numbered globally,
+    with a gap of two ids between towers so that only floors of one tower are
+    consecutive (the AFC rule pairs PMTs on consecutive floors of a tower)."""
     one_pos, one_floor = _tower_positions(n_floors, per_floor, dz, arm)
     pos, floor, tid, txy = [], [], [], []
     k = 0
@@ -96,7 +98,7 @@ def block(nx: int = 4, ny: int = 8, pitch: float = 90.0, n_floors: int = 14,
             p[:, 0] += x0
             p[:, 1] += y0
             pos.append(p)
-            floor.append(one_floor + k * n_floors)
+            floor.append(one_floor + k * (n_floors + 2))   # a gap: no two towers have consecutive floors
             tid.append(np.full(len(one_floor), k, np.int32))
             txy.append((x0, y0))
             k += 1

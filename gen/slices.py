@@ -177,8 +177,12 @@ def make_slice(geom: Geometry, length_ns: int, rate_hz, seed, *, t0: int = T0_EP
     if perm is not None:
         pmt, t, q, src = pmt[perm], t[perm], q[perm], src[perm]
     tracks = []
+    # positions of each track's hits, ascending (one pass over the slice)
+    tpos = np.nonzero(src >= 0)[0]
+    tpos = tpos[np.argsort(src[tpos], kind="stable")]
+    bounds = np.searchsorted(src[tpos], np.arange(n_tracks + 1))
     for j in range(n_tracks):
-        pos = np.nonzero(src == j)[0]
+        pos = tpos[bounds[j]:bounds[j + 1]]
         tracks.append(Track(pmt=pmt[pos].astype(np.int64), t=t[pos], q=q[pos].astype(np.int64),
                             hit_index=pos, t_axis=track_axis_times[j]))
     return Slice(pmt=np.ascontiguousarray(pmt), t=np.ascontiguousarray(t),

@@ -57,8 +57,12 @@ extern "C" {
 
 typedef struct trig_ctx trig_ctx;   /* opaque; owns every device buffer it allocates */
 
-/* Create a context on HIP device `device`.  hbm_budget_bytes caps the device
- * memory the context may hold (0 = 32 GiB).  *out is NULL on failure. */
+/* Create a context on HIP device `device`: the state of one trigger process
+ * (Sec. 2: the trigger CPUs receive the time slices of the Hit Managers; Sec. 4:
+ * the TCPU keeps its GPU busy with successive slices).  hbm_budget_bytes caps
+ * the device memory the context may hold (0 = 64 GiB).  Returns TRIG_OK,
+ * TRIG_EINVAL (null out, no such device) or TRIG_EHIP; *out is NULL on
+ * failure.  The context owns every device and pinned host buffer it takes. */
 int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes);
 
 /* Destroy a context: waits for all submitted stream work to finish (tickets
@@ -173,7 +177,7 @@ typedef struct {
  * room for tagged_cap input indices).  The library fills the counts, status
  * and tag.  Fires are ordered by (t_ns, pmt_id, hit_index), events by t_begin.
  * tagged receives the hits inside the event windows (paper Sec. 4.2: the hits
- * within +-3 us of a trigger seed are tagged to be saved; Sec. 2: the 6 us
+ * within +-3 us of a trigger seed are marked for storage; Sec. 2: the 6 us
  * window of tower data around the trigger is stored): the input index of every
  * hit with t_begin <= t <= t_end for some event, ordered by (t, pmt, input
  * index); it is computed only when tagged is not NULL (trig_slice and
@@ -196,30 +200,49 @@ typedef struct {
     uint64_t    tagged_cap, n_tagged;
 } trig_result;
 
-/* Trigger one slice.  Synchronous with respect to the caller's buffers: it
- * returns after the results are in host memory.  Returns result->status. */
+/* Trigger one slice (Sec. 2: the 200 ms time slice is the unit of trigger
+ * work; Sec. 4: the TGPU steps of preparing the slice, sending it to the GPU,
+ * sorting and triggering there (Sec. 4.2), and bringing the trigger seeds and
+ * tagged hits back to be stored).  slice: the hits, host or device memory
+ * (borrowed for the call); params: the rule; result: caller-owned host
+ * buffers, filled as described above; hip_stream: the work is ordered on it.
+ * Synchronous with respect to the caller's buffers: it returns after the
+ * results are in host memory.  Returns result->status: TRIG_OK, TRIG_EINVAL,
+ * TRIG_ERANGE, TRIG_EOVERFLOW (counts filled, no list written), TRIG_ENOMEM
+ * or TRIG_EHIP. */
 int trig_slice(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
                trig_result *result, void *hip_stream);
 
-/* Trigger n slices together: every stage runs once over all slices (device
- * work queues spread the uneven slices over the GPU).  results[i] receives
- * slice i; a bad slice gets its own error status and the others complete.
- * Returns TRIG_OK if every slice succeeded, else the first failing status. */
+/* Trigger n slices together (Sec. 2: successive slices, possibly of several
+ * towers, are handed to trigger processes; Sec. 4: one GPU serves the slices of
+ * a trigger CPU; here every stage runs once over all slices, and device work
+ * lists spread the uneven slices over the GPU).  slices[n] / results[n]: as for
+ * trig_slice, results[i] receives slice i; a bad slice gets its own error
+ * status and the others complete.  Returns TRIG_OK if every slice succeeded,
+ * else the first failing status. */
 int trig_batch(trig_ctx *ctx, uint32_t n, const trig_slice_desc *slices, const trig_params *params,
                trig_result *results, void *hip_stream);
 
-/* Serving: submit a slice for asynchronous triggering.  The inputs are copied
- * (host memory) or borrowed (device memory) and admitted when the context's
- * device budget allows.  Returns TRIG_OK with a ticket, TRIG_EAGAIN when the
- * budget or the slots are full right now, TRIG_ENOMEM when the slice can
- * never fit. */
+/* Serving: submit a slice for asynchronous triggering (Sec. 2: slices arrive
+ * from the Hit Managers every 200 ms and must be triggered within the time the
+ * next ones take to arrive; Sec. 4: the host prepares and sends a slice while
+ * the GPU works on others).  The inputs are copied (host memory, before the
+ * call returns) or borrowed (device memory, until the poll that returns the
+ * result) and admitted when the context's device budget allows.  Returns
+ * TRIG_OK with *ticket set, TRIG_EAGAIN when the budget or the slots are full
+ * right now, TRIG_ENOMEM when the slice can never fit, TRIG_EINVAL /
+ * TRIG_ERANGE for bad arguments. */
 int trig_stream_submit(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
                        uint64_t *ticket);
 
 /* Serving: wait up to timeout_us (0 = do not wait, <0 = wait forever) for a
- * ticket.  Returns TRIG_PENDING if not done, else the slice's status with
- * *result filled as for trig_slice (the caller's buffers in *result are
- * used).  A ticket is released by the poll that returns its result. */
+ * ticket (Sec. 4.2: the trigger seeds and tagged data go back to the CPU, to be
+ * passed on for storage).  Returns TRIG_PENDING if not done (or while another
+ * thread's poll of the same ticket is delivering it), else the slice's status
+ * with *result filled as for trig_slice (the caller's buffers in *result are
+ * used; TRIG_EOVERFLOW keeps the ticket for a poll with larger buffers).  A
+ * ticket is released by the poll that returns its result; polling it again
+ * (or one never issued) gives TRIG_EINVAL. */
 int trig_stream_poll(trig_ctx *ctx, uint64_t ticket, trig_result *result, int32_t timeout_us);
 
 /* Serving: the next ticket whose slice finished (or was cancelled), in order of

@@ -47,7 +47,7 @@
  *           adjacent); seed_mode 0: S_k = Q_k or FC_k or SC_k or AFC_k;
  *           seed_mode 1: S_k = Q_k or ((SC_k or FC_k) and AFC_k)
  *   tagged hits (Sec. 4.2: the hits within +-3 us of a trigger seed are
- *           tagged to be saved): T = { k : |t_k - t_f| <= H for some f in F },
+ *           marked for storage): T = { k : |t_k - t_f| <= H for some f in F },
  *           ordered by (t, p, k)
  *
  * Two forms:  "strict" evaluates every pair (O(n^2));  "blocked" evaluates
@@ -416,8 +416,8 @@ uint64_t orc_events(const orc_fire *f, uint64_t nf, uint32_t half_event_ns, orc_
     return ne;
 }
 
-/* Tagged hits (Sec. 4.2: once the trigger fires, every hit within +-3 us of a
- * trigger seed is tagged to be saved; Sec. 2: the 6 us window of tower data
+/* Tagged hits (Sec. 4.2: once the trigger fires, the hits within +-3 us of a
+ * trigger seed are marked for storage; Sec. 2: the 6 us window of tower data
  * centred on the trigger seed is what goes to storage).  Hit k is tagged when
  * some fire f has |t_k - t_f| <= H.  fires must be ordered by time (as
  * collect_fires leaves them).  out[] (room for n) receives the tagged hits'

@@ -83,17 +83,21 @@ struct Arena {
         return nullptr;
     }
 
-    // A region of `bytes`, growing by a new chunk if no free range fits;
-    // null when the budget does not allow it now.
-    char *alloc(trig_ctx *c, size_t bytes) {
-        bytes = round_up(std::max<size_t>(bytes, 1));
-        if (char *p = take(bytes)) return p;
+    // Size of a new chunk: an eighth of the budget, between 64 MiB and 1 GiB.
+    static size_t grow_min(const trig_ctx *c) {
+        const size_t e = (size_t)(c->budget / 8) & ~(ALIGN - 1);
+        return std::min<size_t>(GROW_MIN, std::max<size_t>(e, 64ull << 20));
+    }
+
+    // A new chunk that starts with a region of `bytes`; null when the budget
+    // does not allow it now.
+    char *grow(trig_ctx *c, size_t bytes) {
         uint64_t room;
         {
             std::lock_guard<std::mutex> g(c->mem_mu);
             room = c->budget > c->bytes_in_use ? c->budget - c->bytes_in_use : 0;
         }
-        size_t want = std::max(bytes, GROW_MIN);
+        size_t want = std::max(bytes, grow_min(c));
         if (want > room) want = room & ~(ALIGN - 1);
         if (want < bytes || ctx_reserve(c, want) != TRIG_OK) return nullptr;
         char *p = nullptr;
@@ -106,6 +110,37 @@ struct Arena {
         if (want > bytes) chunks.back().free.emplace(bytes, want - bytes);
         total += want;
         return p;
+    }
+
+    // Give every chunk that holds no region back to HIP; true if any was.
+    bool shrink(trig_ctx *c) {
+        bool any = false;
+        for (auto it = chunks.begin(); it != chunks.end();) {
+            const bool empty = it->free.size() == 1 && it->free.begin()->first == 0 &&
+                               it->free.begin()->second == it->size;
+            if (empty) {
+                hipFree(it->base);
+                ctx_release(c, it->size);
+                total -= it->size;
+                it = chunks.erase(it);
+                any = true;
+            } else {
+                ++it;
+            }
+        }
+        return any;
+    }
+
+    // A region of `bytes`: first fit in the chunks held, else a new chunk; when
+    // the budget leaves no room for one, the chunks that hold no region are
+    // returned to HIP first (a region never spans chunks, so a slice larger than
+    // any chunk held needs the room they occupy).  Null when nothing fits now.
+    char *alloc(trig_ctx *c, size_t bytes) {
+        bytes = round_up(std::max<size_t>(bytes, 1));
+        if (char *p = take(bytes)) return p;
+        if (char *p = grow(c, bytes)) return p;
+        if (shrink(c)) return grow(c, bytes);
+        return nullptr;
     }
 
     void release(char *p, size_t bytes) {
@@ -417,21 +452,35 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
         return TRIG_EINVAL;
     }
     std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->tickets.find(ticket);
-    if (it == S->tickets.end()) {
+    // The ticket is looked up again after every wait: another thread's poll may
+    // have delivered (and deleted) it meanwhile.  Only the poll that marks the
+    // ticket busy may erase it.
+    auto lookup = [&]() -> Ticket * {
+        auto f = S->tickets.find(ticket);
+        return f == S->tickets.end() ? nullptr : f->second;
+    };
+    Ticket *t = lookup();
+    if (!t) {
         ctx_set_error(c, "unknown ticket %llu", (unsigned long long)ticket);
         return TRIG_EINVAL;
     }
-    Ticket *t = it->second;
     if (t->busy) return TRIG_PENDING;   // another poll of this ticket is delivering it
     if (!t->done) {
         if (timeout_us == 0) return TRIG_PENDING;
-        if (timeout_us < 0) {
-            S->cv_done.wait(lk, [&] { return t->done; });
-        } else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return t->done; })) {
-            return TRIG_PENDING;
+        auto ready = [&] {
+            Ticket *x = lookup();
+            return !x || x->done;
+        };
+        if (timeout_us < 0) S->cv_done.wait(lk, ready);
+        else S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+        t = lookup();
+        if (!t) {
+            ctx_set_error(c, "ticket %llu was delivered by another poll", (unsigned long long)ticket);
+            return TRIG_EINVAL;
         }
+        if (!t->done || t->busy) return TRIG_PENDING;
     }
+    auto it = S->tickets.find(ticket);
     r->n_hits = t->n_hits ? t->n_hits : t->desc.n_hits;
     r->n_seeds = t->n_seeds;
     r->n_fires = t->n_fires;
@@ -489,6 +538,8 @@ int trig_stream_poll(trig_ctx *c, uint64_t ticket, trig_result *r, int32_t timeo
     const int st = t->status;
     S->tickets.erase(it);
     delete t;
+    lk.unlock();
+    S->cv_done.notify_all();   // other polls waiting on this ticket see it gone
     return st;
 }
 

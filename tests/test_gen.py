@@ -88,3 +88,19 @@ def test_bar_end_groups():
             assert m.sum() == per_floor // 2
             assert len(np.unique(geom.floor_id[m])) == 1
             assert np.allclose(geom.pos[m, :2], geom.pos[m, :2][0])
+
+
+def test_block_floors_consecutive_only_within_a_tower():
+    """In the 32-tower block, two PMTs whose floor ids differ by exactly 1 (an AFC
+    pair) always belong to one tower, and every tower's own floors are
+    consecutive; the same-floor (FC) pairs never cross towers either."""
+    from gen import geometry as G
+    g = G.block()
+    f = g.floor_id.astype(np.int64)
+    d = np.abs(f[:, None] - f[None, :])
+    same_tower = g.tower_id[:, None] == g.tower_id[None, :]
+    assert same_tower[d == 1].all()
+    assert same_tower[d == 0].all()
+    for k in np.unique(g.tower_id):
+        fl = np.unique(f[g.tower_id == k])
+        assert len(fl) == 14 and (np.diff(fl) == 1).all()

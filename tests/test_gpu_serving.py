@@ -215,3 +215,124 @@ def test_stream_submitter_equals_alone(T, pool):
             assert np.array_equal(r["events"], alone[k]["events"])
     finally:
         T.trig_destroy(ctx)
+
+
+def _oracle_lists(pool):
+    from oracle import cpu as orc
+    g, thr = pool.geoms["km3"]
+    return [orc.run(s.pmt, s.t, s.q, g.floor_id, thr, pool.params, "blocked") for _, s in pool.slices]
+
+
+def test_serving_pool_equals_oracle_alone_and_in_the_mix(T):
+    """Every slice of a serving pool (rates 50-150 kHz per PMT, two slices at 5x
+    rate) triggered through the stream loop, alone and with the whole pool in
+    flight, gives the oracle's fires, events and seed count."""
+    from gen import configs as C
+    pool = C.serving_pool(seed=4, n_pool=10, length_ns=20_000_000, burst_frac=0.2)
+    rates = [s.n for _, s in pool.slices]
+    assert max(rates) > 3 * min(rates)          # the 5x slices are in the pool
+    refs = _oracle_lists(pool)
+    g, thr = pool.geoms["km3"]
+    ctx = T.trig_create(0)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+
+        def check(k, st, r):
+            assert st == 0
+            assert r["n_seeds"] == int(refs[k]["seed"].sum())
+            assert np.array_equal(r["fires"], refs[k]["fires"])
+            assert np.array_equal(r["events"], refs[k]["events"])
+
+        for k, (_, s) in enumerate(pool.slices):          # alone: one ticket at a time
+            st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+            assert st == 0
+            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 16, event_cap=1 << 16))
+        tks = []
+        for rep in range(3):                                # in the mix: all in flight
+            for k, (_, s) in enumerate(pool.slices):
+                st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+                assert st == 0
+                tks.append((tk, k))
+        for tk, k in tks:
+            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 16, event_cap=1 << 16))
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_two_threads_polling_one_ticket(T, pool):
+    """Two threads wait on the same ticket: exactly one receives the result, the
+    other sees it pending or already delivered, and nothing is freed twice."""
+    s = pool.slices[4][1]
+    g, thr = pool.geoms["km3"]
+    alone = _alone(T, pool)[4]
+    ctx = T.trig_create(0)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        for rep in range(12):
+            T.trig_stream_pause(ctx, True)
+            st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
+            assert st == 0
+            out = [None, None]
+
+            def poller(j):
+                out[j] = T.trig_stream_poll(ctx, tk, -1 if rep % 2 == 0 else 2_000_000,
+                                            fire_cap=1 << 16, event_cap=1 << 16)
+
+            ths = [threading.Thread(target=poller, args=(j,)) for j in range(2)]
+            for th in ths:
+                th.start()
+            T.trig_stream_pause(ctx, False)
+            for th in ths:
+                th.join()
+            codes = sorted(o[0] for o in out)
+            assert codes.count(T.TRIG_OK) == 1, codes
+            other = [c for c in codes if c != T.TRIG_OK][0]
+            assert other in (T.TRIG_PENDING, T.TRIG_EINVAL), codes
+            r = [o[1] for o in out if o[0] == T.TRIG_OK][0]
+            assert np.array_equal(r["fires"], alone["fires"])
+            assert np.array_equal(r["events"], alone["events"])
+            # the ticket is gone for everybody now
+            assert T.trig_stream_poll(ctx, tk, 0)[0] == T.TRIG_EINVAL
+    finally:
+        T.trig_destroy(ctx)
+
+
+def test_slice_larger_than_a_chunk_after_the_arena_filled(T, pool):
+    """The serving arena grows in chunks; once it has grown to the budget with
+    small slices, a slice larger than any chunk is still admitted when the loop
+    is idle (chunks holding no region are given back first) and gives the same
+    result as alone."""
+    from gen import configs as C
+    g, thr = pool.geoms["km3"]
+    small = pool.slices[0][1]
+    big = C.km3(seed=5, length_ns=150_000_000, n_tracks=10).slices[0][1]   # ~700k hits
+    with T.Trigger(0) as tr:
+        gid0 = tr.load_geometry(g.floor_id, thr)
+        ref = tr.slice(gid0, big.pmt, big.t, big.q, pool.params)
+    budget = 512 << 20          # chunks of budget / 8 = 64 MiB
+    ctx = T.trig_create(0, budget)
+    try:
+        gid = T.trig_geom_load(ctx, g.floor_id, thr)
+        T.trig_stream_pause(ctx, True)
+        tks = []
+        while True:
+            st, tk = T.trig_stream_submit(ctx, gid, small.pmt, small.t, small.q, pool.params)
+            if st == T.TRIG_EAGAIN:
+                break
+            assert st == 0 and len(tks) < 200
+            tks.append(tk)
+        assert len(tks) >= 8
+        st, _ = T.trig_stream_submit(ctx, gid, big.pmt, big.t, big.q, pool.params)
+        assert st == T.TRIG_EAGAIN            # the small slices hold the arena
+        T.trig_stream_pause(ctx, False)
+        for tk in tks:
+            assert T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 14, event_cap=1 << 14)[0] == 0
+        st, tk = T.trig_stream_submit(ctx, gid, big.pmt, big.t, big.q, pool.params)
+        assert st == 0, T.trig_last_error(ctx)
+        st, r = T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 20, event_cap=1 << 20)
+        assert st == 0
+        assert np.array_equal(r["fires"], ref["fires"])
+        assert np.array_equal(r["events"], ref["events"])
+        assert T.trig_stream_stats_get(ctx)["device_bytes_peak"] <= budget
+    finally:
+        T.trig_destroy(ctx)
