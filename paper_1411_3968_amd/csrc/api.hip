@@ -192,8 +192,16 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
 // kernels binary-search), then plans and counters.
 static size_t desc_upload_bytes(uint32_t n) { return n * sizeof(SliceDev) + 2 * (size_t)n * sizeof(uint32_t); }
 
-size_t job_meta_bytes(uint32_t n) {
-    return align256(desc_upload_bytes(n)) + align256(n * sizeof(Plan)) + 256;
+size_t job_meta_bytes(uint32_t n, uint32_t total_tiles) {
+    return align256(desc_upload_bytes(n)) + align256(n * sizeof(Plan)) + 256 + align256((size_t)total_tiles * 4);
+}
+
+// Fixed memory: descriptors, plans and counters, then the radix scratch of
+// slices of at most 30 hits (a larger slice holds it in its own fire and event
+// areas), then `ws_total` bytes of slice workspaces.
+static constexpr size_t FIXED_GEN_BYTES = 4096;
+static size_t fixed_layout_bytes(size_t ws_total, uint32_t n, uint32_t total_tiles) {
+    return align256(job_meta_bytes(n, total_tiles)) + FIXED_GEN_BYTES + ws_total;
 }
 
 size_t slice_footprint(uint64_t n, bool host_input) {
@@ -284,9 +292,41 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     total_chunks = chunk_base;
     total_tiles = tile_base;
-    const size_t desc_bytes = job_meta_bytes(n);
-    const bool own_ws = ext_ws.empty();
-    if (!own_ws) {
+    // counting-kernel groups: the largest tile group and halo the slices' classes
+    // ask for, fewer tiles per group while that would leave a compute unit with
+    // less than two workgroups
+    tile_group = 1;
+    halo_cap = 256;
+    for (const SliceInfo &si : slices) {
+        tile_group = std::max(tile_group, si.tune.tile_group);
+        halo_cap = std::max(halo_cap, si.tune.halo_cap);
+    }
+    auto count_groups = [&](uint32_t g) {
+        uint32_t tot = 0;
+        for (const SliceInfo &si : slices) tot += groups_of(si.n_tiles, g);
+        return tot;
+    };
+    while (tile_group > 1 && count_groups(tile_group) < 2u * (uint32_t)std::max(1, c->cfg.n_cu)) tile_group /= 2;
+    total_groups = 0;
+    for (SliceInfo &si : slices) {
+        si.group_base = total_groups;
+        total_groups += groups_of(si.n_tiles, tile_group);
+    }
+    const size_t desc_bytes = job_meta_bytes(n, total_tiles);
+    const bool fixed = fixed_ws != nullptr;
+    if (fixed) {
+        // one region for everything: descriptors, plans and counters first, then
+        // the radix scratch of tiny slices, then the slices' workspaces
+        const size_t need = fixed_layout_bytes(total, n, total_tiles);
+        const size_t pin_need = align256(desc_upload_bytes(n)) + n * sizeof(Plan);
+        if (need > fixed_cap || pin_need > fixed_pin_cap) {
+            ctx_set_error(c, "slice needs %zu bytes of the fixed scratch, which holds %zu", need, fixed_cap);
+            return TRIG_ENOMEM;
+        }
+        ext_ws.clear();
+    }
+    const bool own_ws = ext_ws.empty() && !fixed;
+    if (!ext_ws.empty()) {
         bool bad = ext_ws.size() != n;
         for (uint32_t i = 0; !bad && i < n; ++i) bad = d[i].mem == TRIG_MEM_HOST && d[i].n_hits;
         if (bad) {   // caller-supplied workspaces hold no input staging
@@ -294,31 +334,43 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
             return TRIG_EINVAL;
         }
     }
-    int rc = own_ws ? ws.ensure(c, total, s) : TRIG_OK;
-    if (rc) return rc;
-    rc = dmeta.ensure(c, desc_bytes, s);
-    if (rc) return rc;
-    if (h_slices.ensure(desc_upload_bytes(n) + 64) || h_plans.ensure(xs + 64)) {
-        ctx_set_error(c, "pinned host allocation failed");
-        return TRIG_ENOMEM;
-    }
-    {
+    char *meta = nullptr, *base = nullptr;
+    SliceDev *hs = nullptr;
+    if (fixed) {
+        meta = fixed_ws;
+        fixed_gen = fixed_ws + align256(desc_bytes);
+        base = fixed_gen + FIXED_GEN_BYTES;
+        hs = (SliceDev *)fixed_pin;
+        x_plans_dev = nullptr;   // results are read back by copies
+        for (uint32_t i = 0; i < n; ++i) slices[i].x_fcap = slices[i].x_ecap = slices[i].x_tcap = 0;
+    } else {
+        int rc = own_ws ? ws.ensure(c, total, s) : TRIG_OK;
+        if (rc) return rc;
+        rc = dmeta.ensure(c, desc_bytes, s);
+        if (rc) return rc;
+        if (h_slices.ensure(desc_upload_bytes(n) + 64) || h_plans.ensure(xs + 64)) {
+            ctx_set_error(c, "pinned host allocation failed");
+            return TRIG_ENOMEM;
+        }
         void *dp = nullptr;
         hipError_t e0 = hipHostGetDevicePointer(&dp, h_plans.ptr, 0);
         if (e0 != hipSuccess) return hip_fail(c, e0, "mapping the result staging");
         x_plans_dev = (Plan *)dp;
+        meta = (char *)dmeta.ptr;
+        base = (char *)ws.ptr;
+        hs = (SliceDev *)h_slices.ptr;
     }
-    d_slices = (SliceDev *)dmeta.ptr;
-    d_plans = (Plan *)((char *)dmeta.ptr + align256(desc_upload_bytes(n)));
+    d_slices = (SliceDev *)meta;
+    d_plans = (Plan *)(meta + align256(desc_upload_bytes(n)));
     // (the counters are written by k_bounds before any kernel reads them)
     d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
-    SliceDev *hs = (SliceDev *)h_slices.ptr;
-    char *base = (char *)ws.ptr;
+    // (the group map is written by k_plan before the counting kernel reads it)
+    d_group_slice = (uint32_t *)((char *)d_counters + 256);
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
         SliceDev S;
         std::memset(&S, 0, sizeof S);   // padding too: descriptors are compared bytewise
-        char *b = own_ws ? base + si.ws_off : ext_ws[i];
+        char *b = ext_ws.empty() ? base + si.ws_off : ext_ws[i];   // (fixed memory: base is its workspace part)
         const SliceLayout &L = si.L;
         const uint64_t nh = si.n;
         if (si.host_status == TRIG_OK) {
@@ -353,6 +405,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.n_chunks = si.n_chunks;
         S.tile_base = si.tile_base;
         S.n_tiles = si.n_tiles;
+        S.group_base = si.group_base;
         if (si.tune.seg_cap <= (uint32_t)WAVE_CAP) {
             S.seg_cap = si.tune.seg_cap;
             S.seg_target = std::min<uint32_t>(si.tune.seg_target, si.tune.seg_cap * 3 / 4);
@@ -374,14 +427,14 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.events = (trig_event *)(b + L.events);
         S.seed_flags = si.want_flags ? (uint8_t *)(b + L.flags) : nullptr;
         S.plan = d_plans + i;
-        S.x_fires = (trig_fire *)((char *)x_plans_dev + si.x_off_f);
-        S.x_events = (trig_event *)((char *)x_plans_dev + si.x_off_e);
+        S.x_fires = x_plans_dev ? (trig_fire *)((char *)x_plans_dev + si.x_off_f) : nullptr;
+        S.x_events = x_plans_dev ? (trig_event *)((char *)x_plans_dev + si.x_off_e) : nullptr;
         S.x_fire_cap = si.x_fcap;
         S.x_event_cap = si.x_ecap;
         S.tagc = (uint32_t *)(b + L.tagc);
         S.tagged = (uint32_t *)(b + L.fsc);   // free once the fires are placed
         S.tag_on = si.want_tag && si.host_status == TRIG_OK ? 1u : 0u;
-        S.x_tagged = si.x_tcap ? (uint32_t *)((char *)x_plans_dev + si.x_off_t) : nullptr;
+        S.x_tagged = si.x_tcap && x_plans_dev ? (uint32_t *)((char *)x_plans_dev + si.x_off_t) : nullptr;
         S.x_tag_cap = si.x_tcap;
         S.l0m = (uint64_t *)(b + L.l0m);
         hs[i] = S;
@@ -395,7 +448,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         hbases[n + i] = slices[i].tile_base;
     }
     const size_t up_bytes = desc_upload_bytes(n);
-    if (up_ptr != dmeta.ptr || up_cap != dmeta.cap || up_slices.size() != up_bytes ||
+    if (fixed || up_ptr != dmeta.ptr || up_cap != dmeta.cap || up_slices.size() != up_bytes ||
         std::memcmp(up_slices.data(), hs, up_bytes) != 0) {
         up_ptr = nullptr;
         hipError_t e = hipMemcpyAsync(d_slices, hs, up_bytes, hipMemcpyHostToDevice, s);
@@ -419,6 +472,10 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.counters = d_counters;
     batch.x_plans = x_plans_dev;
     batch.prm = params;
+    batch.tile_group = tile_group;
+    batch.halo_cap = halo_cap;
+    batch.total_groups = total_groups;
+    batch.group_slice = d_group_slice;
     return TRIG_OK;
 }
 
@@ -445,7 +502,7 @@ int Job::launch(trig_ctx *c, bool profile) {
         }
         return TRIG_OK;
     };
-    if (profile || !graphs_ok || !c->use_graphs) return eager(stream);
+    if (profile || !graphs_ok || !c->use_graphs || fixed_ws) return eager(stream);
     // every host-side launch choice: kernel arguments, grids, variants, LDS sizes
     const uint32_t extra[5] = {seg_cap, wave_cap, wave_wgs, max_pmt, any_tag ? 1u : 0u};
     std::vector<uint8_t> key(sizeof(BatchDev) + sizeof(TrigLaunchCfg) + sizeof(extra));
@@ -504,7 +561,7 @@ int Job::enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only) {
 // After the plans arrived on the host: run the general ordering for the slices
 // that need it, then their tail.
 int Job::generic_pass(trig_ctx *c, bool profile) {
-    Plan *hp = (Plan *)h_plans.ptr;
+    Plan *hp = host_plans();
     std::vector<uint32_t> todo;
     for (uint32_t i = 0; i < slices.size(); ++i)
         if (slices[i].host_status == TRIG_OK && hp[i].state == ST_NEED_GENERIC) todo.push_back(i);
@@ -518,7 +575,13 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
         const size_t need = trig_generic_scratch_bytes(si.n);
         const size_t avail = si.L.events + align256(si.n * sizeof(trig_event) + 32) - si.L.fires;
         void *scratch = si.dev.fires;
-        if (need > avail) {
+        if (need > avail && fixed_ws) {
+            if (need > FIXED_GEN_BYTES) {
+                ctx_set_error(c, "internal: radix scratch of %zu bytes does not fit the fixed region", need);
+                return TRIG_ENOMEM;
+            }
+            scratch = fixed_gen;
+        } else if (need > avail) {
             const int rc = gscratch.ensure(c, need, stream);
             if (rc) return rc;
             scratch = gscratch.ptr;
@@ -537,6 +600,8 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
     }
     int rc2 = enqueue_flags(c, &todo);
     if (rc2) return rc2;
+    rc2 = fetch_plans(c);
+    if (rc2) return rc2;
     const hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (general path)");
     return TRIG_OK;
@@ -545,7 +610,7 @@ int Job::generic_pass(trig_ctx *c, bool profile) {
 // After the plans arrived on the host: rerun the trigger stage of the slices
 // whose windows outran the staged halo, with a precomputed seed mask.
 int Job::dense_pass(trig_ctx *c, bool profile) {
-    Plan *hp = (Plan *)h_plans.ptr;
+    Plan *hp = host_plans();
     std::vector<uint32_t> todo;
     for (uint32_t i = 0; i < slices.size(); ++i)
         if (slices[i].host_status == TRIG_OK && hp[i].status == TRIG_OK && hp[i].dense &&
@@ -561,6 +626,8 @@ int Job::dense_pass(trig_ctx *c, bool profile) {
         if (e != hipSuccess) return hip_fail(c, e, "trigger stage (dense rerun)");
     }
     int rc = enqueue_flags(c, &todo);
+    if (rc) return rc;
+    rc = fetch_plans(c);
     if (rc) return rc;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (dense rerun)");
@@ -578,6 +645,8 @@ int Job::tag_pass(trig_ctx *c, bool profile) {
     void (*mark)(void *, const char *, int) = profile ? prof_mark : nullptr;
     hipError_t e = trig_launch_tag(batch, stream, mark, c);
     if (e != hipSuccess) return hip_fail(c, e, "tagged hits");
+    const int rc = fetch_plans(c);
+    if (rc) return rc;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise (tagged hits)");
     return TRIG_OK;
@@ -594,13 +663,14 @@ BatchDev Job::one_slice(uint32_t i, uint32_t state) const {
     b1.total_tiles = slices[i].n_tiles;
     b1.x_plans = x_plans_dev ? x_plans_dev + i : nullptr;
     b1.tail_state = state;
+    b1.total_groups = groups_of(slices[i].n_tiles, tile_group);
     return b1;
 }
 
 // Copy the results of slice i into the caller's result record.
 int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     const SliceInfo &si = slices[i];
-    const Plan &P = ((Plan *)h_plans.ptr)[i];
+    const Plan &P = host_plans()[i];
     r->tag = si.desc.tag;
     r->n_hits = si.desc.n_hits;
     r->path = (P.generic ? 1u : 0u) | (P.dense ? 2u : 0u);
@@ -656,6 +726,18 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     return r->status = TRIG_OK;
 }
 
+Plan *Job::host_plans() const {
+    if (fixed_ws) return (Plan *)((char *)fixed_pin + align256(desc_upload_bytes((uint32_t)slices.size())));
+    return (Plan *)h_plans.ptr;
+}
+
+int Job::fetch_plans(trig_ctx *c) {
+    if (!fixed_ws || slices.empty()) return TRIG_OK;
+    const hipError_t e = hipMemcpyAsync(host_plans(), d_plans, slices.size() * sizeof(Plan), hipMemcpyDeviceToHost,
+                                        stream);
+    return e == hipSuccess ? TRIG_OK : hip_fail(c, e, "D2H of the plans");
+}
+
 void Job::release(trig_ctx *c) {
     if (graph_exec) hipGraphExecDestroy(graph_exec);
     graph_exec = nullptr;
@@ -690,7 +772,7 @@ int check_params(trig_ctx *c, const trig_params *p) {
     return TRIG_OK;
 }
 
-int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
+int run_sync(trig_ctx *c, Job &J, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
              hipStream_t s) {
     int rc = check_params(c, prm);
     if (rc) return rc;
@@ -708,8 +790,7 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
         fcap[i] = res[i].fires ? res[i].fire_cap : 0;
         ecap[i] = res[i].events ? res[i].event_cap : 0;
     }
-    Job &J = c->sync_job;
-    const bool prof = c->prof_on;
+    const bool prof = c->prof_on && !J.fixed_ws;
     if (prof) c->prof_stream = s;
     rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data(), tcap.data());
     if (rc) return rc;
@@ -717,6 +798,8 @@ int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_param
     rc = J.launch(c, prof);
     if (rc) return rc;
     rc = J.enqueue_flags(c, nullptr);
+    if (rc) return rc;
+    rc = J.fetch_plans(c);
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(c, e, "synchronise");
@@ -765,8 +848,12 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     c->cfg.persist_per_cu = 2;
     const char *g = getenv("TRIG_GRAPHS");
     c->use_graphs = !(g && g[0] == '0');
-    trig_tune def = {384, (uint32_t)WAVE_CAP, 3, 0};   // wave per segment; 3 workgroups of 4 waves per CU
-    c->tunes.push_back({0xFFFFFFFFu, def});
+    // wave per segment, 3 workgroups of 4 waves per CU; towers: four tiles per
+    // counting workgroup with small halos; larger detectors: two tiles, wide halos
+    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 4, 256, 0};
+    const trig_tune block = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
+    c->tunes.push_back({128u, tower});
+    c->tunes.push_back({0xFFFFFFFFu, block});
     *out = c;
     return TRIG_OK;
 }
@@ -881,7 +968,7 @@ int trig_slice(trig_ctx *c, const trig_slice_desc *slice, const trig_params *par
         return TRIG_EINVAL;
     }
     hipSetDevice(c->device);
-    int rc = run_sync(c, 1, slice, params, result, (hipStream_t)hip_stream);
+    int rc = run_sync(c, c->sync_job, 1, slice, params, result, (hipStream_t)hip_stream);
     if (rc != TRIG_OK && result->status == TRIG_OK) result->status = rc;
     return rc;
 }
@@ -890,7 +977,7 @@ int trig_batch(trig_ctx *c, uint32_t n, const trig_slice_desc *slices, const tri
                trig_result *results, void *hip_stream) {
     if (!c) return TRIG_EINVAL;
     hipSetDevice(c->device);
-    return run_sync(c, n, slices, params, results, (hipStream_t)hip_stream);
+    return run_sync(c, c->sync_job, n, slices, params, results, (hipStream_t)hip_stream);
 }
 
 int trig_tune_get(trig_ctx *c, uint32_t n_pmt, trig_tune *out) {
@@ -904,7 +991,9 @@ int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
     if (!(t->seg_cap == (uint32_t)WAVE_CAP || t->seg_cap == (uint32_t)WAVE_CAP_SMALL || t->seg_cap == 2048 ||
           t->seg_cap == 4096 || t->seg_cap == 8192) ||
         t->seg_target == 0 ||
-        t->grid_per_cu == 0 || t->grid_per_cu > 16) {
+        t->grid_per_cu == 0 || t->grid_per_cu > 16 ||
+        !(t->tile_group == 1 || t->tile_group == 2 || t->tile_group == 4) ||
+        !(t->halo_cap == 256 || t->halo_cap == 1024)) {
         ctx_set_error(c, "bad tuning values");
         return TRIG_EINVAL;
     }

@@ -49,7 +49,7 @@ struct SliceInfo {
     bool want_flags;
     size_t ws_off;
     SliceLayout L;
-    uint32_t chunk_base, n_chunks, tile_base, n_tiles;
+    uint32_t chunk_base, n_chunks, tile_base, n_tiles, group_base;
     trig_tune tune;
     trigdev::SliceDev dev;
     size_t x_off_f, x_off_e, x_off_t;   // result staging offsets in the pinned buffer
@@ -68,6 +68,8 @@ struct Job {
     uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
     uint32_t wave_cap = 0;            // variant of the wave-per-segment kernel (largest tuned capacity)
     uint32_t total_chunks = 0, total_tiles = 0;
+    uint32_t tile_group = 1, halo_cap = 256, total_groups = 0;   // counting-kernel launch shape
+    uint32_t *d_group_slice = nullptr;
     uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;
     PinBuf h_slices, h_plans;
@@ -90,6 +92,16 @@ struct Job {
     std::vector<uint8_t> seen_key, graph_key;
     hipGraphExec_t graph_exec = nullptr;
     bool graphs_ok = true;
+    // Fixed memory (the allocation-free entry point): when fixed_ws is set, the
+    // workspace, descriptors, plans and counters live in the caller-given device
+    // region [fixed_ws, fixed_ws + fixed_cap) and the descriptor upload and plan
+    // read-back go through the pinned block fixed_pin (allocated beforehand); no
+    // result is staged in host-mapped memory and no graph is captured.
+    char *fixed_ws = nullptr;
+    size_t fixed_cap = 0;
+    void *fixed_pin = nullptr;
+    size_t fixed_pin_cap = 0;
+    char *fixed_gen = nullptr;        // radix scratch of slices too small to hold it in their own lists
     bool copies_queued = false;       // deliver queued a device-to-host copy
     bool any_tag = false;             // some slice asked for its tagged hits (tagged in the launch)
     bool reran = false;               // a general-ordering or dense-window rerun changed events
@@ -106,6 +118,12 @@ struct Job {
     int tag_pass(trig_ctx *c, bool profile);
     int deliver(trig_ctx *c, uint32_t i, trig_result *r);
     trigdev::BatchDev one_slice(uint32_t i, uint32_t state) const;
+    // Host copy of the plans: the pinned staging, or (fixed memory) the pinned block.
+    trigdev::Plan *host_plans() const;
+    // Fixed memory: queue the copy of the device plans to host_plans() (ordered
+    // before the next synchronisation); otherwise nothing (the kernels write the
+    // host-mapped copy themselves).
+    int fetch_plans(trig_ctx *c);
     void release(trig_ctx *c);
 };
 
@@ -144,11 +162,12 @@ int hip_fail(trig_ctx *c, hipError_t e, const char *where);
 int ctx_reserve(trig_ctx *c, uint64_t bytes);
 void ctx_release(trig_ctx *c, uint64_t bytes);
 trig_tune ctx_tune_for(const trig_ctx *c, uint32_t n_pmt);
-int run_sync(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
+int run_sync(trig_ctx *c, Job &J, uint32_t n, const trig_slice_desc *d, const trig_params *prm, trig_result *res,
              hipStream_t s);
 void serve_shutdown(trig_ctx *c);
 // Device bytes one slice of n hits needs in a job workspace (host inputs staged in it or not).
 size_t slice_footprint(uint64_t n, bool host_input);
-// Device bytes of a job's descriptors, plans and counters for n slices.
-size_t job_meta_bytes(uint32_t n);
+// Device bytes of a job's descriptors, plans, counters and group map for n
+// slices of total_tiles trigger tiles.
+size_t job_meta_bytes(uint32_t n, uint32_t total_tiles);
 int check_params(trig_ctx *c, const trig_params *p);   // TRIG_OK or TRIG_EINVAL (message set)

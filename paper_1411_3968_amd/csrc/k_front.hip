@@ -204,6 +204,12 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         }
     }
     if (threadIdx.x == 0) *P = p;
+    // the counting kernel's map from its groups to their slice (every slice,
+    // whatever its state: each group looks its slice up there)
+    if (b.n_slices > 1 && b.group_slice) {
+        const uint32_t ng = groups_of(S.n_tiles, b.tile_group);
+        for (uint32_t g = threadIdx.x; g < ng; g += NT) b.group_slice[S.group_base + g] = si;
+    }
 }
 
 // Work lists of the two ordering kernels (run-merge slices' segments), by one

@@ -43,6 +43,13 @@ __device__ __forceinline__ uint32_t umax(uint32_t a, uint32_t b) { return a > b 
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) { return wave_max_all(v); }
 
+// LDS written by some lanes of a wave, then read by others of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ TileAgg agg_empty() {
     TileAgg a;
     a.F = a.S = a.E_int = a.first_t = a.last_t = a.m_head = a.m_tail = a.ls_t = 0;
@@ -562,8 +569,16 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     const uint32_t t1 = (t0 + per < nt) ? t0 + per : nt;
     // the tile summaries are read in flight with the plan state (they are only
     // used when the slice is in this pass)
+    // (four summaries in flight per thread at a time)
+    constexpr int TB = 4;
     TileAgg mine = agg_empty();
-    for (uint32_t t = t0; t < t1; ++t) mine = agg_combine(mine, gload(&tstat[t].agg), twoH);
+    for (uint32_t t = t0; t < t1; t += TB) {
+        TileAgg x[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) x[u] = t + u < t1 ? gload(&tstat[t + u].agg) : agg_empty();
+#pragma unroll
+        for (int u = 0; u < TB; ++u) mine = agg_combine(mine, x[u], twoH);
+    }
     const uint32_t state = Pp->state;
     if (!slice_in_tail(b, state)) {
         if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
@@ -583,10 +598,15 @@ __global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
     __syncthreads();
     const TileAgg before = wpre[w];   // waves before this one
     TileAgg P = agg_combine(before, wave_shr1(inc, agg_empty()), twoH);
-    for (uint32_t t = t0; t < t1; ++t) {
-        const TileAgg A = gload(&tstat[t].agg);
-        gstore(&tstat[t].pre, P);
-        P = agg_combine(P, A, twoH);
+    for (uint32_t t = t0; t < t1; t += TB) {
+        TileAgg x[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) x[u] = t + u < t1 ? gload(&tstat[t + u].agg) : agg_empty();
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+            if (t + u < t1) gstore(&tstat[t + u].pre, P);
+            P = agg_combine(P, x[u], twoH);
+        }
     }
     if (threadIdx.x != NTS - 1) return;
     const TileAgg I = P;   // the last thread ends with the whole slice
@@ -870,6 +890,388 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
     return launch_tile_nt<NT_MANY, HMAX, MASK, MENU>(b, floor_lds, s);
 }
 
+
+// ------------------------------------------------------------------ k_count
+// The counting kernel of the plain rule (charge or floor-coincidence seeds,
+// causal folds, fires): one workgroup of 256 threads per group of G consecutive
+// tiles of one slice, found through the group map that k_plan writes.
+//  1. The group and up to HMAX ordered neighbours on each side (the halo, sized
+//     from the slice's mean density to span w_ns + t_floor_ns) are staged in
+//     LDS as time and pmt << 16 | floor, a hit per lane and round, so a wave's
+//     round is one 64-hit word: the charge seeds and level-0 bits of the word
+//     come from two ballots.
+//  2. Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., while any
+//     lane of the wave still has its d-th successor within t_floor_ns: a pair
+//     of two PMTs of one floor marks both hits (the successor through 64-bit LDS
+//     ORs at bit x + d).  Most hits have no neighbour that close, so a wave
+//     usually stops after a few steps.
+//  3. The stage's seeds are compacted in LDS (time order kept).
+//  4. Each wave folds 64 consecutive seeds of the group at a time: the seeds
+//     within w_ns of the first and the last of them are read in turn, the same
+//     one by every lane, and each lane counts those within min(thr, w_ns) of its
+//     own seed (eight table reads in flight).
+//  5. Wave t writes the fires of tile t of the group to the tile's slot and the
+//     tile's summary (TileAgg), as the tile-per-workgroup kernel does.
+// A group whose halo does not span the window, or whose stage holds more seeds
+// than the lists, flags its slice for the rerun with a seed mask.
+template <int G, int HMAX>
+struct CountShape {
+    static constexpr int NT = 256, NW = NT / 64;
+    static constexpr int STG = G * TILE + 2 * HMAX;   // staged ordered hits at most
+    static constexpr int U = STG / NT;                // staged hits per thread
+    static constexpr int NWD = STG / 64;              // 64-hit words of the stage
+    static constexpr int CS = STG / 4;                // seeds of a stage the lists hold
+    static constexpr size_t lds_bytes() {
+        return (size_t)STG * 4 * 2 + (size_t)CS * 4 * 2 + (size_t)NWD * 8 * 3 + (size_t)(NWD + 2) * 4 +
+               (size_t)CS * 2 * 3;
+    }
+    static_assert(STG % NT == 0 && G <= NW, "stage layout");
+    static_assert(STG <= 65535, "stage positions are 16-bit");
+};
+
+template <int G, int HMAX>
+__global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
+    using Sh = CountShape<G, HMAX>;
+    constexpr int NT = Sh::NT, U = Sh::U, NWD = Sh::NWD, CS = Sh::CS;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *st = (uint32_t *)smem;                    // staged t - t_min
+    uint32_t *spf = st + Sh::STG;                       // staged pmt << 16 | dense floor index
+    uint32_t *ct = spf + Sh::STG;                       // compacted seeds: time
+    uint32_t *fold = ct + CS;                           // fold of each seed of the group
+    uint64_t *qw = (uint64_t *)(fold + CS);             // charge seeds, then all seeds, per word
+    uint64_t *lw = qw + NWD;                            // level-0 pass bits per word
+    uint64_t *pw = lw + NWD;                            // floor-partner bits per word
+    uint32_t *wpre = (uint32_t *)(pw + NWD);            // seeds before each word (NWD + 1)
+    uint16_t *cp = (uint16_t *)(wpre + NWD + 2);        // compacted seeds: PMT
+    uint16_t *cidx = cp + CS;                           // compacted seeds: stage position
+    uint16_t *fci = cidx + CS;                          // fires of each tile: compacted index
+    uint16_t *lfl = fci + CS;                           // dense floor index of every PMT (floor_lds of them)
+    __shared__ uint32_t sh[Sh::NW + 1];
+
+    // XCD-aware order: workgroup b runs on XCD b % 8 and takes groups from that
+    // XCD's contiguous eighth of the list (neighbouring groups share halos in one L2)
+    const uint32_t per_xcd = (b.total_groups + 7) / 8;
+    const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (item >= b.total_groups) return;
+    const uint32_t si = b.n_slices <= 1 ? 0u : gmem(b.group_slice)[item];
+    const SliceDev &S = b.slices[si];
+    const uint32_t g = item - (b.n_slices <= 1 ? 0u : S.group_base);
+    const uint32_t k0 = g * (uint32_t)G;            // first tile of the group
+    if (k0 >= S.n_tiles) return;
+    Plan *Pp = b.plans + si;
+    const TRIG_GAS Plan *Pg = gmem(Pp);
+    if (!slice_in_tail(b, Pg->state)) return;
+    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
+    const TRIG_GAS uint32_t *o_pq = gmem(S.o_pq);
+    const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
+    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
+    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
+    const TRIG_GAS uint16_t *floor16 = gmem(S.floor16);
+    TRIG_GAS uint8_t *seed_flags = gmem(S.seed_flags);
+    const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
+    const uint32_t n_pmt = S.n_pmt;
+    const uint64_t n = S.n;
+    const uint32_t n_tiles = S.n_tiles;
+    const int64_t t_min = Pg->t_min;
+    const uint64_t span = (uint64_t)(Pg->t_max - t_min);
+    const uint32_t W = b.prm.w_ns;
+    const uint32_t N = b.prm.min_fold;
+    const int32_t tau = b.prm.t_floor_ns;
+    const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
+    const uint32_t q_seed = b.prm.q_seed;
+    const bool L0 = b.prm.l0_n > 0;
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+
+    const uint64_t a = (uint64_t)k0 * TILE;
+    const uint64_t e = (a + (uint64_t)G * TILE < n) ? a + (uint64_t)G * TILE : n;
+    // halo: twice the mean number of hits in w_ns + t_floor_ns, plus a margin
+    const uint64_t reach = (uint64_t)W + tau_u;
+    uint64_t halo = (2ull * n * reach) / (span + 1) + 64;
+    if (halo > (uint64_t)HMAX) halo = HMAX;
+    const uint64_t sl = a > halo ? a - halo : 0;
+    const uint64_t she = (e + halo < n) ? e + halo : n;
+    const uint32_t len = (uint32_t)(she - sl);
+    const uint32_t nwords = (len + 63) / 64;
+
+    // 1. stage: all loads of a thread in flight, then the words of each round
+    uint32_t vt[U], vp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t x = u * NT + threadIdx.x;
+        if (x < len) {
+            vt[u] = o_t[sl + x];
+            vp[u] = o_pq[sl + x];
+        }
+    }
+    const bool floor_in_lds = n_pmt <= floor_lds;
+    if (floor_in_lds)
+        for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t x = u * NT + threadIdx.x;
+        const bool in = x < len;
+        bool l0x = in;
+        if (L0 && in) {
+            const uint64_t j = sl + x;
+            l0x = (l0m[j >> 6] >> (j & 63)) & 1ull;
+        }
+        const uint64_t lb = __ballot(l0x);
+        const uint64_t qb = __ballot(in && (vp[u] & 0xFFFFu) >= q_seed) & lb;
+        const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
+        if (lane == 0) {
+            qw[wd] = qb;
+            lw[wd] = lb;
+            pw[wd] = 0ull;
+        }
+        if (in) st[x] = vt[u];
+    }
+    __syncthreads();   // floor numbering and times staged
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t x = u * NT + threadIdx.x;
+        if (x < len) {
+            const uint32_t p = vp[u] >> 16;
+            const uint32_t f = floor_in_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
+            vp[u] = (p << 16) | f;
+            spf[x] = vp[u];
+        }
+    }
+    __syncthreads();
+    const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
+    // the stage spans the window of every seed of the group when the halo reaches
+    // past w_ns + t_floor_ns on both sides (or the slice ends there)
+    const bool cover_l = sl == 0 || (uint64_t)st[0] + reach < (uint64_t)ta;
+    const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + reach;
+    const bool covered = cover_l && cover_r;
+
+    // 2. floor-coincidence pairs (x, x + d) within the stage
+    if (covered && tau >= 0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if ((uint32_t)(u * NT + w * 64) >= len) break;   // (wave-uniform)
+            const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
+            const uint32_t x = u * NT + threadIdx.x;
+            const bool in0 = x < len;
+            const uint32_t t = in0 ? vt[u] : 0u, f = in0 ? vp[u] : 0u;
+            const bool l0x = (lw[wd] >> lane) & 1ull;
+            uint64_t own = 0;
+            for (uint32_t d = 1;; ++d) {
+                const uint32_t y = x + d;
+                const bool inr = in0 && y < len;
+                const uint32_t yc = inr ? y : 0u;
+                const uint32_t ty = st[yc], gy = spf[yc];
+                const bool near = inr && ty - t <= tau_u;
+                if (!__ballot(near)) break;
+                const bool l0y = !L0 || ((lw[yc >> 6] >> (yc & 63)) & 1ull);
+                const bool pr = near && ((gy & 0xFFFFu) == (f & 0xFFFFu)) && ((gy >> 16) != (f >> 16)) && l0x && l0y;
+                const uint64_t M = __ballot(pr);
+                if (M) {
+                    own |= M;
+                    if (lane == 0) {
+                        // the successors at x + d: bit (lane + d) counted from word wd
+                        const uint32_t s = d & 63, w0 = wd + (d >> 6);
+                        atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << s));
+                        const uint64_t spill = s ? (M >> (64 - s)) : 0ull;
+                        if (spill) atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                    }
+                }
+            }
+            if (lane == 0 && own) atomicOr((unsigned long long *)&pw[wd], (unsigned long long)own);
+        }
+    }
+    __syncthreads();
+
+    // 3. seed words, their prefix, and the compacted seeds of the stage
+    uint32_t total = 0;
+    {
+        uint64_t sw = 0;
+        if (threadIdx.x < nwords) sw = qw[threadIdx.x] | pw[threadIdx.x];
+        static_assert(NWD <= NT, "one word per thread");
+        const uint32_t ex = block_excl_scan<NT>((uint32_t)__popcll(sw), total, sh);
+        if (threadIdx.x < nwords) {
+            qw[threadIdx.x] = sw;
+            wpre[threadIdx.x] = ex;
+        }
+        if (threadIdx.x == 0) wpre[nwords] = total;
+    }
+    __syncthreads();
+    // seeds before stage position x (x <= len)
+    auto seeds_before = [&](uint32_t x) -> uint32_t {
+        const uint32_t wd = x >> 6, bit = x & 63;
+        if (wd >= nwords) return total;
+        return wpre[wd] + (bit ? (uint32_t)__popcll(qw[wd] & (~0ull >> (64 - bit))) : 0u);
+    };
+    const bool fits = total <= (uint32_t)CS;
+    const bool ok = covered && fits;
+    if (!ok && threadIdx.x == 0) atomicOr(&Pp->dense, 1u);   // rerun with a seed mask
+    const uint32_t ca = ok ? seeds_before((uint32_t)(a - sl)) : 0u;
+    const uint32_t cb = ok ? seeds_before((uint32_t)(e - sl)) : 0u;
+    if (ok) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
+            if (x < len && ((qw[x >> 6] >> (x & 63)) & 1ull)) {
+                const uint32_t r = seeds_before(x);
+                ct[r] = vt[u];
+                cp[r] = (uint16_t)(vp[u] >> 16);
+                cidx[r] = (uint16_t)x;
+            }
+        }
+    }
+    __syncthreads();
+
+    // 4. causal folds of the group's seeds, 64 consecutive seeds per wave at a time
+    if (ok) {
+        const bool t16 = W <= 65535u;
+        for (uint32_t c0 = ca + (uint32_t)w * 64; c0 < cb; c0 += NT) {
+            const uint32_t i = c0 + (uint32_t)lane;
+            const bool vi = i < cb;
+            const uint32_t last = (c0 + 63 < cb) ? c0 + 63 : cb - 1;
+            const uint32_t ti = ct[vi ? i : last];
+            const uint64_t row = (uint64_t)cp[vi ? i : last] * n_pmt;
+            // seeds within w_ns of the first and the last seed of this run
+            const uint32_t t_lo = ct[c0] > W ? ct[c0] - W : 0u;
+            const uint64_t t_hi = (uint64_t)ct[last] + W;
+            uint32_t jl = 0, z = c0;
+            while (jl < z) {
+                const uint32_t mid = (jl + z) >> 1;
+                if (ct[mid] < t_lo) jl = mid + 1; else z = mid;
+            }
+            uint32_t jr = last + 1;
+            z = total;
+            while (jr < z) {
+                const uint32_t mid = (jr + z) >> 1;
+                if ((uint64_t)ct[mid] <= t_hi) jr = mid + 1; else z = mid;
+            }
+            constexpr int CB = 8;
+            uint32_t c = 0;
+            for (uint32_t j0 = jl; j0 < jr; j0 += CB) {
+                uint32_t dd[CB], lim[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const uint32_t j = j0 + k;
+                    const uint32_t jc = j < jr ? j : jr - 1;
+                    const uint32_t tj = ct[jc];
+                    const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                    const bool use = vi && j < jr && j != i && dt <= W;
+                    dd[k] = 0xFFFFFFFFu;
+                    lim[k] = 0;
+                    if (use) {
+                        const uint64_t x = row + cp[jc];
+                        lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
+                        dd[k] = dt;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
+            }
+            if (vi) fold[i - ca] = c + 1;
+        }
+        if (seed_flags) {
+            for (uint64_t j = a + threadIdx.x; j < e; j += NT) {
+                const uint32_t x = (uint32_t)(j - sl);
+                seed_flags[o_idx[j]] = (uint8_t)((qw[x >> 6] >> (x & 63)) & 1ull);
+            }
+        }
+    }
+    __syncthreads();
+
+    // 5. fires and summary of tile k0 + w, by wave w
+    if (w >= G) return;
+    const uint32_t tt = k0 + (uint32_t)w;
+    if (tt >= n_tiles) return;
+    const uint64_t ta0 = (uint64_t)tt * TILE;
+    const uint64_t te0 = (ta0 + TILE < n) ? ta0 + TILE : n;
+    const uint32_t cs = ok ? seeds_before((uint32_t)(ta0 - sl)) : 0u;
+    const uint32_t ce = ok ? seeds_before((uint32_t)(te0 - sl)) : 0u;
+    TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)tt * TILE;
+    uint16_t *tf = fci + (cs - ca);   // this tile's fires, as compacted indices
+    uint32_t nf = 0;
+    for (uint32_t r0 = cs; r0 < ce; r0 += 64) {
+        const uint32_t i = r0 + (uint32_t)lane;
+        const bool f = i < ce && fold[i - ca] >= N;
+        const uint64_t M = __ballot(f);
+        if (f) {
+            const uint32_t pos = nf + (uint32_t)__popcll(M & ((1ull << lane) - 1ull));
+            tf[pos] = (uint16_t)i;
+            FireRec fr;
+            fr.t = ct[i];
+            fr.hit = o_idx[sl + cidx[i]];
+            fr.fold = fold[i - ca];
+            fr.pmt = cp[i];
+            gstore(slot + pos, fr);
+        }
+        nf += (uint32_t)__popcll(M);
+    }
+    wave_lds_sync();
+    TileAgg A = agg_empty();
+    A.S = ce - cs;
+    A.F = nf;
+    uint32_t prev_t = 0, first_int = NO_START, last_int = NO_START, m_head = 0, m_tail = 0;
+    for (uint32_t r0 = 0; r0 < nf; r0 += 64) {
+        const uint32_t r = r0 + (uint32_t)lane;
+        const bool v = r < nf;
+        uint32_t t = 0, fd = 0;
+        if (v) {
+            const uint32_t ci = tf[r];
+            t = ct[ci];
+            fd = fold[ci - ca];
+        }
+        // the lane move runs in every lane (under a select lane 1 would read the fill value)
+        const uint32_t t_below = wave_shr1(t, 0u);
+        const uint32_t tp = lane == 0 ? prev_t : t_below;
+        const bool is_int = v && r > 0 && (uint64_t)(t - tp) > twoH;
+        const uint64_t ib = __ballot(is_int);
+        if (r0 == 0) A.first_t = lane_read(t, 0);
+        prev_t = lane_read(t, 63);
+        if (ib) {
+            const int lo = __ffsll((unsigned long long)ib) - 1;
+            const int hi = 63 - __clzll((long long)ib);
+            if (first_int == NO_START) {
+                first_int = r0 + lo;
+                m_head = umax(m_head, wave_max_u32(v && lane < lo ? fd : 0u));
+            }
+            last_int = r0 + hi;
+            m_tail = wave_max_u32(v && lane >= hi ? fd : 0u);
+            A.ls_t = lane_read(t, hi);
+        } else {
+            const uint32_t mx = wave_max_u32(v ? fd : 0u);
+            if (first_int == NO_START) m_head = umax(m_head, mx);
+            m_tail = umax(m_tail, mx);
+        }
+        A.E_int += (uint32_t)__popcll(ib);
+    }
+    if (nf) A.last_t = ct[tf[nf - 1]];
+    A.m_tail = m_tail;
+    A.m_head = first_int == NO_START ? m_tail : m_head;
+    A.ls_idx = last_int;
+    if (last_int == NO_START) A.ls_t = 0;
+    if (lane == 0) gstore(&gmem(S.tstat)[tt].agg, A);
+}
+
+template <int G, int HMAX>
+hipError_t launch_count_v(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
+    using Sh = CountShape<G, HMAX>;
+    const size_t shm = Sh::lds_bytes() + ((floor_lds * 2 + 15) & ~15u);
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_count<G, HMAX>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(Sh::lds_bytes() + FLOOR_LDS_MAX * 2));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_count<G, HMAX>), dim3(((b.total_groups + 7) / 8) * 8), dim3(256), shm, s, b, floor_lds);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
+    const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
+    const bool wide = b.halo_cap > 256;
+    switch (b.tile_group) {
+    case 4: return wide ? launch_count_v<4, 1024>(b, floor_lds, s) : launch_count_v<4, 256>(b, floor_lds, s);
+    case 2: return wide ? launch_count_v<2, 1024>(b, floor_lds, s) : launch_count_v<2, 256>(b, floor_lds, s);
+    default: return wide ? launch_count_v<1, 1024>(b, floor_lds, s) : launch_count_v<1, 256>(b, floor_lds, s);
+    }
+}
+
 }  // namespace
 
 #define TRIG_MARK(name, ph) do { if (mark) mark(mark_ctx, name, ph); } while (0)
@@ -882,14 +1284,16 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
         hipError_t e0 = trig_launch_l0(b, s, mark, mark_ctx);
         if (e0 != hipSuccess) return e0;
     }
-    TRIG_MARK("k_tile", 0);
-    // the seed menu (SC, AFC, their combination) runs in a variant of its own
+    // the seed menu (SC, AFC, their combination) and the dense rerun run in
+    // variants of the tile-per-workgroup kernel; the plain rule in the counting kernel
     const bool menu = b.prm.t_adj_ns >= 0 || b.prm.t_afloor_ns >= 0 || b.prm.seed_mode != 0;
+    const char *kname = (dense || menu) ? "k_tile" : "k_count";
+    TRIG_MARK(kname, 0);
     hipError_t e = dense ? launch_tile<HALO_BIG, true, false>(b, max_pmt, n_cu, s)
                  : menu  ? launch_tile<HALO_SMALL, false, true>(b, max_pmt, n_cu, s)
-                         : launch_tile<HALO_SMALL, false, false>(b, max_pmt, n_cu, s);
+                         : launch_count(b, max_pmt, s);
     if (e != hipSuccess) return e;
-    TRIG_MARK("k_tile", 1);
+    TRIG_MARK(kname, 1);
     TRIG_MARK("k_tscan", 0);
     hipLaunchKernelGGL(k_tscan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();

@@ -213,7 +213,7 @@ static void run_round(ServeState *S, Job &job, hipStream_t stream, std::vector<T
     if (rc == TRIG_OK) rc = job.generic_pass(c, false);
     if (rc == TRIG_OK) rc = job.dense_pass(c, false);
     if (rc == TRIG_OK) {
-        const trigdev::Plan *hp = (const trigdev::Plan *)job.h_plans.ptr;
+        const trigdev::Plan *hp = job.host_plans();
         for (uint32_t i = 0; i < n; ++i) {
             Ticket *t = round[i];
             const SliceInfo &si = job.slices[i];
@@ -309,7 +309,7 @@ static ServeState *serve_get(trig_ctx *c) {
     // a budget filled by admitted slices never starves a round of them
     for (int i = 0; i < SLOTS; ++i) {
         S->jobs.emplace_back(new Job());
-        (void)S->jobs.back()->dmeta.ensure(c, job_meta_bytes(MAX_PER_ROUND), S->streams[i]);
+        (void)S->jobs.back()->dmeta.ensure(c, job_meta_bytes(MAX_PER_ROUND, MAX_PER_ROUND * 4096u), S->streams[i]);
     }
     for (int i = 0; i < SLOTS; ++i) S->threads.emplace_back(slot_main, S, i);
     c->serve = S;

@@ -129,6 +129,8 @@ struct SliceDev {
     uint32_t n_pmt, pbits;
     uint32_t chunk_base, n_chunks;
     uint32_t tile_base, n_tiles;   // k_trig tiles: max(1, chunks) (an empty slice has one)
+    uint32_t group_base;     // first counting-kernel group of the slice (groups of BatchDev::tile_group tiles)
+    uint32_t group_pad;
     uint32_t seg_target, seg_cap;
     uint64_t pos_cap;
     ChunkPart *part;
@@ -167,6 +169,12 @@ struct BatchDev {
     uint32_t *counters;
     Plan *x_plans;           // host-mapped copy of the plans written at the end of the tail
     trig_params prm;
+    // counting kernel: groups of tile_group consecutive tiles of one slice per
+    // workgroup, halo_cap ordered hits staged at most on each side; group_slice
+    // maps every group to its slice (written by k_plan; unused for one slice)
+    uint32_t tile_group, halo_cap;
+    uint32_t total_groups, pad_groups;
+    uint32_t *group_slice;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -359,6 +367,10 @@ __device__ __forceinline__ uint32_t tile_base_of(const BatchDev &b, uint32_t si)
 }
 __device__ __forceinline__ uint32_t chunk_base_of(const BatchDev &b, uint32_t si) {
     return b.n_slices <= 1 ? 0u : b.chunk_bases[si];
+}
+// Groups of the counting kernel of a slice with n_tiles tiles.
+__host__ __device__ __forceinline__ uint32_t groups_of(uint32_t n_tiles, uint32_t tile_group) {
+    return (n_tiles + tile_group - 1) / tile_group;
 }
 
 // Packed copy of the input hits for the ordering stage, one word per input hit:

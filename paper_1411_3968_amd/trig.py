@@ -61,7 +61,7 @@ class Result(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("seg_target", C.c_uint32), ("seg_cap", C.c_uint32), ("grid_per_cu", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("tile_group", C.c_uint32), ("halo_cap", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class KernelTime(C.Structure):
@@ -109,7 +109,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.trig_profile_read.argtypes = [P, C.POINTER(KernelTime), C.c_uint32, C.POINTER(C.c_uint32)]
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice", "trig_batch",
+        if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice",
+                                               "trig_batch",
                                                "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done",
                                                "trig_stream_stats_get",
                                                "trig_stream_pause",
@@ -259,6 +260,12 @@ def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed
     """Trigger one slice; retries once with exact capacities on TRIG_EOVERFLOW.
     ``tagged=True`` also returns the input indices of the hits inside the event
     windows (``tagged``, ordered by time, PMT, input index)."""
+    return _one_slice(_LIB.trig_slice, ctx, geom_id, pmt, t, q, params, seed_flags, fire_cap, event_cap, stream,
+                      tag, raise_on_error, tagged, tagged_cap)
+
+
+def _one_slice(fn, ctx, geom_id, pmt, t, q, params, seed_flags, fire_cap, event_cap, stream, tag, raise_on_error,
+               tagged, tagged_cap) -> dict:
     d, keep = slice_desc(geom_id, pmt, t, q, tag)
     n = int(d.n_hits)
     fc, ec = _default_caps(n)
@@ -272,7 +279,7 @@ def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed
     tc = (tagged_cap if tagged_cap is not None else max(4096, n // 8)) if tagged else None
     for attempt in range(2):
         rb = ResultBuffers(fc, ec, n, seed_flags, tc)
-        rc = _LIB.trig_slice(ctx, C.byref(d), C.byref(prm), C.byref(rb.rec), sp)
+        rc = fn(ctx, C.byref(d), C.byref(prm), C.byref(rb.rec), sp)
         if rc == TRIG_EOVERFLOW and attempt == 0 and fire_cap is None and event_cap is None \
                 and (not tagged or tagged_cap is None):
             fc, ec = int(rb.rec.n_fires), int(rb.rec.n_events)
@@ -413,11 +420,19 @@ def trig_tune_get(ctx, n_pmt: int) -> dict:
     rc = _LIB.trig_tune_get(ctx, int(n_pmt), C.byref(t))
     if rc != TRIG_OK:
         raise TrigError(rc, _err(ctx))
-    return dict(seg_target=t.seg_target, seg_cap=t.seg_cap, grid_per_cu=t.grid_per_cu)
+    return dict(seg_target=t.seg_target, seg_cap=t.seg_cap, grid_per_cu=t.grid_per_cu, tile_group=t.tile_group,
+                halo_cap=t.halo_cap)
 
 
-def trig_tune_set(ctx, n_pmt_max: int, seg_target: int, seg_cap: int, grid_per_cu: int) -> None:
-    t = Tune(int(seg_target), int(seg_cap), int(grid_per_cu), 0)
+def trig_tune_set(ctx, n_pmt_max: int, seg_target: int, seg_cap: int, grid_per_cu: int,
+                  tile_group: int | None = None, halo_cap: int | None = None) -> None:
+    """Set the knobs of one PMT-count class; a knob left at None keeps the value
+    the class has now."""
+    if tile_group is None or halo_cap is None:
+        cur = trig_tune_get(ctx, n_pmt_max)
+        tile_group = cur["tile_group"] if tile_group is None else tile_group
+        halo_cap = cur["halo_cap"] if halo_cap is None else halo_cap
+    t = Tune(int(seg_target), int(seg_cap), int(grid_per_cu), int(tile_group), int(halo_cap), 0)
     rc = _LIB.trig_tune_set(ctx, int(n_pmt_max), C.byref(t))
     if rc != TRIG_OK:
         raise TrigError(rc, _err(ctx))

@@ -224,11 +224,11 @@ def _oracle_lists(pool):
 
 
 def test_serving_pool_equals_oracle_alone_and_in_the_mix(T):
-    """Every slice of a serving pool (rates 50-150 kHz per PMT, two slices at 5x
+    """Every slice of a serving pool (rates 50-150 kHz per PMT, three slices at 5x
     rate) triggered through the stream loop, alone and with the whole pool in
     flight, gives the oracle's fires, events and seed count."""
     from gen import configs as C
-    pool = C.serving_pool(seed=4, n_pool=10, length_ns=20_000_000, burst_frac=0.2)
+    pool = C.serving_pool(seed=4, n_pool=10, length_ns=20_000_000, burst_frac=0.3)
     rates = [s.n for _, s in pool.slices]
     assert max(rates) > 3 * min(rates)          # the 5x slices are in the pool
     refs = _oracle_lists(pool)
@@ -243,10 +243,11 @@ def test_serving_pool_equals_oracle_alone_and_in_the_mix(T):
             assert np.array_equal(r["fires"], refs[k]["fires"])
             assert np.array_equal(r["events"], refs[k]["events"])
 
+        cap = max(max(len(r["fires"]), len(r["events"])) for r in refs) + 1
         for k, (_, s) in enumerate(pool.slices):          # alone: one ticket at a time
             st, tk = T.trig_stream_submit(ctx, gid, s.pmt, s.t, s.q, pool.params)
             assert st == 0
-            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 16, event_cap=1 << 16))
+            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=cap, event_cap=cap))
         tks = []
         for rep in range(3):                                # in the mix: all in flight
             for k, (_, s) in enumerate(pool.slices):
@@ -254,7 +255,7 @@ def test_serving_pool_equals_oracle_alone_and_in_the_mix(T):
                 assert st == 0
                 tks.append((tk, k))
         for tk, k in tks:
-            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=1 << 16, event_cap=1 << 16))
+            check(k, *T.trig_stream_poll(ctx, tk, -1, fire_cap=cap, event_cap=cap))
     finally:
         T.trig_destroy(ctx)
 
