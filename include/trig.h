@@ -213,6 +213,29 @@ typedef struct {
 int trig_slice(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
                trig_result *result, void *hip_stream);
 
+/* Allocation-free variant of trig_slice, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments, semantics and results as
+ * trig_slice, except:
+ *  - the slice's arrays must be device memory (TRIG_EINVAL otherwise);
+ *  - the slice's workspace, descriptors, plans and counters live in a fixed
+ *    device scratch of TRIG_NOALLOC_SCRATCH_BYTES per GPU (a static device
+ *    array that every GPU the library runs on holds until the process ends;
+ *    its device address is looked up once per device when the first context on
+ *    it is created), so the call allocates no device or pinned host memory,
+ *    captures no graph and records no per-kernel timing;
+ *  - a slice whose workspace does not fit the scratch (more than about 2.78
+ *    million hits, or 2.75 million with seed flags: 96 bytes per hit) returns
+ *    TRIG_ENOMEM, with both sizes in trig_last_error, and runs nothing;
+ *  - the result lists are copied from device memory into the caller's buffers.
+ * Every call on one GPU shares that GPU's scratch, whichever context makes it,
+ * and the scratch keeps the last call's contents (nothing in it needs to start
+ * at zero): calls that overlap in time on one GPU (two host threads, two
+ * contexts) race and give wrong results, so the caller serialises them. */
+#define TRIG_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int trig_slice_noalloc(trig_ctx *ctx, const trig_slice_desc *slice, const trig_params *params,
+                       trig_result *result, void *hip_stream);
+
 /* Trigger n slices together (Sec. 2: successive slices, possibly of several
  * towers, are handed to trigger processes; Sec. 4: one GPU serves the slices of
  * a trigger CPU; here every stage runs once over all slices, and device work

@@ -824,6 +824,40 @@ int run_sync(trig_ctx *c, Job &J, uint32_t n, const trig_slice_desc *d, const tr
     return first_bad;
 }
 
+// ------------------------------------------- fixed scratch (no allocation)
+
+// Device memory of trig_slice_noalloc: workspace, descriptors, plans and
+// counters of one slice, TRIG_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU
+// the library runs on until the process ends.  Host code never uses the name
+// itself as an address (on the host it is only a handle of the symbol): the
+// device address of each GPU's copy is looked up once per device, with that
+// device current, when the first context on it is created.
+static __device__ __align__(256) unsigned char scratch[TRIG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+constexpr size_t NA_PIN_BYTES = 4096;
+std::mutex na_mu;
+char *na_scratch_dev[NA_MAX_DEVICES] = {};
+}  // namespace
+
+// The device address of the fixed scratch on `device` (current), or null.
+static char *na_scratch_of(int device, hipError_t *err) {
+    *err = hipSuccess;
+    if (device < 0 || device >= NA_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(na_mu);
+    if (!na_scratch_dev[device]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        na_scratch_dev[device] = (char *)ptr;
+    }
+    return na_scratch_dev[device];
+}
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -854,6 +888,15 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     const trig_tune block = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
     c->tunes.push_back({128u, tower});
     c->tunes.push_back({0xFFFFFFFFu, block});
+    // set-up of the allocation-free entry point: this device's fixed scratch and
+    // a small pinned block for its descriptor upload and plan read-back
+    hipError_t e = hipSuccess;
+    c->na_scratch = na_scratch_of(device, &e);
+    if (!c->na_scratch || hipHostMalloc(&c->na_pin, NA_PIN_BYTES, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        c->na_pin = nullptr;
+        ctx_set_error(c, "fixed scratch unavailable: %s", hipGetErrorString(e));
+    }
     *out = c;
     return TRIG_OK;
 }
@@ -864,6 +907,8 @@ void trig_destroy(trig_ctx *c) {
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     c->sync_job.release(c);
+    c->na_job.release(c);
+    if (c->na_pin) hipHostFree(c->na_pin);
     for (auto &g : c->geoms) {
         hipFree(g.floor_id);
         hipFree(g.floor16);
@@ -969,6 +1014,33 @@ int trig_slice(trig_ctx *c, const trig_slice_desc *slice, const trig_params *par
     }
     hipSetDevice(c->device);
     int rc = run_sync(c, c->sync_job, 1, slice, params, result, (hipStream_t)hip_stream);
+    if (rc != TRIG_OK && result->status == TRIG_OK) result->status = rc;
+    return rc;
+}
+
+int trig_slice_noalloc(trig_ctx *c, const trig_slice_desc *slice, const trig_params *params, trig_result *result,
+                       void *hip_stream) {
+    if (!c) return TRIG_EINVAL;
+    if (!slice || !result) {
+        ctx_set_error(c, "null slice or result");
+        return TRIG_EINVAL;
+    }
+    if (slice->n_hits && slice->mem != TRIG_MEM_DEVICE) {
+        ctx_set_error(c, "trig_slice_noalloc takes device inputs only");
+        return result->status = TRIG_EINVAL;
+    }
+    if (!c->na_scratch || !c->na_pin) {
+        ctx_set_error(c, "the fixed scratch of device %d is unavailable", c->device);
+        return result->status = TRIG_EHIP;
+    }
+    hipSetDevice(c->device);
+    Job &J = c->na_job;
+    J.fixed_ws = c->na_scratch;
+    J.fixed_cap = TRIG_NOALLOC_SCRATCH_BYTES;
+    J.fixed_pin = c->na_pin;
+    J.fixed_pin_cap = NA_PIN_BYTES;
+    J.graphs_ok = false;
+    const int rc = run_sync(c, J, 1, slice, params, result, (hipStream_t)hip_stream);
     if (rc != TRIG_OK && result->status == TRIG_OK) result->status = rc;
     return rc;
 }

@@ -155,6 +155,9 @@ struct trig_ctx {
     std::vector<trig_kernel_time> prof;
     std::mutex serve_mu;     // guards creation of the serving loop
     ServeState *serve = nullptr;
+    Job na_job;              // trig_slice_noalloc: runs in the device's fixed scratch
+    void *na_pin = nullptr;  // its pinned block (descriptor upload, plan read-back)
+    char *na_scratch = nullptr;   // device address of the fixed scratch on this context's device
 };
 
 void ctx_set_error(trig_ctx *c, const char *fmt, ...);

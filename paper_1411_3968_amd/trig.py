@@ -77,7 +77,7 @@ class StreamStats(C.Structure):
 assert C.sizeof(Result) == 112 and C.sizeof(SliceDesc) == 48 and C.sizeof(Params) == 44
 
 EXPORTS = ["trig_create", "trig_destroy", "trig_last_error", "trig_version", "trig_geom_load", "trig_slice",
-           "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
+           "trig_slice_noalloc", "trig_batch", "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done", "trig_stream_pause",
            "trig_stream_stats_get",
            "trig_tune_get",
            "trig_tune_set", "trig_profile_enable", "trig_profile_read"]
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.trig_version.restype = C.c_char_p
     lib.trig_geom_load.argtypes = [P, C.POINTER(GeomDesc), C.POINTER(C.c_uint32)]
     lib.trig_slice.argtypes = [P, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(Result), V]
+    lib.trig_slice_noalloc.argtypes = [P, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(Result), V]
     lib.trig_batch.argtypes = [P, C.c_uint32, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(Result), V]
     lib.trig_stream_submit.argtypes = [P, C.POINTER(SliceDesc), C.POINTER(Params), C.POINTER(C.c_uint64)]
     lib.trig_stream_poll.argtypes = [P, C.c_uint64, C.POINTER(Result), C.c_int32]
@@ -109,7 +110,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.trig_profile_read.argtypes = [P, C.POINTER(KernelTime), C.c_uint32, C.POINTER(C.c_uint32)]
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice",
+        if fn.restype is C.c_int or name in ("trig_create", "trig_geom_load", "trig_slice", "trig_slice_noalloc",
                                                "trig_batch",
                                                "trig_stream_submit", "trig_stream_poll", "trig_stream_next_done",
                                                "trig_stream_stats_get",
@@ -262,6 +263,15 @@ def trig_slice(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed
     windows (``tagged``, ordered by time, PMT, input index)."""
     return _one_slice(_LIB.trig_slice, ctx, geom_id, pmt, t, q, params, seed_flags, fire_cap, event_cap, stream,
                       tag, raise_on_error, tagged, tagged_cap)
+
+
+def trig_slice_noalloc(ctx, geom_id: int, pmt, t, q, params: dict | None = None, *, seed_flags: bool = False,
+                       fire_cap: int | None = None, event_cap: int | None = None, stream=None, tag: int = 0,
+                       raise_on_error: bool = True, tagged: bool = False, tagged_cap: int | None = None) -> dict:
+    """``trig_slice`` through the allocation-free entry point: device inputs only,
+    the workspace in the library's fixed per-GPU scratch (TRIG_ENOMEM beyond it)."""
+    return _one_slice(_LIB.trig_slice_noalloc, ctx, geom_id, pmt, t, q, params, seed_flags, fire_cap, event_cap,
+                      stream, tag, raise_on_error, tagged, tagged_cap)
 
 
 def _one_slice(fn, ctx, geom_id, pmt, t, q, params, seed_flags, fire_cap, event_cap, stream, tag, raise_on_error,
