@@ -209,9 +209,23 @@ size_t slice_footprint(uint64_t n, bool host_input) {
     return slice_layout(n, host_input, false, L) + align256(sizeof(SliceDev)) + align256(sizeof(Plan));
 }
 
+// Device address of a caller's host buffer of `bytes` bytes when it is pinned
+// (HIP host memory, so the kernels can write the results there directly), else
+// null.  Asked only for lists worth it: below 1 MiB the copy from the staging
+// costs less than the query.
+static void *pinned_dev_ptr(const void *p, size_t bytes) {
+    if (!p || bytes < (1u << 20)) return nullptr;
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return at.type == hipMemoryTypeHost ? at.devicePointer : nullptr;
+}
+
 int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
                  const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
-                 const uint8_t *want_tags, const uint64_t *tag_caps) {
+                 const uint8_t *want_tags, const uint64_t *tag_caps, const trig_result *res) {
     stream = s;
     params = *prm;
     slices.assign(n, SliceInfo{});
@@ -262,7 +276,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
                 sort_kernels |= 1u;
                 wave_wgs = std::max(wave_wgs, si.tune.grid_per_cu);
                 wave_cap = std::max(wave_cap, si.tune.seg_cap);
-                if (np > (uint32_t)WAVE_RUNS) sort_kernels |= 2u;   // a slice may hand over to the block kernel
+                if (np > (uint32_t)WAVE_RUNS) sort_kernels |= 4u;   // a slice may take the two-level merge
             } else {
                 sort_kernels |= 2u;
                 cap_max = std::max(cap_max, si.tune.seg_cap);
@@ -272,23 +286,32 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     seg_cap = cap_max ? cap_max : 4096;
     // pinned result staging: plans, then per slice min(n, cap) fires and events,
-    // and the tagged list when asked for
+    // and the tagged list when asked for; a list whose caller buffer is pinned
+    // host memory is written there directly instead
     size_t xs = align256(n * sizeof(Plan));
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
         const uint64_t dflt = si.n / 16 + 4096;
         const uint64_t fc = std::min<uint64_t>(si.n, fire_caps ? fire_caps[i] : dflt);
         const uint64_t ec = std::min<uint64_t>(si.n, event_caps ? event_caps[i] : dflt);
+        const uint64_t tc = si.want_tag ? std::min<uint64_t>(si.n, tag_caps ? tag_caps[i] : dflt) : 0;
+        si.direct_f = nullptr;
+        si.direct_e = nullptr;
+        si.direct_t = nullptr;
+        if (res && !fixed_ws && si.host_status == TRIG_OK) {
+            si.direct_f = (trig_fire *)pinned_dev_ptr(res[i].fires, fc * sizeof(trig_fire));
+            si.direct_e = (trig_event *)pinned_dev_ptr(res[i].events, ec * sizeof(trig_event));
+            si.direct_t = si.want_tag ? (uint32_t *)pinned_dev_ptr(res[i].tagged, tc * sizeof(uint32_t)) : nullptr;
+        }
         si.x_fcap = (uint32_t)fc;
         si.x_ecap = (uint32_t)ec;
-        si.x_off_f = xs;
-        xs = align256(xs + fc * sizeof(trig_fire));
-        si.x_off_e = xs;
-        xs = align256(xs + ec * sizeof(trig_event));
-        const uint64_t tc = si.want_tag ? std::min<uint64_t>(si.n, tag_caps ? tag_caps[i] : dflt) : 0;
         si.x_tcap = (uint32_t)tc;
+        si.x_off_f = xs;
+        if (!si.direct_f) xs = align256(xs + fc * sizeof(trig_fire));
+        si.x_off_e = xs;
+        if (!si.direct_e) xs = align256(xs + ec * sizeof(trig_event));
         si.x_off_t = xs;
-        xs = align256(xs + tc * sizeof(uint32_t));
+        if (!si.direct_t) xs = align256(xs + tc * sizeof(uint32_t));
     }
     total_chunks = chunk_base;
     total_tiles = tile_base;
@@ -427,14 +450,16 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.events = (trig_event *)(b + L.events);
         S.seed_flags = si.want_flags ? (uint8_t *)(b + L.flags) : nullptr;
         S.plan = d_plans + i;
-        S.x_fires = x_plans_dev ? (trig_fire *)((char *)x_plans_dev + si.x_off_f) : nullptr;
-        S.x_events = x_plans_dev ? (trig_event *)((char *)x_plans_dev + si.x_off_e) : nullptr;
+        S.x_fires = si.direct_f ? si.direct_f : x_plans_dev ? (trig_fire *)((char *)x_plans_dev + si.x_off_f) : nullptr;
+        S.x_events = si.direct_e ? si.direct_e
+                                 : x_plans_dev ? (trig_event *)((char *)x_plans_dev + si.x_off_e) : nullptr;
         S.x_fire_cap = si.x_fcap;
         S.x_event_cap = si.x_ecap;
         S.tagc = (uint32_t *)(b + L.tagc);
         S.tagged = (uint32_t *)(b + L.fsc);   // free once the fires are placed
         S.tag_on = si.want_tag && si.host_status == TRIG_OK ? 1u : 0u;
-        S.x_tagged = si.x_tcap && x_plans_dev ? (uint32_t *)((char *)x_plans_dev + si.x_off_t) : nullptr;
+        S.x_tagged = si.direct_t ? si.direct_t
+                     : si.x_tcap && x_plans_dev ? (uint32_t *)((char *)x_plans_dev + si.x_off_t) : nullptr;
         S.x_tag_cap = si.x_tcap;
         S.l0m = (uint64_t *)(b + L.l0m);
         hs[i] = S;
@@ -696,7 +721,9 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
     const char *xb = (const char *)h_plans.ptr;
     hipError_t e = hipSuccess;
     if (P.n_fires) {
-        if (P.n_fires <= si.x_fcap)
+        if (P.n_fires <= si.x_fcap && si.direct_f)
+            ;   // the kernels wrote the list into the caller's pinned buffer
+        else if (P.n_fires <= si.x_fcap)
             std::memcpy(r->fires, xb + si.x_off_f, (size_t)P.n_fires * sizeof(trig_fire));
         else {
             e = hipMemcpyAsync(r->fires, si.dev.fires, (size_t)P.n_fires * sizeof(trig_fire),
@@ -705,7 +732,9 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
         }
     }
     if (e == hipSuccess && P.n_events) {
-        if (P.n_events <= si.x_ecap)
+        if (P.n_events <= si.x_ecap && si.direct_e)
+            ;
+        else if (P.n_events <= si.x_ecap)
             std::memcpy(r->events, xb + si.x_off_e, (size_t)P.n_events * sizeof(trig_event));
         else {
             e = hipMemcpyAsync(r->events, si.dev.events, (size_t)P.n_events * sizeof(trig_event),
@@ -714,7 +743,9 @@ int Job::deliver(trig_ctx *c, uint32_t i, trig_result *r) {
         }
     }
     if (e == hipSuccess && si.want_tag && P.n_tagged) {
-        if (P.n_tagged <= si.x_tcap)
+        if (P.n_tagged <= si.x_tcap && si.direct_t)
+            ;
+        else if (P.n_tagged <= si.x_tcap)
             std::memcpy(r->tagged, xb + si.x_off_t, (size_t)P.n_tagged * sizeof(uint32_t));
         else {
             e = hipMemcpyAsync(r->tagged, si.dev.tagged, (size_t)P.n_tagged * sizeof(uint32_t),
@@ -792,7 +823,7 @@ int run_sync(trig_ctx *c, Job &J, uint32_t n, const trig_slice_desc *d, const tr
     }
     const bool prof = c->prof_on && !J.fixed_ws;
     if (prof) c->prof_stream = s;
-    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data(), tcap.data());
+    rc = J.prepare(c, n, d, prm, flags.data(), fcap.data(), ecap.data(), s, tags.data(), tcap.data(), res);
     if (rc) return rc;
     for (uint32_t i = 0; i < n; ++i) J.slices[i].flags_dst = res[i].seed_flags;
     rc = J.launch(c, prof);
@@ -882,9 +913,9 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     c->cfg.persist_per_cu = 2;
     const char *g = getenv("TRIG_GRAPHS");
     c->use_graphs = !(g && g[0] == '0');
-    // wave per segment, 3 workgroups of 4 waves per CU; towers: four tiles per
-    // counting workgroup with small halos; larger detectors: two tiles, wide halos
-    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 4, 256, 0};
+    // wave per segment, 3 workgroups of 4 waves per CU; counting workgroups of two
+    // tiles, with small halos for towers and wide ones for larger detectors
+    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 2, 256, 0};
     const trig_tune block = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
     c->tunes.push_back({128u, tower});
     c->tunes.push_back({0xFFFFFFFFu, block});

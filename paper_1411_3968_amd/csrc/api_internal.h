@@ -56,6 +56,11 @@ struct SliceInfo {
     uint32_t x_fcap, x_ecap, x_tcap;
     uint8_t *flags_dst;          // caller's host buffer for seed flags (or null)
     bool want_tag;               // the tagged-hit list is asked for
+    // device addresses of the caller's result buffers when they are pinned host
+    // memory (the kernels write the lists there directly), else null
+    trig_fire *direct_f;
+    trig_event *direct_e;
+    uint32_t *direct_t;
 };
 
 // One device round over a set of slices: workspace, descriptors, plans.
@@ -110,7 +115,8 @@ struct Job {
     // default staging capacity).
     int prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_params *prm,
                 const uint8_t *want_flags, const uint64_t *fire_caps, const uint64_t *event_caps, hipStream_t s,
-                const uint8_t *want_tags = nullptr, const uint64_t *tag_caps = nullptr);
+                const uint8_t *want_tags = nullptr, const uint64_t *tag_caps = nullptr,
+                const trig_result *res = nullptr);
     int launch(trig_ctx *c, bool profile);
     int enqueue_flags(trig_ctx *c, const std::vector<uint32_t> *only);   // null: every slice
     int generic_pass(trig_ctx *c, bool profile);

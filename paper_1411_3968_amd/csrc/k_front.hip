@@ -174,10 +174,14 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         if (pmax >= S.n_pmt || span >= (1ull << 31) || lo < INT64_MIN + H || hi > INT64_MAX - H) {
             p.status = TRIG_ERANGE;
         } else {
-            // ordering kernel: wave per segment for few runs, else block per segment
+            // ordering kernel: wave per segment for few runs; for more runs than a
+            // wave merges, two levels of wave merges (groups of runs, then the
+            // groups' ordered stretches) or, when tuned to it, block per segment
             uint32_t cap = S.seg_cap, target = S.seg_target;
             bool ok = true;
-            if (cap <= (uint32_t)WAVE_CAP && runs > (uint32_t)WAVE_RUNS) {
+            const bool many = cap <= (uint32_t)WAVE_CAP && runs > (uint32_t)WAVE_RUNS;
+            const bool tl = many && (b.sort_kernels & 4u) != 0 && runs <= (uint32_t)(WAVE_RUNS * WAVE_RUNS);
+            if (many && !tl) {
                 cap = b.block_cap;
                 target = b.block_target;
                 ok = (b.sort_kernels & 2u) != 0;
@@ -186,20 +190,42 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             // segment width: the largest power of two with expected occupancy <= target
             // at the slice's mean density plus its densest chunk's (a burst on one
             // PMT would otherwise overflow the segments it crosses)
-            const float dens = (float)S.n / ((float)span + 1.0f) + dmax;
-            const float xf = (float)target / dens;
-            const uint64_t x = xf >= 1.0f ? (uint64_t)fminf(xf, 4.0e18f) : 0ull;
-            uint32_t sft = x ? 63u - (uint32_t)__clzll(x) : 0u;
-            if (sft > 31) sft = 31;
-            // many runs: widen the segments (up to half the LDS capacity expected)
-            // until the boundary table fits its budget
-            while (sft < 31 && (uint64_t)runs * ((span >> sft) + 2) > S.pos_cap &&
-                   2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)cap)
-                ++sft;
+            auto shift_for = [&](float dens) -> uint32_t {
+                const float xf = (float)target / dens;
+                const uint64_t x = xf >= 1.0f ? (uint64_t)fminf(xf, 4.0e18f) : 0ull;
+                const uint32_t sf = x ? 63u - (uint32_t)__clzll(x) : 0u;
+                return sf > 31 ? 31u : sf;
+            };
+            const float mean = (float)S.n / ((float)span + 1.0f);
+            uint32_t sft = shift_for(mean + dmax);
+            if (tl) {
+                // level 2 merges the groups' stretches at the slice's density; level 1
+                // orders each group of rg runs at its share of it (a burst stays in
+                // its own group), widened while the level-1 table is over budget
+                const uint32_t rg = max((uint32_t)64, (runs + WAVE_RUNS - 1) / WAVE_RUNS);
+                const uint32_t ngrp = (runs + rg - 1) / rg;
+                p.tl = 1;
+                p.run_grp = rg;
+                p.n_grp = ngrp;
+                p.shift2 = sft;
+                p.n_seg2 = (uint32_t)((span >> sft) + 1);
+                uint32_t s1 = shift_for(mean / (float)ngrp + dmax);
+                while (s1 < 31 && (uint64_t)runs * ((span >> s1) + 2) > S.pos_cap &&
+                       2 * ((S.n << (s1 + 1)) / ((span + 1) * ngrp)) <= (uint64_t)cap)
+                    ++s1;
+                sft = s1;
+            } else {
+                // many runs: widen the segments (up to half the LDS capacity expected)
+                // until the boundary table fits its budget
+                while (sft < 31 && (uint64_t)runs * ((span >> sft) + 2) > S.pos_cap &&
+                       2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)cap)
+                    ++sft;
+            }
             const uint64_t nseg = (span >> sft) + 1;
             p.shift = sft;
             p.n_seg = (uint32_t)nseg;
-            const bool fits = ok && (uint64_t)runs * (nseg + 1) <= S.pos_cap;
+            bool fits = ok && (uint64_t)runs * (nseg + 1) <= S.pos_cap;
+            if (tl) fits = fits && (uint64_t)p.n_grp * ((uint64_t)p.n_seg2 + 1) <= S.pos_cap;
             p.state = fits ? ST_FAST : ST_NEED_GENERIC;
         }
     }
@@ -226,7 +252,7 @@ __device__ void build_segment_lists(const BatchDev &b) {
         if (i < b.n_slices) {
             const Plan &P = b.plans[i];
             if (P.state == ST_FAST) {
-                if (P.seg_kind == 0) nw = P.n_seg; else nb = P.n_seg;
+                if (P.seg_kind == 0) nw = P.tl ? P.n_grp * P.n_seg : P.n_seg; else nb = P.n_seg;
             }
         }
         uint32_t tw, tbk;
@@ -245,16 +271,40 @@ __device__ void build_segment_lists(const BatchDev &b) {
     }
 }
 
+// Work list of the second level (two-level slices still on the run merge).
+__device__ void build_level2_lists(const BatchDev &b) {
+    constexpr int NT = 256;
+    __shared__ uint32_t sh[NT / 64 + 1];
+    uint32_t acc = 0;
+    for (uint32_t i0 = 0; i0 < b.n_slices; i0 += NT) {
+        const uint32_t i = i0 + threadIdx.x;
+        uint32_t nw = 0;
+        if (i < b.n_slices) {
+            const Plan &P = b.plans[i];
+            if (P.state == ST_FAST && P.tl) nw = P.n_seg2;
+        }
+        uint32_t tw;
+        const uint32_t ew = block_excl_scan<NT>(nw, tw, sh);
+        if (i < b.n_slices) b.plans[i].seg_item_base2 = acc + ew;
+        acc += tw;
+    }
+    if (threadIdx.x == 0) b.counters[Q_SEG_TOTAL2] = acc;
+}
+
 // Per chunk: for every run r and segment boundary j (time j << shift relative to
 // t_min), pos[j][r] = first position of run r whose time is at or after the
 // boundary; pos[n_seg][r] = end of run r.  Runs are maximal time-non-decreasing
 // stretches.  The table is segment-major (pos[j * n_runs + r]) so that one
 // segment's bounds over all runs are contiguous for the ordering kernels.
+// L2: the same over the level-1 output of two-level slices (its runs and
+// segments of the second level; the level-1 table is no longer needed).
+template <bool L2>
 __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     constexpr int NT = 256, PER = CHUNK / NT;
     const uint32_t item = blockIdx.x;
     if (item == b.total_chunks) {   // one extra block
-        build_segment_lists(b);
+        if (L2) build_level2_lists(b);
+        else build_segment_lists(b);
         return;
     }
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
@@ -262,16 +312,24 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
     const Plan P = gload(gmem(b.plans + si));
-    if (P.state != ST_FAST) return;
+    if (P.state != ST_FAST || (L2 && !P.tl)) return;
     const TRIG_GAS int64_t *tin = gmem(S.t);
+    const TRIG_GAS uint64_t *l1 = level1_hits(S);
+    const uint32_t tm32 = (uint32_t)(uint64_t)P.t_min;
+    // time at position k: the input time, or (level 2) the level-1 local time
+    auto time_at = [&](uint64_t k) -> int64_t { return L2 ? (int64_t)((uint32_t)l1[k] - tm32) : tin[k]; };
     __shared__ int64_t st[CHUNK + 2];
     __shared__ uint32_t sh[NT / 64 + 1];
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint32_t len = (uint32_t)((k0 + CHUNK < S.n) ? CHUNK : S.n - k0);
-    stage_copy<NT, PER>(st + 1, tin + k0, len);
+    if (L2) {
+        for (uint32_t i = threadIdx.x; i < len; i += NT) st[i + 1] = time_at(k0 + i);
+    } else {
+        stage_copy<NT, PER>(st + 1, tin + k0, len);
+    }
     if (threadIdx.x == 0) {
-        st[0] = k0 ? tin[k0 - 1] : INT64_MIN;
-        st[len + 1] = (k0 + len < S.n) ? tin[k0 + len] : INT64_MIN;
+        st[0] = k0 ? time_at(k0 - 1) : INT64_MIN;
+        st[len + 1] = (k0 + len < S.n) ? time_at(k0 + len) : INT64_MIN;
     }
     __syncthreads();
     const uint32_t a = threadIdx.x * PER;
@@ -282,9 +340,10 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<NT>(starts, tot, sh);
-    const uint64_t R = P.n_runs;
-    const uint32_t sft = P.shift;
-    const int64_t tmin = P.t_min;
+    const uint64_t R = L2 ? P.n_runs2 : P.n_runs;
+    const uint32_t sft = L2 ? P.shift2 : P.shift;
+    const uint32_t n_seg = L2 ? P.n_seg2 : P.n_seg;
+    const int64_t tmin = L2 ? 0 : P.t_min;
     int64_t r = (int64_t)gmem(S.part)[c].run_base + ex - 1;   // run of the element before a
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = a + e;
@@ -303,7 +362,70 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
             for (uint32_t j = gp + 1; j <= g; ++j) col[(uint64_t)j * R] = (uint32_t)k;
         }
         if (is_end)
-            for (uint32_t j = g + 1; j <= P.n_seg; ++j) col[(uint64_t)j * R] = (uint32_t)(k + 1);
+            for (uint32_t j = g + 1; j <= n_seg; ++j) col[(uint64_t)j * R] = (uint32_t)(k + 1);
+    }
+}
+
+// Second level of the two-level ordering, per chunk of the level-1 output: its
+// run starts (position 0 and every position whose time is below its
+// predecessor's).
+__global__ __launch_bounds__(256) void k_ingest2(BatchDev b) {
+    constexpr int NT = 256, PER = CHUNK / NT;
+    const uint32_t item = blockIdx.x;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
+    const SliceDev &S = b.slices[si];
+    const uint32_t c = item - chunk_base_of(b, si);
+    if (c >= S.n_chunks) return;
+    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
+    if (Pg->state != ST_FAST || !Pg->tl) return;
+    const uint32_t tm32 = (uint32_t)(uint64_t)Pg->t_min;
+    const TRIG_GAS uint64_t *l1 = level1_hits(S);
+    const uint64_t k0 = (uint64_t)c * CHUNK;
+    const uint64_t k1 = (k0 + CHUNK < S.n) ? k0 + CHUNK : S.n;
+    uint32_t ns = 0;
+    uint32_t tv[PER], tp[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint64_t k = k0 + (uint64_t)e * NT + threadIdx.x;
+        if (k < k1) {
+            tv[e] = (uint32_t)l1[k] - tm32;
+            tp[e] = k ? (uint32_t)l1[k - 1] - tm32 : 0u;
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const uint64_t k = k0 + (uint64_t)e * NT + threadIdx.x;
+        if (k < k1) ns += (k == 0) || (tv[e] < tp[e]);
+    }
+    __shared__ uint32_t sh[NT / 64 + 1];
+    const uint32_t tot = block_sum<NT>(ns, sh);
+    if (threadIdx.x == 0) gmem(S.part)[c].n_start = tot;
+}
+
+// Second level, per two-level slice: numbering of the level-1 output's runs
+// (each chunk's run_base) and the check that its boundary table fits.
+__global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
+    constexpr int NT = 1024;
+    const uint32_t si = blockIdx.x;
+    const SliceDev &S = b.slices[si];
+    Plan *P = S.plan;
+    if (P->state != ST_FAST || !P->tl) return;
+    __shared__ uint32_t sh[NT / 64 + 1];
+    TRIG_GAS ChunkPart *part = gmem(S.part);
+    uint32_t runs = 0;
+    for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT) {
+        const uint32_t c = c0 + threadIdx.x;
+        const uint32_t ns = c < S.n_chunks ? part[c].n_start : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<NT>(ns, tot, sh);
+        if (c < S.n_chunks) part[c].run_base = runs + ex;
+        runs += tot;
+    }
+    if (threadIdx.x == 0) {
+        P->n_runs2 = runs;
+        // each group's output is time-ordered, so at most n_grp runs remain
+        const bool fits = runs <= (uint32_t)WAVE_RUNS && (uint64_t)runs * ((uint64_t)P->n_seg2 + 1) <= S.pos_cap;
+        if (!fits) P->state = ST_NEED_GENERIC;
     }
 }
 
@@ -546,14 +668,20 @@ struct WaveSeg {
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total(v); }
 
-template <int CAP>
+// L2 = false: single-level slices, and level 1 of two-level slices (a work item is
+// a segment of one group of run_grp consecutive runs; the group's ordered hits
+// go, as packed words with their input indices, to the level-1 output at the
+// group's own input range).  L2 = true: level 2 of two-level slices (the
+// level-1 output's stretches merged; the input index of each hit comes from the
+// level-1 output).
+template <int CAP, bool L2>
 __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     constexpr int EG = CAP / 64;
     constexpr int RI = WAVE_RUNS / 64;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = lane_id();
     WaveSeg<CAP> &sm = reinterpret_cast<WaveSeg<CAP> *>(smem_raw)[w];
-    const uint32_t total = b.counters[Q_SEG_TOTAL];
+    const uint32_t total = b.counters[L2 ? Q_SEG_TOTAL2 : Q_SEG_TOTAL];
     // XCD-aware split: workgroup b runs on XCD b % 8 (round-robin dispatch), and
     // each XCD takes one contiguous eighth of the segment list, so the cache lines
     // that neighbouring segments share in every run are fetched into one L2
@@ -568,28 +696,46 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     const TRIG_GAS uint64_t *in_pk = nullptr;
     const TRIG_GAS uint32_t *pos = nullptr;
     TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
+    TRIG_GAS uint64_t *l1_out = nullptr;
+    TRIG_GAS uint32_t *l1_idx = nullptr;
     Plan P = {};
+    // the plan fields of this launch's level
+    uint32_t n_runs = 0, shift = 0, n_seg = 1;
+    bool tl1 = false;   // level 1 of a two-level slice
     for (uint32_t item = first; item < end; ++item) {
         if (item < s_base || item >= s_end) {
-            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base; });
+            si = find_slice(b.n_slices, item,
+                            [&](uint32_t i) { return L2 ? b.plans[i].seg_item_base2 : b.plans[i].seg_item_base; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
-            in_pk = packed_hits(S); pos = gmem(S.pos);
+            in_pk = L2 ? level1_hits(S) : packed_hits(S);
+            pos = gmem(S.pos);
             o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx);
-            s_base = P.seg_item_base;
-            s_end = s_base + P.n_seg;
+            l1_out = level1_hits(S);
+            l1_idx = level1_index(S);
+            tl1 = !L2 && P.tl;
+            n_runs = L2 ? P.n_runs2 : P.n_runs;
+            shift = L2 ? P.shift2 : P.shift;
+            n_seg = L2 ? P.n_seg2 : P.n_seg;
+            s_base = L2 ? P.seg_item_base2 : P.seg_item_base;
+            s_end = s_base + (tl1 ? P.n_grp * n_seg : n_seg);
         }
-        const uint32_t j = item - s_base;
-        const uint64_t R = P.n_runs;
-        const uint32_t seg_lo = (uint32_t)((uint64_t)j << P.shift);
-        // the segment's stretch of every run (run r = i * 64 + lane), from the
-        // contiguous bound rows j and j + 1 and the run starts (row 0)
+        const uint32_t jj = item - s_base;
+        // the segment and (level 1 of a two-level slice) the group of runs
+        const uint32_t grp = tl1 ? jj / n_seg : 0u;
+        const uint32_t j = tl1 ? jj - grp * n_seg : jj;
+        const uint32_t r_lo = tl1 ? grp * P.run_grp : 0u;
+        const uint32_t r_hi = tl1 ? min(r_lo + P.run_grp, n_runs) : n_runs;
+        const uint64_t R = n_runs;
+        const uint32_t seg_lo = (uint32_t)((uint64_t)j << shift);
+        // the segment's stretch of every run (run r = r_lo + i * 64 + lane), from
+        // the contiguous bound rows j and j + 1 and the run starts (row 0)
         uint32_t lo[RI], hi[RI], st[RI];
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
-            const uint32_t r = (uint32_t)(i * 64 + lane);
+            const uint32_t r = r_lo + (uint32_t)(i * 64 + lane);
             lo[i] = hi[i] = st[i] = 0;
-            if (r < R) {
+            if (r < r_hi) {
                 lo[i] = pos[(uint64_t)j * R + r];
                 hi[i] = pos[(uint64_t)(j + 1) * R + r];
                 st[i] = pos[r];
@@ -600,15 +746,17 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
         for (int i = 0; i < RI; ++i) {
             const uint32_t c = hi[i] - lo[i];
             const uint32_t incl = wave_incl_scan(c);
-            const uint32_t r = (uint32_t)(i * 64 + lane);
-            if (r < R) {
-                sm.run_lo[r] = lo[i];
-                sm.run_base[r] = m + incl - c;
+            const uint32_t rl = (uint32_t)(i * 64 + lane);   // run index within the item
+            if (r_lo + rl < r_hi) {
+                sm.run_lo[rl] = lo[i];
+                sm.run_base[rl] = m + incl - c;
             }
             m += lane_read(incl, 63);
             gpart += lo[i] - st[i];
         }
-        const uint32_t goff = wave_sum_u32(gpart);
+        // output offset: hits of the item's runs before the segment (level 1: after
+        // the group's first input position, where its ordered hits go)
+        const uint32_t goff = wave_sum_u32(gpart) + (tl1 ? lane_read(st[0], 0) : 0u);
         if (m > (uint32_t)CAP) {
             if (lane == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
             continue;
@@ -619,8 +767,8 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
         wave_sync();
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
-            const uint32_t r = (uint32_t)(i * 64 + lane);
-            if (r < R && hi[i] > lo[i]) sm.aux[sm.run_base[r]] = (uint16_t)r;
+            const uint32_t rl = (uint32_t)(i * 64 + lane);
+            if (r_lo + rl < r_hi && hi[i] > lo[i]) sm.aux[sm.run_base[rl]] = (uint16_t)rl;
         }
         wave_sync();
         // gather: run of element k = the largest mark at or before k (the EG
@@ -658,7 +806,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
         }
         // key of each element: (local time, PMT, gather position), unique and in
         // the output order; bucket by the top 8 bits of the local time
-        const uint32_t tb = P.shift > 8 ? P.shift - 8 : 0u;
+        const uint32_t tb = shift > 8 ? shift - 8 : 0u;
 #pragma unroll
         for (int i = 0; i < 4; ++i) sm.bcount[lane * 4 + i] = 0;
         wave_sync();
@@ -715,6 +863,7 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
         for (int e = 0; e < EG; ++e)
             if (src[e] != 0xFFFFFFFFu) sm.key[ebase[e] + rank[e]] = key[e];
         wave_sync();
+        const uint32_t tm32 = (uint32_t)(uint64_t)P.t_min;
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t i = (uint32_t)(e * 64 + lane);
@@ -722,28 +871,36 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 const uint64_t kk = sm.key[i];
                 const uint32_t k = (uint32_t)kk & KEY_K_MASK;
                 const uint32_t p = (uint32_t)(kk >> KEY_P_SHIFT) & 0xFFFFu;
-                o_t[goff + i] = seg_lo + (uint32_t)(kk >> KEY_T_SHIFT);
-                o_pq[goff + i] = (p << 16) | sm.dq[k];
+                const uint32_t t_loc = seg_lo + (uint32_t)(kk >> KEY_T_SHIFT);
+                const uint32_t pq = (p << 16) | sm.dq[k];
                 const uint32_t r = sm.aux[k];
-                o_idx[goff + i] = sm.run_lo[r] + (k - sm.run_base[r]);
+                const uint32_t from = sm.run_lo[r] + (k - sm.run_base[r]);   // gathered position
+                if (tl1) {
+                    l1_out[goff + i] = ((uint64_t)pq << 32) | (uint32_t)(t_loc + tm32);
+                    l1_idx[goff + i] = from;
+                } else {
+                    o_t[goff + i] = t_loc;
+                    o_pq[goff + i] = pq;
+                    o_idx[goff + i] = L2 ? l1_idx[from] : from;
+                }
             }
         }
         wave_sync();
     }
 }
 
-template <int CAP>
+template <int CAP, bool L2>
 hipError_t launch_segsort_w(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream_t s) {
     const size_t shm = 4 * sizeof(WaveSeg<CAP>);
     static bool attr_done = false;
     if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_segsort_w<CAP>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_segsort_w<CAP, L2>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_done = true;
     }
     const int grid = ((cfg.n_cu * cfg.persist_per_cu + 7) / 8) * 8;   // a multiple of the 8 XCDs
-    hipLaunchKernelGGL(k_segsort_w<CAP>, dim3(grid), dim3(256), shm, s, b);
+    hipLaunchKernelGGL((k_segsort_w<CAP, L2>), dim3(grid), dim3(256), shm, s, b);
     return hipGetLastError();
 }
 
@@ -782,19 +939,40 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
     TRIG_MARK("k_plan", 1);
     // always launched: its extra block writes the segment counts the ordering kernels read
     TRIG_MARK("k_bounds", 0);
-    hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bounds<false>, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_bounds", 1);
     hipError_t e;
+    TrigLaunchCfg wc = cfg;
+    wc.persist_per_cu = wave_wgs_per_cu;
     if (b.sort_kernels & 1u) {
         TRIG_MARK("k_segsort_w", 0);
-        TrigLaunchCfg wc = cfg;
-        wc.persist_per_cu = wave_wgs_per_cu;
         // segments of slices tuned for the small variant also fit the large one
-        e = wave_cap <= (uint32_t)WAVE_CAP_SMALL ? launch_segsort_w<WAVE_CAP_SMALL>(b, wc, s)
-                                                 : launch_segsort_w<WAVE_CAP>(b, wc, s);
+        e = wave_cap <= (uint32_t)WAVE_CAP_SMALL ? launch_segsort_w<WAVE_CAP_SMALL, false>(b, wc, s)
+                                                 : launch_segsort_w<WAVE_CAP, false>(b, wc, s);
         if (e != hipSuccess) return e;
         TRIG_MARK("k_segsort_w", 1);
+    }
+    if (b.sort_kernels & 4u) {
+        // second level of the two-level slices: run starts and numbering of the
+        // level-1 output, its boundary table, the merge
+        TRIG_MARK("k_ingest2", 0);
+        hipLaunchKernelGGL(k_ingest2, dim3(b.total_chunks), dim3(256), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_ingest2", 1);
+        TRIG_MARK("k_plan2", 0);
+        hipLaunchKernelGGL(k_plan2, dim3(b.n_slices), dim3(1024), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_plan2", 1);
+        TRIG_MARK("k_bounds2", 0);
+        hipLaunchKernelGGL(k_bounds<true>, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_bounds2", 1);
+        TRIG_MARK("k_segsort_w2", 0);
+        e = wave_cap <= (uint32_t)WAVE_CAP_SMALL ? launch_segsort_w<WAVE_CAP_SMALL, true>(b, wc, s)
+                                                 : launch_segsort_w<WAVE_CAP, true>(b, wc, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_segsort_w2", 1);
     }
     if (b.sort_kernels & 2u) {
         TRIG_MARK("k_segsort", 0);

@@ -1121,46 +1121,46 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     }
     __syncthreads();
 
-    // 4. causal folds of the group's seeds, 64 consecutive seeds per wave at a time
+    // 4. causal folds of the group's seeds: a lane per seed, each over its own
+    // window of compacted seeds (bounds by fixed-count binary searches), CB table
+    // reads in flight per lane and round
     if (ok) {
         const bool t16 = W <= 65535u;
+        uint32_t top = 1;   // the largest power of two <= total
+        while (top * 2 <= total) top *= 2;
+        constexpr int CB = 8;
         for (uint32_t c0 = ca + (uint32_t)w * 64; c0 < cb; c0 += NT) {
             const uint32_t i = c0 + (uint32_t)lane;
             const bool vi = i < cb;
-            const uint32_t last = (c0 + 63 < cb) ? c0 + 63 : cb - 1;
-            const uint32_t ti = ct[vi ? i : last];
-            const uint64_t row = (uint64_t)cp[vi ? i : last] * n_pmt;
-            // seeds within w_ns of the first and the last seed of this run
-            const uint32_t t_lo = ct[c0] > W ? ct[c0] - W : 0u;
-            const uint64_t t_hi = (uint64_t)ct[last] + W;
-            uint32_t jl = 0, z = c0;
-            while (jl < z) {
-                const uint32_t mid = (jl + z) >> 1;
-                if (ct[mid] < t_lo) jl = mid + 1; else z = mid;
+            const uint32_t ic = vi ? i : cb - 1;
+            const uint32_t ti = ct[ic];
+            const uint64_t row = (uint64_t)cp[ic] * n_pmt;
+            const uint32_t t_lo = ti > W ? ti - W : 0u;
+            const uint64_t t_hi = (uint64_t)ti + W;
+            uint32_t jl = 0, jr = 0;   // seeds with time < t_lo, seeds with time <= t_hi
+            for (uint32_t step = top; step; step >>= 1) {
+                const uint32_t ml = jl + step, mr = jr + step;
+                if (ml <= total && ct[ml - 1] < t_lo) jl = ml;
+                if (mr <= total && (uint64_t)ct[mr - 1] <= t_hi) jr = mr;
             }
-            uint32_t jr = last + 1;
-            z = total;
-            while (jr < z) {
-                const uint32_t mid = (jr + z) >> 1;
-                if ((uint64_t)ct[mid] <= t_hi) jr = mid + 1; else z = mid;
-            }
-            constexpr int CB = 8;
+            if (!vi) jr = jl;
             uint32_t c = 0;
-            for (uint32_t j0 = jl; j0 < jr; j0 += CB) {
+            for (uint32_t j0 = jl;; j0 += CB) {
+                if (!__ballot(j0 < jr)) break;
                 uint32_t dd[CB], lim[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
                     const uint32_t j = j0 + k;
-                    const uint32_t jc = j < jr ? j : jr - 1;
-                    const uint32_t tj = ct[jc];
-                    const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                    const bool use = vi && j < jr && j != i && dt <= W;
                     dd[k] = 0xFFFFFFFFu;
                     lim[k] = 0;
-                    if (use) {
-                        const uint64_t x = row + cp[jc];
-                        lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
-                        dd[k] = dt;
+                    if (j < jr && j != i) {
+                        const uint32_t tj = ct[j];
+                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                        if (dt <= W) {
+                            const uint64_t x = row + cp[j];
+                            lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
+                            dd[k] = dt;
+                        }
                     }
                 }
 #pragma unroll

@@ -56,6 +56,7 @@ enum State : uint32_t {
 enum Counter : int {
     Q_SEG_TOTAL = 0,     // number of segment items of the wave-per-segment kernel
     Q_SEG_TOTAL_B = 1,   // number of segment items of the block-per-segment kernel
+    Q_SEG_TOTAL2 = 2,    // number of segment items of the second level (two-level slices)
     N_COUNTERS = 16,
 };
 
@@ -115,6 +116,14 @@ struct Plan {
     uint32_t dense;          // a trigger tile's window outran its staged halo: rerun with a seed mask
     uint32_t generic;        // ordered by the general path
     uint32_t n_tagged;       // hits inside the event windows (slices that ask for the tagged list)
+    // two-level ordering (slices with more runs than a wave merges): level 1 orders
+    // groups of run_grp consecutive runs over segments of 2^shift ns (n_grp * n_seg
+    // work items), level 2 merges the n_runs2 time-ordered stretches that level 1
+    // leaves over segments of 2^shift2 ns
+    uint32_t tl;
+    uint32_t n_grp, run_grp;
+    uint32_t n_runs2, shift2, n_seg2, seg_item_base2;
+    uint32_t pad2;
 };
 
 struct SliceDev {
@@ -164,7 +173,8 @@ struct BatchDev {
     uint32_t total_chunks;
     uint32_t total_tiles;
     uint32_t tail_state;     // the tail kernels process slices in this state
-    uint32_t sort_kernels;   // ordering kernels launched: bit 0 wave-per-segment, bit 1 block-per-segment
+    uint32_t sort_kernels;   // ordering kernels launched: bit 0 wave-per-segment, bit 1 block-per-segment,
+                             // bit 2 the second level of the two-level ordering
     uint32_t block_cap, block_target;   // block kernel capacity / target for slices it takes over
     uint32_t *counters;
     Plan *x_plans;           // host-mapped copy of the plans written at the end of the tail
@@ -380,6 +390,16 @@ __host__ __device__ __forceinline__ uint32_t groups_of(uint32_t n_tiles, uint32_
 // bytes per hit there, 8 needed).
 __device__ __forceinline__ TRIG_GAS uint64_t *packed_hits(const SliceDev &S) {
     return (TRIG_GAS uint64_t *)gmem(S.fsc);
+}
+
+// Two-level ordering: level 1 writes each group's ordered hits as packed words
+// (same format as packed_hits) into the second half of the fire-record area, and
+// their input indices into the fire area (both unused until the trigger stage).
+__device__ __forceinline__ TRIG_GAS uint64_t *level1_hits(const SliceDev &S) {
+    return (TRIG_GAS uint64_t *)gmem(S.fsc) + (uint64_t)S.n_tiles * TILE;
+}
+__device__ __forceinline__ TRIG_GAS uint32_t *level1_index(const SliceDev &S) {
+    return (TRIG_GAS uint32_t *)gmem(S.fires);
 }
 
 __device__ __forceinline__ bool slice_in_tail(const BatchDev &b, uint32_t state) {

@@ -204,14 +204,28 @@ def slice_desc(geom_id: int, pmt, t, q, tag: int = 0):
     return d, (pmt, t, q)
 
 
-class ResultBuffers:
-    """Host buffers of one result record."""
+def _host_array(count: int, dtype, pinned: bool):
+    """A zeroed host array; ``pinned`` places it in pinned (page-locked) memory,
+    which the library's kernels write large result lists into directly."""
+    dtype = np.dtype(dtype)
+    if not pinned:
+        return np.zeros(count, dtype), None
+    import torch
+    buf = torch.zeros(count * dtype.itemsize, dtype=torch.uint8, pin_memory=True)
+    return buf.numpy().view(dtype), buf
 
-    def __init__(self, fire_cap: int, event_cap: int, n_hits: int, seed_flags: bool, tagged_cap: int | None = None):
-        self.fires = np.zeros(max(fire_cap, 1), FIRE_DTYPE)
-        self.events = np.zeros(max(event_cap, 1), EVENT_DTYPE)
+
+class ResultBuffers:
+    """Host buffers of one result record (``pinned``: fire, event and tagged
+    lists in pinned memory)."""
+
+    def __init__(self, fire_cap: int, event_cap: int, n_hits: int, seed_flags: bool, tagged_cap: int | None = None,
+                 pinned: bool = False):
+        self.fires, self._pf = _host_array(max(fire_cap, 1), FIRE_DTYPE, pinned)
+        self.events, self._pe = _host_array(max(event_cap, 1), EVENT_DTYPE, pinned)
         self.flags = np.zeros(max(n_hits, 1), np.uint8) if seed_flags else None
-        self.tagged = np.zeros(max(tagged_cap, 1), np.uint32) if tagged_cap is not None else None
+        self.tagged, self._pt = _host_array(max(tagged_cap, 1), np.uint32, pinned) if tagged_cap is not None \
+            else (None, None)
         self.rec = Result()
         self.reset()
 
@@ -470,13 +484,13 @@ class SliceRunner:
     """
 
     def __init__(self, ctx, geom_id, pmt, t, q, params=None, *, stream=None, fire_cap=None, event_cap=None,
-                 seed_flags=False, tagged=False, tagged_cap=None):
+                 seed_flags=False, tagged=False, tagged_cap=None, pinned=False):
         self.ctx = ctx
         self.desc, self._keep = slice_desc(geom_id, pmt, t, q)
         n = int(self.desc.n_hits)
         fc, ec = _default_caps(n)
         tc = (tagged_cap or max(4096, n // 8)) if tagged else None
-        self.buf = ResultBuffers(fire_cap or fc, event_cap or ec, n, seed_flags, tc)
+        self.buf = ResultBuffers(fire_cap or fc, event_cap or ec, n, seed_flags, tc, pinned)
         self.prm = params_struct(params)
         if stream is None and _is_torch(t):
             import torch
