@@ -1044,12 +1044,28 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     const bool cover_l = sl == 0 || (uint64_t)st[0] + reach < (uint64_t)ta;
     const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + reach;
     const bool covered = cover_l && cover_r;
+    // the stage positions that matter: seeds within w_ns of the group's hits
+    // ([p_l, p_r)) and, for their floor partners, the hits within t_floor_ns
+    // before them (from p_lp); the halo is sized with a margin, so the rest of it
+    // is skipped
+    auto first_ge = [&](uint64_t tv) -> uint32_t {   // first stage position with time >= tv
+        uint32_t lo = 0, hi = len;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((uint64_t)st[mid] < tv) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    const uint32_t p_lp = (uint64_t)ta >= reach ? first_ge((uint64_t)ta - reach) : 0u;
+    const uint32_t p_l = ta >= W ? first_ge((uint64_t)ta - W) : 0u;
+    const uint32_t p_r = first_ge((uint64_t)te + W + 1);
 
-    // 2. floor-coincidence pairs (x, x + d) within the stage
+    // 2. floor-coincidence pairs (x, x + d) within the stage, for x in [p_lp, p_r)
     if (covered && tau >= 0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if ((uint32_t)(u * NT + w * 64) >= len) break;   // (wave-uniform)
+            if ((uint32_t)(u * NT + w * 64) >= p_r) break;   // (wave-uniform)
+            if ((uint32_t)(u * NT + w * 64 + 64) <= p_lp) continue;
             const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
             const uint32_t x = u * NT + threadIdx.x;
             const bool in0 = x < len;
@@ -1082,11 +1098,18 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     }
     __syncthreads();
 
-    // 3. seed words, their prefix, and the compacted seeds of the stage
+    // 3. seed words (the seeds in [p_l, p_r) only: no other can be within w_ns
+    // of the group's seeds), their prefix, and the compacted seeds
     uint32_t total = 0;
     {
         uint64_t sw = 0;
-        if (threadIdx.x < nwords) sw = qw[threadIdx.x] | pw[threadIdx.x];
+        if (threadIdx.x < nwords) {
+            const uint32_t b0 = threadIdx.x * 64;
+            const uint32_t lo = p_l > b0 ? min(p_l - b0, 64u) : 0u;
+            const uint32_t hi = p_r > b0 ? min(p_r - b0, 64u) : 0u;
+            const uint64_t keep = (hi > lo) ? ((hi == 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull)) : 0ull;
+            sw = (qw[threadIdx.x] | pw[threadIdx.x]) & keep;
+        }
         static_assert(NWD <= NT, "one word per thread");
         const uint32_t ex = block_excl_scan<NT>((uint32_t)__popcll(sw), total, sh);
         if (threadIdx.x < nwords) {
