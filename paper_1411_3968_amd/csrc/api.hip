@@ -404,6 +404,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
             S.thr16 = g.thr16;
             S.adj32 = g.adj32;
             S.afl32 = g.afl32;
+            S.tbnd = g.tbnd;
+            S.nbk = g.nbk;
             S.n_pmt = g.n_pmt;
             S.pbits = pbits_of(g.n_pmt);
         } else {
@@ -499,6 +501,12 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.prm = params;
     batch.tile_group = tile_group;
     batch.halo_cap = halo_cap;
+    {
+        uint32_t nb_max = 0;
+        for (const SliceInfo &si : slices)
+            if (si.host_status == TRIG_OK) nb_max = std::max(nb_max, si.dev.nbk);
+        batch.tbnd_lds = nb_max && nb_max <= (uint32_t)TBND_LDS_MAX ? nb_max * nb_max : 0u;
+    }
     batch.total_groups = total_groups;
     batch.group_slice = d_group_slice;
     return TRIG_OK;
@@ -947,6 +955,7 @@ void trig_destroy(trig_ctx *c) {
         hipFree(g.thr16);
         hipFree(g.adj32);
         hipFree(g.afl32);
+        hipFree(g.tbnd);
     }
     for (auto ev : c->ev_pool) hipEventDestroy(ev);
     for (auto &m : c->prof_pending) hipEventDestroy(m.ev);
@@ -966,7 +975,8 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     }
     hipSetDevice(c->device);
     const uint64_t P = g->n_pmt;
-    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2 + P * 8;
+    const uint64_t nbb = P >= TBND_MIN_PMT ? (P + 31) / 32 : 0;
+    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2 + P * 8 + nbb * nbb * 2;
     if (ctx_reserve(c, bytes) != TRIG_OK) {
         ctx_set_error(c, "device budget exceeded by geometry");
         return TRIG_ENOMEM;
@@ -1008,7 +1018,32 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
             afl[fl[i].second] = r;
         }
     }
+    // bounds of min(thr, 65535) per pair of 32-PMT blocks, in 16 ns units (the lower
+    // bound rounded down, capped at 4080 ns; the upper rounded up, 255 when above
+    // 4064 ns: no bound): the counting kernel decides most pairs from them and
+    // reads the table only in between
+    std::vector<uint16_t> tb;
+    if (P >= TBND_MIN_PMT) {
+        const uint64_t nb = (P + (1u << TBND_SHIFT) - 1) >> TBND_SHIFT;
+        d.nbk = (uint32_t)nb;
+        tb.assign(nb * nb, 0);
+        for (uint64_t bi = 0; bi < nb; ++bi)
+            for (uint64_t bj = 0; bj < nb; ++bj) {
+                uint32_t mn = 0xFFFFu, mx = 0u;
+                for (uint64_t i = bi << TBND_SHIFT; i < std::min(P, (bi + 1) << TBND_SHIFT); ++i)
+                    for (uint64_t j = bj << TBND_SHIFT; j < std::min(P, (bj + 1) << TBND_SHIFT); ++j) {
+                        const uint32_t v = t16[i * P + j];
+                        mn = std::min(mn, v);
+                        mx = std::max(mx, v);
+                    }
+                const uint32_t lo = std::min(mn, 4080u) / 16u;
+                const uint32_t hi = mx <= 4064u ? (mx + 15u) / 16u : 255u;
+                tb[bi * nb + bj] = (uint16_t)(lo | (hi << 8));
+            }
+    }
     hipError_t e = hipMalloc(&d.floor_id, P * 4);
+    if (e == hipSuccess && d.nbk) e = hipMalloc(&d.tbnd, tb.size() * 2);
+    if (e == hipSuccess && d.nbk) e = hipMemcpy(d.tbnd, tb.data(), tb.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d.adj32, P * 4);
     if (e == hipSuccess) e = hipMalloc(&d.afl32, P * 4);
     if (e == hipSuccess) e = hipMemcpy(d.adj32, adj.data(), P * 4, hipMemcpyHostToDevice);
@@ -1021,6 +1056,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     if (e == hipSuccess) e = hipMemcpy(d.thr32, g->thr_ns, P * P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d.thr16, t16.data(), P * P * 2, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
+        hipFree(d.tbnd);
         hipFree(d.floor16);
         hipFree(d.floor_id);
         hipFree(d.adj32);

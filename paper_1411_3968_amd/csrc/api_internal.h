@@ -34,6 +34,10 @@ struct GeomDev {
     uint16_t *thr16 = nullptr;
     uint32_t *adj32 = nullptr;     // dense adjacency group (a PMT of its own when none is given)
     uint32_t *afl32 = nullptr;     // floor rank, consecutive floor ids one apart, others two
+    // bounds of the table per pair of 32-PMT blocks (lower | upper << 8, 16 ns
+    // units), nbk x nbk; nbk = 0 (no bounds) for small detectors whose table stays in cache
+    uint16_t *tbnd = nullptr;
+    uint32_t nbk = 0;
 };
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).

@@ -26,6 +26,11 @@ __device__ __forceinline__ bool l0_slice(const BatchDev &b, const SliceDev &S, u
     return slice_in_tail(b, gmem(b.plans + si)->state);
 }
 
+// The distinct-PMT form stages its tile and DN_HALO ordered neighbours (after
+// the tile for the windows that start in it, before it for the starts that hold
+// its hits) in LDS; a window reaching past them reads global memory.
+constexpr int DN_HALO = 512;
+
 __global__ __launch_bounds__(NTL) void k_l0_ok(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
@@ -42,20 +47,32 @@ __global__ __launch_bounds__(NTL) void k_l0_ok(BatchDev b) {
     const uint32_t N = b.prm.l0_n, TW = b.prm.l0_tw_ns;
     const bool distinct = b.prm.l0_distinct != 0;
     const int lane = lane_id(), w = threadIdx.x >> 6;
+    __shared__ uint32_t lt[TILE + DN_HALO];
+    __shared__ uint16_t lp[TILE + DN_HALO];
+    const uint64_t se = distinct ? ((e + DN_HALO < n) ? e + DN_HALO : n) : a;   // staged [a, se)
+    if (distinct) {
+        for (uint32_t x = threadIdx.x; x < (uint32_t)(se - a); x += NTL) {
+            lt[x] = o_t[a + x];
+            lp[x] = (uint16_t)(o_pq[a + x] >> 16);
+        }
+        __syncthreads();
+    }
+    auto t_at = [&](uint64_t m) -> uint32_t { return m < se ? lt[m - a] : o_t[m]; };
+    auto p_at = [&](uint64_t m) -> uint32_t { return m < se ? (uint32_t)lp[m - a] : (o_pq[m] >> 16); };
     for (uint32_t x0 = 0; x0 < (uint32_t)TILE; x0 += NTL) {
         const uint64_t i = a + x0 + threadIdx.x;
         bool ok = false;
         if (i < e) {
-            const uint32_t ti = o_t[i];
             if (!distinct) {
-                ok = i + N - 1 < n && o_t[i + N - 1] - ti < TW;
+                ok = i + N - 1 < n && o_t[i + N - 1] - o_t[i] < TW;
             } else {
                 // distinct PMTs among the hits from i on within TW (stop at N)
+                const uint32_t ti = t_at(i);
                 uint32_t c = 0;
-                for (uint64_t m = i; m < n && o_t[m] - ti < TW && c < N; ++m) {
-                    const uint32_t pm = o_pq[m] >> 16;
+                for (uint64_t m = i; m < n && t_at(m) - ti < TW && c < N; ++m) {
+                    const uint32_t pm = p_at(m);
                     bool dup = false;
-                    for (uint64_t u = i; u < m && !dup; ++u) dup = (o_pq[u] >> 16) == pm;
+                    for (uint64_t u = i; u < m && !dup; ++u) dup = p_at(u) == pm;
                     c += dup ? 0u : 1u;
                 }
                 ok = c >= N;
@@ -84,6 +101,14 @@ __global__ __launch_bounds__(NTL) void k_l0_pass(BatchDev b) {
     const uint32_t N = b.prm.l0_n, TW = b.prm.l0_tw_ns;
     const bool distinct = b.prm.l0_distinct != 0;
     const int lane = lane_id(), w = threadIdx.x >> 6;
+    // the distinct-PMT form: times of the tile and DN_HALO positions before it in LDS
+    __shared__ uint32_t lt[TILE + DN_HALO];
+    const uint64_t s0 = distinct ? (a > (uint64_t)DN_HALO ? a - DN_HALO : 0) : a;   // staged [s0, e)
+    if (distinct) {
+        for (uint32_t x = threadIdx.x; x < (uint32_t)(e - s0); x += NTL) lt[x] = o_t[s0 + x];
+        __syncthreads();
+    }
+    auto t_at = [&](uint64_t m) -> uint32_t { return m >= s0 && m < e ? lt[m - s0] : o_t[m]; };
     for (uint32_t x0 = 0; x0 < (uint32_t)TILE; x0 += NTL) {
         const uint64_t x = a + x0 + threadIdx.x;
         bool pass = false;
@@ -100,9 +125,9 @@ __global__ __launch_bounds__(NTL) void k_l0_pass(BatchDev b) {
             }
         } else if (x < e) {
             // counting PMTs: every start at or before x (in time order) that still holds x
-            const uint32_t tx = o_t[x];
+            const uint32_t tx = t_at(x);
             for (uint64_t i = x + 1; i-- > 0 && !pass;) {
-                if (tx - o_t[i] >= TW) break;
+                if (tx - t_at(i) >= TW) break;
                 pass = bit_at(okw, i);
             }
         }

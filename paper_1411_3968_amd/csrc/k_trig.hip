@@ -922,7 +922,7 @@ struct CountShape {
     static constexpr int NWD = STG / 64;              // 64-hit words of the stage
     static constexpr int CS = STG / 4;                // seeds of a stage the lists hold
     static constexpr size_t lds_bytes() {
-        return (size_t)STG * 4 * 2 + (size_t)CS * 4 * 2 + (size_t)NWD * 8 * 3 + (size_t)(NWD + 2) * 4 +
+        return (size_t)STG * 4 * 2 + (size_t)CS * 4 * 2 + (size_t)NWD * 8 * 4 + (size_t)(NWD + 2) * 4 +
                (size_t)CS * 2 * 3;
     }
     static_assert(STG % NT == 0 && G <= NW, "stage layout");
@@ -940,12 +940,14 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     uint32_t *fold = ct + CS;                           // fold of each seed of the group
     uint64_t *qw = (uint64_t *)(fold + CS);             // charge seeds, then all seeds, per word
     uint64_t *lw = qw + NWD;                            // level-0 pass bits per word
-    uint64_t *pw = lw + NWD;                            // floor-partner bits per word
-    uint32_t *wpre = (uint32_t *)(pw + NWD);            // seeds before each word (NWD + 1)
+    uint64_t *pw = lw + NWD;                            // floor-partner bits from far pairs per word
+    uint64_t *pin = pw + NWD;                           // floor-partner bits from the word before
+    uint32_t *wpre = (uint32_t *)(pin + NWD);           // seeds before each word (NWD + 1)
     uint16_t *cp = (uint16_t *)(wpre + NWD + 2);        // compacted seeds: PMT
     uint16_t *cidx = cp + CS;                           // compacted seeds: stage position
     uint16_t *fci = cidx + CS;                          // fires of each tile: compacted index
     uint16_t *lfl = fci + CS;                           // dense floor index of every PMT (floor_lds of them)
+    uint16_t *ltb = lfl + ((floor_lds + 1) & ~1u);      // the table bounds (b.tbnd_lds of them)
     __shared__ uint32_t sh[Sh::NW + 1];
 
     // XCD-aware order: workgroup b runs on XCD b % 8 and takes groups from that
@@ -994,48 +996,54 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     const uint32_t len = (uint32_t)(she - sl);
     const uint32_t nwords = (len + 63) / 64;
 
-    // 1. stage: all loads of a thread in flight, then the words of each round
+    // 1. stage: all loads of a thread in flight (positions past the stage read
+    // its last hit: no branch around a load), then the words of each round
+    const uint32_t lastx = len - 1;
     uint32_t vt[U], vp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t x = u * NT + threadIdx.x;
-        if (x < len) {
-            vt[u] = o_t[sl + x];
-            vp[u] = o_pq[sl + x];
-        }
+        const uint32_t x = min((uint32_t)(u * NT) + threadIdx.x, lastx);
+        vt[u] = o_t[sl + x];
+        vp[u] = o_pq[sl + x];
     }
     const bool floor_in_lds = n_pmt <= floor_lds;
     if (floor_in_lds)
         for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
+    // the table bounds of a large detector (read by the folds after the barriers below)
+    const uint32_t nbk = S.nbk;
+    const bool bounds = nbk != 0 && W <= 65535u;
+    const bool tb_in_lds = bounds && nbk * nbk <= b.tbnd_lds;
+    const TRIG_GAS uint16_t *tbnd = gmem(S.tbnd);
+    if (tb_in_lds)
+        for (uint32_t x = threadIdx.x; x < nbk * nbk; x += NT) ltb[x] = tbnd[x];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t x = u * NT + threadIdx.x;
         const bool in = x < len;
         bool l0x = in;
-        if (L0 && in) {
-            const uint64_t j = sl + x;
-            l0x = (l0m[j >> 6] >> (j & 63)) & 1ull;
+        if (L0) {
+            const uint64_t j = sl + min(x, lastx);
+            l0x = in & (((l0m[j >> 6] >> (j & 63)) & 1ull) != 0);
         }
         const uint64_t lb = __ballot(l0x);
-        const uint64_t qb = __ballot(in && (vp[u] & 0xFFFFu) >= q_seed) & lb;
+        const uint64_t qb = __ballot(in & ((vp[u] & 0xFFFFu) >= q_seed)) & lb;
         const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
         if (lane == 0) {
             qw[wd] = qb;
             lw[wd] = lb;
             pw[wd] = 0ull;
+            pin[wd] = 0ull;
         }
-        if (in) st[x] = vt[u];
+        st[x] = vt[u];   // (positions past the stage are never read)
     }
     __syncthreads();   // floor numbering and times staged
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t x = u * NT + threadIdx.x;
-        if (x < len) {
-            const uint32_t p = vp[u] >> 16;
-            const uint32_t f = floor_in_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
-            vp[u] = (p << 16) | f;
-            spf[x] = vp[u];
-        }
+        const uint32_t p = vp[u] >> 16;
+        const uint32_t f = floor_in_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
+        vp[u] = (p << 16) | f;
+        spf[x] = vp[u];
     }
     __syncthreads();
     const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
@@ -1060,7 +1068,12 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     const uint32_t p_l = ta >= W ? first_ge((uint64_t)ta - W) : 0u;
     const uint32_t p_r = first_ge((uint64_t)te + W + 1);
 
-    // 2. floor-coincidence pairs (x, x + d) within the stage, for x in [p_lp, p_r)
+    // 2. floor-coincidence pairs (x, x + d) within the stage, for x in [p_lp, p_r).
+    // A pair found marks x (the word's own bits) and x + d: within the word or,
+    // for d < 64, in the next word's incoming bits (written by this wave alone);
+    // pairs 64 or more positions apart (a burst of equal times) are ORed into the
+    // far bits.  Every value is computed in every lane (bitwise operators, clamped
+    // reads), so the loop branches only on its exit and on a pair found.
     if (covered && tau >= 0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1069,31 +1082,51 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
             const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
             const uint32_t x = u * NT + threadIdx.x;
             const bool in0 = x < len;
-            const uint32_t t = in0 ? vt[u] : 0u, f = in0 ? vp[u] : 0u;
-            const bool l0x = (lw[wd] >> lane) & 1ull;
-            uint64_t own = 0;
-            for (uint32_t d = 1;; ++d) {
-                const uint32_t y = x + d;
-                const bool inr = in0 && y < len;
-                const uint32_t yc = inr ? y : 0u;
-                const uint32_t ty = st[yc], gy = spf[yc];
-                const bool near = inr && ty - t <= tau_u;
-                if (!__ballot(near)) break;
-                const bool l0y = !L0 || ((lw[yc >> 6] >> (yc & 63)) & 1ull);
-                const bool pr = near && ((gy & 0xFFFFu) == (f & 0xFFFFu)) && ((gy >> 16) != (f >> 16)) && l0x && l0y;
-                const uint64_t M = __ballot(pr);
-                if (M) {
+            const uint32_t t = vt[u], f = vp[u];
+            const bool l0x = ((lw[wd] >> lane) & 1ull) != 0;
+            uint64_t own = 0, fwd0 = 0, fwd1 = 0;
+            // four distances per step, their reads issued together; times are
+            // ordered, so once no lane is near at distance d none is further on
+            constexpr int DU = 4;
+            for (uint32_t d0 = 1;; d0 += DU) {
+                uint32_t ty[DU], gy[DU];
+#pragma unroll
+                for (int k = 0; k < DU; ++k) {
+                    const uint32_t yc = min(x + d0 + k, lastx);
+                    ty[k] = st[yc];
+                    gy[k] = spf[yc];
+                }
+                bool near = false;
+#pragma unroll
+                for (int k = 0; k < DU; ++k) {
+                    const uint32_t d = d0 + k, y = x + d;
+                    near = in0 & (y < len) & (ty[k] - t <= tau_u);
+                    bool l0y = true;
+                    if (L0) {
+                        const uint32_t yc = min(y, lastx);
+                        l0y = ((lw[yc >> 6] >> (yc & 63)) & 1ull) != 0;
+                    }
+                    const bool pr = near & (((gy[k] ^ f) & 0xFFFFu) == 0u) & ((gy[k] >> 16) != (f >> 16)) & l0x & l0y;
+                    const uint64_t M = __ballot(pr);
                     own |= M;
-                    if (lane == 0) {
-                        // the successors at x + d: bit (lane + d) counted from word wd
-                        const uint32_t s = d & 63, w0 = wd + (d >> 6);
-                        atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << s));
-                        const uint64_t spill = s ? (M >> (64 - s)) : 0ull;
-                        if (spill) atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                    if (M) {
+                        if (d < 64) {
+                            fwd0 |= M << d;
+                            fwd1 |= M >> (64 - d);
+                        } else if (lane == 0) {
+                            const uint32_t sft = d & 63, w0 = wd + (d >> 6);
+                            atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << sft));
+                            const uint64_t spill = sft ? (M >> (64 - sft)) : 0ull;
+                            if (spill) atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                        }
                     }
                 }
+                if (!__ballot(near)) break;   // (near at the step's last distance)
             }
-            if (lane == 0 && own) atomicOr((unsigned long long *)&pw[wd], (unsigned long long)own);
+            if (lane == 0) {
+                qw[wd] |= own | fwd0;
+                if (wd + 1 < (uint32_t)NWD) pin[wd + 1] = fwd1;
+            }
         }
     }
     __syncthreads();
@@ -1108,7 +1141,7 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
             const uint32_t lo = p_l > b0 ? min(p_l - b0, 64u) : 0u;
             const uint32_t hi = p_r > b0 ? min(p_r - b0, 64u) : 0u;
             const uint64_t keep = (hi > lo) ? ((hi == 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull)) : 0ull;
-            sw = (qw[threadIdx.x] | pw[threadIdx.x]) & keep;
+            sw = (qw[threadIdx.x] | pin[threadIdx.x] | pw[threadIdx.x]) & keep;
         }
         static_assert(NWD <= NT, "one word per thread");
         const uint32_t ex = block_excl_scan<NT>((uint32_t)__popcll(sw), total, sh);
@@ -1168,26 +1201,64 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
             }
             if (!vi) jr = jl;
             uint32_t c = 0;
-            for (uint32_t j0 = jl;; j0 += CB) {
-                if (!__ballot(j0 < jr)) break;
-                uint32_t dd[CB], lim[CB];
+            if (bounds) {
+                // large tables: the block-pair bounds decide most pairs (min(thr, W)
+                // at least their lower bound: counted; above their upper bound: not),
+                // the table is read only for the pairs in between
+                const uint32_t brow = ((uint32_t)cp[ic] >> TBND_SHIFT) * nbk;
+                for (uint32_t j0 = jl;; j0 += CB) {
+                    if (!__ballot(j0 < jr)) break;
+                    uint32_t dd[CB], bb[CB], pj[CB];
 #pragma unroll
-                for (int k = 0; k < CB; ++k) {
-                    const uint32_t j = j0 + k;
-                    dd[k] = 0xFFFFFFFFu;
-                    lim[k] = 0;
-                    if (j < jr && j != i) {
-                        const uint32_t tj = ct[j];
-                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                        if (dt <= W) {
-                            const uint64_t x = row + cp[j];
-                            lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
-                            dd[k] = dt;
+                    for (int k = 0; k < CB; ++k) {
+                        const uint32_t j = j0 + k;
+                        dd[k] = 0xFFFFFFFFu;
+                        bb[k] = 0;
+                        pj[k] = 0;
+                        if (j < jr && j != i) {
+                            const uint32_t tj = ct[j];
+                            const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                            if (dt <= W) {
+                                pj[k] = cp[j];
+                                const uint32_t bx = brow + (pj[k] >> TBND_SHIFT);
+                                bb[k] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
+                                dd[k] = dt;
+                            }
                         }
                     }
-                }
+                    uint32_t lim[CB];
 #pragma unroll
-                for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
+                    for (int k = 0; k < CB; ++k) {
+                        const uint32_t hb = bb[k] >> 8;
+                        const uint32_t mn = min((bb[k] & 0xFFu) * 16u, W), mx = hb == 255u ? W : min(hb * 16u, W);
+                        lim[k] = dd[k] <= mn ? W : 0u;
+                        if (dd[k] != 0xFFFFFFFFu && dd[k] > mn && dd[k] <= mx) lim[k] = (uint32_t)thr16[row + pj[k]];
+                    }
+#pragma unroll
+                    for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
+                }
+            } else {
+                for (uint32_t j0 = jl;; j0 += CB) {
+                    if (!__ballot(j0 < jr)) break;
+                    uint32_t dd[CB], lim[CB];
+#pragma unroll
+                    for (int k = 0; k < CB; ++k) {
+                        const uint32_t j = j0 + k;
+                        dd[k] = 0xFFFFFFFFu;
+                        lim[k] = 0;
+                        if (j < jr && j != i) {
+                            const uint32_t tj = ct[j];
+                            const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                            if (dt <= W) {
+                                const uint64_t x = row + cp[j];
+                                lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
+                                dd[k] = dt;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
+                }
             }
             if (vi) fold[i - ca] = c + 1;
         }
@@ -1276,10 +1347,10 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
 template <int G, int HMAX>
 hipError_t launch_count_v(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
     using Sh = CountShape<G, HMAX>;
-    const size_t shm = Sh::lds_bytes() + ((floor_lds * 2 + 15) & ~15u);
-    static const hipError_t attr = hipFuncSetAttribute((const void *)k_count<G, HMAX>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       (int)(Sh::lds_bytes() + FLOOR_LDS_MAX * 2));
+    const size_t shm = Sh::lds_bytes() + (((floor_lds + 1) & ~1u) * 2) + (((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_count<G, HMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(Sh::lds_bytes() + FLOOR_LDS_MAX * 2 + TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16));
     if (attr != hipSuccess) return attr;
     hipLaunchKernelGGL((k_count<G, HMAX>), dim3(((b.total_groups + 7) / 8) * 8), dim3(256), shm, s, b, floor_lds);
     return hipGetLastError();

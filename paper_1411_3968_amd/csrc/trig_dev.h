@@ -163,7 +163,14 @@ struct SliceDev {
     uint64_t *l0m;           // level-0 pass bits by ordered position (level 0 on)
     const uint32_t *adj32;   // per PMT: adjacency group (SC)
     const uint32_t *afl32;   // per PMT: floor rank, 1 apart exactly for consecutive floors (AFC)
+    const uint16_t *tbnd;    // table bounds per pair of 32-PMT blocks, nbk x nbk: lower | upper << 8 in
+                             // 16 ns units (upper 255: none)
+    uint32_t nbk, nbk_pad;   // blocks per side, 0: no bounds
 };
+
+constexpr int TBND_SHIFT = 5;   // 32 PMTs per block of the table bounds
+constexpr uint32_t TBND_MIN_PMT = 256;   // bounds only for detectors with more PMTs
+constexpr int TBND_LDS_MAX = 128;   // bounds staged in LDS up to 128 x 128 blocks (32 KB)
 
 struct BatchDev {
     SliceDev *slices;
@@ -183,7 +190,8 @@ struct BatchDev {
     // workgroup, halo_cap ordered hits staged at most on each side; group_slice
     // maps every group to its slice (written by k_plan; unused for one slice)
     uint32_t tile_group, halo_cap;
-    uint32_t total_groups, pad_groups;
+    uint32_t total_groups;
+    uint32_t tbnd_lds;       // table-bound entries the counting kernel stages in LDS (0: none)
     uint32_t *group_slice;
 };
 
