@@ -66,7 +66,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--legs", default="headline,tower,batch,serving",
+                    help="legs to run: headline (the block slice), tower, batch, serving")
     ap.add_argument("--only-headline", action="store_true", help="the block slice only (profiling runs)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned launch parameters: applied when it holds a class, else written")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline legs")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -244,9 +248,15 @@ def bench_batch(T, torch, dev, a):
     tr = T.Trigger(0)
     gids = {k: tr.load_geometry(g.floor_id, thr) for k, (g, thr) in w.geoms.items()}
     tuned = {}
-    sample = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in held.slices]
+    sample = []
+
+    def mixed():
+        if not sample:
+            sample.extend((gids[k],) + _dev_slice(torch, dev, s) for k, s in held.slices)
+        return sample, "held-out mixed batch: seed 12, %d slices" % len(held.slices)
+
     for key, pmax in (("km3", 84), ("nemo", 32)):
-        tuned[key] = autotune.tune_class(tr.ctx, pmax, sample, w.params, reps=5, time_budget_s=20.0)
+        tuned[key] = tune_or_apply(autotune, tr.ctx, a.tune_cache, pmax, mixed, w.params, key)
     del sample
     dsl = [(gids[k],) + _dev_slice(torch, dev, s) for k, s in w.slices]
     n = int(sum(s.n for _, s in w.slices))
@@ -281,8 +291,7 @@ def bench_batch(T, torch, dev, a):
                 per_slice_loop=dict(value=round(n / el_loop, 1), ms=round(el_loop * 1e3, 3)),
                 speedup_vs_per_slice=round(el_loop / el, 3), results_equal_per_slice=bool(same),
                 fires=int(sum(r["n_fires"] for r in res)), kernels=kernels, gen_seconds=round(gen_s, 1),
-                autotune={key: dict({k: t["best"][k] for k in autotune.KNOBS},
-                                    sample="held-out mixed batch: seed 12, %d slices" % len(held.slices),
+                autotune={key: dict({k: t["best"][k] for k in autotune.KNOBS}, sample=t["sample"],
                                     candidates=len(t["trials"]), seconds=round(t["seconds"], 1))
                           for key, t in tuned.items()})
 
@@ -486,20 +495,38 @@ def oracle_baseline(orc, w, cpu_seconds):
     return cpu, ref
 
 
-def main():
-    a = parse()
-    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py drives a single MI355X: multi-GPU runs are not supported", file=sys.stderr)
-        sys.exit(2)
-    import torch
+def tune_or_apply(autotune, ctx, cache, n_pmt_max, sample_fn, params, label):
+    """The class's launch parameters: from the cache file when it holds them (a
+    later profiling run of the same configuration), else tuned on the sample that
+    sample_fn() returns (and added to the cache when one is named)."""
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            doc = json.load(f)
+        for c in doc.get("classes", []):
+            if int(c["n_pmt_max"]) == n_pmt_max:
+                autotune.apply_one(ctx, c)
+                return dict(best=dict(c), trials=[], seconds=0.0, sample="from " + os.path.basename(cache))
+    sample, desc = sample_fn()
+    t = autotune.tune_class(ctx, n_pmt_max, sample, params, reps=5, time_budget_s=20.0)
+    t["sample"] = desc
+    if cache:
+        doc = {"device": "", "classes": []}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                doc = json.load(f)
+        doc["classes"] = [c for c in doc["classes"] if int(c["n_pmt_max"]) != n_pmt_max] + \
+            [dict(n_pmt_max=n_pmt_max, **{k: t["best"][k] for k in autotune.KNOBS})]
+        with open(cache, "w") as f:
+            json.dump(doc, f, indent=1)
+    print(f"[bench] {label} class tuned: {t['best']}", file=sys.stderr, flush=True)
+    return t
 
+
+def bench_headline(T, torch, dev, a):
+    """The block slice: timed steps (graph-replayed), per-kernel durations with the
+    MALL flushed, the host-input rate, and the oracle on the host cores."""
     from gen import configs as C
-    from paper_1411_3968_amd import trig as T
-
-    if not torch.cuda.is_available():
-        print("no GPU", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
+    from paper_1411_3968_amd import autotune
     g0 = time.perf_counter()
     w = C.block_workload(seed=3)
     gen_s = time.perf_counter() - g0
@@ -511,14 +538,15 @@ def main():
     tr = T.Trigger(0)
     gid = tr.load_geometry(g.floor_id, thr)
     stream = torch.cuda.current_stream()
+
     # launch parameters of the block class from the autotuner, tuned on a held-out
     # 50 ms slice of the same detector (another seed), not on the timed slice
-    from paper_1411_3968_amd import autotune
-    held = C.block_workload(seed=13, length_ns=50_000_000, n_tracks=50).slices[0][1]
-    held_d = _dev_slice(torch, dev, held)
-    tuned = autotune.tune_class(tr.ctx, 65536, [(gid,) + held_d], w.params, reps=5, time_budget_s=20.0)
-    del held_d
-    print(f"[bench] block class tuned: {tuned['best']}", file=sys.stderr, flush=True)
+    def held_sample():
+        held = C.block_workload(seed=13, length_ns=50_000_000, n_tracks=50).slices[0][1]
+        return [(gid,) + _dev_slice(torch, dev, held)], f"held-out: seed 13, 50 ms, {held.n} hits"
+
+    tuned = tune_or_apply(autotune, tr.ctx, a.tune_cache, 65536, held_sample, w.params, "block")
+    torch.cuda.empty_cache()
     first = tr.slice(gid, pmt, t, q, w.params, stream=stream)
     assert first["status"] == 0
     # result lists into pinned host buffers (the kernels write them there directly)
@@ -552,13 +580,14 @@ def main():
     # inside every step (PCIe-inclusive rate; not the benchmark value)
     hp = [torch.from_numpy(x).pin_memory() for x in (s.pmt.view(np.int16), s.t, s.q.view(np.int16))]
     run_h = T.SliceRunner(tr.ctx, gid, hp[0].numpy().view(np.uint16), hp[1].numpy(), hp[2].numpy().view(np.uint16),
-                          w.params, stream=stream, fire_cap=first["n_fires"], event_cap=first["n_events"])
+                          w.params, stream=stream, fire_cap=first["n_fires"], event_cap=first["n_events"], pinned=True)
     el_h, _, r_h = time_steps(torch, run_h, max(3, a.steps // 4), 2)
     assert np.array_equal(r_h["fires"], first["fires"]) and np.array_equal(r_h["events"], first["events"])
     host_leg = dict(value=round(n / el_h, 1), unit="hits/s", ms_per_step=round(el_h * 1e3, 4),
                     inputs="pinned host memory, copied to the device inside every step (PCIe-inclusive)")
     del run_h, hp
-    first_fires, first_events = first["fires"], first["events"]
+    first_fires, first_events = first["fires"].copy(), first["events"].copy()
+    del run
     tr.close()
     del pmt, t, q
     torch.cuda.empty_cache()
@@ -572,36 +601,15 @@ def main():
                              and int(ref["seed"].sum()) == first["n_seeds"])
         del ref
     print("[bench] headline and CPU baseline done", file=sys.stderr, flush=True)
-
-    tower = batch = serving = None
-    if not a.only_headline:
-        tower = None if a.no_tower else bench_tower(T, torch, dev, a, orc)
-        print("[bench] tower legs done", file=sys.stderr, flush=True)
-        batch = None if a.no_batch else bench_batch(T, torch, dev, a)
-        print("[bench] batched leg done", file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
-        serving = None if a.no_serve else bench_serving(T, torch, dev, a, orc)
-
     lat_ms = np.array(lat) * 1e3
-    out = dict(
-        metric="hits/s triggered on 1 MI355X",
+    return dict(
         value=round(n / el, 1),
-        unit="hits/s",
-        n_gpus=1,
-        steps=a.steps,
-        warmup=a.warmup,
         ms_per_step=round(el * 1e3, 4),
-        higher_is_better=True,
-        scaling="weak",
-        vs_baseline=None,
-        dtype="u32",
-        data="synthetic",
         config=dict(workload="block-32x84pmt-200ms", n_pmt=int(g.n_pmt), towers=32, hits=n, slice_ms=200,
                     rate_khz=55, burst_pmts="1% at 1 MHz for 20 ms", tracks=200, inputs="device-resident",
-                    params=w.params, gen_seconds=round(gen_s, 1),
-                    autotune=dict({k: tuned["best"][k] for k in autotune.KNOBS},
-                                  sample=f"held-out: seed 13, 50 ms, {held.n} hits", candidates=len(tuned["trials"]),
-                                  seconds=round(tuned["seconds"], 1))),
+                    results="pinned host buffers", params=w.params, gen_seconds=round(gen_s, 1),
+                    autotune=dict({k: tuned["best"][k] for k in autotune.KNOBS}, sample=tuned["sample"],
+                                  candidates=len(tuned["trials"]), seconds=round(tuned["seconds"], 1))),
         latency_ms=dict(p50=round(float(np.percentile(lat_ms, 50)), 4),
                         p99=round(float(np.percentile(lat_ms, 99)), 4)),
         roofline=roofline,
@@ -612,10 +620,55 @@ def main():
         results=dict(n_seeds=first["n_seeds"], n_fires=first["n_fires"], n_events=first["n_events"],
                      path=first["path"], equals_oracle=equals_oracle),
         host_inputs=host_leg,
-        tower=tower,
-        batched=batch,
-        serving=serving,
+    ), orc
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py drives a single MI355X: multi-GPU runs are not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1411_3968_amd import trig as T
+
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    legs = set(x.strip() for x in a.legs.split(",") if x.strip())
+    if a.only_headline:
+        legs = {"headline"}
+    for flag, leg in ((a.no_tower, "tower"), (a.no_batch, "batch"), (a.no_serve, "serving")):
+        if flag:
+            legs.discard(leg)
+    head, orc = bench_headline(T, torch, dev, a) if "headline" in legs else ({}, None)
+    if orc is None and not a.no_cpu and legs - {"headline"}:
+        from oracle import cpu as orc
+    tower = bench_tower(T, torch, dev, a, orc) if "tower" in legs else None
+    print("[bench] tower legs done", file=sys.stderr, flush=True)
+    batch = bench_batch(T, torch, dev, a) if "batch" in legs else None
+    print("[bench] batched leg done", file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
+    serving = bench_serving(T, torch, dev, a, orc) if "serving" in legs else None
+
+    out = dict(
+        metric="hits/s triggered on 1 MI355X",
+        value=head.get("value"),
+        unit="hits/s",
+        n_gpus=1,
+        steps=a.steps,
+        warmup=a.warmup,
+        ms_per_step=head.get("ms_per_step"),
+        higher_is_better=True,
+        scaling="weak",
+        vs_baseline=None,
+        dtype="u32",
+        data="synthetic",
+        config=head.get("config", dict(workload="block-32x84pmt-200ms", legs=sorted(legs))),
     )
+    out.update({k: v for k, v in head.items() if k not in out})
+    out.update(tower=tower, batched=batch, serving=serving)
     print(json.dumps(out))
 
 

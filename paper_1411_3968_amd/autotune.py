@@ -101,11 +101,16 @@ def save(path: str, results: list, device: str = "") -> None:
     os.replace(tmp, path)
 
 
+def apply_one(ctx, c: dict) -> None:
+    """Set one class record of a cache (n_pmt_max and the knobs) on the context."""
+    T.trig_tune_set(ctx, int(c["n_pmt_max"]), int(c["seg_target"]), int(c["seg_cap"]), int(c["grid_per_cu"]),
+                    c.get("tile_group"), c.get("halo_cap"))
+
+
 def apply(ctx, path: str) -> list:
     """Load a JSON cache written by :func:`save` and set it on the context."""
     with open(path) as f:
         doc = json.load(f)
     for c in doc["classes"]:
-        T.trig_tune_set(ctx, int(c["n_pmt_max"]), int(c["seg_target"]), int(c["seg_cap"]), int(c["grid_per_cu"]),
-                        c.get("tile_group"), c.get("halo_cap"))
+        apply_one(ctx, c)
     return doc["classes"]
