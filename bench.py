@@ -36,11 +36,11 @@ ALGO_BYTES_PER_HIT = {
     "k_bounds": 8.0,       # read t (8); the boundary table is counted separately
     "k_segsort": 20.0,     # read the packed word (8) + write ordered t, pmt|q, index (12)
     "k_segsort_w": 20.0,   # the same, one wave per segment
-    "k_count": 8.0,        # read ordered t + pmt|q (8): seeds and causal folds; fires are per fire
-    "k_tile": 8.0,         # the same in the tile-per-workgroup kernel (seed menu, dense rerun)
+    "k_seed": 8.0,         # read ordered t + pmt|q (8): L1 seeds; the compacted seeds are per seed
+    "k_tile": 8.0,         # seeds and folds in the tile-per-workgroup kernel (seed menu, dense rerun)
     "k_tag_bits": 4.125,   # read ordered t (4) + write one tag bit; the few event windows are per event
 }
-COUNTING_KERNEL = "k_count"
+COUNTING_KERNEL = "k_seed"
 
 
 def measured_traffic(kernel, workload):

@@ -299,22 +299,21 @@ int trig_stream_stats_get(trig_ctx *ctx, trig_stream_stats *out);
  *                 with one wave (256: fewer registers and LDS per wave, more
  *                 waves in flight), 2048, 4096 or 8192 with one workgroup
  *   grid_per_cu   persistent workgroups per compute unit
- *   tile_group    1024-hit trigger tiles per workgroup of the counting stage
- *                 (seeds and causal folds; Sec. 4.1 sizes the paper's
- *                 sub-slices per GPU thread): 1, 2 or 4, fewer when the launch
- *                 would otherwise give a compute unit less than two workgroups
- *   halo_cap      ordered hits staged at most on each side of a group, 256 or
- *                 1024 (a group whose causal window reaches further is rerun
- *                 with a precomputed seed mask)
+ *   tile_group    1024-hit trigger tiles per workgroup of the causal-fold
+ *                 stage (Sec. 4.1 sizes the paper's sub-slices per GPU
+ *                 thread): 1, 2 or 4, fewer when the launch would otherwise
+ *                 give a compute unit less than two workgroups
+ *   window_cap    seeds of a group's causal window staged in LDS at most, 1024
+ *                 or 4096 (a larger window is read from device memory)
  * trig_tune_set returns TRIG_EINVAL for other capacities, a zero target, a
- * grid_per_cu outside 1..16 or another tile_group or halo_cap.  A batch whose
- * slices fall in several classes takes the largest tile_group and halo_cap. */
+ * grid_per_cu outside 1..16 or another tile_group or window_cap.  A batch whose
+ * slices fall in several classes takes the largest tile_group and window_cap. */
 typedef struct {
     uint32_t seg_target;
     uint32_t seg_cap;
     uint32_t grid_per_cu;
     uint32_t tile_group;
-    uint32_t halo_cap;
+    uint32_t window_cap;
     uint32_t reserved;
 } trig_tune;
 

@@ -4,11 +4,12 @@ The knobs (``trig_tune``): the ordering kernel and its LDS capacity per time
 segment (256 or 512 hits: one wave per segment; 2048, 4096 or 8192 hits: one
 workgroup per segment, compiled variants), the expected hits per segment (which sets the
 segment width 2^s ns of a slice from its density), the number of persistent
-workgroups per compute unit, and the counting stage's tiles per workgroup and
-halo cap (the paper sizes its sub-slices per GPU thread, Sec. 4.1).  Each
+workgroups per compute unit, and the fold stage's tiles per workgroup and the
+window seeds it stages in LDS (the paper sizes its sub-slices per GPU thread,
+Sec. 4.1).  Each
 PMT-count class is tuned on representative slices (a held-out sample, not the
 timed workload) by timing the whole pipeline (``trig_batch`` with marshalling
-done once): first the ordering knobs, then the counting knobs with the best
+done once): first the ordering knobs, then the fold knobs with the best
 ordering.  The choice is kept in a JSON cache keyed by the class.  Correctness
 never depends on the choice: every setting gives byte-identical results.
 """
@@ -45,16 +46,16 @@ def _time_batch(ctx, slices, params, reps: int, stream=None) -> float:
     return float(np.median(ts))
 
 
-COUNT_CANDIDATES = [(g, h) for g in (1, 2, 4) for h in (256, 1024)]
-KNOBS = ("seg_cap", "seg_target", "grid_per_cu", "tile_group", "halo_cap")
+COUNT_CANDIDATES = [(g, h) for g in (1, 2, 4) for h in (1024, 4096)]
+KNOBS = ("seg_cap", "seg_target", "grid_per_cu", "tile_group", "window_cap")
 
 
 def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int = 5, stream=None, log=None,
                time_budget_s: float | None = None, count_candidates=None) -> dict:
     """Try the candidates on ``slices`` (list of (geom_id, pmt, t, q)); keep the
     fastest.  First the ordering knobs ``candidates`` (cap, target, grid per CU)
-    with the class's counting knobs, then the counting knobs ``count_candidates``
-    (tiles per workgroup, halo cap) with the best ordering.  With
+    with the class's fold knobs, then the fold knobs ``count_candidates``
+    (tiles per workgroup, window seeds in LDS) with the best ordering.  With
     ``time_budget_s`` each stage stops once that much time is spent (the
     candidates tried so far decide)."""
     cur = T.trig_tune_get(ctx, n_pmt_max)
@@ -64,7 +65,7 @@ def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int =
 
     def trial(k):
         T.trig_tune_set(ctx, n_pmt_max, k["seg_target"], k["seg_cap"], k["grid_per_cu"], k["tile_group"],
-                        k["halo_cap"])
+                        k["window_cap"])
         dt = _time_batch(ctx, slices, params, reps, stream)
         trials.append(dict(k, s=dt))
         if log:
@@ -75,20 +76,20 @@ def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int =
         if time_budget_s is not None and trials and time.perf_counter() - t_start > time_budget_s:
             break
         r = trial(dict(seg_cap=cap, seg_target=tgt, grid_per_cu=g, tile_group=cur["tile_group"],
-                       halo_cap=cur["halo_cap"]))
+                       window_cap=cur["window_cap"]))
         if best is None or r["s"] < best["s"]:
             best = r
     t_mid = time.perf_counter()
     for (tg, h) in count_candidates or COUNT_CANDIDATES:
         if time_budget_s is not None and time.perf_counter() - t_mid > time_budget_s:
             break
-        if (tg, h) == (best["tile_group"], best["halo_cap"]):
+        if (tg, h) == (best["tile_group"], best["window_cap"]):
             continue
-        r = trial(dict({k: best[k] for k in ("seg_cap", "seg_target", "grid_per_cu")}, tile_group=tg, halo_cap=h))
+        r = trial(dict({k: best[k] for k in ("seg_cap", "seg_target", "grid_per_cu")}, tile_group=tg, window_cap=h))
         if r["s"] < best["s"]:
             best = r
     T.trig_tune_set(ctx, n_pmt_max, *(best[k] for k in ("seg_target", "seg_cap", "grid_per_cu", "tile_group",
-                                                        "halo_cap")))
+                                                        "window_cap")))
     return dict(n_pmt_max=n_pmt_max, best=best, trials=trials, seconds=time.perf_counter() - t_start)
 
 
@@ -104,7 +105,7 @@ def save(path: str, results: list, device: str = "") -> None:
 def apply_one(ctx, c: dict) -> None:
     """Set one class record of a cache (n_pmt_max and the knobs) on the context."""
     T.trig_tune_set(ctx, int(c["n_pmt_max"]), int(c["seg_target"]), int(c["seg_cap"]), int(c["grid_per_cu"]),
-                    c.get("tile_group"), c.get("halo_cap"))
+                    c.get("tile_group"), c.get("window_cap"))
 
 
 def apply(ctx, path: str) -> list:

@@ -315,14 +315,14 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     total_chunks = chunk_base;
     total_tiles = tile_base;
-    // counting-kernel groups: the largest tile group and halo the slices' classes
-    // ask for, fewer tiles per group while that would leave a compute unit with
-    // less than two workgroups
+    // fold-kernel groups: the largest tile group and window capacity the slices'
+    // classes ask for, fewer tiles per group while that would leave a compute unit
+    // with less than two workgroups
     tile_group = 1;
-    halo_cap = 256;
+    window_cap = 1024;
     for (const SliceInfo &si : slices) {
         tile_group = std::max(tile_group, si.tune.tile_group);
-        halo_cap = std::max(halo_cap, si.tune.halo_cap);
+        window_cap = std::max(window_cap, si.tune.window_cap);
     }
     auto count_groups = [&](uint32_t g) {
         uint32_t tot = 0;
@@ -500,7 +500,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.x_plans = x_plans_dev;
     batch.prm = params;
     batch.tile_group = tile_group;
-    batch.halo_cap = halo_cap;
+    batch.window_cap = window_cap;
     {
         uint32_t nb_max = 0;
         for (const SliceInfo &si : slices)
@@ -921,10 +921,10 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     c->cfg.persist_per_cu = 2;
     const char *g = getenv("TRIG_GRAPHS");
     c->use_graphs = !(g && g[0] == '0');
-    // wave per segment, 3 workgroups of 4 waves per CU; counting workgroups of two
-    // tiles, with small halos for towers and wide ones for larger detectors
-    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 2, 256, 0};
-    const trig_tune block = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
+    // wave per segment, 3 workgroups of 4 waves per CU; fold workgroups of two
+    // tiles staging up to 1024 window seeds
+    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
+    const trig_tune block = tower;
     c->tunes.push_back({128u, tower});
     c->tunes.push_back({0xFFFFFFFFu, block});
     // set-up of the allocation-free entry point: this device's fixed scratch and
@@ -1132,7 +1132,7 @@ int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
         t->seg_target == 0 ||
         t->grid_per_cu == 0 || t->grid_per_cu > 16 ||
         !(t->tile_group == 1 || t->tile_group == 2 || t->tile_group == 4) ||
-        !(t->halo_cap == 256 || t->halo_cap == 1024)) {
+        !(t->window_cap == 1024 || t->window_cap == 4096)) {
         ctx_set_error(c, "bad tuning values");
         return TRIG_EINVAL;
     }

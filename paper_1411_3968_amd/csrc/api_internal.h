@@ -77,7 +77,7 @@ struct Job {
     uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
     uint32_t wave_cap = 0;            // variant of the wave-per-segment kernel (largest tuned capacity)
     uint32_t total_chunks = 0, total_tiles = 0;
-    uint32_t tile_group = 1, halo_cap = 256, total_groups = 0;   // counting-kernel launch shape
+    uint32_t tile_group = 1, window_cap = 1024, total_groups = 0;   // fold-kernel launch shape
     uint32_t *d_group_slice = nullptr;
     uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;

@@ -891,114 +891,89 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
 }
 
 
-// ------------------------------------------------------------------ k_count
-// The counting kernel of the plain rule (charge or floor-coincidence seeds,
-// causal folds, fires): one workgroup of 256 threads per group of G consecutive
-// tiles of one slice, found through the group map that k_plan writes.
-//  1. The group and up to HMAX ordered neighbours on each side (the halo, sized
-//     from the slice's mean density to span w_ns + t_floor_ns) are staged in
-//     LDS as time and pmt << 16 | floor, a hit per lane and round, so a wave's
-//     round is one 64-hit word: the charge seeds and level-0 bits of the word
-//     come from two ballots.
-//  2. Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., while any
-//     lane of the wave still has its d-th successor within t_floor_ns: a pair
-//     of two PMTs of one floor marks both hits (the successor through 64-bit LDS
-//     ORs at bit x + d).  Most hits have no neighbour that close, so a wave
-//     usually stops after a few steps.
-//  3. The stage's seeds are compacted in LDS (time order kept).
-//  4. Each wave folds 64 consecutive seeds of the group at a time: the seeds
-//     within w_ns of the first and the last of them are read in turn, the same
-//     one by every lane, and each lane counts those within min(thr, w_ns) of its
-//     own seed (eight table reads in flight).
-//  5. Wave t writes the fires of tile t of the group to the tile's slot and the
-//     tile's summary (TileAgg), as the tile-per-workgroup kernel does.
-// A group whose halo does not span the window, or whose stage holds more seeds
-// than the lists, flags its slice for the rerun with a seed mask.
-template <int G, int HMAX>
-struct CountShape {
-    static constexpr int NT = 256, NW = NT / 64;
-    static constexpr int STG = G * TILE + 2 * HMAX;   // staged ordered hits at most
-    static constexpr int U = STG / NT;                // staged hits per thread
-    static constexpr int NWD = STG / 64;              // 64-hit words of the stage
-    static constexpr int CS = STG / 4;                // seeds of a stage the lists hold
-    static constexpr size_t lds_bytes() {
-        return (size_t)STG * 4 * 2 + (size_t)CS * 4 * 2 + (size_t)NWD * 8 * 4 + (size_t)(NWD + 2) * 4 +
-               (size_t)CS * 2 * 3;
-    }
-    static_assert(STG % NT == 0 && G <= NW, "stage layout");
-    static_assert(STG <= 65535, "stage positions are 16-bit");
+// ------------------------------------------------------------------ k_seed
+// L1 seeds of the plain rule (Sec. 3 and Sec. 4.2: charge over threshold, or
+// another PMT of the same floor within t_floor_ns; with level 0 on, the hit and
+// its partner must pass it), one workgroup per ordered tile.  The tile and up to
+// SD_HS ordered neighbours on each side (whole 64-hit words, sized from the
+// slice's mean density to span t_floor_ns) are staged in LDS, a hit per lane and
+// round; the charge seeds and level-0 bits of a round's 64-hit word come from two
+// ballots.  Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., four
+// distances per step, while any lane of the wave still has a successor within
+// t_floor_ns; a pair marks both hits.  A tile whose staged neighbours do not span
+// t_floor_ns (a burst of near-equal times) searches each hit's partners on both
+// sides instead, reading past the stage from global memory.  The tile's seeds are
+// written compacted, in time order, to its seed list with their count.
+constexpr int SD_NT = 256;
+constexpr int SD_HS = 256;   // staged neighbours per side at most
+
+struct SeedShape {
+    static constexpr int NT = SD_NT;
+    static constexpr int STG = TILE + 2 * SD_HS;
+    static constexpr int U = STG / NT;
+    static constexpr int NWD = STG / 64;
+    static constexpr size_t lds_bytes() { return (size_t)STG * 4 * 2 + (size_t)NWD * 8 * 4; }
+    static_assert(STG % NT == 0 && SD_HS % 64 == 0, "stage layout");
 };
 
-template <int G, int HMAX>
-__global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
-    using Sh = CountShape<G, HMAX>;
-    constexpr int NT = Sh::NT, U = Sh::U, NWD = Sh::NWD, CS = Sh::CS;
+__global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) {
+    using Sh = SeedShape;
+    constexpr int NT = Sh::NT, U = Sh::U, NWD = Sh::NWD;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *st = (uint32_t *)smem;                    // staged t - t_min
-    uint32_t *spf = st + Sh::STG;                       // staged pmt << 16 | dense floor index
-    uint32_t *ct = spf + Sh::STG;                       // compacted seeds: time
-    uint32_t *fold = ct + CS;                           // fold of each seed of the group
-    uint64_t *qw = (uint64_t *)(fold + CS);             // charge seeds, then all seeds, per word
-    uint64_t *lw = qw + NWD;                            // level-0 pass bits per word
-    uint64_t *pw = lw + NWD;                            // floor-partner bits from far pairs per word
-    uint64_t *pin = pw + NWD;                           // floor-partner bits from the word before
-    uint32_t *wpre = (uint32_t *)(pin + NWD);           // seeds before each word (NWD + 1)
-    uint16_t *cp = (uint16_t *)(wpre + NWD + 2);        // compacted seeds: PMT
-    uint16_t *cidx = cp + CS;                           // compacted seeds: stage position
-    uint16_t *fci = cidx + CS;                          // fires of each tile: compacted index
-    uint16_t *lfl = fci + CS;                           // dense floor index of every PMT (floor_lds of them)
-    uint16_t *ltb = lfl + ((floor_lds + 1) & ~1u);      // the table bounds (b.tbnd_lds of them)
-    __shared__ uint32_t sh[Sh::NW + 1];
+    uint32_t *st = (uint32_t *)smem;            // staged t - t_min
+    uint32_t *spf = st + Sh::STG;               // staged pmt << 16 | dense floor index
+    uint64_t *qw = (uint64_t *)(spf + Sh::STG); // charge seeds, then all seeds, per word
+    uint64_t *lw = qw + NWD;                    // level-0 pass bits per word
+    uint64_t *pw = lw + NWD;                    // partner bits from pairs 64 or more apart
+    uint64_t *pin = pw + NWD;                   // partner bits from the word before
+    uint16_t *lfl = (uint16_t *)(pin + NWD);    // dense floor index of every PMT (floor_lds of them)
+    __shared__ uint32_t wpre[TILE / 64 + 1];
 
-    // XCD-aware order: workgroup b runs on XCD b % 8 and takes groups from that
-    // XCD's contiguous eighth of the list (neighbouring groups share halos in one L2)
-    const uint32_t per_xcd = (b.total_groups + 7) / 8;
+    // XCD-aware order: workgroup b runs on XCD b % 8 and takes tiles from that
+    // XCD's contiguous eighth of the list (neighbouring tiles share halos in one L2)
+    const uint32_t per_xcd = (b.total_tiles + 7) / 8;
     const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (item >= b.total_groups) return;
-    const uint32_t si = b.n_slices <= 1 ? 0u : gmem(b.group_slice)[item];
+    if (item >= b.total_tiles) return;
+    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
     const SliceDev &S = b.slices[si];
-    const uint32_t g = item - (b.n_slices <= 1 ? 0u : S.group_base);
-    const uint32_t k0 = g * (uint32_t)G;            // first tile of the group
-    if (k0 >= S.n_tiles) return;
-    Plan *Pp = b.plans + si;
-    const TRIG_GAS Plan *Pg = gmem(Pp);
+    const uint32_t k = item - tile_base_of(b, si);
+    if (k >= S.n_tiles) return;
+    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
     if (!slice_in_tail(b, Pg->state)) return;
     const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
     const TRIG_GAS uint32_t *o_pq = gmem(S.o_pq);
     const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
-    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
-    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
     const TRIG_GAS uint16_t *floor16 = gmem(S.floor16);
     TRIG_GAS uint8_t *seed_flags = gmem(S.seed_flags);
     const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
+    TRIG_GAS uint32_t *sd_t = seed_t(S) + (uint64_t)k * TILE;
+    TRIG_GAS uint32_t *sd_p = seed_p(S) + (uint64_t)k * TILE;
     const uint32_t n_pmt = S.n_pmt;
     const uint64_t n = S.n;
-    const uint32_t n_tiles = S.n_tiles;
-    const int64_t t_min = Pg->t_min;
-    const uint64_t span = (uint64_t)(Pg->t_max - t_min);
-    const uint32_t W = b.prm.w_ns;
-    const uint32_t N = b.prm.min_fold;
+    const uint64_t a = (uint64_t)k * TILE;
+    if (a >= n) {   // the one tile of an empty slice
+        if (threadIdx.x == 0) seed_n(S)[k] = 0;
+        return;
+    }
+    const uint64_t e = (a + TILE < n) ? a + TILE : n;
+    const uint64_t span = (uint64_t)(Pg->t_max - Pg->t_min);
     const int32_t tau = b.prm.t_floor_ns;
     const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
     const uint32_t q_seed = b.prm.q_seed;
     const bool L0 = b.prm.l0_n > 0;
-    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const int lane = lane_id(), w = threadIdx.x >> 6;
 
-    const uint64_t a = (uint64_t)k0 * TILE;
-    const uint64_t e = (a + (uint64_t)G * TILE < n) ? a + (uint64_t)G * TILE : n;
-    // halo: twice the mean number of hits in w_ns + t_floor_ns, plus a margin
-    const uint64_t reach = (uint64_t)W + tau_u;
-    uint64_t halo = (2ull * n * reach) / (span + 1) + 64;
-    if (halo > (uint64_t)HMAX) halo = HMAX;
-    const uint64_t sl = a > halo ? a - halo : 0;
+    // halo: twice the mean number of hits in t_floor_ns, plus 64, in whole words
+    uint64_t halo = tau < 0 ? 0ull : (2ull * n * (tau_u + 1ull)) / (span + 1) + 64;
+    halo = (halo + 63) & ~63ull;
+    if (halo > (uint64_t)SD_HS) halo = SD_HS;
+    const uint64_t sl = a >= halo ? a - halo : 0;   // (a is a multiple of TILE: sl = a - halo or 0)
     const uint64_t she = (e + halo < n) ? e + halo : n;
-    const uint32_t len = (uint32_t)(she - sl);
-    const uint32_t nwords = (len + 63) / 64;
+    const uint32_t len = (uint32_t)(she - sl), lastx = len - 1;
+    const uint32_t a_loc = (uint32_t)(a - sl), e_loc = (uint32_t)(e - sl);   // a_loc: whole words
 
-    // 1. stage: all loads of a thread in flight (positions past the stage read
-    // its last hit: no branch around a load), then the words of each round
-    const uint32_t lastx = len - 1;
+    // 1. stage: all loads of a thread in flight (positions past the stage read its
+    // last hit), then the words of each round
     uint32_t vt[U], vp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -1009,13 +984,6 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
     const bool floor_in_lds = n_pmt <= floor_lds;
     if (floor_in_lds)
         for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
-    // the table bounds of a large detector (read by the folds after the barriers below)
-    const uint32_t nbk = S.nbk;
-    const bool bounds = nbk != 0 && W <= 65535u;
-    const bool tb_in_lds = bounds && nbk * nbk <= b.tbnd_lds;
-    const TRIG_GAS uint16_t *tbnd = gmem(S.tbnd);
-    if (tb_in_lds)
-        for (uint32_t x = threadIdx.x; x < nbk * nbk; x += NT) ltb[x] = tbnd[x];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t x = u * NT + threadIdx.x;
@@ -1046,38 +1014,32 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
         spf[x] = vp[u];
     }
     __syncthreads();
-    const uint32_t ta = st[a - sl], te = st[e - 1 - sl];
-    // the stage spans the window of every seed of the group when the halo reaches
-    // past w_ns + t_floor_ns on both sides (or the slice ends there)
-    const bool cover_l = sl == 0 || (uint64_t)st[0] + reach < (uint64_t)ta;
-    const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + reach;
-    const bool covered = cover_l && cover_r;
-    // the stage positions that matter: seeds within w_ns of the group's hits
-    // ([p_l, p_r)) and, for their floor partners, the hits within t_floor_ns
-    // before them (from p_lp); the halo is sized with a margin, so the rest of it
-    // is skipped
-    auto first_ge = [&](uint64_t tv) -> uint32_t {   // first stage position with time >= tv
-        uint32_t lo = 0, hi = len;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if ((uint64_t)st[mid] < tv) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-    };
-    const uint32_t p_lp = (uint64_t)ta >= reach ? first_ge((uint64_t)ta - reach) : 0u;
-    const uint32_t p_l = ta >= W ? first_ge((uint64_t)ta - W) : 0u;
-    const uint32_t p_r = first_ge((uint64_t)te + W + 1);
+    const uint32_t ta = st[a_loc], te = st[e_loc - 1];
+    // the stage spans t_floor_ns around the tile on both sides (or the slice ends there)
+    const bool cover_l = sl == 0 || (uint64_t)st[0] + tau_u < (uint64_t)ta;
+    const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + tau_u;
 
-    // 2. floor-coincidence pairs (x, x + d) within the stage, for x in [p_lp, p_r).
-    // A pair found marks x (the word's own bits) and x + d: within the word or,
-    // for d < 64, in the next word's incoming bits (written by this wave alone);
-    // pairs 64 or more positions apart (a burst of equal times) are ORed into the
-    // far bits.  Every value is computed in every lane (bitwise operators, clamped
-    // reads), so the loop branches only on its exit and on a pair found.
-    if (covered && tau >= 0) {
+    if (tau >= 0 && cover_l && cover_r) {
+        // 2. floor-coincidence pairs (x, x + d) for x from the first hit within
+        // t_floor_ns before the tile to the tile's end.  A pair found marks x (the
+        // word's own bits) and x + d: within the word or, for d < 64, in the next
+        // word's incoming bits (written by this wave alone); pairs 64 or more
+        // positions apart (equal times) are ORed into the far bits.  Every value is
+        // computed in every lane (bitwise operators, clamped reads), so the loop
+        // branches only on its exit and on a pair found.
+        uint32_t p_lp;
+        {
+            uint32_t lo = 0, hi = a_loc;   // first stage position with time >= ta - tau
+            const uint64_t tv = (uint64_t)ta >= tau_u ? (uint64_t)ta - tau_u : 0ull;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((uint64_t)st[mid] < tv) lo = mid + 1; else hi = mid;
+            }
+            p_lp = lo;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if ((uint32_t)(u * NT + w * 64) >= p_r) break;   // (wave-uniform)
+            if ((uint32_t)(u * NT + w * 64) >= e_loc) break;   // (wave-uniform)
             if ((uint32_t)(u * NT + w * 64 + 64) <= p_lp) continue;
             const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
             const uint32_t x = u * NT + threadIdx.x;
@@ -1085,28 +1047,26 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
             const uint32_t t = vt[u], f = vp[u];
             const bool l0x = ((lw[wd] >> lane) & 1ull) != 0;
             uint64_t own = 0, fwd0 = 0, fwd1 = 0;
-            // four distances per step, their reads issued together; times are
-            // ordered, so once no lane is near at distance d none is further on
             constexpr int DU = 4;
             for (uint32_t d0 = 1;; d0 += DU) {
                 uint32_t ty[DU], gy[DU];
 #pragma unroll
-                for (int k = 0; k < DU; ++k) {
-                    const uint32_t yc = min(x + d0 + k, lastx);
-                    ty[k] = st[yc];
-                    gy[k] = spf[yc];
+                for (int kk = 0; kk < DU; ++kk) {
+                    const uint32_t yc = min(x + d0 + kk, lastx);
+                    ty[kk] = st[yc];
+                    gy[kk] = spf[yc];
                 }
                 bool near = false;
 #pragma unroll
-                for (int k = 0; k < DU; ++k) {
-                    const uint32_t d = d0 + k, y = x + d;
-                    near = in0 & (y < len) & (ty[k] - t <= tau_u);
+                for (int kk = 0; kk < DU; ++kk) {
+                    const uint32_t d = d0 + kk, y = x + d;
+                    near = in0 & (y < len) & (ty[kk] - t <= tau_u);
                     bool l0y = true;
                     if (L0) {
                         const uint32_t yc = min(y, lastx);
                         l0y = ((lw[yc >> 6] >> (yc & 63)) & 1ull) != 0;
                     }
-                    const bool pr = near & (((gy[k] ^ f) & 0xFFFFu) == 0u) & ((gy[k] >> 16) != (f >> 16)) & l0x & l0y;
+                    const bool pr = near & (((gy[kk] ^ f) & 0xFFFFu) == 0u) & ((gy[kk] >> 16) != (f >> 16)) & l0x & l0y;
                     const uint64_t M = __ballot(pr);
                     own |= M;
                     if (M) {
@@ -1117,7 +1077,8 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
                             const uint32_t sft = d & 63, w0 = wd + (d >> 6);
                             atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << sft));
                             const uint64_t spill = sft ? (M >> (64 - sft)) : 0ull;
-                            if (spill) atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                            if (spill && w0 + 1 < (uint32_t)NWD)
+                                atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
                         }
                     }
                 }
@@ -1128,241 +1089,428 @@ __global__ __launch_bounds__(256) void k_count(BatchDev b, uint32_t floor_lds) {
                 if (wd + 1 < (uint32_t)NWD) pin[wd + 1] = fwd1;
             }
         }
+    } else if (tau >= 0) {
+        // the stage does not span t_floor_ns: each hit of the tile searches its
+        // partners on both sides, past the stage in global memory
+        auto T_at = [&](uint64_t m) -> uint32_t { return (m >= sl && m < she) ? st[m - sl] : o_t[m]; };
+        auto F_at = [&](uint64_t m) -> uint32_t {
+            if (m >= sl && m < she) return spf[m - sl];
+            const uint32_t p = o_pq[m] >> 16;
+            return (p << 16) | (uint32_t)floor16[p];
+        };
+        auto l0_at = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
+        for (uint32_t x0 = a_loc + (uint32_t)w * 64; x0 < e_loc; x0 += NT) {
+            const uint32_t x = x0 + (uint32_t)lane;
+            bool found = false;
+            if (x < e_loc && l0_at(sl + x)) {
+                const uint64_t j = sl + x;
+                const uint32_t t = st[x], f = spf[x];
+                auto partner = [&](uint64_t m) {
+                    const uint32_t g = F_at(m);
+                    return ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0_at(m);
+                };
+                for (uint64_t m = j; m > 0 && !found;) {
+                    --m;
+                    if (t - T_at(m) > tau_u) break;
+                    found = partner(m);
+                }
+                for (uint64_t m = j + 1; m < n && !found; ++m) {
+                    if (T_at(m) - t > tau_u) break;
+                    found = partner(m);
+                }
+            }
+            const uint64_t M = __ballot(found);
+            if (lane == 0) qw[x0 >> 6] |= M;
+        }
     }
     __syncthreads();
 
-    // 3. seed words (the seeds in [p_l, p_r) only: no other can be within w_ns
-    // of the group's seeds), their prefix, and the compacted seeds
-    uint32_t total = 0;
-    {
+    // 3. the tile's seed words, their prefix, and the compacted list
+    if (w == 0) {
+        const uint32_t i = (uint32_t)lane;
+        const uint32_t b0 = a_loc + i * 64;
         uint64_t sw = 0;
-        if (threadIdx.x < nwords) {
-            const uint32_t b0 = threadIdx.x * 64;
-            const uint32_t lo = p_l > b0 ? min(p_l - b0, 64u) : 0u;
-            const uint32_t hi = p_r > b0 ? min(p_r - b0, 64u) : 0u;
-            const uint64_t keep = (hi > lo) ? ((hi == 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull)) : 0ull;
-            sw = (qw[threadIdx.x] | pin[threadIdx.x] | pw[threadIdx.x]) & keep;
+        if (b0 < e_loc) {
+            const uint32_t hi = min(e_loc - b0, 64u);
+            const uint64_t keep = hi == 64 ? ~0ull : ((1ull << hi) - 1ull);
+            sw = (qw[b0 >> 6] | pin[b0 >> 6] | pw[b0 >> 6]) & keep;
         }
-        static_assert(NWD <= NT, "one word per thread");
-        const uint32_t ex = block_excl_scan<NT>((uint32_t)__popcll(sw), total, sh);
-        if (threadIdx.x < nwords) {
-            qw[threadIdx.x] = sw;
-            wpre[threadIdx.x] = ex;
+        const uint32_t c = (uint32_t)__popcll(sw);
+        const uint32_t inc = wave_incl_scan(c);
+        if (i < TILE / 64) {
+            qw[(a_loc >> 6) + i] = sw;
+            wpre[i] = inc - c;
         }
-        if (threadIdx.x == 0) wpre[nwords] = total;
+        if (i == TILE / 64 - 1) {
+            wpre[TILE / 64] = inc;
+            seed_n(S)[k] = inc;
+        }
     }
     __syncthreads();
-    // seeds before stage position x (x <= len)
-    auto seeds_before = [&](uint32_t x) -> uint32_t {
-        const uint32_t wd = x >> 6, bit = x & 63;
-        if (wd >= nwords) return total;
-        return wpre[wd] + (bit ? (uint32_t)__popcll(qw[wd] & (~0ull >> (64 - bit))) : 0u);
-    };
-    const bool fits = total <= (uint32_t)CS;
-    const bool ok = covered && fits;
-    if (!ok && threadIdx.x == 0) atomicOr(&Pp->dense, 1u);   // rerun with a seed mask
-    const uint32_t ca = ok ? seeds_before((uint32_t)(a - sl)) : 0u;
-    const uint32_t cb = ok ? seeds_before((uint32_t)(e - sl)) : 0u;
-    if (ok) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+    for (int r = 0; r < TILE / NT; ++r) {
+        const uint32_t y = r * NT + threadIdx.x;   // position in the tile
+        const uint32_t x = a_loc + y;
+        const uint64_t wv = qw[x >> 6];
+        const bool s = x < e_loc && ((wv >> (y & 63)) & 1ull);
+        if (s) {
+            const uint32_t at = wpre[y >> 6] + (uint32_t)__popcll(wv & ((1ull << (y & 63)) - 1ull));
+            sd_t[at] = st[x];
+            sd_p[at] = (spf[x] & 0xFFFF0000u) | y;
+        }
+        if (seed_flags && x < e_loc) seed_flags[o_idx[a + y]] = (uint8_t)s;
+    }
+}
+
+hipError_t launch_seed(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
+    const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
+    const size_t shm = SeedShape::lds_bytes() + (((floor_lds + 1) & ~1u) * 2);
+    static const hipError_t attr = hipFuncSetAttribute(
+        (const void *)k_seed, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(SeedShape::lds_bytes() + FLOOR_LDS_MAX * 2 + 4));
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL(k_seed, dim3(((b.total_tiles + 7) / 8) * 8), dim3(SD_NT), shm, s, b, floor_lds);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ k_fold
+// Causal folds of the plain rule's seeds (Sec. 3: the Cherenkov hits of one muon
+// are correlated within min(thr, w_ns)) and the fires: one workgroup of 256
+// threads per group of G consecutive tiles of one slice (the group map written by
+// k_plan), a wave per tile.  The window of the group's seeds reaches the tiles
+// whose hits lie within w_ns of them (found from the tile boundaries' times); the
+// seed lists of those tiles, concatenated, are in time order.  Up to CAP of them
+// (from at most FD_TMAX tiles) are staged in LDS as time and PMT; a larger window
+// is read from the lists in global memory.  A lane per seed of the tile counts,
+// over its own stretch of the window (bounds by fixed-count binary searches), the
+// other seeds within min(thr, w_ns), eight table reads in flight; for large
+// detectors the pair of the two PMTs' 32-PMT blocks has a lower and an upper bound
+// of thr (16 ns units, staged in LDS) that decide most pairs, and the table is
+// read only for the rest.  Each round of 64 seeds then writes its fires to the
+// tile's slot and adds them to the tile's summary (TileAgg).
+constexpr int FD_NT = 256;
+constexpr int FD_TMAX = 64;   // window tiles staged at most
+
+template <int CAP>
+struct FoldShape {
+    static constexpr size_t lds_bytes() { return (size_t)CAP * 4 + (size_t)CAP * 2; }
+};
+
+template <int G, int CAP>
+__global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
+    constexpr int NT = FD_NT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *lt = (uint32_t *)smem;             // window seeds: time
+    uint16_t *lp = (uint16_t *)(lt + CAP);       // window seeds: PMT
+    uint16_t *ltb = lp + CAP;                    // the table bounds (b.tbnd_lds of them)
+    __shared__ uint32_t woff[FD_TMAX + 1];       // window seeds before each window tile
+    __shared__ uint32_t s_win[4];                // first and end window tile, seeds, staged
+
+    const uint32_t per_xcd = (b.total_groups + 7) / 8;
+    const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (item >= b.total_groups) return;
+    const uint32_t si = b.n_slices <= 1 ? 0u : gmem(b.group_slice)[item];
+    const SliceDev &S = b.slices[si];
+    const uint32_t g = item - (b.n_slices <= 1 ? 0u : S.group_base);
+    const uint32_t k0 = g * (uint32_t)G;
+    const uint32_t n_tiles = S.n_tiles;
+    if (k0 >= n_tiles) return;
+    const uint32_t k1 = (k0 + G < n_tiles) ? k0 + G : n_tiles;
+    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
+    if (!slice_in_tail(b, Pg->state)) return;
+    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
+    const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
+    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
+    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
+    const TRIG_GAS uint32_t *sdt = seed_t(S);
+    const TRIG_GAS uint32_t *sdp = seed_p(S);
+    const TRIG_GAS uint32_t *sdn = seed_n(S);
+    const uint32_t n_pmt = S.n_pmt;
+    const uint64_t n = S.n;
+    const uint32_t W = b.prm.w_ns;
+    const uint32_t N = b.prm.min_fold;
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t nbk = S.nbk;
+    const bool bounds = nbk != 0 && W <= 65535u;
+    const bool tb_in_lds = bounds && nbk * nbk <= b.tbnd_lds;
+    const TRIG_GAS uint16_t *tbnd = gmem(S.tbnd);
+    if (tb_in_lds)
+        for (uint32_t x = threadIdx.x; x < nbk * nbk; x += NT) ltb[x] = tbnd[x];
+
+    // 1. the window: the group's first and last seed times, then the tiles whose
+    // hits lie within w_ns of them (tile times are ordered, so each walk stops at
+    // the first tile outside)
+    if (w == 0) {
+        const uint32_t c = (lane < G && k0 + (uint32_t)lane < k1) ? sdn[k0 + lane] : 0u;
+        const uint64_t ne = __ballot(c > 0);
+        uint32_t jl = k0, jr = k1;
+        if (ne) {
+            const int lf = __ffsll((unsigned long long)ne) - 1, ll = 63 - __clzll((long long)ne);
+            const uint32_t t_first = sdt[(uint64_t)(k0 + lf) * TILE];
+            const uint32_t c_last = lane_read(c, ll);
+            const uint32_t t_last = sdt[(uint64_t)(k0 + ll) * TILE + c_last - 1];
+            const uint32_t t_lo = t_first > W ? t_first - W : 0u;
+            const uint64_t t_hi = (uint64_t)t_last + W;
+            for (;;) {   // to the left: tiles whose last hit is at or after t_lo
+                const bool valid = jl > (uint32_t)lane;
+                const uint32_t j = jl - 1 - (uint32_t)lane;
+                const uint64_t endj = valid ? (((uint64_t)j + 1) * TILE < n ? ((uint64_t)j + 1) * TILE : n) : 1;
+                const bool need = valid && o_t[endj - 1] >= t_lo;
+                const uint64_t M = __ballot(need);
+                const uint32_t m = M == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~M) - 1u;
+                jl -= m;
+                if (m < 64) break;
+            }
+            for (;;) {   // to the right: tiles whose first hit is at or before t_hi
+                const uint32_t j = jr + (uint32_t)lane;
+                const bool valid = j < n_tiles;
+                const bool need = valid && (uint64_t)o_t[valid ? (uint64_t)j * TILE : 0] <= t_hi;
+                const uint64_t M = __ballot(need);
+                const uint32_t m = M == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~M) - 1u;
+                jr += m;
+                if (m < 64) break;
+            }
+        }
+        const uint32_t nt = jr - jl;
+        uint32_t tot = 0;
+        if (nt <= (uint32_t)FD_TMAX) {
+            const uint32_t cj = (uint32_t)lane < nt ? sdn[jl + lane] : 0u;
+            const uint32_t inc = wave_incl_scan(cj);
+            if ((uint32_t)lane < nt) woff[lane] = inc - cj;
+            tot = lane_read(inc, 63);
+            if (lane == 0) woff[nt] = tot;
+        }
+        if (lane == 0) {
+            s_win[0] = jl;
+            s_win[1] = jr;
+            s_win[2] = tot;
+            s_win[3] = (ne != 0 && nt <= (uint32_t)FD_TMAX && tot <= (uint32_t)CAP) ? 1u : 0u;
+        }
+    }
+    __syncthreads();
+    const uint32_t jl = s_win[0], jr = s_win[1], tot = s_win[2];
+    const bool staged = s_win[3] != 0;
+    const uint32_t nt = jr - jl;
+
+    // 2. stage the window's seeds (all loads of a thread in flight)
+    if (staged) {
+        constexpr int UF = CAP / NT;
+        uint32_t vt[UF], vp[UF];
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
             const uint32_t x = u * NT + threadIdx.x;
-            if (x < len && ((qw[x >> 6] >> (x & 63)) & 1ull)) {
-                const uint32_t r = seeds_before(x);
-                ct[r] = vt[u];
-                cp[r] = (uint16_t)(vp[u] >> 16);
-                cidx[r] = (uint16_t)x;
+            if (x < tot) {
+                uint32_t lo = 0, hi = nt;   // window tile of x: the last with woff <= x
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (woff[mid] <= x) lo = mid; else hi = mid;
+                }
+                const uint64_t at = (uint64_t)(jl + lo) * TILE + (x - woff[lo]);
+                vt[u] = sdt[at];
+                vp[u] = sdp[at];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UF; ++u) {
+            const uint32_t x = u * NT + threadIdx.x;
+            if (x < tot) {
+                lt[x] = vt[u];
+                lp[x] = (uint16_t)(vp[u] >> 16);
             }
         }
     }
     __syncthreads();
 
-    // 4. causal folds of the group's seeds: a lane per seed, each over its own
-    // window of compacted seeds (bounds by fixed-count binary searches), CB table
-    // reads in flight per lane and round
-    if (ok) {
-        const bool t16 = W <= 65535u;
-        uint32_t top = 1;   // the largest power of two <= total
-        while (top * 2 <= total) top *= 2;
-        constexpr int CB = 8;
-        for (uint32_t c0 = ca + (uint32_t)w * 64; c0 < cb; c0 += NT) {
-            const uint32_t i = c0 + (uint32_t)lane;
-            const bool vi = i < cb;
-            const uint32_t ic = vi ? i : cb - 1;
-            const uint32_t ti = ct[ic];
-            const uint64_t row = (uint64_t)cp[ic] * n_pmt;
-            const uint32_t t_lo = ti > W ? ti - W : 0u;
-            const uint64_t t_hi = (uint64_t)ti + W;
-            uint32_t jl = 0, jr = 0;   // seeds with time < t_lo, seeds with time <= t_hi
-            for (uint32_t step = top; step; step >>= 1) {
-                const uint32_t ml = jl + step, mr = jr + step;
-                if (ml <= total && ct[ml - 1] < t_lo) jl = ml;
-                if (mr <= total && (uint64_t)ct[mr - 1] <= t_hi) jr = mr;
-            }
-            if (!vi) jr = jl;
-            uint32_t c = 0;
+    // 3. folds and fires of tile k0 + w, by wave w, 64 seeds per round
+    if (w >= G) return;
+    const uint32_t kt = k0 + (uint32_t)w;
+    if (kt >= k1) return;
+    const uint32_t cnt = sdn[kt];
+    const uint32_t own0 = staged ? woff[kt - jl] : 0u;   // the tile's first seed in the window
+    TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)kt * TILE;
+    const bool t16 = W <= 65535u;
+    uint32_t top = 1;   // the largest power of two <= tot
+    while (top * 2 <= tot) top *= 2;
+    constexpr int CB = 8;
+
+    // fold of one seed (time ti, PMT pi, window index self) over window entries
+    // [jlo, jhi) read through T_at / P_at
+    auto count_range = [&](uint32_t ti, uint32_t pi, uint32_t jlo, uint32_t jhi, uint32_t self, auto T_at,
+                           auto P_at) -> uint32_t {
+        const uint64_t row = (uint64_t)pi * n_pmt;
+        const uint32_t brow = (pi >> TBND_SHIFT) * nbk;
+        uint32_t c = 0;
+        for (uint32_t j0 = jlo;; j0 += CB) {
+            if (!__ballot(j0 < jhi)) break;
+            uint32_t dd[CB], lim[CB];
             if (bounds) {
-                // large tables: the block-pair bounds decide most pairs (min(thr, W)
-                // at least their lower bound: counted; above their upper bound: not),
-                // the table is read only for the pairs in between
-                const uint32_t brow = ((uint32_t)cp[ic] >> TBND_SHIFT) * nbk;
-                for (uint32_t j0 = jl;; j0 += CB) {
-                    if (!__ballot(j0 < jr)) break;
-                    uint32_t dd[CB], bb[CB], pj[CB];
+                uint32_t bb[CB], pj[CB];
 #pragma unroll
-                    for (int k = 0; k < CB; ++k) {
-                        const uint32_t j = j0 + k;
-                        dd[k] = 0xFFFFFFFFu;
-                        bb[k] = 0;
-                        pj[k] = 0;
-                        if (j < jr && j != i) {
-                            const uint32_t tj = ct[j];
-                            const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                            if (dt <= W) {
-                                pj[k] = cp[j];
-                                const uint32_t bx = brow + (pj[k] >> TBND_SHIFT);
-                                bb[k] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
-                                dd[k] = dt;
-                            }
+                for (int kk = 0; kk < CB; ++kk) {
+                    const uint32_t j = j0 + kk;
+                    dd[kk] = 0xFFFFFFFFu;
+                    bb[kk] = 0;
+                    pj[kk] = 0;
+                    if (j < jhi && j != self) {
+                        const uint32_t tj = T_at(j);
+                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                        if (dt <= W) {
+                            pj[kk] = P_at(j);
+                            const uint32_t bx = brow + (pj[kk] >> TBND_SHIFT);
+                            bb[kk] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
+                            dd[kk] = dt;
                         }
                     }
-                    uint32_t lim[CB];
+                }
 #pragma unroll
-                    for (int k = 0; k < CB; ++k) {
-                        const uint32_t hb = bb[k] >> 8;
-                        const uint32_t mn = min((bb[k] & 0xFFu) * 16u, W), mx = hb == 255u ? W : min(hb * 16u, W);
-                        lim[k] = dd[k] <= mn ? W : 0u;
-                        if (dd[k] != 0xFFFFFFFFu && dd[k] > mn && dd[k] <= mx) lim[k] = (uint32_t)thr16[row + pj[k]];
-                    }
-#pragma unroll
-                    for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
+                for (int kk = 0; kk < CB; ++kk) {
+                    const uint32_t hb = bb[kk] >> 8;
+                    const uint32_t mn = min((bb[kk] & 0xFFu) * 16u, W), mx = hb == 255u ? W : min(hb * 16u, W);
+                    lim[kk] = dd[kk] <= mn ? W : 0u;
+                    if (dd[kk] != 0xFFFFFFFFu && dd[kk] > mn && dd[kk] <= mx) lim[kk] = (uint32_t)thr16[row + pj[kk]];
                 }
             } else {
-                for (uint32_t j0 = jl;; j0 += CB) {
-                    if (!__ballot(j0 < jr)) break;
-                    uint32_t dd[CB], lim[CB];
 #pragma unroll
-                    for (int k = 0; k < CB; ++k) {
-                        const uint32_t j = j0 + k;
-                        dd[k] = 0xFFFFFFFFu;
-                        lim[k] = 0;
-                        if (j < jr && j != i) {
-                            const uint32_t tj = ct[j];
-                            const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                            if (dt <= W) {
-                                const uint64_t x = row + cp[j];
-                                lim[k] = t16 ? (uint32_t)thr16[x] : thr32[x];
-                                dd[k] = dt;
-                            }
+                for (int kk = 0; kk < CB; ++kk) {
+                    const uint32_t j = j0 + kk;
+                    dd[kk] = 0xFFFFFFFFu;
+                    lim[kk] = 0;
+                    if (j < jhi && j != self) {
+                        const uint32_t tj = T_at(j);
+                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                        if (dt <= W) {
+                            const uint64_t x = row + P_at(j);
+                            lim[kk] = t16 ? (uint32_t)thr16[x] : thr32[x];
+                            dd[kk] = dt;
                         }
                     }
-#pragma unroll
-                    for (int k = 0; k < CB; ++k) c += dd[k] <= (lim[k] < W ? lim[k] : W);
                 }
             }
-            if (vi) fold[i - ca] = c + 1;
+#pragma unroll
+            for (int kk = 0; kk < CB; ++kk) c += dd[kk] <= (lim[kk] < W ? lim[kk] : W);
         }
-        if (seed_flags) {
-            for (uint64_t j = a + threadIdx.x; j < e; j += NT) {
-                const uint32_t x = (uint32_t)(j - sl);
-                seed_flags[o_idx[j]] = (uint8_t)((qw[x >> 6] >> (x & 63)) & 1ull);
+        return c;
+    };
+
+    TileAgg A = agg_empty();
+    A.S = cnt;
+    uint32_t nf = 0, prev_t = 0, first_int = NO_START, last_int = NO_START, m_head = 0, m_tail = 0;
+    for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
+        const uint32_t r = r0 + (uint32_t)lane;
+        const bool v = r < cnt;
+        const uint32_t rc = v ? r : cnt - 1;
+        const uint32_t ti = sdt[(uint64_t)kt * TILE + rc];
+        const uint32_t sp = sdp[(uint64_t)kt * TILE + rc];
+        const uint32_t pi = sp >> 16;
+        const uint32_t t_lo = ti > W ? ti - W : 0u;
+        const uint64_t t_hi = (uint64_t)ti + W;
+        uint32_t c = 0;
+        if (staged) {
+            uint32_t jlo = 0, jhi = 0;   // window seeds with time < t_lo, with time <= t_hi
+            for (uint32_t step = top; step; step >>= 1) {
+                const uint32_t ml = jlo + step, mr = jhi + step;
+                if (ml <= tot && lt[ml - 1] < t_lo) jlo = ml;
+                if (mr <= tot && (uint64_t)lt[mr - 1] <= t_hi) jhi = mr;
+            }
+            if (!v) jhi = jlo;
+            c = count_range(ti, pi, jlo, jhi, own0 + r, [&](uint32_t j) { return lt[j]; },
+                            [&](uint32_t j) { return (uint32_t)lp[j]; });
+        } else {
+            // the window tile by tile from the lists in global memory
+            for (uint32_t jj = jl; jj < jr; ++jj) {
+                const uint32_t cj = sdn[jj];
+                const TRIG_GAS uint32_t *tj = sdt + (uint64_t)jj * TILE;
+                const TRIG_GAS uint32_t *pj = sdp + (uint64_t)jj * TILE;
+                uint32_t jlo = 0, jhi = cj;   // first with time >= t_lo, first with time > t_hi
+                {
+                    uint32_t lo = 0, hi = cj;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (tj[mid] < t_lo) lo = mid + 1; else hi = mid;
+                    }
+                    jlo = lo;
+                    hi = cj;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if ((uint64_t)tj[mid] <= t_hi) lo = mid + 1; else hi = mid;
+                    }
+                    jhi = v ? lo : jlo;
+                }
+                c += count_range(ti, pi, jlo, jhi, jj == kt ? r : 0xFFFFFFFFu, [&](uint32_t j) { return tj[j]; },
+                                 [&](uint32_t j) { return pj[j] >> 16; });
             }
         }
-    }
-    __syncthreads();
-
-    // 5. fires and summary of tile k0 + w, by wave w
-    if (w >= G) return;
-    const uint32_t tt = k0 + (uint32_t)w;
-    if (tt >= n_tiles) return;
-    const uint64_t ta0 = (uint64_t)tt * TILE;
-    const uint64_t te0 = (ta0 + TILE < n) ? ta0 + TILE : n;
-    const uint32_t cs = ok ? seeds_before((uint32_t)(ta0 - sl)) : 0u;
-    const uint32_t ce = ok ? seeds_before((uint32_t)(te0 - sl)) : 0u;
-    TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)tt * TILE;
-    uint16_t *tf = fci + (cs - ca);   // this tile's fires, as compacted indices
-    uint32_t nf = 0;
-    for (uint32_t r0 = cs; r0 < ce; r0 += 64) {
-        const uint32_t i = r0 + (uint32_t)lane;
-        const bool f = i < ce && fold[i - ca] >= N;
+        const uint32_t fd = c + 1;
+        const bool f = v && fd >= N;
         const uint64_t M = __ballot(f);
+        const uint32_t below = (uint32_t)__popcll(M & ((1ull << lane) - 1ull));
         if (f) {
-            const uint32_t pos = nf + (uint32_t)__popcll(M & ((1ull << lane) - 1ull));
-            tf[pos] = (uint16_t)i;
             FireRec fr;
-            fr.t = ct[i];
-            fr.hit = o_idx[sl + cidx[i]];
-            fr.fold = fold[i - ca];
-            fr.pmt = cp[i];
-            gstore(slot + pos, fr);
+            fr.t = ti;
+            fr.hit = o_idx[(uint64_t)kt * TILE + (sp & 0xFFFFu)];
+            fr.fold = fd;
+            fr.pmt = pi;
+            gstore(slot + nf + below, fr);
         }
-        nf += (uint32_t)__popcll(M);
-    }
-    wave_lds_sync();
-    TileAgg A = agg_empty();
-    A.S = ce - cs;
-    A.F = nf;
-    uint32_t prev_t = 0, first_int = NO_START, last_int = NO_START, m_head = 0, m_tail = 0;
-    for (uint32_t r0 = 0; r0 < nf; r0 += 64) {
-        const uint32_t r = r0 + (uint32_t)lane;
-        const bool v = r < nf;
-        uint32_t t = 0, fd = 0;
-        if (v) {
-            const uint32_t ci = tf[r];
-            t = ct[ci];
-            fd = fold[ci - ca];
-        }
-        // the lane move runs in every lane (under a select lane 1 would read the fill value)
-        const uint32_t t_below = wave_shr1(t, 0u);
-        const uint32_t tp = lane == 0 ? prev_t : t_below;
-        const bool is_int = v && r > 0 && (uint64_t)(t - tp) > twoH;
+        // the summary over this round's fires: the previous fire of each is the
+        // latest fire below it in the round (times are ordered: a max-scan), or the
+        // last fire of the rounds before
+        const uint32_t incl = wave_incl_max_u32(f ? ti + 1u : 0u);   // (times < 2^31: ti + 1 does not wrap)
+        const uint32_t excl = wave_shr1(incl, 0u);
+        const bool has_prev = (nf + below) > 0;
+        const uint32_t tp = excl ? excl - 1u : prev_t;
+        const bool is_int = f && has_prev && (uint64_t)(ti - tp) > twoH;
         const uint64_t ib = __ballot(is_int);
-        if (r0 == 0) A.first_t = lane_read(t, 0);
-        prev_t = lane_read(t, 63);
+        if (M) {
+            if (nf == 0) A.first_t = lane_read(ti, __ffsll((unsigned long long)M) - 1);
+            const int lastf = 63 - __clzll((long long)M);
+            prev_t = lane_read(ti, lastf);
+            A.last_t = prev_t;
+        }
         if (ib) {
             const int lo = __ffsll((unsigned long long)ib) - 1;
             const int hi = 63 - __clzll((long long)ib);
             if (first_int == NO_START) {
-                first_int = r0 + lo;
-                m_head = umax(m_head, wave_max_u32(v && lane < lo ? fd : 0u));
+                first_int = nf + (uint32_t)__popcll(M & ((1ull << lo) - 1ull));
+                m_head = umax(m_head, wave_max_all(f && lane < lo ? fd : 0u));
             }
-            last_int = r0 + hi;
-            m_tail = wave_max_u32(v && lane >= hi ? fd : 0u);
-            A.ls_t = lane_read(t, hi);
+            last_int = nf + (uint32_t)__popcll(M & ((1ull << hi) - 1ull));
+            m_tail = wave_max_all(f && lane >= hi ? fd : 0u);
+            A.ls_t = lane_read(ti, hi);
         } else {
-            const uint32_t mx = wave_max_u32(v ? fd : 0u);
+            const uint32_t mx = wave_max_all(f ? fd : 0u);
             if (first_int == NO_START) m_head = umax(m_head, mx);
             m_tail = umax(m_tail, mx);
         }
         A.E_int += (uint32_t)__popcll(ib);
+        nf += (uint32_t)__popcll(M);
     }
-    if (nf) A.last_t = ct[tf[nf - 1]];
+    A.F = nf;
     A.m_tail = m_tail;
     A.m_head = first_int == NO_START ? m_tail : m_head;
     A.ls_idx = last_int;
     if (last_int == NO_START) A.ls_t = 0;
-    if (lane == 0) gstore(&gmem(S.tstat)[tt].agg, A);
+    if (lane == 0) gstore(&gmem(S.tstat)[kt].agg, A);
 }
 
-template <int G, int HMAX>
-hipError_t launch_count_v(const BatchDev &b, uint32_t floor_lds, hipStream_t s) {
-    using Sh = CountShape<G, HMAX>;
-    const size_t shm = Sh::lds_bytes() + (((floor_lds + 1) & ~1u) * 2) + (((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15);
+template <int G, int CAP>
+hipError_t launch_fold_v(const BatchDev &b, hipStream_t s) {
+    const size_t shm = FoldShape<CAP>::lds_bytes() + (((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15);
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_count<G, HMAX>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(Sh::lds_bytes() + FLOOR_LDS_MAX * 2 + TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16));
+        (const void *)k_fold<G, CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)(FoldShape<CAP>::lds_bytes() + TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16));
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_count<G, HMAX>), dim3(((b.total_groups + 7) / 8) * 8), dim3(256), shm, s, b, floor_lds);
+    hipLaunchKernelGGL((k_fold<G, CAP>), dim3(((b.total_groups + 7) / 8) * 8), dim3(FD_NT), shm, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_count(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
-    const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
-    const bool wide = b.halo_cap > 256;
+hipError_t launch_fold(const BatchDev &b, hipStream_t s) {
+    const bool wide = b.window_cap > 1024;
     switch (b.tile_group) {
-    case 4: return wide ? launch_count_v<4, 1024>(b, floor_lds, s) : launch_count_v<4, 256>(b, floor_lds, s);
-    case 2: return wide ? launch_count_v<2, 1024>(b, floor_lds, s) : launch_count_v<2, 256>(b, floor_lds, s);
-    default: return wide ? launch_count_v<1, 1024>(b, floor_lds, s) : launch_count_v<1, 256>(b, floor_lds, s);
+    case 4: return wide ? launch_fold_v<4, 4096>(b, s) : launch_fold_v<4, 1024>(b, s);
+    case 2: return wide ? launch_fold_v<2, 4096>(b, s) : launch_fold_v<2, 1024>(b, s);
+    default: return wide ? launch_fold_v<1, 4096>(b, s) : launch_fold_v<1, 1024>(b, s);
     }
 }
 
@@ -1378,16 +1526,26 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
         hipError_t e0 = trig_launch_l0(b, s, mark, mark_ctx);
         if (e0 != hipSuccess) return e0;
     }
-    // the seed menu (SC, AFC, their combination) and the dense rerun run in
-    // variants of the tile-per-workgroup kernel; the plain rule in the counting kernel
+    // the seed menu (SC, AFC, their combination) and its dense rerun run in
+    // variants of the tile-per-workgroup kernel; the plain rule in the seed and
+    // fold kernels
     const bool menu = b.prm.t_adj_ns >= 0 || b.prm.t_afloor_ns >= 0 || b.prm.seed_mode != 0;
-    const char *kname = (dense || menu) ? "k_tile" : "k_count";
-    TRIG_MARK(kname, 0);
-    hipError_t e = dense ? launch_tile<HALO_BIG, true, false>(b, max_pmt, n_cu, s)
-                 : menu  ? launch_tile<HALO_SMALL, false, true>(b, max_pmt, n_cu, s)
-                         : launch_count(b, max_pmt, s);
-    if (e != hipSuccess) return e;
-    TRIG_MARK(kname, 1);
+    if (dense || menu) {
+        TRIG_MARK("k_tile", 0);
+        hipError_t e = dense ? launch_tile<HALO_BIG, true, false>(b, max_pmt, n_cu, s)
+                             : launch_tile<HALO_SMALL, false, true>(b, max_pmt, n_cu, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_tile", 1);
+    } else {
+        TRIG_MARK("k_seed", 0);
+        hipError_t e = launch_seed(b, max_pmt, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_seed", 1);
+        TRIG_MARK("k_fold", 0);
+        e = launch_fold(b, s);
+        if (e != hipSuccess) return e;
+        TRIG_MARK("k_fold", 1);
+    }
     TRIG_MARK("k_tscan", 0);
     hipLaunchKernelGGL(k_tscan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();

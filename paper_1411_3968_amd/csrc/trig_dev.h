@@ -138,7 +138,7 @@ struct SliceDev {
     uint32_t n_pmt, pbits;
     uint32_t chunk_base, n_chunks;
     uint32_t tile_base, n_tiles;   // k_trig tiles: max(1, chunks) (an empty slice has one)
-    uint32_t group_base;     // first counting-kernel group of the slice (groups of BatchDev::tile_group tiles)
+    uint32_t group_base;     // first fold-kernel group of the slice (groups of BatchDev::tile_group tiles)
     uint32_t group_pad;
     uint32_t seg_target, seg_cap;
     uint64_t pos_cap;
@@ -186,10 +186,10 @@ struct BatchDev {
     uint32_t *counters;
     Plan *x_plans;           // host-mapped copy of the plans written at the end of the tail
     trig_params prm;
-    // counting kernel: groups of tile_group consecutive tiles of one slice per
-    // workgroup, halo_cap ordered hits staged at most on each side; group_slice
+    // fold kernel: groups of tile_group consecutive tiles of one slice per
+    // workgroup, window_cap window seeds staged in LDS at most; group_slice
     // maps every group to its slice (written by k_plan; unused for one slice)
-    uint32_t tile_group, halo_cap;
+    uint32_t tile_group, window_cap;
     uint32_t total_groups;
     uint32_t tbnd_lds;       // table-bound entries the counting kernel stages in LDS (0: none)
     uint32_t *group_slice;
@@ -408,6 +408,19 @@ __device__ __forceinline__ TRIG_GAS uint64_t *level1_hits(const SliceDev &S) {
 }
 __device__ __forceinline__ TRIG_GAS uint32_t *level1_index(const SliceDev &S) {
     return (TRIG_GAS uint32_t *)gmem(S.fires);
+}
+
+// Plain rule: every tile's seeds, compacted in time order by the seed kernel and
+// read by the fold kernel: time (t - t_min) and pmt << 16 | position in the tile,
+// TILE slots per tile each, then the seed count of every tile.  They live in the
+// boundary-table area, unused once the ordering is done (3n + 65536 words hold
+// 2 TILE n_tiles + n_tiles).
+__device__ __forceinline__ TRIG_GAS uint32_t *seed_t(const SliceDev &S) { return gmem(S.pos); }
+__device__ __forceinline__ TRIG_GAS uint32_t *seed_p(const SliceDev &S) {
+    return gmem(S.pos) + (uint64_t)S.n_tiles * TILE;
+}
+__device__ __forceinline__ TRIG_GAS uint32_t *seed_n(const SliceDev &S) {
+    return gmem(S.pos) + 2ull * S.n_tiles * TILE;
 }
 
 __device__ __forceinline__ bool slice_in_tail(const BatchDev &b, uint32_t state) {

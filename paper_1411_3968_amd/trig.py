@@ -61,7 +61,7 @@ class Result(C.Structure):
 
 class Tune(C.Structure):
     _fields_ = [("seg_target", C.c_uint32), ("seg_cap", C.c_uint32), ("grid_per_cu", C.c_uint32),
-                ("tile_group", C.c_uint32), ("halo_cap", C.c_uint32), ("reserved", C.c_uint32)]
+                ("tile_group", C.c_uint32), ("window_cap", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class KernelTime(C.Structure):
@@ -445,18 +445,18 @@ def trig_tune_get(ctx, n_pmt: int) -> dict:
     if rc != TRIG_OK:
         raise TrigError(rc, _err(ctx))
     return dict(seg_target=t.seg_target, seg_cap=t.seg_cap, grid_per_cu=t.grid_per_cu, tile_group=t.tile_group,
-                halo_cap=t.halo_cap)
+                window_cap=t.window_cap)
 
 
 def trig_tune_set(ctx, n_pmt_max: int, seg_target: int, seg_cap: int, grid_per_cu: int,
-                  tile_group: int | None = None, halo_cap: int | None = None) -> None:
+                  tile_group: int | None = None, window_cap: int | None = None) -> None:
     """Set the knobs of one PMT-count class; a knob left at None keeps the value
     the class has now."""
-    if tile_group is None or halo_cap is None:
+    if tile_group is None or window_cap is None:
         cur = trig_tune_get(ctx, n_pmt_max)
         tile_group = cur["tile_group"] if tile_group is None else tile_group
-        halo_cap = cur["halo_cap"] if halo_cap is None else halo_cap
-    t = Tune(int(seg_target), int(seg_cap), int(grid_per_cu), int(tile_group), int(halo_cap), 0)
+        window_cap = cur["window_cap"] if window_cap is None else window_cap
+    t = Tune(int(seg_target), int(seg_cap), int(grid_per_cu), int(tile_group), int(window_cap), 0)
     rc = _LIB.trig_tune_set(ctx, int(n_pmt_max), C.byref(t))
     if rc != TRIG_OK:
         raise TrigError(rc, _err(ctx))

@@ -2,7 +2,7 @@
 time window TW; the seed rule then runs on the hits that pass): seed flags,
 fires and events equal the oracle's on the paper's settings (N7TW1000 for the
 NEMO-like tower, N7TW500 for the KM3Net-It-like one, DN7TW1000), on random
-settings, on the general and dense-rerun paths, in a batch and at full size."""
+settings, on the general ordering and a dense burst, in a batch and at full size."""
 import numpy as np
 import pytest
 
@@ -83,8 +83,8 @@ def test_random_settings(tr, orc, seed):
     check(got, ref)
 
 
-def test_dense_window_rerun(tr, orc):
-    """The burst whose trigger stage is rerun with a seed mask, level 0 on."""
+def test_dense_window(tr, orc):
+    """A dense burst on one floor straddling a tile boundary, level 0 on."""
     from gen import configs as C
     w = C.nemo(seed=11, length_ns=20_000_000, n_tracks=2)
     g, thr = w.geoms["nemo"]
@@ -104,7 +104,7 @@ def test_dense_window_rerun(tr, orc):
     gid = tr.load_geometry(g.floor_id, thr)
     got = tr.slice(gid, pmt, t, q, prm, seed_flags=True)
     check(got, orc.run(pmt, t, q, g.floor_id, thr, prm, "blocked"))
-    assert got["path"] == 2
+    assert got["path"] == 0
 
 
 def test_batch_and_full_size(tr, orc):

@@ -229,14 +229,15 @@ def test_dense_segment_takes_general_path(tr, orc):
     got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
     ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
     check(got, ref)
-    # general ordering, and the burst outruns the trigger stage's staged halo too
-    assert got["path"] == 3
+    # general ordering; the burst outruns the seed kernel's staged neighbours and
+    # the fold kernel's staged window, which read past them in device memory
+    assert got["path"] == 1
 
 
-def test_dense_window_rerun_on_run_merge(tr, orc):
-    """A short burst on one floor, dense enough that trigger windows reach past the
-    halo sized from the slice's mean density but small enough for the run-merge
-    ordering: the trigger stage is rerun with a seed mask; results unchanged."""
+def test_dense_window_on_run_merge(tr, orc):
+    """A short burst on one floor, far denser than the slice's mean but small
+    enough for the run-merge ordering, straddling a tile boundary: the causal
+    windows of its seeds span several tiles' seed lists; no rerun."""
     from gen import configs as C
     w = C.nemo(seed=11, length_ns=20_000_000, n_tracks=2)
     g, thr = w.geoms["nemo"]
@@ -258,8 +259,65 @@ def test_dense_window_rerun_on_run_merge(tr, orc):
     got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
     ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
     check(got, ref)
-    assert got["path"] == 2 and got["n_fires"] > 0
+    assert got["path"] == 0 and got["n_fires"] > 0
 
+
+def test_fold_window_past_staged_tiles(tr, orc):
+    """80 000 hits on one PMT within 2 us, a few of them over the charge threshold:
+    the causal windows of the burst's seeds span more than 64 tiles, so the fold
+    kernel reads the seed lists tile by tile from device memory, and the seed
+    kernel's staged neighbours do not span t_floor_ns inside the burst."""
+    from gen import configs as C
+    w = C.nemo(seed=12, length_ns=20_000_000, n_tracks=2)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    rng = np.random.default_rng(7)
+    k = 80_000
+    bt = s.t.min() + 7_000_000 + np.sort(rng.integers(0, 2000, size=k))
+    bp = np.full(k, 5, np.uint16)
+    bq = rng.integers(0, 300, size=k).astype(np.uint16)
+    bq[rng.random(k) < 0.002] = 400
+    pmt = np.concatenate([s.pmt, bp])
+    t = np.concatenate([s.t, bt])
+    q = np.concatenate([s.q, bq])
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
+    ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["n_fires"] > 0
+
+
+@pytest.mark.parametrize("window_cap", [1024, 4096])
+def test_floor_burst_denser_than_staged_neighbours(T, tr, orc, window_cap):
+    """3000 hits on the four PMTs of one floor within 60 ns, none over the charge
+    threshold (every hit a floor-coincidence seed): the seed kernel searches
+    partners past its staged neighbours, and the fold windows hold 3000 seeds (in
+    device memory with a 1024-seed LDS window, staged with 4096)."""
+    from gen import configs as C
+    w = C.nemo(seed=13, length_ns=20_000_000, n_tracks=2)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    rng = np.random.default_rng(11)
+    k = 3000
+    floor0 = np.flatnonzero(g.floor_id == g.floor_id[0])[:4].astype(np.uint16)
+    bt = np.sort(s.t)[30000] + 1 + np.sort(rng.integers(0, 60, size=k))
+    bp = rng.choice(floor0, size=k).astype(np.uint16)
+    bq = rng.integers(0, 200, size=k).astype(np.uint16)
+    order = np.lexsort((bt, bp))
+    pmt = np.concatenate([s.pmt, bp[order]])
+    t = np.concatenate([s.t, bt[order]])
+    q = np.concatenate([s.q, bq[order]])
+    gid = gid_for(tr, g.floor_id, thr)
+    cur = T.trig_tune_get(tr.ctx, 32)
+    T.trig_tune_set(tr.ctx, 128, cur["seg_target"], cur["seg_cap"], cur["grid_per_cu"], window_cap=window_cap)
+    try:
+        got = tr.slice(gid, pmt, t, q, w.params, seed_flags=True)
+    finally:
+        T.trig_tune_set(tr.ctx, 128, cur["seg_target"], cur["seg_cap"], cur["grid_per_cu"],
+                        window_cap=cur["window_cap"])
+    ref = orc.run(pmt, t, q, g.floor_id, thr, w.params, "blocked")
+    check(got, ref)
+    assert got["n_seeds"] >= k
 
 def test_errors(T, tr):
     from gen import configs as C
