@@ -300,11 +300,11 @@ int trig_stream_stats_get(trig_ctx *ctx, trig_stream_stats *out);
  *                 waves in flight), 2048, 4096 or 8192 with one workgroup
  *   grid_per_cu   persistent workgroups per compute unit
  *   tile_group    1024-hit trigger tiles per workgroup of the causal-fold
- *                 stage (Sec. 4.1 sizes the paper's sub-slices per GPU
- *                 thread): 1, 2 or 4, fewer when the launch would otherwise
- *                 give a compute unit less than two workgroups
- *   window_cap    seeds of a group's causal window staged in LDS at most, 1024
- *                 or 4096 (a larger window is read from device memory)
+ *                 stage, a wave per tile (Sec. 4.1 sizes the paper's
+ *                 sub-slices per GPU thread): 1, 2 or 4, fewer when the launch
+ *                 would otherwise give a compute unit less than two workgroups
+ *   window_cap    seeds of a tile's causal window staged in LDS at most, 512 or
+ *                 2048 (a larger window is read from device memory)
  * trig_tune_set returns TRIG_EINVAL for other capacities, a zero target, a
  * grid_per_cu outside 1..16 or another tile_group or window_cap.  A batch whose
  * slices fall in several classes takes the largest tile_group and window_cap. */

@@ -46,7 +46,7 @@ def _time_batch(ctx, slices, params, reps: int, stream=None) -> float:
     return float(np.median(ts))
 
 
-COUNT_CANDIDATES = [(g, h) for g in (1, 2, 4) for h in (1024, 4096)]
+COUNT_CANDIDATES = [(g, h) for g in (1, 2, 4) for h in (512, 2048)]
 KNOBS = ("seg_cap", "seg_target", "grid_per_cu", "tile_group", "window_cap")
 
 

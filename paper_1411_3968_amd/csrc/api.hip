@@ -178,6 +178,7 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.o_pq = take(n * 4 + 4);
     L.o_idx = take(n * 4 + 4);
     L.tstat = take(std::max<uint64_t>(n_tiles, 1) * sizeof(TileStat));
+    L.cagg = take((std::max<uint64_t>(n_tiles, 1) + TS_CH - 1) / TS_CH * sizeof(TileAgg));
     L.dmask = take((n / 64 + 1) * 8);
     L.fsc = take(std::max<uint64_t>(n_tiles, 1) * TILE * sizeof(FireRec));
     L.fires = take(n * sizeof(trig_fire) + 32);
@@ -319,7 +320,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     // classes ask for, fewer tiles per group while that would leave a compute unit
     // with less than two workgroups
     tile_group = 1;
-    window_cap = 1024;
+    window_cap = 512;
     for (const SliceInfo &si : slices) {
         tile_group = std::max(tile_group, si.tune.tile_group);
         window_cap = std::max(window_cap, si.tune.window_cap);
@@ -406,6 +407,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
             S.afl32 = g.afl32;
             S.tbnd = g.tbnd;
             S.nbk = g.nbk;
+            S.rmax = g.rmax;
+            S.thr_max = g.thr_max;
             S.n_pmt = g.n_pmt;
             S.pbits = pbits_of(g.n_pmt);
         } else {
@@ -446,6 +449,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.o_pq = (uint32_t *)(b + L.o_pq);
         S.o_idx = (uint32_t *)(b + L.o_idx);
         S.tstat = (TileStat *)(b + L.tstat);
+        S.cagg = (TileAgg *)(b + L.cagg);
         S.dmask = (uint64_t *)(b + L.dmask);
         S.fsc = (FireRec *)(b + L.fsc);
         S.fires = (trig_fire *)(b + L.fires);
@@ -492,6 +496,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     batch.n_slices = n;
     batch.total_chunks = total_chunks;
     batch.total_tiles = total_tiles;
+    batch.max_tiles = 1;
+    for (const SliceInfo &si : slices) batch.max_tiles = std::max(batch.max_tiles, si.n_tiles);
     batch.tail_state = ST_FAST;
     batch.sort_kernels = sort_kernels;
     batch.block_cap = seg_cap;
@@ -694,6 +700,7 @@ BatchDev Job::one_slice(uint32_t i, uint32_t state) const {
     b1.n_slices = 1;
     b1.total_chunks = slices[i].n_chunks;
     b1.total_tiles = slices[i].n_tiles;
+    b1.max_tiles = std::max(1u, slices[i].n_tiles);
     b1.x_plans = x_plans_dev ? x_plans_dev + i : nullptr;
     b1.tail_state = state;
     b1.total_groups = groups_of(slices[i].n_tiles, tile_group);
@@ -922,8 +929,8 @@ int trig_create(trig_ctx **out, int device, uint64_t hbm_budget_bytes) {
     const char *g = getenv("TRIG_GRAPHS");
     c->use_graphs = !(g && g[0] == '0');
     // wave per segment, 3 workgroups of 4 waves per CU; fold workgroups of two
-    // tiles staging up to 1024 window seeds
-    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 2, 1024, 0};
+    // tiles, each wave staging up to 512 window seeds
+    const trig_tune tower = {384, (uint32_t)WAVE_CAP, 3, 2, 512, 0};
     const trig_tune block = tower;
     c->tunes.push_back({128u, tower});
     c->tunes.push_back({0xFFFFFFFFu, block});
@@ -956,6 +963,7 @@ void trig_destroy(trig_ctx *c) {
         hipFree(g.adj32);
         hipFree(g.afl32);
         hipFree(g.tbnd);
+        hipFree(g.rmax);
     }
     for (auto ev : c->ev_pool) hipEventDestroy(ev);
     for (auto &m : c->prof_pending) hipEventDestroy(m.ev);
@@ -976,7 +984,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     hipSetDevice(c->device);
     const uint64_t P = g->n_pmt;
     const uint64_t nbb = P >= TBND_MIN_PMT ? (P + 31) / 32 : 0;
-    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2 + P * 8 + nbb * nbb * 2;
+    const uint64_t bytes = P * 4 + P * 2 + P * P * 4 + P * P * 2 + P * 8 + nbb * nbb * 2 + P * 4;
     if (ctx_reserve(c, bytes) != TRIG_OK) {
         ctx_set_error(c, "device budget exceeded by geometry");
         return TRIG_ENOMEM;
@@ -1041,7 +1049,15 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
                 tb[bi * nb + bj] = (uint16_t)(lo | (hi << 8));
             }
     }
+    // the reach of each PMT's seeds: its row's largest entry
+    std::vector<uint32_t> rmax(P, 0u);
+    for (uint64_t i = 0; i < P; ++i) {
+        for (uint64_t j = 0; j < P; ++j) rmax[i] = std::max(rmax[i], g->thr_ns[i * P + j]);
+        d.thr_max = std::max(d.thr_max, rmax[i]);
+    }
     hipError_t e = hipMalloc(&d.floor_id, P * 4);
+    if (e == hipSuccess) e = hipMalloc(&d.rmax, P * 4);
+    if (e == hipSuccess) e = hipMemcpy(d.rmax, rmax.data(), P * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess && d.nbk) e = hipMalloc(&d.tbnd, tb.size() * 2);
     if (e == hipSuccess && d.nbk) e = hipMemcpy(d.tbnd, tb.data(), tb.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d.adj32, P * 4);
@@ -1057,6 +1073,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     if (e == hipSuccess) e = hipMemcpy(d.thr16, t16.data(), P * P * 2, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         hipFree(d.tbnd);
+        hipFree(d.rmax);
         hipFree(d.floor16);
         hipFree(d.floor_id);
         hipFree(d.adj32);
@@ -1132,7 +1149,7 @@ int trig_tune_set(trig_ctx *c, uint32_t n_pmt_max, const trig_tune *t) {
         t->seg_target == 0 ||
         t->grid_per_cu == 0 || t->grid_per_cu > 16 ||
         !(t->tile_group == 1 || t->tile_group == 2 || t->tile_group == 4) ||
-        !(t->window_cap == 1024 || t->window_cap == 4096)) {
+        !(t->window_cap == 512 || t->window_cap == 2048)) {
         ctx_set_error(c, "bad tuning values");
         return TRIG_EINVAL;
     }

@@ -38,11 +38,15 @@ struct GeomDev {
     // units), nbk x nbk; nbk = 0 (no bounds) for small detectors whose table stays in cache
     uint16_t *tbnd = nullptr;
     uint32_t nbk = 0;
+    // largest entry of each row of the table (the reach of that PMT's seeds) and of
+    // the whole table
+    uint32_t *rmax = nullptr;
+    uint32_t thr_max = 0;
 };
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
 struct SliceLayout {
-    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, dmask, fsc, fires, events, flags, tagc, l0m;
+    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, cagg, dmask, fsc, fires, events, flags, tagc, l0m;
     uint64_t pos_cap;
 };
 
@@ -77,7 +81,7 @@ struct Job {
     uint32_t wave_wgs = 0, block_wgs = 0;   // persistent workgroups per CU of each
     uint32_t wave_cap = 0;            // variant of the wave-per-segment kernel (largest tuned capacity)
     uint32_t total_chunks = 0, total_tiles = 0;
-    uint32_t tile_group = 1, window_cap = 1024, total_groups = 0;   // fold-kernel launch shape
+    uint32_t tile_group = 1, window_cap = 512, total_groups = 0;   // fold-kernel launch shape
     uint32_t *d_group_slice = nullptr;
     uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;

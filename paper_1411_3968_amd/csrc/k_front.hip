@@ -458,18 +458,19 @@ __global__ __launch_bounds__(NT) void k_segsort(BatchDev b) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SegShared<NT, CAP> &sm = *reinterpret_cast<SegShared<NT, CAP> *>(smem_raw);
     const uint32_t total = b.counters[Q_SEG_TOTAL_B];
-    const uint32_t per = (total + gridDim.x - 1) / gridDim.x;
-    const uint32_t first = blockIdx.x * per;
-    const uint32_t end = (first + per < total) ? first + per : total;
+    // as in the wave kernel: each XCD a contiguous eighth of the segments,
+    // interleaved over its workgroups
+    const uint32_t xcd = blockIdx.x % 8, wg_in_xcd = blockIdx.x / 8, wg_per_xcd = gridDim.x / 8;
+    const uint32_t x0 = (uint32_t)(((uint64_t)total * xcd) / 8), x1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / 8);
     uint32_t si = 0, s_base = 1, s_end = 0;
     const TRIG_GAS uint64_t *in_pk = nullptr;
     const TRIG_GAS uint32_t *pos = nullptr;
     TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     uint32_t pbits = 0;
     Plan P = {};
-    for (uint32_t item = first; item < end; ++item) {
+    for (uint32_t item = x0 + wg_in_xcd; item < x1; item += wg_per_xcd) {
         if (item < s_base || item >= s_end) {
-            si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.plans[i].seg_item_base_b; });
+            si = find_slice_from(b.n_slices, si, item, [&](uint32_t i) { return b.plans[i].seg_item_base_b; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
             in_pk = packed_hits(S); pos = gmem(S.pos);
@@ -683,15 +684,14 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     WaveSeg<CAP> &sm = reinterpret_cast<WaveSeg<CAP> *>(smem_raw)[w];
     const uint32_t total = b.counters[L2 ? Q_SEG_TOTAL2 : Q_SEG_TOTAL];
     // XCD-aware split: workgroup b runs on XCD b % 8 (round-robin dispatch), and
-    // each XCD takes one contiguous eighth of the segment list, so the cache lines
-    // that neighbouring segments share in every run are fetched into one L2
+    // each XCD takes one contiguous eighth of the segment list, its items
+    // interleaved over the XCD's waves: the segments in flight on an XCD at any
+    // time are neighbours, so the cache lines they share in every run are fetched
+    // into its L2 once
     const uint32_t xcd = blockIdx.x % 8, wg_in_xcd = blockIdx.x / 8, wg_per_xcd = gridDim.x / 8;
     const uint32_t x0 = (uint32_t)(((uint64_t)total * xcd) / 8), x1 = (uint32_t)(((uint64_t)total * (xcd + 1)) / 8);
     const uint32_t nwv = wg_per_xcd * 4;
     const uint32_t gw = wg_in_xcd * 4 + (uint32_t)w;
-    const uint32_t per = (x1 - x0 + nwv - 1) / nwv;
-    const uint32_t first = x0 + gw * per;
-    const uint32_t end = (first + per < x1) ? first + per : x1;
     uint32_t si = 0, s_base = 1, s_end = 0;
     const TRIG_GAS uint64_t *in_pk = nullptr;
     const TRIG_GAS uint32_t *pos = nullptr;
@@ -702,10 +702,10 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
     // the plan fields of this launch's level
     uint32_t n_runs = 0, shift = 0, n_seg = 1;
     bool tl1 = false;   // level 1 of a two-level slice
-    for (uint32_t item = first; item < end; ++item) {
+    for (uint32_t item = x0 + gw; item < x1; item += nwv) {
         if (item < s_base || item >= s_end) {
-            si = find_slice(b.n_slices, item,
-                            [&](uint32_t i) { return L2 ? b.plans[i].seg_item_base2 : b.plans[i].seg_item_base; });
+            si = find_slice_from(b.n_slices, si, item,
+                                 [&](uint32_t i) { return L2 ? b.plans[i].seg_item_base2 : b.plans[i].seg_item_base; });
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
             in_pk = L2 ? level1_hits(S) : packed_hits(S);
@@ -914,7 +914,7 @@ hipError_t launch_segsort(const BatchDev &b, const TrigLaunchCfg &cfg, hipStream
         if (e != hipSuccess) return e;
         attr_done = true;
     }
-    const int grid = cfg.n_cu * cfg.persist_per_cu;
+    const int grid = ((cfg.n_cu * cfg.persist_per_cu + 7) / 8) * 8;   // a multiple of the 8 XCDs
     hipLaunchKernelGGL((k_segsort<NT, CAP>), dim3(grid), dim3(NT), shm, s, b);
     return hipGetLastError();
 }

@@ -552,64 +552,97 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     if (lane == 0) gstore(&gmem(S.tstat)[k].agg, A);
 }
 
-// Per slice (1024 threads): exclusive scan of the tile summaries, counts, the
-// end of the slice's last event, and the plan to host-mapped staging.
-__global__ __launch_bounds__(1024) void k_tscan(BatchDev b) {
-    constexpr int NTS = 1024, NWS = NTS / 64;
-    const uint32_t si = blockIdx.x;
+// Tile scan, in chunks of TS_CH tiles of one slice (grid: chunks x slices), 256
+// threads of four tiles each.  k_tsum (launched when a slice has more than one
+// chunk): each chunk's combined summary.  k_tscan: each chunk combines the
+// summaries of the chunks before it, then scans its tiles: every tile gets the
+// summary of the tiles of the slice before it; the last chunk ends with the whole
+// slice: its counts, the end of its last event, and the plan to host-mapped
+// staging.
+constexpr int TS_NT = 256;
+constexpr int TS_PT = (int)TS_CH / TS_NT;   // tiles per thread
+
+// Summary of this thread's tiles of chunk c, with the tiles' own summaries.
+__device__ __forceinline__ TileAgg tscan_thread(const TRIG_GAS TileStat *tstat, uint32_t t0, uint32_t nt,
+                                                uint64_t twoH, TileAgg (&x)[TS_PT]) {
+    TileAgg mine = agg_empty();
+#pragma unroll
+    for (int u = 0; u < TS_PT; ++u) x[u] = t0 + u < nt ? gload(&tstat[t0 + u].agg) : agg_empty();
+#pragma unroll
+    for (int u = 0; u < TS_PT; ++u) mine = agg_combine(mine, x[u], twoH);
+    return mine;
+}
+
+__global__ __launch_bounds__(TS_NT) void k_tsum(BatchDev b) {
+    constexpr int NW = TS_NT / 64;
+    const uint32_t si = blockIdx.y, c = blockIdx.x;
     const SliceDev &S = b.slices[si];
-    TRIG_GAS Plan *Pp = gmem(b.plans + si);
-    TRIG_GAS TileStat *tstat = gmem(S.tstat);
-    __shared__ TileAgg wsum[NWS], wpre[NWS];
+    const uint32_t nt = S.n_tiles;
+    if ((uint64_t)c * TS_CH >= nt) return;
+    if (!slice_in_tail(b, gmem(b.plans + si)->state)) return;
+    __shared__ TileAgg wsum[NW];
     const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
     const int lane = lane_id(), w = threadIdx.x >> 6;
-    const uint32_t nt = S.n_tiles;
-    const uint32_t per = (nt + NTS - 1) / NTS;
-    const uint32_t t0 = threadIdx.x * per;
-    const uint32_t t1 = (t0 + per < nt) ? t0 + per : nt;
-    // the tile summaries are read in flight with the plan state (they are only
-    // used when the slice is in this pass)
-    // (four summaries in flight per thread at a time)
-    constexpr int TB = 4;
-    TileAgg mine = agg_empty();
-    for (uint32_t t = t0; t < t1; t += TB) {
-        TileAgg x[TB];
-#pragma unroll
-        for (int u = 0; u < TB; ++u) x[u] = t + u < t1 ? gload(&tstat[t + u].agg) : agg_empty();
-#pragma unroll
-        for (int u = 0; u < TB; ++u) mine = agg_combine(mine, x[u], twoH);
-    }
-    const uint32_t state = Pp->state;
-    if (!slice_in_tail(b, state)) {
-        if (threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
-        return;
-    }
-    // inclusive scan within the wave
-    const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
+    TileAgg x[TS_PT];
+    const TileAgg mine = tscan_thread(gmem(S.tstat), c * TS_CH + threadIdx.x * TS_PT, nt, twoH, x);
+    const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &p, const TileAgg &q) { return agg_combine(p, q, twoH); });
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    // the wave totals scanned by the first wave (exclusive: the waves before each)
+    if (threadIdx.x == 0) {
+        TileAgg t = wsum[0];
+        for (int i = 1; i < NW; ++i) t = agg_combine(t, wsum[i], twoH);
+        gstore(gmem(S.cagg) + c, t);
+    }
+}
+
+__global__ __launch_bounds__(TS_NT) void k_tscan(BatchDev b) {
+    constexpr int NW = TS_NT / 64;
+    const uint32_t si = blockIdx.y, c = blockIdx.x;
+    const SliceDev &S = b.slices[si];
+    const uint32_t nt = S.n_tiles;
+    if ((uint64_t)c * TS_CH >= nt) return;
+    TRIG_GAS Plan *Pp = gmem(b.plans + si);
+    TRIG_GAS TileStat *tstat = gmem(S.tstat);
+    __shared__ TileAgg wpre[NW + 1];
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t nch = (nt + TS_CH - 1) / TS_CH;
+    // the tile summaries are read in flight with the plan state (they are only
+    // used when the slice is in this pass)
+    TileAgg x[TS_PT];
+    const uint32_t t0 = c * TS_CH + threadIdx.x * TS_PT;
+    const TileAgg mine = tscan_thread(tstat, t0, nt, twoH, x);
+    const uint32_t state = Pp->state;
+    if (!slice_in_tail(b, state)) {
+        if (c == 0 && threadIdx.x == 0 && b.x_plans && export_as_is(state)) gstore(gmem(b.x_plans) + si, gload(Pp));
+        return;
+    }
+    // the chunks before this one, combined in order by the first wave (64 at a time)
     if (w == 0) {
-        const TileAgg v = lane < NWS ? wsum[lane] : agg_empty();
-        const TileAgg vi = wave_scan(v, agg_empty(), [&](const TileAgg &x, const TileAgg &y) { return agg_combine(x, y, twoH); });
-        const TileAgg vx = wave_shr1(vi, agg_empty());
-        if (lane < NWS) wpre[lane] = vx;
-    }
-    __syncthreads();
-    const TileAgg before = wpre[w];   // waves before this one
-    TileAgg P = agg_combine(before, wave_shr1(inc, agg_empty()), twoH);
-    for (uint32_t t = t0; t < t1; t += TB) {
-        TileAgg x[TB];
-#pragma unroll
-        for (int u = 0; u < TB; ++u) x[u] = t + u < t1 ? gload(&tstat[t + u].agg) : agg_empty();
-#pragma unroll
-        for (int u = 0; u < TB; ++u) {
-            if (t + u < t1) gstore(&tstat[t + u].pre, P);
-            P = agg_combine(P, x[u], twoH);
+        TileAgg P0 = agg_empty();
+        for (uint32_t c0 = 0; c0 < c; c0 += 64) {
+            const uint32_t ci = c0 + (uint32_t)lane;
+            const TileAgg v = ci < c ? gload(gmem(S.cagg) + ci) : agg_empty();
+            const TileAgg vi = wave_scan(v, agg_empty(), [&](const TileAgg &p, const TileAgg &q) { return agg_combine(p, q, twoH); });
+            P0 = agg_combine(P0, lane_read_all(vi, 63), twoH);
         }
+        if (lane == 0) wpre[NW] = P0;
     }
-    if (threadIdx.x != NTS - 1) return;
-    const TileAgg I = P;   // the last thread ends with the whole slice
+    // inclusive scan within the wave
+    const TileAgg inc = wave_scan(mine, agg_empty(), [&](const TileAgg &p, const TileAgg &q) { return agg_combine(p, q, twoH); });
+    if (lane == 63) wpre[w] = inc;
+    __syncthreads();
+    // the waves before this one, after the chunks before this one
+    TileAgg before = wpre[NW];
+    for (int i = 0; i < w; ++i) before = agg_combine(before, wpre[i], twoH);
+    TileAgg P = agg_combine(before, wave_shr1(inc, agg_empty()), twoH);
+#pragma unroll
+    for (int u = 0; u < TS_PT; ++u) {
+        if (t0 + u < nt) gstore(&tstat[t0 + u].pre, P);
+        P = agg_combine(P, x[u], twoH);
+    }
+    if (c != nch - 1 || threadIdx.x != TS_NT - 1) return;
+    const TileAgg I = P;   // the last thread of the last chunk ends with the whole slice
     const uint32_t n_ev = I.F ? 1 + I.E_int : 0u;
     const int64_t H = (int64_t)b.prm.half_event_ns;
     const int64_t t_min = Pp->t_min;
@@ -903,7 +936,8 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
 // t_floor_ns; a pair marks both hits.  A tile whose staged neighbours do not span
 // t_floor_ns (a burst of near-equal times) searches each hit's partners on both
 // sides instead, reading past the stage from global memory.  The tile's seeds are
-// written compacted, in time order, to its seed list with their count.
+// written compacted, in time order, to its seed list, with its record (count,
+// first and last seed time).
 constexpr int SD_NT = 256;
 constexpr int SD_HS = 256;   // staged neighbours per side at most
 
@@ -952,7 +986,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
     const uint64_t n = S.n;
     const uint64_t a = (uint64_t)k * TILE;
     if (a >= n) {   // the one tile of an empty slice
-        if (threadIdx.x == 0) seed_n(S)[k] = 0;
+        if (threadIdx.x == 0) gstore(seed_rec(S) + k, SeedRec{0u, 0u, 0u, 0u});
         return;
     }
     const uint64_t e = (a + TILE < n) ? a + TILE : n;
@@ -1143,10 +1177,11 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
         }
         if (i == TILE / 64 - 1) {
             wpre[TILE / 64] = inc;
-            seed_n(S)[k] = inc;
+            gstore(&seed_rec(S)[k].n, inc);
         }
     }
     __syncthreads();
+    const uint32_t total = wpre[TILE / 64];
 #pragma unroll
     for (int r = 0; r < TILE / NT; ++r) {
         const uint32_t y = r * NT + threadIdx.x;   // position in the tile
@@ -1155,8 +1190,11 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
         const bool s = x < e_loc && ((wv >> (y & 63)) & 1ull);
         if (s) {
             const uint32_t at = wpre[y >> 6] + (uint32_t)__popcll(wv & ((1ull << (y & 63)) - 1ull));
-            sd_t[at] = st[x];
+            const uint32_t tx = st[x];
+            sd_t[at] = tx;
             sd_p[at] = (spf[x] & 0xFFFF0000u) | y;
+            if (at == 0) gstore(&seed_rec(S)[k].first_t, tx);
+            if (at + 1 == total) gstore(&seed_rec(S)[k].last_t, tx);
         }
         if (seed_flags && x < e_loc) seed_flags[o_idx[a + y]] = (uint8_t)s;
     }
@@ -1175,36 +1213,39 @@ hipError_t launch_seed(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
 
 // ------------------------------------------------------------------ k_fold
 // Causal folds of the plain rule's seeds (Sec. 3: the Cherenkov hits of one muon
-// are correlated within min(thr, w_ns)) and the fires: one workgroup of 256
-// threads per group of G consecutive tiles of one slice (the group map written by
-// k_plan), a wave per tile.  The window of the group's seeds reaches the tiles
-// whose hits lie within w_ns of them (found from the tile boundaries' times); the
-// seed lists of those tiles, concatenated, are in time order.  Up to CAP of them
-// (from at most FD_TMAX tiles) are staged in LDS as time and PMT; a larger window
-// is read from the lists in global memory.  A lane per seed of the tile counts,
-// over its own stretch of the window (bounds by fixed-count binary searches), the
-// other seeds within min(thr, w_ns), eight table reads in flight; for large
-// detectors the pair of the two PMTs' 32-PMT blocks has a lower and an upper bound
-// of thr (16 ns units, staged in LDS) that decide most pairs, and the table is
-// read only for the rest.  Each round of 64 seeds then writes its fires to the
-// tile's slot and adds them to the tile's summary (TileAgg).
-constexpr int FD_NT = 256;
+// are correlated within min(thr, w_ns)) and the fires: one wave per tile, G tiles
+// of one slice per workgroup (the group map written by k_plan; the table bounds
+// of a large detector staged in LDS once for them).  A seed of PMT p counts the
+// other seeds within R_p = min(w_ns, the largest entry of p's row of the table),
+// so a tile's window reaches the tiles with seeds within min(w_ns, the table's
+// largest entry) of its own: the records of the 32 tiles before it and the 31
+// after it, read at once, give that window (further tiles are walked 64 at a
+// time).  Its seeds, concatenated in time order, are staged in the wave's LDS (at
+// most CAP; a larger window is read from the lists in device memory).  A lane per
+// seed counts, over its stretch of the window (bounds by fixed-count binary
+// searches), the other seeds within min(thr, w_ns), eight table reads in flight;
+// for large detectors the pair of the two PMTs' 32-PMT blocks has a lower and an
+// upper bound of thr (16 ns units) that decide most pairs, and the table is read
+// only for the rest.  Each round of 64 seeds then writes its fires to the tile's
+// slot and adds them to the tile's summary (TileAgg).
 constexpr int FD_TMAX = 64;   // window tiles staged at most
 
 template <int CAP>
 struct FoldShape {
-    static constexpr size_t lds_bytes() { return (size_t)CAP * 4 + (size_t)CAP * 2; }
+    static constexpr size_t wave_bytes() { return (size_t)CAP * 8; }   // per wave: time, pmt << 16 | position
 };
 
 template <int G, int CAP>
-__global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
-    constexpr int NT = FD_NT;
+__global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
+    constexpr int NT = 64 * G;
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *lt = (uint32_t *)smem;             // window seeds: time
-    uint16_t *lp = (uint16_t *)(lt + CAP);       // window seeds: PMT
-    uint16_t *ltb = lp + CAP;                    // the table bounds (b.tbnd_lds of them)
-    __shared__ uint32_t woff[FD_TMAX + 1];       // window seeds before each window tile
-    __shared__ uint32_t s_win[4];                // first and end window tile, seeds, staged
+    const size_t tb_bytes = ((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15;
+    const int lane = lane_id(), w = threadIdx.x >> 6;
+    uint16_t *ltb = (uint16_t *)smem;                 // the table bounds (b.tbnd_lds of them)
+    uint32_t *lt = (uint32_t *)(smem + tb_bytes + (size_t)w * FoldShape<CAP>::wave_bytes());   // window seeds: time
+    uint32_t *lp = lt + CAP;                          // window seeds: pmt << 16 | position in the tile
+    __shared__ uint32_t woff_all[G][FD_TMAX + 1];     // window seeds before each window tile
+    uint32_t *woff = woff_all[w];
 
     const uint32_t per_xcd = (b.total_groups + 7) / 8;
     const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -1215,118 +1256,147 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
     const uint32_t k0 = g * (uint32_t)G;
     const uint32_t n_tiles = S.n_tiles;
     if (k0 >= n_tiles) return;
-    const uint32_t k1 = (k0 + G < n_tiles) ? k0 + G : n_tiles;
     const TRIG_GAS Plan *Pg = gmem(b.plans + si);
     if (!slice_in_tail(b, Pg->state)) return;
-    const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
-    const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
-    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
-    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
-    const TRIG_GAS uint32_t *sdt = seed_t(S);
-    const TRIG_GAS uint32_t *sdp = seed_p(S);
-    const TRIG_GAS uint32_t *sdn = seed_n(S);
-    const uint32_t n_pmt = S.n_pmt;
-    const uint64_t n = S.n;
     const uint32_t W = b.prm.w_ns;
-    const uint32_t N = b.prm.min_fold;
-    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
-    const int lane = lane_id(), w = threadIdx.x >> 6;
     const uint32_t nbk = S.nbk;
     const bool bounds = nbk != 0 && W <= 65535u;
     const bool tb_in_lds = bounds && nbk * nbk <= b.tbnd_lds;
     const TRIG_GAS uint16_t *tbnd = gmem(S.tbnd);
-    if (tb_in_lds)
+    if (tb_in_lds) {
         for (uint32_t x = threadIdx.x; x < nbk * nbk; x += NT) ltb[x] = tbnd[x];
-
-    // 1. the window: the group's first and last seed times, then the tiles whose
-    // hits lie within w_ns of them (tile times are ordered, so each walk stops at
-    // the first tile outside)
-    if (w == 0) {
-        const uint32_t c = (lane < G && k0 + (uint32_t)lane < k1) ? sdn[k0 + lane] : 0u;
-        const uint64_t ne = __ballot(c > 0);
-        uint32_t jl = k0, jr = k1;
-        if (ne) {
-            const int lf = __ffsll((unsigned long long)ne) - 1, ll = 63 - __clzll((long long)ne);
-            const uint32_t t_first = sdt[(uint64_t)(k0 + lf) * TILE];
-            const uint32_t c_last = lane_read(c, ll);
-            const uint32_t t_last = sdt[(uint64_t)(k0 + ll) * TILE + c_last - 1];
-            const uint32_t t_lo = t_first > W ? t_first - W : 0u;
-            const uint64_t t_hi = (uint64_t)t_last + W;
-            for (;;) {   // to the left: tiles whose last hit is at or after t_lo
-                const bool valid = jl > (uint32_t)lane;
-                const uint32_t j = jl - 1 - (uint32_t)lane;
-                const uint64_t endj = valid ? (((uint64_t)j + 1) * TILE < n ? ((uint64_t)j + 1) * TILE : n) : 1;
-                const bool need = valid && o_t[endj - 1] >= t_lo;
-                const uint64_t M = __ballot(need);
-                const uint32_t m = M == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~M) - 1u;
-                jl -= m;
-                if (m < 64) break;
-            }
-            for (;;) {   // to the right: tiles whose first hit is at or before t_hi
-                const uint32_t j = jr + (uint32_t)lane;
-                const bool valid = j < n_tiles;
-                const bool need = valid && (uint64_t)o_t[valid ? (uint64_t)j * TILE : 0] <= t_hi;
-                const uint64_t M = __ballot(need);
-                const uint32_t m = M == ~0ull ? 64u : (uint32_t)__ffsll((unsigned long long)~M) - 1u;
-                jr += m;
-                if (m < 64) break;
-            }
-        }
-        const uint32_t nt = jr - jl;
-        uint32_t tot = 0;
-        if (nt <= (uint32_t)FD_TMAX) {
-            const uint32_t cj = (uint32_t)lane < nt ? sdn[jl + lane] : 0u;
-            const uint32_t inc = wave_incl_scan(cj);
-            if ((uint32_t)lane < nt) woff[lane] = inc - cj;
-            tot = lane_read(inc, 63);
-            if (lane == 0) woff[nt] = tot;
-        }
-        if (lane == 0) {
-            s_win[0] = jl;
-            s_win[1] = jr;
-            s_win[2] = tot;
-            s_win[3] = (ne != 0 && nt <= (uint32_t)FD_TMAX && tot <= (uint32_t)CAP) ? 1u : 0u;
-        }
+        __syncthreads();
     }
-    __syncthreads();
-    const uint32_t jl = s_win[0], jr = s_win[1], tot = s_win[2];
-    const bool staged = s_win[3] != 0;
-    const uint32_t nt = jr - jl;
-
-    // 2. stage the window's seeds (all loads of a thread in flight)
-    if (staged) {
-        constexpr int UF = CAP / NT;
-        uint32_t vt[UF], vp[UF];
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            const uint32_t x = u * NT + threadIdx.x;
-            if (x < tot) {
-                uint32_t lo = 0, hi = nt;   // window tile of x: the last with woff <= x
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (woff[mid] <= x) lo = mid; else hi = mid;
-                }
-                const uint64_t at = (uint64_t)(jl + lo) * TILE + (x - woff[lo]);
-                vt[u] = sdt[at];
-                vp[u] = sdp[at];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UF; ++u) {
-            const uint32_t x = u * NT + threadIdx.x;
-            if (x < tot) {
-                lt[x] = vt[u];
-                lp[x] = (uint16_t)(vp[u] >> 16);
-            }
-        }
-    }
-    __syncthreads();
-
-    // 3. folds and fires of tile k0 + w, by wave w, 64 seeds per round
-    if (w >= G) return;
     const uint32_t kt = k0 + (uint32_t)w;
-    if (kt >= k1) return;
-    const uint32_t cnt = sdn[kt];
+    if (kt >= n_tiles) return;
+    const TRIG_GAS uint32_t *o_idx = gmem(S.o_idx);
+    const TRIG_GAS uint16_t *thr16 = gmem(S.thr16);
+    const TRIG_GAS uint32_t *thr32 = gmem(S.thr32);
+    const TRIG_GAS uint32_t *rmax = gmem(S.rmax);
+    const TRIG_GAS uint32_t *sdt = seed_t(S);
+    const TRIG_GAS uint32_t *sdp = seed_p(S);
+    const TRIG_GAS SeedRec *recs = seed_rec(S);
+    const uint32_t n_pmt = S.n_pmt;
+    const uint32_t N = b.prm.min_fold;
+    const uint64_t twoH = 2ull * (uint64_t)b.prm.half_event_ns;
+    const uint32_t Wr = W < S.thr_max ? W : S.thr_max;   // the reach of any seed
+
+    // 1. the window: lane l holds the record of tile kt - 32 + l
+    const int64_t jj = (int64_t)kt - 32 + lane;
+    const bool vj = jj >= 0 && jj < (int64_t)n_tiles;
+    SeedRec R = SeedRec{0u, 0u, 0u, 0u};
+    if (vj) R = gload(recs + jj);
+    const uint32_t cnt = lane_read(R.n, 32);
+    TileAgg A = agg_empty();
+    if (cnt == 0) {
+        if (lane == 0) gstore(&gmem(S.tstat)[kt].agg, A);
+        return;
+    }
+    const uint32_t t_first = lane_read(R.first_t, 32), t_last = lane_read(R.last_t, 32);
+    const uint32_t t_lo_w = t_first > Wr ? t_first - Wr : 0u;
+    const uint64_t t_hi_w = (uint64_t)t_last + Wr;
+    // the nearest tile on each side whose seeds all lie outside: it and the tiles
+    // beyond it hold none within reach
+    const uint64_t stopL = __ballot(lane < 32 && vj && R.n > 0 && R.last_t < t_lo_w);
+    const uint64_t stopR = __ballot(lane > 32 && vj && R.n > 0 && (uint64_t)R.first_t > t_hi_w);
+    bool near = true;
+    uint32_t jl, jr;
+    if (stopL) {
+        jl = kt - 32 + (uint32_t)(63 - __clzll((long long)stopL)) + 1;
+    } else if (kt < 32) {
+        jl = 0;
+    } else {
+        near = false;
+        jl = kt - 32;
+        for (;;) {
+            const bool v = jl > (uint32_t)lane;
+            SeedRec Rw = SeedRec{0u, 0u, 0u, 0u};
+            if (v) Rw = gload(recs + (jl - 1 - (uint32_t)lane));
+            const uint64_t M = __ballot(!v || (Rw.n > 0 && Rw.last_t < t_lo_w));
+            if (M) {
+                jl -= (uint32_t)(__ffsll((unsigned long long)M) - 1);
+                break;
+            }
+            jl -= 64;
+        }
+    }
+    if (stopR) {
+        jr = kt - 32 + (uint32_t)(__ffsll((unsigned long long)stopR) - 1);
+    } else if ((uint64_t)kt + 32 >= n_tiles) {
+        jr = n_tiles;
+    } else {
+        near = false;
+        jr = kt + 32;
+        for (;;) {
+            const uint32_t j = jr + (uint32_t)lane;
+            const bool v = j < n_tiles;
+            SeedRec Rw = SeedRec{0u, 0u, 0u, 0u};
+            if (v) Rw = gload(recs + j);
+            const uint64_t M = __ballot(!v || (Rw.n > 0 && (uint64_t)Rw.first_t > t_hi_w));
+            if (M) {
+                jr += (uint32_t)(__ffsll((unsigned long long)M) - 1);
+                break;
+            }
+            jr += 64;
+        }
+    }
+    const uint32_t nt = jr - jl;
+    uint32_t tot = 0;
+    bool staged = false;
+    if (near || nt <= (uint32_t)FD_TMAX) {
+        // window seeds before each window tile (the records already in the lanes
+        // when the window lies within them)
+        uint32_t c = 0, at = 0;
+        bool in = false;
+        if (near) {
+            in = vj && jj >= (int64_t)jl && jj < (int64_t)jr;
+            c = in ? R.n : 0u;
+            at = (uint32_t)(jj - (int64_t)jl);
+        } else {
+            in = (uint32_t)lane < nt;
+            c = in ? gload(recs + jl + lane).n : 0u;
+            at = (uint32_t)lane;
+        }
+        const uint32_t inc = wave_incl_scan(c);
+        tot = lane_read(inc, 63);
+        if (in) woff[at] = inc - c;
+        if (lane == 0) woff[nt] = tot;
+        staged = tot <= (uint32_t)CAP;
+        wave_lds_sync();
+    }
+
+    // 2. stage the window's seeds (UB loads in flight per lane)
+    if (staged) {
+        constexpr int UB = 8;
+        for (uint32_t x0 = 0; x0 < tot; x0 += 64 * UB) {
+            uint32_t vt[UB], vp[UB];
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const uint32_t x = x0 + u * 64 + (uint32_t)lane;
+                if (x < tot) {
+                    uint32_t lo = 0, hi = nt;   // window tile of x: the last with woff <= x
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (woff[mid] <= x) lo = mid; else hi = mid;
+                    }
+                    const uint64_t src = (uint64_t)(jl + lo) * TILE + (x - woff[lo]);
+                    vt[u] = sdt[src];
+                    vp[u] = sdp[src];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const uint32_t x = x0 + u * 64 + (uint32_t)lane;
+                if (x < tot) {
+                    lt[x] = vt[u];
+                    lp[x] = vp[u];
+                }
+            }
+        }
+        wave_lds_sync();
+    }
+
+    // 3. folds and fires, 64 seeds per round
     const uint32_t own0 = staged ? woff[kt - jl] : 0u;   // the tile's first seed in the window
     TRIG_GAS FireRec *slot = gmem(S.fsc) + (uint64_t)kt * TILE;
     const bool t16 = W <= 65535u;
@@ -1336,8 +1406,8 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
 
     // fold of one seed (time ti, PMT pi, window index self) over window entries
     // [jlo, jhi) read through T_at / P_at
-    auto count_range = [&](uint32_t ti, uint32_t pi, uint32_t jlo, uint32_t jhi, uint32_t self, auto T_at,
-                           auto P_at) -> uint32_t {
+    auto count_range = [&](uint32_t ti, uint32_t pi, uint32_t lim_w, uint32_t jlo, uint32_t jhi, uint32_t self,
+                           auto T_at, auto P_at) -> uint32_t {
         const uint64_t row = (uint64_t)pi * n_pmt;
         const uint32_t brow = (pi >> TBND_SHIFT) * nbk;
         uint32_t c = 0;
@@ -1355,7 +1425,7 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
                     if (j < jhi && j != self) {
                         const uint32_t tj = T_at(j);
                         const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                        if (dt <= W) {
+                        if (dt <= lim_w) {
                             pj[kk] = P_at(j);
                             const uint32_t bx = brow + (pj[kk] >> TBND_SHIFT);
                             bb[kk] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
@@ -1379,7 +1449,7 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
                     if (j < jhi && j != self) {
                         const uint32_t tj = T_at(j);
                         const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                        if (dt <= W) {
+                        if (dt <= lim_w) {
                             const uint64_t x = row + P_at(j);
                             lim[kk] = t16 ? (uint32_t)thr16[x] : thr32[x];
                             dd[kk] = dt;
@@ -1393,18 +1463,25 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
         return c;
     };
 
-    TileAgg A = agg_empty();
     A.S = cnt;
     uint32_t nf = 0, prev_t = 0, first_int = NO_START, last_int = NO_START, m_head = 0, m_tail = 0;
     for (uint32_t r0 = 0; r0 < cnt; r0 += 64) {
         const uint32_t r = r0 + (uint32_t)lane;
         const bool v = r < cnt;
         const uint32_t rc = v ? r : cnt - 1;
-        const uint32_t ti = sdt[(uint64_t)kt * TILE + rc];
-        const uint32_t sp = sdp[(uint64_t)kt * TILE + rc];
+        uint32_t ti, sp;
+        if (staged) {
+            ti = lt[own0 + rc];
+            sp = lp[own0 + rc];
+        } else {
+            ti = sdt[(uint64_t)kt * TILE + rc];
+            sp = sdp[(uint64_t)kt * TILE + rc];
+        }
         const uint32_t pi = sp >> 16;
-        const uint32_t t_lo = ti > W ? ti - W : 0u;
-        const uint64_t t_hi = (uint64_t)ti + W;
+        const uint32_t rm = rmax[pi];
+        const uint32_t Ri = W < rm ? W : rm;   // this seed's reach
+        const uint32_t t_lo = ti > Ri ? ti - Ri : 0u;
+        const uint64_t t_hi = (uint64_t)ti + Ri;
         uint32_t c = 0;
         if (staged) {
             uint32_t jlo = 0, jhi = 0;   // window seeds with time < t_lo, with time <= t_hi
@@ -1414,15 +1491,15 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
                 if (mr <= tot && (uint64_t)lt[mr - 1] <= t_hi) jhi = mr;
             }
             if (!v) jhi = jlo;
-            c = count_range(ti, pi, jlo, jhi, own0 + r, [&](uint32_t j) { return lt[j]; },
-                            [&](uint32_t j) { return (uint32_t)lp[j]; });
+            c = count_range(ti, pi, Ri, jlo, jhi, own0 + r, [&](uint32_t j) { return lt[j]; },
+                            [&](uint32_t j) { return lp[j] >> 16; });
         } else {
-            // the window tile by tile from the lists in global memory
-            for (uint32_t jj = jl; jj < jr; ++jj) {
-                const uint32_t cj = sdn[jj];
-                const TRIG_GAS uint32_t *tj = sdt + (uint64_t)jj * TILE;
-                const TRIG_GAS uint32_t *pj = sdp + (uint64_t)jj * TILE;
-                uint32_t jlo = 0, jhi = cj;   // first with time >= t_lo, first with time > t_hi
+            // the window tile by tile from the lists in device memory
+            for (uint32_t jt = jl; jt < jr; ++jt) {
+                const uint32_t cj = gload(recs + jt).n;
+                const TRIG_GAS uint32_t *tj = sdt + (uint64_t)jt * TILE;
+                const TRIG_GAS uint32_t *pj = sdp + (uint64_t)jt * TILE;
+                uint32_t jlo, jhi;   // first with time >= t_lo, first with time > t_hi
                 {
                     uint32_t lo = 0, hi = cj;
                     while (lo < hi) {
@@ -1437,7 +1514,7 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
                     }
                     jhi = v ? lo : jlo;
                 }
-                c += count_range(ti, pi, jlo, jhi, jj == kt ? r : 0xFFFFFFFFu, [&](uint32_t j) { return tj[j]; },
+                c += count_range(ti, pi, Ri, jlo, jhi, jt == kt ? r : 0xFFFFFFFFu, [&](uint32_t j) { return tj[j]; },
                                  [&](uint32_t j) { return pj[j] >> 16; });
             }
         }
@@ -1464,8 +1541,7 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
         const uint64_t ib = __ballot(is_int);
         if (M) {
             if (nf == 0) A.first_t = lane_read(ti, __ffsll((unsigned long long)M) - 1);
-            const int lastf = 63 - __clzll((long long)M);
-            prev_t = lane_read(ti, lastf);
+            prev_t = lane_read(ti, 63 - __clzll((long long)M));
             A.last_t = prev_t;
         }
         if (ib) {
@@ -1496,21 +1572,22 @@ __global__ __launch_bounds__(FD_NT) void k_fold(BatchDev b) {
 
 template <int G, int CAP>
 hipError_t launch_fold_v(const BatchDev &b, hipStream_t s) {
-    const size_t shm = FoldShape<CAP>::lds_bytes() + (((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15);
+    const size_t tb_bytes = ((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15;
+    const size_t shm = tb_bytes + (size_t)G * FoldShape<CAP>::wave_bytes();
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_fold<G, CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(FoldShape<CAP>::lds_bytes() + TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16));
+        (int)(TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16 + (size_t)G * FoldShape<CAP>::wave_bytes()));
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_fold<G, CAP>), dim3(((b.total_groups + 7) / 8) * 8), dim3(FD_NT), shm, s, b);
+    hipLaunchKernelGGL((k_fold<G, CAP>), dim3(((b.total_groups + 7) / 8) * 8), dim3(64 * G), shm, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_fold(const BatchDev &b, hipStream_t s) {
-    const bool wide = b.window_cap > 1024;
+    const bool wide = b.window_cap > 512;
     switch (b.tile_group) {
-    case 4: return wide ? launch_fold_v<4, 4096>(b, s) : launch_fold_v<4, 1024>(b, s);
-    case 2: return wide ? launch_fold_v<2, 4096>(b, s) : launch_fold_v<2, 1024>(b, s);
-    default: return wide ? launch_fold_v<1, 4096>(b, s) : launch_fold_v<1, 1024>(b, s);
+    case 4: return wide ? launch_fold_v<4, 2048>(b, s) : launch_fold_v<4, 512>(b, s);
+    case 2: return wide ? launch_fold_v<2, 2048>(b, s) : launch_fold_v<2, 512>(b, s);
+    default: return wide ? launch_fold_v<1, 2048>(b, s) : launch_fold_v<1, 512>(b, s);
     }
 }
 
@@ -1546,10 +1623,19 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
         if (e != hipSuccess) return e;
         TRIG_MARK("k_fold", 1);
     }
-    TRIG_MARK("k_tscan", 0);
-    hipLaunchKernelGGL(k_tscan, dim3(b.n_slices), dim3(1024), 0, s, b);
-    TRIG_CHECK();
-    TRIG_MARK("k_tscan", 1);
+    {
+        const uint32_t nch = (b.max_tiles + TS_CH - 1) / TS_CH;
+        if (nch > 1) {
+            TRIG_MARK("k_tsum", 0);
+            hipLaunchKernelGGL(k_tsum, dim3(nch, b.n_slices), dim3(TS_NT), 0, s, b);
+            TRIG_CHECK();
+            TRIG_MARK("k_tsum", 1);
+        }
+        TRIG_MARK("k_tscan", 0);
+        hipLaunchKernelGGL(k_tscan, dim3(nch, b.n_slices), dim3(TS_NT), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_tscan", 1);
+    }
     TRIG_MARK("k_place", 0);
     {
         // one wave per tile up to 8 per CU, then persistent waves; a multiple of the 8 XCDs

@@ -36,6 +36,7 @@ namespace trigdev {
 
 constexpr int CHUNK = 1024;       // hits per ingest / bounds item
 constexpr int TILE = 1024;        // ordered hits per trigger tile
+constexpr uint32_t TS_CH = 1024;  // tiles per chunk of the tile scan
 constexpr int HALO_SMALL = 256;   // ordered hits staged on each side of a tile (first pass)
 constexpr int HALO_BIG = 1024;    // the same in the dense-window rerun
 constexpr int GTILE = 4096;       // elements per block of the general radix sort
@@ -146,6 +147,7 @@ struct SliceDev {
     uint32_t *pos;           // run-major: pos[r * (n_seg + 1) + j]
     uint32_t *o_t, *o_pq, *o_idx;   // ordered: t - t_min, pmt << 16 | q, input index
     TileStat *tstat;         // per trigger tile
+    TileAgg *cagg;           // per chunk of TS_CH tiles: their combined summary (tile scan)
     FireRec *fsc;            // per trigger tile, TILE fire slots
     uint64_t *dmask;         // seed bits by ordered position (dense-window rerun only)
     trig_fire *fires;
@@ -165,7 +167,9 @@ struct SliceDev {
     const uint32_t *afl32;   // per PMT: floor rank, 1 apart exactly for consecutive floors (AFC)
     const uint16_t *tbnd;    // table bounds per pair of 32-PMT blocks, nbk x nbk: lower | upper << 8 in
                              // 16 ns units (upper 255: none)
-    uint32_t nbk, nbk_pad;   // blocks per side, 0: no bounds
+    const uint32_t *rmax;    // per PMT: the largest entry of its row of the table
+    uint32_t nbk;            // blocks per side, 0: no bounds
+    uint32_t thr_max;        // the largest entry of the table
 };
 
 constexpr int TBND_SHIFT = 5;   // 32 PMTs per block of the table bounds
@@ -191,6 +195,7 @@ struct BatchDev {
     // maps every group to its slice (written by k_plan; unused for one slice)
     uint32_t tile_group, window_cap;
     uint32_t total_groups;
+    uint32_t max_tiles;      // the most tiles of one slice (the tile scan's grid)
     uint32_t tbnd_lds;       // table-bound entries the counting kernel stages in LDS (0: none)
     uint32_t *group_slice;
 };
@@ -266,6 +271,18 @@ __device__ __forceinline__ T wave_shr1(const T &v, const T &id) { return dpp_wor
 // Value of lane `src` (uniform) in every lane.
 __device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+// A word-sized struct of lane `src` (uniform) in every lane.
+template <class T>
+__device__ __forceinline__ T lane_read_all(const T &v, int src) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized values only");
+    T r;
+    const uint32_t *pv = (const uint32_t *)&v;
+    uint32_t *pr = (uint32_t *)&r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) pr[i] = lane_read(pv[i], src);
+    return r;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -378,6 +395,24 @@ __device__ __forceinline__ uint32_t find_slice(uint32_t n_slices, uint32_t item,
     return lo ? lo - 1 : 0;
 }
 
+// The same for work items met in increasing order, from slice `from` (at or
+// before the item's): a few steps forward, then a binary search over the rest.
+template <class BaseOf>
+__device__ __forceinline__ uint32_t find_slice_from(uint32_t n_slices, uint32_t from, uint32_t item, BaseOf base_of) {
+    if (n_slices <= 1) return 0;
+    uint32_t s = from;
+    for (int k = 0; k < 4; ++k) {
+        if (s + 1 >= n_slices || base_of(s + 1) > item) return s;
+        ++s;
+    }
+    uint32_t lo = s + 1, hi = n_slices;   // first index with base > item, in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base_of(mid) <= item) lo = mid + 1; else hi = mid;
+    }
+    return lo - 1;
+}
+
 // First tile / chunk of slice si in the launch's numbering: a one-slice launch
 // (one slice of a larger batch rerun on its own) numbers from 0.
 __device__ __forceinline__ uint32_t tile_base_of(const BatchDev &b, uint32_t si) {
@@ -412,15 +447,21 @@ __device__ __forceinline__ TRIG_GAS uint32_t *level1_index(const SliceDev &S) {
 
 // Plain rule: every tile's seeds, compacted in time order by the seed kernel and
 // read by the fold kernel: time (t - t_min) and pmt << 16 | position in the tile,
-// TILE slots per tile each, then the seed count of every tile.  They live in the
-// boundary-table area, unused once the ordering is done (3n + 65536 words hold
-// 2 TILE n_tiles + n_tiles).
+// TILE slots per tile each, then a record per tile (seed count, first and last
+// seed time).  They live in the boundary-table area, unused once the ordering is
+// done (3n + 65536 words hold 2 TILE n_tiles + 4 n_tiles).
+struct SeedRec {
+    uint32_t n;          // seeds of the tile
+    uint32_t first_t;    // t - t_min of its first and last seed (n > 0)
+    uint32_t last_t;
+    uint32_t pad;
+};
 __device__ __forceinline__ TRIG_GAS uint32_t *seed_t(const SliceDev &S) { return gmem(S.pos); }
 __device__ __forceinline__ TRIG_GAS uint32_t *seed_p(const SliceDev &S) {
     return gmem(S.pos) + (uint64_t)S.n_tiles * TILE;
 }
-__device__ __forceinline__ TRIG_GAS uint32_t *seed_n(const SliceDev &S) {
-    return gmem(S.pos) + 2ull * S.n_tiles * TILE;
+__device__ __forceinline__ TRIG_GAS SeedRec *seed_rec(const SliceDev &S) {
+    return (TRIG_GAS SeedRec *)(gmem(S.pos) + 2ull * S.n_tiles * TILE);
 }
 
 __device__ __forceinline__ bool slice_in_tail(const BatchDev &b, uint32_t state) {

@@ -23,16 +23,16 @@ def test_count_candidates_are_valid_tunings():
     from paper_1411_3968_amd import autotune
     assert len(set(autotune.COUNT_CANDIDATES)) == len(autotune.COUNT_CANDIDATES)
     for g, h in autotune.COUNT_CANDIDATES:
-        assert g in (1, 2, 4) and h in (1024, 4096)
+        assert g in (1, 2, 4) and h in (512, 2048)
 
 
 def test_cache_roundtrip_format(tmp_path):
     from paper_1411_3968_amd import autotune
-    res = [dict(n_pmt_max=84, best=dict(seg_cap=512, seg_target=256, grid_per_cu=3, tile_group=2, window_cap=1024,
+    res = [dict(n_pmt_max=84, best=dict(seg_cap=512, seg_target=256, grid_per_cu=3, tile_group=2, window_cap=512,
                                         s=0.01), trials=[])]
     path = str(tmp_path / "tune.json")
     autotune.save(path, res, device="test")
     doc = json.load(open(path))
     assert doc["device"] == "test"
     assert doc["classes"] == [dict(n_pmt_max=84, seg_cap=512, seg_target=256, grid_per_cu=3, tile_group=2,
-                                   window_cap=1024)]
+                                   window_cap=512)]

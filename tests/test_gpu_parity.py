@@ -287,20 +287,20 @@ def test_fold_window_past_staged_tiles(tr, orc):
     assert got["n_fires"] > 0
 
 
-@pytest.mark.parametrize("window_cap", [1024, 4096])
+@pytest.mark.parametrize("window_cap", [512, 2048])
 def test_floor_burst_denser_than_staged_neighbours(T, tr, orc, window_cap):
-    """3000 hits on the four PMTs of one floor within 60 ns, none over the charge
+    """1500 hits on the four PMTs of one floor within 30 ns, none over the charge
     threshold (every hit a floor-coincidence seed): the seed kernel searches
-    partners past its staged neighbours, and the fold windows hold 3000 seeds (in
-    device memory with a 1024-seed LDS window, staged with 4096)."""
+    partners past its staged neighbours, and the fold windows hold 1500 seeds (in
+    device memory with a 512-seed LDS window, staged with 2048)."""
     from gen import configs as C
     w = C.nemo(seed=13, length_ns=20_000_000, n_tracks=2)
     g, thr = w.geoms["nemo"]
     s = w.slices[0][1]
     rng = np.random.default_rng(11)
-    k = 3000
+    k = 1500
     floor0 = np.flatnonzero(g.floor_id == g.floor_id[0])[:4].astype(np.uint16)
-    bt = np.sort(s.t)[30000] + 1 + np.sort(rng.integers(0, 60, size=k))
+    bt = np.sort(s.t)[30000] + 1 + np.sort(rng.integers(0, 30, size=k))
     bp = rng.choice(floor0, size=k).astype(np.uint16)
     bq = rng.integers(0, 200, size=k).astype(np.uint16)
     order = np.lexsort((bt, bp))
