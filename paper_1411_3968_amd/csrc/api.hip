@@ -512,6 +512,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         for (const SliceInfo &si : slices)
             if (si.host_status == TRIG_OK) nb_max = std::max(nb_max, si.dev.nbk);
         batch.tbnd_lds = nb_max && nb_max <= (uint32_t)TBND_LDS_MAX ? nb_max * nb_max : 0u;
+        batch.any_bounds = nb_max ? 1u : 0u;
     }
     batch.total_groups = total_groups;
     batch.group_slice = d_group_slice;

@@ -931,7 +931,7 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
 // SD_HS ordered neighbours on each side (whole 64-hit words, sized from the
 // slice's mean density to span t_floor_ns) are staged in LDS, a hit per lane and
 // round; the charge seeds and level-0 bits of a round's 64-hit word come from two
-// ballots.  Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., four
+// ballots.  Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., two
 // distances per step, while any lane of the wave still has a successor within
 // t_floor_ns; a pair marks both hits.  A tile whose staged neighbours do not span
 // t_floor_ns (a burst of near-equal times) searches each hit's partners on both
@@ -950,7 +950,7 @@ struct SeedShape {
     static_assert(STG % NT == 0 && SD_HS % 64 == 0, "stage layout");
 };
 
-__global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) {
+__global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     using Sh = SeedShape;
     constexpr int NT = Sh::NT, U = Sh::U, NWD = Sh::NWD;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -960,7 +960,6 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
     uint64_t *lw = qw + NWD;                    // level-0 pass bits per word
     uint64_t *pw = lw + NWD;                    // partner bits from pairs 64 or more apart
     uint64_t *pin = pw + NWD;                   // partner bits from the word before
-    uint16_t *lfl = (uint16_t *)(pin + NWD);    // dense floor index of every PMT (floor_lds of them)
     __shared__ uint32_t wpre[TILE / 64 + 1];
 
     // XCD-aware order: workgroup b runs on XCD b % 8 and takes tiles from that
@@ -982,7 +981,6 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
     const TRIG_GAS uint64_t *l0m = gmem(S.l0m);
     TRIG_GAS uint32_t *sd_t = seed_t(S) + (uint64_t)k * TILE;
     TRIG_GAS uint32_t *sd_p = seed_p(S) + (uint64_t)k * TILE;
-    const uint32_t n_pmt = S.n_pmt;
     const uint64_t n = S.n;
     const uint64_t a = (uint64_t)k * TILE;
     if (a >= n) {   // the one tile of an empty slice
@@ -1015,9 +1013,6 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
         vt[u] = o_t[sl + x];
         vp[u] = o_pq[sl + x];
     }
-    const bool floor_in_lds = n_pmt <= floor_lds;
-    if (floor_in_lds)
-        for (uint32_t x = threadIdx.x; x < n_pmt; x += NT) lfl[x] = floor16[x];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t x = u * NT + threadIdx.x;
@@ -1038,13 +1033,13 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
         }
         st[x] = vt[u];   // (positions past the stage are never read)
     }
-    __syncthreads();   // floor numbering and times staged
+    // the floor numbering, gathered from the table in device memory (a few KB,
+    // cache-resident: cheaper than a copy in LDS per tile)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t x = u * NT + threadIdx.x;
         const uint32_t p = vp[u] >> 16;
-        const uint32_t f = floor_in_lds ? (uint32_t)lfl[p] : (uint32_t)floor16[p];
-        vp[u] = (p << 16) | f;
+        vp[u] = (p << 16) | (uint32_t)floor16[p];
         spf[x] = vp[u];
     }
     __syncthreads();
@@ -1081,7 +1076,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
             const uint32_t t = vt[u], f = vp[u];
             const bool l0x = ((lw[wd] >> lane) & 1ull) != 0;
             uint64_t own = 0, fwd0 = 0, fwd1 = 0;
-            constexpr int DU = 4;
+            constexpr int DU = 2;   // distances per step, their reads issued together
             for (uint32_t d0 = 1;; d0 += DU) {
                 uint32_t ty[DU], gy[DU];
 #pragma unroll
@@ -1091,9 +1086,10 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
                     gy[kk] = spf[yc];
                 }
                 bool near = false;
+                uint32_t prb = 0;   // bit kk: a pair at distance d0 + kk
 #pragma unroll
                 for (int kk = 0; kk < DU; ++kk) {
-                    const uint32_t d = d0 + kk, y = x + d;
+                    const uint32_t y = x + d0 + kk;
                     near = in0 & (y < len) & (ty[kk] - t <= tau_u);
                     bool l0y = true;
                     if (L0) {
@@ -1101,18 +1097,27 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
                         l0y = ((lw[yc >> 6] >> (yc & 63)) & 1ull) != 0;
                     }
                     const bool pr = near & (((gy[kk] ^ f) & 0xFFFFu) == 0u) & ((gy[kk] >> 16) != (f >> 16)) & l0x & l0y;
-                    const uint64_t M = __ballot(pr);
-                    own |= M;
-                    if (M) {
-                        if (d < 64) {
-                            fwd0 |= M << d;
-                            fwd1 |= M >> (64 - d);
-                        } else if (lane == 0) {
-                            const uint32_t sft = d & 63, w0 = wd + (d >> 6);
-                            atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << sft));
-                            const uint64_t spill = sft ? (M >> (64 - sft)) : 0ull;
-                            if (spill && w0 + 1 < (uint32_t)NWD)
-                                atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                    prb |= (uint32_t)pr << kk;
+                }
+                // pairs are rare (another PMT of the same floor): one ballot asks
+                // for any, the distances are taken apart only when there is one
+                if (__ballot(prb != 0u)) {
+#pragma unroll
+                    for (int kk = 0; kk < DU; ++kk) {
+                        const uint32_t d = d0 + kk;
+                        const uint64_t M = __ballot(((prb >> kk) & 1u) != 0u);
+                        own |= M;
+                        if (M) {
+                            if (d < 64) {
+                                fwd0 |= M << d;
+                                fwd1 |= M >> (64 - d);
+                            } else if (lane == 0) {
+                                const uint32_t sft = d & 63, w0 = wd + (d >> 6);
+                                atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << sft));
+                                const uint64_t spill = sft ? (M >> (64 - sft)) : 0ull;
+                                if (spill && w0 + 1 < (uint32_t)NWD)
+                                    atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
+                            }
                         }
                     }
                 }
@@ -1200,14 +1205,12 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b, uint32_t floor_lds) 
     }
 }
 
-hipError_t launch_seed(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
-    const uint32_t floor_lds = max_pmt <= (uint32_t)FLOOR_LDS_MAX ? max_pmt : 0u;
-    const size_t shm = SeedShape::lds_bytes() + (((floor_lds + 1) & ~1u) * 2);
-    static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_seed, hipFuncAttributeMaxDynamicSharedMemorySize,
-        (int)(SeedShape::lds_bytes() + FLOOR_LDS_MAX * 2 + 4));
+hipError_t launch_seed(const BatchDev &b, hipStream_t s) {
+    const size_t shm = SeedShape::lds_bytes();
+    static const hipError_t attr = hipFuncSetAttribute((const void *)k_seed, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)shm);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL(k_seed, dim3(((b.total_tiles + 7) / 8) * 8), dim3(SD_NT), shm, s, b, floor_lds);
+    hipLaunchKernelGGL(k_seed, dim3(((b.total_tiles + 7) / 8) * 8), dim3(SD_NT), shm, s, b);
     return hipGetLastError();
 }
 
@@ -1223,10 +1226,10 @@ hipError_t launch_seed(const BatchDev &b, uint32_t max_pmt, hipStream_t s) {
 // time).  Its seeds, concatenated in time order, are staged in the wave's LDS (at
 // most CAP; a larger window is read from the lists in device memory).  A lane per
 // seed counts, over its stretch of the window (bounds by fixed-count binary
-// searches), the other seeds within min(thr, w_ns), eight table reads in flight;
-// for large detectors the pair of the two PMTs' 32-PMT blocks has a lower and an
-// upper bound of thr (16 ns units) that decide most pairs, and the table is read
-// only for the rest.  Each round of 64 seeds then writes its fires to the tile's
+// searches), the other seeds within min(thr, w_ns), four or eight table reads in
+// flight; for large detectors the pair of the two PMTs' 32-PMT blocks has a lower
+// and an upper bound of thr (16 ns units) that decide most pairs, and the table
+// is read only for the rest.  Each round of 64 seeds then writes its fires to the tile's
 // slot and adds them to the tile's summary (TileAgg).
 constexpr int FD_TMAX = 64;   // window tiles staged at most
 
@@ -1235,7 +1238,7 @@ struct FoldShape {
     static constexpr size_t wave_bytes() { return (size_t)CAP * 8; }   // per wave: time, pmt << 16 | position
 };
 
-template <int G, int CAP>
+template <int G, int CAP, bool BOUNDS>
 __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     constexpr int NT = 64 * G;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -1402,7 +1405,11 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     const bool t16 = W <= 65535u;
     uint32_t top = 1;   // the largest power of two <= tot
     while (top * 2 <= tot) top *= 2;
-    constexpr int CB = 8;
+    // table reads in flight per lane and step: eight in the variant for batches
+    // with large detectors (32-PMT block bounds decide most pairs of their dense
+    // windows; the slices without bounds in such a batch share the loop), four
+    // in the one for towers only (every pair reads the table; short windows)
+    constexpr int CB = BOUNDS ? 8 : 4;
 
     // fold of one seed (time ti, PMT pi, window index self) over window entries
     // [jlo, jhi) read through T_at / P_at
@@ -1414,7 +1421,7 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
         for (uint32_t j0 = jlo;; j0 += CB) {
             if (!__ballot(j0 < jhi)) break;
             uint32_t dd[CB], lim[CB];
-            if (bounds) {
+            if (BOUNDS && bounds) {
                 uint32_t bb[CB], pj[CB];
 #pragma unroll
                 for (int kk = 0; kk < CB; ++kk) {
@@ -1570,25 +1577,31 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     if (lane == 0) gstore(&gmem(S.tstat)[kt].agg, A);
 }
 
-template <int G, int CAP>
+template <int G, int CAP, bool BOUNDS>
 hipError_t launch_fold_v(const BatchDev &b, hipStream_t s) {
     const size_t tb_bytes = ((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15;
     const size_t shm = tb_bytes + (size_t)G * FoldShape<CAP>::wave_bytes();
     static const hipError_t attr = hipFuncSetAttribute(
-        (const void *)k_fold<G, CAP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        (const void *)k_fold<G, CAP, BOUNDS>, hipFuncAttributeMaxDynamicSharedMemorySize,
         (int)(TBND_LDS_MAX * TBND_LDS_MAX * 2 + 16 + (size_t)G * FoldShape<CAP>::wave_bytes()));
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_fold<G, CAP>), dim3(((b.total_groups + 7) / 8) * 8), dim3(64 * G), shm, s, b);
+    hipLaunchKernelGGL((k_fold<G, CAP, BOUNDS>), dim3(((b.total_groups + 7) / 8) * 8), dim3(64 * G), shm, s, b);
     return hipGetLastError();
 }
 
-hipError_t launch_fold(const BatchDev &b, hipStream_t s) {
+template <bool BOUNDS>
+hipError_t launch_fold_b(const BatchDev &b, hipStream_t s) {
     const bool wide = b.window_cap > 512;
     switch (b.tile_group) {
-    case 4: return wide ? launch_fold_v<4, 2048>(b, s) : launch_fold_v<4, 512>(b, s);
-    case 2: return wide ? launch_fold_v<2, 2048>(b, s) : launch_fold_v<2, 512>(b, s);
-    default: return wide ? launch_fold_v<1, 2048>(b, s) : launch_fold_v<1, 512>(b, s);
+    case 4: return wide ? launch_fold_v<4, 2048, BOUNDS>(b, s) : launch_fold_v<4, 512, BOUNDS>(b, s);
+    case 2: return wide ? launch_fold_v<2, 2048, BOUNDS>(b, s) : launch_fold_v<2, 512, BOUNDS>(b, s);
+    default: return wide ? launch_fold_v<1, 2048, BOUNDS>(b, s) : launch_fold_v<1, 512, BOUNDS>(b, s);
     }
+}
+
+// The variant with table bounds when a slice of the batch has them.
+hipError_t launch_fold(const BatchDev &b, hipStream_t s) {
+    return b.any_bounds ? launch_fold_b<true>(b, s) : launch_fold_b<false>(b, s);
 }
 
 }  // namespace
@@ -1615,7 +1628,7 @@ static hipError_t launch_trigger(const BatchDev &b, uint32_t max_pmt, uint32_t n
         TRIG_MARK("k_tile", 1);
     } else {
         TRIG_MARK("k_seed", 0);
-        hipError_t e = launch_seed(b, max_pmt, s);
+        hipError_t e = launch_seed(b, s);
         if (e != hipSuccess) return e;
         TRIG_MARK("k_seed", 1);
         TRIG_MARK("k_fold", 0);

@@ -196,7 +196,8 @@ struct BatchDev {
     uint32_t tile_group, window_cap;
     uint32_t total_groups;
     uint32_t max_tiles;      // the most tiles of one slice (the tile scan's grid)
-    uint32_t tbnd_lds;       // table-bound entries the counting kernel stages in LDS (0: none)
+    uint32_t tbnd_lds;       // table-bound entries the fold kernel stages in LDS (0: none)
+    uint32_t any_bounds;     // some slice has table bounds (the fold kernel's variant)
     uint32_t *group_slice;
 };
 
