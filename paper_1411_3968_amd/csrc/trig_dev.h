@@ -422,7 +422,27 @@ __device__ __forceinline__ uint32_t tile_base_of(const BatchDev &b, uint32_t si)
 __device__ __forceinline__ uint32_t chunk_base_of(const BatchDev &b, uint32_t si) {
     return b.n_slices <= 1 ? 0u : b.chunk_bases[si];
 }
-// Groups of the counting kernel of a slice with n_tiles tiles.
+// Boundary table of the ordering stage: entry (j, r) = the first position of run
+// r at or after segment boundary j.  Rows j come in tiles of TJ consecutive
+// boundaries, run-major inside a tile.  With TJ = BND_TJ one run's entries for 16
+// consecutive boundaries are one 64-byte stretch, written whole by the chunk that
+// crosses them (neighbouring segments read the same lines): the single-level and
+// level-1 tables.  Level 2 of the two-level ordering (a few dozen long runs) keeps
+// TJ = 1, a segment's entries over all runs contiguous: its ordering kernel reads
+// them far more often than they are written (measured on the 2688-PMT block: 273
+// against 427 us for that kernel).
+constexpr uint32_t BND_TJ = 16;
+template <uint32_t TJ>
+__host__ __device__ __forceinline__ uint64_t bnd_at(uint32_t j, uint32_t r, uint64_t R) {
+    return (uint64_t)(j / TJ) * R * TJ + (uint64_t)r * TJ + (j % TJ);
+}
+// Entries of a table of `rows` boundaries over R runs.
+template <uint32_t TJ>
+__host__ __device__ __forceinline__ uint64_t bnd_entries(uint64_t rows, uint64_t R) {
+    return ((rows + TJ - 1) / TJ) * TJ * R;
+}
+
+// Groups of the fold kernel of a slice with n_tiles tiles.
 __host__ __device__ __forceinline__ uint32_t groups_of(uint32_t n_tiles, uint32_t tile_group) {
     return (n_tiles + tile_group - 1) / tile_group;
 }
