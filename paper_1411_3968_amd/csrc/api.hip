@@ -194,7 +194,9 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
 static size_t desc_upload_bytes(uint32_t n) { return n * sizeof(SliceDev) + 2 * (size_t)n * sizeof(uint32_t); }
 
 size_t job_meta_bytes(uint32_t n, uint32_t total_tiles) {
-    return align256(desc_upload_bytes(n)) + align256(n * sizeof(Plan)) + 256 + align256((size_t)total_tiles * 4);
+    // descriptors, plans, counters, then the maps from groups, tiles and chunks
+    // to their slice (at most total_tiles entries each)
+    return align256(desc_upload_bytes(n)) + align256(n * sizeof(Plan)) + 256 + 3 * align256((size_t)total_tiles * 4);
 }
 
 // Fixed memory: descriptors, plans and counters, then the radix scratch of
@@ -388,8 +390,10 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     d_plans = (Plan *)(meta + align256(desc_upload_bytes(n)));
     // (the counters are written by k_bounds before any kernel reads them)
     d_counters = (uint32_t *)((char *)d_plans + align256(n * sizeof(Plan)));
-    // (the group map is written by k_plan before the counting kernel reads it)
+    // (the group, tile and chunk maps are written by k_plan before any kernel reads them)
     d_group_slice = (uint32_t *)((char *)d_counters + 256);
+    d_tile_slice = (uint32_t *)((char *)d_group_slice + align256((size_t)total_tiles * 4));
+    d_chunk_slice = (uint32_t *)((char *)d_tile_slice + align256((size_t)total_tiles * 4));
     for (uint32_t i = 0; i < n; ++i) {
         SliceInfo &si = slices[i];
         SliceDev S;
@@ -516,6 +520,8 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
     }
     batch.total_groups = total_groups;
     batch.group_slice = d_group_slice;
+    batch.tile_slice = d_tile_slice;
+    batch.chunk_slice = d_chunk_slice;
     return TRIG_OK;
 }
 

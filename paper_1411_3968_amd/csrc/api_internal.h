@@ -82,7 +82,7 @@ struct Job {
     uint32_t wave_cap = 0;            // variant of the wave-per-segment kernel (largest tuned capacity)
     uint32_t total_chunks = 0, total_tiles = 0;
     uint32_t tile_group = 1, window_cap = 512, total_groups = 0;   // fold-kernel launch shape
-    uint32_t *d_group_slice = nullptr;
+    uint32_t *d_group_slice = nullptr, *d_tile_slice = nullptr, *d_chunk_slice = nullptr;
     uint32_t max_pmt = 0;             // largest PMT count among the slices' geometries
     DevBuf ws, dmeta, gscratch;
     PinBuf h_slices, h_plans;

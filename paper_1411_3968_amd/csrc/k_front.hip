@@ -230,11 +230,14 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         }
     }
     if (threadIdx.x == 0) *P = p;
-    // the counting kernel's map from its groups to their slice (every slice,
-    // whatever its state: each group looks its slice up there)
+    // the maps from the fold kernel's groups, from tiles and from chunks to their
+    // slice (every slice, whatever its state: each work item looks its slice up
+    // there)
     if (b.n_slices > 1 && b.group_slice) {
         const uint32_t ng = groups_of(S.n_tiles, b.tile_group);
         for (uint32_t g = threadIdx.x; g < ng; g += NT) b.group_slice[S.group_base + g] = si;
+        for (uint32_t t = threadIdx.x; t < S.n_tiles; t += NT) b.tile_slice[S.tile_base + t] = si;
+        for (uint32_t c = threadIdx.x; c < S.n_chunks; c += NT) b.chunk_slice[S.chunk_base + c] = si;
     }
 }
 
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         else build_segment_lists(b);
         return;
     }
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
+    const uint32_t si = slice_of_chunk(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
@@ -375,7 +378,7 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
 __global__ __launch_bounds__(256) void k_ingest2(BatchDev b) {
     constexpr int NT = 256, PER = CHUNK / NT;
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
+    const uint32_t si = slice_of_chunk(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;

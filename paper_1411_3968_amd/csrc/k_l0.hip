@@ -33,7 +33,7 @@ constexpr int DN_HALO = 512;
 
 __global__ __launch_bounds__(NTL) void k_l0_ok(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     uint32_t k;
     if (!l0_slice(b, S, k, si, item)) return;
@@ -87,7 +87,7 @@ __device__ __forceinline__ bool bit_at(const TRIG_GAS uint64_t *wv, uint64_t j) 
 
 __global__ __launch_bounds__(NTL) void k_l0_pass(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     uint32_t k;
     if (!l0_slice(b, S, k, si, item)) return;

@@ -31,7 +31,7 @@ __device__ __forceinline__ bool tag_slice(const SliceDev &S, const TRIG_GAS Plan
 
 __global__ __launch_bounds__(NTT) void k_tag_bits(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(1024) void k_tag_scan(BatchDev b) {
 __global__ __launch_bounds__(NTT) void k_tag_write(BatchDev b) {
     constexpr int WPT = TILE / 64;   // tag words per tile
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;

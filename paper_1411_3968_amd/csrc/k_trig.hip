@@ -164,7 +164,7 @@ __global__ __launch_bounds__(NT) void k_tile(BatchDev b, uint32_t floor_lds) {
     const uint32_t per_xcd = (b.total_tiles + 7) / 8;
     const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (item >= b.total_tiles) return;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
@@ -790,7 +790,7 @@ __global__ __launch_bounds__(64) void k_place(BatchDev b) {
     const uint32_t end = (item + per < x1) ? item + per : x1;
     const int lane = lane_id();
     while (item < end) {
-        const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+        const uint32_t si = slice_of_tile(b, item);
         const SliceDev &S = b.slices[si];
         const uint32_t base = tile_base_of(b, si);
         uint32_t s_end = base + S.n_tiles;          // first item past this slice
@@ -825,7 +825,7 @@ constexpr int NTD = 256;
 
 __global__ __launch_bounds__(NTD) void k_dseed(BatchDev b) {
     const uint32_t item = blockIdx.x;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
@@ -967,7 +967,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const uint32_t per_xcd = (b.total_tiles + 7) / 8;
     const uint32_t item = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (item >= b.total_tiles) return;
-    const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.tile_bases[i]; });
+    const uint32_t si = slice_of_tile(b, item);
     const SliceDev &S = b.slices[si];
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
@@ -995,9 +995,11 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const bool L0 = b.prm.l0_n > 0;
     const int lane = lane_id(), w = threadIdx.x >> 6;
 
-    // halo: twice the mean number of hits in t_floor_ns, plus 64, in whole words
-    uint64_t halo = tau < 0 ? 0ull : (2ull * n * (tau_u + 1ull)) / (span + 1) + 64;
-    halo = (halo + 63) & ~63ull;
+    // halo: four times the mean number of hits in t_floor_ns, at least one word, in
+    // whole words (a burst that outruns it takes the search past the stage below)
+    uint64_t halo = tau < 0 ? 0ull : (4ull * n * (tau_u + 1ull)) / (span + 1);
+    halo = halo < 64 ? 64 : (halo + 63) & ~63ull;
+    if (tau < 0) halo = 0;
     if (halo > (uint64_t)SD_HS) halo = SD_HS;
     const uint64_t sl = a >= halo ? a - halo : 0;   // (a is a multiple of TILE: sl = a - halo or 0)
     const uint64_t she = (e + halo < n) ? e + halo : n;
@@ -1005,7 +1007,8 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const uint32_t a_loc = (uint32_t)(a - sl), e_loc = (uint32_t)(e - sl);   // a_loc: whole words
 
     // 1. stage: all loads of a thread in flight (positions past the stage read its
-    // last hit), then the words of each round
+    // last hit; skipping the rounds past it, under branches, was slower), then the
+    // words of each round
     uint32_t vt[U], vp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {

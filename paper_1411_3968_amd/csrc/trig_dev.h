@@ -199,6 +199,9 @@ struct BatchDev {
     uint32_t tbnd_lds;       // table-bound entries the fold kernel stages in LDS (0: none)
     uint32_t any_bounds;     // some slice has table bounds (the fold kernel's variant)
     uint32_t *group_slice;
+    // the slice of every tile and of every chunk of the launch (written by k_plan
+    // for the kernels after it; a one-slice launch reads none)
+    uint32_t *tile_slice, *chunk_slice;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -440,6 +443,14 @@ __host__ __device__ __forceinline__ uint64_t bnd_at(uint32_t j, uint32_t r, uint
 template <uint32_t TJ>
 __host__ __device__ __forceinline__ uint64_t bnd_entries(uint64_t rows, uint64_t R) {
     return ((rows + TJ - 1) / TJ) * TJ * R;
+}
+
+// The slice of tile / chunk `item` of a launch that k_plan has mapped.
+__device__ __forceinline__ uint32_t slice_of_tile(const BatchDev &b, uint32_t item) {
+    return b.n_slices <= 1 ? 0u : gmem(b.tile_slice)[item];
+}
+__device__ __forceinline__ uint32_t slice_of_chunk(const BatchDev &b, uint32_t item) {
+    return b.n_slices <= 1 ? 0u : gmem(b.chunk_slice)[item];
 }
 
 // Groups of the fold kernel of a slice with n_tiles tiles.
