@@ -927,40 +927,44 @@ hipError_t launch_tile(const BatchDev &b, uint32_t max_pmt, uint32_t n_cu, hipSt
 // ------------------------------------------------------------------ k_seed
 // L1 seeds of the plain rule (Sec. 3 and Sec. 4.2: charge over threshold, or
 // another PMT of the same floor within t_floor_ns; with level 0 on, the hit and
-// its partner must pass it), one workgroup per ordered tile.  The tile and up to
+// its partner must pass it), one 256-thread workgroup per ordered tile, each
+// thread owning four consecutive hits of the tile (16-byte loads; their times,
+// PMTs, floors, charges and level-0 bits stay in registers).  The tile and up to
 // SD_HS ordered neighbours on each side (whole 64-hit words, sized from the
-// slice's mean density to span t_floor_ns) are staged in LDS, a hit per lane and
-// round; the charge seeds and level-0 bits of a round's 64-hit word come from two
-// ballots.  Floor coincidences are found as pairs (x, x + d), d = 1, 2, ..., two
-// distances per step, while any lane of the wave still has a successor within
-// t_floor_ns; a pair marks both hits.  A tile whose staged neighbours do not span
-// t_floor_ns (a burst of near-equal times) searches each hit's partners on both
-// sides instead, reading past the stage from global memory.  The tile's seeds are
-// written compacted, in time order, to its seed list, with its record (count,
-// first and last seed time).
+// slice's mean density to span t_floor_ns) are staged in LDS.  A thread checks
+// the pairs of its four hits among themselves and with the next four staged hits
+// (one 16-byte LDS read of times and one of floors: distances up to 7), and
+// reads further blocks of four only while its last hit's successors are still
+// within t_floor_ns; a pair of two PMTs of one floor marks both hits (a partner
+// ahead of the thread's own hits through an LDS atomic: pairs are rare).  Hits
+// within t_floor_ns of the tile's start also look back into the left halo.  A
+// tile whose staged neighbours do not span t_floor_ns (a burst of near-equal
+// times) searches each hit's partners on both sides instead, reading past the
+// stage from global memory.  The tile's seeds are written compacted, in time
+// order (one block scan of the threads' counts), to its seed list, with its
+// record (count, first and last seed time).
 constexpr int SD_NT = 256;
-constexpr int SD_HS = 256;   // staged neighbours per side at most
+constexpr int SD_HS = 256;   // staged neighbours per side at most (whole words)
+constexpr int SD_PL = 4;     // consecutive hits per thread
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));   // 16-byte loads and stores
 
 struct SeedShape {
     static constexpr int NT = SD_NT;
     static constexpr int STG = TILE + 2 * SD_HS;
-    static constexpr int U = STG / NT;
     static constexpr int NWD = STG / 64;
-    static constexpr size_t lds_bytes() { return (size_t)STG * 4 * 2 + (size_t)NWD * 8 * 4; }
-    static_assert(STG % NT == 0 && SD_HS % 64 == 0, "stage layout");
+    static constexpr size_t lds_bytes() { return (size_t)STG * 4 * 2 + (size_t)NWD * 8 * 2; }
+    static_assert(TILE == NT * SD_PL && SD_HS % 64 == 0, "stage layout");
 };
 
 __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     using Sh = SeedShape;
-    constexpr int NT = Sh::NT, U = Sh::U, NWD = Sh::NWD;
+    constexpr int NT = Sh::NT, NWD = Sh::NWD;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *st = (uint32_t *)smem;            // staged t - t_min
     uint32_t *spf = st + Sh::STG;               // staged pmt << 16 | dense floor index
-    uint64_t *qw = (uint64_t *)(spf + Sh::STG); // charge seeds, then all seeds, per word
-    uint64_t *lw = qw + NWD;                    // level-0 pass bits per word
-    uint64_t *pw = lw + NWD;                    // partner bits from pairs 64 or more apart
-    uint64_t *pin = pw + NWD;                   // partner bits from the word before
-    __shared__ uint32_t wpre[TILE / 64 + 1];
+    uint64_t *lw = (uint64_t *)(spf + Sh::STG); // level-0 pass bits per word (level 0 on)
+    uint64_t *mk = lw + NWD;                    // partner marks per word
+    __shared__ uint32_t wsum[NT / 64 + 1];
 
     // XCD-aware order: workgroup b runs on XCD b % 8 and takes tiles from that
     // XCD's contiguous eighth of the list (neighbouring tiles share halos in one L2)
@@ -993,7 +997,8 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
     const uint32_t q_seed = b.prm.q_seed;
     const bool L0 = b.prm.l0_n > 0;
-    const int lane = lane_id(), w = threadIdx.x >> 6;
+    const uint32_t tid = threadIdx.x;
+    const int lane = lane_id(), w = (int)(tid >> 6);
 
     // halo: four times the mean number of hits in t_floor_ns, at least one word, in
     // whole words (a burst that outruns it takes the search past the stage below)
@@ -1003,209 +1008,209 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     if (halo > (uint64_t)SD_HS) halo = SD_HS;
     const uint64_t sl = a >= halo ? a - halo : 0;   // (a is a multiple of TILE: sl = a - halo or 0)
     const uint64_t she = (e + halo < n) ? e + halo : n;
-    const uint32_t len = (uint32_t)(she - sl), lastx = len - 1;
+    const uint32_t len = (uint32_t)(she - sl);
     const uint32_t a_loc = (uint32_t)(a - sl), e_loc = (uint32_t)(e - sl);   // a_loc: whole words
+    const uint32_t nwords = (len + 63) / 64;
 
-    // 1. stage: all loads of a thread in flight (positions past the stage read its
-    // last hit; skipping the rounds past it, under branches, was slower), then the
-    // words of each round
-    uint32_t vt[U], vp[U];
+    // 1. this thread's four hits (tile positions 4 tid .. 4 tid + 3), then the
+    // halo's groups of four (by the first threads), all loads in flight; the
+    // floor numbering gathered from the table in device memory (cache-resident)
+    const uint32_t x0 = a_loc + SD_PL * tid;                 // stage position of the first own hit
+    const uint32_t own = e_loc > x0 ? min(e_loc - x0, (uint32_t)SD_PL) : 0u;   // own hits in the tile
+    uint32_t t4[SD_PL], p4[SD_PL];
+    auto load4 = [&](uint32_t x, uint32_t (&tv)[SD_PL], uint32_t (&pv)[SD_PL]) {   // stage positions x .. x + 3
+        if (x + SD_PL <= len) {
+            const u32x4 tq = *(const TRIG_GAS u32x4 *)(o_t + sl + x);
+            const u32x4 pq = *(const TRIG_GAS u32x4 *)(o_pq + sl + x);
+            tv[0] = tq.x; tv[1] = tq.y; tv[2] = tq.z; tv[3] = tq.w;
+            pv[0] = pq.x; pv[1] = pq.y; pv[2] = pq.z; pv[3] = pq.w;
+        } else {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t x = min((uint32_t)(u * NT) + threadIdx.x, lastx);
-        vt[u] = o_t[sl + x];
-        vp[u] = o_pq[sl + x];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t x = u * NT + threadIdx.x;
-        const bool in = x < len;
-        bool l0x = in;
-        if (L0) {
-            const uint64_t j = sl + min(x, lastx);
-            l0x = in & (((l0m[j >> 6] >> (j & 63)) & 1ull) != 0);
+            for (int s = 0; s < SD_PL; ++s) {
+                const uint32_t xc = min(x + (uint32_t)s, len - 1);
+                tv[s] = o_t[sl + xc];
+                pv[s] = o_pq[sl + xc];
+            }
         }
-        const uint64_t lb = __ballot(l0x);
-        const uint64_t qb = __ballot(in & ((vp[u] & 0xFFFFu) >= q_seed)) & lb;
-        const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
-        if (lane == 0) {
-            qw[wd] = qb;
-            lw[wd] = lb;
-            pw[wd] = 0ull;
-            pin[wd] = 0ull;
-        }
-        st[x] = vt[u];   // (positions past the stage are never read)
-    }
-    // the floor numbering, gathered from the table in device memory (a few KB,
-    // cache-resident: cheaper than a copy in LDS per tile)
+    };
+    load4(x0 < len ? x0 : len - 1, t4, p4);
+    // halo groups: [0, a_loc) on the left, [e_loc, len) on the right
+    const uint32_t nhl = a_loc / SD_PL, nh = nhl + (len - e_loc + SD_PL - 1) / SD_PL;
+    const bool has_h = tid < nh;
+    const uint32_t xh = tid < nhl ? SD_PL * tid : e_loc + SD_PL * (tid - nhl);
+    uint32_t th[SD_PL], ph[SD_PL];
+    if (has_h) load4(xh, th, ph);
+    uint32_t q4 = 0;   // charge over threshold, bit s
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t x = u * NT + threadIdx.x;
-        const uint32_t p = vp[u] >> 16;
-        vp[u] = (p << 16) | (uint32_t)floor16[p];
-        spf[x] = vp[u];
+    for (int s = 0; s < SD_PL; ++s) {
+        q4 |= (uint32_t)((uint32_t)s < own && (p4[s] & 0xFFFFu) >= q_seed) << s;
+        const uint32_t p = p4[s] >> 16;
+        p4[s] = (p << 16) | (uint32_t)floor16[p];
+    }
+    if (has_h) {
+#pragma unroll
+        for (int s = 0; s < SD_PL; ++s) {
+            const uint32_t p = ph[s] >> 16;
+            ph[s] = (p << 16) | (uint32_t)floor16[p];
+        }
+    }
+    if (x0 + SD_PL <= Sh::STG) {
+        *(u32x4 *)(st + x0) = u32x4{t4[0], t4[1], t4[2], t4[3]};
+        *(u32x4 *)(spf + x0) = u32x4{p4[0], p4[1], p4[2], p4[3]};
+    }
+    if (has_h) {
+        *(u32x4 *)(st + xh) = u32x4{th[0], th[1], th[2], th[3]};
+        *(u32x4 *)(spf + xh) = u32x4{ph[0], ph[1], ph[2], ph[3]};
+    }
+    if (tid < nwords) {
+        mk[tid] = 0ull;
+        if (L0) lw[tid] = l0m[(sl >> 6) + tid];   // (sl is a whole word)
     }
     __syncthreads();
+    // level-0 pass bit of stage position x (level 0 on)
+    auto l0_at = [&](uint32_t x) -> bool { return !L0 || ((lw[x >> 6] >> (x & 63)) & 1ull); };
+    uint32_t l4 = (1u << SD_PL) - 1u;   // own hits passing level 0
+    if (L0) {
+        l4 = 0;
+#pragma unroll
+        for (int s = 0; s < SD_PL; ++s) l4 |= (uint32_t)l0_at(min(x0 + (uint32_t)s, len - 1)) << s;
+    }
+    q4 &= l4;
+
     const uint32_t ta = st[a_loc], te = st[e_loc - 1];
     // the stage spans t_floor_ns around the tile on both sides (or the slice ends there)
     const bool cover_l = sl == 0 || (uint64_t)st[0] + tau_u < (uint64_t)ta;
     const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + tau_u;
-
+    uint32_t f4 = 0;   // own hits with a floor partner, bit s
+    // a pair of two PMTs of one floor within t_floor_ns (t_y >= t_x), both passing level 0
+    auto pair = [&](uint32_t tx, uint32_t px, uint32_t ty, uint32_t py) -> bool {
+        return (ty - tx <= tau_u) & (((py ^ px) & 0xFFFFu) == 0u) & ((py >> 16) != (px >> 16));
+    };
     if (tau >= 0 && cover_l && cover_r) {
-        // 2. floor-coincidence pairs (x, x + d) for x from the first hit within
-        // t_floor_ns before the tile to the tile's end.  A pair found marks x (the
-        // word's own bits) and x + d: within the word or, for d < 64, in the next
-        // word's incoming bits (written by this wave alone); pairs 64 or more
-        // positions apart (equal times) are ORed into the far bits.  Every value is
-        // computed in every lane (bitwise operators, clamped reads), so the loop
-        // branches only on its exit and on a pair found.
-        uint32_t p_lp;
-        {
-            uint32_t lo = 0, hi = a_loc;   // first stage position with time >= ta - tau
-            const uint64_t tv = (uint64_t)ta >= tau_u ? (uint64_t)ta - tau_u : 0ull;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if ((uint64_t)st[mid] < tv) lo = mid + 1; else hi = mid;
-            }
-            p_lp = lo;
-        }
+        // 2. the own hits among themselves and with the staged hits after them,
+        // four at a time; marks of partners after the own hits go to LDS
+        if (own) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if ((uint32_t)(u * NT + w * 64) >= e_loc) break;   // (wave-uniform)
-            if ((uint32_t)(u * NT + w * 64 + 64) <= p_lp) continue;
-            const uint32_t wd = (uint32_t)(u * NT) / 64 + (uint32_t)w;
-            const uint32_t x = u * NT + threadIdx.x;
-            const bool in0 = x < len;
-            const uint32_t t = vt[u], f = vp[u];
-            const bool l0x = ((lw[wd] >> lane) & 1ull) != 0;
-            uint64_t own = 0, fwd0 = 0, fwd1 = 0;
-            constexpr int DU = 2;   // distances per step, their reads issued together
-            for (uint32_t d0 = 1;; d0 += DU) {
-                uint32_t ty[DU], gy[DU];
+            for (int s = 0; s < SD_PL; ++s)
 #pragma unroll
-                for (int kk = 0; kk < DU; ++kk) {
-                    const uint32_t yc = min(x + d0 + kk, lastx);
-                    ty[kk] = st[yc];
-                    gy[kk] = spf[yc];
+                for (int s2 = s + 1; s2 < SD_PL; ++s2) {
+                    const bool pr = (uint32_t)s2 < own && pair(t4[s], p4[s], t4[s2], p4[s2]) &&
+                                    ((l4 >> s) & (l4 >> s2) & 1u);
+                    f4 |= ((uint32_t)pr << s) | ((uint32_t)pr << s2);
                 }
-                bool near = false;
-                uint32_t prb = 0;   // bit kk: a pair at distance d0 + kk
+            const uint32_t tl = t4[own - 1];   // the last own hit: the one nearest what follows
+            for (uint32_t y0 = x0 + SD_PL;; y0 += SD_PL) {
+                if (y0 >= len || st[y0] - tl > tau_u) break;
+                uint32_t ty[SD_PL], py[SD_PL];
+                if (y0 + SD_PL <= len) {
+                    const u32x4 tq = *(const u32x4 *)(st + y0);
+                    const u32x4 pq = *(const u32x4 *)(spf + y0);
+                    ty[0] = tq.x; ty[1] = tq.y; ty[2] = tq.z; ty[3] = tq.w;
+                    py[0] = pq.x; py[1] = pq.y; py[2] = pq.z; py[3] = pq.w;
+                } else {
 #pragma unroll
-                for (int kk = 0; kk < DU; ++kk) {
-                    const uint32_t y = x + d0 + kk;
-                    near = in0 & (y < len) & (ty[kk] - t <= tau_u);
-                    bool l0y = true;
-                    if (L0) {
-                        const uint32_t yc = min(y, lastx);
-                        l0y = ((lw[yc >> 6] >> (yc & 63)) & 1ull) != 0;
+                    for (int j = 0; j < SD_PL; ++j) {
+                        const uint32_t yc = min(y0 + (uint32_t)j, len - 1);
+                        ty[j] = st[yc];
+                        py[j] = spf[yc];
                     }
-                    const bool pr = near & (((gy[kk] ^ f) & 0xFFFFu) == 0u) & ((gy[kk] >> 16) != (f >> 16)) & l0x & l0y;
-                    prb |= (uint32_t)pr << kk;
                 }
-                // pairs are rare (another PMT of the same floor): one ballot asks
-                // for any, the distances are taken apart only when there is one
-                if (__ballot(prb != 0u)) {
+                uint32_t hit_y = 0;   // staged hits of this block with a partner among the own hits
 #pragma unroll
-                    for (int kk = 0; kk < DU; ++kk) {
-                        const uint32_t d = d0 + kk;
-                        const uint64_t M = __ballot(((prb >> kk) & 1u) != 0u);
-                        own |= M;
-                        if (M) {
-                            if (d < 64) {
-                                fwd0 |= M << d;
-                                fwd1 |= M >> (64 - d);
-                            } else if (lane == 0) {
-                                const uint32_t sft = d & 63, w0 = wd + (d >> 6);
-                                atomicOr((unsigned long long *)&pw[w0], (unsigned long long)(M << sft));
-                                const uint64_t spill = sft ? (M >> (64 - sft)) : 0ull;
-                                if (spill && w0 + 1 < (uint32_t)NWD)
-                                    atomicOr((unsigned long long *)&pw[w0 + 1], (unsigned long long)spill);
-                            }
+                for (int j = 0; j < SD_PL; ++j) {
+                    const bool yin = y0 + (uint32_t)j < len && l0_at(min(y0 + (uint32_t)j, len - 1));
+#pragma unroll
+                    for (int s = 0; s < SD_PL; ++s) {
+                        const bool pr = (uint32_t)s < own && yin && ((l4 >> s) & 1u) && pair(t4[s], p4[s], ty[j], py[j]);
+                        f4 |= (uint32_t)pr << s;
+                        hit_y |= (uint32_t)pr << j;
+                    }
+                }
+                if (hit_y) {   // (rare)
+#pragma unroll
+                    for (int j = 0; j < SD_PL; ++j)
+                        if ((hit_y >> j) & 1u) {
+                            const uint32_t y = y0 + (uint32_t)j;
+                            atomicOr((unsigned long long *)&mk[y >> 6], 1ull << (y & 63));
+                        }
+                }
+            }
+            // own hits within t_floor_ns of the tile's start: partners in the left halo
+            if (a_loc > 0 && t4[0] - st[a_loc - 1] <= tau_u) {
+#pragma unroll
+                for (int s = 0; s < SD_PL; ++s) {
+                    if ((uint32_t)s >= own || !((l4 >> s) & 1u)) continue;
+                    for (uint32_t y = a_loc; y > 0;) {
+                        --y;
+                        if (t4[s] - st[y] > tau_u) break;
+                        if (l0_at(y) && pair(st[y], spf[y], t4[s], p4[s])) {
+                            f4 |= 1u << s;
+                            break;
                         }
                     }
                 }
-                if (!__ballot(near)) break;   // (near at the step's last distance)
-            }
-            if (lane == 0) {
-                qw[wd] |= own | fwd0;
-                if (wd + 1 < (uint32_t)NWD) pin[wd + 1] = fwd1;
             }
         }
     } else if (tau >= 0) {
-        // the stage does not span t_floor_ns: each hit of the tile searches its
-        // partners on both sides, past the stage in global memory
+        // the stage does not span t_floor_ns: each own hit searches its partners on
+        // both sides, past the stage in global memory
         auto T_at = [&](uint64_t m) -> uint32_t { return (m >= sl && m < she) ? st[m - sl] : o_t[m]; };
         auto F_at = [&](uint64_t m) -> uint32_t {
             if (m >= sl && m < she) return spf[m - sl];
             const uint32_t p = o_pq[m] >> 16;
             return (p << 16) | (uint32_t)floor16[p];
         };
-        auto l0_at = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
-        for (uint32_t x0 = a_loc + (uint32_t)w * 64; x0 < e_loc; x0 += NT) {
-            const uint32_t x = x0 + (uint32_t)lane;
+        auto l0g = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
+        for (int s = 0; s < SD_PL; ++s) {
+            if ((uint32_t)s >= own || !((l4 >> s) & 1u)) continue;
+            const uint64_t j = sl + x0 + (uint32_t)s;
+            const uint32_t t = t4[s], f = p4[s];
             bool found = false;
-            if (x < e_loc && l0_at(sl + x)) {
-                const uint64_t j = sl + x;
-                const uint32_t t = st[x], f = spf[x];
-                auto partner = [&](uint64_t m) {
-                    const uint32_t g = F_at(m);
-                    return ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0_at(m);
-                };
-                for (uint64_t m = j; m > 0 && !found;) {
-                    --m;
-                    if (t - T_at(m) > tau_u) break;
-                    found = partner(m);
-                }
-                for (uint64_t m = j + 1; m < n && !found; ++m) {
-                    if (T_at(m) - t > tau_u) break;
-                    found = partner(m);
-                }
+            for (uint64_t m = j; m > 0 && !found;) {
+                --m;
+                if (t - T_at(m) > tau_u) break;
+                const uint32_t g = F_at(m);
+                found = ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0g(m);
             }
-            const uint64_t M = __ballot(found);
-            if (lane == 0) qw[x0 >> 6] |= M;
+            for (uint64_t m = j + 1; m < n && !found; ++m) {
+                if (T_at(m) - t > tau_u) break;
+                const uint32_t g = F_at(m);
+                found = ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0g(m);
+            }
+            f4 |= (uint32_t)found << s;
         }
     }
     __syncthreads();
 
-    // 3. the tile's seed words, their prefix, and the compacted list
-    if (w == 0) {
-        const uint32_t i = (uint32_t)lane;
-        const uint32_t b0 = a_loc + i * 64;
-        uint64_t sw = 0;
-        if (b0 < e_loc) {
-            const uint32_t hi = min(e_loc - b0, 64u);
-            const uint64_t keep = hi == 64 ? ~0ull : ((1ull << hi) - 1ull);
-            sw = (qw[b0 >> 6] | pin[b0 >> 6] | pw[b0 >> 6]) & keep;
-        }
-        const uint32_t c = (uint32_t)__popcll(sw);
-        const uint32_t inc = wave_incl_scan(c);
-        if (i < TILE / 64) {
-            qw[(a_loc >> 6) + i] = sw;
-            wpre[i] = inc - c;
-        }
-        if (i == TILE / 64 - 1) {
-            wpre[TILE / 64] = inc;
-            gstore(&seed_rec(S)[k].n, inc);
-        }
-    }
+    // 3. the own seeds (charge, partner found here, or marked by another thread),
+    // their place among the tile's seeds (block scan), the compacted list
+    uint32_t s4 = q4 | f4;
+    if (own) s4 |= (uint32_t)(mk[x0 >> 6] >> (x0 & 63)) & ((1u << own) - 1u);   // (4 bits of one word)
+    s4 &= (1u << own) - 1u;
+    const uint32_t c = (uint32_t)__popc(s4);
+    const uint32_t inc = wave_incl_scan(c);
+    if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    const uint32_t total = wpre[TILE / 64];
+    uint32_t before = 0, total = 0;
 #pragma unroll
-    for (int r = 0; r < TILE / NT; ++r) {
-        const uint32_t y = r * NT + threadIdx.x;   // position in the tile
-        const uint32_t x = a_loc + y;
-        const uint64_t wv = qw[x >> 6];
-        const bool s = x < e_loc && ((wv >> (y & 63)) & 1ull);
-        if (s) {
-            const uint32_t at = wpre[y >> 6] + (uint32_t)__popcll(wv & ((1ull << (y & 63)) - 1ull));
-            const uint32_t tx = st[x];
-            sd_t[at] = tx;
-            sd_p[at] = (spf[x] & 0xFFFF0000u) | y;
-            if (at == 0) gstore(&seed_rec(S)[k].first_t, tx);
-            if (at + 1 == total) gstore(&seed_rec(S)[k].last_t, tx);
-        }
-        if (seed_flags && x < e_loc) seed_flags[o_idx[a + y]] = (uint8_t)s;
+    for (int i = 0; i < NT / 64; ++i) {
+        const uint32_t v = wsum[i];
+        before += i < w ? v : 0u;
+        total += v;
     }
+    uint32_t at = before + inc - c;
+#pragma unroll
+    for (int s = 0; s < SD_PL; ++s) {
+        if ((s4 >> s) & 1u) {
+            sd_t[at] = t4[s];
+            sd_p[at] = (p4[s] & 0xFFFF0000u) | (SD_PL * tid + (uint32_t)s);
+            if (at == 0) gstore(&seed_rec(S)[k].first_t, t4[s]);
+            if (at + 1 == total) gstore(&seed_rec(S)[k].last_t, t4[s]);
+            ++at;
+        }
+        if (seed_flags && (uint32_t)s < own) seed_flags[o_idx[a + SD_PL * tid + s]] = (uint8_t)((s4 >> s) & 1u);
+    }
+    if (tid == 0) gstore(&seed_rec(S)[k].n, total);
 }
 
 hipError_t launch_seed(const BatchDev &b, hipStream_t s) {
