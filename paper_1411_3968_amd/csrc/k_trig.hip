@@ -1243,18 +1243,20 @@ constexpr int FD_TMAX = 64;   // window tiles staged at most
 
 template <int CAP>
 struct FoldShape {
-    static constexpr size_t wave_bytes() { return (size_t)CAP * 8; }   // per wave: time, pmt << 16 | position
+    static constexpr size_t wave_bytes() { return (size_t)CAP * 8; }   // per wave: time | (pmt << 16 | position) << 32
 };
 
 template <int G, int CAP, bool BOUNDS>
 __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     constexpr int NT = 64 * G;
     extern __shared__ __align__(16) unsigned char smem[];
-    const size_t tb_bytes = ((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15;
+    // LDS: the table bounds (large detectors), then each wave's window of seeds,
+    // one 8-byte entry per seed (one LDS read per candidate)
+    const size_t tb_bytes = ((size_t)(BOUNDS ? b.tbnd_lds : 0u) * 2 + 15) & ~(size_t)15;
     const int lane = lane_id(), w = threadIdx.x >> 6;
     uint16_t *ltb = (uint16_t *)smem;                 // the table bounds (b.tbnd_lds of them)
-    uint32_t *lt = (uint32_t *)(smem + tb_bytes + (size_t)w * FoldShape<CAP>::wave_bytes());   // window seeds: time
-    uint32_t *lp = lt + CAP;                          // window seeds: pmt << 16 | position in the tile
+    uint64_t *lwin = (uint64_t *)(smem + tb_bytes + (size_t)w * FoldShape<CAP>::wave_bytes());   // window seeds
+    const uint32_t *lt = (const uint32_t *)lwin;      // their times: the low word of each entry (stride 2)
     __shared__ uint32_t woff_all[G][FD_TMAX + 1];     // window seeds before each window tile
     uint32_t *woff = woff_all[w];
 
@@ -1399,8 +1401,7 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
             for (int u = 0; u < UB; ++u) {
                 const uint32_t x = x0 + u * 64 + (uint32_t)lane;
                 if (x < tot) {
-                    lt[x] = vt[u];
-                    lp[x] = vp[u];
+                    lwin[x] = (uint64_t)vt[u] | ((uint64_t)vp[u] << 32);
                 }
             }
         }
@@ -1420,9 +1421,9 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     constexpr int CB = BOUNDS ? 8 : 4;
 
     // fold of one seed (time ti, PMT pi, window index self) over window entries
-    // [jlo, jhi) read through T_at / P_at
+    // [jlo, jhi), each read through E_at as time | (pmt << 16 | position) << 32
     auto count_range = [&](uint32_t ti, uint32_t pi, uint32_t lim_w, uint32_t jlo, uint32_t jhi, uint32_t self,
-                           auto T_at, auto P_at) -> uint32_t {
+                           auto E_at) -> uint32_t {
         const uint64_t row = (uint64_t)pi * n_pmt;
         const uint32_t brow = (pi >> TBND_SHIFT) * nbk;
         uint32_t c = 0;
@@ -1438,10 +1439,11 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                     bb[kk] = 0;
                     pj[kk] = 0;
                     if (j < jhi && j != self) {
-                        const uint32_t tj = T_at(j);
+                        const uint64_t ej = E_at(j);
+                        const uint32_t tj = (uint32_t)ej;
                         const uint32_t dt = tj > ti ? tj - ti : ti - tj;
                         if (dt <= lim_w) {
-                            pj[kk] = P_at(j);
+                            pj[kk] = (uint32_t)(ej >> 48);
                             const uint32_t bx = brow + (pj[kk] >> TBND_SHIFT);
                             bb[kk] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
                             dd[kk] = dt;
@@ -1462,10 +1464,11 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                     dd[kk] = 0xFFFFFFFFu;
                     lim[kk] = 0;
                     if (j < jhi && j != self) {
-                        const uint32_t tj = T_at(j);
+                        const uint64_t ej = E_at(j);
+                        const uint32_t tj = (uint32_t)ej;
                         const uint32_t dt = tj > ti ? tj - ti : ti - tj;
                         if (dt <= lim_w) {
-                            const uint64_t x = row + P_at(j);
+                            const uint64_t x = row + (uint32_t)(ej >> 48);
                             lim[kk] = t16 ? (uint32_t)thr16[x] : thr32[x];
                             dd[kk] = dt;
                         }
@@ -1486,8 +1489,9 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
         const uint32_t rc = v ? r : cnt - 1;
         uint32_t ti, sp;
         if (staged) {
-            ti = lt[own0 + rc];
-            sp = lp[own0 + rc];
+            const uint64_t ev = lwin[own0 + rc];
+            ti = (uint32_t)ev;
+            sp = (uint32_t)(ev >> 32);
         } else {
             ti = sdt[(uint64_t)kt * TILE + rc];
             sp = sdp[(uint64_t)kt * TILE + rc];
@@ -1502,12 +1506,11 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
             uint32_t jlo = 0, jhi = 0;   // window seeds with time < t_lo, with time <= t_hi
             for (uint32_t step = top; step; step >>= 1) {
                 const uint32_t ml = jlo + step, mr = jhi + step;
-                if (ml <= tot && lt[ml - 1] < t_lo) jlo = ml;
-                if (mr <= tot && (uint64_t)lt[mr - 1] <= t_hi) jhi = mr;
+                if (ml <= tot && lt[2 * (ml - 1)] < t_lo) jlo = ml;
+                if (mr <= tot && (uint64_t)lt[2 * (mr - 1)] <= t_hi) jhi = mr;
             }
             if (!v) jhi = jlo;
-            c = count_range(ti, pi, Ri, jlo, jhi, own0 + r, [&](uint32_t j) { return lt[j]; },
-                            [&](uint32_t j) { return lp[j] >> 16; });
+            c = count_range(ti, pi, Ri, jlo, jhi, own0 + r, [&](uint32_t j) { return lwin[j]; });
         } else {
             // the window tile by tile from the lists in device memory
             for (uint32_t jt = jl; jt < jr; ++jt) {
@@ -1529,8 +1532,8 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                     }
                     jhi = v ? lo : jlo;
                 }
-                c += count_range(ti, pi, Ri, jlo, jhi, jt == kt ? r : 0xFFFFFFFFu, [&](uint32_t j) { return tj[j]; },
-                                 [&](uint32_t j) { return pj[j] >> 16; });
+                c += count_range(ti, pi, Ri, jlo, jhi, jt == kt ? r : 0xFFFFFFFFu,
+                                 [&](uint32_t j) { return (uint64_t)tj[j] | ((uint64_t)pj[j] << 32); });
             }
         }
         const uint32_t fd = c + 1;
@@ -1587,7 +1590,7 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
 
 template <int G, int CAP, bool BOUNDS>
 hipError_t launch_fold_v(const BatchDev &b, hipStream_t s) {
-    const size_t tb_bytes = ((size_t)b.tbnd_lds * 2 + 15) & ~(size_t)15;
+    const size_t tb_bytes = ((size_t)(BOUNDS ? b.tbnd_lds : 0u) * 2 + 15) & ~(size_t)15;
     const size_t shm = tb_bytes + (size_t)G * FoldShape<CAP>::wave_bytes();
     static const hipError_t attr = hipFuncSetAttribute(
         (const void *)k_fold<G, CAP, BOUNDS>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1607,7 +1610,9 @@ hipError_t launch_fold_b(const BatchDev &b, hipStream_t s) {
     }
 }
 
-// The variant with table bounds when a slice of the batch has them.
+// The variant with table bounds when a slice of the batch has them.  (For towers
+// only, a copy of the whole table in LDS per workgroup cost more than the reads
+// it saved: 0.36 against 0.21 ms on the 256-slice batch.)
 hipError_t launch_fold(const BatchDev &b, hipStream_t s) {
     return b.any_bounds ? launch_fold_b<true>(b, s) : launch_fold_b<false>(b, s);
 }
