@@ -513,7 +513,7 @@ def tune_or_apply(autotune, ctx, cache, n_pmt_max, sample_fn, params, label):
                 autotune.apply_one(ctx, c)
                 return dict(best=dict(c), trials=[], seconds=0.0, sample="from " + os.path.basename(cache))
     sample, desc = sample_fn()
-    t = autotune.tune_class(ctx, n_pmt_max, sample, params, reps=5, time_budget_s=20.0)
+    t = autotune.tune_class(ctx, n_pmt_max, sample, params, reps=11, time_budget_s=20.0)
     t["sample"] = desc
     if cache:
         doc = {"device": "", "classes": []}

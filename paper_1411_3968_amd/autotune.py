@@ -50,7 +50,7 @@ COUNT_CANDIDATES = [(g, h) for g in (1, 2, 4) for h in (512, 2048)]
 KNOBS = ("seg_cap", "seg_target", "grid_per_cu", "tile_group", "window_cap")
 
 
-def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int = 5, stream=None, log=None,
+def tune_class(ctx, n_pmt_max: int, slices, params, candidates=None, reps: int = 9, stream=None, log=None,
                time_budget_s: float | None = None, count_candidates=None) -> dict:
     """Try the candidates on ``slices`` (list of (geom_id, pmt, t, q)); keep the
     fastest.  First the ordering knobs ``candidates`` (cap, target, grid per CU)

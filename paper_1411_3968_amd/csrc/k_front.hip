@@ -97,15 +97,18 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 template <int NT, int RP>
 __device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax, uint32_t &runs,
                                             float &dmax, uint32_t *sh) {
+    // (descriptor fields read once: the stores below could alias them)
     TRIG_GAS ChunkPart *part = gmem(S.part);
-    for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT * RP) {
+    const uint32_t nch = S.n_chunks;
+    const uint64_t n = S.n;
+    for (uint32_t c0 = 0; c0 < nch; c0 += NT * RP) {
         const uint32_t cb = c0 + threadIdx.x * RP;
         int64_t tl[RP], th[RP];
         uint32_t pm[RP], ns[RP];
 #pragma unroll
         for (int u = 0; u < RP; ++u) {
             ns[u] = 0;
-            if (cb + u < S.n_chunks) {
+            if (cb + u < nch) {
                 tl[u] = part[cb + u].t_min;
                 th[u] = part[cb + u].t_max;
                 pm[u] = part[cb + u].pmt_max;
@@ -115,12 +118,12 @@ __device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int6
         uint32_t sum = 0;
 #pragma unroll
         for (int u = 0; u < RP; ++u) {
-            if (cb + u < S.n_chunks) {
+            if (cb + u < nch) {
                 lo = tl[u] < lo ? tl[u] : lo;
                 hi = th[u] > hi ? th[u] : hi;
                 pmax = pm[u] > pmax ? pm[u] : pmax;
                 sum += ns[u];
-                const uint64_t cnt = (cb + u + 1 < S.n_chunks) ? (uint64_t)CHUNK : S.n - (uint64_t)(cb + u) * CHUNK;
+                const uint64_t cnt = (cb + u + 1 < nch) ? (uint64_t)CHUNK : n - (uint64_t)(cb + u) * CHUNK;
                 const float d = (float)cnt / ((float)(uint64_t)(th[u] - tl[u]) + 1.0f);
                 dmax = d > dmax ? d : dmax;
             }
@@ -129,7 +132,7 @@ __device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int6
         uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
 #pragma unroll
         for (int u = 0; u < RP; ++u) {
-            if (cb + u < S.n_chunks) part[cb + u].run_base = run;
+            if (cb + u < nch) part[cb + u].run_base = run;
             run += ns[u];
         }
         runs += tot;
@@ -418,13 +421,26 @@ __global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
     if (P->state != ST_FAST || !P->tl) return;
     __shared__ uint32_t sh[NT / 64 + 1];
     TRIG_GAS ChunkPart *part = gmem(S.part);
+    const uint32_t nch = S.n_chunks;
     uint32_t runs = 0;
-    for (uint32_t c0 = 0; c0 < S.n_chunks; c0 += NT) {
-        const uint32_t c = c0 + threadIdx.x;
-        const uint32_t ns = c < S.n_chunks ? part[c].n_start : 0u;
+    // eight chunks per thread and round, their loads in flight together (one chunk
+    // per thread and round made the block slice's 29 rounds latency-bound)
+    constexpr int RP = 8;
+    for (uint32_t c0 = 0; c0 < nch; c0 += NT * RP) {
+        const uint32_t cb = c0 + threadIdx.x * RP;
+        uint32_t ns[RP], sum = 0;
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            ns[u] = cb + u < nch ? part[cb + u].n_start : 0u;
+            sum += ns[u];
+        }
         uint32_t tot;
-        const uint32_t ex = block_excl_scan<NT>(ns, tot, sh);
-        if (c < S.n_chunks) part[c].run_base = runs + ex;
+        uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
+#pragma unroll
+        for (int u = 0; u < RP; ++u) {
+            if (cb + u < nch) part[cb + u].run_base = run;
+            run += ns[u];
+        }
         runs += tot;
     }
     if (threadIdx.x == 0) {
