@@ -173,6 +173,7 @@ static size_t slice_layout(uint64_t n, bool host_input, bool want_flags, SliceLa
     L.in_t = host_input ? take(n * 8) : SIZE_MAX;
     L.in_q = host_input ? take(n * 2) : SIZE_MAX;
     L.part = take(std::max<uint64_t>(n_chunks, 1) * sizeof(ChunkPart));
+    L.ppart = take((std::max<uint64_t>(n_chunks, 1) + PL_CH - 1) / PL_CH * sizeof(PlanPart));
     L.pos = take(L.pos_cap * 4);
     L.o_t = take(n * 4 + 4);
     L.o_pq = take(n * 4 + 4);
@@ -448,6 +449,7 @@ int Job::prepare(trig_ctx *c, uint32_t n, const trig_slice_desc *d, const trig_p
         S.seg_target = std::max<uint32_t>(S.seg_target, 1);
         S.pos_cap = L.pos_cap;
         S.part = (ChunkPart *)(b + L.part);
+        S.ppart = (PlanPart *)(b + L.ppart);
         S.pos = (uint32_t *)(b + L.pos);
         S.o_t = (uint32_t *)(b + L.o_t);
         S.o_pq = (uint32_t *)(b + L.o_pq);

@@ -46,7 +46,7 @@ struct GeomDev {
 
 // Byte offsets of one slice's arrays inside a job workspace (SIZE_MAX = absent).
 struct SliceLayout {
-    size_t in_pmt, in_t, in_q, part, pos, o_t, o_pq, o_idx, tstat, cagg, dmask, fsc, fires, events, flags, tagc, l0m;
+    size_t in_pmt, in_t, in_q, part, ppart, pos, o_t, o_pq, o_idx, tstat, cagg, dmask, fsc, fires, events, flags, tagc, l0m;
     uint64_t pos_cap;
 };
 

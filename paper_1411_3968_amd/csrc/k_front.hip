@@ -88,57 +88,94 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     }
 }
 
-// Per slice: reduce the chunks, validate the input range, number the runs and
-// choose the segment width and the ordering kernel of the slice.
-// One read of every chunk summary, RP consecutive chunks per thread per round:
-// the time range, largest PMT id, the run numbering (each chunk's run_base from a
-// block scan of the run starts) and the largest chunk density in hits per ns (a
-// chunk is mostly one run: a burst on one PMT shows as a short chunk).
-template <int NT, int RP>
-__device__ __forceinline__ void plan_chunks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax, uint32_t &runs,
-                                            float &dmax, uint32_t *sh) {
-    // (descriptor fields read once: the stores below could alias them)
-    TRIG_GAS ChunkPart *part = gmem(S.part);
+// Partial sums of the plan over a block of PL_CH chunks of a slice (grid: blocks x
+// slices, a chunk per thread; many CUs instead of one workgroup per slice): the
+// time range, largest PMT id, the largest chunk density in hits per ns (a chunk
+// is mostly one run: a burst on one PMT shows as a short chunk), and the run
+// numbering within the block (each chunk's run_base from a block scan of the run
+// starts; the plan adds the runs before the block).  L2: the run numbering of the
+// level-1 output of two-level slices only.
+template <bool L2>
+__global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
+    constexpr int NT = 1024, NW = NT / 64;
+    const uint32_t si = blockIdx.y, blk = blockIdx.x;
+    const SliceDev &S = b.slices[si];
     const uint32_t nch = S.n_chunks;
     const uint64_t n = S.n;
-    for (uint32_t c0 = 0; c0 < nch; c0 += NT * RP) {
-        const uint32_t cb = c0 + threadIdx.x * RP;
-        int64_t tl[RP], th[RP];
-        uint32_t pm[RP], ns[RP];
-#pragma unroll
-        for (int u = 0; u < RP; ++u) {
-            ns[u] = 0;
-            if (cb + u < nch) {
-                tl[u] = part[cb + u].t_min;
-                th[u] = part[cb + u].t_max;
-                pm[u] = part[cb + u].pmt_max;
-                ns[u] = part[cb + u].n_start;
-            }
+    if ((uint64_t)blk * PL_CH >= nch) return;
+    if (L2) {
+        const TRIG_GAS Plan *P = gmem(b.plans + si);
+        if (P->state != ST_FAST || !P->tl) return;
+    }
+    TRIG_GAS ChunkPart *part = gmem(S.part);
+    const uint32_t c = blk * PL_CH + threadIdx.x;
+    const bool in = c < nch;
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    uint32_t pmax = 0, ns = 0;
+    float dmax = 0.f;
+    if (in) {
+        const ChunkPart cp = gload(part + c);
+        ns = cp.n_start;
+        if (!L2) {
+            lo = cp.t_min;
+            hi = cp.t_max;
+            pmax = cp.pmt_max;
+            const uint64_t cnt = (c + 1 < nch) ? (uint64_t)CHUNK : n - (uint64_t)c * CHUNK;
+            dmax = (float)cnt / ((float)(uint64_t)(cp.t_max - cp.t_min) + 1.0f);
         }
-        uint32_t sum = 0;
-#pragma unroll
-        for (int u = 0; u < RP; ++u) {
-            if (cb + u < nch) {
-                lo = tl[u] < lo ? tl[u] : lo;
-                hi = th[u] > hi ? th[u] : hi;
-                pmax = pm[u] > pmax ? pm[u] : pmax;
-                sum += ns[u];
-                const uint64_t cnt = (cb + u + 1 < nch) ? (uint64_t)CHUNK : n - (uint64_t)(cb + u) * CHUNK;
-                const float d = (float)cnt / ((float)(uint64_t)(th[u] - tl[u]) + 1.0f);
-                dmax = d > dmax ? d : dmax;
+    }
+    __shared__ uint32_t sh[NW + 1];
+    __shared__ int64_t slo[NW], shi[NW];
+    __shared__ uint32_t spm[NW];
+    __shared__ float sdm[NW];
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<NT>(ns, tot, sh);
+    if (in) part[c].run_base = ex;
+    if (!L2) {
+        lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
+        // (densities are non-negative: their bit patterns order as unsigned integers)
+        dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
+        const int w = threadIdx.x >> 6;
+        if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; sdm[w] = dmax; }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int i = 1; i < NW; ++i) {
+                lo = slo[i] < lo ? slo[i] : lo;
+                hi = shi[i] > hi ? shi[i] : hi;
+                pmax = spm[i] > pmax ? spm[i] : pmax;
+                dmax = sdm[i] > dmax ? sdm[i] : dmax;
             }
+    }
+    if (threadIdx.x == 0) gstore(gmem(S.ppart) + blk, PlanPart{lo, hi, pmax, tot, dmax, 0u});
+}
+
+// The runs started before each block of chunks (from the blocks' run counts),
+// their total, and (not L2) the blocks' time range, largest PMT id and density.
+template <int NT, bool L2>
+__device__ __forceinline__ void plan_blocks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax,
+                                            uint32_t &runs, float &dmax, uint32_t *sh) {
+    TRIG_GAS PlanPart *pp = gmem(S.ppart);
+    const uint32_t nb = (S.n_chunks + PL_CH - 1) / PL_CH;
+    for (uint32_t i0 = 0; i0 < nb; i0 += NT) {
+        const uint32_t i = i0 + threadIdx.x;
+        PlanPart q = PlanPart{INT64_MAX, INT64_MIN, 0u, 0u, 0.f, 0u};
+        if (i < nb) q = gload(pp + i);
+        if (!L2) {
+            lo = q.t_min < lo ? q.t_min : lo;
+            hi = q.t_max > hi ? q.t_max : hi;
+            pmax = q.pmt_max > pmax ? q.pmt_max : pmax;
+            dmax = q.dmax > dmax ? q.dmax : dmax;
         }
         uint32_t tot;
-        uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
-#pragma unroll
-        for (int u = 0; u < RP; ++u) {
-            if (cb + u < nch) part[cb + u].run_base = run;
-            run += ns[u];
-        }
+        const uint32_t ex = block_excl_scan<NT>(q.runs, tot, sh);
+        if (i < nb) pp[i].run_off = runs + ex;
         runs += tot;
     }
 }
 
+// Per slice: combine the chunk blocks' partial sums, validate the input range,
+// number the runs and choose the segment width and the ordering kernel of the
+// slice.
 __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
     constexpr int NT = 1024, NW = NT / 64;
     const uint32_t si = blockIdx.x;
@@ -155,9 +192,7 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
         uint32_t pmax = 0, runs = 0;
         float dmax = 0.f;
-        // a chunk per thread up to NT chunks (16M hits), else eight per thread per round
-        if (S.n_chunks <= (uint32_t)NT) plan_chunks<NT, 1>(S, lo, hi, pmax, runs, dmax, sh);
-        else plan_chunks<NT, 8>(S, lo, hi, pmax, runs, dmax, sh);
+        plan_blocks<NT, false>(S, lo, hi, pmax, runs, dmax, sh);
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
         // (densities are non-negative: their bit patterns order as unsigned integers)
         dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
@@ -353,7 +388,8 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const uint32_t sft = L2 ? P.shift2 : P.shift;
     const uint32_t n_seg = L2 ? P.n_seg2 : P.n_seg;
     const int64_t tmin = L2 ? 0 : P.t_min;
-    int64_t r = (int64_t)gmem(S.part)[c].run_base + ex - 1;   // run of the element before a
+    // run of the element before a: the runs before the chunk's block, before the chunk in it, before a in it
+    int64_t r = (int64_t)gmem(S.ppart)[c / PL_CH].run_off + gmem(S.part)[c].run_base + ex - 1;
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = a + e;
         if (i >= len) break;
@@ -412,7 +448,8 @@ __global__ __launch_bounds__(256) void k_ingest2(BatchDev b) {
 }
 
 // Second level, per two-level slice: numbering of the level-1 output's runs
-// (each chunk's run_base) and the check that its boundary table fits.
+// (the runs before each block of chunks, from k_psum's counts) and the check that
+// its boundary table fits.
 __global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
     constexpr int NT = 1024;
     const uint32_t si = blockIdx.x;
@@ -420,29 +457,10 @@ __global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
     Plan *P = S.plan;
     if (P->state != ST_FAST || !P->tl) return;
     __shared__ uint32_t sh[NT / 64 + 1];
-    TRIG_GAS ChunkPart *part = gmem(S.part);
-    const uint32_t nch = S.n_chunks;
-    uint32_t runs = 0;
-    // eight chunks per thread and round, their loads in flight together (one chunk
-    // per thread and round made the block slice's 29 rounds latency-bound)
-    constexpr int RP = 8;
-    for (uint32_t c0 = 0; c0 < nch; c0 += NT * RP) {
-        const uint32_t cb = c0 + threadIdx.x * RP;
-        uint32_t ns[RP], sum = 0;
-#pragma unroll
-        for (int u = 0; u < RP; ++u) {
-            ns[u] = cb + u < nch ? part[cb + u].n_start : 0u;
-            sum += ns[u];
-        }
-        uint32_t tot;
-        uint32_t run = runs + block_excl_scan<NT>(sum, tot, sh);
-#pragma unroll
-        for (int u = 0; u < RP; ++u) {
-            if (cb + u < nch) part[cb + u].run_base = run;
-            run += ns[u];
-        }
-        runs += tot;
-    }
+    int64_t lo = 0, hi = 0;
+    uint32_t pmax = 0, runs = 0;
+    float dmax = 0.f;
+    plan_blocks<NT, true>(S, lo, hi, pmax, runs, dmax, sh);
     if (threadIdx.x == 0) {
         P->n_runs2 = runs;
         // each group's output is time-ordered, so at most n_grp runs remain
@@ -955,6 +973,10 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
         TRIG_CHECK();
         TRIG_MARK("k_ingest", 1);
     }
+    TRIG_MARK("k_psum", 0);
+    hipLaunchKernelGGL(k_psum<false>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
+    TRIG_CHECK();
+    TRIG_MARK("k_psum", 1);
     TRIG_MARK("k_plan", 0);
     hipLaunchKernelGGL(k_plan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
@@ -982,6 +1004,10 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
         hipLaunchKernelGGL(k_ingest2, dim3(b.total_chunks), dim3(256), 0, s, b);
         TRIG_CHECK();
         TRIG_MARK("k_ingest2", 1);
+        TRIG_MARK("k_psum2", 0);
+        hipLaunchKernelGGL(k_psum<true>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_psum2", 1);
         TRIG_MARK("k_plan2", 0);
         hipLaunchKernelGGL(k_plan2, dim3(b.n_slices), dim3(1024), 0, s, b);
         TRIG_CHECK();

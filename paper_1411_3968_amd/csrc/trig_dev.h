@@ -92,6 +92,18 @@ struct FireRec {
     uint32_t pmt;
 };
 
+// The plan's partial sums over a block of PL_CH chunks of one slice: time range,
+// largest PMT id and chunk density, run starts, and (written by the plan) the runs
+// started before the block.
+constexpr uint32_t PL_CH = 1024;
+struct PlanPart {
+    int64_t t_min, t_max;
+    uint32_t pmt_max;
+    uint32_t runs;
+    float dmax;
+    uint32_t run_off;
+};
+
 struct ChunkPart {
     int64_t t_min, t_max;
     uint32_t pmt_max;
@@ -144,6 +156,7 @@ struct SliceDev {
     uint32_t seg_target, seg_cap;
     uint64_t pos_cap;
     ChunkPart *part;
+    PlanPart *ppart;         // per block of PL_CH chunks: the plan's partial sums
     uint32_t *pos;           // run-major: pos[r * (n_seg + 1) + j]
     uint32_t *o_t, *o_pq, *o_idx;   // ordered: t - t_min, pmt << 16 | q, input index
     TileStat *tstat;         // per trigger tile
