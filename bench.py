@@ -546,10 +546,11 @@ def bench_headline(T, torch, dev, a):
     stream = torch.cuda.current_stream()
 
     # launch parameters of the block class from the autotuner, tuned on a held-out
-    # 50 ms slice of the same detector (another seed), not on the timed slice
+    # slice of the same detector and size (another seed), not on the timed slice
+    # (a 50 ms sample misjudged the occupancy of the full slice's fold kernel)
     def held_sample():
-        held = C.block_workload(seed=13, length_ns=50_000_000, n_tracks=50).slices[0][1]
-        return [(gid,) + _dev_slice(torch, dev, held)], f"held-out: seed 13, 50 ms, {held.n} hits"
+        held = C.block_workload(seed=13).slices[0][1]
+        return [(gid,) + _dev_slice(torch, dev, held)], f"held-out: seed 13, 200 ms, {held.n} hits"
 
     tuned = tune_or_apply(autotune, tr.ctx, a.tune_cache, 65536, held_sample, w.params, "block")
     torch.cuda.empty_cache()

@@ -88,31 +88,23 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     }
 }
 
-// Partial sums of the plan over a block of PL_CH chunks of a slice (grid: blocks x
-// slices, a chunk per thread; many CUs instead of one workgroup per slice): the
-// time range, largest PMT id, the largest chunk density in hits per ns (a chunk
-// is mostly one run: a burst on one PMT shows as a short chunk), and the run
-// numbering within the block (each chunk's run_base from a block scan of the run
-// starts; the plan adds the runs before the block).  L2: the run numbering of the
-// level-1 output of two-level slices only.
+// The sums of block blk of PL_CH chunks of slice S, a chunk per thread of a
+// 1024-thread workgroup; every thread ends with them (L2: the runs only).
 template <bool L2>
-__global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
+__device__ __forceinline__ void block_sums(const SliceDev &S, uint32_t blk, int64_t &lo, int64_t &hi, uint32_t &pmax,
+                                           float &dmax, uint32_t &runs) {
     constexpr int NT = 1024, NW = NT / 64;
-    const uint32_t si = blockIdx.y, blk = blockIdx.x;
-    const SliceDev &S = b.slices[si];
+    static_assert(PL_CH == (uint32_t)NT, "a chunk per thread");
     const uint32_t nch = S.n_chunks;
     const uint64_t n = S.n;
-    if ((uint64_t)blk * PL_CH >= nch) return;
-    if (L2) {
-        const TRIG_GAS Plan *P = gmem(b.plans + si);
-        if (P->state != ST_FAST || !P->tl) return;
-    }
     TRIG_GAS ChunkPart *part = gmem(S.part);
     const uint32_t c = blk * PL_CH + threadIdx.x;
     const bool in = c < nch;
-    int64_t lo = INT64_MAX, hi = INT64_MIN;
-    uint32_t pmax = 0, ns = 0;
-    float dmax = 0.f;
+    lo = INT64_MAX;
+    hi = INT64_MIN;
+    pmax = 0;
+    dmax = 0.f;
+    uint32_t ns = 0;
     if (in) {
         const ChunkPart cp = gload(part + c);
         ns = cp.n_start;
@@ -128,8 +120,7 @@ __global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
     __shared__ int64_t slo[NW], shi[NW];
     __shared__ uint32_t spm[NW];
     __shared__ float sdm[NW];
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan<NT>(ns, tot, sh);
+    const uint32_t ex = block_excl_scan<NT>(ns, runs, sh);
     if (in) part[c].run_base = ex;
     if (!L2) {
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
@@ -138,15 +129,37 @@ __global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
         const int w = threadIdx.x >> 6;
         if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; sdm[w] = dmax; }
         __syncthreads();
-        if (threadIdx.x == 0)
-            for (int i = 1; i < NW; ++i) {
-                lo = slo[i] < lo ? slo[i] : lo;
-                hi = shi[i] > hi ? shi[i] : hi;
-                pmax = spm[i] > pmax ? spm[i] : pmax;
-                dmax = sdm[i] > dmax ? sdm[i] : dmax;
-            }
+        lo = slo[0]; hi = shi[0]; pmax = spm[0]; dmax = sdm[0];
+        for (int i = 1; i < NW; ++i) {
+            lo = slo[i] < lo ? slo[i] : lo;
+            hi = shi[i] > hi ? shi[i] : hi;
+            pmax = spm[i] > pmax ? spm[i] : pmax;
+            dmax = sdm[i] > dmax ? sdm[i] : dmax;
+        }
     }
-    if (threadIdx.x == 0) gstore(gmem(S.ppart) + blk, PlanPart{lo, hi, pmax, tot, dmax, 0u});
+}
+
+// Partial sums of the plan over a block of PL_CH chunks of a slice (grid: blocks x
+// slices; many CUs instead of one workgroup per slice), launched when a slice has
+// more than one block: the time range, largest PMT id, the largest chunk density
+// in hits per ns (a chunk is mostly one run: a burst on one PMT shows as a short
+// chunk), and the run numbering within the block (each chunk's run_base from a
+// block scan of the run starts; the plan adds the runs before the block).  L2: the
+// run numbering of the level-1 output of two-level slices only.
+template <bool L2>
+__global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
+    const uint32_t si = blockIdx.y, blk = blockIdx.x;
+    const SliceDev &S = b.slices[si];
+    if ((uint64_t)blk * PL_CH >= S.n_chunks) return;
+    if (L2) {
+        const TRIG_GAS Plan *P = gmem(b.plans + si);
+        if (P->state != ST_FAST || !P->tl) return;
+    }
+    int64_t lo, hi;
+    uint32_t pmax, runs;
+    float dmax;
+    block_sums<L2>(S, blk, lo, hi, pmax, dmax, runs);
+    if (threadIdx.x == 0) gstore(gmem(S.ppart) + blk, PlanPart{lo, hi, pmax, runs, dmax, 0u});
 }
 
 // The runs started before each block of chunks (from the blocks' run counts),
@@ -192,7 +205,12 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
         uint32_t pmax = 0, runs = 0;
         float dmax = 0.f;
-        plan_blocks<NT, false>(S, lo, hi, pmax, runs, dmax, sh);
+        if (b.max_tiles > PL_CH) {
+            plan_blocks<NT, false>(S, lo, hi, pmax, runs, dmax, sh);   // k_psum's blocks
+        } else {
+            block_sums<false>(S, 0, lo, hi, pmax, dmax, runs);         // the one block, here
+            if (threadIdx.x == 0) gmem(S.ppart)[0].run_off = 0u;
+        }
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
         // (densities are non-negative: their bit patterns order as unsigned integers)
         dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
@@ -460,7 +478,12 @@ __global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
     int64_t lo = 0, hi = 0;
     uint32_t pmax = 0, runs = 0;
     float dmax = 0.f;
-    plan_blocks<NT, true>(S, lo, hi, pmax, runs, dmax, sh);
+    if (b.max_tiles > PL_CH) {
+        plan_blocks<NT, true>(S, lo, hi, pmax, runs, dmax, sh);   // k_psum's blocks
+    } else {
+        block_sums<true>(S, 0, lo, hi, pmax, dmax, runs);         // the one block, here
+        if (threadIdx.x == 0) gmem(S.ppart)[0].run_off = 0u;
+    }
     if (threadIdx.x == 0) {
         P->n_runs2 = runs;
         // each group's output is time-ordered, so at most n_grp runs remain
@@ -973,10 +996,12 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
         TRIG_CHECK();
         TRIG_MARK("k_ingest", 1);
     }
-    TRIG_MARK("k_psum", 0);
-    hipLaunchKernelGGL(k_psum<false>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
-    TRIG_CHECK();
-    TRIG_MARK("k_psum", 1);
+    if (b.max_tiles > PL_CH) {   // (else each slice is one block, summed by k_plan itself)
+        TRIG_MARK("k_psum", 0);
+        hipLaunchKernelGGL(k_psum<false>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
+        TRIG_CHECK();
+        TRIG_MARK("k_psum", 1);
+    }
     TRIG_MARK("k_plan", 0);
     hipLaunchKernelGGL(k_plan, dim3(b.n_slices), dim3(1024), 0, s, b);
     TRIG_CHECK();
@@ -1004,10 +1029,13 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
         hipLaunchKernelGGL(k_ingest2, dim3(b.total_chunks), dim3(256), 0, s, b);
         TRIG_CHECK();
         TRIG_MARK("k_ingest2", 1);
-        TRIG_MARK("k_psum2", 0);
-        hipLaunchKernelGGL(k_psum<true>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
-        TRIG_CHECK();
-        TRIG_MARK("k_psum2", 1);
+        if (b.max_tiles > PL_CH) {
+            TRIG_MARK("k_psum2", 0);
+            hipLaunchKernelGGL(k_psum<true>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s,
+                               b);
+            TRIG_CHECK();
+            TRIG_MARK("k_psum2", 1);
+        }
         TRIG_MARK("k_plan2", 0);
         hipLaunchKernelGGL(k_plan2, dim3(b.n_slices), dim3(1024), 0, s, b);
         TRIG_CHECK();
