@@ -116,6 +116,13 @@ struct Job {
     size_t fixed_pin_cap = 0;
     char *fixed_gen = nullptr;        // radix scratch of slices too small to hold it in their own lists
     bool copies_queued = false;       // deliver queued a device-to-host copy
+    // copies from the host-mapped staging into the callers' buffers, collected by
+    // deliver when defer_copies is set and run together (in parallel when large)
+    struct HostCopy { void *dst; const void *src; size_t bytes; };
+    std::vector<HostCopy> host_copies;
+    bool defer_copies = false;
+    void host_copy(void *dst, const void *src, size_t bytes);
+    void run_host_copies();
     bool any_tag = false;             // some slice asked for its tagged hits (tagged in the launch)
     bool reran = false;               // a general-ordering or dense-window rerun changed events
 

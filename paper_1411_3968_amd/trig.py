@@ -498,11 +498,22 @@ class SliceRunner:
         self.sp = _stream_ptr(stream)
         self._pd, self._pp, self._pr = C.byref(self.desc), C.byref(self.prm), C.byref(self.buf.rec)
 
-    def __call__(self) -> dict:
+    def launch(self) -> int:
+        """One ``trig_slice`` call: the results are in the buffers on return
+        (read them with :meth:`results`)."""
         rc = _LIB.trig_slice(self.ctx, self._pd, self._pp, self._pr, self.sp)
-        r = self.buf.rec
         if rc != TRIG_OK:
             raise TrigError(rc, _err(self.ctx))
+        return rc
+
+    def __call__(self) -> dict:
+        self.launch()
+        return self.results()
+
+    def results(self) -> dict:
+        """The last call's results (views into the buffers)."""
+        r = self.buf.rec
+        rc = TRIG_OK
         out = dict(status=rc, n_seeds=int(r.n_seeds), n_fires=int(r.n_fires), n_events=int(r.n_events),
                    path=int(r.path), fires=self.buf.fires[:r.n_fires], events=self.buf.events[:r.n_events])
         if self.buf.flags is not None:
@@ -544,12 +555,22 @@ class BatchRunner:
             stream = torch.cuda.current_stream()
         self.sp = _stream_ptr(stream)
 
-    def __call__(self) -> list:
+    def launch(self) -> int:
+        """One ``trig_batch`` call: the results are in the buffers on return
+        (read them with :meth:`results`); returns its status."""
         for i in range(self.n):
             self.recs[i] = self.bufs[i].rec
         rc = _LIB.trig_batch(self.ctx, self.n, self.descs, C.byref(self.prm), self.recs, self.sp)
         if rc not in (TRIG_OK, TRIG_ERANGE, TRIG_EINVAL, TRIG_EOVERFLOW):
             raise TrigError(rc, _err(self.ctx))
+        return rc
+
+    def __call__(self) -> list:
+        self.launch()
+        return self.results()
+
+    def results(self) -> list:
+        """The last call's results, one dict per slice (views into the buffers)."""
         out = []
         for i in range(self.n):
             r, b = self.recs[i], self.bufs[i]
