@@ -185,8 +185,9 @@ typedef struct {
  * On TRIG_EOVERFLOW n_fires / n_events / n_tagged hold the required counts
  * and no list is written.  path reports how the slice was processed: bit 0 set
  * when the general radix sort ordered it (else the run merge), bit 1 set when
- * its trigger stage was rerun with a precomputed seed mask (a burst far denser
- * than the slice's mean density). */
+ * its trigger stage was rerun with a precomputed seed mask (with the seed menu
+ * on, a burst far denser than the slice's mean density; the plain rule reads
+ * such windows from device memory in the same pass). */
 typedef struct {
     trig_fire  *fires;
     uint64_t    fire_cap, n_fires;

@@ -1076,7 +1076,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     }
     // bounds of min(thr, 65535) per pair of 32-PMT blocks, in 16 ns units (the lower
     // bound rounded down, capped at 4080 ns; the upper rounded up, 255 when above
-    // 4064 ns: no bound): the counting kernel decides most pairs from them and
+    // 4064 ns: no bound): the fold kernel decides most pairs from them and
     // reads the table only in between
     std::vector<uint16_t> tb;
     if (P >= TBND_MIN_PMT) {

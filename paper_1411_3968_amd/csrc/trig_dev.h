@@ -386,12 +386,6 @@ __device__ __forceinline__ void stage_copy(T *dst, const TRIG_GAS T *src, uint32
     stage_copy<NT, U>(dst, src, n, [](T x) { return x; });
 }
 
-// Device-scope load that bypasses a possibly stale L1 line (data written by
-// other workgroups of the same kernel before a release fence).
-__device__ __forceinline__ uint32_t load_acquire(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <int NT>
 __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
     uint32_t tot;
