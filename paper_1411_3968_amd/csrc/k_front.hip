@@ -739,9 +739,10 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total
 // level-1 output's stretches merged; the input index of each hit comes from the
 // level-1 output).
 template <int CAP, bool L2>
-__global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
+__global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves per SIMD: what the LDS allows
     constexpr int EG = CAP / 64;
     constexpr int RI = WAVE_RUNS / 64;
+    static_assert((CAP & (CAP - 1)) == 0 && (WAVE_RUNS & (WAVE_RUNS - 1)) == 0, "masks below need powers of two");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int w = threadIdx.x >> 6, lane = lane_id();
     WaveSeg<CAP> &sm = reinterpret_cast<WaveSeg<CAP> *>(smem_raw)[w];
@@ -804,15 +805,16 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
                 st[i] = pos[bnd_at<L2 ? 1u : BND_TJ>(0, r, R)];
             }
         }
-        uint32_t m = 0, gpart = 0;
+        uint32_t m = 0, gpart = 0, rb[RI];
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
             const uint32_t c = hi[i] - lo[i];
             const uint32_t incl = wave_incl_scan(c);
             const uint32_t rl = (uint32_t)(i * 64 + lane);   // run index within the item
+            rb[i] = m + incl - c;
             if (r_lo + rl < r_hi) {
                 sm.run_lo[rl] = lo[i];
-                sm.run_base[rl] = m + incl - c;
+                sm.run_base[rl] = rb[i];
             }
             m += lane_read(incl, 63);
             gpart += lo[i] - st[i];
@@ -824,24 +826,26 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             if (lane == 0) { b.slices[si].plan->overflow = 1u; b.slices[si].plan->state = ST_NEED_GENERIC; }
             continue;
         }
+        // Every phase below reads LDS unconditionally at in-range addresses and
+        // selects the result, so that the reads of a lane's EG elements are in
+        // flight together rather than one round trip each.
+        //
         // run marks: each non-empty run's index at its first gathered position
+        // (positions past m stay 0)
 #pragma unroll
         for (int e = 0; e < EG; ++e) sm.aux[e * 64 + lane] = 0;
         wave_sync();
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
             const uint32_t rl = (uint32_t)(i * 64 + lane);
-            if (r_lo + rl < r_hi && hi[i] > lo[i]) sm.aux[sm.run_base[rl]] = (uint16_t)rl;
+            if (r_lo + rl < r_hi && hi[i] > lo[i]) sm.aux[rb[i]] = (uint16_t)rl;
         }
         wave_sync();
         // gather: run of element k = the largest mark at or before k (the EG
         // scans are independent; their carries are a max over earlier groups)
         uint32_t src[EG], rr[EG];
 #pragma unroll
-        for (int e = 0; e < EG; ++e) {
-            const uint32_t k = (uint32_t)(e * 64 + lane);
-            rr[e] = k < m ? (uint32_t)sm.aux[k] : 0u;
-        }
+        for (int e = 0; e < EG; ++e) rr[e] = sm.aux[e * 64 + lane];
 #pragma unroll
         for (int e = 0; e < EG; ++e) rr[e] = wave_incl_max_u32(rr[e]);
         {
@@ -854,17 +858,27 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             }
         }
         // (each lane rewrites only its own marks: the run of element k, from which
-        // the output recomputes the input index)
+        // the output recomputes the input index; rr < WAVE_RUNS for every k)
+        {
+            uint32_t rlo[EG], rbs[EG];
+#pragma unroll
+            for (int e = 0; e < EG; ++e) { rlo[e] = sm.run_lo[rr[e]]; rbs[e] = sm.run_base[rr[e]]; }
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t k = (uint32_t)(e * 64 + lane);
+                src[e] = k < m ? rlo[e] + (k - rbs[e]) : 0xFFFFFFFFu;
+            }
+        }
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)(e * 64 + lane);
-            src[e] = k < m ? sm.run_lo[rr[e]] + (k - sm.run_base[rr[e]]) : 0xFFFFFFFFu;
             if (k < m) sm.aux[k] = (uint16_t)rr[e];
         }
         // one packed word per hit: a single stream of lines per run stretch
         uint64_t hv[EG];
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
+            hv[e] = 0;
             if (src[e] != 0xFFFFFFFFu) hv[e] = in_pk[src[e]];
         }
         // key of each element: (local time, PMT, gather position), unique and in
@@ -898,53 +912,73 @@ __global__ __launch_bounds__(256) void k_segsort_w(BatchDev b) {
             for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = (uint16_t)run; run += v[i]; }
         }
         wave_sync();
-        // keys grouped by bucket
+        // keys grouped by bucket (an element without a hit reads bucket 0 and
+        // takes no part: its count is 0)
         uint32_t ebase[EG], ecnt[EG], rank[EG];
         uint32_t most = 0;
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
-            ebase[e] = ecnt[e] = rank[e] = 0;
-            if (src[e] != 0xFFFFFFFFu) {
-                const uint32_t bk = (uint32_t)(key[e] >> KEY_T_SHIFT) >> tb;
-                ebase[e] = sm.bbase[bk];
-                ecnt[e] = sm.bcount[bk];
-                sm.key[ebase[e] + slot[e]] = key[e];
-            }
+            const uint32_t bk = (uint32_t)(key[e] >> KEY_T_SHIFT) >> tb;
+            ebase[e] = sm.bbase[bk];
+            ecnt[e] = sm.bcount[bk];
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            rank[e] = 0;
+            if (src[e] == 0xFFFFFFFFu) ecnt[e] = 0;
+            else sm.key[ebase[e] + slot[e]] = key[e];
             most = ecnt[e] > most ? ecnt[e] : most;
         }
         wave_sync();
-        // rank within the bucket: the members with a smaller key (independent
-        // reads; the EG elements of a lane walk their buckets together)
+        // rank within the bucket: the members with a smaller key (the EG reads
+        // of a step are independent; past its bucket an element reads a clamped
+        // address and counts nothing)
         for (uint32_t x = 0; x < most; ++x) {
+            uint64_t kx[EG];
 #pragma unroll
-            for (int e = 0; e < EG; ++e)
-                if (x < ecnt[e]) rank[e] += sm.key[ebase[e] + x] < key[e] ? 1u : 0u;
+            for (int e = 0; e < EG; ++e) kx[e] = sm.key[min(ebase[e] + x, (uint32_t)CAP - 1u)];
+#pragma unroll
+            for (int e = 0; e < EG; ++e) rank[e] += (x < ecnt[e] && kx[e] < key[e]) ? 1u : 0u;
         }
         wave_sync();
         // keys in output order (each bucket's range rewritten by its own members)
 #pragma unroll
         for (int e = 0; e < EG; ++e)
-            if (src[e] != 0xFFFFFFFFu) sm.key[ebase[e] + rank[e]] = key[e];
+            if (ecnt[e] != 0) sm.key[ebase[e] + rank[e]] = key[e];
         wave_sync();
+        // output in order: key, then the element's charge and run, then the
+        // run's stretch (positions past m read stale entries, masked in range,
+        // and store nothing)
         const uint32_t tm32 = (uint32_t)(uint64_t)P.t_min;
+        uint64_t kk[EG];
+        uint32_t dqv[EG], rv[EG], from[EG];
+#pragma unroll
+        for (int e = 0; e < EG; ++e) kk[e] = sm.key[e * 64 + lane];
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)kk[e] & (uint32_t)(CAP - 1);
+            dqv[e] = sm.dq[k];
+            rv[e] = sm.aux[k] & (uint32_t)(WAVE_RUNS - 1);
+        }
+#pragma unroll
+        for (int e = 0; e < EG; ++e) {
+            const uint32_t k = (uint32_t)kk[e] & (uint32_t)(CAP - 1);
+            from[e] = sm.run_lo[rv[e]] + (k - sm.run_base[rv[e]]);   // gathered position
+        }
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t i = (uint32_t)(e * 64 + lane);
             if (i < m) {
-                const uint64_t kk = sm.key[i];
-                const uint32_t k = (uint32_t)kk & KEY_K_MASK;
-                const uint32_t p = (uint32_t)(kk >> KEY_P_SHIFT) & 0xFFFFu;
-                const uint32_t t_loc = seg_lo + (uint32_t)(kk >> KEY_T_SHIFT);
-                const uint32_t pq = (p << 16) | sm.dq[k];
-                const uint32_t r = sm.aux[k];
-                const uint32_t from = sm.run_lo[r] + (k - sm.run_base[r]);   // gathered position
+                const uint32_t p = (uint32_t)(kk[e] >> KEY_P_SHIFT) & 0xFFFFu;
+                const uint32_t t_loc = seg_lo + (uint32_t)(kk[e] >> KEY_T_SHIFT);
+                const uint32_t pq = (p << 16) | dqv[e];
                 if (tl1) {
                     l1_out[goff + i] = ((uint64_t)pq << 32) | (uint32_t)(t_loc + tm32);
-                    l1_idx[goff + i] = from;
+                    l1_idx[goff + i] = from[e];
                 } else {
                     o_t[goff + i] = t_loc;
                     o_pq[goff + i] = pq;
-                    o_idx[goff + i] = L2 ? l1_idx[from] : from;
+                    o_idx[goff + i] = L2 ? l1_idx[from[e]] : from[e];
                 }
             }
         }
