@@ -89,8 +89,7 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
 }
 
 // The sums of block blk of PL_CH chunks of slice S, a chunk per thread of a
-// 1024-thread workgroup; every thread ends with them (L2: the runs only).
-template <bool L2>
+// 1024-thread workgroup; every thread ends with them.
 __device__ __forceinline__ void block_sums(const SliceDev &S, uint32_t blk, int64_t &lo, int64_t &hi, uint32_t &pmax,
                                            float &dmax, uint32_t &runs) {
     constexpr int NT = 1024, NW = NT / 64;
@@ -108,13 +107,11 @@ __device__ __forceinline__ void block_sums(const SliceDev &S, uint32_t blk, int6
     if (in) {
         const ChunkPart cp = gload(part + c);
         ns = cp.n_start;
-        if (!L2) {
-            lo = cp.t_min;
-            hi = cp.t_max;
-            pmax = cp.pmt_max;
-            const uint64_t cnt = (c + 1 < nch) ? (uint64_t)CHUNK : n - (uint64_t)c * CHUNK;
-            dmax = (float)cnt / ((float)(uint64_t)(cp.t_max - cp.t_min) + 1.0f);
-        }
+        lo = cp.t_min;
+        hi = cp.t_max;
+        pmax = cp.pmt_max;
+        const uint64_t cnt = (c + 1 < nch) ? (uint64_t)CHUNK : n - (uint64_t)c * CHUNK;
+        dmax = (float)cnt / ((float)(uint64_t)(cp.t_max - cp.t_min) + 1.0f);
     }
     __shared__ uint32_t sh[NW + 1];
     __shared__ int64_t slo[NW], shi[NW];
@@ -122,20 +119,18 @@ __device__ __forceinline__ void block_sums(const SliceDev &S, uint32_t blk, int6
     __shared__ float sdm[NW];
     const uint32_t ex = block_excl_scan<NT>(ns, runs, sh);
     if (in) part[c].run_base = ex;
-    if (!L2) {
-        lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
-        // (densities are non-negative: their bit patterns order as unsigned integers)
-        dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
-        const int w = threadIdx.x >> 6;
-        if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; sdm[w] = dmax; }
-        __syncthreads();
-        lo = slo[0]; hi = shi[0]; pmax = spm[0]; dmax = sdm[0];
-        for (int i = 1; i < NW; ++i) {
-            lo = slo[i] < lo ? slo[i] : lo;
-            hi = shi[i] > hi ? shi[i] : hi;
-            pmax = spm[i] > pmax ? spm[i] : pmax;
-            dmax = sdm[i] > dmax ? sdm[i] : dmax;
-        }
+    lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
+    // (densities are non-negative: their bit patterns order as unsigned integers)
+    dmax = __uint_as_float(wave_maxu(__float_as_uint(dmax)));
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) { slo[w] = lo; shi[w] = hi; spm[w] = pmax; sdm[w] = dmax; }
+    __syncthreads();
+    lo = slo[0]; hi = shi[0]; pmax = spm[0]; dmax = sdm[0];
+    for (int i = 1; i < NW; ++i) {
+        lo = slo[i] < lo ? slo[i] : lo;
+        hi = shi[i] > hi ? shi[i] : hi;
+        pmax = spm[i] > pmax ? spm[i] : pmax;
+        dmax = sdm[i] > dmax ? sdm[i] : dmax;
     }
 }
 
@@ -144,27 +139,21 @@ __device__ __forceinline__ void block_sums(const SliceDev &S, uint32_t blk, int6
 // more than one block: the time range, largest PMT id, the largest chunk density
 // in hits per ns (a chunk is mostly one run: a burst on one PMT shows as a short
 // chunk), and the run numbering within the block (each chunk's run_base from a
-// block scan of the run starts; the plan adds the runs before the block).  L2: the
-// run numbering of the level-1 output of two-level slices only.
-template <bool L2>
+// block scan of the run starts; the plan adds the runs before the block).
 __global__ __launch_bounds__(1024) void k_psum(BatchDev b) {
     const uint32_t si = blockIdx.y, blk = blockIdx.x;
     const SliceDev &S = b.slices[si];
     if ((uint64_t)blk * PL_CH >= S.n_chunks) return;
-    if (L2) {
-        const TRIG_GAS Plan *P = gmem(b.plans + si);
-        if (P->state != ST_FAST || !P->tl) return;
-    }
     int64_t lo, hi;
     uint32_t pmax, runs;
     float dmax;
-    block_sums<L2>(S, blk, lo, hi, pmax, dmax, runs);
+    block_sums(S, blk, lo, hi, pmax, dmax, runs);
     if (threadIdx.x == 0) gstore(gmem(S.ppart) + blk, PlanPart{lo, hi, pmax, runs, dmax, 0u});
 }
 
 // The runs started before each block of chunks (from the blocks' run counts),
-// their total, and (not L2) the blocks' time range, largest PMT id and density.
-template <int NT, bool L2>
+// their total, and the blocks' time range, largest PMT id and density.
+template <int NT>
 __device__ __forceinline__ void plan_blocks(const SliceDev &S, int64_t &lo, int64_t &hi, uint32_t &pmax,
                                             uint32_t &runs, float &dmax, uint32_t *sh) {
     TRIG_GAS PlanPart *pp = gmem(S.ppart);
@@ -173,12 +162,10 @@ __device__ __forceinline__ void plan_blocks(const SliceDev &S, int64_t &lo, int6
         const uint32_t i = i0 + threadIdx.x;
         PlanPart q = PlanPart{INT64_MAX, INT64_MIN, 0u, 0u, 0.f, 0u};
         if (i < nb) q = gload(pp + i);
-        if (!L2) {
-            lo = q.t_min < lo ? q.t_min : lo;
-            hi = q.t_max > hi ? q.t_max : hi;
-            pmax = q.pmt_max > pmax ? q.pmt_max : pmax;
-            dmax = q.dmax > dmax ? q.dmax : dmax;
-        }
+        lo = q.t_min < lo ? q.t_min : lo;
+        hi = q.t_max > hi ? q.t_max : hi;
+        pmax = q.pmt_max > pmax ? q.pmt_max : pmax;
+        dmax = q.dmax > dmax ? q.dmax : dmax;
         uint32_t tot;
         const uint32_t ex = block_excl_scan<NT>(q.runs, tot, sh);
         if (i < nb) pp[i].run_off = runs + ex;
@@ -206,9 +193,9 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         uint32_t pmax = 0, runs = 0;
         float dmax = 0.f;
         if (b.max_tiles > PL_CH) {
-            plan_blocks<NT, false>(S, lo, hi, pmax, runs, dmax, sh);   // k_psum's blocks
+            plan_blocks<NT>(S, lo, hi, pmax, runs, dmax, sh);   // k_psum's blocks
         } else {
-            block_sums<false>(S, 0, lo, hi, pmax, dmax, runs);         // the one block, here
+            block_sums(S, 0, lo, hi, pmax, dmax, runs);         // the one block, here
             if (threadIdx.x == 0) gmem(S.ppart)[0].run_off = 0u;
         }
         lo = wave_min64(lo); hi = wave_max64(hi); pmax = wave_maxu(pmax);
@@ -227,6 +214,14 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
         p.t_min = lo; p.t_max = hi; p.n_runs = runs;
         const uint64_t span = (uint64_t)hi - (uint64_t)lo;
         const int64_t H = (int64_t)b.prm.half_event_ns;
+        // the seed kernel's halo: four times the mean number of hits in t_floor_ns,
+        // at least one 64-hit word, in whole words (none for a negative t_floor_ns)
+        {
+            const int32_t tau = b.prm.t_floor_ns;
+            const double hf = tau < 0 ? 0.0 : 4.0 * (double)S.n * ((double)tau + 1.0) / ((double)span + 1.0);
+            const uint32_t h = hf >= 1048576.0 ? 1048576u : (uint32_t)hf;
+            p.seed_halo = tau < 0 ? 0u : (h < 64 ? 64u : (h + 63) & ~63u);
+        }
         if (pmax >= S.n_pmt || span >= (1ull << 31) || lo < INT64_MIN + H || hi > INT64_MAX - H) {
             p.status = TRIG_ERANGE;
         } else {
@@ -254,6 +249,7 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
             };
             const float mean = (float)S.n / ((float)span + 1.0f);
             uint32_t sft = shift_for(mean + dmax);
+            uint64_t tcap = S.pos_cap;   // entries of the (level-1) boundary table at most
             if (tl) {
                 // level 2 merges the groups' stretches at the slice's density; level 1
                 // orders each group of rg runs at its share of it (a burst stays in
@@ -263,25 +259,28 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
                 p.tl = 1;
                 p.run_grp = rg;
                 p.n_grp = ngrp;
+                p.n_runs2 = ngrp;
                 p.shift2 = sft;
                 p.n_seg2 = (uint32_t)((span >> sft) + 1);
+                // (the level-2 table takes the end of the area)
+                const uint64_t l2e = level2_entries(p);
+                tcap = l2e < S.pos_cap ? S.pos_cap - l2e : 0;
                 uint32_t s1 = shift_for(mean / (float)ngrp + dmax);
-                while (s1 < 31 && bnd_entries<BND_TJ>((span >> s1) + 2, runs) > S.pos_cap &&
+                while (s1 < 31 && bnd_entries<BND_TJ>((span >> s1) + 2, runs) > tcap &&
                        2 * ((S.n << (s1 + 1)) / ((span + 1) * ngrp)) <= (uint64_t)cap)
                     ++s1;
                 sft = s1;
             } else {
                 // many runs: widen the segments (up to half the LDS capacity expected)
                 // until the boundary table fits its budget
-                while (sft < 31 && bnd_entries<BND_TJ>((span >> sft) + 2, runs) > S.pos_cap &&
+                while (sft < 31 && bnd_entries<BND_TJ>((span >> sft) + 2, runs) > tcap &&
                        2 * ((S.n << (sft + 1)) / (span + 1)) <= (uint64_t)cap)
                     ++sft;
             }
             const uint64_t nseg = (span >> sft) + 1;
             p.shift = sft;
             p.n_seg = (uint32_t)nseg;
-            bool fits = ok && bnd_entries<BND_TJ>(nseg + 1, runs) <= S.pos_cap;
-            if (tl) fits = fits && bnd_entries<1>((uint64_t)p.n_seg2 + 1, p.n_grp) <= S.pos_cap;
+            const bool fits = ok && bnd_entries<BND_TJ>(nseg + 1, runs) <= tcap;
             p.state = fits ? ST_FAST : ST_NEED_GENERIC;
         }
     }
@@ -304,69 +303,51 @@ __global__ __launch_bounds__(1024) void k_plan(BatchDev b) {
 __device__ void build_segment_lists(const BatchDev &b) {
     constexpr int NT = 256;
     __shared__ uint32_t sh[NT / 64 + 1];
-    uint32_t acc = 0, acc_b = 0;
+    uint32_t acc = 0, acc_b = 0, acc_2 = 0;
     for (uint32_t i0 = 0; i0 < b.n_slices; i0 += NT) {
         const uint32_t i = i0 + threadIdx.x;
-        uint32_t nw = 0, nb = 0;
+        uint32_t nw = 0, nb = 0, n2 = 0;
         if (i < b.n_slices) {
             const Plan &P = b.plans[i];
             if (P.state == ST_FAST) {
                 if (P.seg_kind == 0) nw = P.tl ? P.n_grp * P.n_seg : P.n_seg; else nb = P.n_seg;
+                if (P.tl) n2 = P.n_seg2;   // (the second level skips a slice that level 1 gave up)
             }
         }
-        uint32_t tw, tbk;
+        uint32_t tw, tbk, t2;
         const uint32_t ew = block_excl_scan<NT>(nw, tw, sh);
         const uint32_t eb = block_excl_scan<NT>(nb, tbk, sh);
+        const uint32_t e2 = block_excl_scan<NT>(n2, t2, sh);
         if (i < b.n_slices) {
             b.plans[i].seg_item_base = acc + ew;
             b.plans[i].seg_item_base_b = acc_b + eb;
+            b.plans[i].seg_item_base2 = acc_2 + e2;
         }
         acc += tw;
         acc_b += tbk;
+        acc_2 += t2;
     }
     if (threadIdx.x == 0) {
         b.counters[Q_SEG_TOTAL] = acc;
         b.counters[Q_SEG_TOTAL_B] = acc_b;
+        b.counters[Q_SEG_TOTAL2] = acc_2;
     }
-}
-
-// Work list of the second level (two-level slices still on the run merge).
-__device__ void build_level2_lists(const BatchDev &b) {
-    constexpr int NT = 256;
-    __shared__ uint32_t sh[NT / 64 + 1];
-    uint32_t acc = 0;
-    for (uint32_t i0 = 0; i0 < b.n_slices; i0 += NT) {
-        const uint32_t i = i0 + threadIdx.x;
-        uint32_t nw = 0;
-        if (i < b.n_slices) {
-            const Plan &P = b.plans[i];
-            if (P.state == ST_FAST && P.tl) nw = P.n_seg2;
-        }
-        uint32_t tw;
-        const uint32_t ew = block_excl_scan<NT>(nw, tw, sh);
-        if (i < b.n_slices) b.plans[i].seg_item_base2 = acc + ew;
-        acc += tw;
-    }
-    if (threadIdx.x == 0) b.counters[Q_SEG_TOTAL2] = acc;
 }
 
 // Per chunk: for every run r and segment boundary j (time j << shift relative to
 // t_min), pos[j][r] = first position of run r whose time is at or after the
 // boundary; pos[n_seg][r] = end of run r.  Runs are maximal time-non-decreasing
-// stretches.  The single-level and level-1 tables come in tiles of BND_TJ
-// consecutive boundaries, run-major inside a tile (bnd_at), so a chunk writes
-// whole 64-byte stretches of its run's entries (segment-major, every entry was a
-// partial cache line of its own, written by a chunk far in time from the ones
-// that share the line: 760 against 544 us on the 256-slice batch).
-// L2: the same over the level-1 output of two-level slices (its runs and
-// segments of the second level; the level-1 table is no longer needed).
-template <bool L2>
+// stretches.  The table comes in tiles of BND_TJ consecutive boundaries,
+// run-major inside a tile (bnd_at), so a chunk writes whole 64-byte stretches of
+// its run's entries (segment-major, every entry was a partial cache line of its
+// own, written by a chunk far in time from the ones that share the line: 760
+// against 544 us on the 256-slice batch).  (The second level's table of
+// two-level slices is written by level 1 itself.)
 __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     constexpr int NT = 256, PER = CHUNK / NT;
     const uint32_t item = blockIdx.x;
     if (item == b.total_chunks) {   // one extra block
-        if (L2) build_level2_lists(b);
-        else build_segment_lists(b);
+        build_segment_lists(b);
         return;
     }
     const uint32_t si = slice_of_chunk(b, item);
@@ -374,24 +355,16 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const uint32_t c = item - chunk_base_of(b, si);
     if (c >= S.n_chunks) return;
     const Plan P = gload(gmem(b.plans + si));
-    if (P.state != ST_FAST || (L2 && !P.tl)) return;
+    if (P.state != ST_FAST) return;
     const TRIG_GAS int64_t *tin = gmem(S.t);
-    const TRIG_GAS uint64_t *l1 = level1_hits(S);
-    const uint32_t tm32 = (uint32_t)(uint64_t)P.t_min;
-    // time at position k: the input time, or (level 2) the level-1 local time
-    auto time_at = [&](uint64_t k) -> int64_t { return L2 ? (int64_t)((uint32_t)l1[k] - tm32) : tin[k]; };
     __shared__ int64_t st[CHUNK + 2];
     __shared__ uint32_t sh[NT / 64 + 1];
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint32_t len = (uint32_t)((k0 + CHUNK < S.n) ? CHUNK : S.n - k0);
-    if (L2) {
-        for (uint32_t i = threadIdx.x; i < len; i += NT) st[i + 1] = time_at(k0 + i);
-    } else {
-        stage_copy<NT, PER>(st + 1, tin + k0, len);
-    }
+    stage_copy<NT, PER>(st + 1, tin + k0, len);
     if (threadIdx.x == 0) {
-        st[0] = k0 ? time_at(k0 - 1) : INT64_MIN;
-        st[len + 1] = (k0 + len < S.n) ? time_at(k0 + len) : INT64_MIN;
+        st[0] = k0 ? tin[k0 - 1] : INT64_MIN;
+        st[len + 1] = (k0 + len < S.n) ? tin[k0 + len] : INT64_MIN;
     }
     __syncthreads();
     const uint32_t a = threadIdx.x * PER;
@@ -402,12 +375,10 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<NT>(starts, tot, sh);
-    const uint64_t R = L2 ? P.n_runs2 : P.n_runs;
-    const uint32_t sft = L2 ? P.shift2 : P.shift;
-    const uint32_t n_seg = L2 ? P.n_seg2 : P.n_seg;
-    const int64_t tmin = L2 ? 0 : P.t_min;
+    const uint64_t R = P.n_runs;
     // run of the element before a: the runs before the chunk's block, before the chunk in it, before a in it
     int64_t r = (int64_t)gmem(S.ppart)[c / PL_CH].run_off + gmem(S.part)[c].run_base + ex - 1;
+    TRIG_GAS uint32_t *pos = gmem(S.pos);
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = a + e;
         if (i >= len) break;
@@ -416,79 +387,15 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         const bool is_start = (k == 0) || (t < st[i]);
         const bool is_end = (k + 1 == S.n) || (st[i + 2] < t);
         if (is_start) ++r;
-        TRIG_GAS uint32_t *pos = gmem(S.pos);
-        const uint32_t g = (uint32_t)((uint64_t)(t - tmin) >> sft);
+        const uint32_t g = (uint32_t)((uint64_t)(t - P.t_min) >> P.shift);
         if (is_start) {
-            for (uint32_t j = 0; j <= g; ++j) pos[bnd_at<L2 ? 1u : BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
+            for (uint32_t j = 0; j <= g; ++j) pos[bnd_at<BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
         } else {
-            const uint32_t gp = (uint32_t)((uint64_t)(st[i] - tmin) >> sft);
-            for (uint32_t j = gp + 1; j <= g; ++j) pos[bnd_at<L2 ? 1u : BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
+            const uint32_t gp = (uint32_t)((uint64_t)(st[i] - P.t_min) >> P.shift);
+            for (uint32_t j = gp + 1; j <= g; ++j) pos[bnd_at<BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
         }
         if (is_end)
-            for (uint32_t j = g + 1; j <= n_seg; ++j) pos[bnd_at<L2 ? 1u : BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)(k + 1);
-    }
-}
-
-// Second level of the two-level ordering, per chunk of the level-1 output: its
-// run starts (position 0 and every position whose time is below its
-// predecessor's).
-__global__ __launch_bounds__(256) void k_ingest2(BatchDev b) {
-    constexpr int NT = 256, PER = CHUNK / NT;
-    const uint32_t item = blockIdx.x;
-    const uint32_t si = slice_of_chunk(b, item);
-    const SliceDev &S = b.slices[si];
-    const uint32_t c = item - chunk_base_of(b, si);
-    if (c >= S.n_chunks) return;
-    const TRIG_GAS Plan *Pg = gmem(b.plans + si);
-    if (Pg->state != ST_FAST || !Pg->tl) return;
-    const uint32_t tm32 = (uint32_t)(uint64_t)Pg->t_min;
-    const TRIG_GAS uint64_t *l1 = level1_hits(S);
-    const uint64_t k0 = (uint64_t)c * CHUNK;
-    const uint64_t k1 = (k0 + CHUNK < S.n) ? k0 + CHUNK : S.n;
-    uint32_t ns = 0;
-    uint32_t tv[PER], tp[PER];
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const uint64_t k = k0 + (uint64_t)e * NT + threadIdx.x;
-        if (k < k1) {
-            tv[e] = (uint32_t)l1[k] - tm32;
-            tp[e] = k ? (uint32_t)l1[k - 1] - tm32 : 0u;
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const uint64_t k = k0 + (uint64_t)e * NT + threadIdx.x;
-        if (k < k1) ns += (k == 0) || (tv[e] < tp[e]);
-    }
-    __shared__ uint32_t sh[NT / 64 + 1];
-    const uint32_t tot = block_sum<NT>(ns, sh);
-    if (threadIdx.x == 0) gmem(S.part)[c].n_start = tot;
-}
-
-// Second level, per two-level slice: numbering of the level-1 output's runs
-// (the runs before each block of chunks, from k_psum's counts) and the check that
-// its boundary table fits.
-__global__ __launch_bounds__(1024) void k_plan2(BatchDev b) {
-    constexpr int NT = 1024;
-    const uint32_t si = blockIdx.x;
-    const SliceDev &S = b.slices[si];
-    Plan *P = S.plan;
-    if (P->state != ST_FAST || !P->tl) return;
-    __shared__ uint32_t sh[NT / 64 + 1];
-    int64_t lo = 0, hi = 0;
-    uint32_t pmax = 0, runs = 0;
-    float dmax = 0.f;
-    if (b.max_tiles > PL_CH) {
-        plan_blocks<NT, true>(S, lo, hi, pmax, runs, dmax, sh);   // k_psum's blocks
-    } else {
-        block_sums<true>(S, 0, lo, hi, pmax, dmax, runs);         // the one block, here
-        if (threadIdx.x == 0) gmem(S.ppart)[0].run_off = 0u;
-    }
-    if (threadIdx.x == 0) {
-        P->n_runs2 = runs;
-        // each group's output is time-ordered, so at most n_grp runs remain
-        const bool fits = runs <= (uint32_t)WAVE_RUNS && bnd_entries<1>((uint64_t)P->n_seg2 + 1, runs) <= S.pos_cap;
-        if (!fits) P->state = ST_NEED_GENERIC;
+            for (uint32_t j = g + 1; j <= P.n_seg; ++j) pos[bnd_at<BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)(k + 1);
     }
 }
 
@@ -762,6 +669,7 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
     TRIG_GAS uint32_t *o_t = nullptr, *o_pq = nullptr, *o_idx = nullptr;
     TRIG_GAS uint64_t *l1_out = nullptr;
     TRIG_GAS uint32_t *l1_idx = nullptr;
+    TRIG_GAS uint32_t *t2 = nullptr;   // (level 1 of a two-level slice) the level-2 table
     Plan P = {};
     // the plan fields of this launch's level
     uint32_t n_runs = 0, shift = 0, n_seg = 1;
@@ -773,17 +681,19 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
             P = b.plans[si];
             const SliceDev &S = b.slices[si];
             in_pk = L2 ? level1_hits(S) : packed_hits(S);
-            pos = gmem(S.pos);
+            pos = L2 ? level2_table(S, P) : gmem(S.pos);
             o_t = gmem(S.o_t); o_pq = gmem(S.o_pq); o_idx = gmem(S.o_idx);
             l1_out = level1_hits(S);
             l1_idx = level1_index(S);
             tl1 = !L2 && P.tl;
+            t2 = tl1 ? level2_table(S, P) : nullptr;
             n_runs = L2 ? P.n_runs2 : P.n_runs;
             shift = L2 ? P.shift2 : P.shift;
             n_seg = L2 ? P.n_seg2 : P.n_seg;
             s_base = L2 ? P.seg_item_base2 : P.seg_item_base;
             s_end = s_base + (tl1 ? P.n_grp * n_seg : n_seg);
         }
+        if (L2 && P.state != ST_FAST) continue;   // (level 1 gave the slice up)
         const uint32_t jj = item - s_base;
         // the segment and (level 1 of a two-level slice) the group of runs
         const uint32_t grp = tl1 ? jj / n_seg : 0u;
@@ -982,6 +892,28 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
                 }
             }
         }
+        if (tl1) {
+            // the level-2 boundary rows of this group that fall in the segment
+            // (rows q for times q << shift2 from j << d on, through n_seg2 in the
+            // last segment): row q = the first output position at or after its time
+            const uint32_t d = shift - P.shift2;
+            const uint32_t q_lo = j << d;
+            const uint32_t q_hi = j + 1 == n_seg ? P.n_seg2 : min(((j + 1) << d) - 1u, P.n_seg2);
+            const uint64_t R2 = P.n_grp;
+            uint32_t carry = q_lo - 1u;   // the row of the element before (wraps for q_lo = 0)
+            uint32_t last = q_lo - 1u;    // the row of the last element
+#pragma unroll
+            for (int e = 0; e < EG; ++e) {
+                const uint32_t i = (uint32_t)(e * 64 + lane);
+                const uint32_t g2 = (seg_lo + (uint32_t)(kk[e] >> KEY_T_SHIFT)) >> P.shift2;
+                const uint32_t pv = wave_shr1(g2, carry);
+                carry = lane_read(g2, 63);
+                if (i < m)
+                    for (uint32_t q = pv + 1u; q <= g2; ++q) t2[bnd_at<1>(q, grp, R2)] = goff + i;
+                if (m && (uint32_t)e == (m - 1u) >> 6) last = lane_read(g2, (int)((m - 1u) & 63u));
+            }
+            for (uint32_t q = last + 1u + (uint32_t)lane; q <= q_hi; q += 64) t2[bnd_at<1>(q, grp, R2)] = goff + m;
+        }
         wave_sync();
     }
 }
@@ -1032,7 +964,7 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
     }
     if (b.max_tiles > PL_CH) {   // (else each slice is one block, summed by k_plan itself)
         TRIG_MARK("k_psum", 0);
-        hipLaunchKernelGGL(k_psum<false>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
+        hipLaunchKernelGGL(k_psum, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s, b);
         TRIG_CHECK();
         TRIG_MARK("k_psum", 1);
     }
@@ -1042,7 +974,7 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
     TRIG_MARK("k_plan", 1);
     // always launched: its extra block writes the segment counts the ordering kernels read
     TRIG_MARK("k_bounds", 0);
-    hipLaunchKernelGGL(k_bounds<false>, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bounds, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
     TRIG_CHECK();
     TRIG_MARK("k_bounds", 1);
     hipError_t e;
@@ -1057,27 +989,8 @@ hipError_t trig_launch_front(const BatchDev &b, uint32_t seg_cap, uint32_t wave_
         TRIG_MARK("k_segsort_w", 1);
     }
     if (b.sort_kernels & 4u) {
-        // second level of the two-level slices: run starts and numbering of the
-        // level-1 output, its boundary table, the merge
-        TRIG_MARK("k_ingest2", 0);
-        hipLaunchKernelGGL(k_ingest2, dim3(b.total_chunks), dim3(256), 0, s, b);
-        TRIG_CHECK();
-        TRIG_MARK("k_ingest2", 1);
-        if (b.max_tiles > PL_CH) {
-            TRIG_MARK("k_psum2", 0);
-            hipLaunchKernelGGL(k_psum<true>, dim3((b.max_tiles + PL_CH - 1) / PL_CH, b.n_slices), dim3(1024), 0, s,
-                               b);
-            TRIG_CHECK();
-            TRIG_MARK("k_psum2", 1);
-        }
-        TRIG_MARK("k_plan2", 0);
-        hipLaunchKernelGGL(k_plan2, dim3(b.n_slices), dim3(1024), 0, s, b);
-        TRIG_CHECK();
-        TRIG_MARK("k_plan2", 1);
-        TRIG_MARK("k_bounds2", 0);
-        hipLaunchKernelGGL(k_bounds<true>, dim3(b.total_chunks + 1), dim3(256), 0, s, b);
-        TRIG_CHECK();
-        TRIG_MARK("k_bounds2", 1);
+        // second level of the two-level slices: the merge of the groups' ordered
+        // outputs (level 1 has written their boundary table)
         TRIG_MARK("k_segsort_w2", 0);
         e = wave_cap <= (uint32_t)WAVE_CAP_SMALL ? launch_segsort_w<WAVE_CAP_SMALL, true>(b, wc, s)
                                                  : launch_segsort_w<WAVE_CAP, true>(b, wc, s);

@@ -976,6 +976,10 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const uint32_t k = item - tile_base_of(b, si);
     if (k >= S.n_tiles) return;
     const TRIG_GAS Plan *Pg = gmem(b.plans + si);
+    // halo: from the plan (four times the mean number of hits in t_floor_ns, whole
+    // words), at most SD_HS (a burst that outruns it takes the search past the
+    // stage below)
+    const uint64_t halo = min(cmem(b.plans + si)->seed_halo, (uint32_t)SD_HS);
     if (!slice_in_tail(b, Pg->state)) return;
     const TRIG_GAS uint32_t *o_t = gmem(S.o_t);
     const TRIG_GAS uint32_t *o_pq = gmem(S.o_pq);
@@ -992,7 +996,6 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
         return;
     }
     const uint64_t e = (a + TILE < n) ? a + TILE : n;
-    const uint64_t span = (uint64_t)(Pg->t_max - Pg->t_min);
     const int32_t tau = b.prm.t_floor_ns;
     const uint32_t tau_u = tau > 0 ? (uint32_t)tau : 0u;
     const uint32_t q_seed = b.prm.q_seed;
@@ -1000,12 +1003,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const uint32_t tid = threadIdx.x;
     const int lane = lane_id(), w = (int)(tid >> 6);
 
-    // halo: four times the mean number of hits in t_floor_ns, at least one word, in
-    // whole words (a burst that outruns it takes the search past the stage below)
-    uint64_t halo = tau < 0 ? 0ull : (4ull * n * (tau_u + 1ull)) / (span + 1);
-    halo = halo < 64 ? 64 : (halo + 63) & ~63ull;
-    if (tau < 0) halo = 0;
-    if (halo > (uint64_t)SD_HS) halo = SD_HS;
+
     const uint64_t sl = a >= halo ? a - halo : 0;   // (a is a multiple of TILE: sl = a - halo or 0)
     const uint64_t she = (e + halo < n) ? e + halo : n;
     const uint32_t len = (uint32_t)(she - sl);

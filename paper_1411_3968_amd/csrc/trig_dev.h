@@ -2,6 +2,7 @@
 //
 // Pipeline of one batch of slices (every kernel covers all slices of the batch):
 //   k_ingest     per 1024-hit chunk: min/max time, max PMT, run starts
+//   k_psum       (slices of more than 1024 chunks) partial sums per block of chunks
 //   k_plan       per slice: validation, t_min, run count, segment width, path and
 //                ordering-kernel kind
 //   k_bounds     per chunk: run start and segment-boundary positions of every run
@@ -10,21 +11,27 @@
 //   k_segsort_w  persistent, one wave per time segment of at most WAVE_CAP hits:
 //                gather the segment's stretch of every run into LDS, order it by
 //                (t, pmt, input index), write the ordered structure-of-arrays
+//                (slices with more runs than a wave merges: first per group of
+//                runs, then k_bounds and k_segsort_w again over the groups'
+//                ordered outputs)
 //   k_segsort    the same with one block per segment, for wider segments
-//   k_tile       per ordered tile of TILE hits: L1 seeds, causal folds and fires of
-//                the tile (fire records to a per-tile scratch slot), and a summary
-//                of its fires and their event structure
-//   k_tscan      per slice: scan of the tile summaries (each tile's place in the
-//                fire and event lists), counts, the last event's end, the plan
-//                to host-mapped staging
+//   k_seed       per ordered tile of TILE hits: L1 seeds, compacted per tile
+//   k_fold       per group of tiles: causal folds of every seed over its window,
+//                fires to a per-tile scratch slot, a summary of the tile's fires
+//                and their event structure
+//   k_tsum/k_tscan  per slice: scan of the tile summaries (each tile's place in
+//                the fire and event lists), counts, the last event's end, the
+//                plan to host-mapped staging
 //   k_place      per tile with fires: fire records and event halves at their
 //                places, also to host-mapped staging
+// (the seed menu and level 0 use k_tile, k_l0_ok and k_l0_pass instead of or
+// before k_seed)
 // A slice with a tile whose time window reaches past its staged halo (a burst far
 // denser than the slice's mean) reruns the trigger stage after k_dseed has
 // written the seed bit of every ordered hit.
 // A slice whose input is not a concatenation of a modest number of time-ordered
 // runs (or whose time density overflows a segment) is re-ordered by a general
-// LSD radix sort (k_g*) and then runs k_trig.
+// LSD radix sort (k_g*) and then runs the trigger stage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -131,12 +138,12 @@ struct Plan {
     uint32_t n_tagged;       // hits inside the event windows (slices that ask for the tagged list)
     // two-level ordering (slices with more runs than a wave merges): level 1 orders
     // groups of run_grp consecutive runs over segments of 2^shift ns (n_grp * n_seg
-    // work items), level 2 merges the n_runs2 time-ordered stretches that level 1
-    // leaves over segments of 2^shift2 ns
+    // work items), level 2 merges the n_runs2 = n_grp time-ordered stretches that
+    // level 1 leaves (one per group) over segments of 2^shift2 ns
     uint32_t tl;
     uint32_t n_grp, run_grp;
     uint32_t n_runs2, shift2, n_seg2, seg_item_base2;
-    uint32_t pad2;
+    uint32_t seed_halo;      // hits staged on each side of a seed-kernel tile (before its cap)
 };
 
 struct SliceDev {
@@ -226,6 +233,10 @@ struct BatchDev {
 #define TRIG_GAS __attribute__((address_space(1)))
 template <class T> __device__ __forceinline__ TRIG_GAS T *gmem(T *p) { return (TRIG_GAS T *)p; }
 template <class T> __device__ __forceinline__ const TRIG_GAS T *gmem(const T *p) { return (const TRIG_GAS T *)p; }
+// Device memory that no kernel of the launch writes (filled by an earlier
+// kernel): uniform loads from it can go through the scalar cache.
+#define TRIG_CAS __attribute__((address_space(4)))
+template <class T> __device__ __forceinline__ const TRIG_CAS T *cmem(const T *p) { return (const TRIG_CAS T *)p; }
 // Whole-struct copies through such pointers, a word at a time.
 template <class T> __device__ __forceinline__ T gload(const TRIG_GAS T *p) {
     static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
@@ -482,6 +493,16 @@ __device__ __forceinline__ TRIG_GAS uint64_t *level1_hits(const SliceDev &S) {
 }
 __device__ __forceinline__ TRIG_GAS uint32_t *level1_index(const SliceDev &S) {
     return (TRIG_GAS uint32_t *)gmem(S.fires);
+}
+// Two-level slices: the level-2 boundary table (rows 0 .. n_seg2 over the n_grp
+// groups, whose ordered level-1 outputs are the runs of level 2; written by
+// level 1 as it orders them) at the end of the table area, after the level-1
+// table that level 1 still reads.
+__host__ __device__ __forceinline__ uint64_t level2_entries(const Plan &P) {
+    return bnd_entries<1>((uint64_t)P.n_seg2 + 1, P.n_grp);
+}
+__device__ __forceinline__ TRIG_GAS uint32_t *level2_table(const SliceDev &S, const Plan &P) {
+    return gmem(S.pos) + (S.pos_cap - level2_entries(P));
 }
 
 // Plain rule: every tile's seeds, compacted in time order by the seed kernel and

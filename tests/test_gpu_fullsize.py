@@ -121,7 +121,7 @@ def test_block_slice_full_size(T, orc):
         run()
         again = run()
         assert np.array_equal(again["fires"], r["fires"]) and np.array_equal(again["events"], r["events"])
-    assert r["status"] == 0 and r["n_fires"] > 100_000
+    assert r["status"] == 0 and r["n_fires"] > 100_000 and r["path"] == 0
     assert r["n_seeds"] == int(r["seed_flags"].sum())
     ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
     assert ref["status"] == 0

@@ -374,6 +374,7 @@ def test_block_slice_reduced(tr, orc):
     got = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
     ref = orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked")
     check(got, ref)
+    assert got["path"] == 0   # (the two-level run merge)
 
 
 def test_batch_many_slices_with_empty_ones(tr, orc):
@@ -421,4 +422,35 @@ def test_one_pmt_burst_keeps_the_fast_ordering(tr, orc):
     gid = gid_for(tr, g.floor_id, thr)
     got = tr.slice(gid, s.pmt, s.t, s.q, params, seed_flags=True)
     check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, params, "blocked"))
+    assert got["path"] == 0
+
+
+@pytest.mark.parametrize("case", ["span_all_ones", "gap_and_burst"])
+def test_two_level_merge_edges(tr, orc, case):
+    """2688 per-PMT runs (more than a wave merges: two ordering levels, the second
+    over the groups' ordered outputs, whose boundary table level 1 writes).
+    span_all_ones: t_max - t_min = 2^24 - 1, so the last level-1 segment also
+    owns the table's final row; gap_and_burst: 4 ms without hits (empty segments
+    at both levels) and one PMT at 2 MHz.  Both stay on the run merge (path 0)
+    and equal the oracle."""
+    from gen import configs as C
+    from gen.slices import make_slice
+    g, thr = C.geometry("block")
+    if case == "span_all_ones":
+        T = 1 << 24
+        s = make_slice(g, T, 20e3, 93, n_tracks=4)
+        t = s.t.copy()
+        t[np.flatnonzero(s.pmt == 0)[0]] = t.min()           # (the runs stay ordered)
+        t[np.flatnonzero(s.pmt == 1)[-1]] = t.min() + T - 1
+        pmt, q = s.pmt, s.q
+        assert int(t.max() - t.min()) == T - 1
+    else:
+        s = make_slice(g, 30_000_000, 20e3, 94, n_tracks=4, bursts=[(7, 2.0e6, 2_000_000, 2_000_000)])
+        rel = s.t - s.t.min()
+        keep = (rel < 10_000_000) | (rel >= 14_000_000)
+        t, pmt, q = s.t[keep], s.pmt[keep], s.q[keep]
+    params = dict(C.DEFAULT_PARAMS)
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, params, seed_flags=True)
+    check(got, orc.run(pmt, t, q, g.floor_id, thr, params, "blocked"))
     assert got["path"] == 0
