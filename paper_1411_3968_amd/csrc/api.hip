@@ -1106,7 +1106,7 @@ int trig_geom_load(trig_ctx *c, const trig_geom_desc *g, uint32_t *geom_id) {
     hipError_t e = hipMalloc(&d.floor_id, P * 4);
     if (e == hipSuccess) e = hipMalloc(&d.rmax, P * 4);
     if (e == hipSuccess) e = hipMemcpy(d.rmax, rmax.data(), P * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess && d.nbk) e = hipMalloc(&d.tbnd, tb.size() * 2);
+    if (e == hipSuccess && d.nbk) e = hipMalloc(&d.tbnd, (tb.size() * 2 + 15) & ~(size_t)15);   // (read in 16-byte pieces)
     if (e == hipSuccess && d.nbk) e = hipMemcpy(d.tbnd, tb.data(), tb.size() * 2, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&d.adj32, P * 4);
     if (e == hipSuccess) e = hipMalloc(&d.afl32, P * 4);

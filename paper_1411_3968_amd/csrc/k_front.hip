@@ -710,9 +710,9 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
             const uint32_t r = r_lo + (uint32_t)(i * 64 + lane);
             lo[i] = hi[i] = st[i] = 0;
             if (r < r_hi) {
-                lo[i] = pos[bnd_at<L2 ? 1u : BND_TJ>(j, r, R)];
-                hi[i] = pos[bnd_at<L2 ? 1u : BND_TJ>(j + 1, r, R)];
-                st[i] = pos[bnd_at<L2 ? 1u : BND_TJ>(0, r, R)];
+                lo[i] = pos[bnd_at<L2 ? BND_TJ2 : BND_TJ>(j, r, R)];
+                hi[i] = pos[bnd_at<L2 ? BND_TJ2 : BND_TJ>(j + 1, r, R)];
+                st[i] = pos[bnd_at<L2 ? BND_TJ2 : BND_TJ>(0, r, R)];
             }
         }
         uint32_t m = 0, gpart = 0, rb[RI];
@@ -909,10 +909,10 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
                 const uint32_t pv = wave_shr1(g2, carry);
                 carry = lane_read(g2, 63);
                 if (i < m)
-                    for (uint32_t q = pv + 1u; q <= g2; ++q) t2[bnd_at<1>(q, grp, R2)] = goff + i;
+                    for (uint32_t q = pv + 1u; q <= g2; ++q) t2[bnd_at<BND_TJ2>(q, grp, R2)] = goff + i;
                 if (m && (uint32_t)e == (m - 1u) >> 6) last = lane_read(g2, (int)((m - 1u) & 63u));
             }
-            for (uint32_t q = last + 1u + (uint32_t)lane; q <= q_hi; q += 64) t2[bnd_at<1>(q, grp, R2)] = goff + m;
+            for (uint32_t q = last + 1u + (uint32_t)lane; q <= q_hi; q += 64) t2[bnd_at<BND_TJ2>(q, grp, R2)] = goff + m;
         }
         wave_sync();
     }

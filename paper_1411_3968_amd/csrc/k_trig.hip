@@ -1274,8 +1274,9 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     const bool bounds = nbk != 0 && W <= 65535u;
     const bool tb_in_lds = bounds && nbk * nbk <= b.tbnd_lds;
     const TRIG_GAS uint16_t *tbnd = gmem(S.tbnd);
-    if (tb_in_lds) {
-        for (uint32_t x = threadIdx.x; x < nbk * nbk; x += NT) ltb[x] = tbnd[x];
+    if (tb_in_lds) {   // (16-byte pieces: the table's allocation is padded to them)
+        const TRIG_GAS u32x4 *src = (const TRIG_GAS u32x4 *)tbnd;
+        for (uint32_t x = threadIdx.x; x < (nbk * nbk + 7) / 8; x += NT) ((u32x4 *)ltb)[x] = src[x];
         __syncthreads();
     }
     const uint32_t kt = k0 + (uint32_t)w;

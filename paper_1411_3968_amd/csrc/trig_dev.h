@@ -448,11 +448,13 @@ __device__ __forceinline__ uint32_t chunk_base_of(const BatchDev &b, uint32_t si
 // boundaries, run-major inside a tile.  With TJ = BND_TJ one run's entries for 16
 // consecutive boundaries are one 64-byte stretch, written whole by the chunk that
 // crosses them (neighbouring segments read the same lines): the single-level and
-// level-1 tables.  Level 2 of the two-level ordering (a few dozen long runs) keeps
-// TJ = 1, a segment's entries over all runs contiguous: its ordering kernel reads
-// them far more often than they are written (measured on the 2688-PMT block: 273
-// against 427 us for that kernel).
+// level-1 tables.  The level-2 table of the two-level ordering (a few dozen long
+// runs, written by level 1, each level-1 segment a run of consecutive rows of
+// its group) takes 8 rows a tile: on the 2688-PMT block the two levels took
+// 329 + 265 us with 1 row (each entry a partial line of its own), 280 + 271 us
+// with 8 and 278 + 286 us with 32 (a level-2 segment's entries over more lines).
 constexpr uint32_t BND_TJ = 16;
+constexpr uint32_t BND_TJ2 = 8;
 template <uint32_t TJ>
 __host__ __device__ __forceinline__ uint64_t bnd_at(uint32_t j, uint32_t r, uint64_t R) {
     return (uint64_t)(j / TJ) * R * TJ + (uint64_t)r * TJ + (j % TJ);
@@ -499,7 +501,7 @@ __device__ __forceinline__ TRIG_GAS uint32_t *level1_index(const SliceDev &S) {
 // level 1 as it orders them) at the end of the table area, after the level-1
 // table that level 1 still reads.
 __host__ __device__ __forceinline__ uint64_t level2_entries(const Plan &P) {
-    return bnd_entries<1>((uint64_t)P.n_seg2 + 1, P.n_grp);
+    return bnd_entries<BND_TJ2>((uint64_t)P.n_seg2 + 1, P.n_grp);
 }
 __device__ __forceinline__ TRIG_GAS uint32_t *level2_table(const SliceDev &S, const Plan &P) {
     return gmem(S.pos) + (S.pos_cap - level2_entries(P));
