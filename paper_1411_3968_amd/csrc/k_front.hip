@@ -23,9 +23,16 @@ __device__ __forceinline__ int64_t wave_max64(int64_t v) {
 __device__ __forceinline__ uint32_t wave_maxu(uint32_t v) { return wave_max_all(v); }
 __device__ __forceinline__ uint32_t wave_sumu(uint32_t v) { return wave_total(v); }
 
+typedef int64_t i64x2 __attribute__((ext_vector_type(2)));    // 16-byte loads
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));   // 16-byte stores
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));   // 8-byte loads
+
 // Per chunk of CHUNK input hits: time range, largest PMT id, run starts
 // (position 0 and every position whose time is below its predecessor's), and
 // the packed copy of the chunk's hits that the wave ordering kernel gathers.
+// A thread takes four consecutive hits: two 16-byte loads of times, one 8-byte
+// load each of PMT ids and charges, two 16-byte stores (scalar accesses at the
+// slice's end or when the caller's arrays are not aligned for them).
 __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const uint32_t item = blockIdx.x;
     const uint32_t si = find_slice(b.n_slices, item, [&](uint32_t i) { return b.chunk_bases[i]; });
@@ -41,33 +48,45 @@ __global__ __launch_bounds__(NT_ING) void k_ingest(BatchDev b) {
     const TRIG_GAS uint16_t *qin = gmem(S.q);
     TRIG_GAS uint64_t *pk = packed_hits(S);
     constexpr int PER = CHUNK / NT_ING;
-    int64_t tv[PER], tp[PER];
+    static_assert(PER == 4, "four consecutive hits per thread");
+    const uint64_t ka = k0 + (uint64_t)threadIdx.x * PER;   // (a multiple of 4)
+    const uint32_t own = ka < k1 ? (uint32_t)min(k1 - ka, (uint64_t)PER) : 0u;
+    const bool aligned = (((uintptr_t)S.t | (uintptr_t)pk) & 15) == 0 && (((uintptr_t)S.pmt | (uintptr_t)S.q) & 7) == 0;
+    int64_t tv[PER];
     uint32_t pv[PER], qv[PER];
+    if (own == PER && aligned) {
+        const i64x2 t01 = *(const TRIG_GAS i64x2 *)(tin + ka), t23 = *(const TRIG_GAS i64x2 *)(tin + ka + 2);
+        const u16x4 p4 = *(const TRIG_GAS u16x4 *)(pin + ka), q4 = *(const TRIG_GAS u16x4 *)(qin + ka);
+        tv[0] = t01.x; tv[1] = t01.y; tv[2] = t23.x; tv[3] = t23.y;
+        pv[0] = p4.x; pv[1] = p4.y; pv[2] = p4.z; pv[3] = p4.w;
+        qv[0] = q4.x; qv[1] = q4.y; qv[2] = q4.z; qv[3] = q4.w;
+    } else {
 #pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
-        if (k < k1) {
-            tv[e] = tin[k];
-            tp[e] = k ? tin[k - 1] : INT64_MIN;
-            pv[e] = pin[k];
-            qv[e] = qin[k];
+        for (int e = 0; e < PER; ++e) {
+            tv[e] = 0; pv[e] = qv[e] = 0;
+            if ((uint32_t)e < own) { tv[e] = tin[ka + e]; pv[e] = pin[ka + e]; qv[e] = qin[ka + e]; }
         }
     }
+    const int64_t tprev = (own && ka) ? tin[ka - 1] : INT64_MIN;   // the hit before the thread's first
+    uint64_t w4[PER];
 #pragma unroll
     for (int e = 0; e < PER; ++e) {
-        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
-        if (k < k1) pk[k] = ((uint64_t)((pv[e] << 16) | qv[e]) << 32) | (uint32_t)(uint64_t)tv[e];
-    }
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-        const uint64_t k = k0 + (uint64_t)e * NT_ING + threadIdx.x;
-        if (k < k1) {
+        w4[e] = ((uint64_t)((pv[e] << 16) | qv[e]) << 32) | (uint32_t)(uint64_t)tv[e];
+        if ((uint32_t)e < own) {
             const int64_t t = tv[e];
             lo = t < lo ? t : lo;
             hi = t > hi ? t : hi;
             pmax = pv[e] > pmax ? pv[e] : pmax;
-            ns += (k == 0) || (t < tp[e]);
+            ns += (ka + e == 0) || (t < (e ? tv[e - 1] : tprev));
         }
+    }
+    if (own == PER && aligned) {
+        *(TRIG_GAS u64x2 *)(pk + ka) = u64x2{w4[0], w4[1]};
+        *(TRIG_GAS u64x2 *)(pk + ka + 2) = u64x2{w4[2], w4[3]};
+    } else {
+#pragma unroll
+        for (int e = 0; e < PER; ++e)
+            if ((uint32_t)e < own) pk[ka + e] = w4[e];
     }
     __shared__ int64_t slo[NT_ING / 64], shi[NT_ING / 64];
     __shared__ uint32_t sp[NT_ING / 64], sn[NT_ING / 64];

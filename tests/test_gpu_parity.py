@@ -454,3 +454,28 @@ def test_two_level_merge_edges(tr, orc, case):
     got = tr.slice(gid, pmt, t, q, params, seed_flags=True)
     check(got, orc.run(pmt, t, q, g.floor_id, thr, params, "blocked"))
     assert got["path"] == 0
+
+
+def test_unaligned_device_inputs(tr, orc):
+    """Device arrays that start one element into their allocations (times 8 bytes
+    and PMT ids and charges 2 bytes past an aligned address): the ingest takes
+    its scalar loads; the result equals the oracle and the aligned call."""
+    import torch
+    from gen import configs as C
+    w = C.km3(seed=5, length_ns=20_000_000, n_tracks=3)
+    g, thr = w.geoms["km3"]
+    s = w.slices[0][1]
+    dev = torch.device("cuda:0")
+
+    def shifted(a, dtype):
+        x = torch.empty(len(a) + 1, dtype=dtype, device=dev)
+        x[1:] = torch.from_numpy(np.ascontiguousarray(a).view(np.int16 if dtype == torch.int16 else np.int64)).to(dev)
+        return x[1:]
+
+    dp, dt, dq = shifted(s.pmt, torch.int16), shifted(s.t, torch.int64), shifted(s.q, torch.int16)
+    assert dt.data_ptr() % 16 == 8 and dp.data_ptr() % 8 == 2
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, dp, dt, dq, w.params, seed_flags=True)
+    check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked"))
+    base = tr.slice(gid, *to_dev(s), w.params, seed_flags=True)
+    assert np.array_equal(got["fires"], base["fires"]) and np.array_equal(got["seed_flags"], base["seed_flags"])
