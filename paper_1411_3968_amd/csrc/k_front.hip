@@ -376,21 +376,33 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
     const Plan P = gload(gmem(b.plans + si));
     if (P.state != ST_FAST) return;
     const TRIG_GAS int64_t *tin = gmem(S.t);
-    __shared__ int64_t st[CHUNK + 2];
+    // the chunk's times at st[2 ..], its predecessor's at st[1] and its
+    // successor's after them (a thread stages its four with two 16-byte loads
+    // and stores when the caller's array allows)
+    __shared__ __align__(16) int64_t st[CHUNK + 4];
     __shared__ uint32_t sh[NT / 64 + 1];
+    static_assert(PER == 4, "four consecutive hits per thread");
     const uint64_t k0 = (uint64_t)c * CHUNK;
     const uint32_t len = (uint32_t)((k0 + CHUNK < S.n) ? CHUNK : S.n - k0);
-    stage_copy<NT, PER>(st + 1, tin + k0, len);
+    const uint32_t a = threadIdx.x * PER;
+    if (a + PER <= len && ((uintptr_t)S.t & 15) == 0) {
+        typedef int64_t i64x2 __attribute__((ext_vector_type(2)));
+        const i64x2 t01 = *(const TRIG_GAS i64x2 *)(tin + k0 + a), t23 = *(const TRIG_GAS i64x2 *)(tin + k0 + a + 2);
+        *(i64x2 *)(st + 2 + a) = t01;
+        *(i64x2 *)(st + 4 + a) = t23;
+    } else {
+        for (uint32_t e = 0; e < (uint32_t)PER; ++e)
+            if (a + e < len) st[2 + a + e] = tin[k0 + a + e];
+    }
     if (threadIdx.x == 0) {
-        st[0] = k0 ? tin[k0 - 1] : INT64_MIN;
-        st[len + 1] = (k0 + len < S.n) ? tin[k0 + len] : INT64_MIN;
+        st[1] = k0 ? tin[k0 - 1] : INT64_MIN;
+        st[len + 2] = (k0 + len < S.n) ? tin[k0 + len] : INT64_MIN;
     }
     __syncthreads();
-    const uint32_t a = threadIdx.x * PER;
     uint32_t starts = 0;
     for (int e = 0; e < PER; ++e) {
         const uint32_t i = a + e;
-        if (i < len) starts += (k0 + i == 0) || (st[i + 1] < st[i]);
+        if (i < len) starts += (k0 + i == 0) || (st[i + 2] < st[i + 1]);
     }
     uint32_t tot;
     const uint32_t ex = block_excl_scan<NT>(starts, tot, sh);
@@ -402,15 +414,15 @@ __global__ __launch_bounds__(256) void k_bounds(BatchDev b) {
         const uint32_t i = a + e;
         if (i >= len) break;
         const uint64_t k = k0 + i;
-        const int64_t t = st[i + 1];
-        const bool is_start = (k == 0) || (t < st[i]);
-        const bool is_end = (k + 1 == S.n) || (st[i + 2] < t);
+        const int64_t t = st[i + 2];
+        const bool is_start = (k == 0) || (t < st[i + 1]);
+        const bool is_end = (k + 1 == S.n) || (st[i + 3] < t);
         if (is_start) ++r;
         const uint32_t g = (uint32_t)((uint64_t)(t - P.t_min) >> P.shift);
         if (is_start) {
             for (uint32_t j = 0; j <= g; ++j) pos[bnd_at<BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
         } else {
-            const uint32_t gp = (uint32_t)((uint64_t)(st[i] - P.t_min) >> P.shift);
+            const uint32_t gp = (uint32_t)((uint64_t)(st[i + 1] - P.t_min) >> P.shift);
             for (uint32_t j = gp + 1; j <= g; ++j) pos[bnd_at<BND_TJ>(j, (uint32_t)r, R)] = (uint32_t)k;
         }
         if (is_end)
@@ -737,6 +749,8 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
         uint32_t m = 0, gpart = 0, rb[RI];
 #pragma unroll
         for (int i = 0; i < RI; ++i) {
+            rb[i] = 0;
+            if ((uint32_t)(i * 64) >= r_hi - r_lo) continue;   // (no run of the item in this group of 64)
             const uint32_t c = hi[i] - lo[i];
             const uint32_t incl = wave_incl_scan(c);
             const uint32_t rl = (uint32_t)(i * 64 + lane);   // run index within the item
