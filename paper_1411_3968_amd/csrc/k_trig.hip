@@ -961,7 +961,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     constexpr int NT = Sh::NT, NWD = Sh::NWD;
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *st = (uint32_t *)smem;            // staged t - t_min
-    uint32_t *spf = st + Sh::STG;               // staged pmt << 16 | dense floor index
+    uint32_t *spf = st + Sh::STG;               // staged dense floor index << 16 | pmt
     uint64_t *lw = (uint64_t *)(spf + Sh::STG); // level-0 pass bits per word (level 0 on)
     uint64_t *mk = lw + NWD;                    // partner marks per word
     __shared__ uint32_t wsum[NT / 64 + 1];
@@ -1043,13 +1043,13 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     for (int s = 0; s < SD_PL; ++s) {
         q4 |= (uint32_t)((uint32_t)s < own && (p4[s] & 0xFFFFu) >= q_seed) << s;
         const uint32_t p = p4[s] >> 16;
-        p4[s] = (p << 16) | (uint32_t)floor16[p];
+        p4[s] = ((uint32_t)floor16[p] << 16) | p;
     }
     if (has_h) {
 #pragma unroll
         for (int s = 0; s < SD_PL; ++s) {
             const uint32_t p = ph[s] >> 16;
-            ph[s] = (p << 16) | (uint32_t)floor16[p];
+            ph[s] = ((uint32_t)floor16[p] << 16) | p;
         }
     }
     if (x0 + SD_PL <= Sh::STG) {
@@ -1080,22 +1080,34 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     const bool cover_l = sl == 0 || (uint64_t)st[0] + tau_u < (uint64_t)ta;
     const bool cover_r = she == n || (uint64_t)st[len - 1] > (uint64_t)te + tau_u;
     uint32_t f4 = 0;   // own hits with a floor partner, bit s
-    // a pair of two PMTs of one floor within t_floor_ns (t_y >= t_x), both passing level 0
-    auto pair = [&](uint32_t tx, uint32_t px, uint32_t ty, uint32_t py) -> bool {
-        return (ty - tx <= tau_u) & (((py ^ px) & 0xFFFFu) == 0u) & ((py >> 16) != (px >> 16));
-    };
-    if (tau >= 0 && cover_l && cover_r) {
+    // keys (floor << 16 | pmt): x ^ y - 1 < 0xFFFF iff one floor and two PMTs
+    auto floor_pair = [](uint32_t kx, uint32_t ky) -> bool { return ((kx ^ ky) - 1u) < 0xFFFFu; };
+    if (tau >= 0 && tau_u < 0xFFFEu && cover_l && cover_r) {
         // 2. the own hits among themselves and with the staged hits after them,
-        // four at a time; marks of partners after the own hits go to LDS
+        // four at a time.  For own hit s and a later hit y (t_y >= t_s) let
+        // m = max((k_s ^ k_y) - 1, t_y - (t_s + tau - 0xFFFE)): the pair counts iff
+        // m < 0xFFFF (one floor, two PMTs, t_y - t_s <= tau).  An own hit that is
+        // not there or fails level 0 takes t_s + tau - 0xFFFE = 2^31, a staged one
+        // t_y = 3 * 2^30: m is then at least 2^30.  Each own hit keeps the least
+        // m of its pairs; marks of partners after the own hits go to LDS.
+        constexpr uint32_t A_NONE = 0x80000000u, T_NONE = 0xC0000000u;
+        uint32_t as[SD_PL], tv[SD_PL], macc[SD_PL];
+#pragma unroll
+        for (int s = 0; s < SD_PL; ++s) {
+            const bool ok = (uint32_t)s < own && ((l4 >> s) & 1u);
+            as[s] = ok ? t4[s] + tau_u - 0xFFFEu : A_NONE;
+            tv[s] = ok ? t4[s] : T_NONE;
+            macc[s] = 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int s = 0; s < SD_PL; ++s)
+#pragma unroll
+            for (int s2 = s + 1; s2 < SD_PL; ++s2) {
+                const uint32_t m = max(((p4[s] ^ p4[s2]) - 1u), tv[s2] - as[s]);
+                macc[s] = min(macc[s], m);
+                macc[s2] = min(macc[s2], m);
+            }
         if (own) {
-#pragma unroll
-            for (int s = 0; s < SD_PL; ++s)
-#pragma unroll
-                for (int s2 = s + 1; s2 < SD_PL; ++s2) {
-                    const bool pr = (uint32_t)s2 < own && pair(t4[s], p4[s], t4[s2], p4[s2]) &&
-                                    ((l4 >> s) & (l4 >> s2) & 1u);
-                    f4 |= ((uint32_t)pr << s) | ((uint32_t)pr << s2);
-                }
             const uint32_t tl = t4[own - 1];   // the last own hit: the one nearest what follows
             for (uint32_t y0 = x0 + SD_PL;; y0 += SD_PL) {
                 if (y0 >= len || st[y0] - tl > tau_u) break;
@@ -1109,30 +1121,39 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
 #pragma unroll
                     for (int j = 0; j < SD_PL; ++j) {
                         const uint32_t yc = min(y0 + (uint32_t)j, len - 1);
-                        ty[j] = st[yc];
+                        ty[j] = y0 + (uint32_t)j < len ? st[yc] : T_NONE;
                         py[j] = spf[yc];
                     }
                 }
-                uint32_t hit_y = 0;   // staged hits of this block with a partner among the own hits
-#pragma unroll
-                for (int j = 0; j < SD_PL; ++j) {
-                    const bool yin = y0 + (uint32_t)j < len && l0_at(min(y0 + (uint32_t)j, len - 1));
-#pragma unroll
-                    for (int s = 0; s < SD_PL; ++s) {
-                        const bool pr = (uint32_t)s < own && yin && ((l4 >> s) & 1u) && pair(t4[s], p4[s], ty[j], py[j]);
-                        f4 |= (uint32_t)pr << s;
-                        hit_y |= (uint32_t)pr << j;
-                    }
-                }
-                if (hit_y) {   // (rare)
+                if (L0) {
 #pragma unroll
                     for (int j = 0; j < SD_PL; ++j)
-                        if ((hit_y >> j) & 1u) {
+                        if (!l0_at(min(y0 + (uint32_t)j, len - 1))) ty[j] = T_NONE;
+                }
+                uint32_t hacc[SD_PL];   // the least m of each staged hit's pairs with the own hits
+#pragma unroll
+                for (int j = 0; j < SD_PL; ++j) {
+                    uint32_t mj[SD_PL];
+#pragma unroll
+                    for (int s = 0; s < SD_PL; ++s) {
+                        mj[s] = max(((p4[s] ^ py[j]) - 1u), ty[j] - as[s]);
+                        macc[s] = min(macc[s], mj[s]);
+                    }
+                    hacc[j] = min(min(mj[0], mj[1]), min(mj[2], mj[3]));
+                }
+                if (min(min(hacc[0], hacc[1]), min(hacc[2], hacc[3])) < 0xFFFFu) {   // (rare)
+#pragma unroll
+                    for (int j = 0; j < SD_PL; ++j)
+                        if (hacc[j] < 0xFFFFu) {
                             const uint32_t y = y0 + (uint32_t)j;
                             atomicOr((unsigned long long *)&mk[y >> 6], 1ull << (y & 63));
                         }
                 }
             }
+        }
+#pragma unroll
+        for (int s = 0; s < SD_PL; ++s) f4 |= (uint32_t)(macc[s] < 0xFFFFu) << s;
+        if (own) {
             // own hits within t_floor_ns of the tile's start: partners in the left halo
             if (a_loc > 0 && t4[0] - st[a_loc - 1] <= tau_u) {
 #pragma unroll
@@ -1141,7 +1162,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
                     for (uint32_t y = a_loc; y > 0;) {
                         --y;
                         if (t4[s] - st[y] > tau_u) break;
-                        if (l0_at(y) && pair(st[y], spf[y], t4[s], p4[s])) {
+                        if (l0_at(y) && floor_pair(spf[y], p4[s])) {
                             f4 |= 1u << s;
                             break;
                         }
@@ -1156,7 +1177,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
         auto F_at = [&](uint64_t m) -> uint32_t {
             if (m >= sl && m < she) return spf[m - sl];
             const uint32_t p = o_pq[m] >> 16;
-            return (p << 16) | (uint32_t)floor16[p];
+            return ((uint32_t)floor16[p] << 16) | p;
         };
         auto l0g = [&](uint64_t m) -> bool { return !L0 || ((l0m[m >> 6] >> (m & 63)) & 1ull); };
         for (int s = 0; s < SD_PL; ++s) {
@@ -1167,13 +1188,11 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
             for (uint64_t m = j; m > 0 && !found;) {
                 --m;
                 if (t - T_at(m) > tau_u) break;
-                const uint32_t g = F_at(m);
-                found = ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0g(m);
+                found = floor_pair(F_at(m), f) && l0g(m);
             }
             for (uint64_t m = j + 1; m < n && !found; ++m) {
                 if (T_at(m) - t > tau_u) break;
-                const uint32_t g = F_at(m);
-                found = ((g ^ f) & 0xFFFFu) == 0u && (g >> 16) != (f >> 16) && l0g(m);
+                found = floor_pair(F_at(m), f) && l0g(m);
             }
             f4 |= (uint32_t)found << s;
         }
@@ -1201,7 +1220,7 @@ __global__ __launch_bounds__(SD_NT) void k_seed(BatchDev b) {
     for (int s = 0; s < SD_PL; ++s) {
         if ((s4 >> s) & 1u) {
             sd_t[at] = t4[s];
-            sd_p[at] = (p4[s] & 0xFFFF0000u) | (SD_PL * tid + (uint32_t)s);
+            sd_p[at] = (p4[s] << 16) | (SD_PL * tid + (uint32_t)s);
             if (at == 0) gstore(&seed_rec(S)[k].first_t, t4[s]);
             if (at + 1 == total) gstore(&seed_rec(S)[k].last_t, t4[s]);
             ++at;

@@ -479,3 +479,18 @@ def test_unaligned_device_inputs(tr, orc):
     check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, w.params, "blocked"))
     base = tr.slice(gid, *to_dev(s), w.params, seed_flags=True)
     assert np.array_equal(got["fires"], base["fires"]) and np.array_equal(got["seed_flags"], base["seed_flags"])
+
+
+@pytest.mark.parametrize("tau", [65533, 65534, 70000])
+def test_long_floor_window(tr, orc, tau):
+    """Same-floor windows near and past 2^16 ns: the seed kernel's staged pair test
+    holds up to 65533 ns and hands longer windows to its search over device
+    memory; both equal the oracle."""
+    from gen import configs as C
+    w = C.nemo(seed=9, length_ns=4_000_000, n_tracks=2)
+    g, thr = w.geoms["nemo"]
+    s = w.slices[0][1]
+    params = dict(C.DEFAULT_PARAMS, t_floor_ns=tau)
+    gid = gid_for(tr, g.floor_id, thr)
+    got = tr.slice(gid, s.pmt, s.t, s.q, params, seed_flags=True)
+    check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, params, "blocked"))
