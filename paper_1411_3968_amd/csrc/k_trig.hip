@@ -1439,34 +1439,37 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     constexpr int CB = BOUNDS ? 8 : 4;
 
     // fold of one seed (time ti, PMT pi, window index self) over window entries
-    // [jlo, jhi), each read through E_at as time | (pmt << 16 | position) << 32
+    // [jlo, jhi), each read through E_at as time | (pmt << 16 | position) << 32.
+    // A step reads CB entries at indexes clamped to jmax (E_at's last readable
+    // one) whatever their range, so the reads are in flight together; entries
+    // past the range, the seed itself and those beyond its reach count nothing
+    // and read the table at the seed's own row start.
     auto count_range = [&](uint32_t ti, uint32_t pi, uint32_t lim_w, uint32_t jlo, uint32_t jhi, uint32_t self,
-                           auto E_at) -> uint32_t {
+                           uint32_t jmax, auto E_at) -> uint32_t {
         const uint64_t row = (uint64_t)pi * n_pmt;
         const uint32_t brow = (pi >> TBND_SHIFT) * nbk;
         uint32_t c = 0;
         for (uint32_t j0 = jlo;; j0 += CB) {
             if (!__ballot(j0 < jhi)) break;
-            uint32_t dd[CB], lim[CB];
+            uint64_t ej[CB];
+#pragma unroll
+            for (int kk = 0; kk < CB; ++kk) ej[kk] = E_at(min(j0 + (uint32_t)kk, jmax));
+            uint32_t dd[CB], lim[CB], pj[CB];
+#pragma unroll
+            for (int kk = 0; kk < CB; ++kk) {
+                const uint32_t j = j0 + (uint32_t)kk;
+                const uint32_t tj = (uint32_t)ej[kk];
+                const uint32_t dt = tj > ti ? tj - ti : ti - tj;
+                const bool ok = j < jhi && j != self && dt <= lim_w;
+                dd[kk] = ok ? dt : 0xFFFFFFFFu;
+                pj[kk] = ok ? (uint32_t)(ej[kk] >> 48) : 0u;
+            }
             if (BOUNDS && bounds) {
-                uint32_t bb[CB], pj[CB];
+                uint32_t bb[CB];
 #pragma unroll
                 for (int kk = 0; kk < CB; ++kk) {
-                    const uint32_t j = j0 + kk;
-                    dd[kk] = 0xFFFFFFFFu;
-                    bb[kk] = 0;
-                    pj[kk] = 0;
-                    if (j < jhi && j != self) {
-                        const uint64_t ej = E_at(j);
-                        const uint32_t tj = (uint32_t)ej;
-                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                        if (dt <= lim_w) {
-                            pj[kk] = (uint32_t)(ej >> 48);
-                            const uint32_t bx = brow + (pj[kk] >> TBND_SHIFT);
-                            bb[kk] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
-                            dd[kk] = dt;
-                        }
-                    }
+                    const uint32_t bx = brow + (pj[kk] >> TBND_SHIFT);
+                    bb[kk] = tb_in_lds ? (uint32_t)ltb[bx] : (uint32_t)tbnd[bx];
                 }
 #pragma unroll
                 for (int kk = 0; kk < CB; ++kk) {
@@ -1478,18 +1481,10 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
             } else {
 #pragma unroll
                 for (int kk = 0; kk < CB; ++kk) {
-                    const uint32_t j = j0 + kk;
-                    dd[kk] = 0xFFFFFFFFu;
                     lim[kk] = 0;
-                    if (j < jhi && j != self) {
-                        const uint64_t ej = E_at(j);
-                        const uint32_t tj = (uint32_t)ej;
-                        const uint32_t dt = tj > ti ? tj - ti : ti - tj;
-                        if (dt <= lim_w) {
-                            const uint64_t x = row + (uint32_t)(ej >> 48);
-                            lim[kk] = t16 ? (uint32_t)thr16[x] : thr32[x];
-                            dd[kk] = dt;
-                        }
+                    if (dd[kk] != 0xFFFFFFFFu) {
+                        const uint64_t x = row + pj[kk];
+                        lim[kk] = t16 ? (uint32_t)thr16[x] : thr32[x];
                     }
                 }
             }
@@ -1528,7 +1523,7 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                 if (mr <= tot && (uint64_t)lt[2 * (mr - 1)] <= t_hi) jhi = mr;
             }
             if (!v) jhi = jlo;
-            c = count_range(ti, pi, Ri, jlo, jhi, own0 + r, [&](uint32_t j) { return lwin[j]; });
+            c = count_range(ti, pi, Ri, jlo, jhi, own0 + r, (uint32_t)CAP - 1u, [&](uint32_t j) { return lwin[j]; });
         } else {
             // the window tile by tile from the lists in device memory
             for (uint32_t jt = jl; jt < jr; ++jt) {
@@ -1550,7 +1545,7 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                     }
                     jhi = v ? lo : jlo;
                 }
-                c += count_range(ti, pi, Ri, jlo, jhi, jt == kt ? r : 0xFFFFFFFFu,
+                c += count_range(ti, pi, Ri, jlo, jhi, jt == kt ? r : 0xFFFFFFFFu, (uint32_t)TILE - 1u,
                                  [&](uint32_t j) { return (uint64_t)tj[j] | ((uint64_t)pj[j] << 32); });
             }
         }
