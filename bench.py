@@ -36,9 +36,8 @@ ALGO_BYTES_PER_HIT = {
     "k_bounds": 8.0,       # read t (8); the boundary table is counted separately
     "k_segsort": 20.0,     # read the packed word (8) + write ordered t, pmt|q, index (12)
     "k_segsort_w": 20.0,   # the same, one wave per segment
-    "k_ingest2": 8.0,      # two-level ordering, level 2: read the level-1 packed words (8)
-    "k_bounds2": 8.0,      # the same (+ 4 B per boundary-table entry)
-    "k_segsort_w2": 20.0,  # read the packed word (8) + its level-1 input index (4), write t, pmt|q (8)
+    "k_segsort_w2": 24.0,  # two-level ordering, level 2: read the level-1 packed word (8) and input
+                           # index (4), write ordered t, pmt|q, index (12)
     "k_seed": 8.0,         # read ordered t + pmt|q (8): L1 seeds; the compacted seeds are per seed
     "k_tile": 8.0,         # seeds and folds in the tile-per-workgroup kernel (seed menu, dense rerun)
     "k_tag_bits": 4.125,   # read ordered t (4) + write one tag bit; the few event windows are per event
