@@ -663,9 +663,8 @@ struct WaveSeg {
     uint64_t key[CAP];           // keys grouped by bucket, then in output order
     uint16_t dq[CAP];            // charge of each gathered element
     uint16_t aux[CAP];           // run marks while gathering, then the run of each element
-    uint32_t run_lo[WAVE_RUNS], run_base[WAVE_RUNS];
-    uint32_t bcount[256];
-    uint16_t bbase[256];
+    uint32_t roff[WAVE_RUNS];    // per run: its first gathered input position minus its first gathered index
+    uint32_t bkt[256];           // per bucket: members counted, then base << 16 | count
 };
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total(v); }
@@ -677,7 +676,7 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) { return wave_total
 // level-1 output's stretches merged; the input index of each hit comes from the
 // level-1 output).
 template <int CAP, bool L2>
-__global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves per SIMD: what the LDS allows
+__global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves per SIMD (at most 128 VGPRs)
     constexpr int EG = CAP / 64;
     constexpr int RI = WAVE_RUNS / 64;
     static_assert((CAP & (CAP - 1)) == 0 && (WAVE_RUNS & (WAVE_RUNS - 1)) == 0, "masks below need powers of two");
@@ -756,8 +755,7 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
             const uint32_t rl = (uint32_t)(i * 64 + lane);   // run index within the item
             rb[i] = m + incl - c;
             if (r_lo + rl < r_hi) {
-                sm.run_lo[rl] = lo[i];
-                sm.run_base[rl] = rb[i];
+                sm.roff[rl] = lo[i] - rb[i];
             }
             m += lane_read(incl, 63);
             gpart += lo[i] - st[i];
@@ -803,13 +801,13 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
         // (each lane rewrites only its own marks: the run of element k, from which
         // the output recomputes the input index; rr < WAVE_RUNS for every k)
         {
-            uint32_t rlo[EG], rbs[EG];
+            uint32_t ro[EG];
 #pragma unroll
-            for (int e = 0; e < EG; ++e) { rlo[e] = sm.run_lo[rr[e]]; rbs[e] = sm.run_base[rr[e]]; }
+            for (int e = 0; e < EG; ++e) ro[e] = sm.roff[rr[e]];
 #pragma unroll
             for (int e = 0; e < EG; ++e) {
                 const uint32_t k = (uint32_t)(e * 64 + lane);
-                src[e] = k < m ? rlo[e] + (k - rbs[e]) : 0xFFFFFFFFu;
+                src[e] = k < m ? ro[e] + k : 0xFFFFFFFFu;
             }
         }
 #pragma unroll
@@ -828,7 +826,7 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
         // the output order; bucket by the top 8 bits of the local time
         const uint32_t tb = shift > 8 ? shift - 8 : 0u;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sm.bcount[lane * 4 + i] = 0;
+        for (int i = 0; i < 4; ++i) sm.bkt[lane * 4 + i] = 0;
         wave_sync();
         uint64_t key[EG];
         uint32_t slot[EG];
@@ -841,18 +839,18 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
                 const uint32_t tl = ((uint32_t)hv[e] - (uint32_t)(uint64_t)P.t_min) - seg_lo;
                 key[e] = ((uint64_t)tl << KEY_T_SHIFT) | ((hv[e] >> 48) << KEY_P_SHIFT) | k;
                 sm.dq[k] = (uint16_t)(hv[e] >> 32);
-                slot[e] = atomicAdd(&sm.bcount[tl >> tb], 1u);
+                slot[e] = atomicAdd(&sm.bkt[tl >> tb], 1u);
             }
         }
         wave_sync();
         {
             uint32_t v[4], sum = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { v[i] = sm.bcount[lane * 4 + i]; sum += v[i]; }
+            for (int i = 0; i < 4; ++i) { v[i] = sm.bkt[lane * 4 + i]; sum += v[i]; }
             const uint32_t incl = wave_incl_scan(sum);
             uint32_t run = incl - sum;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { sm.bbase[lane * 4 + i] = (uint16_t)run; run += v[i]; }
+            for (int i = 0; i < 4; ++i) { sm.bkt[lane * 4 + i] = (run << 16) | v[i]; run += v[i]; }
         }
         wave_sync();
         // keys grouped by bucket (an element without a hit reads bucket 0 and
@@ -862,8 +860,9 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t bk = (uint32_t)(key[e] >> KEY_T_SHIFT) >> tb;
-            ebase[e] = sm.bbase[bk];
-            ecnt[e] = sm.bcount[bk];
+            const uint32_t wb = sm.bkt[bk];
+            ebase[e] = wb >> 16;
+            ecnt[e] = wb & 0xFFFFu;
         }
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
@@ -906,7 +905,7 @@ __global__ __launch_bounds__(256, 4) void k_segsort_w(BatchDev b) {   // 4 waves
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
             const uint32_t k = (uint32_t)kk[e] & (uint32_t)(CAP - 1);
-            from[e] = sm.run_lo[rv[e]] + (k - sm.run_base[rv[e]]);   // gathered position
+            from[e] = sm.roff[rv[e]] + k;   // gathered position
         }
 #pragma unroll
         for (int e = 0; e < EG; ++e) {
