@@ -1432,11 +1432,13 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
     const bool t16 = W <= 65535u;
     uint32_t top = 1;   // the largest power of two <= tot
     while (top * 2 <= tot) top *= 2;
-    // table reads in flight per lane and step: eight in the variant for batches
-    // with large detectors (32-PMT block bounds decide most pairs of their dense
-    // windows; the slices without bounds in such a batch share the loop), four
-    // in the one for towers only (every pair reads the table; short windows)
-    constexpr int CB = BOUNDS ? 8 : 4;
+    // window entries per lane and step: twelve in the variant for batches with
+    // large detectors (32-PMT block bounds decide most pairs of their dense
+    // windows, and the rest read the table from far memory: on the block 8 took
+    // 209 us, 12 200 us, 16 215 us; the slices without bounds in such a batch
+    // share the loop), four in the one for towers only (every pair reads the
+    // table; short windows)
+    constexpr int CB = BOUNDS ? 12 : 4;
 
     // fold of one seed (time ti, PMT pi, window index self) over window entries
     // [jlo, jhi), each read through E_at as time | (pmt << 16 | position) << 32.
