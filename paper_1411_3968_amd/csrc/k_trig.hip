@@ -699,10 +699,13 @@ __device__ void place_tile(const BatchDev &b, const SliceDev &S, const TRIG_GAS 
         const bool v = r < nf;
         FireRec fr = {0, 0, 0, 0};
         if (v) fr = gload(slot + r);
+        // (lane 63) the next round's first fire time, read with this round's fires
+        const uint32_t t_after = (lane == 63 && r + 1 < nf) ? slot[r + 1].t : 0u;
         const uint32_t t = fr.t, fd = fr.fold;
-        // the lane move runs in every lane (under a select it would run with lane 0
-        // masked off, and lane 1 would read the fill value)
+        // the lane moves run in every lane (under a select they would run with
+        // lanes masked off, and their neighbours would read the fill value)
         const uint32_t t_below = wave_shr1(t, 0u);
+        const uint32_t t_next = wave_shl1(t, t_after);   // the next fire's time
         const uint32_t tp = lane == 0 ? prev_t : t_below;
         const bool first_of_slice = r == 0 && P.F == 0;
         const bool st = v && (first_of_slice || (uint64_t)(t - tp) > twoH);
@@ -758,7 +761,7 @@ __device__ void place_tile(const BatchDev &b, const SliceDev &S, const TRIG_GAS 
                 }
             }
             // the next fire of the tile starts a new event: this one ends its event
-            if (r + 1 < nf && (uint64_t)(slot[r + 1].t - t) > twoH) {
+            if (r + 1 < nf && (uint64_t)(t_next - t) > twoH) {
                 const uint32_t sg = latest >= 0 ? P.F + (uint32_t)latest : p_open;
                 const int64_t tend = out.t_ns + H;
                 events[ev].t_end = tend;

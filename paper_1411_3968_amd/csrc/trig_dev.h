@@ -295,6 +295,9 @@ __device__ __forceinline__ T wave_scan(T v, const T &id, Op op) {
 // must run with all lanes active: a lane masked off reads as id.
 template <class T>
 __device__ __forceinline__ T wave_shr1(const T &v, const T &id) { return dpp_words<0x138, 0xF>(id, v); }
+// Value of the lane above (lane 63 receives id); all lanes active, as above.
+template <class T>
+__device__ __forceinline__ T wave_shl1(const T &v, const T &id) { return dpp_words<0x130, 0xF>(id, v); }
 
 // Value of lane `src` (uniform) in every lane.
 __device__ __forceinline__ uint32_t lane_read(uint32_t v, int src) {
