@@ -494,3 +494,39 @@ def test_long_floor_window(tr, orc, tau):
     gid = gid_for(tr, g.floor_id, thr)
     got = tr.slice(gid, s.pmt, s.t, s.q, params, seed_flags=True)
     check(got, orc.run(s.pmt, s.t, s.q, g.floor_id, thr, params, "blocked"))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_block_bounds_random_tables(tr, orc, seed):
+    """Detectors of 256 PMTs or more: the fold kernel decides most pairs from
+    lower and upper bounds of the table per pair of PMT blocks and reads the
+    table only in between.  Random asymmetric tables with block structure at
+    another granularity, entries of 0, exact multiples of 16 ns, beyond the
+    bounds' 4064 ns range and beyond 65535, and windows below, at and past those
+    limits (W > 65535 turns the bounds off): equal to the oracle."""
+    rng = np.random.default_rng(7100 + seed)
+    P = int(rng.integers(256, 900))
+    gsz = int(rng.choice([8, 32, 50]))
+    nb = (P + gsz - 1) // gsz
+    base = rng.integers(0, 4200, size=(nb, nb))
+    spread = int(rng.choice([1, 16, 300]))
+    blk = np.arange(P) // gsz
+    thr = (base[blk][:, blk] + rng.integers(0, spread, size=(P, P))).astype(np.uint32)
+    u = rng.random((P, P))
+    thr[u < 0.02] = 0
+    thr[(u >= 0.02) & (u < 0.04)] = (thr[(u >= 0.02) & (u < 0.04)] // 16) * 16
+    thr[(u >= 0.04) & (u < 0.05)] = rng.integers(4064, 70000, size=int(((u >= 0.04) & (u < 0.05)).sum()))
+    floor_id = (np.arange(P) // 6).astype(np.int32)
+    n = int(rng.integers(5000, 25000))
+    pmt = rng.integers(0, P, size=n).astype(np.uint16)
+    t = rng.integers(0, n * 40, size=n).astype(np.int64) + 10**15
+    q = rng.integers(0, 600, size=n).astype(np.uint16)
+    o = np.lexsort((t, pmt))   # runs per PMT
+    pmt, t, q = pmt[o], t[o], q[o]
+    w_ns = int(rng.choice([int(rng.integers(50, 5000)), 4064, 4080, 65535, 70000]))
+    params = dict(q_seed=int(rng.integers(250, 500)), t_floor_ns=int(rng.integers(-1, 30)), w_ns=w_ns,
+                  min_fold=int(rng.integers(2, 12)), half_event_ns=int(rng.integers(0, 3000)))
+    gid = gid_for(tr, floor_id, thr)
+    got = tr.slice(gid, pmt, t, q, params, seed_flags=True)
+    check(got, orc.run(pmt, t, q, floor_id, thr, params, "blocked"))
+    assert got["n_fires"] > 0
