@@ -1454,12 +1454,12 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
         const uint64_t row = (uint64_t)pi * n_pmt;
         const uint32_t brow = (pi >> TBND_SHIFT) * nbk;
         uint32_t c = 0;
-        for (uint32_t j0 = jlo;; j0 += CB) {
-            if (!__ballot(j0 < jhi)) break;
+        // one step: the distances of CB entries (0xFFFFFFFF: out of range, the seed
+        // itself or beyond its reach) and their PMTs
+        auto load_step = [&](uint32_t j0, uint32_t (&dd)[CB], uint32_t (&pj)[CB]) {
             uint64_t ej[CB];
 #pragma unroll
             for (int kk = 0; kk < CB; ++kk) ej[kk] = E_at(min(j0 + (uint32_t)kk, jmax));
-            uint32_t dd[CB], lim[CB], pj[CB];
 #pragma unroll
             for (int kk = 0; kk < CB; ++kk) {
                 const uint32_t j = j0 + (uint32_t)kk;
@@ -1469,6 +1469,11 @@ __global__ __launch_bounds__(64 * G) void k_fold(BatchDev b) {
                 dd[kk] = ok ? dt : 0xFFFFFFFFu;
                 pj[kk] = ok ? (uint32_t)(ej[kk] >> 48) : 0u;
             }
+        };
+        for (uint32_t j0 = jlo;; j0 += CB) {
+            if (!__ballot(j0 < jhi)) break;
+            uint32_t dd[CB], pj[CB], lim[CB];
+            load_step(j0, dd, pj);
             if (BOUNDS && bounds) {
                 uint32_t bb[CB];
 #pragma unroll
